@@ -1,0 +1,518 @@
+"""Seeded synthetic inputs: power-law knowledge graphs and query graphs.
+
+This module only *draws* inputs. It holds none of the matching method's
+arithmetic (no candidate filter, no edge collection, no join): the GPU path
+and the CPU oracle both receive the arrays produced here and nothing else.
+
+Data graphs stand in for the commonsense knowledge graphs of the thesis
+(Ch. 3, Sec. "Commonsense Knowledge as a Graph": triples become directed,
+relation-labelled edges; Sec. "Performance Evaluation": SenticNet, Gowalla and
+Enron, none of which ship here). Recipe, per graph:
+
+* out-degrees: i.i.d. discrete power law P(d) ~ d^-2.1 on [1, V-1], drawn by
+  inverse CDF, then corrected to exactly E edges (proportional scaling, then
+  largest-remainder +-1, keeping 1 <= d <= V-1);
+* destinations: d distinct uniform vertices other than the source (the graph
+  is simple: no parallel (src, dst) pairs, no self-loops);
+* vertex types: uniform over 64; edge relations: Zipf(1.2) over 32.
+
+Queries are grown on the data graph itself (random walk, random tree, star,
+or a tree plus extra data edges for cycles), keep each data vertex's type as
+the query vertex label and each data edge's relation and direction, and pin
+some vertices to their data vertex (concept nodes, Ch. 3 Sec. "Commonsense
+Graph Transformation"). Because every query is a copy of a piece of the data
+graph, it has at least one embedding.
+
+A query may be accepted only when H(q), the number of homomorphisms of its
+spanning tree under the label / pin / relation constraints, falls in a band;
+H(q) is an upper bound on the embeddings of that tree and is used purely to
+keep the sampled workloads enumerable.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+N_TYPES = 64
+N_RELS = 32
+DEG_EXPONENT = 2.1
+ZIPF_S = 1.2
+BASE_SEED = 180708804
+
+# Graph sizes of the synthetic workloads: name -> (vertices, edges, seed offset)
+GRAPHS = {
+    "tiny": (2_000, 8_000, 0),
+    "medium": (300_000, 1_600_000, 1),
+    "large": (4_000_000, 20_000_000, 2),
+}
+
+
+@dataclasses.dataclass
+class KG:
+    """A directed, edge-labelled, vertex-typed graph in int32 CSR form.
+
+    ``row_ptr[V+1]``, ``col[E]``, ``rel[E]``: out-adjacency, each row sorted by
+    (dst, rel). ``vtype[V]``: vertex type. ``in_ptr``/``in_col``/``in_rel``:
+    the same edges grouped by destination (used by the query generator only).
+    """
+
+    V: int
+    E: int
+    row_ptr: np.ndarray
+    col: np.ndarray
+    rel: np.ndarray
+    vtype: np.ndarray
+    in_ptr: np.ndarray | None = None
+    in_col: np.ndarray | None = None
+    in_rel: np.ndarray | None = None
+
+    def src(self) -> np.ndarray:
+        return np.repeat(np.arange(self.V, dtype=np.int32), np.diff(self.row_ptr))
+
+    def edge_list(self):
+        """(src, dst, rel) int32 triples, the form the oracle takes."""
+        return self.src(), self.col, self.rel
+
+    def ensure_in(self):
+        if self.in_ptr is None:
+            src = self.src()
+            order = np.lexsort((self.rel, src, self.col))  # by dst, then src, then rel
+            self.in_col = np.ascontiguousarray(src[order])
+            self.in_rel = np.ascontiguousarray(self.rel[order])
+            cnt = np.bincount(self.col, minlength=self.V)
+            self.in_ptr = np.zeros(self.V + 1, np.int64)
+            np.cumsum(cnt, out=self.in_ptr[1:])
+        return self
+
+
+@dataclasses.dataclass
+class Query:
+    """A query graph: ``n`` vertices, edges ``(src[i], dst[i], label[i])``.
+
+    ``vlabel[u]`` is a vertex type or -1 (any type); ``vpin[u]`` a data vertex
+    id (concept node) or -1 (variable node); ``elabel[i]`` a relation or -1
+    (variable edge). ``walk`` is the data vertex each query vertex was grown
+    from (a known embedding), kept for tests.
+    """
+
+    n: int
+    vlabel: np.ndarray
+    vpin: np.ndarray
+    esrc: np.ndarray
+    edst: np.ndarray
+    elabel: np.ndarray
+    walk: np.ndarray | None = None
+    shape: str = ""
+
+    @property
+    def m(self) -> int:
+        return int(len(self.esrc))
+
+    def as_dict(self):
+        return dict(n=self.n, vlabel=self.vlabel.tolist(), vpin=self.vpin.tolist(),
+                    esrc=self.esrc.tolist(), edst=self.edst.tolist(),
+                    elabel=self.elabel.tolist(), shape=self.shape,
+                    walk=None if self.walk is None else self.walk.tolist())
+
+    @staticmethod
+    def from_dict(d):
+        return Query(n=int(d["n"]), vlabel=np.asarray(d["vlabel"], np.int32),
+                     vpin=np.asarray(d["vpin"], np.int32),
+                     esrc=np.asarray(d["esrc"], np.int32),
+                     edst=np.asarray(d["edst"], np.int32),
+                     elabel=np.asarray(d["elabel"], np.int32),
+                     walk=None if d.get("walk") is None else np.asarray(d["walk"], np.int64),
+                     shape=d.get("shape", ""))
+
+
+# --------------------------------------------------------------------------
+# data graphs
+# --------------------------------------------------------------------------
+
+def _powerlaw_outdegrees(rng, V: int, E: int, alpha: float = DEG_EXPONENT) -> np.ndarray:
+    d = np.arange(1, V, dtype=np.float64)
+    cdf = np.cumsum(d ** -alpha)
+    cdf /= cdf[-1]
+    deg = np.searchsorted(cdf, rng.random(V), side="right").astype(np.int64) + 1
+    np.minimum(deg, V - 1, out=deg)
+    # proportional correction to exactly E, then largest remainder +-1
+    scaled = deg * (E / float(deg.sum()))
+    base = np.clip(np.floor(scaled).astype(np.int64), 1, V - 1)
+    frac = scaled - np.floor(scaled)
+    tie = rng.random(V)
+    for _ in range(64):
+        diff = int(E - base.sum())
+        if diff == 0:
+            break
+        if diff > 0:
+            elig = np.nonzero(base < V - 1)[0]
+            order = elig[np.lexsort((tie[elig], -frac[elig]))]
+            take = order[:diff]
+            base[take] += 1
+        else:
+            elig = np.nonzero(base > 1)[0]
+            order = elig[np.lexsort((tie[elig], frac[elig]))]
+            take = order[:-diff]
+            base[take] -= 1
+    if int(base.sum()) != E:
+        raise RuntimeError("degree correction did not converge")
+    return base
+
+
+def _distinct_destinations(rng, V: int, deg: np.ndarray) -> np.ndarray:
+    """For each source, deg[src] distinct uniform destinations != src,
+    returned grouped by source and ascending within each source."""
+    E = int(deg.sum())
+    src = np.repeat(np.arange(V, dtype=np.int64), deg)
+    dst = rng.integers(0, V - 1, size=E, dtype=np.int64)
+    dst += dst >= src
+    idx = np.arange(E, dtype=np.int64)  # edges still under duplicate check
+    for _ in range(10_000):
+        key = src[idx] * V + dst[idx]
+        order = np.argsort(key, kind="stable")
+        sk = key[order]
+        dupm = np.zeros(len(idx), bool)
+        dupm[order[1:]] = sk[1:] == sk[:-1]
+        nd = int(dupm.sum())
+        if nd == 0:
+            break
+        bad = idx[dupm]
+        new = rng.integers(0, V - 1, size=nd, dtype=np.int64)
+        new += new >= src[bad]
+        dst[bad] = new
+        # re-check only the rows that held a duplicate
+        rows = np.unique(src[bad])
+        rp = np.zeros(V + 1, np.int64)
+        np.cumsum(deg, out=rp[1:])
+        starts, ends = rp[rows], rp[rows + 1]
+        lens = ends - starts
+        idx = np.repeat(starts - np.concatenate(([0], np.cumsum(lens)[:-1])), lens) + np.arange(lens.sum())
+    else:
+        raise RuntimeError("destination sampling did not converge")
+    # sort within rows
+    order = np.lexsort((dst, src))
+    return dst[order]
+
+
+def make_graph(V: int, E: int, seed: int, n_types: int = N_TYPES, n_rels: int = N_RELS,
+               alpha: float = DEG_EXPONENT, zipf_s: float = ZIPF_S) -> KG:
+    """Draw a seeded power-law knowledge graph (recipe in the module doc)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    deg = _powerlaw_outdegrees(rng, V, E, alpha)
+    dst = _distinct_destinations(rng, V, deg)
+    k = np.arange(1, n_rels + 1, dtype=np.float64)
+    zcdf = np.cumsum(k ** -zipf_s)
+    zcdf /= zcdf[-1]
+    rel = np.searchsorted(zcdf, rng.random(E), side="right").astype(np.int32)
+    np.minimum(rel, n_rels - 1, out=rel)
+    vtype = rng.integers(0, n_types, size=V, dtype=np.int32)
+    row_ptr = np.zeros(V + 1, np.int64)
+    np.cumsum(deg, out=row_ptr[1:])
+    return KG(V=V, E=E, row_ptr=row_ptr.astype(np.int32), col=dst.astype(np.int32),
+              rel=rel, vtype=vtype)
+
+
+def named_graph(name: str) -> KG:
+    V, E, off = GRAPHS[name]
+    return make_graph(V, E, BASE_SEED + off)
+
+
+# --------------------------------------------------------------------------
+# queries
+# --------------------------------------------------------------------------
+
+def _out_row(g: KG, v: int):
+    a, b = int(g.row_ptr[v]), int(g.row_ptr[v + 1])
+    return g.col[a:b], g.rel[a:b]
+
+
+def _in_row(g: KG, v: int):
+    a, b = int(g.in_ptr[v]), int(g.in_ptr[v + 1])
+    return g.in_col[a:b], g.in_rel[a:b]
+
+
+def _has_edge(g: KG, x: int, y: int):
+    """Relation of data edge x->y, or None."""
+    cols, rels = _out_row(g, x)
+    i = int(np.searchsorted(cols, y))
+    if i < len(cols) and cols[i] == y:
+        return int(rels[i])
+    return None
+
+
+def _random_neighbour(g: KG, rng, x: int, exclude: set, tries: int = 32):
+    """A uniformly drawn undirected neighbour of x not in ``exclude``, with the
+    data edge joining them as (src, dst, rel); None if none found."""
+    oc, orl = _out_row(g, x)
+    ic, irl = _in_row(g, x)
+    no, ni = len(oc), len(ic)
+    tot = no + ni
+    if tot == 0:
+        return None
+    for _ in range(tries):
+        j = int(rng.integers(tot))
+        if j < no:
+            y, e = int(oc[j]), (x, int(oc[j]), int(orl[j]))
+        else:
+            y, e = int(ic[j - no]), (int(ic[j - no]), x, int(irl[j - no]))
+        if y not in exclude:
+            return y, e
+    if tot <= 4096:  # exhaustive fallback for small rows
+        cand = [(int(y), (x, int(y), int(r))) for y, r in zip(oc, orl) if int(y) not in exclude]
+        cand += [(int(y), (int(y), x, int(r))) for y, r in zip(ic, irl) if int(y) not in exclude]
+        if cand:
+            return cand[int(rng.integers(len(cand)))]
+    return None
+
+
+def _grow(g: KG, rng, n: int, shape: str):
+    """Grow n distinct data vertices and a spanning set of data edges."""
+    for _attempt in range(1000):
+        start = int(rng.integers(g.V))
+        verts = [start]
+        inset = {start}
+        edges = []
+        ok = True
+        if shape == "star":
+            oc, _ = _out_row(g, start)
+            ic, _ = _in_row(g, start)
+            if len(oc) + len(ic) < n - 1:
+                continue
+        while len(verts) < n:
+            if shape == "path":
+                x = verts[-1]
+            elif shape == "star":
+                x = start
+            else:
+                x = verts[int(rng.integers(len(verts)))]
+            r = _random_neighbour(g, rng, x, inset)
+            if r is None:
+                if shape in ("path", "star"):
+                    ok = False
+                    break
+                continue_tries = False
+                for x2 in rng.permutation(verts):
+                    r = _random_neighbour(g, rng, int(x2), inset)
+                    if r is not None:
+                        continue_tries = True
+                        break
+                if not continue_tries:
+                    ok = False
+                    break
+            y, e = r
+            verts.append(y)
+            inset.add(y)
+            edges.append(e)
+        if ok:
+            return verts, edges
+    raise RuntimeError("could not grow a query")
+
+
+def _extra_edges(g: KG, verts, edges):
+    """All data edges among ``verts`` that are not already in ``edges``."""
+    have = set((s, d) for s, d, _ in edges)
+    out = []
+    vs = set(verts)
+    for x in verts:
+        cols, rels = _out_row(g, x)
+        if len(cols) > 4 * len(verts):
+            for y in verts:
+                if y != x and (x, y) not in have:
+                    r = _has_edge(g, x, y)
+                    if r is not None:
+                        out.append((x, y, r))
+        else:
+            for y, r in zip(cols.tolist(), rels.tolist()):
+                if y in vs and (x, y) not in have:
+                    out.append((x, y, r))
+    return out
+
+
+def _to_query(g: KG, verts, edges, pins, shape) -> Query:
+    idx = {v: i for i, v in enumerate(verts)}
+    n = len(verts)
+    vlabel = g.vtype[np.asarray(verts, np.int64)].astype(np.int32)
+    vpin = np.full(n, -1, np.int32)
+    for p in pins:
+        vpin[p] = verts[p]
+    es = np.asarray([idx[s] for s, _, _ in edges], np.int32)
+    ed = np.asarray([idx[d] for _, d, _ in edges], np.int32)
+    el = np.asarray([r for _, _, r in edges], np.int32)
+    return Query(n=n, vlabel=vlabel, vpin=vpin, esrc=es, edst=ed, elabel=el,
+                 walk=np.asarray(verts, np.int64), shape=shape)
+
+
+def draw_query(g: KG, rng, n: int, shape: str, n_pins: int, n_cycles: int = 0) -> Query:
+    """One query of ``n`` vertices grown on ``g`` (module doc), with ``n_pins``
+    pinned vertices and, for shape "cyclic", ``n_cycles`` extra edges."""
+    g.ensure_in()
+    base = "tree" if shape == "cyclic" else shape
+    for _ in range(10_000):
+        verts, edges = _grow(g, rng, n, base)
+        if n_cycles > 0:
+            extra = _extra_edges(g, verts, edges)
+            if len(extra) < n_cycles:
+                continue
+            pick = rng.choice(len(extra), size=n_cycles, replace=False)
+            edges = edges + [extra[int(i)] for i in sorted(pick)]
+        pins = sorted(rng.choice(n, size=n_pins, replace=False).tolist()) if n_pins else []
+        return _to_query(g, verts, edges, pins, shape)
+    raise RuntimeError("could not draw a query")
+
+
+def draw_cyclic_dense(g: KG, rng, n: int, n_cycles: int, n_pins: int = 0,
+                      max_tries: int = 100_000) -> Query:
+    """A connected query of n vertices with n-1+n_cycles edges. Grows greedily
+    towards vertices with the most data edges into the chosen set so that the
+    cycles exist; cycles are sparse in these random graphs otherwise."""
+    g.ensure_in()
+    for _ in range(max_tries):
+        start = int(rng.integers(g.V))
+        verts = [start]
+        inset = {start}
+        edges = []
+        fail = False
+        while len(verts) < n:
+            # sample frontier
+            cand = {}
+            for x in verts:
+                for _k in range(8):
+                    r = _random_neighbour(g, rng, x, inset, tries=4)
+                    if r is not None:
+                        cand.setdefault(r[0], r[1])
+            if not cand:
+                fail = True
+                break
+            ys = list(cand.keys())
+            score = []
+            for y in ys:
+                s = 0
+                for x in verts:
+                    if _has_edge(g, x, y) is not None or _has_edge(g, y, x) is not None:
+                        s += 1
+                score.append(s)
+            best = max(score)
+            choices = [y for y, s in zip(ys, score) if s == best]
+            y = choices[int(rng.integers(len(choices)))]
+            verts.append(y)
+            inset.add(y)
+            edges.append(cand[y])
+        if fail:
+            continue
+        extra = _extra_edges(g, verts, edges)
+        if len(extra) < n_cycles:
+            continue
+        pick = rng.choice(len(extra), size=n_cycles, replace=False)
+        edges = edges + [extra[int(i)] for i in sorted(pick)]
+        pins = sorted(rng.choice(n, size=n_pins, replace=False).tolist()) if n_pins else []
+        return _to_query(g, verts, edges, pins, "cyclic")
+    raise RuntimeError("could not draw a cyclic query")
+
+
+# --------------------------------------------------------------------------
+# acceptance bound H(q)
+# --------------------------------------------------------------------------
+
+def tree_hom_bound(g: KG, q: Query) -> float:
+    """H(q): homomorphisms of a BFS spanning tree of q (rooted at query vertex
+    0) into g under the vertex-type, pin and relation constraints, by a sparse
+    post-order dynamic program. Float64 (overflow gives inf). Assumes g has no
+    parallel (src, dst) pairs, which holds for generated graphs."""
+    g.ensure_in()
+    n = q.n
+    adj = [[] for _ in range(n)]
+    for i in range(q.m):
+        a, b = int(q.esrc[i]), int(q.edst[i])
+        adj[a].append((b, i, True))    # a -> b: from a, follow out-edges
+        adj[b].append((a, i, False))   # from b, follow in-edges
+    parent = [-1] * n
+    pedge = [None] * n
+    order = [0]
+    seen = {0}
+    for u in order:
+        for v, i, fwd in adj[u]:
+            if v not in seen:
+                seen.add(v)
+                parent[v] = u
+                pedge[v] = (i, fwd)
+                order.append(v)
+    if len(order) != n:
+        raise ValueError("query not connected")
+
+    def base_support(u):
+        if q.vpin[u] >= 0:
+            p = int(q.vpin[u])
+            ok = q.vlabel[u] < 0 or g.vtype[p] == q.vlabel[u]
+            return np.asarray([p] if ok else [], np.int64), np.ones(1 if ok else 0)
+        if q.vlabel[u] >= 0:
+            s = np.nonzero(g.vtype == q.vlabel[u])[0]
+        else:
+            s = np.arange(g.V, dtype=np.int64)
+        return s.astype(np.int64), np.ones(len(s))
+
+    h = {}
+    for u in reversed(order):
+        sup, val = base_support(u)
+        for c in range(n):
+            if parent[c] != u:
+                continue
+            csup, cval = h.pop(c)
+            i, fwd = pedge[c]
+            lab = int(q.elabel[i])
+            # edge u->c (fwd) : s(v) = sum over out-edges v->x of h_c(x)
+            #   -> push h_c(x) along in-edges of x
+            ptr, nb, rl = (g.in_ptr, g.in_col, g.in_rel) if fwd else (g.row_ptr, g.col, g.rel)
+            if len(csup) == 0:
+                sup, val = sup[:0], val[:0]
+                break
+            st = ptr[csup].astype(np.int64)
+            ln = (ptr[csup + 1] - ptr[csup]).astype(np.int64)
+            tot = int(ln.sum())
+            if tot == 0:
+                sup, val = sup[:0], val[:0]
+                break
+            eidx = np.repeat(st - np.concatenate(([0], np.cumsum(ln)[:-1])), ln) + np.arange(tot)
+            w = np.repeat(cval, ln)
+            tgt = nb[eidx].astype(np.int64)
+            if lab >= 0:
+                keep = rl[eidx] == lab
+                tgt, w = tgt[keep], w[keep]
+            if len(tgt) == 0:
+                sup, val = sup[:0], val[:0]
+                break
+            ut, inv = np.unique(tgt, return_inverse=True)
+            sv = np.bincount(inv, weights=w)
+            # intersect with current support
+            common, ia, ib = np.intersect1d(sup, ut, assume_unique=True, return_indices=True)
+            sup, val = common, val[ia] * sv[ib]
+        h[u] = (sup, val)
+    return float(h[0][1].sum()) if len(h[0][1]) else 0.0
+
+
+# --------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------
+
+def tiny_query(g: KG, seed: int = BASE_SEED + 100) -> Query:
+    """One 4-vertex, 4-edge query (one cycle) with one pinned vertex."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return draw_cyclic_dense(g, rng, 4, 1, n_pins=1)
+
+
+def medium_queries(g: KG, count: int = 100, seed: int = BASE_SEED + 1 + 100,
+                   hmax: float = 1e7):
+    """Random-walk queries of 6..10 vertices, half paths and half trees, 0..2
+    pinned vertices, accepted when H(q) <= hmax."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    rejected = 0
+    while len(out) < count:
+        n = int(rng.integers(6, 11))
+        shape = "path" if len(out) % 2 == 0 else "tree"
+        pins = int(rng.integers(0, 3))
+        q = draw_query(g, rng, n, shape, pins)
+        if tree_hom_bound(g, q) <= hmax:
+            out.append(q)
+        else:
+            rejected += 1
+    return out, rejected

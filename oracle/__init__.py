@@ -1,0 +1,125 @@
+"""CPU oracle for exact subgraph matching -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The GPU library never imports, links
+or calls it, and the two share no code.
+
+The C file ``sgm_oracle.c`` holds the enumerator (definition of the result:
+thesis Ch. 3, Def. 3.1 / Def. 3.2, see the file header). This module only
+marshals numpy arrays through ctypes and compiles the C file on demand.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sgm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OR_OK, OR_EINVAL, OR_ENOMEM, OR_ETOOBIG = 0, -1, -2, -4
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (OpenMP, -O3)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-march=native", "-fopenmp", "-shared", "-fPIC",
+                               "-Wall", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        lib.oracle_graph_build.restype = ctypes.c_void_p
+        lib.oracle_graph_build.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, i32p]
+        lib.oracle_graph_free.argtypes = [ctypes.c_void_p]
+        lib.oracle_graph_num_edges.restype = ctypes.c_int64
+        lib.oracle_graph_num_edges.argtypes = [ctypes.c_void_p]
+        lib.oracle_match.restype = ctypes.c_int
+        lib.oracle_match.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, i32p, i32p,
+                                     i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int,
+                                     ctypes.POINTER(i32p), ctypes.POINTER(ctypes.c_int64)]
+        lib.oracle_free.argtypes = [ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+def _i32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, n_rows=0):
+        super().__init__(f"oracle error {code}")
+        self.code = code
+        self.n_rows = n_rows
+
+
+class Graph:
+    """The oracle's own adjacency, built from a raw (src, dst, rel) triple
+    list; duplicate triples collapse into one edge."""
+
+    def __init__(self, V: int, src, dst, rel, vtype):
+        lib = _load()
+        self._keep = [_i32(src), _i32(dst), _i32(rel), _i32(vtype)]
+        (s, sp), (d, dp), (r, rp), (t, tp) = self._keep
+        if not (len(s) == len(d) == len(r)) or len(t) != V:
+            raise ValueError("array lengths")
+        self.V = int(V)
+        self._h = lib.oracle_graph_build(int(V), int(len(s)), sp, dp, rp, tp)
+        if not self._h:
+            raise ValueError("invalid graph")
+        self._keep = None
+        self.E = int(lib.oracle_graph_num_edges(self._h))
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _load().oracle_graph_free(self._h)
+            self._h = None
+
+    def match(self, n, vlabel, vpin, esrc, edst, elabel, max_rows: int = -1,
+              nthreads: int = 0, count_only: bool = False):
+        """All matches as an [rows, n] int32 array in ascending lexicographic
+        order (or the count if ``count_only``)."""
+        lib = _load()
+        (vl, vlp), (vp, vpp) = _i32(vlabel), _i32(vpin)
+        (es, esp), (ed, edp), (el, elp) = _i32(esrc), _i32(edst), _i32(elabel)
+        if len(vl) != n or len(vp) != n or not (len(es) == len(ed) == len(el)):
+            raise ValueError("query array lengths")
+        rows = ctypes.POINTER(ctypes.c_int32)()
+        nrows = ctypes.c_int64(0)
+        rc = lib.oracle_match(self._h, int(n), int(len(es)), vlp, vpp, esp, edp, elp,
+                              int(max_rows), int(nthreads),
+                              None if count_only else ctypes.byref(rows), ctypes.byref(nrows))
+        if rc != OR_OK:
+            raise OracleError(rc, nrows.value)
+        if count_only:
+            return int(nrows.value)
+        k = int(nrows.value)
+        out = np.empty((k, n), np.int32)
+        if k:
+            ctypes.memmove(out.ctypes.data, rows, k * n * 4)
+        lib.oracle_free(rows)
+        return out
+
+    def match_query(self, q, **kw):
+        """Same as :meth:`match` for a ``kggen.Query``-like object."""
+        return self.match(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel, **kw)
+
+
+def graph_from_kg(kg) -> Graph:
+    s, d, r = kg.edge_list()
+    return Graph(kg.V, s, d, r, kg.vtype)

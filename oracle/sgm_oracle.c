@@ -1,0 +1,469 @@
+/*
+ * CPU oracle for exact subgraph matching -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the package smoke check and the benchmark's
+ * CPU-baseline leg may load this library. The GPU product path never calls
+ * it, never links it and shares no code, header or table with it.
+ *
+ * What it computes (thesis Ch. 3, Def. 3.1 and Def. 3.2, with the readings
+ * listed below): given a data graph -- vertices 0..V-1 with a type each and a
+ * SET of directed, relation-labelled edges (s, d, r) -- and a query graph --
+ * vertices 0..n-1 with a type label or -1 (any type), a pin (concept node,
+ * Ch. 3 "Commonsense Graph Transformation") or -1 (variable node), and
+ * directed edges (a, b, rho) with a relation or -1 (variable edge) -- the
+ * result is the set of all maps f: {0..n-1} -> V such that
+ *   1. f is injective                                      (Def. 3.2);
+ *   2. label(u) = -1 or type(f(u)) = label(u)              (Def. 3.2);
+ *   3. pin(u)   = -1 or f(u) = pin(u)                      (concept nodes);
+ *   4. for every query edge (a, b, rho) some data edge (f(a), f(b), r)
+ *      exists with rho = -1 or r = rho (directed, non-induced).
+ * Each f is one row (f(0), ..., f(n-1)); rows are unique and returned in
+ * ascending lexicographic order. Several data relations between the same
+ * pair still give one row, because a match is the vertex map.
+ *
+ * How: plain depth-first backtracking over the query vertices in a fixed
+ * connected order, testing each condition above directly. It performs no
+ * candidate filtering of any kind: every check is one clause of the
+ * definition. OpenMP splits the work over the candidates of the first vertex.
+ *
+ * Parity pins (tests): brute-force enumeration of all V^n maps on micro
+ * graphs, closed-form counts (complete digraphs, directed cycles, stars,
+ * trace(A^3) and friends via scipy.sparse), and networkx's monomorphism
+ * matcher on small simple graphs.
+ */
+#define _GNU_SOURCE
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define OR_OK 0
+#define OR_EINVAL -1
+#define OR_ENOMEM -2
+#define OR_ETOOBIG -4
+#define OR_MAXQ 32
+
+typedef struct {
+    int32_t dst;
+    int32_t rel;
+} or_pair;
+
+typedef struct oracle_graph {
+    int32_t V;
+    int64_t E;          /* distinct triples */
+    int64_t *out_off;   /* [V+1] */
+    or_pair *out;       /* sorted by (dst, rel) within each source */
+    int64_t *in_off;    /* [V+1] */
+    or_pair *in;        /* (src, rel) sorted within each destination */
+    int32_t *vtype;     /* [V] */
+} oracle_graph;
+
+static int pair_cmp(const void *a, const void *b) {
+    const or_pair *x = (const or_pair *)a, *y = (const or_pair *)b;
+    if (x->dst != y->dst) return x->dst < y->dst ? -1 : 1;
+    if (x->rel != y->rel) return x->rel < y->rel ? -1 : 1;
+    return 0;
+}
+
+/* Group (key, other, rel) triples by key with a counting pass, sort each
+ * group by (other, rel) and drop exact duplicates. Returns the number of
+ * distinct triples, fills off[V+1] and arr. */
+static int64_t group_edges(int32_t V, int64_t E, const int32_t *key, const int32_t *other,
+                           const int32_t *rel, int64_t *off, or_pair *arr) {
+    memset(off, 0, sizeof(int64_t) * ((size_t)V + 1));
+    for (int64_t i = 0; i < E; i++) off[key[i] + 1]++;
+    for (int32_t v = 0; v < V; v++) off[v + 1] += off[v];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * ((size_t)V + 1));
+    if (!fill) return -1;
+    memcpy(fill, off, sizeof(int64_t) * ((size_t)V + 1));
+    for (int64_t i = 0; i < E; i++) {
+        or_pair p;
+        p.dst = other[i];
+        p.rel = rel[i];
+        arr[fill[key[i]]++] = p;
+    }
+    free(fill);
+    /* sort + dedupe each group, compacting in place */
+    int64_t w = 0;
+    int64_t start = 0;
+    for (int32_t v = 0; v < V; v++) {
+        int64_t end = off[v + 1];
+        int64_t len = end - start;
+        if (len > 1) qsort(arr + start, (size_t)len, sizeof(or_pair), pair_cmp);
+        int64_t row_begin = w;
+        for (int64_t i = start; i < end; i++) {
+            if (w > row_begin && arr[w - 1].dst == arr[i].dst && arr[w - 1].rel == arr[i].rel) continue;
+            arr[w++] = arr[i];
+        }
+        off[v] = row_begin;
+        start = end;
+    }
+    off[V] = w;
+    return w;
+}
+
+void oracle_graph_free(oracle_graph *g) {
+    if (!g) return;
+    free(g->out_off);
+    free(g->out);
+    free(g->in_off);
+    free(g->in);
+    free(g->vtype);
+    free(g);
+}
+
+/* Build the oracle's own adjacency from a raw triple list. Duplicate triples
+ * collapse (the edge set of Def. 3.1). Returns NULL on bad input. */
+oracle_graph *oracle_graph_build(int32_t V, int64_t E, const int32_t *src, const int32_t *dst,
+                                 const int32_t *rel, const int32_t *vtype) {
+    if (V <= 0 || E < 0) return NULL;
+    for (int64_t i = 0; i < E; i++)
+        if (src[i] < 0 || src[i] >= V || dst[i] < 0 || dst[i] >= V || rel[i] < 0) return NULL;
+    for (int32_t v = 0; v < V; v++)
+        if (vtype[v] < 0) return NULL;
+    oracle_graph *g = (oracle_graph *)calloc(1, sizeof(oracle_graph));
+    if (!g) return NULL;
+    g->V = V;
+    g->out_off = (int64_t *)malloc(sizeof(int64_t) * ((size_t)V + 1));
+    g->in_off = (int64_t *)malloc(sizeof(int64_t) * ((size_t)V + 1));
+    g->out = (or_pair *)malloc(sizeof(or_pair) * (size_t)(E > 0 ? E : 1));
+    g->in = (or_pair *)malloc(sizeof(or_pair) * (size_t)(E > 0 ? E : 1));
+    g->vtype = (int32_t *)malloc(sizeof(int32_t) * (size_t)V);
+    if (!g->out_off || !g->in_off || !g->out || !g->in || !g->vtype) {
+        oracle_graph_free(g);
+        return NULL;
+    }
+    memcpy(g->vtype, vtype, sizeof(int32_t) * (size_t)V);
+    int64_t e1 = group_edges(V, E, src, dst, rel, g->out_off, g->out);
+    int64_t e2 = group_edges(V, E, dst, src, rel, g->in_off, g->in);
+    if (e1 < 0 || e2 < 0 || e1 != e2) {
+        oracle_graph_free(g);
+        return NULL;
+    }
+    g->E = e1;
+    return g;
+}
+
+int64_t oracle_graph_num_edges(const oracle_graph *g) { return g ? g->E : -1; }
+
+/* Does the data edge x -> y exist with relation rho (rho = -1: any)? */
+static int has_edge(const oracle_graph *g, int32_t x, int32_t y, int32_t rho) {
+    int64_t lo = g->out_off[x], hi = g->out_off[x + 1];
+    /* first entry with (dst, rel) >= (y, rho or -inf) */
+    int32_t r0 = rho < 0 ? INT32_MIN : rho;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        const or_pair *p = &g->out[mid];
+        if (p->dst < y || (p->dst == y && p->rel < r0)) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo >= g->out_off[x + 1]) return 0;
+    const or_pair *p = &g->out[lo];
+    if (p->dst != y) return 0;
+    return rho < 0 || p->rel == rho;
+}
+
+typedef struct {
+    int32_t n, m;
+    const int32_t *vlabel, *vpin, *esrc, *edst, *elabel;
+    int32_t order[OR_MAXQ];
+    int32_t pos[OR_MAXQ];          /* pos[u] = depth of u in order */
+} or_query;
+
+typedef struct {
+    int32_t *rows;
+    int64_t n_rows, cap;
+    int failed;
+} or_buf;
+
+static int buf_push(or_buf *b, const int32_t *row, int32_t n) {
+    if (b->n_rows == b->cap) {
+        int64_t nc = b->cap ? b->cap * 2 : 1024;
+        int32_t *nr = (int32_t *)realloc(b->rows, sizeof(int32_t) * (size_t)nc * (size_t)n);
+        if (!nr) return -1;
+        b->rows = nr;
+        b->cap = nc;
+    }
+    memcpy(b->rows + (size_t)b->n_rows * (size_t)n, row, sizeof(int32_t) * (size_t)n);
+    b->n_rows++;
+    return 0;
+}
+
+/* Clauses 1-4 of the definition for query vertex u mapped to data vertex x,
+ * against every query vertex placed earlier in the order. */
+static int consistent(const oracle_graph *g, const or_query *q, const int32_t *f, int depth, int32_t u,
+                      int32_t x) {
+    if (q->vlabel[u] >= 0 && g->vtype[x] != q->vlabel[u]) return 0;
+    if (q->vpin[u] >= 0 && x != q->vpin[u]) return 0;
+    for (int d = 0; d < depth; d++)
+        if (f[q->order[d]] == x) return 0;
+    for (int i = 0; i < q->m; i++) {
+        int32_t a = q->esrc[i], b = q->edst[i];
+        if (a == u && q->pos[b] < depth) {
+            if (!has_edge(g, x, f[b], q->elabel[i])) return 0;
+        } else if (b == u && q->pos[a] < depth) {
+            if (!has_edge(g, f[a], x, q->elabel[i])) return 0;
+        }
+    }
+    return 1;
+}
+
+typedef struct {
+    const oracle_graph *g;
+    const or_query *q;
+    or_buf *buf;
+    int count_only;
+    int64_t max_rows;
+    int64_t *total;   /* shared running count */
+    int *abort_flag;
+} or_ctx;
+
+static void dfs(or_ctx *c, int32_t *f, int depth) {
+    const or_query *q = c->q;
+    const oracle_graph *g = c->g;
+    if (__atomic_load_n(c->abort_flag, __ATOMIC_RELAXED)) return;
+    if (depth == q->n) {
+        int64_t t = __atomic_add_fetch(c->total, 1, __ATOMIC_RELAXED);
+        if (c->max_rows >= 0 && t > c->max_rows) {
+            __atomic_store_n(c->abort_flag, 1, __ATOMIC_RELAXED);
+            return;
+        }
+        if (!c->count_only && buf_push(c->buf, f, q->n) != 0) {
+            c->buf->failed = 1;
+            __atomic_store_n(c->abort_flag, 1, __ATOMIC_RELAXED);
+        }
+        return;
+    }
+    int32_t u = q->order[depth];
+    if (q->vpin[u] >= 0) {
+        int32_t x = q->vpin[u];
+        if (consistent(g, q, f, depth, u, x)) {
+            f[u] = x;
+            dfs(c, f, depth + 1);
+        }
+        return;
+    }
+    /* generate from the already-placed neighbour with the shortest data row */
+    int best_len_set = 0;
+    int64_t best_lo = 0, best_hi = 0;
+    const or_pair *best_arr = NULL;
+    for (int i = 0; i < q->m; i++) {
+        int32_t a = q->esrc[i], b = q->edst[i];
+        int64_t lo, hi;
+        const or_pair *arr;
+        if (b == u && q->pos[a] < depth) { /* f(a) -> x : x among out-neighbours of f(a) */
+            lo = g->out_off[f[a]];
+            hi = g->out_off[f[a] + 1];
+            arr = g->out;
+        } else if (a == u && q->pos[b] < depth) { /* x -> f(b) : x among in-neighbours */
+            lo = g->in_off[f[b]];
+            hi = g->in_off[f[b] + 1];
+            arr = g->in;
+        } else {
+            continue;
+        }
+        if (!best_len_set || hi - lo < best_hi - best_lo) {
+            best_len_set = 1;
+            best_lo = lo;
+            best_hi = hi;
+            best_arr = arr;
+        }
+    }
+    if (!best_len_set) return; /* unreachable for connected queries past depth 0 */
+    int32_t prev = -1;
+    for (int64_t k = best_lo; k < best_hi; k++) {
+        int32_t x = best_arr[k].dst;
+        if (x == prev) continue; /* same neighbour, other relation */
+        prev = x;
+        if (consistent(g, q, f, depth, u, x)) {
+            f[u] = x;
+            dfs(c, f, depth + 1);
+            if (__atomic_load_n(c->abort_flag, __ATOMIC_RELAXED)) return;
+        }
+    }
+}
+
+static int row_cmp(const void *a, const void *b, void *arg) {
+    const int32_t *x = (const int32_t *)a, *y = (const int32_t *)b;
+    int n = *(const int *)arg;
+    for (int i = 0; i < n; i++)
+        if (x[i] != y[i]) return x[i] < y[i] ? -1 : 1;
+    return 0;
+}
+
+/* Validate a query: 1..32 vertices, edge endpoints in range, no self-loop,
+ * connected as an undirected graph. */
+static int query_ok(int32_t V, int32_t n, int32_t m, const int32_t *vpin, const int32_t *esrc,
+                    const int32_t *edst) {
+    if (n < 1 || n > OR_MAXQ || m < 0) return 0;
+    for (int u = 0; u < n; u++)
+        if (vpin[u] >= V) return 0;
+    for (int i = 0; i < m; i++) {
+        if (esrc[i] < 0 || esrc[i] >= n || edst[i] < 0 || edst[i] >= n) return 0;
+        if (esrc[i] == edst[i]) return 0;
+    }
+    int seen[OR_MAXQ] = {0}, stack[OR_MAXQ], sp = 0, cnt = 1;
+    seen[0] = 1;
+    stack[sp++] = 0;
+    while (sp) {
+        int u = stack[--sp];
+        for (int i = 0; i < m; i++) {
+            int v = -1;
+            if (esrc[i] == u) v = edst[i];
+            else if (edst[i] == u) v = esrc[i];
+            if (v >= 0 && !seen[v]) {
+                seen[v] = 1;
+                cnt++;
+                stack[sp++] = v;
+            }
+        }
+    }
+    return cnt == n;
+}
+
+/*
+ * All matches of the query in g (definition in the file header).
+ * rows_out: if non-NULL receives a malloc'd row-major [n_rows][n] int32
+ *           table, unique rows in ascending lexicographic order (free with
+ *           oracle_free); if NULL only the count is produced.
+ * max_rows: stop with OR_ETOOBIG once more rows than this exist (-1: no cap).
+ * nthreads: OpenMP threads (<= 0: runtime default).
+ * Returns OR_OK, OR_EINVAL (malformed query), OR_ENOMEM or OR_ETOOBIG.
+ */
+int oracle_match(const oracle_graph *g, int32_t n, int32_t m, const int32_t *vlabel,
+                 const int32_t *vpin, const int32_t *esrc, const int32_t *edst,
+                 const int32_t *elabel, int64_t max_rows, int nthreads, int32_t **rows_out,
+                 int64_t *nrows_out) {
+    if (!g || !nrows_out) return OR_EINVAL;
+    *nrows_out = 0;
+    if (rows_out) *rows_out = NULL;
+    if (!query_ok(g->V, n, m, vpin, esrc, edst)) return OR_EINVAL;
+    or_query q;
+    q.n = n;
+    q.m = m;
+    q.vlabel = vlabel;
+    q.vpin = vpin;
+    q.esrc = esrc;
+    q.edst = edst;
+    q.elabel = elabel;
+    /* root: the lowest-index pinned vertex, else the vertex whose type
+     * matches the fewest data vertices (lowest index on ties) */
+    int32_t root = -1;
+    for (int u = 0; u < n && root < 0; u++)
+        if (vpin[u] >= 0) root = u;
+    if (root < 0) {
+        int64_t best = -1;
+        for (int u = 0; u < n; u++) {
+            int64_t c = 0;
+            if (vlabel[u] < 0) c = g->V;
+            else
+                for (int32_t v = 0; v < g->V; v++) c += g->vtype[v] == vlabel[u];
+            if (best < 0 || c < best) {
+                best = c;
+                root = u;
+            }
+        }
+    }
+    /* BFS order over the undirected query graph, neighbours by index */
+    int placed[OR_MAXQ] = {0};
+    int head = 0, tail = 0;
+    q.order[tail++] = root;
+    placed[root] = 1;
+    while (head < tail) {
+        int32_t u = q.order[head++];
+        for (int32_t v = 0; v < n; v++) {
+            if (placed[v]) continue;
+            int adj = 0;
+            for (int i = 0; i < m && !adj; i++)
+                adj = (esrc[i] == u && edst[i] == v) || (esrc[i] == v && edst[i] == u);
+            if (adj) {
+                placed[v] = 1;
+                q.order[tail++] = v;
+            }
+        }
+    }
+    for (int d = 0; d < n; d++) q.pos[q.order[d]] = d;
+
+    /* first-level candidates */
+    int32_t *roots = NULL;
+    int64_t n_roots = 0;
+    if (vpin[root] >= 0) {
+        roots = (int32_t *)malloc(sizeof(int32_t));
+        if (!roots) return OR_ENOMEM;
+        roots[0] = vpin[root];
+        n_roots = 1;
+    } else {
+        roots = (int32_t *)malloc(sizeof(int32_t) * (size_t)g->V);
+        if (!roots) return OR_ENOMEM;
+        for (int32_t v = 0; v < g->V; v++)
+            if (vlabel[root] < 0 || g->vtype[v] == vlabel[root]) roots[n_roots++] = v;
+    }
+
+    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+    or_buf *bufs = (or_buf *)calloc((size_t)nt, sizeof(or_buf));
+    if (!bufs) {
+        free(roots);
+        return OR_ENOMEM;
+    }
+    int64_t total = 0;
+    int abort_flag = 0;
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = omp_get_thread_num();
+        or_ctx c;
+        c.g = g;
+        c.q = &q;
+        c.buf = &bufs[tid];
+        c.count_only = rows_out == NULL;
+        c.max_rows = max_rows;
+        c.total = &total;
+        c.abort_flag = &abort_flag;
+        int32_t f[OR_MAXQ];
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < n_roots; i++) {
+            if (__atomic_load_n(&abort_flag, __ATOMIC_RELAXED)) continue;
+            int32_t x = roots[i];
+            if (!consistent(g, &q, f, 0, root, x)) continue;
+            f[root] = x;
+            dfs(&c, f, 1);
+        }
+    }
+    free(roots);
+    int failed = 0;
+    for (int t = 0; t < nt; t++) failed |= bufs[t].failed;
+    if (failed) {
+        for (int t = 0; t < nt; t++) free(bufs[t].rows);
+        free(bufs);
+        return OR_ENOMEM;
+    }
+    if (abort_flag) {
+        for (int t = 0; t < nt; t++) free(bufs[t].rows);
+        free(bufs);
+        *nrows_out = total;
+        return OR_ETOOBIG;
+    }
+    *nrows_out = total;
+    if (rows_out) {
+        int32_t *all = (int32_t *)malloc(sizeof(int32_t) * (size_t)(total > 0 ? total : 1) * (size_t)n);
+        if (!all) {
+            for (int t = 0; t < nt; t++) free(bufs[t].rows);
+            free(bufs);
+            return OR_ENOMEM;
+        }
+        int64_t off = 0;
+        for (int t = 0; t < nt; t++) {
+            if (bufs[t].n_rows)
+                memcpy(all + (size_t)off * (size_t)n, bufs[t].rows,
+                       sizeof(int32_t) * (size_t)bufs[t].n_rows * (size_t)n);
+            off += bufs[t].n_rows;
+        }
+        int nn = n;
+        if (total > 1) qsort_r(all, (size_t)total, sizeof(int32_t) * (size_t)n, row_cmp, &nn);
+        *rows_out = all;
+    }
+    for (int t = 0; t < nt; t++) free(bufs[t].rows);
+    free(bufs);
+    return OR_OK;
+}
+
+void oracle_free(void *p) { free(p); }
