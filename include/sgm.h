@@ -1,0 +1,208 @@
+/*
+ * sgm.h -- C ABI of the MI355X (gfx950) subgraph-matching library.
+ *
+ * The library finds every embedding of a small labelled query graph in a
+ * large directed, relation-labelled, vertex-typed data graph with the
+ * filtering-and-joining method of the thesis (Ch. 3, Sec. "Subgraph
+ * Similarity Search", Alg. 3.1): plan on the host, initialise and refine
+ * per-query-vertex candidate sets on the GPU (Alg. 3.2 and Sec. "Candidate
+ * Nodes Refinement"), collect candidate edges per query edge (Sec. "Joining
+ * Phase", two-step output), and join them into full matches.
+ *
+ * Conventions for every entry point:
+ *  - ids, labels and CSR offsets are int32; counts that can pass 2^31 are
+ *    int64;
+ *  - pointer arguments are HOST pointers; the library copies what it needs
+ *    during the call, so the caller may free its arrays on return;
+ *  - objects the library returns (graphs, results) are library-owned and
+ *    freed only with the matching sgm_free_* call (NULL is accepted);
+ *  - the return value is SGM_OK (0) or a negative SGM_E* code; on error
+ *    every output pointer is set to NULL; no C++ exception crosses the ABI;
+ *  - a graph is immutable after load; calls on one graph are serialised
+ *    internally, so several threads may share it.
+ */
+#ifndef SGM_H
+#define SGM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SGM_OK 0
+#define SGM_EINVAL (-1)       /* malformed CSR or query (see each call) */
+#define SGM_ENOMEM (-2)       /* host or device allocation failed / admission refused */
+#define SGM_EDEVICE (-3)      /* a HIP call failed; sgm_last_error() has the text */
+#define SGM_ETOOBIG (-4)      /* result rows exceed options.result_cap_rows */
+#define SGM_EUNSUPPORTED (-5) /* query beyond the library's limits */
+
+#define SGM_MAX_QV 16 /* query vertices */
+#define SGM_MAX_QE 64 /* query edges */
+
+/* sgm_match_* flags */
+#define SGM_SORTED 0u     /* default: rows unique, ascending lexicographic */
+#define SGM_COUNT_ONLY 1u /* only n_rows (rows == NULL) */
+
+typedef struct sgm_graph sgm_graph;
+
+/* Tuning knobs; sgm_default_options() fills the defaults. */
+typedef struct {
+    int32_t device;            /* HIP device ordinal (default 0) */
+    int32_t refine_rounds;     /* refinement rounds after initialisation (default 1;
+                                  -1 = repeat until no candidate is removed) */
+    int32_t refine_reversed;   /* 1 (default): refine in reversed visit order */
+    int32_t low_conn_degree;   /* query vertices of at most this many distinct
+                                  neighbours are skipped by refinement (default 1) */
+    int64_t result_cap_rows;   /* > 0: fail with SGM_ETOOBIG above this many rows */
+    int64_t join_budget_bytes; /* > 0: bound on one join level's output table;
+                                  larger levels are processed in chunks */
+    int32_t profile;           /* 1: time every kernel launch with HIP events
+                                  (sgm_kernel_stats) */
+    int32_t reserved[7];
+} sgm_options;
+
+/* A query graph (thesis Ch. 3, Sec. "Commonsense Graph Transformation" and
+ * Def. 3.2): 1..SGM_MAX_QV vertices, 0..SGM_MAX_QE directed edges.
+ *   vertex_label[u]: vertex type >= 0, or -1 for any type;
+ *   vertex_pin[u]:   data vertex id (a concept node), or -1 (variable node);
+ *   edge_src/dst[i]: query vertex indices, src != dst;
+ *   edge_label[i]:   relation >= 0, or -1 (variable edge: any relation).
+ * The query must be connected as an undirected graph and may not repeat an
+ * identical (src, dst, label) edge. */
+typedef struct {
+    int32_t n_vertices;
+    int32_t n_edges;
+    const int32_t *vertex_label;
+    const int32_t *vertex_pin;
+    const int32_t *edge_src;
+    const int32_t *edge_dst;
+    const int32_t *edge_label;
+} sgm_query;
+
+/* Per-query statistics (filled for every successful or ETOOBIG result). */
+typedef struct {
+    int64_t cand[SGM_MAX_QV];      /* final candidate-set size per query vertex */
+    int64_t ec[SGM_MAX_QE];        /* candidate-edge count per query edge */
+    int64_t level_rows[SGM_MAX_QV];/* rows after each join level (level 0 = seed keys) */
+    int32_t join_order[SGM_MAX_QV];/* query vertex bound at each join level */
+    int32_t visit_order[SGM_MAX_QV];/* filtering visit order O; -1 padded */
+    int64_t peak_rows;             /* largest intermediate table, rows */
+    int64_t peak_bytes;            /* largest intermediate table, bytes */
+    int32_t n_chunks;              /* join chunks (1 = no chunking) */
+    int32_t n_launches;            /* kernel launches for this query */
+    int64_t ns_total;              /* host wall time of the call */
+    int64_t ns_filter, ns_collect, ns_join, ns_finish;
+} sgm_stats;
+
+typedef struct {
+    int32_t status;   /* SGM_OK or an SGM_E* code (batch members) */
+    int32_t n_cols;   /* = query n_vertices; column u holds f(u) */
+    int64_t n_rows;   /* number of matches (exact, also for ETOOBIG) */
+    int32_t *rows;    /* host, row-major [n_rows][n_cols], unique, ascending
+                         lexicographic; non-NULL (also for 0 rows) on SGM_OK
+                         without SGM_COUNT_ONLY, NULL otherwise */
+    sgm_stats stats;
+} sgm_result;
+
+/* Per-kernel timing, accumulated while options.profile = 1. */
+typedef struct {
+    int64_t launches;
+    double ms_total;      /* sum of HIP-event durations on the library stream */
+    double bytes_total;   /* algorithmic bytes (what the step must move) */
+} sgm_kstat;
+
+#define SGM_K_CHECK 0     /* candidate initialisation sweep (label/degree) */
+#define SGM_K_COLLECT 1   /* bitmap -> sorted candidate list + rank table */
+#define SGM_K_EXPLORE 2   /* prune + push along spanning-tree edges */
+#define SGM_K_REFINE 3    /* prune over all query edges */
+#define SGM_K_EC_COUNT 4  /* candidate edges, count pass */
+#define SGM_K_EC_WRITE 5  /* candidate edges, write pass */
+#define SGM_K_JOIN 6      /* join levels (fan, count, write) */
+#define SGM_K_SORT 7      /* final ordering */
+#define SGM_K_OTHER 8     /* scans, clears, gathers */
+#define SGM_K_COUNT 9
+
+/* Fill *o with the defaults documented above. */
+void sgm_default_options(sgm_options *o);
+
+/*
+ * Load a data graph onto the device (thesis Ch. 3: nodes array + edges array
+ * + node-label and edge-label arrays; Sec. "GpSense" optimisations: both an
+ * outgoing and an incoming graph).
+ *   row_ptr[n_vertices+1]: out-CSR offsets, row_ptr[0] = 0, non-decreasing,
+ *                          row_ptr[n_vertices] = n_edges;
+ *   col[n_edges]:  destination of each edge, 0 <= col < n_vertices;
+ *   rel[n_edges]:  relation label >= 0;
+ *   type[n_vertices]: vertex type >= 0.
+ * Rows may be unsorted and may repeat a (dst, rel) pair: the library sorts
+ * each row by (dst, rel), drops exact duplicate triples (the edge set of
+ * Def. 3.1) and builds the incoming CSR. Self-loops are kept (they never
+ * match, since matches are injective).
+ * opts may be NULL (defaults). Errors: SGM_EINVAL for malformed CSR,
+ * SGM_ENOMEM, SGM_EDEVICE. On success *out owns all device memory.
+ */
+int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
+                   const int32_t *col, const int32_t *rel, const int32_t *type,
+                   const sgm_options *opts, sgm_graph **out);
+
+/*
+ * All matches of q in g (thesis Alg. 3.1; result contract of Def. 3.2: f
+ * injective, type labels and pins respected, every query edge present in
+ * the data graph with its relation or any relation for -1).
+ * flags: SGM_SORTED (0) or SGM_COUNT_ONLY.
+ * Errors: SGM_EINVAL (disconnected query, self-loop, index out of range,
+ * duplicate edge, pin out of range), SGM_EUNSUPPORTED (more than
+ * SGM_MAX_QV vertices or SGM_MAX_QE edges), SGM_ETOOBIG (then *out still
+ * holds the exact n_rows and stats, rows = NULL), SGM_ENOMEM, SGM_EDEVICE.
+ * On SGM_OK or SGM_ETOOBIG, *out is a library-owned result.
+ */
+int sgm_match_query(sgm_graph *g, const sgm_query *q, uint32_t flags, sgm_result **out);
+
+/*
+ * n queries at once; out[i] receives one result per query (free each with
+ * sgm_free_result). A failure of one query is reported in out[i]->status
+ * and does not affect the others; the call itself returns SGM_OK unless
+ * the arguments are invalid (SGM_EINVAL) or a global failure occurs.
+ */
+int sgm_match_batch(sgm_graph *g, const sgm_query *qs, int32_t n, uint32_t flags,
+                    sgm_result **out);
+
+void sgm_free_result(sgm_result *r);
+void sgm_free_graph(sgm_graph *g);
+
+/* Static text for an SGM_E* code. */
+const char *sgm_strerror(int code);
+/* Text of the last SGM_EDEVICE / SGM_EINVAL detail on this thread. */
+const char *sgm_last_error(void);
+
+/* Graph properties after load (deduplicated edge count etc.). */
+int sgm_graph_info(const sgm_graph *g, int32_t *n_vertices, int64_t *n_edges,
+                   int32_t *max_out_degree, int32_t *max_in_degree);
+
+/* Per-kernel timing accumulated since load or the last reset
+ * (options.profile = 1). kernel is one of SGM_K_*. */
+int sgm_kernel_stats(sgm_graph *g, int32_t kernel, sgm_kstat *out);
+int sgm_reset_kernel_stats(sgm_graph *g);
+
+/*
+ * Query plan on the host only (no device needed), thesis Ch. 3 Sec. "Query
+ * Plan Generation" with the commonsense variant of Sec. "GpSense":
+ * rank f(u) = deg(u) / freq(u), freq = 1 for a pinned vertex, else the number
+ * of data vertices of u's type (type_freq[label], or n_vertices for -1).
+ *   type_freq[n_types]: data vertex count per type;
+ *   visit_order[SGM_MAX_QV]: out, the expanded vertices O, -1 padded;
+ *   parent[SGM_MAX_QV]: out, spanning-tree parent (-1 for the root);
+ *   parent_edge[SGM_MAX_QV]: out, query edge joining u to its parent (-1);
+ *   init_order[SGM_MAX_QV]: out, the order in which vertices obtain
+ *                           candidate sets.
+ * Errors as for sgm_match_query's query checks.
+ */
+int sgm_plan_query(const sgm_query *q, int32_t n_vertices, const int64_t *type_freq,
+                   int32_t n_types, int32_t *visit_order, int32_t *parent,
+                   int32_t *parent_edge, int32_t *init_order);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGM_H */

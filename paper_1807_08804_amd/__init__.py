@@ -1,0 +1,298 @@
+"""Python binding of the MI355X subgraph-matching library (``libsgm.so``).
+
+Argument marshalling only: every step of a match runs in the library's HIP
+kernels. The entry points keep the C names of ``include/sgm.h``
+(``sgm_load_graph``, ``sgm_match_query``, ``sgm_match_batch``,
+``sgm_free_result``, ...); :class:`Graph` wraps them for numpy callers.
+
+Importing this package never compiles anything; ``build()`` does. If the
+shared library is missing, every entry point raises ``RuntimeError``: there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsgm.so")
+
+SGM_OK, SGM_EINVAL, SGM_ENOMEM, SGM_EDEVICE, SGM_ETOOBIG, SGM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SGM_MAX_QV, SGM_MAX_QE = 16, 64
+SGM_SORTED, SGM_COUNT_ONLY = 0, 1
+(SGM_K_CHECK, SGM_K_COLLECT, SGM_K_EXPLORE, SGM_K_REFINE, SGM_K_EC_COUNT, SGM_K_EC_WRITE,
+ SGM_K_JOIN, SGM_K_SORT, SGM_K_OTHER, SGM_K_COUNT) = range(10)
+KERNEL_NAMES = ["check", "collect", "explore", "refine", "ec_count", "ec_write", "join",
+                "sort", "other"]
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+class sgm_options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("refine_rounds", ctypes.c_int32),
+                ("refine_reversed", ctypes.c_int32), ("low_conn_degree", ctypes.c_int32),
+                ("result_cap_rows", ctypes.c_int64), ("join_budget_bytes", ctypes.c_int64),
+                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class sgm_query(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int32), ("n_edges", ctypes.c_int32),
+                ("vertex_label", _i32p), ("vertex_pin", _i32p), ("edge_src", _i32p),
+                ("edge_dst", _i32p), ("edge_label", _i32p)]
+
+
+class sgm_stats(ctypes.Structure):
+    _fields_ = [("cand", ctypes.c_int64 * SGM_MAX_QV), ("ec", ctypes.c_int64 * SGM_MAX_QE),
+                ("level_rows", ctypes.c_int64 * SGM_MAX_QV),
+                ("join_order", ctypes.c_int32 * SGM_MAX_QV),
+                ("visit_order", ctypes.c_int32 * SGM_MAX_QV),
+                ("peak_rows", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
+                ("n_chunks", ctypes.c_int32), ("n_launches", ctypes.c_int32),
+                ("ns_total", ctypes.c_int64), ("ns_filter", ctypes.c_int64),
+                ("ns_collect", ctypes.c_int64), ("ns_join", ctypes.c_int64),
+                ("ns_finish", ctypes.c_int64)]
+
+
+class sgm_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_cols", ctypes.c_int32),
+                ("n_rows", ctypes.c_int64), ("rows", _i32p), ("stats", sgm_stats)]
+
+
+class sgm_kstat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms_total", ctypes.c_double),
+                ("bytes_total", ctypes.c_double)]
+
+
+EXPORTS = {
+    "sgm_default_options": (None, [ctypes.POINTER(sgm_options)]),
+    "sgm_load_graph": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p,
+                                      ctypes.POINTER(sgm_options), ctypes.POINTER(ctypes.c_void_p)]),
+    "sgm_match_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query), ctypes.c_uint32,
+                                       ctypes.POINTER(ctypes.POINTER(sgm_result))]),
+    "sgm_match_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query), ctypes.c_int32,
+                                       ctypes.c_uint32, ctypes.POINTER(ctypes.POINTER(sgm_result))]),
+    "sgm_free_result": (None, [ctypes.POINTER(sgm_result)]),
+    "sgm_free_graph": (None, [ctypes.c_void_p]),
+    "sgm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "sgm_last_error": (ctypes.c_char_p, []),
+    "sgm_graph_info": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i64p, _i32p, _i32p]),
+    "sgm_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(sgm_kstat)]),
+    "sgm_reset_kernel_stats": (ctypes.c_int, [ctypes.c_void_p]),
+    "sgm_plan_query": (ctypes.c_int, [ctypes.POINTER(sgm_query), ctypes.c_int32, _i64p,
+                                      ctypes.c_int32, _i32p, _i32p, _i32p, _i32p]),
+}
+
+_lib = None
+
+
+def build() -> str:
+    """Compile libsgm.so (hipcc, gfx950)."""
+    from . import builder
+    return builder.build()
+
+
+def lib():
+    """The loaded ``libsgm.so`` (RuntimeError if it was never built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+class SGMError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        l = lib()
+        msg = l.sgm_strerror(code).decode()
+        detail = (l.sgm_last_error() or b"").decode()
+        super().__init__(f"{where}: {msg} ({code}) {detail}".strip())
+        self.code = code
+
+
+def _arr(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return a, a.ctypes.data_as(_i32p)
+
+
+# --- C-named entry points -------------------------------------------------------------
+
+def sgm_default_options() -> sgm_options:
+    o = sgm_options()
+    lib().sgm_default_options(ctypes.byref(o))
+    return o
+
+
+def sgm_load_graph(n_vertices, n_edges, row_ptr, col, rel, vtype, opts=None):
+    """Returns an opaque graph handle (raises SGMError on failure)."""
+    (rp, rpp), (c, cp), (r, rlp), (t, tp) = _arr(row_ptr), _arr(col), _arr(rel), _arr(vtype)
+    h = ctypes.c_void_p()
+    rc = lib().sgm_load_graph(int(n_vertices), int(n_edges), rpp, cp, rlp, tp,
+                              ctypes.byref(opts) if opts is not None else None, ctypes.byref(h))
+    if rc != SGM_OK:
+        raise SGMError(rc, "sgm_load_graph")
+    return h
+
+
+def _make_query(n, vlabel, vpin, esrc, edst, elabel):
+    keep = [_arr(vlabel), _arr(vpin), _arr(esrc), _arr(edst), _arr(elabel)]
+    q = sgm_query(int(n), int(len(keep[2][0])), keep[0][1], keep[1][1], keep[2][1], keep[3][1],
+                  keep[4][1])
+    return q, keep
+
+
+def sgm_match_query(g, q: sgm_query, flags: int = SGM_SORTED):
+    out = ctypes.POINTER(sgm_result)()
+    rc = lib().sgm_match_query(g, ctypes.byref(q), int(flags), ctypes.byref(out))
+    return rc, out
+
+
+def sgm_match_batch(g, qs, flags: int = SGM_SORTED):
+    n = len(qs)
+    arr = (sgm_query * max(n, 1))(*qs)
+    outs = (ctypes.POINTER(sgm_result) * max(n, 1))()
+    rc = lib().sgm_match_batch(g, arr, n, int(flags), outs)
+    return rc, [outs[i] for i in range(n)]
+
+
+def sgm_free_result(r):
+    lib().sgm_free_result(r)
+
+
+def sgm_free_graph(g):
+    lib().sgm_free_graph(g)
+
+
+def sgm_strerror(code: int) -> str:
+    return lib().sgm_strerror(code).decode()
+
+
+def sgm_plan_query(n, vlabel, vpin, esrc, edst, elabel, n_vertices, type_freq):
+    """Host-only query plan: dict with visit_order, parent, parent_edge,
+    init_order (each trimmed of -1 padding where it is an order)."""
+    q, keep = _make_query(n, vlabel, vpin, esrc, edst, elabel)
+    tf = np.ascontiguousarray(np.asarray(type_freq, np.int64))
+    outs = [np.full(SGM_MAX_QV, -7, np.int32) for _ in range(4)]
+    rc = lib().sgm_plan_query(ctypes.byref(q), int(n_vertices), tf.ctypes.data_as(_i64p),
+                              int(len(tf)), *[o.ctypes.data_as(_i32p) for o in outs])
+    if rc != SGM_OK:
+        raise SGMError(rc, "sgm_plan_query")
+    vo, par, pe, io = outs
+    return dict(visit_order=[int(x) for x in vo if x >= 0], parent=par[:n].tolist(),
+                parent_edge=pe[:n].tolist(), init_order=[int(x) for x in io if x >= 0])
+
+
+# --- numpy convenience ----------------------------------------------------------------
+
+def _result_to_numpy(r, n):
+    res = r.contents
+    k = int(res.n_rows)
+    if res.rows:
+        out = np.empty((k, n), np.int32)
+        if k:
+            ctypes.memmove(out.ctypes.data, res.rows, k * n * 4)
+    else:
+        out = None
+    return k, out
+
+
+def stats_dict(st: sgm_stats, n: int, m: int) -> dict:
+    return dict(cand=list(st.cand[:n]), ec=list(st.ec[:m]), level_rows=list(st.level_rows[:n]),
+                join_order=list(st.join_order[:n]),
+                visit_order=[x for x in st.visit_order if x >= 0],
+                peak_rows=st.peak_rows, peak_bytes=st.peak_bytes, n_chunks=st.n_chunks,
+                n_launches=st.n_launches, ns_total=st.ns_total, ns_filter=st.ns_filter,
+                ns_collect=st.ns_collect, ns_join=st.ns_join, ns_finish=st.ns_finish)
+
+
+class Graph:
+    """A data graph resident on the GPU."""
+
+    def __init__(self, row_ptr, col, rel, vtype, **options):
+        opts = sgm_default_options()
+        for k, v in options.items():
+            setattr(opts, k, v)
+        row_ptr = np.asarray(row_ptr)
+        self.V = int(len(row_ptr) - 1)
+        self._h = sgm_load_graph(self.V, int(row_ptr[-1]), row_ptr, col, rel, vtype, opts)
+
+    @classmethod
+    def from_kg(cls, kg, **options):
+        return cls(kg.row_ptr, kg.col, kg.rel, kg.vtype, **options)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            sgm_free_graph(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        nv, ne, mo, mi = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        lib().sgm_graph_info(self._h, ctypes.byref(nv), ctypes.byref(ne), ctypes.byref(mo),
+                             ctypes.byref(mi))
+        return dict(n_vertices=nv.value, n_edges=ne.value, max_out=mo.value, max_in=mi.value)
+
+    def match(self, n, vlabel, vpin, esrc, edst, elabel, count_only=False, with_stats=False):
+        """All matches as an [rows, n] int32 array (ascending lexicographic),
+        or the count when ``count_only``. Raises SGMError on failure."""
+        q, keep = _make_query(n, vlabel, vpin, esrc, edst, elabel)
+        rc, r = sgm_match_query(self._h, q, SGM_COUNT_ONLY if count_only else SGM_SORTED)
+        if rc != SGM_OK:
+            err = SGMError(rc, "sgm_match_query")
+            if r:
+                err.n_rows = int(r.contents.n_rows)
+                sgm_free_result(r)
+            raise err
+        try:
+            k, rows = _result_to_numpy(r, n)
+            st = stats_dict(r.contents.stats, n, len(keep[2][0]))
+        finally:
+            sgm_free_result(r)
+        out = k if count_only else rows
+        return (out, st) if with_stats else out
+
+    def match_query(self, q, **kw):
+        return self.match(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel, **kw)
+
+    def match_batch(self, queries, count_only=False):
+        """Results (arrays, counts, or SGMError instances) for a list of
+        kggen-style queries, through sgm_match_batch."""
+        built = [_make_query(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel) for q in queries]
+        rc, outs = sgm_match_batch(self._h, [b[0] for b in built],
+                                   SGM_COUNT_ONLY if count_only else SGM_SORTED)
+        if rc != SGM_OK:
+            raise SGMError(rc, "sgm_match_batch")
+        res = []
+        for q, r in zip(queries, outs):
+            st = r.contents.status
+            if st != SGM_OK:
+                res.append(SGMError(st, "batch member"))
+            else:
+                k, rows = _result_to_numpy(r, q.n)
+                res.append(k if count_only else rows)
+            sgm_free_result(r)
+        return res
+
+    def kernel_stats(self):
+        out = {}
+        for kid, name in enumerate(KERNEL_NAMES):
+            s = sgm_kstat()
+            lib().sgm_kernel_stats(self._h, kid, ctypes.byref(s))
+            out[name] = dict(launches=s.launches, ms=s.ms_total, bytes=s.bytes_total)
+        return out
+
+    def reset_kernel_stats(self):
+        lib().sgm_reset_kernel_stats(self._h)

@@ -1,0 +1,1131 @@
+// C ABI of the sgm library: graph residency, per-query orchestration of the
+// filtering-and-joining pipeline (thesis Alg. 3.1), batching, statistics.
+// Every step of a match runs in the HIP kernels of sgm_kernels.hip; this file
+// only validates, plans, sizes buffers and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "sgm_internal.h"
+#include "sgm_plan.h"
+
+using namespace sgm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const char *what, hipError_t e) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    g_last_error = buf;
+}
+
+struct DeviceError {
+    int code;
+};
+
+#define HIPX(call)                                         \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) {                            \
+            set_error(#call, e_);                          \
+            throw DeviceError{SGM_EDEVICE};                \
+        }                                                  \
+    } while (0)
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// Caching device allocator: buffers return to size-keyed free lists and are
+// reused by later work on the same stream (stream order makes reuse safe).
+class DevPool {
+   public:
+    void *get(size_t bytes) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        if (bytes == 0) bytes = 256;
+        auto it = free_.lower_bound(bytes);
+        if (it != free_.end() && it->first <= 2 * bytes + (1u << 20)) {
+            void *p = it->second;
+            free_.erase(it);
+            live_ += size_[p];
+            return p;
+        }
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            // drop cached blocks and retry once
+            (void)hipGetLastError();
+            trim();
+            e = hipMalloc(&p, bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                g_last_error = "device allocation failed";
+                throw DeviceError{SGM_ENOMEM};
+            }
+        }
+        size_[p] = bytes;
+        live_ += bytes;
+        return p;
+    }
+    void put(void *p) {
+        if (!p) return;
+        auto it = size_.find(p);
+        if (it == size_.end()) return;
+        live_ -= it->second;
+        free_.emplace(it->second, p);
+    }
+    void trim() {
+        for (auto &kv : free_) {
+            (void)hipFree(kv.second);
+            size_.erase(kv.second);
+        }
+        free_.clear();
+    }
+    ~DevPool() {
+        trim();
+        for (auto &kv : size_) (void)hipFree(kv.first);
+    }
+    size_t live() const { return live_; }
+
+   private:
+    std::multimap<size_t, void *> free_;
+    std::unordered_map<void *, size_t> size_;
+    size_t live_ = 0;
+};
+
+// Buffers taken from the pool during one query, returned at its end.
+struct Scope {
+    DevPool &pool;
+    std::vector<void *> held;
+    explicit Scope(DevPool &p) : pool(p) {}
+    template <class T>
+    T *get(int64_t n) {
+        void *p = pool.get(sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+        held.push_back(p);
+        return (T *)p;
+    }
+    void release(void *p) {
+        for (auto &h : held)
+            if (h == p) {
+                pool.put(p);
+                h = nullptr;
+            }
+    }
+    ~Scope() {
+        for (void *p : held) pool.put(p);
+    }
+};
+
+constexpr int kMaxSlots = 1024;
+constexpr int kMaxRounds = 32;
+constexpr int kMaxDesc = 2048;
+
+// Small per-query counters, cleared with one memset per query.
+struct DevCounters {
+    int32_t cand_count[SGM_MAX_QV + 1];
+    int32_t big_count[kMaxSlots];
+    unsigned long long removed[kMaxRounds + 1];
+    unsigned long long ec_total[SGM_MAX_QE];
+};
+
+}  // namespace
+
+struct sgm_graph {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    sgm_options opts;
+    int32_t V = 0;
+    int64_t E = 0;
+    int32_t nwords = 0;
+    int32_t max_out = 0, max_in = 0;
+    int32_t n_big = 0;  // vertices with a direction above kBigDegree
+    int32_t n_types = 0;
+    std::vector<int64_t> type_freq;
+    DevGraph dg{};
+    // device memory owned by the graph
+    int32_t *d_out_off = nullptr, *d_in_off = nullptr, *d_vtype = nullptr;
+    int2 *d_out_adj = nullptr, *d_in_adj = nullptr;
+    uint64_t *d_bits = nullptr;   // [SGM_MAX_QV + 1][nwords] (last: push scratch)
+    int32_t *d_lists = nullptr;   // [SGM_MAX_QV][V]
+    int32_t *d_prefix = nullptr;  // [SGM_MAX_QV][nwords + 1]
+    int32_t *d_big = nullptr;     // [max(n_big,1)]
+    NbrDesc *d_desc = nullptr;    // [kMaxDesc]
+    DevCounters *d_cnt = nullptr;
+    int32_t *d_slots = nullptr;   // [SGM_MAX_QV] ids for multi-collect
+    // pinned host staging
+    NbrDesc *h_desc = nullptr;
+    DevCounters *h_cnt = nullptr;
+    int32_t *h_slots = nullptr;
+    int64_t *h_small = nullptr;   // [64] small readbacks
+    void *h_rows = nullptr;
+    size_t h_rows_cap = 0;
+    DevPool pool;
+    std::mutex mu;
+    // profiling
+    std::vector<hipEvent_t> ev_free;
+    struct Pending {
+        int kid;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Pending> pending;
+    sgm_kstat kstat[SGM_K_COUNT]{};
+    int launches = 0;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// profiling helpers
+// ---------------------------------------------------------------------------
+
+struct Prof {
+    sgm_graph *g;
+    int kid;
+    double bytes;
+    hipEvent_t a = nullptr, b = nullptr;
+    Prof(sgm_graph *g_, int kid_, double bytes_) : g(g_), kid(kid_), bytes(bytes_) {
+        g->launches++;
+        if (!g->opts.profile) return;
+        a = take();
+        b = take();
+        HIPX(hipEventRecord(a, g->stream));
+    }
+    hipEvent_t take() {
+        if (g->ev_free.empty()) {
+            hipEvent_t e;
+            HIPX(hipEventCreate(&e));
+            return e;
+        }
+        hipEvent_t e = g->ev_free.back();
+        g->ev_free.pop_back();
+        return e;
+    }
+    ~Prof() {
+        if (!a) return;
+        if (hipEventRecord(b, g->stream) == hipSuccess) g->pending.push_back({kid, a, b, bytes});
+    }
+};
+
+// after a full stream sync: fold pending event pairs into the stats
+void prof_flush(sgm_graph *g) {
+    for (auto &p : g->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            g->kstat[p.kid].launches++;
+            g->kstat[p.kid].ms_total += ms;
+            g->kstat[p.kid].bytes_total += p.bytes;
+        }
+        g->ev_free.push_back(p.a);
+        g->ev_free.push_back(p.b);
+    }
+    g->pending.clear();
+}
+
+void sync(sgm_graph *g) {
+    HIPX(hipStreamSynchronize(g->stream));
+    prof_flush(g);
+}
+
+// ---------------------------------------------------------------------------
+// graph load
+// ---------------------------------------------------------------------------
+
+int normalize_csr(int32_t V, int32_t E, const int32_t *row_ptr, const int32_t *col,
+                  const int32_t *rel, std::vector<int32_t> &off, std::vector<int2> &adj) {
+    if (row_ptr[0] != 0 || row_ptr[V] != E) return SGM_EINVAL;
+    for (int32_t v = 0; v < V; ++v)
+        if (row_ptr[v + 1] < row_ptr[v]) return SGM_EINVAL;
+    for (int64_t i = 0; i < E; ++i)
+        if (col[i] < 0 || col[i] >= V || rel[i] < 0) return SGM_EINVAL;
+    off.assign((size_t)V + 1, 0);
+    adj.resize((size_t)E);
+    int64_t w = 0;
+    auto less = [](const int2 &a, const int2 &b) { return a.x != b.x ? a.x < b.x : a.y < b.y; };
+    for (int32_t v = 0; v < V; ++v) {
+        const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+        off[v] = (int32_t)w;
+        const int64_t start = w;
+        bool sorted = true;
+        for (int64_t i = b; i < e; ++i) {
+            adj[w] = make_int2(col[i], rel[i]);
+            if (w > start && !less(adj[w - 1], adj[w])) sorted = false;
+            ++w;
+        }
+        if (!sorted) {
+            std::sort(adj.begin() + start, adj.begin() + w, less);
+            int64_t k = start;
+            for (int64_t i = start; i < w; ++i)
+                if (k == start || adj[k - 1].x != adj[i].x || adj[k - 1].y != adj[i].y)
+                    adj[k++] = adj[i];
+            w = k;
+        }
+    }
+    off[V] = (int32_t)w;
+    adj.resize((size_t)w);
+    return SGM_OK;
+}
+
+void build_in(int32_t V, const std::vector<int32_t> &off, const std::vector<int2> &adj,
+              std::vector<int32_t> &in_off, std::vector<int2> &in_adj) {
+    in_off.assign((size_t)V + 1, 0);
+    for (const int2 &e : adj) in_off[e.x + 1]++;
+    for (int32_t v = 0; v < V; ++v) in_off[v + 1] += in_off[v];
+    std::vector<int32_t> fill(in_off.begin(), in_off.end() - 1);
+    in_adj.resize(adj.size());
+    // sources visited in ascending order, relations ascending within a
+    // source, so every in-row comes out sorted by (src, rel)
+    for (int32_t v = 0; v < V; ++v)
+        for (int32_t i = off[v]; i < off[v + 1]; ++i) in_adj[fill[adj[i].x]++] = make_int2(v, adj[i].y);
+}
+
+template <class T>
+T *dev_upload(const std::vector<T> &h) {
+    T *p = nullptr;
+    HIPX(hipMalloc(&p, sizeof(T) * std::max<size_t>(h.size(), 1)));
+    if (!h.empty()) HIPX(hipMemcpy(p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+    return p;
+}
+
+void free_graph_mem(sgm_graph *g) {
+    (void)hipSetDevice(g->device);
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    for (auto &p : g->pending) {
+        g->ev_free.push_back(p.a);
+        g->ev_free.push_back(p.b);
+    }
+    for (hipEvent_t e : g->ev_free) (void)hipEventDestroy(e);
+    void *dp[] = {g->d_out_off, g->d_in_off, g->d_vtype, g->d_out_adj, g->d_in_adj, g->d_bits,
+                  g->d_lists,   g->d_prefix, g->d_big,   g->d_desc,    g->d_cnt,    g->d_slots};
+    for (void *p : dp)
+        if (p) (void)hipFree(p);
+    void *hp[] = {g->h_desc, g->h_cnt, g->h_slots, g->h_small, g->h_rows};
+    for (void *p : hp)
+        if (p) (void)hipHostFree(p);
+    if (g->stream) (void)hipStreamDestroy(g->stream);
+}
+
+// ---------------------------------------------------------------------------
+// one query
+// ---------------------------------------------------------------------------
+
+struct ECTab {
+    int key;      // key vertex
+    int other;
+    int dir;      // 0: keys are sources (scan out-edges), 1: keys are destinations
+    int slot;     // big-list counter slot
+    int32_t *cnt = nullptr;
+    int32_t *offs = nullptr;
+    int32_t *vals = nullptr;
+    int32_t *big = nullptr;
+    int64_t n = 0;
+};
+
+struct Query {
+    sgm_graph *g;
+    const QInfo &qi;
+    Plan pl;
+    Scope sc;
+    sgm_result *res;
+    uint32_t flags;
+    int next_slot = 0;
+    Query(sgm_graph *g_, const QInfo &q_, sgm_result *r, uint32_t f)
+        : g(g_), qi(q_), sc(g_->pool), res(r), flags(f) {}
+
+    uint64_t *bits(int u) const { return g->d_bits + (int64_t)u * g->nwords; }
+    uint64_t *scratch() const { return g->d_bits + (int64_t)SGM_MAX_QV * g->nwords; }
+    int32_t *list(int u) const { return g->d_lists + (int64_t)u * g->V; }
+    int32_t *prefix(int u) const { return g->d_prefix + (int64_t)u * (g->nwords + 1); }
+    int32_t *cand_count_dev(int u) const { return &g->d_cnt->cand_count[u]; }
+    hipStream_t st() const { return g->stream; }
+
+    VPred pred(int u) const {
+        return VPred{qi.label[u], qi.pin[u], qi.qout[u], qi.qin[u]};
+    }
+
+    void collect_one(int u) {
+        Prof p(g, SGM_K_COLLECT, (double)g->nwords * 12.0);
+        launch_collect_multi(st(), g->dg, bits(u), g->nwords, list(u), g->V, cand_count_dev(u),
+                             prefix(u), g->nwords + 1, nullptr, 1);
+    }
+
+    void collect_all() {
+        Prof p(g, SGM_K_COLLECT, (double)qi.n * g->nwords * 12.0);
+        launch_collect_multi(st(), g->dg, g->d_bits, g->nwords, g->d_lists, g->V,
+                             g->d_cnt->cand_count, g->d_prefix, g->nwords + 1, nullptr, qi.n);
+    }
+
+    int grid_small_for(int64_t items) const {
+        int64_t gsz = (items + (kBlock / 16) - 1) / (kBlock / 16);
+        return (int)std::max<int64_t>(1, std::min<int64_t>(gsz, 2048));
+    }
+    int grid_big() const { return std::max(1, std::min(g->n_big, 1024)); }
+
+    int filter_launch(int u, const NbrDesc *dev_desc, int n_nbr, bool push, int64_t items_bound,
+                      unsigned long long *removed, int kid) {
+        FilterArgs a{};
+        a.g = g->dg;
+        a.items = list(u);
+        a.count = cand_count_dev(u);
+        a.self_bits = bits(u);
+        a.nbr = dev_desc;
+        a.n_nbr = n_nbr;
+        a.do_push = push ? 1 : 0;
+        a.big_items = g->d_big;
+        const int slot = next_slot++;
+        if (slot >= kMaxSlots) return SGM_EUNSUPPORTED;
+        a.big_count = &g->d_cnt->big_count[slot];
+        a.removed = removed;
+        Prof p(g, kid, 0.0);
+        launch_filter(st(), a, grid_small_for(items_bound), grid_big());
+        return SGM_OK;
+    }
+
+    // Filtering phase: Alg. 3.2 initialisation along the spanning tree, then
+    // the refinement rounds.
+    int filter() {
+        const int n = qi.n;
+        HIPX(hipMemsetAsync(g->d_bits, 0, sizeof(uint64_t) * (size_t)n * g->nwords, st()));
+        HIPX(hipMemsetAsync(g->d_cnt, 0, sizeof(DevCounters), st()));
+        // descriptors for every filter launch, uploaded once
+        std::vector<NbrDesc> &hd = desc_;
+        hd.clear();
+        struct Step {
+            int u;
+            int first, count;
+            bool push;
+            int parent_push;  // vertex whose bitmap is intersected with the scratch, or -1
+        };
+        std::vector<Step> init_steps;
+        bool initialized[SGM_MAX_QV] = {};
+        for (int oi = 0; oi < pl.n_visit; ++oi) {
+            const int u = pl.visit[oi];
+            initialized[u] = true;
+            Step s{u, (int)hd.size(), 0, true, -1};
+            // spanning-tree neighbours: parent, then children
+            auto add = [&](int v, int e) {
+                NbrDesc d{};
+                const bool out = qi.esrc[e] == u;
+                d.dir = out ? 0 : 1;
+                d.rel = qi.elabel[e];
+                d.pred = pred(v);
+                d.push = 1;
+                if (initialized[v]) {
+                    d.mode = 0;
+                    d.test_bits = bits(v);
+                    d.push_bits = scratch();
+                    s.parent_push = v;
+                } else {
+                    d.mode = 1;
+                    d.test_bits = nullptr;
+                    d.push_bits = bits(v);
+                }
+                hd.push_back(d);
+            };
+            if (pl.parent[u] >= 0) add(pl.parent[u], pl.parent_edge[u]);
+            for (int x = 0; x < n; ++x)
+                if (pl.parent[x] == u) add(x, pl.parent_edge[x]);
+            s.count = (int)hd.size() - s.first;
+            init_steps.push_back(s);
+            if (pl.parent[u] >= 0) initialized[pl.parent[u]] = true;
+            for (int x = 0; x < n; ++x)
+                if (pl.parent[x] == u) initialized[x] = true;
+        }
+        // refinement: all query edges between vertices above the
+        // low-connectivity threshold, reversed visit order by default
+        const int thr = g->opts.low_conn_degree;
+        std::vector<int> rorder;
+        for (int i = 0; i < pl.n_init; ++i) {
+            const int u = pl.init[g->opts.refine_reversed ? pl.n_init - 1 - i : i];
+            if (qi.deg[u] > thr) rorder.push_back(u);
+        }
+        std::vector<Step> ref_steps;
+        for (int u : rorder) {
+            Step s{u, (int)hd.size(), 0, false, -1};
+            for (int e = 0; e < qi.m; ++e) {
+                int v;
+                NbrDesc d{};
+                if (qi.esrc[e] == u) {
+                    v = qi.edst[e];
+                    d.dir = 0;
+                } else if (qi.edst[e] == u) {
+                    v = qi.esrc[e];
+                    d.dir = 1;
+                } else {
+                    continue;
+                }
+                if (qi.deg[v] <= thr) continue;
+                d.rel = qi.elabel[e];
+                d.mode = 0;
+                d.test_bits = bits(v);
+                d.pred = pred(v);
+                hd.push_back(d);
+            }
+            s.count = (int)hd.size() - s.first;
+            if (s.count) ref_steps.push_back(s);
+        }
+        if ((int)hd.size() > kMaxDesc) return SGM_EUNSUPPORTED;
+        if (!hd.empty()) {
+            std::memcpy(g->h_desc, hd.data(), sizeof(NbrDesc) * hd.size());
+            HIPX(hipMemcpyAsync(g->d_desc, g->h_desc, sizeof(NbrDesc) * hd.size(),
+                                hipMemcpyHostToDevice, st()));
+        }
+        // root check (kernel_check): the first vertex of O
+        const int root = pl.visit[0];
+        if (qi.pin[root] >= 0) {
+            Prof p(g, SGM_K_CHECK, 12.0);
+            launch_check_pin(st(), g->dg, pred(root), bits(root));
+        } else {
+            Prof p(g, SGM_K_CHECK, 12.0 * g->V + g->nwords * 8.0);
+            launch_check_sweep(st(), g->dg, pred(root), bits(root));
+        }
+        for (const Step &s : init_steps) {
+            if (s.count == 0) continue;
+            collect_one(s.u);
+            if (s.parent_push >= 0)
+                HIPX(hipMemsetAsync(scratch(), 0, sizeof(uint64_t) * g->nwords, st()));
+            const int64_t bound = qi.pin[s.u] >= 0 ? 1 : g->V;
+            int rc = filter_launch(s.u, g->d_desc + s.first, s.count, true, bound,
+                                   &g->d_cnt->removed[kMaxRounds], SGM_K_EXPLORE);
+            if (rc) return rc;
+            if (s.parent_push >= 0) {
+                Prof p(g, SGM_K_OTHER, g->nwords * 24.0);
+                launch_and(st(), bits(s.parent_push), scratch(), g->nwords);
+            }
+        }
+        int rounds = g->opts.refine_rounds;
+        const bool fixpoint = rounds < 0;
+        if (fixpoint) rounds = kMaxRounds;
+        rounds = std::min(rounds, kMaxRounds);
+        for (int r = 0; r < rounds && !ref_steps.empty(); ++r) {
+            for (const Step &s : ref_steps) {
+                collect_one(s.u);
+                const int64_t bound = qi.pin[s.u] >= 0 ? 1 : g->V;
+                int rc = filter_launch(s.u, g->d_desc + s.first, s.count, false, bound,
+                                       &g->d_cnt->removed[r], SGM_K_REFINE);
+                if (rc) return rc;
+            }
+            if (fixpoint) {
+                HIPX(hipMemcpyAsync(g->h_small, &g->d_cnt->removed[r], sizeof(unsigned long long),
+                                    hipMemcpyDeviceToHost, st()));
+                sync(g);
+                if (g->h_small[0] == 0) break;
+            }
+        }
+        collect_all();
+        return SGM_OK;
+    }
+
+    std::vector<NbrDesc> desc_;
+    int32_t ccount[SGM_MAX_QV] = {};
+    ECTab ec[SGM_MAX_QE];
+    int jorder[SGM_MAX_QV];   // query vertex at each join column
+    int jpos[SGM_MAX_QV];     // join column of each query vertex
+
+    ECDesc ec_desc(const ECTab &t, int e) {
+        ECDesc d{};
+        d.key_vertex = t.key;
+        d.dir = t.dir;
+        d.rel = qi.elabel[e];
+        d.keys = list(t.key);
+        d.key_count = cand_count_dev(t.key);
+        d.other_bits = bits(t.other);
+        d.cnt = t.cnt;
+        d.offs = t.offs;
+        d.vals = t.vals;
+        d.total = &g->d_cnt->ec_total[e];
+        d.big_items = t.big;
+        d.big_count = &g->d_cnt->big_count[t.slot];
+        return d;
+    }
+
+    void ec_count(ECTab &t, int e) {
+        t.cnt = sc.get<int32_t>(ccount[t.key]);
+        t.big = sc.get<int32_t>(std::min<int64_t>(ccount[t.key], std::max(g->n_big, 1)));
+        t.slot = next_slot++;
+        if (t.slot >= kMaxSlots) throw DeviceError{SGM_EUNSUPPORTED};
+        Prof p(g, SGM_K_EC_COUNT, 0.0);
+        launch_ec_count(st(), g->dg, ec_desc(t, e), grid_small_for(ccount[t.key]), grid_big());
+    }
+
+    // Joining phase, part 1: candidate edges of every query edge, then the
+    // join order (Sec. "Joining Phase": start from the edge with the fewest
+    // candidate edges; prefer edges whose endpoints are both bound; ties by
+    // fewest candidates, then lowest edge index).
+    int collect_edges() {
+        const int m = qi.m;
+        for (int e = 0; e < m; ++e) {
+            ECTab &t = ec[e];
+            t.key = qi.esrc[e];
+            t.other = qi.edst[e];
+            t.dir = 0;
+            ec_count(t, e);
+        }
+        HIPX(hipMemcpyAsync(g->h_cnt->ec_total, g->d_cnt->ec_total,
+                            sizeof(unsigned long long) * m, hipMemcpyDeviceToHost, st()));
+        sync(g);
+        int64_t tot[SGM_MAX_QE];
+        for (int e = 0; e < m; ++e) {
+            tot[e] = (int64_t)g->h_cnt->ec_total[e];
+            res->stats.ec[e] = tot[e];
+        }
+        for (int e = 0; e < m; ++e)
+            if (tot[e] == 0) return 1;  // no match
+        // join order
+        bool vis[SGM_MAX_QV] = {}, used[SGM_MAX_QE] = {};
+        int e0 = 0;
+        for (int e = 1; e < m; ++e)
+            if (tot[e] < tot[e0]) e0 = e;
+        int nj = 0;
+        jorder[nj++] = qi.esrc[e0];
+        vis[qi.esrc[e0]] = true;
+        ext_.clear();
+        // each join level: new vertex, extension edge, check edges
+        auto add_level = [&](int e_ext) {
+            const int a = qi.esrc[e_ext], b = qi.edst[e_ext];
+            const int w = vis[a] ? b : a;
+            Level L{};
+            L.w = w;
+            L.ext = e_ext;
+            used[e_ext] = true;
+            for (int e = 0; e < m; ++e) {
+                if (used[e]) continue;
+                const int x = qi.esrc[e], y = qi.edst[e];
+                if ((x == w && vis[y]) || (y == w && vis[x])) {
+                    L.chk[L.n_chk++] = e;
+                    used[e] = true;
+                }
+            }
+            vis[w] = true;
+            jorder[nj++] = w;
+            ext_.push_back(L);
+        };
+        add_level(e0);
+        while (nj < qi.n) {
+            int best = -1;
+            for (int e = 0; e < m; ++e) {
+                if (used[e]) continue;
+                const bool va = vis[qi.esrc[e]], vb = vis[qi.edst[e]];
+                if (va == vb) continue;
+                if (best < 0 || tot[e] < tot[best]) best = e;
+            }
+            if (best < 0) return SGM_EINVAL;
+            add_level(best);
+        }
+        for (int j = 0; j < qi.n; ++j) jpos[jorder[j]] = j;
+        // orientation: key = the endpoint bound first
+        for (int e = 0; e < m; ++e) {
+            ECTab &t = ec[e];
+            const int a = qi.esrc[e], b = qi.edst[e];
+            const bool key_src = jpos[a] < jpos[b];
+            if (!key_src) {
+                sc.release(t.cnt);
+                sc.release(t.big);
+                t.key = b;
+                t.other = a;
+                t.dir = 1;
+                // count again keyed by the destination (total unchanged)
+                ec_count(t, e);
+            }
+        }
+        for (int e = 0; e < m; ++e) {
+            ECTab &t = ec[e];
+            t.n = tot[e];
+            t.offs = sc.get<int32_t>((int64_t)ccount[t.key] + 1);
+            t.vals = sc.get<int32_t>(t.n);
+            {
+                Prof p(g, SGM_K_OTHER, 8.0 * ccount[t.key]);
+                launch_scan_i32(st(), t.cnt, cand_count_dev(t.key), t.offs);
+            }
+            Prof p(g, SGM_K_EC_WRITE, 0.0);
+            launch_ec_write(st(), g->dg, ec_desc(t, e), grid_small_for(ccount[t.key]), grid_big());
+        }
+        return SGM_OK;
+    }
+
+    struct Level {
+        int w, ext, n_chk;
+        int chk[SGM_MAX_QE];
+    };
+    std::vector<Level> ext_;
+
+    JoinEdge jedge(int e) const {
+        const ECTab &t = ec[e];
+        JoinEdge j{};
+        j.col = jpos[t.key];
+        j.rank = RankRef{bits(t.key), prefix(t.key)};
+        j.offs = t.offs;
+        j.vals = t.vals;
+        return j;
+    }
+
+    // Joining phase, part 2: extend the table one query vertex at a time.
+    int join(int32_t **table_out, int64_t *rows_out) {
+        const int seed = jorder[0];
+        const int32_t *table = list(seed);
+        int64_t R = ccount[seed];
+        int32_t *owned = nullptr;
+        res->stats.level_rows[0] = R;
+        int k = 1;
+        for (size_t li = 0; li < ext_.size(); ++li) {
+            const Level &L = ext_[li];
+            if (L.n_chk > SGM_MAX_QV) return SGM_EUNSUPPORTED;
+            JoinArgs a{};
+            a.table = table;
+            a.R = R;
+            a.k = k;
+            a.ext = jedge(L.ext);
+            a.n_chk = L.n_chk;
+            for (int c = 0; c < L.n_chk; ++c) a.chk[c] = jedge(L.chk[c]);
+            int64_t *fan = sc.get<int64_t>(R);
+            int64_t *poff = sc.get<int64_t>(R + 1);
+            int64_t *tmp = sc.get<int64_t>(scan_tmp_words(R) + 1);
+            {
+                Prof p(g, SGM_K_JOIN, R * (4.0 * k + 24.0));
+                launch_join_fan(st(), a, fan);
+            }
+            {
+                Prof p(g, SGM_K_OTHER, 16.0 * R);
+                launch_scan_i64(st(), fan, R, poff, tmp);
+            }
+            HIPX(hipMemcpyAsync(g->h_small, poff + R, sizeof(int64_t), hipMemcpyDeviceToHost, st()));
+            sync(g);
+            const int64_t P = g->h_small[0];
+            sc.release(fan);
+            sc.release(tmp);
+            if (P == 0) {
+                R = 0;
+                res->stats.level_rows[li + 1] = 0;
+                break;
+            }
+            a.pair_off = poff;
+            a.P = P;
+            const int64_t tiles = join_tiles(P);
+            int64_t *bcnt = sc.get<int64_t>(tiles);
+            int64_t *boff = sc.get<int64_t>(tiles + 1);
+            int64_t *tmp2 = sc.get<int64_t>(scan_tmp_words(tiles) + 1);
+            a.block_cnt = bcnt;
+            {
+                Prof p(g, SGM_K_JOIN, P * (4.0 * k + 16.0));
+                launch_join_count(st(), a);
+            }
+            {
+                Prof p(g, SGM_K_OTHER, 16.0 * tiles);
+                launch_scan_i64(st(), bcnt, tiles, boff, tmp2);
+            }
+            HIPX(hipMemcpyAsync(g->h_small, boff + tiles, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                st()));
+            sync(g);
+            const int64_t R2 = g->h_small[0];
+            res->stats.level_rows[li + 1] = R2;
+            const bool last = li + 1 == ext_.size();
+            if (last && g->opts.result_cap_rows > 0 && R2 > g->opts.result_cap_rows) {
+                *rows_out = R2;
+                *table_out = nullptr;
+                return SGM_ETOOBIG;
+            }
+            if (R2 == 0 || (last && (flags & SGM_COUNT_ONLY))) {
+                R = R2;
+                table = nullptr;
+                break;
+            }
+            int32_t *out = sc.get<int32_t>(R2 * (k + 1));
+            a.out = out;
+            a.block_cnt = boff;
+            a.out_base = 0;
+            {
+                Prof p(g, SGM_K_JOIN, P * (4.0 * k + 16.0) + R2 * 4.0 * (k + 1));
+                launch_join_write(st(), a);
+            }
+            res->stats.peak_rows = std::max(res->stats.peak_rows, R2);
+            res->stats.peak_bytes = std::max<int64_t>(res->stats.peak_bytes, R2 * 4 * (k + 1));
+            sc.release(poff);
+            sc.release(bcnt);
+            sc.release(tmp2);
+            if (owned) sc.release(owned);
+            owned = out;
+            table = out;
+            R = R2;
+            ++k;
+        }
+        *rows_out = R;
+        *table_out = const_cast<int32_t *>(table);
+        return SGM_OK;
+    }
+
+    // Final ordering (rows ascending in query-vertex column order) and the
+    // copy to host.
+    void finish(const int32_t *table, int64_t R) {
+        const int n = qi.n;
+        int32_t colpos[SGM_MAX_QV];
+        bool identity = true;
+        for (int u = 0; u < n; ++u) {
+            colpos[u] = jpos[u];
+            identity &= jpos[u] == u;
+        }
+        int32_t *idx = nullptr;
+        if (!identity && R > 1) {
+            if (R <= small_sort_limit()) {
+                idx = sc.get<int32_t>(R);
+                Prof p(g, SGM_K_SORT, 4.0 * R * n);
+                launch_sort_small(st(), table, n, colpos, (int32_t)R, idx);
+            } else {
+                int nbits = 1;
+                while ((1ll << nbits) < g->V) ++nbits;
+                int32_t *ia = sc.get<int32_t>(R), *ib = sc.get<int32_t>(R);
+                int32_t *ka = sc.get<int32_t>(R), *kb = sc.get<int32_t>(R);
+                const int64_t tiles = radix_tiles(R);
+                int64_t *hist = sc.get<int64_t>(256 * tiles);
+                int64_t *hoff = sc.get<int64_t>(256 * tiles + 1);
+                int64_t *tmp = sc.get<int64_t>(scan_tmp_words(256 * tiles) + 1);
+                {
+                    Prof p(g, SGM_K_SORT, 4.0 * R);
+                    launch_iota(st(), ia, R);
+                }
+                for (int u = n - 1; u >= 0; --u) {
+                    {
+                        Prof p(g, SGM_K_SORT, 12.0 * R);
+                        launch_gather_key(st(), table, n, colpos[u], ia, R, ka);
+                    }
+                    for (int sh = 0; sh < nbits; sh += 8) {
+                        Prof p(g, SGM_K_SORT, 20.0 * R);
+                        launch_radix_hist(st(), ka, R, sh, hist);
+                        launch_scan_i64(st(), hist, 256 * tiles, hoff, tmp);
+                        launch_radix_scatter(st(), ka, ia, R, sh, hoff, kb, ib);
+                        std::swap(ka, kb);
+                        std::swap(ia, ib);
+                    }
+                }
+                idx = ia;
+            }
+        }
+        int32_t *out = sc.get<int32_t>(R * n);
+        {
+            Prof p(g, SGM_K_OTHER, 8.0 * R * n);
+            launch_gather_rows(st(), table, n, idx, R, colpos, out);
+        }
+        const size_t bytes = sizeof(int32_t) * (size_t)R * n;
+        if (g->h_rows_cap < bytes) {
+            if (g->h_rows) (void)hipHostFree(g->h_rows);
+            g->h_rows = nullptr;
+            g->h_rows_cap = 0;
+            size_t cap = std::max<size_t>(bytes, 1 << 20);
+            HIPX(hipHostMalloc(&g->h_rows, cap, hipHostMallocDefault));
+            g->h_rows_cap = cap;
+        }
+        HIPX(hipMemcpyAsync(g->h_rows, out, bytes, hipMemcpyDeviceToHost, st()));
+        sync(g);
+        res->rows = (int32_t *)std::malloc(std::max<size_t>(bytes, 1));
+        if (!res->rows) throw DeviceError{SGM_ENOMEM};
+        std::memcpy(res->rows, g->h_rows, bytes);
+    }
+
+    int run() {
+        const int64_t t0 = now_ns();
+        const int n = qi.n;
+        int rc = make_plan(qi, g->V, g->type_freq.data(), g->n_types, &pl);
+        if (rc) return rc;
+        for (int i = 0; i < SGM_MAX_QV; ++i) res->stats.visit_order[i] = pl.visit[i];
+        res->n_cols = n;
+        rc = filter();
+        if (rc) return rc;
+        HIPX(hipMemcpyAsync(g->h_cnt->cand_count, g->d_cnt->cand_count, sizeof(int32_t) * n,
+                            hipMemcpyDeviceToHost, st()));
+        sync(g);
+        const int64_t t1 = now_ns();
+        res->stats.ns_filter = t1 - t0;
+        bool empty = false;
+        for (int u = 0; u < n; ++u) {
+            ccount[u] = g->h_cnt->cand_count[u];
+            res->stats.cand[u] = ccount[u];
+            empty |= ccount[u] == 0;
+        }
+        res->stats.n_chunks = 1;
+        if (empty) return done(0, t0);
+        if (qi.m == 0) {
+            // single vertex: the candidate list is the (sorted) answer
+            jorder[0] = 0;
+            jpos[0] = 0;
+            res->stats.join_order[0] = 0;
+            const int64_t R = ccount[0];
+            if (g->opts.result_cap_rows > 0 && R > g->opts.result_cap_rows) {
+                res->n_rows = R;
+                return SGM_ETOOBIG;
+            }
+            if (!(flags & SGM_COUNT_ONLY)) finish(list(0), R);
+            return done(R, t0);
+        }
+        rc = collect_edges();
+        const int64_t t2 = now_ns();
+        res->stats.ns_collect = t2 - t1;
+        if (rc == 1) return done(0, t0);
+        if (rc) return rc;
+        for (int j = 0; j < n; ++j) res->stats.join_order[j] = jorder[j];
+        int32_t *table = nullptr;
+        int64_t R = 0;
+        rc = join(&table, &R);
+        const int64_t t3 = now_ns();
+        res->stats.ns_join = t3 - t2;
+        if (rc == SGM_ETOOBIG) {
+            res->n_rows = R;
+            res->stats.ns_total = now_ns() - t0;
+            return rc;
+        }
+        if (rc) return rc;
+        if (!(flags & SGM_COUNT_ONLY) && R > 0) finish(table, R);
+        res->stats.ns_finish = now_ns() - t3;
+        return done(R, t0);
+    }
+
+    int done(int64_t R, int64_t t0) {
+        res->n_rows = R;
+        // rows is non-NULL for every successful SORTED result, also when empty
+        if (!(flags & SGM_COUNT_ONLY) && !res->rows) {
+            res->rows = (int32_t *)std::malloc(sizeof(int32_t));
+            if (!res->rows) throw std::bad_alloc();
+        }
+        res->stats.ns_total = now_ns() - t0;
+        return SGM_OK;
+    }
+};
+
+int match_locked(sgm_graph *g, const sgm_query *q, uint32_t flags, sgm_result *res) {
+    QInfo qi;
+    int rc = check_query(q, g->V, &qi);
+    if (rc) return rc;
+    const int l0 = g->launches;
+    try {
+        Query Q(g, qi, res, flags);
+        rc = Q.run();
+    } catch (const DeviceError &e) {
+        rc = e.code;
+        (void)hipStreamSynchronize(g->stream);
+        (void)hipGetLastError();
+        g->pending.clear();
+    } catch (const std::bad_alloc &) {
+        rc = SGM_ENOMEM;
+    }
+    res->stats.n_launches = g->launches - l0;
+    return rc;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+void sgm_default_options(sgm_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->device = 0;
+    o->refine_rounds = 1;
+    o->refine_reversed = 1;
+    o->low_conn_degree = 1;
+    o->result_cap_rows = 0;
+    o->join_budget_bytes = 0;
+    o->profile = 0;
+}
+
+const char *sgm_strerror(int code) {
+    switch (code) {
+        case SGM_OK: return "ok";
+        case SGM_EINVAL: return "invalid argument";
+        case SGM_ENOMEM: return "out of memory";
+        case SGM_EDEVICE: return "device error";
+        case SGM_ETOOBIG: return "result exceeds the row cap";
+        case SGM_EUNSUPPORTED: return "unsupported query";
+        default: return "unknown error";
+    }
+}
+
+const char *sgm_last_error(void) { return g_last_error.c_str(); }
+
+int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
+                   const int32_t *col, const int32_t *rel, const int32_t *type,
+                   const sgm_options *opts, sgm_graph **out) {
+    if (!out) return SGM_EINVAL;
+    *out = nullptr;
+    if (n_vertices < 1 || n_edges < 0 || !row_ptr || !type || (n_edges > 0 && (!col || !rel)))
+        return SGM_EINVAL;
+    if (n_vertices > (1 << 30)) return SGM_EUNSUPPORTED;
+    for (int32_t v = 0; v < n_vertices; ++v)
+        if (type[v] < 0) return SGM_EINVAL;
+    std::vector<int32_t> off, in_off;
+    std::vector<int2> adj, in_adj;
+    int rc;
+    try {
+        rc = normalize_csr(n_vertices, n_edges, row_ptr, col, rel, off, adj);
+        if (rc) {
+            g_last_error = "malformed CSR";
+            return rc;
+        }
+        build_in(n_vertices, off, adj, in_off, in_adj);
+    } catch (const std::bad_alloc &) {
+        return SGM_ENOMEM;
+    }
+    sgm_graph *g = new (std::nothrow) sgm_graph();
+    if (!g) return SGM_ENOMEM;
+    if (opts) g->opts = *opts;
+    else sgm_default_options(&g->opts);
+    g->device = g->opts.device;
+    g->V = n_vertices;
+    g->E = (int64_t)adj.size();
+    g->nwords = (n_vertices + 63) / 64;
+    int32_t maxt = 0;
+    for (int32_t v = 0; v < n_vertices; ++v) maxt = std::max(maxt, type[v]);
+    g->n_types = maxt + 1;
+    g->type_freq.assign((size_t)g->n_types, 0);
+    for (int32_t v = 0; v < n_vertices; ++v) g->type_freq[type[v]]++;
+    int nbig = 0;
+    for (int32_t v = 0; v < n_vertices; ++v) {
+        const int32_t od = off[v + 1] - off[v], id = in_off[v + 1] - in_off[v];
+        g->max_out = std::max(g->max_out, od);
+        g->max_in = std::max(g->max_in, id);
+        if (od > kBigDegree || id > kBigDegree) ++nbig;
+    }
+    g->n_big = nbig;
+    try {
+        HIPX(hipSetDevice(g->device));
+        HIPX(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+        g->d_out_off = dev_upload(off);
+        g->d_in_off = dev_upload(in_off);
+        g->d_out_adj = dev_upload(adj);
+        g->d_in_adj = dev_upload(in_adj);
+        std::vector<int32_t> tv(type, type + n_vertices);
+        g->d_vtype = dev_upload(tv);
+        HIPX(hipMalloc(&g->d_bits, sizeof(uint64_t) * (size_t)(SGM_MAX_QV + 1) * g->nwords));
+        HIPX(hipMalloc(&g->d_lists, sizeof(int32_t) * (size_t)SGM_MAX_QV * g->V));
+        HIPX(hipMalloc(&g->d_prefix, sizeof(int32_t) * (size_t)SGM_MAX_QV * (g->nwords + 1)));
+        HIPX(hipMalloc(&g->d_big, sizeof(int32_t) * (size_t)std::max(nbig, 1)));
+        HIPX(hipMalloc(&g->d_desc, sizeof(NbrDesc) * kMaxDesc));
+        HIPX(hipMalloc(&g->d_cnt, sizeof(DevCounters)));
+        HIPX(hipMalloc(&g->d_slots, sizeof(int32_t) * SGM_MAX_QV));
+        HIPX(hipHostMalloc(&g->h_desc, sizeof(NbrDesc) * kMaxDesc, hipHostMallocDefault));
+        HIPX(hipHostMalloc(&g->h_cnt, sizeof(DevCounters), hipHostMallocDefault));
+        HIPX(hipHostMalloc(&g->h_slots, sizeof(int32_t) * SGM_MAX_QV, hipHostMallocDefault));
+        HIPX(hipHostMalloc(&g->h_small, sizeof(int64_t) * 64, hipHostMallocDefault));
+        g->dg.V = g->V;
+        g->dg.nwords = g->nwords;
+        g->dg.out_off = g->d_out_off;
+        g->dg.in_off = g->d_in_off;
+        g->dg.out_adj = g->d_out_adj;
+        g->dg.in_adj = g->d_in_adj;
+        g->dg.vtype = g->d_vtype;
+        HIPX(hipDeviceSynchronize());
+    } catch (const DeviceError &e) {
+        free_graph_mem(g);
+        delete g;
+        return e.code;
+    }
+    *out = g;
+    return SGM_OK;
+}
+
+void sgm_free_graph(sgm_graph *g) {
+    if (!g) return;
+    free_graph_mem(g);
+    delete g;
+}
+
+int sgm_graph_info(const sgm_graph *g, int32_t *n_vertices, int64_t *n_edges,
+                   int32_t *max_out_degree, int32_t *max_in_degree) {
+    if (!g) return SGM_EINVAL;
+    if (n_vertices) *n_vertices = g->V;
+    if (n_edges) *n_edges = g->E;
+    if (max_out_degree) *max_out_degree = g->max_out;
+    if (max_in_degree) *max_in_degree = g->max_in;
+    return SGM_OK;
+}
+
+int sgm_match_query(sgm_graph *g, const sgm_query *q, uint32_t flags, sgm_result **out) {
+    if (!out) return SGM_EINVAL;
+    *out = nullptr;
+    if (!g || !q || (flags & ~SGM_COUNT_ONLY)) return SGM_EINVAL;
+    sgm_result *res = (sgm_result *)std::calloc(1, sizeof(sgm_result));
+    if (!res) return SGM_ENOMEM;
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (hipSetDevice(g->device) != hipSuccess) {
+            std::free(res);
+            return SGM_EDEVICE;
+        }
+        rc = match_locked(g, q, flags, res);
+    }
+    res->status = rc;
+    if (rc == SGM_OK || rc == SGM_ETOOBIG) {
+        *out = res;
+        return rc;
+    }
+    std::free(res->rows);
+    std::free(res);
+    return rc;
+}
+
+int sgm_match_batch(sgm_graph *g, const sgm_query *qs, int32_t n, uint32_t flags,
+                    sgm_result **out) {
+    if (!g || !out || n < 0 || (n > 0 && !qs) || (flags & ~SGM_COUNT_ONLY)) return SGM_EINVAL;
+    for (int32_t i = 0; i < n; ++i) out[i] = nullptr;
+    for (int32_t i = 0; i < n; ++i) {
+        sgm_result *res = (sgm_result *)std::calloc(1, sizeof(sgm_result));
+        if (!res) {
+            for (int32_t j = 0; j < i; ++j) {
+                sgm_free_result(out[j]);
+                out[j] = nullptr;
+            }
+            return SGM_ENOMEM;
+        }
+        int rc;
+        {
+            std::lock_guard<std::mutex> lk(g->mu);
+            if (hipSetDevice(g->device) != hipSuccess) rc = SGM_EDEVICE;
+            else rc = match_locked(g, &qs[i], flags, res);
+        }
+        res->status = rc;
+        if (rc != SGM_OK) {
+            std::free(res->rows);
+            res->rows = nullptr;
+        }
+        out[i] = res;
+    }
+    return SGM_OK;
+}
+
+void sgm_free_result(sgm_result *r) {
+    if (!r) return;
+    std::free(r->rows);
+    std::free(r);
+}
+
+int sgm_kernel_stats(sgm_graph *g, int32_t kernel, sgm_kstat *out) {
+    if (!g || !out || kernel < 0 || kernel >= SGM_K_COUNT) return SGM_EINVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    *out = g->kstat[kernel];
+    return SGM_OK;
+}
+
+int sgm_reset_kernel_stats(sgm_graph *g) {
+    if (!g) return SGM_EINVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    for (auto &k : g->kstat) k = sgm_kstat{};
+    return SGM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,186 @@
+// Host-side query checks and query plan (no device code).
+//
+// Plan: thesis Ch. 3, Sec. "Query Plan Generation" (rank f(u) = deg(u) /
+// freq(u.label); first edge maximising f(u) + f(v); spanning tree T and
+// visit order O of expanded vertices) and the commonsense variant of Sec.
+// "GpSense" (a concept node has frequency 1, so pinned vertices of highest
+// degree come first; the next vertex is the one whose adjacency holds the
+// most vertices not yet reached; stop once the tree covers the query).
+#include "sgm_plan.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace sgm {
+
+int check_query(const sgm_query *q, int32_t V, QInfo *qi) {
+    if (!q) return SGM_EINVAL;
+    const int n = q->n_vertices, m = q->n_edges;
+    if (n < 1 || m < 0) return SGM_EINVAL;
+    if (n > SGM_MAX_QV || m > SGM_MAX_QE) return SGM_EUNSUPPORTED;
+    if (!q->vertex_label || !q->vertex_pin || (m > 0 && (!q->edge_src || !q->edge_dst || !q->edge_label)))
+        return SGM_EINVAL;
+    std::memset(qi, 0, sizeof(*qi));
+    qi->n = n;
+    qi->m = m;
+    for (int u = 0; u < n; ++u) {
+        qi->label[u] = q->vertex_label[u];
+        qi->pin[u] = q->vertex_pin[u];
+        if (qi->label[u] < -1 || qi->pin[u] < -1 || qi->pin[u] >= V) return SGM_EINVAL;
+    }
+    for (int i = 0; i < m; ++i) {
+        const int a = q->edge_src[i], b = q->edge_dst[i], r = q->edge_label[i];
+        if (a < 0 || a >= n || b < 0 || b >= n || a == b || r < -1) return SGM_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (qi->esrc[j] == a && qi->edst[j] == b && qi->elabel[j] == r) return SGM_EINVAL;
+        qi->esrc[i] = a;
+        qi->edst[i] = b;
+        qi->elabel[i] = r;
+        qi->out_mask[a] |= 1u << b;
+        qi->in_mask[b] |= 1u << a;
+    }
+    for (int u = 0; u < n; ++u) {
+        qi->qout[u] = __builtin_popcount(qi->out_mask[u]);
+        qi->qin[u] = __builtin_popcount(qi->in_mask[u]);
+        qi->deg[u] = __builtin_popcount(qi->out_mask[u] | qi->in_mask[u]);
+    }
+    // connected (undirected)
+    uint32_t seen = 1u, frontier = 1u;
+    while (frontier) {
+        uint32_t next = 0;
+        for (int u = 0; u < n; ++u)
+            if (frontier & (1u << u)) next |= qi->out_mask[u] | qi->in_mask[u];
+        next &= ~seen;
+        seen |= next;
+        frontier = next;
+    }
+    if (seen != ((n == 32) ? 0xffffffffu : ((1u << n) - 1u))) return SGM_EINVAL;
+    return SGM_OK;
+}
+
+namespace {
+
+// f(u) = deg(u) / freq(u) as an exact fraction
+struct Frac {
+    int64_t num, den;
+};
+
+Frac rank_f(const QInfo &qi, int u, int32_t V, const int64_t *type_freq, int32_t n_types) {
+    int64_t freq;
+    if (qi.pin[u] >= 0) freq = 1;
+    else if (qi.label[u] < 0) freq = V;
+    else freq = (qi.label[u] < n_types) ? type_freq[qi.label[u]] : 0;
+    if (freq < 1) freq = 1;  // no data vertex of this type: no match either way
+    return Frac{qi.deg[u], freq};
+}
+
+// a < b for non-negative fractions
+bool frac_less(Frac a, Frac b) {
+    return (__int128)a.num * b.den < (__int128)b.num * a.den;
+}
+
+bool sum_less(Frac a1, Frac a2, Frac b1, Frac b2) {
+    // (a1 + a2) < (b1 + b2) with 128-bit intermediates
+    const __int128 an = (__int128)a1.num * a2.den + (__int128)a2.num * a1.den;
+    const __int128 ad = (__int128)a1.den * a2.den;
+    const __int128 bn = (__int128)b1.num * b2.den + (__int128)b2.num * b1.den;
+    const __int128 bd = (__int128)b1.den * b2.den;
+    // an/ad < bn/bd  <=>  an*bd < bn*ad ; magnitudes: an <= 2^36, bd <= 2^62
+    // -> products <= 2^98 fit in 128 bits
+    return an * bd < bn * ad;
+}
+
+}  // namespace
+
+int make_plan(const QInfo &qi, int32_t V, const int64_t *type_freq, int32_t n_types, Plan *p) {
+    const int n = qi.n, m = qi.m;
+    std::memset(p, 0, sizeof(*p));
+    for (int u = 0; u < SGM_MAX_QV; ++u) {
+        p->parent[u] = -1;
+        p->parent_edge[u] = -1;
+        p->visit[u] = -1;
+        p->init[u] = -1;
+    }
+    Frac f[SGM_MAX_QV];
+    for (int u = 0; u < n; ++u) f[u] = rank_f(qi, u, V, type_freq, n_types);
+    if (m == 0) {
+        p->n_visit = 1;
+        p->visit[0] = 0;
+        p->n_init = 1;
+        p->init[0] = 0;
+        return SGM_OK;
+    }
+    // first edge: maximum f(a) + f(b), lowest edge index on ties
+    int best = 0;
+    for (int i = 1; i < m; ++i)
+        if (sum_less(f[qi.esrc[best]], f[qi.edst[best]], f[qi.esrc[i]], f[qi.edst[i]])) best = i;
+    int a = qi.esrc[best], b = qi.edst[best];
+    // u = endpoint with f(u) >= f(v); lower vertex id if equal
+    int root;
+    if (frac_less(f[a], f[b])) root = b;
+    else if (frac_less(f[b], f[a])) root = a;
+    else root = std::min(a, b);
+
+    uint32_t in_tree = 0, expanded = 0;
+    auto nbr_mask = [&](int u) { return qi.out_mask[u] | qi.in_mask[u]; };
+    auto lowest_edge = [&](int u, int v) {
+        for (int i = 0; i < m; ++i)
+            if ((qi.esrc[i] == u && qi.edst[i] == v) || (qi.esrc[i] == v && qi.edst[i] == u))
+                return i;
+        return -1;
+    };
+    auto expand = [&](int u) {
+        expanded |= 1u << u;
+        p->visit[p->n_visit++] = u;
+        const uint32_t nb = nbr_mask(u) & ~in_tree;
+        for (int x = 0; x < n; ++x) {
+            if (!(nb & (1u << x))) continue;
+            in_tree |= 1u << x;
+            p->parent[x] = u;
+            p->parent_edge[x] = lowest_edge(u, x);
+            p->init[p->n_init++] = x;
+        }
+    };
+    in_tree |= 1u << root;
+    p->init[p->n_init++] = root;
+    expand(root);
+    const uint32_t all = (1u << n) - 1u;
+    while (in_tree != all) {
+        // next: reached but unexpanded vertex whose adjacency holds the most
+        // unreached vertices; then larger f; then lower id
+        int nxt = -1, nxt_new = 0;
+        for (int v = 0; v < n; ++v) {
+            if (!(in_tree & (1u << v)) || (expanded & (1u << v))) continue;
+            const int nn = __builtin_popcount(nbr_mask(v) & ~in_tree);
+            if (nn == 0) continue;
+            if (nxt < 0 || nn > nxt_new || (nn == nxt_new && frac_less(f[nxt], f[v]))) {
+                nxt = v;
+                nxt_new = nn;
+            }
+        }
+        if (nxt < 0) return SGM_EINVAL;  // disconnected (checked earlier)
+        expand(nxt);
+    }
+    return SGM_OK;
+}
+
+}  // namespace sgm
+
+extern "C" int sgm_plan_query(const sgm_query *q, int32_t n_vertices, const int64_t *type_freq,
+                              int32_t n_types, int32_t *visit_order, int32_t *parent,
+                              int32_t *parent_edge, int32_t *init_order) {
+    if (n_vertices < 1 || (n_types > 0 && !type_freq) || n_types < 0) return SGM_EINVAL;
+    sgm::QInfo qi;
+    int rc = sgm::check_query(q, n_vertices, &qi);
+    if (rc != SGM_OK) return rc;
+    sgm::Plan p;
+    rc = sgm::make_plan(qi, n_vertices, type_freq, n_types, &p);
+    if (rc != SGM_OK) return rc;
+    for (int u = 0; u < SGM_MAX_QV; ++u) {
+        if (visit_order) visit_order[u] = p.visit[u];
+        if (parent) parent[u] = p.parent[u];
+        if (parent_edge) parent_edge[u] = p.parent_edge[u];
+        if (init_order) init_order[u] = p.init[u];
+    }
+    return SGM_OK;
+}

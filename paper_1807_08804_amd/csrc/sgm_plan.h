@@ -1,0 +1,36 @@
+// Host-side query checks and query plan of the sgm library (internal).
+#pragma once
+
+#include <stdint.h>
+
+#include "../../include/sgm.h"
+
+namespace sgm {
+
+// A validated query with its per-vertex neighbour masks.
+struct QInfo {
+    int n, m;
+    int32_t label[SGM_MAX_QV], pin[SGM_MAX_QV];
+    int32_t esrc[SGM_MAX_QE], edst[SGM_MAX_QE], elabel[SGM_MAX_QE];
+    uint32_t out_mask[SGM_MAX_QV];  // bit v: some edge u -> v
+    uint32_t in_mask[SGM_MAX_QV];   // bit v: some edge v -> u
+    int32_t qout[SGM_MAX_QV];       // distinct out-neighbours
+    int32_t qin[SGM_MAX_QV];        // distinct in-neighbours
+    int32_t deg[SGM_MAX_QV];        // distinct neighbours, either direction
+};
+
+// Spanning tree T and orders of the filtering phase.
+struct Plan {
+    int n_visit;
+    int32_t visit[SGM_MAX_QV];        // O: expanded vertices in order
+    int32_t parent[SGM_MAX_QV];       // tree parent, -1 for the root
+    int32_t parent_edge[SGM_MAX_QV];  // query edge to the parent, -1 for the root
+    int n_init;
+    int32_t init[SGM_MAX_QV];         // order in which vertices enter T
+};
+
+// SGM_OK, SGM_EINVAL or SGM_EUNSUPPORTED (see sgm_match_query).
+int check_query(const sgm_query *q, int32_t V, QInfo *qi);
+int make_plan(const QInfo &qi, int32_t V, const int64_t *type_freq, int32_t n_types, Plan *p);
+
+}  // namespace sgm

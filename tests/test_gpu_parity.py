@@ -1,0 +1,176 @@
+"""GPU parity: the HIP library's embedding tables against the CPU oracle,
+element by element (bit-exact: all work is integer)."""
+import sys
+
+import numpy as np
+import pytest
+
+import kggen
+import oracle
+import paper_1807_08804_amd as P
+from tests.micro import MicroQuery, random_graph, random_query
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def same(gpu_rows, want):
+    assert gpu_rows.shape == want.shape, (gpu_rows.shape, want.shape)
+    assert np.array_equal(gpu_rows, want)
+
+
+@pytest.fixture(scope="module")
+def g_tiny(tiny_kg):
+    return P.Graph.from_kg(tiny_kg)
+
+
+@pytest.fixture(scope="module")
+def g_medium(medium_kg):
+    return P.Graph.from_kg(medium_kg)
+
+
+@pytest.fixture(scope="module")
+def medium_queries(medium_kg):
+    qs, _ = kggen.medium_queries(medium_kg, 100)
+    return qs
+
+
+def test_tiny_config(tiny_kg, g_tiny, oracle_tiny):
+    say("case: tiny config query")
+    q = kggen.tiny_query(tiny_kg)
+    same(g_tiny.match_query(q), oracle_tiny.match_query(q))
+
+
+def test_graph_info(tiny_kg, g_tiny):
+    info = g_tiny.info()
+    assert info["n_vertices"] == tiny_kg.V and info["n_edges"] == tiny_kg.E
+    assert info["max_out"] == int(np.diff(tiny_kg.row_ptr).max())
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_micro_random(seed):
+    """Micro graphs with repeated triples, self-loops and multi-relation
+    pairs; queries with any-type vertices, variable edges, pins, 2-cycles."""
+    rng = np.random.default_rng(500 + seed)
+    V = int(rng.integers(2, 40))
+    mg = random_graph(rng, V, int(rng.integers(1, 4 * V)), n_types=3, n_rels=3)
+    rp, col, rel, typ = mg.csr()
+    say(f"case: micro seed={seed} V={V} E={len(col)}")
+    g = P.Graph(rp, col, rel, typ)
+    og = oracle.Graph(V, mg.src, mg.dst, mg.rel, mg.vtype)
+    for i in range(10):
+        q = random_query(rng, int(rng.integers(1, 6)), 3, 3, V, p_pin=0.15, extra=3)
+        same(g.match_query(q), og.match_query(q))
+    g.close()
+
+
+def test_medium_config(medium_kg, g_medium, oracle_medium, medium_queries):
+    """100 random-walk queries of 6-10 vertices (paths and trees, <= 2 pins)."""
+    tot = 0
+    for i, q in enumerate(medium_queries):
+        say(f"case: medium query {i} n={q.n} m={q.m} pins={(q.vpin >= 0).sum()}")
+        got = g_medium.match_query(q)
+        same(got, oracle_medium.match_query(q))
+        assert tuple(q.walk) in set(map(tuple, got.tolist()))
+        tot += len(got)
+    assert tot > 0
+
+
+def any_query(n, edges, vlabel=None, vpin=None):
+    return MicroQuery(n, [-1] * n if vlabel is None else vlabel,
+                      [-1] * n if vpin is None else vpin,
+                      [e[0] for e in edges], [e[1] for e in edges], [e[2] for e in edges])
+
+
+@pytest.mark.parametrize("name,q", [
+    ("edge-any", any_query(2, [(0, 1, -1)])),
+    ("path3-reversed-cols", any_query(3, [(2, 1, -1), (1, 0, -1)])),
+    ("triangle", any_query(3, [(0, 1, -1), (1, 2, -1), (0, 2, -1)])),
+    ("2cycle+tail", any_query(3, [(0, 1, -1), (1, 0, -1), (2, 1, 0)])),
+    ("star3-typed", any_query(4, [(1, 0, -1), (1, 2, -1), (1, 3, -1)], vlabel=[-1, -1, 3, 3])),
+    ("square", any_query(4, [(0, 1, -1), (1, 2, -1), (3, 2, -1), (0, 3, -1)])),
+])
+def test_tiny_large_outputs(name, q, g_tiny, oracle_tiny):
+    """Unlabelled queries with thousands of rows: multi-tile joins, the
+    radix-sorted final ordering and column permutations."""
+    say(f"case: tiny large-output {name}")
+    same(g_tiny.match_query(q), oracle_tiny.match_query(q))
+
+
+def test_medium_large_output(g_medium, oracle_medium):
+    """~8.5M-row 2-path table on the medium graph (hub rows, big-degree
+    paths, multi-pass radix ordering)."""
+    q = any_query(3, [(1, 0, -1), (2, 1, -1)])
+    say("case: medium 2-path any")
+    same(g_medium.match_query(q), oracle_medium.match_query(q))
+
+
+def test_medium_hub_star(medium_kg, g_medium, oracle_medium):
+    """Pinned hub centre: candidates pushed from a ~64K-degree row."""
+    hub = int(np.argmax(np.diff(medium_kg.row_ptr)))
+    for t in (0, 9):
+        q = any_query(3, [(0, 1, -1), (0, 2, 0)], vlabel=[-1, t, -1], vpin=[hub, -1, -1])
+        say(f"case: medium hub star type={t}")
+        same(g_medium.match_query(q), oracle_medium.match_query(q))
+    q = any_query(3, [(1, 0, -1), (2, 1, -1)], vlabel=[-1, -1, 4], vpin=[hub, -1, -1])
+    same(g_medium.match_query(q), oracle_medium.match_query(q))
+
+
+@pytest.mark.parametrize("opts", [dict(refine_rounds=0), dict(refine_rounds=-1),
+                                  dict(refine_reversed=0), dict(low_conn_degree=0),
+                                  dict(low_conn_degree=4, refine_rounds=3)])
+def test_filter_options_do_not_change_results(opts, medium_kg, oracle_medium, medium_queries):
+    say(f"case: options {opts}")
+    g = P.Graph.from_kg(medium_kg, **opts)
+    for q in medium_queries[:25]:
+        same(g.match_query(q), oracle_medium.match_query(q))
+    g.close()
+
+
+def test_count_only_and_cap(tiny_kg, oracle_tiny):
+    q = any_query(3, [(0, 1, -1), (1, 2, -1)])
+    want = oracle_tiny.match_query(q, count_only=True)
+    g = P.Graph.from_kg(tiny_kg, result_cap_rows=10)
+    with pytest.raises(P.SGMError) as e:
+        g.match_query(q)
+    assert e.value.code == P.SGM_ETOOBIG and e.value.n_rows == want
+    g.close()
+    g = P.Graph.from_kg(tiny_kg)
+    assert g.match_query(q, count_only=True) == want
+    g.close()
+
+
+def test_invalid_queries(g_tiny):
+    for q, code in [(any_query(2, [(0, 0, -1)]), P.SGM_EINVAL),
+                    (any_query(3, [(0, 1, -1)]), P.SGM_EINVAL),
+                    (any_query(2, [(0, 1, 1), (0, 1, 1)]), P.SGM_EINVAL)]:
+        with pytest.raises(P.SGMError) as e:
+            g_tiny.match_query(q)
+        assert e.value.code == code
+
+
+def test_single_vertex_and_empty(tiny_kg, g_tiny, oracle_tiny):
+    for q in [any_query(1, []), any_query(1, [], vlabel=[7]), any_query(1, [], vpin=[5]),
+              any_query(2, [(0, 1, 99)]), any_query(2, [(0, 1, -1)], vlabel=[63, 99])]:
+        same(g_tiny.match_query(q), oracle_tiny.match_query(q))
+
+
+def test_batch_equals_alone(g_medium, medium_queries):
+    qs = medium_queries[:20] + [any_query(2, [(0, 0, -1)])]
+    alone = [g_medium.match_query(q) for q in qs[:-1]]
+    batch = g_medium.match_batch(qs)
+    for a, b in zip(alone, batch[:-1]):
+        same(b, a)
+    assert isinstance(batch[-1], P.SGMError) and batch[-1].code == P.SGM_EINVAL
+
+
+def test_repeat_is_deterministic(g_medium, medium_queries):
+    q = medium_queries[3]
+    a, sa = g_medium.match_query(q, with_stats=True)
+    b, sb = g_medium.match_query(q, with_stats=True)
+    same(a, b)
+    assert sa["cand"] == sb["cand"] and sa["level_rows"] == sb["level_rows"]

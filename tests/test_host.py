@@ -1,0 +1,128 @@
+"""CPU-only checks of the library: it loads, exports every declared symbol,
+and its host logic (query checks, query plan, CSR checks) behaves as the
+thesis describes. No kernel is launched here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1807_08804_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "sgm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sgm_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.lib()
+    names = declared_functions()
+    assert "sgm_load_graph" in names and "sgm_match_batch" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(P.EXPORTS)
+
+
+def plan(n, vlabel, vpin, edges, V=1000, type_freq=None):
+    tf = np.full(64, 10) if type_freq is None else type_freq
+    return P.sgm_plan_query(n, vlabel, vpin, [e[0] for e in edges], [e[1] for e in edges],
+                            [e[2] for e in edges], V, tf)
+
+
+def err(n, vlabel, vpin, edges, V=1000):
+    with pytest.raises(P.SGMError) as e:
+        plan(n, vlabel, vpin, edges, V)
+    return e.value.code
+
+
+def test_query_checks():
+    assert err(2, [-1, -1], [-1, -1], [(0, 0, -1)]) == P.SGM_EINVAL          # self-loop
+    assert err(3, [-1] * 3, [-1] * 3, [(0, 1, -1)]) == P.SGM_EINVAL           # disconnected
+    assert err(2, [-1, -1], [-1, -1], [(0, 1, 2), (0, 1, 2)]) == P.SGM_EINVAL  # duplicate
+    assert err(2, [-1, -1], [5000, -1], [(0, 1, -1)]) == P.SGM_EINVAL         # pin out of range
+    assert err(2, [-1, -1], [-1, -1], [(0, 2, -1)]) == P.SGM_EINVAL           # bad index
+    assert err(2, [-2, -1], [-1, -1], [(0, 1, -1)]) == P.SGM_EINVAL           # bad label
+    assert err(17, [-1] * 17, [-1] * 17, [(i, i + 1, -1) for i in range(16)]) == P.SGM_EUNSUPPORTED
+    # same pair, two relations, both directions: allowed
+    plan(2, [-1, -1], [-1, -1], [(0, 1, 2), (0, 1, 3), (1, 0, -1)])
+
+
+def check_tree(p, n, edges):
+    # parents form a spanning tree rooted at visit_order[0] whose parent edges
+    # join each vertex to its parent
+    root = p["visit_order"][0]
+    assert p["parent"][root] == -1
+    assert sorted(p["init_order"]) == list(range(n))
+    assert p["init_order"][0] == root
+    for u in range(n):
+        if u == root:
+            continue
+        par, e = p["parent"][u], p["parent_edge"][u]
+        assert {edges[e][0], edges[e][1]} == {u, par}
+        assert par in p["visit_order"]
+        # the parent entered the tree before u
+        assert p["init_order"].index(par) < p["init_order"].index(u)
+    # the expanded vertices are exactly the tree's internal vertices
+    internal = {p["parent"][u] for u in range(n) if p["parent"][u] >= 0}
+    assert internal == set(p["visit_order"]) or n == 1
+
+
+def test_plan_prefers_pinned_vertex_of_max_degree():
+    # star centre 0 (degree 3) pinned, leaf 3 pinned: centre first
+    edges = [(0, 1, -1), (0, 2, -1), (3, 0, -1), (1, 2, -1)]
+    p = plan(4, [1, 1, 1, 1], [7, -1, -1, 9], edges)
+    assert p["visit_order"][0] == 0
+    check_tree(p, 4, edges)
+
+
+def test_plan_rank_by_degree_over_frequency():
+    # unpinned: f(u) = deg(u) / freq(label); rare label wins
+    tf = np.full(64, 100)
+    tf[5] = 2
+    edges = [(0, 1, -1), (1, 2, -1), (2, 3, -1)]
+    p = plan(4, [1, 1, 1, 5], [-1] * 4, edges, type_freq=tf)
+    # edge (2,3): f(2)=2/100, f(3)=1/2 -> largest sum; u = 3 (larger f)
+    assert p["visit_order"][0] == 3
+    check_tree(p, 4, edges)
+
+
+def test_plan_next_vertex_reaches_most_new_vertices():
+    # path 0-1-2 with a fan at 2 (2 -> 3,4,5); root pinned at 0
+    edges = [(0, 1, -1), (1, 2, -1), (2, 3, -1), (2, 4, -1), (2, 5, -1)]
+    p = plan(6, [-1] * 6, [4, -1, -1, -1, -1, -1], edges)
+    assert p["visit_order"] == [0, 1, 2]
+    check_tree(p, 6, edges)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_plan_random_queries_give_spanning_trees(seed):
+    from tests.micro import random_query
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 17))
+    q = random_query(rng, n, 4, 3, 1000, extra=4)
+    edges = list(zip(q.esrc.tolist(), q.edst.tolist(), q.elabel.tolist()))
+    p = plan(n, q.vlabel, q.vpin, edges, type_freq=rng.integers(1, 500, 64))
+    check_tree(p, n, edges)
+
+
+def test_load_graph_rejects_malformed_csr_before_touching_device():
+    for row_ptr, col, rel, typ in [
+        ([0, 1, 5], [1, 0], [0, 0], [0, 0]),       # row_ptr[V] != E
+        ([0, 2, 1], [1, 0], [0, 0], [0, 0]),       # decreasing
+        ([0, 1, 2], [1, 2], [0, 0], [0, 0]),       # col out of range
+        ([0, 1, 2], [1, 0], [0, -1], [0, 0]),      # negative relation
+        ([0, 1, 2], [1, 0], [0, 0], [0, -3]),      # negative type
+    ]:
+        with pytest.raises(P.SGMError) as e:
+            P.sgm_load_graph(len(row_ptr) - 1, row_ptr[-1] if row_ptr[-1] <= 2 else 2, row_ptr,
+                             col, rel, typ)
+        assert e.value.code == P.SGM_EINVAL
+
+
+def test_strerror():
+    assert P.sgm_strerror(P.SGM_ETOOBIG)
+    assert P.sgm_strerror(12345) == "unknown error"
