@@ -56,11 +56,15 @@ def main():
     g = P.Graph.from_kg(kg)
     gp = P.Graph.from_kg(kg, profile=1)
 
-    def one_step(graph, lat=None):
+    def one_step(graph, lat=None, stats=None):
         rows = 0
         for q in queries:
             a = time.perf_counter_ns()
-            r = graph.match_query(q)
+            if stats is None:
+                r = graph.match_query(q)
+            else:
+                r, st = graph.match_query(q, with_stats=True)
+                stats.append(st)
             if lat is not None:
                 lat.append(time.perf_counter_ns() - a)
             rows += len(r)
@@ -90,6 +94,14 @@ def main():
     el_b = time.perf_counter() - t
     batch_qps = nq / el_b
     log(f"batch path {el_b:.3f}s")
+
+    # per-phase device times of the persistent kernel (one pass)
+    stl = []
+    one_step(g, stats=stl)
+    narrow = [st for st in stl if st["path"] == P.SGM_PATH_NARROW]
+    phases = {k: round(statistics.mean(st[k] for st in narrow) / 1e3, 2) if narrow else None
+              for k in ("ns_filter", "ns_collect", "ns_join", "ns_finish")}
+    phases["queries_on_persistent_kernel"] = len(narrow)
 
     # roofline: every launch timed with HIP events on the library stream
     one_step(gp)
@@ -146,6 +158,7 @@ def main():
         "embeddings_per_s": round(rows / el, 1),
         "latency_ms": {"p50": round(p50, 3), "p99": round(p99, 3)},
         "batch_api_queries_per_s": round(batch_qps, 3),
+        "persistent_kernel_phase_us": phases,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

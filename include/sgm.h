@@ -59,8 +59,20 @@ typedef struct {
                                   larger levels are processed in chunks */
     int32_t profile;           /* 1: time every kernel launch with HIP events
                                   (sgm_kernel_stats) */
-    int32_t reserved[7];
+    int32_t path;              /* SGM_PATH_AUTO (default), SGM_PATH_WIDE or
+                                  SGM_PATH_NARROW (see below) */
+    int32_t reserved[6];
 } sgm_options;
+
+/* Execution paths. NARROW: one persistent kernel in which each workgroup
+ * runs whole queries (used for batches and for single queries that fit a
+ * workgroup's slot); WIDE: one multi-kernel pipeline per query using the
+ * whole GPU for each phase. AUTO runs NARROW first and reruns on WIDE every
+ * query that outgrows a slot; NARROW alone fails such a query with
+ * SGM_EUNSUPPORTED. Results are identical on every path. */
+#define SGM_PATH_AUTO 0
+#define SGM_PATH_WIDE 1
+#define SGM_PATH_NARROW 2
 
 /* A query graph (thesis Ch. 3, Sec. "Commonsense Graph Transformation" and
  * Def. 3.2): 1..SGM_MAX_QV vertices, 0..SGM_MAX_QE directed edges.
@@ -91,8 +103,14 @@ typedef struct {
     int64_t peak_bytes;            /* largest intermediate table, bytes */
     int32_t n_chunks;              /* join chunks (1 = no chunking) */
     int32_t n_launches;            /* kernel launches for this query */
-    int64_t ns_total;              /* host wall time of the call */
-    int64_t ns_filter, ns_collect, ns_join, ns_finish;
+    int64_t ns_total;              /* host wall time of the call (of the whole batch
+                                      for sgm_match_batch) */
+    int64_t ns_filter, ns_collect, ns_join, ns_finish; /* phase times: host-measured on
+                                      the multi-kernel path, device clock on the
+                                      persistent kernel */
+    int64_t device_bytes;          /* persistent kernel: algorithmic bytes moved */
+    int32_t path;                  /* SGM_PATH_WIDE or SGM_PATH_NARROW: where it ran */
+    int32_t pad_;
 } sgm_stats;
 
 typedef struct {
@@ -121,7 +139,8 @@ typedef struct {
 #define SGM_K_JOIN 6      /* join levels (fan, count, write) */
 #define SGM_K_SORT 7      /* final ordering */
 #define SGM_K_OTHER 8     /* scans, clears, gathers */
-#define SGM_K_COUNT 9
+#define SGM_K_PERSIST 9   /* persistent per-query kernel (whole queries) */
+#define SGM_K_COUNT 10
 
 /* Fill *o with the defaults documented above. */
 void sgm_default_options(sgm_options *o);

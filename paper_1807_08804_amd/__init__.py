@@ -22,10 +22,11 @@ LIB_PATH = os.path.join(HERE, "libsgm.so")
 SGM_OK, SGM_EINVAL, SGM_ENOMEM, SGM_EDEVICE, SGM_ETOOBIG, SGM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 SGM_MAX_QV, SGM_MAX_QE = 16, 64
 SGM_SORTED, SGM_COUNT_ONLY = 0, 1
+SGM_PATH_AUTO, SGM_PATH_WIDE, SGM_PATH_NARROW = 0, 1, 2
 (SGM_K_CHECK, SGM_K_COLLECT, SGM_K_EXPLORE, SGM_K_REFINE, SGM_K_EC_COUNT, SGM_K_EC_WRITE,
- SGM_K_JOIN, SGM_K_SORT, SGM_K_OTHER, SGM_K_COUNT) = range(10)
+ SGM_K_JOIN, SGM_K_SORT, SGM_K_OTHER, SGM_K_PERSIST, SGM_K_COUNT) = range(11)
 KERNEL_NAMES = ["check", "collect", "explore", "refine", "ec_count", "ec_write", "join",
-                "sort", "other"]
+                "sort", "other", "persist"]
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -35,7 +36,8 @@ class sgm_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("refine_rounds", ctypes.c_int32),
                 ("refine_reversed", ctypes.c_int32), ("low_conn_degree", ctypes.c_int32),
                 ("result_cap_rows", ctypes.c_int64), ("join_budget_bytes", ctypes.c_int64),
-                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("profile", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class sgm_query(ctypes.Structure):
@@ -53,7 +55,8 @@ class sgm_stats(ctypes.Structure):
                 ("n_chunks", ctypes.c_int32), ("n_launches", ctypes.c_int32),
                 ("ns_total", ctypes.c_int64), ("ns_filter", ctypes.c_int64),
                 ("ns_collect", ctypes.c_int64), ("ns_join", ctypes.c_int64),
-                ("ns_finish", ctypes.c_int64)]
+                ("ns_finish", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("path", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class sgm_result(ctypes.Structure):
@@ -210,7 +213,8 @@ def stats_dict(st: sgm_stats, n: int, m: int) -> dict:
                 visit_order=[x for x in st.visit_order if x >= 0],
                 peak_rows=st.peak_rows, peak_bytes=st.peak_bytes, n_chunks=st.n_chunks,
                 n_launches=st.n_launches, ns_total=st.ns_total, ns_filter=st.ns_filter,
-                ns_collect=st.ns_collect, ns_join=st.ns_join, ns_finish=st.ns_finish)
+                ns_collect=st.ns_collect, ns_join=st.ns_join, ns_finish=st.ns_finish,
+                device_bytes=st.device_bytes, path=st.path)
 
 
 class Graph:

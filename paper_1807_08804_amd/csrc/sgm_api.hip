@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "sgm_internal.h"
+#include "sgm_narrow.h"
 #include "sgm_plan.h"
 
 using namespace sgm;
@@ -153,6 +154,7 @@ struct sgm_graph {
     int32_t nwords = 0;
     int32_t max_out = 0, max_in = 0;
     int32_t n_big = 0;  // vertices with a direction above kBigDegree
+    double ns_per_tick = 10.0;  // device wall clock period
     int32_t n_types = 0;
     std::vector<int64_t> type_freq;
     DevGraph dg{};
@@ -185,6 +187,26 @@ struct sgm_graph {
     std::vector<Pending> pending;
     sgm_kstat kstat[SGM_K_COUNT]{};
     int launches = 0;
+    // persistent per-query kernel: slots, descriptors, output arena
+    struct Narrow {
+        int slots = 0;
+        int32_t lcap = 0;
+        int64_t slab_bytes = 0;
+        uint64_t *bits = nullptr;
+        int32_t *lists = nullptr;
+        char *slab = nullptr;
+        int qcap = 0;
+        NQuery *d_q = nullptr, *h_q = nullptr;
+        NResult *d_res = nullptr, *h_res = nullptr;
+        int32_t *d_root_q = nullptr, *h_root_q = nullptr;
+        int root_cap = 0;
+        uint64_t *d_rootbits = nullptr;
+        int32_t *d_out = nullptr;
+        int64_t out_cap = 0;
+        unsigned long long *d_ctr = nullptr, *h_ctr = nullptr;  // [0] queue, [1] out used
+        int32_t *h_out = nullptr;
+        int64_t h_out_cap = 0;
+    } nw;
 };
 
 namespace {
@@ -316,6 +338,14 @@ void free_graph_mem(sgm_graph *g) {
     void *hp[] = {g->h_desc, g->h_cnt, g->h_slots, g->h_small, g->h_rows};
     for (void *p : hp)
         if (p) (void)hipHostFree(p);
+    auto &nw = g->nw;
+    void *ndp[] = {nw.bits, nw.lists, nw.slab, nw.d_q, nw.d_res, nw.d_root_q, nw.d_rootbits,
+                   nw.d_out, nw.d_ctr};
+    for (void *p : ndp)
+        if (p) (void)hipFree(p);
+    void *nhp[] = {nw.h_q, nw.h_res, nw.h_root_q, nw.h_ctr, nw.h_out};
+    for (void *p : nhp)
+        if (p) (void)hipHostFree(p);
     if (g->stream) (void)hipStreamDestroy(g->stream);
 }
 
@@ -402,81 +432,20 @@ struct Query {
         HIPX(hipMemsetAsync(g->d_bits, 0, sizeof(uint64_t) * (size_t)n * g->nwords, st()));
         HIPX(hipMemsetAsync(g->d_cnt, 0, sizeof(DevCounters), st()));
         // descriptors for every filter launch, uploaded once
+        Program pr;
+        build_program(qi, pl, g->opts.low_conn_degree, g->opts.refine_reversed, &pr);
         std::vector<NbrDesc> &hd = desc_;
         hd.clear();
-        struct Step {
-            int u;
-            int first, count;
-            bool push;
-            int parent_push;  // vertex whose bitmap is intersected with the scratch, or -1
-        };
-        std::vector<Step> init_steps;
-        bool initialized[SGM_MAX_QV] = {};
-        for (int oi = 0; oi < pl.n_visit; ++oi) {
-            const int u = pl.visit[oi];
-            initialized[u] = true;
-            Step s{u, (int)hd.size(), 0, true, -1};
-            // spanning-tree neighbours: parent, then children
-            auto add = [&](int v, int e) {
-                NbrDesc d{};
-                const bool out = qi.esrc[e] == u;
-                d.dir = out ? 0 : 1;
-                d.rel = qi.elabel[e];
-                d.pred = pred(v);
-                d.push = 1;
-                if (initialized[v]) {
-                    d.mode = 0;
-                    d.test_bits = bits(v);
-                    d.push_bits = scratch();
-                    s.parent_push = v;
-                } else {
-                    d.mode = 1;
-                    d.test_bits = nullptr;
-                    d.push_bits = bits(v);
-                }
-                hd.push_back(d);
-            };
-            if (pl.parent[u] >= 0) add(pl.parent[u], pl.parent_edge[u]);
-            for (int x = 0; x < n; ++x)
-                if (pl.parent[x] == u) add(x, pl.parent_edge[x]);
-            s.count = (int)hd.size() - s.first;
-            init_steps.push_back(s);
-            if (pl.parent[u] >= 0) initialized[pl.parent[u]] = true;
-            for (int x = 0; x < n; ++x)
-                if (pl.parent[x] == u) initialized[x] = true;
-        }
-        // refinement: all query edges between vertices above the
-        // low-connectivity threshold, reversed visit order by default
-        const int thr = g->opts.low_conn_degree;
-        std::vector<int> rorder;
-        for (int i = 0; i < pl.n_init; ++i) {
-            const int u = pl.init[g->opts.refine_reversed ? pl.n_init - 1 - i : i];
-            if (qi.deg[u] > thr) rorder.push_back(u);
-        }
-        std::vector<Step> ref_steps;
-        for (int u : rorder) {
-            Step s{u, (int)hd.size(), 0, false, -1};
-            for (int e = 0; e < qi.m; ++e) {
-                int v;
-                NbrDesc d{};
-                if (qi.esrc[e] == u) {
-                    v = qi.edst[e];
-                    d.dir = 0;
-                } else if (qi.edst[e] == u) {
-                    v = qi.esrc[e];
-                    d.dir = 1;
-                } else {
-                    continue;
-                }
-                if (qi.deg[v] <= thr) continue;
-                d.rel = qi.elabel[e];
-                d.mode = 0;
-                d.test_bits = bits(v);
-                d.pred = pred(v);
-                hd.push_back(d);
-            }
-            s.count = (int)hd.size() - s.first;
-            if (s.count) ref_steps.push_back(s);
+        for (const PNbr &p : pr.nbr) {
+            NbrDesc d{};
+            d.dir = p.dir;
+            d.rel = p.rel;
+            d.mode = p.mode;
+            d.push = 1;
+            d.pred = pred(p.v);
+            d.test_bits = bits(p.v);
+            d.push_bits = p.mode == 0 ? scratch() : bits(p.v);
+            hd.push_back(d);
         }
         if ((int)hd.size() > kMaxDesc) return SGM_EUNSUPPORTED;
         if (!hd.empty()) {
@@ -493,26 +462,25 @@ struct Query {
             Prof p(g, SGM_K_CHECK, 12.0 * g->V + g->nwords * 8.0);
             launch_check_sweep(st(), g->dg, pred(root), bits(root));
         }
-        for (const Step &s : init_steps) {
-            if (s.count == 0) continue;
+        for (const PStep &s : pr.init) {
             collect_one(s.u);
-            if (s.parent_push >= 0)
+            if (s.parent >= 0)
                 HIPX(hipMemsetAsync(scratch(), 0, sizeof(uint64_t) * g->nwords, st()));
             const int64_t bound = qi.pin[s.u] >= 0 ? 1 : g->V;
             int rc = filter_launch(s.u, g->d_desc + s.first, s.count, true, bound,
                                    &g->d_cnt->removed[kMaxRounds], SGM_K_EXPLORE);
             if (rc) return rc;
-            if (s.parent_push >= 0) {
+            if (s.parent >= 0) {
                 Prof p(g, SGM_K_OTHER, g->nwords * 24.0);
-                launch_and(st(), bits(s.parent_push), scratch(), g->nwords);
+                launch_and(st(), bits(s.parent), scratch(), g->nwords);
             }
         }
         int rounds = g->opts.refine_rounds;
         const bool fixpoint = rounds < 0;
         if (fixpoint) rounds = kMaxRounds;
         rounds = std::min(rounds, kMaxRounds);
-        for (int r = 0; r < rounds && !ref_steps.empty(); ++r) {
-            for (const Step &s : ref_steps) {
+        for (int r = 0; r < rounds && !pr.refine.empty(); ++r) {
+            for (const PStep &s : pr.refine) {
                 collect_one(s.u);
                 const int64_t bound = qi.pin[s.u] >= 0 ? 1 : g->V;
                 int rc = filter_launch(s.u, g->d_desc + s.first, s.count, false, bound,
@@ -903,11 +871,256 @@ struct Query {
     }
 };
 
-int match_locked(sgm_graph *g, const sgm_query *q, uint32_t flags, sgm_result *res) {
-    QInfo qi;
-    int rc = check_query(q, g->V, &qi);
-    if (rc) return rc;
+// ---------------------------------------------------------------------------
+// persistent per-query kernel: resources and one batch
+// ---------------------------------------------------------------------------
+
+constexpr int kNarrowMaxSlots = 512;                 // 2 workgroups per CU
+constexpr int64_t kNarrowSlabBytes = 8ll << 20;      // per slot
+constexpr int32_t kNarrowListCap = 1 << 16;          // per query vertex
+constexpr int kNarrowQueryCap = 4096;                // queries per launch
+constexpr int64_t kNarrowOutCap = 64ll << 20;        // int32 elements (256 MB)
+
+template <class T>
+void dev_free(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+template <class T>
+void host_free(T *&p) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+}
+
+void narrow_reserve(sgm_graph *g, int slots, int nq, int nroot) {
+    auto &nw = g->nw;
+    if (nw.lcap == 0) {
+        nw.lcap = std::min<int32_t>(g->V, kNarrowListCap);
+        nw.slab_bytes = kNarrowSlabBytes;
+        HIPX(hipMalloc(&nw.d_ctr, sizeof(unsigned long long) * 2));
+        HIPX(hipHostMalloc(&nw.h_ctr, sizeof(unsigned long long) * 2, hipHostMallocDefault));
+        nw.out_cap = kNarrowOutCap;
+        HIPX(hipMalloc(&nw.d_out, sizeof(int32_t) * nw.out_cap));
+    }
+    if (slots > nw.slots) {
+        HIPX(hipStreamSynchronize(g->stream));
+        dev_free(nw.bits);
+        dev_free(nw.lists);
+        dev_free(nw.slab);
+        nw.slots = 0;
+        const size_t bw = (size_t)(SGM_MAX_QV + 1) * g->nwords;
+        HIPX(hipMalloc(&nw.bits, sizeof(uint64_t) * bw * slots));
+        HIPX(hipMemsetAsync(nw.bits, 0, sizeof(uint64_t) * bw * slots, g->stream));
+        HIPX(hipMalloc(&nw.lists, sizeof(int32_t) * (size_t)SGM_MAX_QV * nw.lcap * slots));
+        HIPX(hipMalloc(&nw.slab, (size_t)nw.slab_bytes * slots));
+        nw.slots = slots;
+    }
+    if (nq > nw.qcap) {
+        HIPX(hipStreamSynchronize(g->stream));
+        dev_free(nw.d_q);
+        dev_free(nw.d_res);
+        host_free(nw.h_q);
+        host_free(nw.h_res);
+        nw.qcap = 0;
+        HIPX(hipMalloc(&nw.d_q, sizeof(NQuery) * nq));
+        HIPX(hipMalloc(&nw.d_res, sizeof(NResult) * nq));
+        HIPX(hipHostMalloc(&nw.h_q, sizeof(NQuery) * nq, hipHostMallocDefault));
+        HIPX(hipHostMalloc(&nw.h_res, sizeof(NResult) * nq, hipHostMallocDefault));
+        nw.qcap = nq;
+    }
+    if (nroot > nw.root_cap) {
+        HIPX(hipStreamSynchronize(g->stream));
+        dev_free(nw.d_root_q);
+        dev_free(nw.d_rootbits);
+        host_free(nw.h_root_q);
+        nw.root_cap = 0;
+        HIPX(hipMalloc(&nw.d_root_q, sizeof(int32_t) * nroot));
+        HIPX(hipHostMalloc(&nw.h_root_q, sizeof(int32_t) * nroot, hipHostMallocDefault));
+        HIPX(hipMalloc(&nw.d_rootbits, sizeof(uint64_t) * (size_t)g->nwords * nroot));
+        nw.root_cap = nroot;
+    }
+}
+
+// Pack one validated query and its plan; false if it exceeds the packed
+// descriptor's capacity (the query then runs on the multi-kernel path).
+bool pack_query(sgm_graph *g, const QInfo &qi, NQuery *nq, int *root_slot_next, Plan *pl_out) {
+    Plan pl;
+    if (make_plan(qi, g->V, g->type_freq.data(), g->n_types, &pl) != SGM_OK) return false;
+    Program pr;
+    build_program(qi, pl, g->opts.low_conn_degree, g->opts.refine_reversed, &pr);
+    if ((int)(pr.init.size() + pr.refine.size()) > kNMaxSteps || (int)pr.nbr.size() > kNMaxNbr)
+        return false;
+    std::memset(nq, 0, sizeof(*nq));
+    nq->n = qi.n;
+    nq->m = qi.m;
+    for (int u = 0; u < qi.n; ++u) nq->pred[u] = VPred{qi.label[u], qi.pin[u], qi.qout[u], qi.qin[u]};
+    for (int e = 0; e < qi.m; ++e) {
+        nq->esrc[e] = qi.esrc[e];
+        nq->edst[e] = qi.edst[e];
+        nq->elabel[e] = qi.elabel[e];
+    }
+    nq->root = pl.visit[0];
+    nq->root_slot = qi.pin[nq->root] >= 0 ? -1 : (*root_slot_next)++;
+    nq->n_init = (int)pr.init.size();
+    nq->n_ref = (int)pr.refine.size();
+    nq->refine_rounds = g->opts.refine_rounds < 0 ? -1 : std::min(g->opts.refine_rounds, 32);
+    int k = 0;
+    for (const auto *v : {&pr.init, &pr.refine})
+        for (const PStep &s : *v) {
+            NStep &t = nq->steps[k++];
+            t.u = (int8_t)s.u;
+            t.push = (int8_t)s.push;
+            t.parent = (int8_t)s.parent;
+            t.first = (int16_t)s.first;
+            t.count = (int16_t)s.count;
+        }
+    for (size_t i = 0; i < pr.nbr.size(); ++i) {
+        nq->nbr[i].v = (int8_t)pr.nbr[i].v;
+        nq->nbr[i].dir = (int8_t)pr.nbr[i].dir;
+        nq->nbr[i].mode = (int8_t)pr.nbr[i].mode;
+        nq->nbr[i].rel = pr.nbr[i].rel;
+    }
+    *pl_out = pl;
+    return true;
+}
+
+// Run queries `which` (already validated into qis) through the persistent
+// kernel. Finished queries get their result in res[i]; the others are
+// appended to `wide` (slot capacity exceeded) for the multi-kernel path.
+void narrow_batch(sgm_graph *g, const std::vector<QInfo> &qis, const std::vector<int> &which,
+                  uint32_t flags, std::vector<sgm_result *> &res, std::vector<int> &wide) {
+    const int64_t t0 = now_ns();
+    std::vector<int> packed;
+    std::vector<Plan> plans;
+    packed.reserve(which.size());
+    for (size_t base = 0; base < which.size(); base += kNarrowQueryCap) {
+        const size_t end = std::min(which.size(), base + kNarrowQueryCap);
+        const int nq = (int)(end - base);
+        narrow_reserve(g, std::min(nq, kNarrowMaxSlots), nq, 0);
+        auto &nw = g->nw;
+        packed.clear();
+        plans.clear();
+        int nroot = 0;
+        for (size_t i = base; i < end; ++i) {
+            Plan pl;
+            NQuery *dst = &nw.h_q[packed.size()];
+            int rs = nroot;
+            if (pack_query(g, qis[which[i]], dst, &rs, &pl)) {
+                nroot = rs;
+                packed.push_back(which[i]);
+                plans.push_back(pl);
+            } else {
+                wide.push_back(which[i]);
+            }
+        }
+        const int np = (int)packed.size();
+        if (np == 0) continue;
+        narrow_reserve(g, std::min(np, kNarrowMaxSlots), np, nroot);
+        int k = 0;
+        for (int i = 0; i < np; ++i)
+            if (nw.h_q[i].root_slot >= 0) nw.h_root_q[k++] = i;
+        hipStream_t st = g->stream;
+        HIPX(hipMemcpyAsync(nw.d_q, nw.h_q, sizeof(NQuery) * np, hipMemcpyHostToDevice, st));
+        if (nroot)
+            HIPX(hipMemcpyAsync(nw.d_root_q, nw.h_root_q, sizeof(int32_t) * nroot,
+                                hipMemcpyHostToDevice, st));
+        HIPX(hipMemsetAsync(nw.d_ctr, 0, sizeof(unsigned long long) * 2, st));
+        if (nroot) {
+            Prof p(g, SGM_K_CHECK, (12.0 + 0.125 * nroot) * g->V);
+            launch_root_sweep(st, g->dg, nw.d_q, nw.d_root_q, nroot, nw.d_rootbits);
+        }
+        NArgs a{};
+        a.g = g->dg;
+        a.qs = nw.d_q;
+        a.nq = np;
+        a.res = nw.d_res;
+        a.queue = (int32_t *)nw.d_ctr;
+        a.bits = nw.bits;
+        a.lists = nw.lists;
+        a.lcap = nw.lcap;
+        a.slab = nw.slab;
+        a.slab_bytes = nw.slab_bytes;
+        a.rootbits = nw.d_rootbits;
+        a.out = nw.d_out;
+        a.out_cap = nw.out_cap;
+        a.out_used = nw.d_ctr + 1;
+        {
+            Prof p(g, SGM_K_PERSIST, 0.0);
+            launch_narrow(st, a, std::min(np, nw.slots));
+        }
+        HIPX(hipMemcpyAsync(nw.h_res, nw.d_res, sizeof(NResult) * np, hipMemcpyDeviceToHost, st));
+        HIPX(hipMemcpyAsync(nw.h_ctr, nw.d_ctr, sizeof(unsigned long long) * 2,
+                            hipMemcpyDeviceToHost, st));
+        sync(g);
+        if (g->opts.profile) {
+            double b = 0;
+            for (int i = 0; i < np; ++i) b += (double)nw.h_res[i].bytes;
+            g->kstat[SGM_K_PERSIST].bytes_total += b;
+        }
+        const int64_t used = std::min<int64_t>((int64_t)nw.h_ctr[1], nw.out_cap);
+        if (!(flags & SGM_COUNT_ONLY) && used > 0) {
+            if (nw.h_out_cap < used) {
+                host_free(nw.h_out);
+                nw.h_out_cap = 0;
+                const int64_t cap = std::max<int64_t>(used, 1 << 20);
+                HIPX(hipHostMalloc(&nw.h_out, sizeof(int32_t) * cap, hipHostMallocDefault));
+                nw.h_out_cap = cap;
+            }
+            HIPX(hipMemcpyAsync(nw.h_out, nw.d_out, sizeof(int32_t) * used, hipMemcpyDeviceToHost,
+                                st));
+            sync(g);
+        }
+        const int64_t t1 = now_ns();
+        for (int i = 0; i < np; ++i) {
+            const NResult &r = nw.h_res[i];
+            const int qi_idx = packed[i];
+            if (r.status != SGM_OK) {
+                wide.push_back(qi_idx);
+                continue;
+            }
+            sgm_result *out = res[qi_idx];
+            const QInfo &qi = qis[qi_idx];
+            out->n_cols = qi.n;
+            out->n_rows = r.n_rows;
+            sgm_stats &stt = out->stats;
+            for (int u = 0; u < qi.n; ++u) {
+                stt.cand[u] = r.cand[u];
+                stt.level_rows[u] = r.level_rows[u];
+                stt.join_order[u] = r.join_order[u];
+            }
+            for (int e = 0; e < qi.m; ++e) stt.ec[e] = r.ec[e];
+            for (int u = 0; u < SGM_MAX_QV; ++u) stt.visit_order[u] = plans[i].visit[u];
+            for (int u = 0; u < qi.n; ++u)
+                stt.peak_rows = std::max(stt.peak_rows, (int64_t)r.level_rows[u]);
+            stt.n_chunks = 1;
+            stt.n_launches = nroot ? 2 : 1;
+            stt.ns_total = t1 - t0;
+            stt.ns_filter = (int64_t)(r.ticks[0] * g->ns_per_tick);
+            stt.ns_collect = (int64_t)(r.ticks[1] * g->ns_per_tick);
+            stt.ns_join = (int64_t)(r.ticks[2] * g->ns_per_tick);
+            stt.ns_finish = (int64_t)(r.ticks[3] * g->ns_per_tick);
+            stt.device_bytes = r.bytes;
+            stt.path = SGM_PATH_NARROW;
+            if (g->opts.result_cap_rows > 0 && r.n_rows > g->opts.result_cap_rows) {
+                out->status = SGM_ETOOBIG;
+                continue;
+            }
+            out->status = SGM_OK;
+            if (!(flags & SGM_COUNT_ONLY)) {
+                const size_t bytes = sizeof(int32_t) * (size_t)r.n_rows * qi.n;
+                out->rows = (int32_t *)std::malloc(std::max<size_t>(bytes, 4));
+                if (!out->rows) throw std::bad_alloc();
+                if (bytes) std::memcpy(out->rows, nw.h_out + r.offset, bytes);
+            }
+        }
+    }
+}
+
+
+// multi-kernel path for one validated query
+int wide_locked(sgm_graph *g, const QInfo &qi, uint32_t flags, sgm_result *res) {
     const int l0 = g->launches;
+    int rc;
     try {
         Query Q(g, qi, res, flags);
         rc = Q.run();
@@ -921,6 +1134,44 @@ int match_locked(sgm_graph *g, const sgm_query *q, uint32_t flags, sgm_result *r
     }
     res->stats.n_launches = g->launches - l0;
     return rc;
+}
+
+// Validate, run the persistent kernel on every valid query, rerun the ones
+// that outgrow a slot on the multi-kernel path. res[i] are zeroed results;
+// per-query outcomes go to res[i]->status. Returns a global error code.
+int run_queries(sgm_graph *g, const sgm_query *qs, int n, uint32_t flags,
+                std::vector<sgm_result *> &res) {
+    std::vector<QInfo> qis((size_t)n);
+    std::vector<int> valid, wide;
+    for (int i = 0; i < n; ++i) {
+        const int rc = check_query(&qs[i], g->V, &qis[i]);
+        res[i]->status = rc;
+        if (rc == SGM_OK) valid.push_back(i);
+    }
+    if (g->opts.path == SGM_PATH_WIDE) {
+        wide = valid;
+    } else {
+        try {
+            narrow_batch(g, qis, valid, flags, res, wide);
+        } catch (const DeviceError &e) {
+            (void)hipStreamSynchronize(g->stream);
+            (void)hipGetLastError();
+            g->pending.clear();
+            return e.code;
+        } catch (const std::bad_alloc &) {
+            return SGM_ENOMEM;
+        }
+    }
+    for (int i : wide) {
+        if (g->opts.path == SGM_PATH_NARROW) {
+            res[i]->status = SGM_EUNSUPPORTED;
+            continue;
+        }
+        std::memset(&res[i]->stats, 0, sizeof(sgm_stats));
+        res[i]->stats.path = SGM_PATH_WIDE;
+        res[i]->status = wide_locked(g, qis[i], flags, res[i]);
+    }
+    return SGM_OK;
 }
 
 }  // namespace
@@ -1004,6 +1255,10 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
     try {
         HIPX(hipSetDevice(g->device));
         HIPX(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device) == hipSuccess &&
+            khz > 0)
+            g->ns_per_tick = 1e6 / khz;
         g->d_out_off = dev_upload(off);
         g->d_in_off = dev_upload(in_off);
         g->d_out_adj = dev_upload(adj);
@@ -1067,10 +1322,16 @@ int sgm_match_query(sgm_graph *g, const sgm_query *q, uint32_t flags, sgm_result
             std::free(res);
             return SGM_EDEVICE;
         }
-        rc = match_locked(g, q, flags, res);
+        std::vector<sgm_result *> rv{res};
+        rc = run_queries(g, q, 1, flags, rv);
+        if (rc == SGM_OK) rc = res->status;
     }
     res->status = rc;
     if (rc == SGM_OK || rc == SGM_ETOOBIG) {
+        if (rc != SGM_OK) {
+            std::free(res->rows);
+            res->rows = nullptr;
+        }
         *out = res;
         return rc;
     }
@@ -1082,28 +1343,31 @@ int sgm_match_query(sgm_graph *g, const sgm_query *q, uint32_t flags, sgm_result
 int sgm_match_batch(sgm_graph *g, const sgm_query *qs, int32_t n, uint32_t flags,
                     sgm_result **out) {
     if (!g || !out || n < 0 || (n > 0 && !qs) || (flags & ~SGM_COUNT_ONLY)) return SGM_EINVAL;
-    for (int32_t i = 0; i < n; ++i) out[i] = nullptr;
+    std::vector<sgm_result *> rv((size_t)n, nullptr);
     for (int32_t i = 0; i < n; ++i) {
-        sgm_result *res = (sgm_result *)std::calloc(1, sizeof(sgm_result));
-        if (!res) {
-            for (int32_t j = 0; j < i; ++j) {
-                sgm_free_result(out[j]);
-                out[j] = nullptr;
-            }
+        out[i] = nullptr;
+        rv[i] = (sgm_result *)std::calloc(1, sizeof(sgm_result));
+        if (!rv[i]) {
+            for (int32_t j = 0; j < i; ++j) std::free(rv[j]);
             return SGM_ENOMEM;
         }
-        int rc;
-        {
-            std::lock_guard<std::mutex> lk(g->mu);
-            if (hipSetDevice(g->device) != hipSuccess) rc = SGM_EDEVICE;
-            else rc = match_locked(g, &qs[i], flags, res);
+    }
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (hipSetDevice(g->device) != hipSuccess) rc = SGM_EDEVICE;
+        else rc = run_queries(g, qs, n, flags, rv);
+    }
+    if (rc != SGM_OK) {
+        for (auto *r : rv) sgm_free_result(r);
+        return rc;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        if (rv[i]->status != SGM_OK) {
+            std::free(rv[i]->rows);
+            rv[i]->rows = nullptr;
         }
-        res->status = rc;
-        if (rc != SGM_OK) {
-            std::free(res->rows);
-            res->rows = nullptr;
-        }
-        out[i] = res;
+        out[i] = rv[i];
     }
     return SGM_OK;
 }

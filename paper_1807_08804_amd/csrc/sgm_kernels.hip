@@ -8,6 +8,7 @@
 // wave64 ballot over 64 consecutive vertices yields exactly one word.
 #include <hip/hip_runtime.h>
 
+#include "sgm_device.h"
 #include "sgm_internal.h"
 
 namespace sgm {
@@ -16,27 +17,12 @@ namespace sgm {
 // helpers
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool bit_test(const uint64_t *bits, int32_t x) {
-    return (bits[x >> 6] >> (x & 63)) & 1ull;
-}
-
 __device__ __forceinline__ void bit_set_atomic(uint64_t *bits, int32_t x) {
     const uint64_t m = 1ull << (x & 63);
     uint64_t *w = bits + (x >> 6);
     // a plain read first avoids most atomics on already-set bits; a stale
     // read only costs one redundant atomic
     if (!(__atomic_load_n(w, __ATOMIC_RELAXED) & m)) atomicOr((unsigned long long *)w, m);
-}
-
-__device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
-
-// Candidate predicate (Def. 3.3 + pin + incoming degree).
-__device__ __forceinline__ bool vpred(const DevGraph &g, const VPred &p, int32_t v) {
-    if (p.pin >= 0 && v != p.pin) return false;
-    if (p.label >= 0 && g.vtype[v] != p.label) return false;
-    if (p.qout > 0 && g.out_off[v + 1] - g.out_off[v] < p.qout) return false;
-    if (p.qin > 0 && g.in_off[v + 1] - g.in_off[v] < p.qin) return false;
-    return true;
 }
 
 __device__ __forceinline__ bool nbr_ok(const DevGraph &g, const NbrDesc &d, int2 e) {
@@ -48,44 +34,6 @@ __device__ __forceinline__ bool nbr_ok(const DevGraph &g, const NbrDesc &d, int2
 __device__ __forceinline__ int32_t rank_of(const RankRef &r, int32_t x) {
     const uint64_t w = r.bits[x >> 6];
     return r.prefix[x >> 6] + __popcll(w & ((1ull << (x & 63)) - 1ull));
-}
-
-// wave-level inclusive scan (int64)
-__device__ __forceinline__ int64_t wave_incl_scan(int64_t x, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int64_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    return x;
-}
-
-__device__ __forceinline__ int32_t wave_incl_scan32(int32_t x, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    return x;
-}
-
-// Block-wide exclusive scan of one int64 per thread (blockDim = kBlock).
-// Returns the exclusive prefix; *total receives the block sum. Uses `sh`
-// (>= kBlock/64 + 1 entries) and ends with a barrier.
-__device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t *sh, int64_t *total) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
-    int64_t inc = wave_incl_scan(x, lane);
-    if (lane == 63) sh[wid] = inc;
-    __syncthreads();
-    int64_t wo = 0, tot = 0;
-    for (int w = 0; w < nw; ++w) {
-        if (w < wid) wo += sh[w];
-        tot += sh[w];
-    }
-    __syncthreads();
-    *total = tot;
-    return wo + inc - x;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,86 @@
+// Persistent per-query kernel of the sgm library (internal): one workgroup
+// runs a whole query -- filtering, candidate edges, join, ordering -- out of
+// its own slot of device memory, then takes the next query from a queue.
+#pragma once
+
+#include <stdint.h>
+
+#include "sgm_internal.h"
+
+namespace sgm {
+
+constexpr int kNarrowThreads = 512;  // threads per workgroup (8 wave64)
+
+// One filter launch of the plan: explore (push = 1) or refine (push = 0) of
+// vertex u against nbr[first .. first+count).
+struct NStep {
+    int8_t u, push, parent;  // parent: vertex intersected with the push scratch, or -1
+    int8_t pad;
+    int16_t first, count;
+};
+
+struct NNbr {
+    int8_t v;     // the other query vertex
+    int8_t dir;   // 0: out-edges of the candidate, 1: in-edges
+    int8_t mode;  // 0: test v's bitmap; 1: test v's predicate
+    int8_t pad;
+    int32_t rel;  // -1: any
+};
+
+constexpr int kNMaxSteps = 2 * SGM_MAX_QV;
+constexpr int kNMaxNbr = 2 * SGM_MAX_QE + 2 * SGM_MAX_QV;
+
+// Packed query + plan, built on the host.
+struct NQuery {
+    int32_t n, m;
+    VPred pred[SGM_MAX_QV];
+    int32_t esrc[SGM_MAX_QE], edst[SGM_MAX_QE], elabel[SGM_MAX_QE];
+    int32_t root;           // first vertex of the visit order
+    int32_t root_slot;      // row of the root sweep output, -1 if the root is pinned
+    int32_t n_init, n_ref;  // explore steps, then refine steps (one round)
+    int32_t refine_rounds;  // -1: until nothing is removed
+    NStep steps[kNMaxSteps];
+    NNbr nbr[kNMaxNbr];
+};
+
+// Per-query outcome.
+struct NResult {
+    int32_t status;        // SGM_OK, or kNeedWide / kOutFull (rerun on the multi-kernel path)
+    int32_t n_cols;
+    int64_t n_rows;
+    int64_t offset;        // first int32 of the rows in the output arena
+    int64_t cand[SGM_MAX_QV];
+    int64_t ec[SGM_MAX_QE];
+    int64_t level_rows[SGM_MAX_QV];
+    int32_t join_order[SGM_MAX_QV];
+    int64_t bytes;         // algorithmic bytes the query's phases moved
+    int64_t ticks[4];      // device wall-clock ticks: filter, edges, join, ordering
+};
+
+constexpr int32_t kNeedWide = 1;  // a capacity of the per-query slot was exceeded
+constexpr int32_t kOutFull = 2;   // the shared output arena was full
+
+struct NArgs {
+    DevGraph g;
+    const NQuery *qs;
+    int32_t nq;
+    NResult *res;
+    int32_t *queue;           // [1] next query index
+    uint64_t *bits;           // [slots][(SGM_MAX_QV + 1) * nwords], zero between queries
+    int32_t *lists;           // [slots][SGM_MAX_QV * lcap]
+    int32_t lcap;
+    char *slab;               // [slots][slab_bytes]
+    int64_t slab_bytes;
+    const uint64_t *rootbits; // [n_root_slots][nwords] root sweep output
+    int32_t *out;             // output arena (int32 rows)
+    int64_t out_cap;          // in int32 elements
+    unsigned long long *out_used;
+};
+
+// root sweep: rootbits[j][w] for every query whose root is unpinned
+void launch_root_sweep(hipStream_t s, const DevGraph &g, const NQuery *qs, const int32_t *root_q,
+                       int32_t n_root, uint64_t *rootbits);
+void launch_narrow(hipStream_t s, const NArgs &a, int grid);
+size_t narrow_lds_bytes();
+
+}  // namespace sgm

@@ -1,0 +1,1023 @@
+// Persistent per-query kernel (gfx950): each workgroup takes queries from a
+// queue and runs the whole filtering-and-joining pipeline of one query
+// (thesis Alg. 3.1) with barrier-separated phases, in its own slot of device
+// memory, then leaves the slot's bitmaps zeroed for the next query.
+//
+// Phases (thesis Ch. 3):
+//   root candidates  -- kernel_check / kernel_collect of Alg. 3.2 (the sweep
+//                       itself runs once for a whole batch in k_root_sweep);
+//   explore          -- kernel_explore of Alg. 3.2 along the spanning tree;
+//   refine           -- Sec. "Candidate Nodes Refinement" (prune only);
+//   candidate edges  -- Sec. "Joining Phase", two-step output per key;
+//   join             -- edge order of Sec. "Joining Phase", one query vertex
+//                       per level, rows staged through LDS offsets;
+//   ordering         -- rows sorted by a packed key of candidate ranks.
+// Candidate lists are kept alongside the bitmaps (a push that sets a new bit
+// appends to the list), so no phase scans all V vertices. When a query
+// outgrows the slot (list, slab or LDS capacities), the workgroup clears its
+// slot and reports kNeedWide; the host then runs the multi-kernel path.
+#include <hip/hip_runtime.h>
+
+#include "sgm_device.h"
+#include "sgm_narrow.h"
+
+namespace sgm {
+namespace {
+
+constexpr int NT = kNarrowThreads;
+constexpr int NW = NT / 64;
+constexpr int kBigCap = 256;
+constexpr int kListSortCap = 8192;    // int32 entries sorted in LDS
+constexpr int kRowSortCap = 2048;     // final rows sorted in LDS (u64 key + int32 index)
+
+struct Smem {
+    int64_t sh[NW + 1];
+    int64_t slab_used;
+    int64_t ectot[SGM_MAX_QE];
+    int32_t *ec_cnt[SGM_MAX_QE];
+    int32_t *ec_offs[SGM_MAX_QE];
+    int32_t *ec_vals[SGM_MAX_QE];
+    int32_t cnt[SGM_MAX_QV];
+    int32_t eckey[SGM_MAX_QE];      // key vertex the join needs for each edge
+    int32_t ecbuilt[SGM_MAX_QE];    // key vertex of the table built first
+    int32_t jorder[SGM_MAX_QV], jpos[SGM_MAX_QV];
+    int32_t lv_ext[SGM_MAX_QV], lv_first[SGM_MAX_QV], lv_nchk[SGM_MAX_QV];
+    int32_t chk[SGM_MAX_QE];
+    int32_t big[kBigCap];
+    int32_t pairoff[NT];
+    int32_t rowlo[NT];
+    int32_t abort_;
+    int32_t q;
+    int32_t nbig;
+    int32_t removed;
+    int32_t ctr;
+    int32_t empty;
+    // per-query outcome, written to global memory by thread 0 at the end
+    int32_t status;
+    int32_t cand[SGM_MAX_QV];
+    int32_t bitsn[SGM_MAX_QV];
+    int64_t level_rows[SGM_MAX_QV];
+    int64_t nrows;
+    int64_t offset;
+    unsigned long long bytes;  // algorithmic bytes moved (see add_bytes)
+    int64_t t[5];              // wall clock at the phase boundaries
+};
+
+// dynamic LDS: sort space
+constexpr size_t kDynLds = sizeof(uint64_t) * kRowSortCap + sizeof(int32_t) * kRowSortCap >
+                                   sizeof(int32_t) * kListSortCap
+                               ? sizeof(uint64_t) * kRowSortCap + sizeof(int32_t) * kRowSortCap
+                               : sizeof(int32_t) * kListSortCap;
+
+struct Ctx {
+    DevGraph g;
+    int32_t lcap;
+    int64_t slab_bytes;
+    int32_t *out;
+    int64_t out_cap;
+    unsigned long long *out_used;
+    const uint64_t *rootbits;
+    const NQuery *Q;
+    Smem *s;
+    uint64_t *bits;     // slot bitmaps [(SGM_MAX_QV + 1) * nwords]
+    uint64_t *scratch;  // the extra bitmap of the slot
+    int32_t *lists;     // slot lists [SGM_MAX_QV * lcap]
+    char *slab;
+    unsigned char *dyn;
+    __device__ uint64_t *B(int u) const { return bits + (int64_t)u * g.nwords; }
+    __device__ int32_t *L(int u) const { return lists + (int64_t)u * lcap; }
+};
+
+__device__ __forceinline__ bool aborted(const Ctx &c) { return c.s->abort_ != 0; }
+
+// Algorithmic byte accounting: every phase adds the global-memory words its
+// algorithm must read or write (adjacency entries 8 B, neighbour tests 4 B,
+// list / table / edge-table ints 4 B, bitmap words 8 B), not what caches
+// happen to serve.
+__device__ __forceinline__ void add_bytes(Ctx &c, uint64_t b) {
+    if (b) atomicAdd(&c.s->bytes, (unsigned long long)b);
+}
+
+// wave-reduced variant: every lane of the wave must call it
+__device__ __forceinline__ void add_bytes_wave(Ctx &c, uint64_t b) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) b += __shfl_xor(b, o, 64);
+    if ((threadIdx.x & 63) == 0) add_bytes(c, b);
+}
+
+__device__ __forceinline__ void mark(Ctx &c, int i) {
+    if (threadIdx.x == 0) c.s->t[i] = wall_clock64();
+}
+
+// All threads call; returns the same pointer everywhere (nullptr + abort on
+// overflow).
+__device__ __forceinline__ char *slab_alloc(Ctx &c, int64_t bytes) {
+    __syncthreads();
+    const int64_t off = (c.s->slab_used + 255) & ~(int64_t)255;
+    char *p = (off + bytes <= c.slab_bytes) ? c.slab + off : nullptr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (p) c.s->slab_used = off + bytes;
+        else c.s->abort_ = 1;
+    }
+    __syncthreads();
+    return p;
+}
+
+// Set bit x; on a newly set bit append x to list (when list != nullptr).
+__device__ __forceinline__ void push_bit(Ctx &c, uint64_t *tb, int32_t *tl, int v, int32_t x) {
+    const uint64_t m = 1ull << (x & 63);
+    uint64_t *w = tb + (x >> 6);
+    if (__atomic_load_n(w, __ATOMIC_RELAXED) & m) return;
+    const uint64_t old = atomicOr((unsigned long long *)w, m);
+    if (tl && !(old & m)) {
+        const int32_t p = atomicAdd(&c.s->cnt[v], 1);
+        if (p < c.lcap) tl[p] = x;
+        else c.s->abort_ = 1;
+    }
+}
+
+__device__ __forceinline__ bool nbr_hit(const Ctx &c, const NNbr &d, int2 e) {
+    if (d.rel >= 0 && e.y != d.rel) return false;
+    return d.mode == 0 ? bit_test(c.B(d.v), e.x) : vpred(c.g, c.Q->pred[d.v], e.x);
+}
+
+// Keep only the list entries whose bit is still set, preserving order.
+__device__ __forceinline__ void compact_list(Ctx &c, int u) {
+    int32_t *l = c.L(u);
+    const uint64_t *b = c.B(u);
+    __syncthreads();
+    const int32_t n = c.s->cnt[u];
+    int64_t out = 0;
+    for (int32_t base = 0; base < n; base += NT) {
+        const int32_t i = base + threadIdx.x;
+        const int32_t x = i < n ? l[i] : 0;
+        const bool keep = i < n && bit_test(b, x);
+        int64_t tot;
+        const int64_t ex = block_excl_scan(keep ? 1 : 0, c.s->sh, &tot);
+        if (keep) l[out + ex] = x;
+        out += tot;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        c.s->cnt[u] = (int32_t)out;
+        add_bytes(c, 12ull * n + 4ull * out);
+    }
+    __syncthreads();
+}
+
+// Rebuild list u from its bitmap in ascending order (O(V/64) words).
+__device__ __forceinline__ void list_from_bits(Ctx &c, int u, const uint64_t *src, bool copy_bits) {
+    const int32_t nwords = c.g.nwords;
+    uint64_t *b = c.B(u);
+    int32_t *l = c.L(u);
+    int64_t out = 0;
+    for (int32_t base = 0; base < nwords; base += NT) {
+        const int32_t w = base + threadIdx.x;
+        uint64_t word = w < nwords ? src[w] : 0ull;
+        if (copy_bits && w < nwords) b[w] = word;
+        int64_t tot;
+        const int64_t ex = block_excl_scan(__popcll(word), c.s->sh, &tot);
+        if (out + tot > c.lcap) {
+            if (threadIdx.x == 0) c.s->abort_ = 1;
+            break;  // uniform: tot and out are block-uniform
+        }
+        int64_t p = out + ex;
+        while (word) {
+            l[p++] = w * 64 + __builtin_ctzll(word);
+            word &= word - 1ull;
+        }
+        out += tot;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && !c.s->abort_) {
+        c.s->cnt[u] = (int32_t)out;
+        add_bytes(c, (copy_bits ? 16ull : 8ull) * nwords + 4ull * out);
+    }
+    __syncthreads();
+}
+
+// Sort list u ascending (LDS bitonic, or a rebuild from the bitmap).
+__device__ __forceinline__ void sort_list(Ctx &c, int u) {
+    __syncthreads();
+    const int32_t n = c.s->cnt[u];
+    if (n <= 1) return;
+    int32_t N = 1, lg = 0;
+    while (N < n) {
+        N <<= 1;
+        ++lg;
+    }
+    // barrier rounds of a bitonic network vs. an ordered rebuild from the
+    // bitmap (two barriers per NT words)
+    const int64_t cost_bitonic = (int64_t)lg * (lg + 1) / 2 * ((N / 2 + NT - 1) / NT);
+    const int64_t cost_bits = 2 * ((c.g.nwords + NT - 1) / NT);
+    if (n > kListSortCap || cost_bits < cost_bitonic) {
+        list_from_bits(c, u, c.B(u), false);
+        return;
+    }
+    int32_t *l = c.L(u);
+    int32_t *t = (int32_t *)c.dyn;
+    for (int32_t i = threadIdx.x; i < N; i += NT) t[i] = i < n ? l[i] : INT32_MAX;
+    __syncthreads();
+    for (int32_t size = 2; size <= N; size <<= 1) {
+        for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int32_t i = threadIdx.x; i < N / 2; i += NT) {
+                const int32_t lo = 2 * i - (i & (stride - 1));
+                const int32_t hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const int32_t x = t[lo], y = t[hi];
+                if ((x > y) == up) {
+                    t[lo] = y;
+                    t[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int32_t i = threadIdx.x; i < n; i += NT) l[i] = t[i];
+    if (threadIdx.x == 0) add_bytes(c, 8ull * n);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// filtering: one explore / refine step (Alg. 3.2 kernel_explore; refinement)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void row_of(const DevGraph &g, int32_t up, int dir, int32_t *beg,
+                                       int32_t *end) {
+    const int32_t *off = dir ? g.in_off : g.out_off;
+    *beg = off[up];
+    *end = off[up + 1];
+}
+
+// Whole workgroup on one candidate (uniform call). Prune: the candidate
+// survives if every listed query edge has a matching neighbour; explore
+// then pushes every matching neighbour.
+__device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb, int ncount, int32_t up,
+                        uint64_t *ub, uint64_t &fb) {
+    const DevGraph &g = c.g;
+    bool alive = true;
+    uint64_t seen = 0;
+    for (int j = 0; j < ncount && alive; ++j) {
+        const NNbr d = nb[j];
+        const int2 *adj = d.dir ? g.in_adj : g.out_adj;
+        int32_t beg, end;
+        row_of(g, up, d.dir, &beg, &end);
+        bool found = false;
+        for (int32_t base = beg; base < end; base += 4 * NT) {
+            bool hit = false;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int32_t i = base + k * NT + threadIdx.x;
+                if (i < end) hit |= nbr_hit(c, d, adj[i]);
+            }
+            seen += min(4 * NT, end - base);
+            if (__syncthreads_or(hit)) {
+                found = true;
+                break;
+            }
+        }
+        alive = found;
+    }
+    if (!alive) {
+        if (threadIdx.x == 0) {
+            atomicAnd((unsigned long long *)&ub[up >> 6], ~(1ull << (up & 63)));
+            atomicAdd(&c.s->removed, 1);
+            fb += 20ull + 12ull * seen;
+        }
+        return;
+    }
+    if (st.push) {
+        for (int j = 0; j < ncount; ++j) {
+            const NNbr d = nb[j];
+            const int2 *adj = d.dir ? g.in_adj : g.out_adj;
+            int32_t beg, end;
+            row_of(g, up, d.dir, &beg, &end);
+            uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
+            int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
+            seen += end - beg;
+            for (int32_t base = beg; base < end; base += 4 * NT) {
+                // four independent loads in flight per thread
+                const int32_t i = base + threadIdx.x;
+                const int2 e0 = i < end ? adj[i] : make_int2(-1, -1);
+                const int2 e1 = i + NT < end ? adj[i + NT] : make_int2(-1, -1);
+                const int2 e2 = i + 2 * NT < end ? adj[i + 2 * NT] : make_int2(-1, -1);
+                const int2 e3 = i + 3 * NT < end ? adj[i + 3 * NT] : make_int2(-1, -1);
+                if (e0.x >= 0 && nbr_hit(c, d, e0)) push_bit(c, tb, tl, d.v, e0.x);
+                if (e1.x >= 0 && nbr_hit(c, d, e1)) push_bit(c, tb, tl, d.v, e1.x);
+                if (e2.x >= 0 && nbr_hit(c, d, e2)) push_bit(c, tb, tl, d.v, e2.x);
+                if (e3.x >= 0 && nbr_hit(c, d, e3)) push_bit(c, tb, tl, d.v, e3.x);
+            }
+        }
+    }
+    if (threadIdx.x == 0) fb += 20ull + 12ull * seen;
+}
+
+// lanes per candidate for n items: the whole workgroup for a handful,
+// otherwise a power of two in [1, 64] so that all lanes hold an item
+__device__ __forceinline__ int lanes_for(int32_t n) {
+    int G = 64;
+    while (G > 1 && (int64_t)G * n > NT) G >>= 1;
+    return G;
+}
+
+__device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
+    const DevGraph &g = c.g;
+    const NNbr *nb = c.Q->nbr + st.first;
+    const int ncount = st.count;
+    const int u = st.u;
+    uint64_t *ub = c.B(u);
+    int32_t *ul = c.L(u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        c.s->nbig = 0;
+        c.s->removed = 0;
+    }
+    __syncthreads();
+    const int32_t n_items = c.s->cnt[u];
+    uint64_t fb = 0;  // algorithmic bytes of this thread's work
+    if (n_items <= NW) {
+        for (int32_t it = 0; it < n_items; ++it) item_wg(c, st, nb, ncount, ul[it], ub, fb);
+    } else {
+        const int G = lanes_for(n_items);
+        const int NGr = NT / G;
+        const int lane = threadIdx.x & 63, gl = lane & (G - 1), gb = lane & ~(G - 1);
+        const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << gb;
+        const int32_t bigdeg = 64 * G;  // more than 64 strides: whole workgroup
+        for (int32_t it = threadIdx.x / G; it < n_items; it += NGr) {
+            const int32_t up = ul[it];
+            const int32_t ob = g.out_off[up], oe = g.out_off[up + 1];
+            const int32_t ib = g.in_off[up], ie = g.in_off[up + 1];
+            int32_t maxd = 0;
+            for (int j = 0; j < ncount; ++j) maxd = max(maxd, nb[j].dir ? ie - ib : oe - ob);
+            if (maxd > bigdeg) {
+                int32_t p = 0;
+                if (gl == 0) p = atomicAdd(&c.s->nbig, 1);
+                p = __shfl(p, gb, 64);
+                if (p < kBigCap) {
+                    if (gl == 0) c.s->big[p] = up;
+                    continue;
+                }
+                // LDS list full: this group handles the item itself
+            }
+            bool alive = true;
+            uint64_t seen = 0;
+            for (int j = 0; j < ncount && alive; ++j) {
+                const NNbr d = nb[j];
+                const int2 *adj = d.dir ? g.in_adj : g.out_adj;
+                const int32_t beg = d.dir ? ib : ob, end = d.dir ? ie : oe;
+                bool found = false;
+                for (int32_t base = beg; base < end; base += G) {
+                    const int32_t i = base + gl;
+                    const bool hit = i < end && nbr_hit(c, d, adj[i]);
+                    seen += min(G, end - base);
+                    if (__ballot(hit) & gmask) {
+                        found = true;
+                        break;
+                    }
+                }
+                alive = found;
+            }
+            if (!alive) {
+                if (gl == 0) {
+                    atomicAnd((unsigned long long *)&ub[up >> 6], ~(1ull << (up & 63)));
+                    atomicAdd(&c.s->removed, 1);
+                    fb += 20ull + 12ull * seen;
+                }
+                continue;
+            }
+            if (st.push)
+                for (int j = 0; j < ncount; ++j) {
+                    const NNbr d = nb[j];
+                    const int2 *adj = d.dir ? g.in_adj : g.out_adj;
+                    const int32_t beg = d.dir ? ib : ob, end = d.dir ? ie : oe;
+                    uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
+                    int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
+                    seen += end - beg;
+                    for (int32_t i = beg + gl; i < end; i += G) {
+                        const int2 e = adj[i];
+                        if (nbr_hit(c, d, e)) push_bit(c, tb, tl, d.v, e.x);
+                    }
+                }
+            if (gl == 0) fb += 20ull + 12ull * seen;
+        }
+        __syncthreads();
+        const int32_t nbig = min(c.s->nbig, kBigCap);
+        for (int32_t b = 0; b < nbig; ++b) item_wg(c, st, nb, ncount, c.s->big[b], ub, fb);
+    }
+    add_bytes_wave(c, fb);
+    __syncthreads();
+    if (c.s->removed) compact_list(c, u);
+    if (st.parent >= 0) {
+        // intersect the parent's candidates with the pushed scratch bitmap
+        const int p = st.parent;
+        uint64_t *pb = c.B(p);
+        const int32_t *pl = c.L(p);
+        const int32_t n = c.s->cnt[p];
+        for (int32_t i = threadIdx.x; i < n; i += NT) {
+            const int32_t x = pl[i];
+            if (!bit_test(c.scratch, x))
+                atomicAnd((unsigned long long *)&pb[x >> 6], ~(1ull << (x & 63)));
+        }
+        __syncthreads();
+        // scratch only holds parent candidates: zero their words
+        for (int32_t i = threadIdx.x; i < n; i += NT) c.scratch[pl[i] >> 6] = 0ull;
+        if (threadIdx.x == 0) add_bytes(c, 28ull * n);
+        __syncthreads();
+        compact_list(c, p);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// candidate edges (Sec. "Joining Phase"): for each key (a candidate of the
+// key vertex, sorted), the sorted candidates of the other endpoint joined to
+// it by a matching data edge. Space per key comes from the data degrees, so
+// one pass writes the table: vals[off[i] .. off[i] + num[i]).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool ec_hit(int32_t rel, const uint64_t *other, const int2 *adj,
+                                       int32_t beg, int32_t i, int32_t key) {
+    const int2 e = adj[i];
+    if (rel >= 0) {
+        if (e.y != rel) return false;
+    } else if (i > beg && adj[i - 1].x == e.x) {
+        return false;  // same neighbour under another relation: one pair
+    }
+    return e.x != key && bit_test(other, e.x);
+}
+
+// one key, whole workgroup, ordered compaction in chunks of 4*NT entries
+__device__ __forceinline__ int64_t ec_key_wg(Ctx &c, int32_t rel, const uint64_t *ob, const int2 *adj,
+                             int32_t beg, int32_t end, int32_t k, int32_t *dst) {
+    int64_t n = 0;
+    for (int32_t base = beg; base < end; base += 4 * NT) {
+        const int32_t i0 = base + 4 * threadIdx.x;
+        uint32_t h = 0;  // bit t: entry i0 + t matches
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (i0 + t < end && ec_hit(rel, ob, adj, beg, i0 + t, k)) h |= 1u << t;
+        int64_t tot;
+        int64_t p = n + block_excl_scan(__popc(h), c.s->sh, &tot);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if ((h >> t) & 1u) dst[p++] = adj[i0 + t].x;
+        n += tot;
+    }
+    return n;
+}
+
+// Build the table of query edge e keyed by `key` (dir 0: keys are sources).
+// Sets s.ec_offs/ec_cnt/ec_vals[e], s.eckey[e] and s.ectot[e].
+__device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int dir) {
+    const DevGraph &g = c.g;
+    const int32_t *keys = c.L(key);
+    const int32_t nk = c.s->cnt[key];
+    const uint64_t *ob = c.B(other);
+    const int32_t rel = c.Q->elabel[e];
+    const int32_t *off = dir ? g.in_off : g.out_off;
+    const int2 *adj = dir ? g.in_adj : g.out_adj;
+    int32_t *degoff = (int32_t *)slab_alloc(c, 4ll * nk + 4);
+    int32_t *num = (int32_t *)slab_alloc(c, 4ll * nk + 4);
+    if (!degoff || !num) return;
+    // exclusive scan of the keys' degrees: space per key
+    int64_t carry = 0;
+    for (int32_t base = 0; base < nk; base += NT) {
+        const int32_t i = base + threadIdx.x;
+        const int32_t d = i < nk ? off[keys[i] + 1] - off[keys[i]] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan(d, c.s->sh, &tot);
+        if (i < nk) degoff[i] = (int32_t)(carry + ex);
+        carry += tot;
+    }
+    int32_t *vals = (int32_t *)slab_alloc(c, 4 * carry + 4);
+    if (!vals) return;
+    if (threadIdx.x == 0) {
+        degoff[nk] = (int32_t)carry;
+        c.s->ec_offs[e] = degoff;
+        c.s->ec_cnt[e] = num;
+        c.s->ec_vals[e] = vals;
+        c.s->eckey[e] = key;
+        c.s->nbig = 0;
+    }
+    __syncthreads();
+    int64_t mytot = 0;
+    uint64_t fb = 0;
+    if (nk <= NW) {
+        for (int32_t it = 0; it < nk; ++it) {
+            const int32_t k = keys[it];
+            const int32_t beg = off[k], end = off[k + 1];
+            const int64_t n = ec_key_wg(c, rel, ob, adj, beg, end, k, vals + degoff[it]);
+            if (threadIdx.x == 0) {
+                num[it] = (int32_t)n;
+                mytot += n;
+                fb += 16ull + 12ull * (end - beg) + 4ull * n;
+            }
+        }
+    } else {
+        const int G = lanes_for(nk);
+        const int NGr = NT / G;
+        const int lane = threadIdx.x & 63, gl = lane & (G - 1), gb = lane & ~(G - 1);
+        const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << gb;
+        const int32_t bigdeg = 64 * G;
+        for (int32_t it = threadIdx.x / G; it < nk; it += NGr) {
+            const int32_t k = keys[it];
+            const int32_t beg = off[k], end = off[k + 1];
+            if (end - beg > bigdeg) {
+                int32_t p = 0;
+                if (gl == 0) p = atomicAdd(&c.s->nbig, 1);
+                p = __shfl(p, gb, 64);
+                if (p < kBigCap) {
+                    if (gl == 0) c.s->big[p] = it;
+                    continue;
+                }
+            }
+            int32_t *dst = vals + degoff[it];
+            int32_t n = 0;
+            for (int32_t base = beg; base < end; base += G) {
+                const int32_t i = base + gl;
+                const bool hit = i < end && ec_hit(rel, ob, adj, beg, i, k);
+                const uint64_t bm = __ballot(hit) & gmask;
+                if (hit) dst[n + __popcll(bm & lanemask_lt(lane))] = adj[i].x;
+                n += __popcll(bm);
+            }
+            if (gl == 0) {
+                num[it] = n;
+                mytot += n;
+                fb += 16ull + 12ull * (end - beg) + 4ull * n;
+            }
+        }
+        __syncthreads();
+        const int32_t nbig = min(c.s->nbig, kBigCap);
+        for (int32_t b = 0; b < nbig; ++b) {
+            const int32_t it = c.s->big[b];
+            const int32_t k = keys[it];
+            const int32_t beg = off[k], end = off[k + 1];
+            const int64_t n = ec_key_wg(c, rel, ob, adj, beg, end, k, vals + degoff[it]);
+            if (threadIdx.x == 0) {
+                num[it] = (int32_t)n;
+                mytot += n;
+                fb += 16ull + 12ull * (end - beg) + 4ull * n;
+            }
+        }
+    }
+    add_bytes_wave(c, fb);
+    int64_t tot;
+    block_excl_scan(mytot, c.s->sh, &tot);
+    if (threadIdx.x == 0) c.s->ectot[e] = tot;
+    __syncthreads();
+}
+
+// Join order of Sec. "Joining Phase" (one thread): start from the edge with
+// the fewest candidate edges; bind one new vertex per level through the
+// cheapest edge with exactly one bound endpoint; all other edges between the
+// new vertex and bound vertices are checks of that level.
+__device__ __forceinline__ void join_order(Ctx &c) {
+    if (threadIdx.x != 0) return;
+    const NQuery &Q = *c.Q;
+    Smem &s = *c.s;
+    uint32_t vis = 0;   // bound query vertices
+    uint64_t used = 0;  // consumed query edges
+    int e0 = 0;
+    for (int e = 1; e < Q.m; ++e)
+        if (s.ectot[e] < s.ectot[e0]) e0 = e;
+    int nj = 0, nc = 0;
+    s.jorder[nj++] = Q.esrc[e0];
+    vis |= 1u << Q.esrc[e0];
+    int ext = e0;
+    for (int lv = 0; lv < Q.n - 1; ++lv) {
+        if (lv > 0) {
+            ext = -1;
+            for (int e = 0; e < Q.m; ++e) {
+                if ((used >> e) & 1ull) continue;
+                const bool va = (vis >> Q.esrc[e]) & 1u, vb = (vis >> Q.edst[e]) & 1u;
+                if (va == vb) continue;
+                if (ext < 0 || s.ectot[e] < s.ectot[ext]) ext = e;
+            }
+        }
+        const int w = ((vis >> Q.esrc[ext]) & 1u) ? Q.edst[ext] : Q.esrc[ext];
+        used |= 1ull << ext;
+        s.lv_ext[lv] = ext;
+        s.lv_first[lv] = nc;
+        for (int e = 0; e < Q.m; ++e) {
+            if ((used >> e) & 1ull) continue;
+            const int x = Q.esrc[e], y = Q.edst[e];
+            if ((x == w && ((vis >> y) & 1u)) || (y == w && ((vis >> x) & 1u))) {
+                s.chk[nc++] = e;
+                used |= 1ull << e;
+            }
+        }
+        s.lv_nchk[lv] = nc - s.lv_first[lv];
+        vis |= 1u << w;
+        s.jorder[nj++] = w;
+    }
+    for (int j = 0; j < Q.n; ++j) s.jpos[s.jorder[j]] = j;
+    for (int e = 0; e < Q.m; ++e)
+        s.eckey[e] = s.jpos[Q.esrc[e]] < s.jpos[Q.edst[e]] ? Q.esrc[e] : Q.edst[e];
+}
+
+__device__ __forceinline__ bool ec_contains(const Ctx &c, int e, int32_t keyval, int32_t x) {
+    const int kv = c.s->eckey[e];
+    const int32_t *kl = c.L(kv);
+    const int32_t i = lower_bound_i32(kl, 0, c.s->cnt[kv], keyval);
+    if (i >= c.s->cnt[kv] || kl[i] != keyval) return false;
+    const int32_t lo = c.s->ec_offs[e][i], hi = lo + c.s->ec_cnt[e][i];
+    const int32_t j = lower_bound_i32(c.s->ec_vals[e], lo, hi, x);
+    return j < hi && c.s->ec_vals[e][j] == x;
+}
+
+// ---------------------------------------------------------------------------
+// one query
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void clear_slot(Ctx &c, bool full) {
+    __syncthreads();
+    const int n = c.Q->n;
+    const int32_t nwords = c.g.nwords;
+    if (full) {
+        for (int u = 0; u < n; ++u)
+            for (int32_t w = threadIdx.x; w < nwords; w += NT) c.B(u)[w] = 0ull;
+        for (int32_t w = threadIdx.x; w < nwords; w += NT) c.scratch[w] = 0ull;
+    } else {
+        for (int u = 0; u < n; ++u) {
+            const int32_t *l = c.L(u);
+            uint64_t *b = c.B(u);
+            const int32_t cn = c.s->cnt[u];
+            for (int32_t i = threadIdx.x; i < cn; i += NT) b[l[i] >> 6] = 0ull;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void run_query(Ctx &c) {
+    const NQuery &Q = *c.Q;
+    const DevGraph &g = c.g;
+    Smem &s = *c.s;
+    const int n = Q.n;
+    if (threadIdx.x < SGM_MAX_QV) {
+        s.cnt[threadIdx.x] = 0;
+        s.cand[threadIdx.x] = 0;
+        s.level_rows[threadIdx.x] = 0;
+        s.jorder[threadIdx.x] = -1;
+    }
+    if (threadIdx.x < SGM_MAX_QE) s.ectot[threadIdx.x] = 0;
+    if (threadIdx.x < 5) s.t[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        s.abort_ = 0;
+        s.slab_used = 0;
+        s.empty = 0;
+        s.status = SGM_OK;
+        s.nrows = 0;
+        s.offset = 0;
+        s.bytes = 0;
+    }
+    __syncthreads();
+    mark(c, 0);
+    // root candidates
+    const int root = Q.root;
+    if (Q.root_slot < 0) {
+        if (threadIdx.x == 0) {
+            const int32_t pin = Q.pred[root].pin;
+            if (pin >= 0 && pin < g.V && vpred(g, Q.pred[root], pin)) {
+                c.B(root)[pin >> 6] |= 1ull << (pin & 63);
+                c.L(root)[0] = pin;
+                s.cnt[root] = 1;
+            }
+        }
+        __syncthreads();
+    } else {
+        list_from_bits(c, root, c.rootbits + (int64_t)Q.root_slot * g.nwords, true);
+    }
+    // explore along the spanning tree, then refinement rounds
+    for (int i = 0; i < Q.n_init && !aborted(c); ++i) filter_step(c, Q.steps[i]);
+    const int rounds = Q.refine_rounds < 0 ? 32 : Q.refine_rounds;
+    for (int r = 0; r < rounds && !aborted(c) && Q.n_ref > 0; ++r) {
+        int removed = 0;
+        for (int i = 0; i < Q.n_ref && !aborted(c); ++i) {
+            filter_step(c, Q.steps[Q.n_init + i]);
+            removed += s.removed;  // read after the step's final barrier
+            __syncthreads();
+        }
+        if (Q.refine_rounds < 0 && removed == 0) break;
+    }
+    __syncthreads();
+    mark(c, 1);
+    if (aborted(c)) {
+        clear_slot(c, true);
+        if (threadIdx.x == 0) s.status = kNeedWide;
+        return;
+    }
+    if (threadIdx.x == 0)
+        for (int u = 0; u < n; ++u) {
+            s.cand[u] = s.cnt[u];
+            if (s.cnt[u] == 0) s.empty = 1;
+        }
+    __syncthreads();
+    int64_t rows = 0;
+    int32_t *table = nullptr;
+    if (!s.empty) {
+        for (int u = 0; u < n && !aborted(c); ++u) sort_list(c, u);
+        if (Q.m == 0) {
+            table = c.L(0);
+            rows = s.cnt[0];
+            if (threadIdx.x == 0) {
+                s.jorder[0] = 0;
+                s.jpos[0] = 0;
+            }
+            __syncthreads();
+        } else if (!aborted(c)) {
+            // candidate edges keyed by each edge's source: totals for the order
+            for (int e = 0; e < Q.m && !aborted(c); ++e) ec_build(c, e, Q.esrc[e], Q.edst[e], 0);
+            __syncthreads();
+            bool none = false;
+            for (int e = 0; e < Q.m; ++e) none |= s.ectot[e] == 0;
+            if (!aborted(c) && !none) {
+                if (threadIdx.x == 0)
+                    for (int e = 0; e < Q.m; ++e) s.ecbuilt[e] = s.eckey[e];
+                join_order(c);
+                __syncthreads();
+                // edges the join looks up by their destination: rebuild keyed so
+                for (int e = 0; e < Q.m && !aborted(c); ++e)
+                    if (s.eckey[e] != s.ecbuilt[e]) ec_build(c, e, Q.edst[e], Q.esrc[e], 1);
+                __syncthreads();
+                // join levels
+                mark(c, 2);
+                table = c.L(s.jorder[0]);
+                rows = s.cnt[s.jorder[0]];
+                if (threadIdx.x == 0) s.level_rows[0] = rows;
+                int k = 1;
+                for (int lv = 0; lv < n - 1 && !aborted(c) && rows > 0; ++lv) {
+                    const int ext = s.lv_ext[lv];
+                    const int p = s.eckey[ext];
+                    const int cp = s.jpos[p];
+                    const int32_t *pk = c.L(p);
+                    const int32_t npk = s.cnt[p];
+                    const int32_t *eoffs = s.ec_offs[ext];
+                    const int32_t *ecnt = s.ec_cnt[ext];
+                    const int32_t *evals = s.ec_vals[ext];
+                    const int nchk = s.lv_nchk[lv];
+                    const int cfirst = s.lv_first[lv];
+                    // output capacity: what is left of the slab
+                    __syncthreads();
+                    const int64_t left = c.slab_bytes - ((s.slab_used + 255) & ~(int64_t)255);
+                    const int64_t cap = left / (4 * (k + 1));
+                    int32_t *out = cap > 0 ? (int32_t *)slab_alloc(c, cap * 4 * (k + 1)) : nullptr;
+                    if (!out) {
+                        if (threadIdx.x == 0) s.abort_ = 1;
+                        __syncthreads();
+                        break;
+                    }
+                    if (threadIdx.x == 0) s.ctr = 0;
+                    __syncthreads();
+                    const int lane = threadIdx.x & 63;
+                    uint64_t jb = 0;  // algorithmic bytes of this thread's rows and pairs
+                    for (int64_t rbase = 0; rbase < rows; rbase += NT) {
+                        const int64_t r = rbase + threadIdx.x;
+                        int32_t fan = 0, lo = 0;
+                        if (r < rows) {
+                            const int32_t pv = table[r * k + cp];
+                            const int32_t i = lower_bound_i32(pk, 0, npk, pv);
+                            if (i < npk && pk[i] == pv) {
+                                lo = eoffs[i];
+                                fan = ecnt[i];
+                            }
+                        }
+                        if (r < rows) jb += 16ull + 4ull * (32 - __clz(npk | 1));
+                        int64_t tot;
+                        const int64_t ex = block_excl_scan(fan, s.sh, &tot);
+                        s.pairoff[threadIdx.x] = (int32_t)ex;
+                        s.rowlo[threadIdx.x] = lo;
+                        __syncthreads();
+                        for (int64_t pb = 0; pb < tot; pb += NT) {
+                            const int64_t pi = pb + threadIdx.x;
+                            bool ok = false;
+                            int32_t x = 0;
+                            int32_t rr = 0;
+                            if (pi < tot) {
+                                // last chunk row whose pair offset <= pi
+                                int32_t a0 = 0, a1 = NT;
+                                while (a1 - a0 > 1) {
+                                    const int32_t mid = (a0 + a1) >> 1;
+                                    if (s.pairoff[mid] <= pi) a0 = mid;
+                                    else a1 = mid;
+                                }
+                                rr = a0;
+                                x = evals[s.rowlo[rr] + (pi - s.pairoff[rr])];
+                                const int32_t *row = table + (rbase + rr) * k;
+                                ok = true;
+                                for (int cc = 0; cc < k; ++cc)
+                                    if (row[cc] == x) ok = false;
+                                for (int ci = 0; ci < nchk && ok; ++ci) {
+                                    const int e = s.chk[cfirst + ci];
+                                    const int kv = s.eckey[e];
+                                    ok = ec_contains(c, e, row[s.jpos[kv]], x);
+                                }
+                            }
+                            if (pi < tot) jb += 4ull + 4ull * k + 24ull * nchk + (ok ? 4ull * (k + 1) : 0ull);
+                            const uint64_t bm = __ballot(ok);
+                            int32_t base = 0;
+                            const int leader = bm ? __builtin_ctzll(bm) : 0;
+                            if (bm && lane == leader) base = atomicAdd(&s.ctr, __popcll(bm));
+                            base = __shfl(base, leader, 64);
+                            if (ok) {
+                                const int64_t pos = (int64_t)base + __popcll(bm & lanemask_lt(lane));
+                                if (pos < cap) {
+                                    int32_t *dst = out + pos * (k + 1);
+                                    const int32_t *row = table + (rbase + rr) * k;
+                                    for (int cc = 0; cc < k; ++cc) dst[cc] = row[cc];
+                                    dst[k] = x;
+                                } else {
+                                    s.abort_ = 1;
+                                }
+                            }
+                        }
+                        __syncthreads();
+                    }
+                    add_bytes(c, jb);
+                    __syncthreads();
+                    rows = s.ctr;
+                    if (threadIdx.x == 0) s.level_rows[lv + 1] = rows;
+                    // give back the unused part of the table allocation
+                    __syncthreads();
+                    if (threadIdx.x == 0 && !s.abort_)
+                        s.slab_used = (int64_t)((char *)out - c.slab) + rows * 4 * (k + 1);
+                    __syncthreads();
+                    table = out;
+                    ++k;
+                }
+            } else if (none) {
+                rows = 0;
+            }
+        }
+    }
+    __syncthreads();
+    mark(c, 3);
+    if (aborted(c)) {
+        clear_slot(c, true);
+        if (threadIdx.x == 0) s.status = kNeedWide;
+        return;
+    }
+    if (threadIdx.x == 0) s.nrows = rows;
+    if (rows > 0) {
+        // ordering: key = concatenated candidate ranks in column order 0..n-1
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tb = 0;
+            for (int u = 0; u < n; ++u) {
+                int b = 0;
+                while ((1ll << b) < s.cnt[u]) ++b;
+                s.bitsn[u] = b;
+                tb += b;
+            }
+            s.ctr = tb;
+        }
+        __syncthreads();
+        if (s.ctr > 64 || rows > kRowSortCap) {
+            clear_slot(c, false);
+            if (threadIdx.x == 0) s.status = kNeedWide;
+            return;
+        }
+        uint64_t *keys = (uint64_t *)c.dyn;
+        int32_t *idx = (int32_t *)(c.dyn + sizeof(uint64_t) * kRowSortCap);
+        const int k = n;
+        int32_t N = 1;
+        while (N < rows) N <<= 1;
+        for (int32_t r = threadIdx.x; r < N; r += NT) {
+            uint64_t key = ~0ull;
+            if (r < rows) {
+                key = 0;
+                const int32_t *row = table + (int64_t)r * k;
+                for (int u = 0; u < n; ++u) {
+                    const int32_t rk = lower_bound_i32(c.L(u), 0, s.cnt[u], row[s.jpos[u]]);
+                    key = (key << s.bitsn[u]) | (uint64_t)rk;
+                }
+            }
+            keys[r] = key;
+            idx[r] = r;
+        }
+        __syncthreads();
+        for (int32_t size = 2; size <= N; size <<= 1) {
+            for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int32_t i = threadIdx.x; i < N / 2; i += NT) {
+                    const int32_t lo = 2 * i - (i & (stride - 1));
+                    const int32_t hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const uint64_t x = keys[lo], y = keys[hi];
+                    if ((x > y) == up) {
+                        keys[lo] = y;
+                        keys[hi] = x;
+                        const int32_t t = idx[lo];
+                        idx[lo] = idx[hi];
+                        idx[hi] = t;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (threadIdx.x == 0) {
+            const unsigned long long need = (unsigned long long)rows * n;
+            const unsigned long long off = atomicAdd(c.out_used, need);
+            s.offset = (off + need <= (unsigned long long)c.out_cap) ? (int64_t)off : -1;
+        }
+        __syncthreads();
+        const int64_t off = s.offset;
+        if (off < 0) {
+            if (threadIdx.x == 0) s.status = kOutFull;
+        } else {
+            for (int64_t t = threadIdx.x; t < rows * n; t += NT) {
+                const int64_t i = t / n;
+                const int cc = (int)(t - i * n);
+                c.out[off + t] = table[(int64_t)idx[i] * k + s.jpos[cc]];
+            }
+            if (threadIdx.x == 0) add_bytes(c, 20ull * rows * n);
+        }
+    }
+    clear_slot(c, false);
+    mark(c, 4);
+}
+
+__global__ __launch_bounds__(NT) void k_narrow(NArgs a) {
+    __shared__ Smem s;
+    extern __shared__ unsigned char dyn[];
+    const int32_t nwords = a.g.nwords;
+    uint64_t *bits = a.bits + (int64_t)blockIdx.x * (SGM_MAX_QV + 1) * nwords;
+    int32_t *lists = a.lists + (int64_t)blockIdx.x * SGM_MAX_QV * a.lcap;
+    char *slab = a.slab + (int64_t)blockIdx.x * a.slab_bytes;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s.q = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int32_t q = s.q;
+        if (q >= a.nq) break;
+        const NQuery &Q = a.qs[q];
+        NResult &R = a.res[q];
+        Ctx c{a.g,  a.lcap, a.slab_bytes, a.out, a.out_cap, a.out_used, a.rootbits, &Q, &s,
+              bits, bits + (int64_t)SGM_MAX_QV * nwords, lists, slab, dyn};
+        run_query(c);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            R.status = s.status;
+            R.n_cols = Q.n;
+            R.n_rows = s.status == SGM_OK ? s.nrows : 0;
+            R.offset = s.offset;
+            for (int u = 0; u < SGM_MAX_QV; ++u) {
+                R.cand[u] = u < Q.n ? s.cand[u] : 0;
+                R.level_rows[u] = u < Q.n ? s.level_rows[u] : 0;
+                R.join_order[u] = u < Q.n ? s.jorder[u] : -1;
+            }
+            for (int e = 0; e < SGM_MAX_QE; ++e) R.ec[e] = e < Q.m ? s.ectot[e] : 0;
+            R.bytes = (int64_t)s.bytes;
+            // phases a query skipped carry the time of the previous mark
+            int64_t prev = s.t[0];
+            for (int i = 1; i < 5; ++i) {
+                const int64_t ti = s.t[i] ? s.t[i] : prev;
+                R.ticks[i - 1] = ti - prev;
+                prev = ti;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// root sweep for a batch: one wave per 64-vertex word, one ballot per
+// unpinned root
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const NQuery *qs,
+                                                    const int32_t *root_q, int32_t n_root,
+                                                    uint64_t *rootbits) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (int32_t w = wave; w < g.nwords; w += nwaves) {
+        const int32_t v = w * 64 + lane;
+        const bool inr = v < g.V;
+        const int32_t t = inr ? g.vtype[v] : -2;
+        const int32_t od = inr ? g.out_off[v + 1] - g.out_off[v] : -1;
+        const int32_t id = inr ? g.in_off[v + 1] - g.in_off[v] : -1;
+        for (int32_t j = 0; j < n_root; ++j) {
+            const NQuery &Q = qs[root_q[j]];
+            const VPred p = Q.pred[Q.root];
+            const bool ok = inr && (p.label < 0 || p.label == t) && od >= p.qout && id >= p.qin;
+            const uint64_t b = __ballot(ok);
+            if (lane == 0) rootbits[(int64_t)j * g.nwords + w] = b;
+        }
+    }
+}
+
+}  // namespace
+
+size_t narrow_lds_bytes() { return kDynLds; }
+
+void launch_narrow(hipStream_t s, const NArgs &a, int grid) {
+    hipLaunchKernelGGL(k_narrow, dim3(grid), dim3(NT), kDynLds, s, a);
+}
+
+void launch_root_sweep(hipStream_t s, const DevGraph &g, const NQuery *qs, const int32_t *root_q,
+                       int32_t n_root, uint64_t *rootbits) {
+    int grid = (g.nwords + 3) / 4;
+    if (grid > 4096) grid = 4096;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_root_sweep, dim3(grid), dim3(256), 0, s, g, qs, root_q, n_root, rootbits);
+}
+
+}  // namespace sgm

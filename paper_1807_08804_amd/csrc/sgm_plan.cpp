@@ -164,6 +164,59 @@ int make_plan(const QInfo &qi, int32_t V, const int64_t *type_freq, int32_t n_ty
     return SGM_OK;
 }
 
+void build_program(const QInfo &qi, const Plan &pl, int low_conn_degree, int refine_reversed,
+                   Program *pr) {
+    pr->init.clear();
+    pr->refine.clear();
+    pr->nbr.clear();
+    const int n = qi.n;
+    bool initialized[SGM_MAX_QV] = {};
+    for (int oi = 0; oi < pl.n_visit; ++oi) {
+        const int u = pl.visit[oi];
+        initialized[u] = true;
+        PStep s{u, (int)pr->nbr.size(), 0, 1, -1};
+        auto add = [&](int v, int e) {
+            PNbr d{};
+            d.v = v;
+            d.dir = qi.esrc[e] == u ? 0 : 1;
+            d.rel = qi.elabel[e];
+            d.mode = initialized[v] ? 0 : 1;
+            if (initialized[v]) s.parent = v;
+            pr->nbr.push_back(d);
+        };
+        if (pl.parent[u] >= 0) add(pl.parent[u], pl.parent_edge[u]);
+        for (int x = 0; x < n; ++x)
+            if (pl.parent[x] == u) add(x, pl.parent_edge[x]);
+        s.count = (int)pr->nbr.size() - s.first;
+        if (s.count) pr->init.push_back(s);
+        for (int x = 0; x < n; ++x)
+            if (pl.parent[x] == u) initialized[x] = true;
+    }
+    for (int i = 0; i < pl.n_init; ++i) {
+        const int u = pl.init[refine_reversed ? pl.n_init - 1 - i : i];
+        if (qi.deg[u] <= low_conn_degree) continue;
+        PStep s{u, (int)pr->nbr.size(), 0, 0, -1};
+        for (int e = 0; e < qi.m; ++e) {
+            PNbr d{};
+            if (qi.esrc[e] == u) {
+                d.v = qi.edst[e];
+                d.dir = 0;
+            } else if (qi.edst[e] == u) {
+                d.v = qi.esrc[e];
+                d.dir = 1;
+            } else {
+                continue;
+            }
+            if (qi.deg[d.v] <= low_conn_degree) continue;
+            d.rel = qi.elabel[e];
+            d.mode = 0;
+            pr->nbr.push_back(d);
+        }
+        s.count = (int)pr->nbr.size() - s.first;
+        if (s.count) pr->refine.push_back(s);
+    }
+}
+
 }  // namespace sgm
 
 extern "C" int sgm_plan_query(const sgm_query *q, int32_t n_vertices, const int64_t *type_freq,

@@ -3,6 +3,8 @@
 
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/sgm.h"
 
 namespace sgm {
@@ -28,6 +30,26 @@ struct Plan {
     int n_init;
     int32_t init[SGM_MAX_QV];         // order in which vertices enter T
 };
+
+// The filtering phase as a fixed sequence of steps. Explore steps follow the
+// visit order (Alg. 3.2): each tests and pushes along its spanning-tree
+// edges; the parent (already initialised) is tested against its bitmap and
+// intersected with what the step pushes (parent >= 0), the children are
+// tested against their candidate predicate and receive the pushes. Refine
+// steps (one round) prune a vertex against all query edges to vertices above
+// the low-connectivity threshold.
+struct PStep {
+    int u, first, count, push, parent;
+};
+struct PNbr {
+    int v, dir, rel, mode;  // dir 0: out-edges of the candidate; mode 0: bitmap test
+};
+struct Program {
+    std::vector<PStep> init, refine;
+    std::vector<PNbr> nbr;
+};
+void build_program(const QInfo &qi, const Plan &pl, int low_conn_degree, int refine_reversed,
+                   Program *pr);
 
 // SGM_OK, SGM_EINVAL or SGM_EUNSUPPORTED (see sgm_match_query).
 int check_query(const sgm_query *q, int32_t V, QInfo *qi);

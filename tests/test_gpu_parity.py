@@ -51,33 +51,78 @@ def test_graph_info(tiny_kg, g_tiny):
     assert info["max_out"] == int(np.diff(tiny_kg.row_ptr).max())
 
 
-@pytest.mark.parametrize("seed", range(24))
-def test_micro_random(seed):
+PATHS = [P.SGM_PATH_AUTO, P.SGM_PATH_WIDE, P.SGM_PATH_NARROW]
+
+
+def match_or_unsupported(g, q):
+    """Rows, or None when the narrow-only path reports the query too big."""
+    try:
+        return g.match_query(q)
+    except P.SGMError as e:
+        if e.code == P.SGM_EUNSUPPORTED:
+            return None
+        raise
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("seed", range(16))
+def test_micro_random(seed, path):
     """Micro graphs with repeated triples, self-loops and multi-relation
     pairs; queries with any-type vertices, variable edges, pins, 2-cycles."""
     rng = np.random.default_rng(500 + seed)
     V = int(rng.integers(2, 40))
     mg = random_graph(rng, V, int(rng.integers(1, 4 * V)), n_types=3, n_rels=3)
     rp, col, rel, typ = mg.csr()
-    say(f"case: micro seed={seed} V={V} E={len(col)}")
-    g = P.Graph(rp, col, rel, typ)
+    say(f"case: micro seed={seed} path={path} V={V} E={len(col)}")
+    g = P.Graph(rp, col, rel, typ, path=path)
     og = oracle.Graph(V, mg.src, mg.dst, mg.rel, mg.vtype)
-    for i in range(10):
-        q = random_query(rng, int(rng.integers(1, 6)), 3, 3, V, p_pin=0.15, extra=3)
-        same(g.match_query(q), og.match_query(q))
+    qs = [random_query(rng, int(rng.integers(1, 6)), 3, 3, V, p_pin=0.15, extra=3)
+          for _ in range(10)]
+    for q in qs:
+        got = match_or_unsupported(g, q)
+        if got is not None or path != P.SGM_PATH_NARROW:
+            same(got, og.match_query(q))
+    # the same queries as one batch
+    for q, b in zip(qs, g.match_batch(qs)):
+        if isinstance(b, P.SGMError):
+            assert path == P.SGM_PATH_NARROW and b.code == P.SGM_EUNSUPPORTED
+        else:
+            same(b, og.match_query(q))
     g.close()
 
 
-def test_medium_config(medium_kg, g_medium, oracle_medium, medium_queries):
-    """100 random-walk queries of 6-10 vertices (paths and trees, <= 2 pins)."""
+@pytest.fixture(scope="module")
+def medium_expected(oracle_medium, medium_queries):
+    return [oracle_medium.match_query(q) for q in medium_queries]
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_medium_config(path, medium_kg, medium_queries, medium_expected):
+    """100 random-walk queries of 6-10 vertices (paths and trees, <= 2 pins),
+    one at a time, on each execution path."""
+    g = P.Graph.from_kg(medium_kg, path=path)
     tot = 0
-    for i, q in enumerate(medium_queries):
-        say(f"case: medium query {i} n={q.n} m={q.m} pins={(q.vpin >= 0).sum()}")
-        got = g_medium.match_query(q)
-        same(got, oracle_medium.match_query(q))
+    narrow_done = 0
+    for i, (q, want) in enumerate(zip(medium_queries, medium_expected)):
+        say(f"case: medium query {i} path={path} n={q.n} m={q.m} pins={(q.vpin >= 0).sum()}")
+        got = match_or_unsupported(g, q)
+        if got is None:
+            assert path == P.SGM_PATH_NARROW
+            continue
+        narrow_done += 1
+        same(got, want)
         assert tuple(q.walk) in set(map(tuple, got.tolist()))
         tot += len(got)
     assert tot > 0
+    assert narrow_done >= 90
+    g.close()
+
+
+def test_medium_batch(medium_kg, g_medium, medium_queries, medium_expected):
+    """The 100 queries as one sgm_match_batch call (one persistent launch)."""
+    say("case: medium batch")
+    for q, got, want in zip(medium_queries, g_medium.match_batch(medium_queries), medium_expected):
+        same(got, want)
 
 
 def any_query(n, edges, vlabel=None, vpin=None):
