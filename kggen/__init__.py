@@ -73,6 +73,19 @@ class KG:
         """(src, dst, rel) int32 triples, the form the oracle takes."""
         return self.src(), self.col, self.rel
 
+    def type_members(self, t: int) -> np.ndarray:
+        """Vertices of type t (ascending), from a cached index."""
+        if getattr(self, "_tidx", None) is None:
+            order = np.argsort(self.vtype, kind="stable").astype(np.int64)
+            cnt = np.bincount(self.vtype, minlength=int(self.vtype.max()) + 1)
+            off = np.zeros(len(cnt) + 1, np.int64)
+            np.cumsum(cnt, out=off[1:])
+            self._tidx = (order, off)
+        order, off = self._tidx
+        if t < 0 or t + 1 >= len(off):
+            return order[:0]
+        return order[off[t]:off[t + 1]]
+
     def ensure_in(self):
         if self.in_ptr is None:
             src = self.src()
@@ -361,7 +374,7 @@ def draw_query(g: KG, rng, n: int, shape: str, n_pins: int, n_cycles: int = 0) -
 
 
 def draw_cyclic_dense(g: KG, rng, n: int, n_cycles: int, n_pins: int = 0,
-                      max_tries: int = 100_000) -> Query:
+                      max_tries: int = 2_000) -> Query:
     """A connected query of n vertices with n-1+n_cycles edges. Grows greedily
     towards vertices with the most data edges into the chosen set so that the
     cycles exist; cycles are sparse in these random graphs otherwise."""
@@ -445,7 +458,7 @@ def tree_hom_bound(g: KG, q: Query) -> float:
             ok = q.vlabel[u] < 0 or g.vtype[p] == q.vlabel[u]
             return np.asarray([p] if ok else [], np.int64), np.ones(1 if ok else 0)
         if q.vlabel[u] >= 0:
-            s = np.nonzero(g.vtype == q.vlabel[u])[0]
+            s = g.type_members(int(q.vlabel[u]))
         else:
             s = np.arange(g.V, dtype=np.int64)
         return s.astype(np.int64), np.ones(len(s))
@@ -480,11 +493,18 @@ def tree_hom_bound(g: KG, q: Query) -> float:
             if len(tgt) == 0:
                 sup, val = sup[:0], val[:0]
                 break
-            ut, inv = np.unique(tgt, return_inverse=True)
-            sv = np.bincount(inv, weights=w)
-            # intersect with current support
-            common, ia, ib = np.intersect1d(sup, ut, assume_unique=True, return_indices=True)
-            sup, val = common, val[ia] * sv[ib]
+            if len(tgt) * 8 > g.V:
+                dense = np.bincount(tgt, weights=w, minlength=g.V)
+                val = val * dense[sup]
+            else:
+                ut, inv = np.unique(tgt, return_inverse=True)
+                sv = np.bincount(inv, weights=w)
+                pos = np.searchsorted(ut, sup)
+                pos[pos >= len(ut)] = 0
+                hitm = ut[pos] == sup
+                val = np.where(hitm, val * sv[pos], 0.0)
+            keep = val > 0
+            sup, val = sup[keep], val[keep]
         h[u] = (sup, val)
     return float(h[0][1].sum()) if len(h[0][1]) else 0.0
 
@@ -512,6 +532,87 @@ def medium_queries(g: KG, count: int = 100, seed: int = BASE_SEED + 1 + 100,
         pins = int(rng.integers(0, 3))
         q = draw_query(g, rng, n, shape, pins)
         if tree_hom_bound(g, q) <= hmax:
+            out.append(q)
+        else:
+            rejected += 1
+    return out, rejected
+
+
+def batch_queries(g: KG, count: int = 1024, seed: int = BASE_SEED + 3 + 100,
+                  hmax: float = 1e6):
+    """Mixed batch on the large graph: sizes uniform in 3..16, shapes in equal
+    shares (path, star, tree, cyclic with 1-3 extra edges), pinned fraction per
+    query uniform in [0, 0.5]; accepted when H(q) <= hmax."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shapes = ("path", "star", "tree", "cyclic")
+    out, rejected = [], 0
+    while len(out) < count:
+        shape = shapes[len(out) % 4]
+        n = int(rng.integers(3, 17))
+        pins = int(round(rng.random() * 0.5 * n))
+        try:
+            if shape == "cyclic":
+                cyc = min(int(rng.integers(1, 4)), max(1, n - 2))
+                q = draw_cyclic_dense(g, rng, n, cyc, n_pins=pins)
+            else:
+                q = draw_query(g, rng, n, shape, pins)
+        except RuntimeError:
+            rejected += 1
+            continue
+        if tree_hom_bound(g, q) <= hmax:
+            out.append(q)
+        else:
+            rejected += 1
+    return out, rejected
+
+
+def serve_queries(g: KG, count: int, seed: int = BASE_SEED + 4 + 100, hmax: float = 1e6):
+    """Served stream: 3..12-vertex walk queries (a tree plus 0 or 1 extra
+    edge), 0..2 pinned vertices; accepted when H(q) <= hmax."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out, rejected = [], 0
+    while len(out) < count:
+        n = int(rng.integers(3, 13))
+        pins = min(n, int(rng.integers(0, 3)))
+        try:
+            if rng.random() < 0.5:
+                q = draw_cyclic_dense(g, rng, n, 1, n_pins=pins)
+            else:
+                q = draw_query(g, rng, n, "tree", pins)
+        except RuntimeError:
+            rejected += 1
+            continue
+        if tree_hom_bound(g, q) <= hmax:
+            out.append(q)
+        else:
+            rejected += 1
+    return out, rejected
+
+
+def poisson_arrivals(count: int, qps: float, seed: int = BASE_SEED + 4 + 200) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson stream of rate qps."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / qps, size=count))
+
+
+def large_queries(g: KG, count: int = 50, seed: int = BASE_SEED + 2 + 100,
+                  hmin: float = 1e7, hmax: float = 2e9, p_any: float = 0.5):
+    """Large-graph queries: 8..16 vertices with 1..3 cycles and no pins; each
+    vertex label and edge label is dropped to "any" with probability p_any so
+    that intermediate tables grow; accepted when hmin <= H(q) <= hmax."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out, rejected = [], 0
+    while len(out) < count:
+        n = int(rng.integers(8, 17))
+        try:
+            q = draw_cyclic_dense(g, rng, n, int(rng.integers(1, 4)))
+        except RuntimeError:
+            rejected += 1
+            continue
+        q.vlabel = np.where(rng.random(q.n) < p_any, -1, q.vlabel).astype(np.int32)
+        q.elabel = np.where(rng.random(q.m) < p_any, -1, q.elabel).astype(np.int32)
+        h = tree_hom_bound(g, q)
+        if hmin <= h <= hmax:
             out.append(q)
         else:
             rejected += 1

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sgm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-OR_OK, OR_EINVAL, OR_ENOMEM, OR_ETOOBIG = 0, -1, -2, -4
+OR_OK, OR_EINVAL, OR_ENOMEM, OR_ETOOBIG, OR_EBUDGET = 0, -1, -2, -4, -6
 
 
 def build(force: bool = False) -> str:
@@ -51,6 +51,11 @@ def _load():
         lib.oracle_match.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, i32p, i32p,
                                      i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int,
                                      ctypes.POINTER(i32p), ctypes.POINTER(ctypes.c_int64)]
+        lib.oracle_match_budget.restype = ctypes.c_int
+        lib.oracle_match_budget.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, i32p,
+                                            i32p, i32p, i32p, i32p, ctypes.c_int64,
+                                            ctypes.c_int64, ctypes.c_int,
+                                            ctypes.POINTER(i32p), ctypes.POINTER(ctypes.c_int64)]
         lib.oracle_free.argtypes = [ctypes.c_void_p]
         _lib = lib
     return _lib
@@ -91,9 +96,10 @@ class Graph:
             self._h = None
 
     def match(self, n, vlabel, vpin, esrc, edst, elabel, max_rows: int = -1,
-              nthreads: int = 0, count_only: bool = False):
+              nthreads: int = 0, count_only: bool = False, max_steps: int = -1):
         """All matches as an [rows, n] int32 array in ascending lexicographic
-        order (or the count if ``count_only``)."""
+        order (or the count if ``count_only``). ``max_steps`` bounds the
+        candidate tests (OracleError with code OR_EBUDGET beyond it)."""
         lib = _load()
         (vl, vlp), (vp, vpp) = _i32(vlabel), _i32(vpin)
         (es, esp), (ed, edp), (el, elp) = _i32(esrc), _i32(edst), _i32(elabel)
@@ -101,9 +107,10 @@ class Graph:
             raise ValueError("query array lengths")
         rows = ctypes.POINTER(ctypes.c_int32)()
         nrows = ctypes.c_int64(0)
-        rc = lib.oracle_match(self._h, int(n), int(len(es)), vlp, vpp, esp, edp, elp,
-                              int(max_rows), int(nthreads),
-                              None if count_only else ctypes.byref(rows), ctypes.byref(nrows))
+        rc = lib.oracle_match_budget(self._h, int(n), int(len(es)), vlp, vpp, esp, edp, elp,
+                                     int(max_rows), int(max_steps), int(nthreads),
+                                     None if count_only else ctypes.byref(rows),
+                                     ctypes.byref(nrows))
         if rc != OR_OK:
             raise OracleError(rc, nrows.value)
         if count_only:

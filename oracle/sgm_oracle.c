@@ -41,6 +41,7 @@
 #define OR_EINVAL -1
 #define OR_ENOMEM -2
 #define OR_ETOOBIG -4
+#define OR_EBUDGET -6
 #define OR_MAXQ 32
 
 typedef struct {
@@ -215,8 +216,24 @@ typedef struct {
     int count_only;
     int64_t max_rows;
     int64_t *total;   /* shared running count */
-    int *abort_flag;
+    int *abort_flag;  /* 1: row cap exceeded, 2: work budget exceeded */
+    int64_t max_steps; /* candidate tests allowed in total (-1: no limit) */
+    int64_t *steps;    /* shared running count of candidate tests */
+    int64_t local_steps;
 } or_ctx;
+
+/* Count one candidate test; past the budget, stop the whole search. */
+static int over_budget(or_ctx *c) {
+    if (c->max_steps < 0) return 0;
+    if (++c->local_steps < 4096) return 0;
+    int64_t t = __atomic_add_fetch(c->steps, c->local_steps, __ATOMIC_RELAXED);
+    c->local_steps = 0;
+    if (t > c->max_steps) {
+        __atomic_store_n(c->abort_flag, 2, __ATOMIC_RELAXED);
+        return 1;
+    }
+    return 0;
+}
 
 static void dfs(or_ctx *c, int32_t *f, int depth) {
     const or_query *q = c->q;
@@ -275,6 +292,7 @@ static void dfs(or_ctx *c, int32_t *f, int depth) {
         int32_t x = best_arr[k].dst;
         if (x == prev) continue; /* same neighbour, other relation */
         prev = x;
+        if (over_budget(c)) return;
         if (consistent(g, q, f, depth, u, x)) {
             f[u] = x;
             dfs(c, f, depth + 1);
@@ -330,10 +348,25 @@ static int query_ok(int32_t V, int32_t n, int32_t m, const int32_t *vpin, const 
  * nthreads: OpenMP threads (<= 0: runtime default).
  * Returns OR_OK, OR_EINVAL (malformed query), OR_ENOMEM or OR_ETOOBIG.
  */
+int oracle_match_budget(const oracle_graph *g, int32_t n, int32_t m, const int32_t *vlabel,
+                        const int32_t *vpin, const int32_t *esrc, const int32_t *edst,
+                        const int32_t *elabel, int64_t max_rows, int64_t max_steps,
+                        int nthreads, int32_t **rows_out, int64_t *nrows_out);
+
 int oracle_match(const oracle_graph *g, int32_t n, int32_t m, const int32_t *vlabel,
                  const int32_t *vpin, const int32_t *esrc, const int32_t *edst,
                  const int32_t *elabel, int64_t max_rows, int nthreads, int32_t **rows_out,
                  int64_t *nrows_out) {
+    return oracle_match_budget(g, n, m, vlabel, vpin, esrc, edst, elabel, max_rows, -1, nthreads,
+                               rows_out, nrows_out);
+}
+
+/* As oracle_match; also stops with OR_EBUDGET after max_steps candidate
+ * tests (max_steps < 0: no limit). */
+int oracle_match_budget(const oracle_graph *g, int32_t n, int32_t m, const int32_t *vlabel,
+                        const int32_t *vpin, const int32_t *esrc, const int32_t *edst,
+                        const int32_t *elabel, int64_t max_rows, int64_t max_steps,
+                        int nthreads, int32_t **rows_out, int64_t *nrows_out) {
     if (!g || !nrows_out) return OR_EINVAL;
     *nrows_out = 0;
     if (rows_out) *rows_out = NULL;
@@ -407,6 +440,7 @@ int oracle_match(const oracle_graph *g, int32_t n, int32_t m, const int32_t *vla
     }
     int64_t total = 0;
     int abort_flag = 0;
+    int64_t steps = 0;
 #pragma omp parallel num_threads(nt)
     {
         int tid = omp_get_thread_num();
@@ -418,10 +452,14 @@ int oracle_match(const oracle_graph *g, int32_t n, int32_t m, const int32_t *vla
         c.max_rows = max_rows;
         c.total = &total;
         c.abort_flag = &abort_flag;
+        c.max_steps = max_steps;
+        c.steps = &steps;
+        c.local_steps = 0;
         int32_t f[OR_MAXQ];
 #pragma omp for schedule(dynamic, 1)
         for (int64_t i = 0; i < n_roots; i++) {
             if (__atomic_load_n(&abort_flag, __ATOMIC_RELAXED)) continue;
+            if (over_budget(&c)) continue;
             int32_t x = roots[i];
             if (!consistent(g, &q, f, 0, root, x)) continue;
             f[root] = x;
@@ -440,7 +478,7 @@ int oracle_match(const oracle_graph *g, int32_t n, int32_t m, const int32_t *vla
         for (int t = 0; t < nt; t++) free(bufs[t].rows);
         free(bufs);
         *nrows_out = total;
-        return OR_ETOOBIG;
+        return abort_flag == 2 ? OR_EBUDGET : OR_ETOOBIG;
     }
     *nrows_out = total;
     if (rows_out) {

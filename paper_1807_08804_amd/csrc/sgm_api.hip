@@ -641,54 +641,82 @@ struct Query {
         return j;
     }
 
-    // Joining phase, part 2: extend the table one query vertex at a time.
-    int join(int32_t **table_out, int64_t *rows_out) {
-        const int seed = jorder[0];
-        const int32_t *table = list(seed);
-        int64_t R = ccount[seed];
-        int32_t *owned = nullptr;
-        res->stats.level_rows[0] = R;
-        int k = 1;
-        for (size_t li = 0; li < ext_.size(); ++li) {
-            const Level &L = ext_[li];
-            if (L.n_chk > SGM_MAX_QV) return SGM_EUNSUPPORTED;
-            JoinArgs a{};
-            a.table = table;
-            a.R = R;
-            a.k = k;
-            a.ext = jedge(L.ext);
-            a.n_chk = L.n_chk;
-            for (int c = 0; c < L.n_chk; ++c) a.chk[c] = jedge(L.chk[c]);
-            int64_t *fan = sc.get<int64_t>(R);
-            int64_t *poff = sc.get<int64_t>(R + 1);
-            int64_t *tmp = sc.get<int64_t>(scan_tmp_words(R) + 1);
-            {
-                Prof p(g, SGM_K_JOIN, R * (4.0 * k + 24.0));
-                launch_join_fan(st(), a, fan);
-            }
-            {
-                Prof p(g, SGM_K_OTHER, 16.0 * R);
-                launch_scan_i64(st(), fan, R, poff, tmp);
-            }
-            HIPX(hipMemcpyAsync(g->h_small, poff + R, sizeof(int64_t), hipMemcpyDeviceToHost, st()));
-            sync(g);
-            const int64_t P = g->h_small[0];
-            sc.release(fan);
-            sc.release(tmp);
-            if (P == 0) {
-                R = 0;
-                res->stats.level_rows[li + 1] = 0;
-                break;
-            }
-            a.pair_off = poff;
-            a.P = P;
-            const int64_t tiles = join_tiles(P);
+    // Joining phase, part 2: extend the table one query vertex per level.
+    // Pair ranges whose output would exceed the join budget are processed as
+    // chunks, depth-first through the remaining levels; final rows are
+    // appended to fin_ in order, so chunking does not change the row order.
+    int32_t *fin_ = nullptr;
+    int64_t fin_rows_ = 0, fin_cap_ = 0;
+    int64_t level_acc_[SGM_MAX_QV] = {};
+    int64_t budget_ = 0;
+
+    void append_final(const int32_t *t, int64_t R, int k) {
+        if (R == 0) return;
+        if (flags & SGM_COUNT_ONLY) {
+            fin_rows_ += R;
+            return;
+        }
+        if (fin_rows_ + R > fin_cap_) {
+            int64_t cap = std::max<int64_t>(2 * fin_cap_, fin_rows_ + R);
+            int32_t *nf = sc.get<int32_t>(cap * k);
+            if (fin_rows_)
+                HIPX(hipMemcpyAsync(nf, fin_, sizeof(int32_t) * fin_rows_ * k,
+                                    hipMemcpyDeviceToDevice, st()));
+            if (fin_) sc.release(fin_);
+            fin_ = nf;
+            fin_cap_ = cap;
+        }
+        HIPX(hipMemcpyAsync(fin_ + fin_rows_ * k, t, sizeof(int32_t) * R * k,
+                            hipMemcpyDeviceToDevice, st()));
+        fin_rows_ += R;
+    }
+
+    int join_from(size_t li, const int32_t *table, int64_t R, int k) {
+        if (li == ext_.size()) {
+            append_final(table, R, k);
+            return SGM_OK;
+        }
+        const Level &L = ext_[li];
+        if (L.n_chk > SGM_MAX_QV) return SGM_EUNSUPPORTED;
+        JoinArgs a{};
+        a.table = table;
+        a.R = R;
+        a.k = k;
+        a.ext = jedge(L.ext);
+        a.n_chk = L.n_chk;
+        for (int c = 0; c < L.n_chk; ++c) a.chk[c] = jedge(L.chk[c]);
+        int64_t *fan = sc.get<int64_t>(R);
+        int64_t *poff = sc.get<int64_t>(R + 1);
+        int64_t *tmp = sc.get<int64_t>(scan_tmp_words(R) + 1);
+        {
+            Prof p(g, SGM_K_JOIN, R * 28.0);
+            launch_join_fan(st(), a, fan);
+        }
+        {
+            Prof p(g, SGM_K_OTHER, 16.0 * R);
+            launch_scan_i64(st(), fan, R, poff, tmp);
+        }
+        HIPX(hipMemcpyAsync(g->h_small, poff + R, sizeof(int64_t), hipMemcpyDeviceToHost, st()));
+        sync(g);
+        const int64_t P = g->h_small[0];
+        sc.release(fan);
+        sc.release(tmp);
+        a.pair_off = poff;
+        const bool last = li + 1 == ext_.size();
+        // pairs bound the output: chunk the pair range to the budget
+        const int64_t chunk = std::max<int64_t>(1, budget_ / (4 * (k + 1)));
+        for (int64_t p0 = 0; p0 < P; p0 += chunk) {
+            const int64_t p1 = std::min(P, p0 + chunk);
+            if (p0 > 0 || p1 < P) res->stats.n_chunks++;
+            a.p0 = p0;
+            a.P = p1;
+            const int64_t tiles = join_tiles(p1 - p0);
             int64_t *bcnt = sc.get<int64_t>(tiles);
             int64_t *boff = sc.get<int64_t>(tiles + 1);
             int64_t *tmp2 = sc.get<int64_t>(scan_tmp_words(tiles) + 1);
             a.block_cnt = bcnt;
             {
-                Prof p(g, SGM_K_JOIN, P * (4.0 * k + 16.0));
+                Prof p(g, SGM_K_JOIN, (p1 - p0) * (4.0 * k + 16.0 + 24.0 * L.n_chk));
                 launch_join_count(st(), a);
             }
             {
@@ -699,39 +727,52 @@ struct Query {
                                 st()));
             sync(g);
             const int64_t R2 = g->h_small[0];
-            res->stats.level_rows[li + 1] = R2;
-            const bool last = li + 1 == ext_.size();
-            if (last && g->opts.result_cap_rows > 0 && R2 > g->opts.result_cap_rows) {
-                *rows_out = R2;
-                *table_out = nullptr;
-                return SGM_ETOOBIG;
-            }
+            level_acc_[li + 1] += R2;
+            sc.release(bcnt);
+            sc.release(tmp2);
             if (R2 == 0 || (last && (flags & SGM_COUNT_ONLY))) {
-                R = R2;
-                table = nullptr;
-                break;
+                if (last) fin_rows_ += R2;
+                sc.release(boff);
+                continue;
             }
             int32_t *out = sc.get<int32_t>(R2 * (k + 1));
             a.out = out;
             a.block_cnt = boff;
             a.out_base = 0;
             {
-                Prof p(g, SGM_K_JOIN, P * (4.0 * k + 16.0) + R2 * 4.0 * (k + 1));
+                Prof p(g, SGM_K_JOIN, (p1 - p0) * (4.0 * k + 16.0 + 24.0 * L.n_chk) +
+                                          R2 * 4.0 * (k + 1));
                 launch_join_write(st(), a);
             }
+            sc.release(boff);
             res->stats.peak_rows = std::max(res->stats.peak_rows, R2);
             res->stats.peak_bytes = std::max<int64_t>(res->stats.peak_bytes, R2 * 4 * (k + 1));
-            sc.release(poff);
-            sc.release(bcnt);
-            sc.release(tmp2);
-            if (owned) sc.release(owned);
-            owned = out;
-            table = out;
-            R = R2;
-            ++k;
+            if (last && !fin_ && p0 == 0 && p1 == P) {
+                // one chunk at the last level: the level's table is the result
+                fin_ = out;
+                fin_rows_ = R2;
+                fin_cap_ = R2;
+                continue;
+            }
+            const int rc = join_from(li + 1, out, R2, k + 1);
+            sc.release(out);
+            if (rc) return rc;
         }
-        *rows_out = R;
-        *table_out = const_cast<int32_t *>(table);
+        sc.release(poff);
+        return SGM_OK;
+    }
+
+    int join(int32_t **table_out, int64_t *rows_out) {
+        const int seed = jorder[0];
+        budget_ = g->opts.join_budget_bytes > 0 ? g->opts.join_budget_bytes : (16ll << 30);
+        level_acc_[0] = ccount[seed];
+        const int rc = join_from(0, list(seed), ccount[seed], 1);
+        for (int l = 0; l < qi.n; ++l) res->stats.level_rows[l] = level_acc_[l];
+        if (rc) return rc;
+        *rows_out = fin_rows_;
+        *table_out = fin_;
+        if (g->opts.result_cap_rows > 0 && fin_rows_ > g->opts.result_cap_rows)
+            return SGM_ETOOBIG;
         return SGM_OK;
     }
 

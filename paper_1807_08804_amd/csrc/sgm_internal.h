@@ -105,7 +105,8 @@ struct JoinArgs {
     int32_t n_chk;
     JoinEdge chk[SGM_MAX_QV];
     const int64_t *pair_off;  // [R+1] exclusive scan of per-row fan-out
-    int64_t P;                // total pairs
+    int64_t p0;               // first pair of this launch (chunking)
+    int64_t P;                // one past the last pair of this launch
     int32_t *out;             // [..][k+1] (write pass)
     int64_t *block_cnt;       // per-tile valid counts (count pass) / offsets (write pass)
     int64_t out_base;         // first output row (chunking)

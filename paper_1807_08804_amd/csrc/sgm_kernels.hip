@@ -462,7 +462,7 @@ __device__ __forceinline__ bool join_pair(const JoinArgs &a, int64_t t, int32_t 
 __global__ __launch_bounds__(kBlock) void k_join_count(JoinArgs a) {
     __shared__ int32_t sh[kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kJoinTile;
+    const int64_t base = a.p0 + (int64_t)blockIdx.x * kJoinTile;
     int32_t cnt = 0;
     for (int k = 0; k < kJoinItems; ++k) {
         const int64_t t = base + (int64_t)k * kBlock + threadIdx.x;
@@ -484,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_join_count(JoinArgs a) {
 __global__ __launch_bounds__(kBlock) void k_join_write(JoinArgs a) {
     __shared__ int32_t sh[kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kJoinTile;
+    const int64_t base = a.p0 + (int64_t)blockIdx.x * kJoinTile;
     int64_t pos = a.out_base + a.block_cnt[blockIdx.x];
     const int k1 = a.k + 1;
     for (int k = 0; k < kJoinItems; ++k) {
@@ -730,12 +730,12 @@ void launch_join_fan(hipStream_t s, const JoinArgs &a, int64_t *fan) {
 int64_t join_tiles(int64_t P) { return (P + kJoinTile - 1) / kJoinTile; }
 
 void launch_join_count(hipStream_t s, const JoinArgs &a) {
-    const int64_t nb = join_tiles(a.P);
+    const int64_t nb = join_tiles(a.P - a.p0);
     if (nb) hipLaunchKernelGGL(k_join_count, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
 }
 
 void launch_join_write(hipStream_t s, const JoinArgs &a) {
-    const int64_t nb = join_tiles(a.P);
+    const int64_t nb = join_tiles(a.P - a.p0);
     if (nb) hipLaunchKernelGGL(k_join_write, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
 }
 
