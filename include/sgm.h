@@ -221,6 +221,61 @@ int sgm_plan_query(const sgm_query *q, int32_t n_vertices, const int64_t *type_f
                    int32_t n_types, int32_t *visit_order, int32_t *parent,
                    int32_t *parent_edge, int32_t *init_order);
 
+/* ------------------------------------------------------------------------
+ * Served form: a request loop that keeps the graph resident, admits arriving
+ * queries against an intermediate-memory cap, batches them as they come and
+ * runs several batches on the device at once (continuous batching over
+ * streams). Results are identical to sgm_match_query's.
+ * ------------------------------------------------------------------------ */
+typedef struct sgm_server sgm_server;
+
+typedef struct {
+    int32_t streams;              /* batches on the device at once (default 4) */
+    int32_t max_batch;            /* queries per batch (default 256) */
+    int64_t max_wait_ns;          /* a batch closes this long after its first
+                                     query arrived (default 100 us) */
+    int64_t admission_cap_bytes;  /* estimated intermediate bytes of admitted,
+                                     unfinished queries (default 64 GiB); one
+                                     query is always admitted when none runs */
+    int32_t reserved[8];
+} sgm_serve_options;
+
+typedef struct {
+    int64_t submitted, completed, batches;
+    int64_t admission_stalls;     /* batches held back by the memory cap */
+    int64_t max_in_flight;        /* most queries admitted at once */
+    int64_t wide_fallbacks;       /* queries rerun on the multi-kernel path */
+} sgm_serve_stats;
+
+void sgm_default_serve_options(sgm_serve_options *o);
+
+/* Start a server on g (g must outlive it). Errors: SGM_EINVAL, SGM_ENOMEM,
+ * SGM_EDEVICE. The server owns its streams and two host threads. */
+int sgm_server_create(sgm_graph *g, const sgm_serve_options *opts, sgm_server **out);
+
+/* Queue one query (copied; the caller may free it on return); *ticket
+ * identifies it for sgm_wait. Invalid queries are accepted and complete
+ * with their error status. Thread-safe. */
+int sgm_submit(sgm_server *s, const sgm_query *q, uint32_t flags, uint64_t *ticket);
+
+/* Wait for a ticket (timeout_ns < 0: forever). SGM_OK: *out receives the
+ * library-owned result (its status may be an error code of that query;
+ * stats.ns_total = completion - submission). SGM_ETOOBIG is not returned
+ * here: it appears in (*out)->status. SGM_EINVAL: unknown ticket;
+ * SGM_EDEVICE on timeout (then the ticket stays valid). */
+int sgm_wait(sgm_server *s, uint64_t ticket, int64_t timeout_ns, sgm_result **out);
+
+int sgm_server_stats(sgm_server *s, sgm_serve_stats *out);
+
+/* Stop accepting, finish everything queued, join the threads, free. */
+void sgm_server_destroy(sgm_server *s);
+
+/* Load generator: submit qs[i] at arrival_ns[i] after the call starts
+ * (non-decreasing), wait for all, and write latency_ns[i] = completion time -
+ * scheduled arrival. out (NULL allowed) receives the results. */
+int sgm_serve_replay(sgm_server *s, const sgm_query *qs, const int64_t *arrival_ns, int32_t n,
+                     uint32_t flags, int64_t *latency_ns, sgm_result **out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,6 +64,18 @@ class sgm_result(ctypes.Structure):
                 ("n_rows", ctypes.c_int64), ("rows", _i32p), ("stats", sgm_stats)]
 
 
+class sgm_serve_options(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("max_wait_ns", ctypes.c_int64), ("admission_cap_bytes", ctypes.c_int64),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+class sgm_serve_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("admission_stalls", ctypes.c_int64),
+                ("max_in_flight", ctypes.c_int64), ("wide_fallbacks", ctypes.c_int64)]
+
+
 class sgm_kstat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("bytes_total", ctypes.c_double)]
@@ -86,6 +98,18 @@ EXPORTS = {
     "sgm_reset_kernel_stats": (ctypes.c_int, [ctypes.c_void_p]),
     "sgm_plan_query": (ctypes.c_int, [ctypes.POINTER(sgm_query), ctypes.c_int32, _i64p,
                                       ctypes.c_int32, _i32p, _i32p, _i32p, _i32p]),
+    "sgm_default_serve_options": (None, [ctypes.POINTER(sgm_serve_options)]),
+    "sgm_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_serve_options),
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "sgm_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query), ctypes.c_uint32,
+                                  ctypes.POINTER(ctypes.c_uint64)]),
+    "sgm_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64,
+                                ctypes.POINTER(ctypes.POINTER(sgm_result))]),
+    "sgm_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_serve_stats)]),
+    "sgm_server_destroy": (None, [ctypes.c_void_p]),
+    "sgm_serve_replay": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query), _i64p,
+                                        ctypes.c_int32, ctypes.c_uint32, _i64p,
+                                        ctypes.POINTER(ctypes.POINTER(sgm_result))]),
 }
 
 _lib = None
@@ -300,3 +324,89 @@ class Graph:
 
     def reset_kernel_stats(self):
         lib().sgm_reset_kernel_stats(self._h)
+
+
+class Server:
+    """The served form on a resident Graph (continuous batching over
+    streams; see sgm_server_create)."""
+
+    def __init__(self, graph: Graph, **options):
+        o = sgm_serve_options()
+        lib().sgm_default_serve_options(ctypes.byref(o))
+        for k, v in options.items():
+            setattr(o, k, v)
+        self.graph = graph
+        h = ctypes.c_void_p()
+        rc = lib().sgm_server_create(graph._h, ctypes.byref(o), ctypes.byref(h))
+        if rc != SGM_OK:
+            raise SGMError(rc, "sgm_server_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sgm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, q, count_only=False) -> int:
+        sq, keep = _make_query(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel)
+        t = ctypes.c_uint64()
+        rc = lib().sgm_submit(self._h, ctypes.byref(sq), SGM_COUNT_ONLY if count_only else 0,
+                              ctypes.byref(t))
+        if rc != SGM_OK:
+            raise SGMError(rc, "sgm_submit")
+        return t.value
+
+    def wait(self, ticket: int, n_cols: int, timeout_ns: int = -1):
+        """(status, rows or None, stats dict) of a ticket."""
+        out = ctypes.POINTER(sgm_result)()
+        rc = lib().sgm_wait(self._h, ticket, timeout_ns, ctypes.byref(out))
+        if rc != SGM_OK:
+            raise SGMError(rc, "sgm_wait")
+        try:
+            st = out.contents.status
+            k, rows = _result_to_numpy(out, n_cols)
+            stats = stats_dict(out.contents.stats, n_cols, 0)
+        finally:
+            sgm_free_result(out)
+        return st, (rows if st == SGM_OK else None), stats
+
+    def stats(self) -> dict:
+        s = sgm_serve_stats()
+        lib().sgm_server_stats(self._h, ctypes.byref(s))
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def replay(self, queries, arrival_s, count_only=False, keep_results=True):
+        """Submit queries at their arrival times (seconds, from now), wait
+        for all; returns (latencies in ns, results list or None)."""
+        n = len(queries)
+        built = [_make_query(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel) for q in queries]
+        arr = (sgm_query * max(n, 1))(*[b[0] for b in built])
+        at = np.ascontiguousarray(np.round(np.asarray(arrival_s) * 1e9).astype(np.int64))
+        lat = np.zeros(n, np.int64)
+        outs = (ctypes.POINTER(sgm_result) * max(n, 1))() if keep_results else None
+        rc = lib().sgm_serve_replay(self._h, arr, at.ctypes.data_as(_i64p), n,
+                                    SGM_COUNT_ONLY if count_only else 0,
+                                    lat.ctypes.data_as(_i64p), outs)
+        res = None
+        if keep_results:
+            res = []
+            for q, r in zip(queries, outs):
+                if not r:
+                    res.append(None)
+                    continue
+                st = r.contents.status
+                if st == SGM_OK:
+                    k, rows = _result_to_numpy(r, q.n)
+                    res.append(k if count_only else rows)
+                else:
+                    res.append(SGMError(st, "served query"))
+                sgm_free_result(r)
+        if rc != SGM_OK:
+            raise SGMError(rc, "sgm_serve_replay")
+        return lat, res

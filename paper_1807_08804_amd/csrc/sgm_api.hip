@@ -5,7 +5,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -143,6 +147,30 @@ struct DevCounters {
     unsigned long long ec_total[SGM_MAX_QE];
 };
 
+// Resources of the persistent per-query kernel on one stream: slots,
+// descriptors, root sweep rows and the output arena.
+struct NarrowCtx {
+    hipStream_t stream = nullptr;
+    int slots = 0;
+    int32_t lcap = 0;
+    int64_t slab_bytes = 0;
+    uint64_t *bits = nullptr;
+    int32_t *lists = nullptr;
+    char *slab = nullptr;
+    int qcap = 0;
+    NQuery *d_q = nullptr, *h_q = nullptr;
+    NResult *d_res = nullptr, *h_res = nullptr;
+    int32_t *d_root_q = nullptr, *h_root_q = nullptr;
+    int root_cap = 0;
+    uint64_t *d_rootbits = nullptr;
+    int32_t *d_out = nullptr;
+    int64_t out_cap = 0;
+    unsigned long long *d_ctr = nullptr, *h_ctr = nullptr;  // [0] queue, [1] out used
+    int32_t *h_out = nullptr;
+    int64_t h_out_cap = 0;
+    hipEvent_t done = nullptr;
+};
+
 }  // namespace
 
 struct sgm_graph {
@@ -186,27 +214,9 @@ struct sgm_graph {
     };
     std::vector<Pending> pending;
     sgm_kstat kstat[SGM_K_COUNT]{};
-    int launches = 0;
-    // persistent per-query kernel: slots, descriptors, output arena
-    struct Narrow {
-        int slots = 0;
-        int32_t lcap = 0;
-        int64_t slab_bytes = 0;
-        uint64_t *bits = nullptr;
-        int32_t *lists = nullptr;
-        char *slab = nullptr;
-        int qcap = 0;
-        NQuery *d_q = nullptr, *h_q = nullptr;
-        NResult *d_res = nullptr, *h_res = nullptr;
-        int32_t *d_root_q = nullptr, *h_root_q = nullptr;
-        int root_cap = 0;
-        uint64_t *d_rootbits = nullptr;
-        int32_t *d_out = nullptr;
-        int64_t out_cap = 0;
-        unsigned long long *d_ctr = nullptr, *h_ctr = nullptr;  // [0] queue, [1] out used
-        int32_t *h_out = nullptr;
-        int64_t h_out_cap = 0;
-    } nw;
+    std::atomic<int> launches{0};
+    // persistent per-query kernel on the graph's own stream
+    NarrowCtx nw;
 };
 
 namespace {
@@ -220,9 +230,10 @@ struct Prof {
     int kid;
     double bytes;
     hipEvent_t a = nullptr, b = nullptr;
-    Prof(sgm_graph *g_, int kid_, double bytes_) : g(g_), kid(kid_), bytes(bytes_) {
+    Prof(sgm_graph *g_, int kid_, double bytes_, bool on_graph_stream = true)
+        : g(g_), kid(kid_), bytes(bytes_) {
         g->launches++;
-        if (!g->opts.profile) return;
+        if (!g->opts.profile || !on_graph_stream) return;
         a = take();
         b = take();
         HIPX(hipEventRecord(a, g->stream));
@@ -323,6 +334,8 @@ T *dev_upload(const std::vector<T> &h) {
     return p;
 }
 
+void narrow_free(NarrowCtx &nw);
+
 void free_graph_mem(sgm_graph *g) {
     (void)hipSetDevice(g->device);
     if (g->stream) (void)hipStreamSynchronize(g->stream);
@@ -338,14 +351,7 @@ void free_graph_mem(sgm_graph *g) {
     void *hp[] = {g->h_desc, g->h_cnt, g->h_slots, g->h_small, g->h_rows};
     for (void *p : hp)
         if (p) (void)hipHostFree(p);
-    auto &nw = g->nw;
-    void *ndp[] = {nw.bits, nw.lists, nw.slab, nw.d_q, nw.d_res, nw.d_root_q, nw.d_rootbits,
-                   nw.d_out, nw.d_ctr};
-    for (void *p : ndp)
-        if (p) (void)hipFree(p);
-    void *nhp[] = {nw.h_q, nw.h_res, nw.h_root_q, nw.h_ctr, nw.h_out};
-    for (void *p : nhp)
-        if (p) (void)hipHostFree(p);
+    narrow_free(g->nw);
     if (g->stream) (void)hipStreamDestroy(g->stream);
 }
 
@@ -933,8 +939,28 @@ void host_free(T *&p) {
     p = nullptr;
 }
 
-void narrow_reserve(sgm_graph *g, int slots, int nq, int nroot) {
-    auto &nw = g->nw;
+void narrow_free(NarrowCtx &nw) {
+    if (nw.stream) (void)hipStreamSynchronize(nw.stream);
+    dev_free(nw.bits);
+    dev_free(nw.lists);
+    dev_free(nw.slab);
+    dev_free(nw.d_q);
+    dev_free(nw.d_res);
+    dev_free(nw.d_root_q);
+    dev_free(nw.d_rootbits);
+    dev_free(nw.d_out);
+    dev_free(nw.d_ctr);
+    host_free(nw.h_q);
+    host_free(nw.h_res);
+    host_free(nw.h_root_q);
+    host_free(nw.h_ctr);
+    host_free(nw.h_out);
+    if (nw.done) (void)hipEventDestroy(nw.done);
+    nw.done = nullptr;
+    nw = NarrowCtx{nw.stream};
+}
+
+void narrow_reserve(sgm_graph *g, NarrowCtx &nw, int slots, int nq, int nroot) {
     if (nw.lcap == 0) {
         nw.lcap = std::min<int32_t>(g->V, kNarrowListCap);
         nw.slab_bytes = kNarrowSlabBytes;
@@ -942,22 +968,23 @@ void narrow_reserve(sgm_graph *g, int slots, int nq, int nroot) {
         HIPX(hipHostMalloc(&nw.h_ctr, sizeof(unsigned long long) * 2, hipHostMallocDefault));
         nw.out_cap = kNarrowOutCap;
         HIPX(hipMalloc(&nw.d_out, sizeof(int32_t) * nw.out_cap));
+        HIPX(hipEventCreateWithFlags(&nw.done, hipEventDisableTiming));
     }
     if (slots > nw.slots) {
-        HIPX(hipStreamSynchronize(g->stream));
+        HIPX(hipStreamSynchronize(nw.stream));
         dev_free(nw.bits);
         dev_free(nw.lists);
         dev_free(nw.slab);
         nw.slots = 0;
         const size_t bw = (size_t)(SGM_MAX_QV + 1) * g->nwords;
         HIPX(hipMalloc(&nw.bits, sizeof(uint64_t) * bw * slots));
-        HIPX(hipMemsetAsync(nw.bits, 0, sizeof(uint64_t) * bw * slots, g->stream));
+        HIPX(hipMemsetAsync(nw.bits, 0, sizeof(uint64_t) * bw * slots, nw.stream));
         HIPX(hipMalloc(&nw.lists, sizeof(int32_t) * (size_t)SGM_MAX_QV * nw.lcap * slots));
         HIPX(hipMalloc(&nw.slab, (size_t)nw.slab_bytes * slots));
         nw.slots = slots;
     }
     if (nq > nw.qcap) {
-        HIPX(hipStreamSynchronize(g->stream));
+        HIPX(hipStreamSynchronize(nw.stream));
         dev_free(nw.d_q);
         dev_free(nw.d_res);
         host_free(nw.h_q);
@@ -970,7 +997,7 @@ void narrow_reserve(sgm_graph *g, int slots, int nq, int nroot) {
         nw.qcap = nq;
     }
     if (nroot > nw.root_cap) {
-        HIPX(hipStreamSynchronize(g->stream));
+        HIPX(hipStreamSynchronize(nw.stream));
         dev_free(nw.d_root_q);
         dev_free(nw.d_rootbits);
         host_free(nw.h_root_q);
@@ -980,6 +1007,14 @@ void narrow_reserve(sgm_graph *g, int slots, int nq, int nroot) {
         HIPX(hipMalloc(&nw.d_rootbits, sizeof(uint64_t) * (size_t)g->nwords * nroot));
         nw.root_cap = nroot;
     }
+}
+
+// Device memory one persistent-kernel slot holds while a query runs in it:
+// the unit of the served form's admission control.
+int64_t narrow_slot_bytes(const sgm_graph *g) {
+    const int64_t lcap = std::min<int32_t>(g->V, kNarrowListCap);
+    return (int64_t)(SGM_MAX_QV + 1) * g->nwords * 8 + (int64_t)SGM_MAX_QV * lcap * 4 +
+           kNarrowSlabBytes;
 }
 
 // Pack one validated query and its plan; false if it exceeds the packed
@@ -1025,138 +1060,161 @@ bool pack_query(sgm_graph *g, const QInfo &qi, NQuery *nq, int *root_slot_next, 
     return true;
 }
 
-// Run queries `which` (already validated into qis) through the persistent
-// kernel. Finished queries get their result in res[i]; the others are
-// appended to `wide` (slot capacity exceeded) for the multi-kernel path.
-void narrow_batch(sgm_graph *g, const std::vector<QInfo> &qis, const std::vector<int> &which,
-                  uint32_t flags, std::vector<sgm_result *> &res, std::vector<int> &wide) {
-    const int64_t t0 = now_ns();
-    std::vector<int> packed;
+// One persistent-kernel launch in flight on a context's stream.
+struct NarrowJob {
+    std::vector<int> packed;   // query indices, in descriptor order
     std::vector<Plan> plans;
-    packed.reserve(which.size());
-    for (size_t base = 0; base < which.size(); base += kNarrowQueryCap) {
-        const size_t end = std::min(which.size(), base + kNarrowQueryCap);
-        const int nq = (int)(end - base);
-        narrow_reserve(g, std::min(nq, kNarrowMaxSlots), nq, 0);
-        auto &nw = g->nw;
-        packed.clear();
-        plans.clear();
-        int nroot = 0;
-        for (size_t i = base; i < end; ++i) {
-            Plan pl;
-            NQuery *dst = &nw.h_q[packed.size()];
-            int rs = nroot;
-            if (pack_query(g, qis[which[i]], dst, &rs, &pl)) {
-                nroot = rs;
-                packed.push_back(which[i]);
-                plans.push_back(pl);
-            } else {
-                wide.push_back(which[i]);
-            }
+    int nroot = 0;
+    int64_t t0 = 0;
+};
+
+// Pack queries which[0..count) (validated into qis), upload and launch them
+// asynchronously on nw.stream; queries that do not fit a descriptor go to
+// `wide`. Returns false when nothing was launched.
+bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, const int *which,
+                   int count, NarrowJob &job, std::vector<int> &wide, bool profiled) {
+    job.t0 = now_ns();
+    job.packed.clear();
+    job.plans.clear();
+    narrow_reserve(g, nw, std::min(count, kNarrowMaxSlots), count, 0);
+    int nroot = 0;
+    for (int i = 0; i < count; ++i) {
+        Plan pl;
+        NQuery *dst = &nw.h_q[job.packed.size()];
+        int rs = nroot;
+        if (pack_query(g, qis[which[i]], dst, &rs, &pl)) {
+            nroot = rs;
+            job.packed.push_back(which[i]);
+            job.plans.push_back(pl);
+        } else {
+            wide.push_back(which[i]);
         }
-        const int np = (int)packed.size();
-        if (np == 0) continue;
-        narrow_reserve(g, std::min(np, kNarrowMaxSlots), np, nroot);
-        int k = 0;
-        for (int i = 0; i < np; ++i)
-            if (nw.h_q[i].root_slot >= 0) nw.h_root_q[k++] = i;
-        hipStream_t st = g->stream;
-        HIPX(hipMemcpyAsync(nw.d_q, nw.h_q, sizeof(NQuery) * np, hipMemcpyHostToDevice, st));
-        if (nroot)
-            HIPX(hipMemcpyAsync(nw.d_root_q, nw.h_root_q, sizeof(int32_t) * nroot,
-                                hipMemcpyHostToDevice, st));
-        HIPX(hipMemsetAsync(nw.d_ctr, 0, sizeof(unsigned long long) * 2, st));
-        if (nroot) {
-            Prof p(g, SGM_K_CHECK, (12.0 + 0.125 * nroot) * g->V);
-            launch_root_sweep(st, g->dg, nw.d_q, nw.d_root_q, nroot, nw.d_rootbits);
+    }
+    job.nroot = nroot;
+    const int np = (int)job.packed.size();
+    if (np == 0) return false;
+    narrow_reserve(g, nw, std::min(np, kNarrowMaxSlots), np, nroot);
+    int k = 0;
+    for (int i = 0; i < np; ++i)
+        if (nw.h_q[i].root_slot >= 0) nw.h_root_q[k++] = i;
+    hipStream_t st = nw.stream;
+    HIPX(hipMemcpyAsync(nw.d_q, nw.h_q, sizeof(NQuery) * np, hipMemcpyHostToDevice, st));
+    if (nroot)
+        HIPX(hipMemcpyAsync(nw.d_root_q, nw.h_root_q, sizeof(int32_t) * nroot,
+                            hipMemcpyHostToDevice, st));
+    HIPX(hipMemsetAsync(nw.d_ctr, 0, sizeof(unsigned long long) * 2, st));
+    if (nroot) {
+        Prof p(g, SGM_K_CHECK, (12.0 + 0.125 * nroot) * g->V, profiled);
+        launch_root_sweep(st, g->dg, nw.d_q, nw.d_root_q, nroot, nw.d_rootbits);
+    }
+    NArgs a{};
+    a.g = g->dg;
+    a.qs = nw.d_q;
+    a.nq = np;
+    a.res = nw.d_res;
+    a.queue = (int32_t *)nw.d_ctr;
+    a.bits = nw.bits;
+    a.lists = nw.lists;
+    a.lcap = nw.lcap;
+    a.slab = nw.slab;
+    a.slab_bytes = nw.slab_bytes;
+    a.rootbits = nw.d_rootbits;
+    a.out = nw.d_out;
+    a.out_cap = nw.out_cap;
+    a.out_used = nw.d_ctr + 1;
+    {
+        Prof p(g, SGM_K_PERSIST, 0.0, profiled);
+        launch_narrow(st, a, std::min(np, nw.slots));
+    }
+    HIPX(hipMemcpyAsync(nw.h_res, nw.d_res, sizeof(NResult) * np, hipMemcpyDeviceToHost, st));
+    HIPX(hipMemcpyAsync(nw.h_ctr, nw.d_ctr, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost,
+                        st));
+    HIPX(hipEventRecord(nw.done, st));
+    return true;
+}
+
+// Wait for a launched job and fill the results of its finished queries;
+// queries that outgrew their slot are appended to `wide`.
+void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vector<QInfo> &qis,
+                    uint32_t flags, std::vector<sgm_result *> &res, std::vector<int> &wide,
+                    bool profiled) {
+    hipStream_t st = nw.stream;
+    HIPX(hipEventSynchronize(nw.done));
+    if (profiled) prof_flush(g);
+    const int np = (int)job.packed.size();
+    if (profiled && g->opts.profile) {
+        double b = 0;
+        for (int i = 0; i < np; ++i) b += (double)nw.h_res[i].bytes;
+        g->kstat[SGM_K_PERSIST].bytes_total += b;
+    }
+    const int64_t used = std::min<int64_t>((int64_t)nw.h_ctr[1], nw.out_cap);
+    if (!(flags & SGM_COUNT_ONLY) && used > 0) {
+        if (nw.h_out_cap < used) {
+            host_free(nw.h_out);
+            nw.h_out_cap = 0;
+            const int64_t cap = std::max<int64_t>(used, 1 << 20);
+            HIPX(hipHostMalloc(&nw.h_out, sizeof(int32_t) * cap, hipHostMallocDefault));
+            nw.h_out_cap = cap;
         }
-        NArgs a{};
-        a.g = g->dg;
-        a.qs = nw.d_q;
-        a.nq = np;
-        a.res = nw.d_res;
-        a.queue = (int32_t *)nw.d_ctr;
-        a.bits = nw.bits;
-        a.lists = nw.lists;
-        a.lcap = nw.lcap;
-        a.slab = nw.slab;
-        a.slab_bytes = nw.slab_bytes;
-        a.rootbits = nw.d_rootbits;
-        a.out = nw.d_out;
-        a.out_cap = nw.out_cap;
-        a.out_used = nw.d_ctr + 1;
-        {
-            Prof p(g, SGM_K_PERSIST, 0.0);
-            launch_narrow(st, a, std::min(np, nw.slots));
+        HIPX(hipMemcpyAsync(nw.h_out, nw.d_out, sizeof(int32_t) * used, hipMemcpyDeviceToHost, st));
+        HIPX(hipStreamSynchronize(st));
+    }
+    const int64_t t1 = now_ns();
+    for (int i = 0; i < np; ++i) {
+        const NResult &r = nw.h_res[i];
+        const int qi_idx = job.packed[i];
+        if (r.status != SGM_OK) {
+            wide.push_back(qi_idx);
+            continue;
         }
-        HIPX(hipMemcpyAsync(nw.h_res, nw.d_res, sizeof(NResult) * np, hipMemcpyDeviceToHost, st));
-        HIPX(hipMemcpyAsync(nw.h_ctr, nw.d_ctr, sizeof(unsigned long long) * 2,
-                            hipMemcpyDeviceToHost, st));
-        sync(g);
-        if (g->opts.profile) {
-            double b = 0;
-            for (int i = 0; i < np; ++i) b += (double)nw.h_res[i].bytes;
-            g->kstat[SGM_K_PERSIST].bytes_total += b;
+        sgm_result *out = res[qi_idx];
+        const QInfo &qi = qis[qi_idx];
+        out->n_cols = qi.n;
+        out->n_rows = r.n_rows;
+        sgm_stats &stt = out->stats;
+        for (int u = 0; u < qi.n; ++u) {
+            stt.cand[u] = r.cand[u];
+            stt.level_rows[u] = r.level_rows[u];
+            stt.join_order[u] = r.join_order[u];
         }
-        const int64_t used = std::min<int64_t>((int64_t)nw.h_ctr[1], nw.out_cap);
-        if (!(flags & SGM_COUNT_ONLY) && used > 0) {
-            if (nw.h_out_cap < used) {
-                host_free(nw.h_out);
-                nw.h_out_cap = 0;
-                const int64_t cap = std::max<int64_t>(used, 1 << 20);
-                HIPX(hipHostMalloc(&nw.h_out, sizeof(int32_t) * cap, hipHostMallocDefault));
-                nw.h_out_cap = cap;
-            }
-            HIPX(hipMemcpyAsync(nw.h_out, nw.d_out, sizeof(int32_t) * used, hipMemcpyDeviceToHost,
-                                st));
-            sync(g);
+        for (int e = 0; e < qi.m; ++e) stt.ec[e] = r.ec[e];
+        for (int u = 0; u < SGM_MAX_QV; ++u) stt.visit_order[u] = job.plans[i].visit[u];
+        for (int u = 0; u < qi.n; ++u)
+            stt.peak_rows = std::max(stt.peak_rows, (int64_t)r.level_rows[u]);
+        stt.n_chunks = 1;
+        stt.n_launches = job.nroot ? 2 : 1;
+        stt.ns_total = t1 - job.t0;
+        stt.ns_filter = (int64_t)(r.ticks[0] * g->ns_per_tick);
+        stt.ns_collect = (int64_t)(r.ticks[1] * g->ns_per_tick);
+        stt.ns_join = (int64_t)(r.ticks[2] * g->ns_per_tick);
+        stt.ns_finish = (int64_t)(r.ticks[3] * g->ns_per_tick);
+        stt.device_bytes = r.bytes;
+        stt.path = SGM_PATH_NARROW;
+        if (g->opts.result_cap_rows > 0 && r.n_rows > g->opts.result_cap_rows) {
+            out->status = SGM_ETOOBIG;
+            continue;
         }
-        const int64_t t1 = now_ns();
-        for (int i = 0; i < np; ++i) {
-            const NResult &r = nw.h_res[i];
-            const int qi_idx = packed[i];
-            if (r.status != SGM_OK) {
-                wide.push_back(qi_idx);
-                continue;
-            }
-            sgm_result *out = res[qi_idx];
-            const QInfo &qi = qis[qi_idx];
-            out->n_cols = qi.n;
-            out->n_rows = r.n_rows;
-            sgm_stats &stt = out->stats;
-            for (int u = 0; u < qi.n; ++u) {
-                stt.cand[u] = r.cand[u];
-                stt.level_rows[u] = r.level_rows[u];
-                stt.join_order[u] = r.join_order[u];
-            }
-            for (int e = 0; e < qi.m; ++e) stt.ec[e] = r.ec[e];
-            for (int u = 0; u < SGM_MAX_QV; ++u) stt.visit_order[u] = plans[i].visit[u];
-            for (int u = 0; u < qi.n; ++u)
-                stt.peak_rows = std::max(stt.peak_rows, (int64_t)r.level_rows[u]);
-            stt.n_chunks = 1;
-            stt.n_launches = nroot ? 2 : 1;
-            stt.ns_total = t1 - t0;
-            stt.ns_filter = (int64_t)(r.ticks[0] * g->ns_per_tick);
-            stt.ns_collect = (int64_t)(r.ticks[1] * g->ns_per_tick);
-            stt.ns_join = (int64_t)(r.ticks[2] * g->ns_per_tick);
-            stt.ns_finish = (int64_t)(r.ticks[3] * g->ns_per_tick);
-            stt.device_bytes = r.bytes;
-            stt.path = SGM_PATH_NARROW;
-            if (g->opts.result_cap_rows > 0 && r.n_rows > g->opts.result_cap_rows) {
-                out->status = SGM_ETOOBIG;
-                continue;
-            }
-            out->status = SGM_OK;
-            if (!(flags & SGM_COUNT_ONLY)) {
-                const size_t bytes = sizeof(int32_t) * (size_t)r.n_rows * qi.n;
-                out->rows = (int32_t *)std::malloc(std::max<size_t>(bytes, 4));
-                if (!out->rows) throw std::bad_alloc();
-                if (bytes) std::memcpy(out->rows, nw.h_out + r.offset, bytes);
-            }
+        out->status = SGM_OK;
+        if (!(flags & SGM_COUNT_ONLY)) {
+            const size_t bytes = sizeof(int32_t) * (size_t)r.n_rows * qi.n;
+            out->rows = (int32_t *)std::malloc(std::max<size_t>(bytes, 4));
+            if (!out->rows) throw std::bad_alloc();
+            if (bytes) std::memcpy(out->rows, nw.h_out + r.offset, bytes);
         }
     }
 }
 
+// Run queries `which` (validated into qis) through the persistent kernel on
+// the graph's own stream, kNarrowQueryCap per launch.
+void narrow_batch(sgm_graph *g, const std::vector<QInfo> &qis, const std::vector<int> &which,
+                  uint32_t flags, std::vector<sgm_result *> &res, std::vector<int> &wide) {
+    for (size_t base = 0; base < which.size(); base += kNarrowQueryCap) {
+        const int count = (int)std::min<size_t>(kNarrowQueryCap, which.size() - base);
+        NarrowJob job;
+        if (narrow_launch(g, g->nw, qis, which.data() + base, count, job, wide, true))
+            narrow_collect(g, g->nw, job, qis, flags, res, wide, true);
+    }
+}
 
 // multi-kernel path for one validated query
 int wide_locked(sgm_graph *g, const QInfo &qi, uint32_t flags, sgm_result *res) {
@@ -1296,6 +1354,7 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
     try {
         HIPX(hipSetDevice(g->device));
         HIPX(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+        g->nw.stream = g->stream;
         int khz = 0;
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device) == hipSuccess &&
             khz > 0)
@@ -1431,6 +1490,371 @@ int sgm_reset_kernel_stats(sgm_graph *g) {
     std::lock_guard<std::mutex> lk(g->mu);
     for (auto &k : g->kstat) k = sgm_kstat{};
     return SGM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// served form: continuous batching over streams
+// ---------------------------------------------------------------------------
+
+struct sgm_server {
+    sgm_graph *g = nullptr;
+    sgm_serve_options o{};
+    int64_t slot_bytes = 0;
+    std::vector<NarrowCtx> ctx;
+    std::vector<char> ctx_busy;
+    struct Ticket {
+        QInfo qi;
+        int status = SGM_OK;  // of the query check
+        uint32_t flags = 0;
+        int64_t t_submit = 0, t_done = 0;
+        int64_t est = 0;
+        sgm_result *res = nullptr;
+        bool done = false;
+    };
+    struct Batch {
+        int ctx = -1;
+        std::vector<uint64_t> ids;
+        std::vector<QInfo> qis;
+        std::vector<sgm_result *> res;
+        std::vector<int> which, wide;
+        NarrowJob job;
+        bool launched = false;
+        int64_t est = 0;
+        uint32_t flags = 0;
+    };
+    std::mutex mu;
+    std::condition_variable cv_in, cv_out, cv_ctx, cv_done;
+    std::deque<uint64_t> pending;
+    std::unordered_map<uint64_t, Ticket> tickets;
+    std::deque<Batch *> inflight;
+    uint64_t next_id = 1;
+    int64_t bytes_in_flight = 0, queries_in_flight = 0;
+    bool stop = false;
+    bool dispatcher_done = false;
+    sgm_serve_stats st{};
+    std::thread dispatcher, completer;
+};
+
+namespace {
+
+void serve_dispatch(sgm_server *S) {
+    sgm_graph *g = S->g;
+    (void)hipSetDevice(g->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        S->cv_in.wait(lk, [&] { return S->stop || !S->pending.empty(); });
+        if (S->pending.empty()) {
+            if (S->stop) break;
+            continue;
+        }
+        // batch window: wait for a full batch or the first query's deadline
+        for (;;) {
+            if ((int)S->pending.size() >= S->o.max_batch || S->stop) break;
+            const int64_t first = S->tickets[S->pending.front()].t_submit;
+            const int64_t left = first + S->o.max_wait_ns - now_ns();
+            if (left <= 0) break;
+            S->cv_in.wait_for(lk, std::chrono::nanoseconds(left));
+        }
+        // a free stream context
+        int ci = -1;
+        S->cv_ctx.wait(lk, [&] {
+            for (size_t i = 0; i < S->ctx.size(); ++i)
+                if (!S->ctx_busy[i]) {
+                    ci = (int)i;
+                    return true;
+                }
+            return false;
+        });
+        // admission: estimated intermediate bytes against the cap; the flags
+        // of a batch are those of its first query
+        sgm_server::Batch *b = new sgm_server::Batch();
+        b->ctx = ci;
+        b->flags = S->tickets[S->pending.front()].flags;
+        bool stalled = false;
+        while (!S->pending.empty() && (int)b->ids.size() < S->o.max_batch) {
+            sgm_server::Ticket &t = S->tickets[S->pending.front()];
+            if (t.flags != b->flags) break;
+            const bool nothing_running = S->queries_in_flight == 0 && b->ids.empty();
+            if (!nothing_running && S->bytes_in_flight + b->est + t.est > S->o.admission_cap_bytes) {
+                stalled = true;
+                break;
+            }
+            b->ids.push_back(S->pending.front());
+            b->est += t.est;
+            S->pending.pop_front();
+        }
+        if (stalled) S->st.admission_stalls++;
+        if (b->ids.empty()) {
+            delete b;
+            // wait for running work to free memory
+            S->cv_done.wait(lk);
+            continue;
+        }
+        S->ctx_busy[ci] = 1;
+        S->bytes_in_flight += b->est;
+        S->queries_in_flight += (int64_t)b->ids.size();
+        S->st.max_in_flight = std::max(S->st.max_in_flight, S->queries_in_flight);
+        S->st.batches++;
+        for (uint64_t id : b->ids) {
+            sgm_server::Ticket &t = S->tickets[id];
+            b->qis.push_back(t.qi);
+            b->res.push_back(t.res);
+        }
+        lk.unlock();
+        for (size_t i = 0; i < b->ids.size(); ++i)
+            if (b->res[i]->status == SGM_OK) b->which.push_back((int)i);
+        try {
+            b->launched = narrow_launch(g, S->ctx[ci], b->qis, b->which.data(),
+                                        (int)b->which.size(), b->job, b->wide, false);
+        } catch (const DeviceError &e) {
+            for (auto *r : b->res) r->status = e.code;
+            b->which.clear();
+            b->wide.clear();
+            b->launched = false;
+        }
+        lk.lock();
+        S->inflight.push_back(b);
+        S->cv_out.notify_one();
+    }
+    S->dispatcher_done = true;
+    S->cv_out.notify_all();
+}
+
+void serve_complete(sgm_server *S) {
+    sgm_graph *g = S->g;
+    (void)hipSetDevice(g->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        S->cv_out.wait(lk, [&] { return !S->inflight.empty() || S->dispatcher_done; });
+        if (S->inflight.empty()) {
+            if (S->dispatcher_done) break;
+            continue;
+        }
+        sgm_server::Batch *b = S->inflight.front();
+        lk.unlock();
+        try {
+            if (b->launched)
+                narrow_collect(g, S->ctx[b->ctx], b->job, b->qis, b->flags, b->res, b->wide, false);
+        } catch (const DeviceError &e) {
+            for (int i : b->which) b->res[i]->status = e.code;
+            b->wide.clear();
+        } catch (const std::bad_alloc &) {
+            for (int i : b->which) b->res[i]->status = SGM_ENOMEM;
+            b->wide.clear();
+        }
+        // queries that outgrew their slot: the multi-kernel path
+        for (int i : b->wide) {
+            std::lock_guard<std::mutex> gl(g->mu);
+            std::memset(&b->res[i]->stats, 0, sizeof(sgm_stats));
+            b->res[i]->stats.path = SGM_PATH_WIDE;
+            b->res[i]->status = wide_locked(g, b->qis[i], b->flags, b->res[i]);
+        }
+        const int64_t t_done = now_ns();
+        lk.lock();
+        S->st.wide_fallbacks += (int64_t)b->wide.size();
+        for (size_t i = 0; i < b->ids.size(); ++i) {
+            auto it = S->tickets.find(b->ids[i]);
+            sgm_server::Ticket &t = it->second;
+            t.t_done = t_done;
+            t.done = true;
+            sgm_result *r = t.res;
+            if (r->status != SGM_OK && r->status != SGM_ETOOBIG) {
+                std::free(r->rows);
+                r->rows = nullptr;
+            }
+            r->stats.ns_total = t_done - t.t_submit;
+        }
+        S->st.completed += (int64_t)b->ids.size();
+        S->bytes_in_flight -= b->est;
+        S->queries_in_flight -= (int64_t)b->ids.size();
+        S->ctx_busy[b->ctx] = 0;
+        S->inflight.pop_front();
+        delete b;
+        S->cv_ctx.notify_all();
+        S->cv_done.notify_all();
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void sgm_default_serve_options(sgm_serve_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->streams = 4;
+    o->max_batch = 256;
+    o->max_wait_ns = 100000;
+    o->admission_cap_bytes = 64ll << 30;
+}
+
+int sgm_server_create(sgm_graph *g, const sgm_serve_options *opts, sgm_server **out) {
+    if (!out) return SGM_EINVAL;
+    *out = nullptr;
+    if (!g) return SGM_EINVAL;
+    sgm_serve_options o;
+    if (opts) o = *opts;
+    else sgm_default_serve_options(&o);
+    if (o.streams < 1 || o.streams > 16 || o.max_batch < 1 || o.max_batch > kNarrowQueryCap ||
+        o.max_wait_ns < 0 || o.admission_cap_bytes <= 0)
+        return SGM_EINVAL;
+    sgm_server *S = new (std::nothrow) sgm_server();
+    if (!S) return SGM_ENOMEM;
+    S->g = g;
+    S->o = o;
+    S->slot_bytes = narrow_slot_bytes(g);
+    S->ctx.resize((size_t)o.streams);
+    S->ctx_busy.assign((size_t)o.streams, 0);
+    try {
+        HIPX(hipSetDevice(g->device));
+        for (auto &c : S->ctx) {
+            HIPX(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+            narrow_reserve(g, c, std::min(o.max_batch, kNarrowMaxSlots), o.max_batch, 0);
+        }
+    } catch (const DeviceError &e) {
+        for (auto &c : S->ctx) {
+            narrow_free(c);
+            if (c.stream) (void)hipStreamDestroy(c.stream);
+        }
+        delete S;
+        return e.code;
+    }
+    S->dispatcher = std::thread(serve_dispatch, S);
+    S->completer = std::thread(serve_complete, S);
+    *out = S;
+    return SGM_OK;
+}
+
+int sgm_submit(sgm_server *s, const sgm_query *q, uint32_t flags, uint64_t *ticket) {
+    if (!s || !q || !ticket || (flags & ~SGM_COUNT_ONLY)) return SGM_EINVAL;
+    sgm_result *res = (sgm_result *)std::calloc(1, sizeof(sgm_result));
+    if (!res) return SGM_ENOMEM;
+    sgm_server::Ticket t;
+    t.status = check_query(q, s->g->V, &t.qi);
+    res->status = t.status;
+    t.flags = flags;
+    t.res = res;
+    t.est = s->slot_bytes;
+    t.t_submit = now_ns();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+        std::free(res);
+        return SGM_EINVAL;
+    }
+    const uint64_t id = s->next_id++;
+    *ticket = id;
+    s->st.submitted++;
+    if (t.status != SGM_OK) {
+        t.done = true;
+        t.t_done = t.t_submit;
+        s->st.completed++;
+        s->tickets.emplace(id, t);
+        s->cv_done.notify_all();
+        return SGM_OK;
+    }
+    s->tickets.emplace(id, t);
+    s->pending.push_back(id);
+    s->cv_in.notify_one();
+    return SGM_OK;
+}
+
+int sgm_wait(sgm_server *s, uint64_t ticket, int64_t timeout_ns, sgm_result **out) {
+    if (!s || !out) return SGM_EINVAL;
+    *out = nullptr;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return SGM_EINVAL;
+    auto ready = [&] { return s->tickets[ticket].done; };
+    if (timeout_ns < 0) s->cv_done.wait(lk, ready);
+    else if (!s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), ready))
+        return SGM_EDEVICE;
+    it = s->tickets.find(ticket);
+    *out = it->second.res;
+    s->tickets.erase(it);
+    return SGM_OK;
+}
+
+int sgm_server_stats(sgm_server *s, sgm_serve_stats *out) {
+    if (!s || !out) return SGM_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    return SGM_OK;
+}
+
+void sgm_server_destroy(sgm_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_in.notify_all();
+    s->cv_out.notify_all();
+    s->cv_ctx.notify_all();
+    s->cv_done.notify_all();
+    if (s->dispatcher.joinable()) s->dispatcher.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->cv_out.notify_all();
+    }
+    if (s->completer.joinable()) s->completer.join();
+    (void)hipSetDevice(s->g->device);
+    for (auto &c : s->ctx) {
+        narrow_free(c);
+        if (c.stream) (void)hipStreamDestroy(c.stream);
+    }
+    for (auto &kv : s->tickets) sgm_free_result(kv.second.res);
+    delete s;
+}
+
+int sgm_serve_replay(sgm_server *s, const sgm_query *qs, const int64_t *arrival_ns, int32_t n,
+                     uint32_t flags, int64_t *latency_ns, sgm_result **out) {
+    if (!s || n < 0 || (n > 0 && (!qs || !arrival_ns || !latency_ns))) return SGM_EINVAL;
+    for (int32_t i = 1; i < n; ++i)
+        if (arrival_ns[i] < arrival_ns[i - 1]) return SGM_EINVAL;
+    // state[i]: 0 = not yet submitted, > 0 = ticket, < 0 = submit error
+    std::vector<std::atomic<int64_t>> state((size_t)n);
+    std::vector<int64_t> sub_t((size_t)n, 0);
+    for (auto &x : state) x.store(0);
+    const int64_t t0 = now_ns();
+    std::thread sub([&] {
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t at = t0 + arrival_ns[i];
+            const int64_t now = now_ns();
+            if (at - now > 200000)
+                std::this_thread::sleep_for(std::chrono::nanoseconds(at - now - 100000));
+            while (now_ns() < at) {
+            }
+            uint64_t tk = 0;
+            sub_t[i] = now_ns();
+            const int rc = sgm_submit(s, &qs[i], flags, &tk);
+            state[i].store(rc == SGM_OK ? (int64_t)tk : (int64_t)rc);
+        }
+    });
+    int ret = SGM_OK;
+    for (int32_t i = 0; i < n; ++i) {
+        int64_t st;
+        while ((st = state[i].load()) == 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        latency_ns[i] = -1;
+        if (out) out[i] = nullptr;
+        if (st < 0) {
+            ret = (int)st;
+            continue;
+        }
+        sgm_result *r = nullptr;
+        const int w = sgm_wait(s, (uint64_t)st, -1, &r);
+        if (w != SGM_OK) {
+            ret = w;
+            continue;
+        }
+        // completion - scheduled arrival (ns_total = completion - submission)
+        latency_ns[i] = sub_t[i] + r->stats.ns_total - (t0 + arrival_ns[i]);
+        if (out) out[i] = r;
+        else sgm_free_result(r);
+    }
+    sub.join();
+    return ret;
 }
 
 }  // extern "C"

@@ -1,0 +1,96 @@
+"""Served form: queries arriving while others run are batched continuously
+over several streams; each result must equal the same query matched alone
+(bit-exact), whatever the arrival rate, batch window or memory cap."""
+import sys
+
+import numpy as np
+import pytest
+
+import kggen
+import paper_1807_08804_amd as P
+from tests.micro import MicroQuery
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def same(a, b):
+    assert a.shape == b.shape, (a.shape, b.shape)
+    assert np.array_equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def g_medium_s(medium_kg):
+    return P.Graph.from_kg(medium_kg)
+
+
+@pytest.fixture(scope="module")
+def medium_alone(g_medium_s, medium_kg):
+    qs, _ = kggen.medium_queries(medium_kg, 100)
+    return qs, [g_medium_s.match_query(q) for q in qs]
+
+
+@pytest.mark.parametrize("qps", [500, 5000, 50000])
+def test_served_equals_alone(qps, g_medium_s, medium_alone):
+    qs, alone = medium_alone
+    # 300 arrivals cycling over the 100 queries
+    stream = [qs[i % len(qs)] for i in range(300)]
+    want = [alone[i % len(qs)] for i in range(300)]
+    arr = kggen.poisson_arrivals(len(stream), qps, seed=qps)
+    say(f"case: served at {qps} qps")
+    srv = P.Server(g_medium_s, streams=4, max_batch=64, max_wait_ns=50_000)
+    lat, res = srv.replay(stream, arr)
+    st = srv.stats()
+    srv.close()
+    for r, w in zip(res, want):
+        same(r, w)
+    assert np.all(lat > 0)
+    assert st["completed"] == len(stream) and st["batches"] >= 1
+    say(f"  batches={st['batches']} max_in_flight={st['max_in_flight']} "
+        f"p50={np.percentile(lat, 50) / 1e3:.0f}us p99={np.percentile(lat, 99) / 1e3:.0f}us")
+
+
+def test_served_tiny_cap_and_errors(g_medium_s, medium_alone):
+    """A 1-byte admission cap admits one query at a time (stalls are
+    counted); an invalid query fails alone without touching the others."""
+    qs, alone = medium_alone
+    bad = MicroQuery(2, [-1, -1], [-1, -1], [0], [0], [-1])  # self-loop
+    stream = qs[:20] + [bad] + qs[20:40]
+    srv = P.Server(g_medium_s, streams=2, max_batch=8, max_wait_ns=0, admission_cap_bytes=1)
+    tickets = [srv.submit(q) for q in stream]
+    outs = [srv.wait(t, q.n) for t, q in zip(tickets, stream)]
+    st = srv.stats()
+    srv.close()
+    for i, (status, rows, _) in enumerate(outs):
+        if i == 20:
+            assert status == P.SGM_EINVAL and rows is None
+        else:
+            assert status == P.SGM_OK
+            same(rows, alone[i if i < 20 else i - 1])
+    assert st["max_in_flight"] == 1
+    assert st["admission_stalls"] >= 1
+
+
+def test_served_large_graph(large_kg_serve):
+    """Walk queries on the 4M/20M graph at 5000 qps: served == alone."""
+    g, qs, alone = large_kg_serve
+    arr = kggen.poisson_arrivals(len(qs), 5000)
+    srv = P.Server(g)
+    lat, res = srv.replay(qs, arr)
+    srv.close()
+    for r, w in zip(res, alone):
+        same(r, w)
+
+
+@pytest.fixture(scope="module")
+def large_kg_serve():
+    kg = kggen.named_graph("large")
+    kg.ensure_in()
+    g = P.Graph.from_kg(kg)
+    qs, _ = kggen.serve_queries(kg, 128)
+    say("case: large serve set ready")
+    return g, qs, [g.match_query(q) for q in qs]
