@@ -1,16 +1,21 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the GPU subgraph matcher on one MI355X.
 
-Workload (default): the medium synthetic knowledge graph (300,000 vertices,
-1.6M directed edges, 64 vertex types, 32 Zipf relations) resident in HBM and
-100 random-walk queries of 6-10 vertices (paths and trees, 0-2 pinned
-vertices), matched one query at a time with full sorted embedding tables
-copied back to the host. One step = the 100 queries. ``value`` = queries/s.
+Default workload ("medium"): the medium synthetic knowledge graph (300,000
+vertices, 1.6M directed edges, 64 vertex types, 32 Zipf relations) resident
+in HBM and 100 random-walk queries of 6-10 vertices (paths and trees, 0-2
+pinned vertices), matched one query at a time with full sorted embedding
+tables copied back to the host. One step = the 100 queries; ``value`` =
+queries/s. Also reported: embeddings/s, per-query latency p50/p99, the same
+queries through sgm_match_batch (one persistent launch), the served form at
+several Poisson arrival rates (sustained qps, p50/p99 of completion minus
+arrival), per-phase device times, the roofline of the dominant kernel class
+and the CPU oracle on a bounded sample.
 
-Also reported: embeddings/s, per-query latency p50/p99, the same 100 queries
-through sgm_match_batch, the roofline of the dominant kernel class (HIP
-events on the library's stream, algorithmic bytes per launch) and the CPU
-oracle on a bounded sample of the same queries.
+``--workload large``: the 4M-vertex / 20M-edge graph with 1024 mixed queries
+(3-16 vertices; paths, stars, trees, cyclic; 0-50% pinned) as one batch vs
+one at a time, the served walk-query stream at 200 / 1000 / 5000 qps, and the
+roofline of the batched root sweep.
 """
 import argparse
 import json
@@ -31,28 +36,66 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--queries", type=int, default=100)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the matcher "
-              "has no multi-GPU path in this build.", file=sys.stderr)
-        sys.exit(2)
+def roofline(ks, kernel=None):
+    """Roofline of one kernel class (the dominant one with byte accounting
+    if not named) from HIP-event times and algorithmic bytes."""
+    if kernel is None:
+        kernel = max((k for k in ks if ks[k]["bytes"] > 0), key=lambda k: ks[k]["ms"])
+    d = ks[kernel]
+    achieved = d["bytes"] / (d["ms"] / 1e3) / 1e9 if d["ms"] > 0 else 0.0
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": None, "launches": d["launches"],
+            "avg_launch_us": round(d["ms"] * 1e3 / max(d["launches"], 1), 3),
+            "bytes_per_launch": round(d["bytes"] / max(d["launches"], 1), 1)}
 
-    import kggen
-    import paper_1807_08804_amd as P
 
+def served_leg(P, kggen, g, queries, rates, arrivals):
+    out = {}
+    for rate in rates:
+        stream = [queries[i % len(queries)] for i in range(arrivals)]
+        arr = kggen.poisson_arrivals(len(stream), rate, seed=int(rate))
+        srv = P.Server(g)
+        t = time.perf_counter()
+        lat, _ = srv.replay(stream, arr, keep_results=False)
+        wall = time.perf_counter() - t
+        sst = srv.stats()
+        srv.close()
+        warm = len(lat) // 20  # the first 5% of arrivals are warm-up
+        lt = np.sort(lat[warm:]) / 1e6
+        out[str(int(rate))] = {
+            "sustained_qps": round(len(stream) / wall, 1),
+            "p50_ms": round(float(np.percentile(lt, 50)), 3),
+            "p99_ms": round(float(np.percentile(lt, 99)), 3),
+            "batches": sst["batches"], "max_in_flight": sst["max_in_flight"],
+            "wide_fallbacks": sst["wide_fallbacks"]}
+        log(f"served at {rate:.0f} qps: {out[str(int(rate))]}")
+    return out
+
+
+def cpu_leg(kg, queries, seconds):
+    import oracle
+    og = oracle.graph_from_kg(kg)
+    cores = os.cpu_count() or 1
+    cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    done, skipped, t = 0, 0, time.perf_counter()
+    while done + skipped < len(queries) and time.perf_counter() - t < seconds:
+        try:
+            og.match_query(queries[done + skipped], nthreads=cores, max_steps=200_000_000)
+            done += 1
+        except oracle.OracleError:
+            skipped += 1
+    el = time.perf_counter() - t
+    return {"value": round(done / el, 3), "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {done + skipped} of the {len(queries)} queries one at a time "
+                      f"({skipped} stopped by the oracle's work budget), {el:.1f}s wall"}
+
+
+def bench_medium(args, P, kggen):
     t0 = time.time()
     kg = kggen.named_graph("medium")
     queries, rejected = kggen.medium_queries(kg, args.queries)
     log(f"inputs ready in {time.time() - t0:.1f}s (rejected {rejected})")
-
     g = P.Graph.from_kg(kg)
     gp = P.Graph.from_kg(kg, profile=1)
 
@@ -81,21 +124,21 @@ def main():
     el = time.perf_counter() - t
     log(f"timed {args.steps} steps in {el:.3f}s")
     nq = len(queries) * args.steps
-    qps = nq / el
     lat_ms = sorted(x / 1e6 for x in lat)
     p50 = lat_ms[len(lat_ms) // 2]
     p99 = lat_ms[min(len(lat_ms) - 1, int(round(0.99 * (len(lat_ms) - 1))))]
 
-    # the same queries through sgm_match_batch
     g.match_batch(queries)
     t = time.perf_counter()
     for i in range(args.steps):
         g.match_batch(queries)
     el_b = time.perf_counter() - t
-    batch_qps = nq / el_b
     log(f"batch path {el_b:.3f}s")
 
-    # per-phase device times of the persistent kernel (one pass)
+    served = served_leg(P, kggen, g, queries,
+                        [float(x) for x in args.serve_rates.split(",") if x],
+                        args.serve_arrivals)
+
     stl = []
     one_step(g, stats=stl)
     narrow = [st for st in stl if st["path"] == P.SGM_PATH_NARROW]
@@ -103,44 +146,18 @@ def main():
               for k in ("ns_filter", "ns_collect", "ns_join", "ns_finish")}
     phases["queries_on_persistent_kernel"] = len(narrow)
 
-    # roofline: every launch timed with HIP events on the library stream
     one_step(gp)
     gp.reset_kernel_stats()
-    t = time.perf_counter()
     for i in range(args.steps):
         one_step(gp)
-    el_p = time.perf_counter() - t
     ks = gp.kernel_stats()
     log("kernel classes (profiled region): " + json.dumps(
         {k: dict(launches=v["launches"], ms=round(v["ms"], 3)) for k, v in ks.items()}))
-    dom = max((k for k in ks if ks[k]["bytes"] > 0), key=lambda k: ks[k]["ms"])
-    d = ks[dom]
-    achieved = d["bytes"] / (d["ms"] / 1e3) / 1e9 if d["ms"] > 0 else 0.0
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": None, "launches": d["launches"],
-            "avg_launch_us": round(d["ms"] * 1e3 / max(d["launches"], 1), 3),
-            "bytes_per_launch": round(d["bytes"] / max(d["launches"], 1), 1)}
 
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        og = oracle.graph_from_kg(kg)
-        cores = os.cpu_count() or 1
-        cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
-        done, t = 0, time.perf_counter()
-        while done < len(queries) and time.perf_counter() - t < args.cpu_seconds:
-            og.match_query(queries[done], nthreads=cores)
-            done += 1
-        el_c = time.perf_counter() - t
-        cpu = {"value": round(done / el_c, 3), "unit": "queries/s", "cores": cores,
-               "kind": "oracle",
-               "sample": f"first {done} of the {len(queries)} medium queries, one at a time, "
-                         f"{el_c:.1f}s wall"}
-
-    out = {
+    cpu = None if args.no_cpu else cpu_leg(kg, queries, args.cpu_seconds)
+    return {
         "metric": "queries/s (single-query, medium KG, 100 walk queries)",
-        "value": round(qps, 3),
+        "value": round(nq / el, 3),
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -157,11 +174,98 @@ def main():
                    "queries_per_step": len(queries)},
         "embeddings_per_s": round(rows / el, 1),
         "latency_ms": {"p50": round(p50, 3), "p99": round(p99, 3)},
-        "batch_api_queries_per_s": round(batch_qps, 3),
+        "batch_api_queries_per_s": round(nq / el_b, 3),
+        "served": served,
         "persistent_kernel_phase_us": phases,
-        "roofline": roof,
+        "roofline": roofline(ks),
         "cpu_baseline": cpu,
     }
+
+
+def bench_large(args, P, kggen):
+    t0 = time.time()
+    kg = kggen.named_graph("large")
+    kg.ensure_in()
+    queries, rejected = kggen.batch_queries(kg, args.batch)
+    log(f"batch inputs ready in {time.time() - t0:.1f}s (rejected {rejected})")
+    t = time.time()
+    g = P.Graph.from_kg(kg)
+    gp = P.Graph.from_kg(kg, profile=1)
+    log(f"graph resident in {time.time() - t:.1f}s")
+
+    g.match_batch(queries)
+    t = time.perf_counter()
+    rows = 0
+    for i in range(args.steps):
+        rows = sum(len(r) for r in g.match_batch(queries))
+    el_b = time.perf_counter() - t
+    log(f"batched: {args.steps} x {len(queries)} in {el_b:.3f}s")
+    t = time.perf_counter()
+    for q in queries:
+        g.match_query(q)
+    el_1 = time.perf_counter() - t
+    log(f"one at a time: {len(queries)} in {el_1:.3f}s")
+
+    gp.match_batch(queries)
+    gp.reset_kernel_stats()
+    for i in range(args.steps):
+        gp.match_batch(queries)
+    ks = gp.kernel_stats()
+    log("kernel classes (profiled region): " + json.dumps(
+        {k: dict(launches=v["launches"], ms=round(v["ms"], 3)) for k, v in ks.items()}))
+
+    sq, _ = kggen.serve_queries(kg, args.serve_queries)
+    log("serve inputs ready")
+    served = served_leg(P, kggen, g, sq, [200.0, 1000.0, 5000.0], args.serve_arrivals)
+    cpu = None if args.no_cpu else cpu_leg(kg, queries, args.cpu_seconds)
+    nq = args.steps * len(queries)
+    return {
+        "metric": "queries/s (batched, large KG, 1024 mixed queries in one persistent launch)",
+        "value": round(nq / el_b, 3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": round(el_b * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "large KG 4M V / 20M E; 1024 queries, 3-16 vertices, "
+                               "paths/stars/trees/cyclic, 0-50% pinned, H <= 1e6",
+                   "queries_per_step": len(queries)},
+        "embeddings_per_s": round(rows * args.steps / el_b, 1),
+        "single_query_queries_per_s": round(len(queries) / el_1, 3),
+        "served": served,
+        "roofline": roofline(ks),
+        "roofline_root_sweep": roofline(ks, "check"),
+        "cpu_baseline": cpu,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["medium", "large"], default="medium")
+    ap.add_argument("--queries", type=int, default=100)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--serve-queries", type=int, default=512)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-rates", default="1000,5000,20000",
+                    help="arrival rates (qps) of the medium served-form measurement")
+    ap.add_argument("--serve-arrivals", type=int, default=2000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the matcher "
+              "has no multi-GPU path in this build.", file=sys.stderr)
+        sys.exit(2)
+    import kggen
+    import paper_1807_08804_amd as P
+    out = bench_large(args, P, kggen) if args.workload == "large" else bench_medium(args, P, kggen)
     print(json.dumps(out), flush=True)
 
 

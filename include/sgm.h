@@ -110,7 +110,10 @@ typedef struct {
                                       persistent kernel */
     int64_t device_bytes;          /* persistent kernel: algorithmic bytes moved */
     int32_t path;                  /* SGM_PATH_WIDE or SGM_PATH_NARROW: where it ran */
-    int32_t pad_;
+    int32_t fallback;              /* why a query left the persistent kernel for the
+                                      multi-kernel path: 1 candidate list capacity,
+                                      2 slot memory, 4 ordering key > 64 bits,
+                                      8 output arena full, 16 plan descriptor size */
 } sgm_stats;
 
 typedef struct {
@@ -220,6 +223,24 @@ int sgm_reset_kernel_stats(sgm_graph *g);
 int sgm_plan_query(const sgm_query *q, int32_t n_vertices, const int64_t *type_freq,
                    int32_t n_types, int32_t *visit_order, int32_t *parent,
                    int32_t *parent_edge, int32_t *init_order);
+
+/*
+ * Verification entry point: the candidate set of every query vertex after
+ * the filtering phase (thesis Alg. 3.2 initialisation along the plan's
+ * spanning tree, then the configured refinement, Sec. "Candidate Nodes
+ * Refinement") and the candidate-edge count of every query edge (Sec.
+ * "Joining Phase"), computed by the multi-kernel path's kernels (the
+ * persistent kernel runs the same filter program).
+ *   counts[SGM_MAX_QV]: out, number of candidates of each query vertex;
+ *   *ids: out, library-owned ascending candidate lists concatenated in
+ *         query-vertex order (free with sgm_free_ids);
+ *   ec[SGM_MAX_QE]: out, candidate edges of each query edge (all 0 when a
+ *         candidate set is empty).
+ * Errors as for sgm_match_query's query checks, SGM_ENOMEM, SGM_EDEVICE.
+ */
+int sgm_inspect_query(sgm_graph *g, const sgm_query *q, int64_t *counts, int32_t **ids,
+                      int64_t *ec);
+void sgm_free_ids(int32_t *ids);
 
 /* ------------------------------------------------------------------------
  * Served form: a request loop that keeps the graph resident, admits arriving

@@ -57,6 +57,18 @@ def _load():
                                             ctypes.c_int64, ctypes.c_int,
                                             ctypes.POINTER(i32p), ctypes.POINTER(ctypes.c_int64)]
         lib.oracle_free.argtypes = [ctypes.c_void_p]
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.oracle_plan.restype = ctypes.c_int
+        lib.oracle_plan.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, i32p, i32p,
+                                    i32p, i32p, i32p, i32p, i32p, i32p, i32p]
+        lib.oracle_filter.restype = ctypes.c_int
+        lib.oracle_filter.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, i32p, i32p,
+                                      i32p, i32p, i32p, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, u8p]
+        lib.oracle_edge_candidates.restype = ctypes.c_int
+        lib.oracle_edge_candidates.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                               i32p, i32p, i32p, u8p, i64p]
         _lib = lib
     return _lib
 
@@ -125,6 +137,46 @@ class Graph:
     def match_query(self, q, **kw):
         """Same as :meth:`match` for a ``kggen.Query``-like object."""
         return self.match(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel, **kw)
+
+    def _qargs(self, q):
+        arrs = [_i32(q.vlabel), _i32(q.vpin), _i32(q.esrc), _i32(q.edst), _i32(q.elabel)]
+        return arrs, [a[1] for a in arrs]
+
+    def plan(self, q):
+        """The query plan: dict of visit_order, parent, parent_edge,
+        init_order."""
+        arrs, ptrs = self._qargs(q)
+        outs = [np.full(max(q.n, 1), -7, np.int32) for _ in range(4)]
+        rc = _load().oracle_plan(self._h, int(q.n), int(len(q.esrc)), *ptrs,
+                                 *[o.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for o in outs])
+        if rc != OR_OK:
+            raise OracleError(rc)
+        vo, par, pe, io = outs
+        return dict(visit_order=[int(x) for x in vo[:q.n] if x >= 0], parent=par[:q.n].tolist(),
+                    parent_edge=pe[:q.n].tolist(), init_order=[int(x) for x in io[:q.n] if x >= 0])
+
+    def filter(self, q, rounds=1, reversed=1, low_conn=1):
+        """Candidate sets after the filtering phase: [n][V] bool."""
+        arrs, ptrs = self._qargs(q)
+        out = np.zeros((q.n, self.V), np.uint8)
+        rc = _load().oracle_filter(self._h, int(q.n), int(len(q.esrc)), *ptrs, int(rounds),
+                                   int(reversed), int(low_conn),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        if rc != OR_OK:
+            raise OracleError(rc)
+        return out.astype(bool)
+
+    def edge_candidates(self, q, cand):
+        """Candidate-edge count of every query edge for candidate sets cand."""
+        arrs, ptrs = self._qargs(q)
+        c = np.ascontiguousarray(np.asarray(cand, np.uint8))
+        ec = np.zeros(max(len(q.esrc), 1), np.int64)
+        rc = _load().oracle_edge_candidates(self._h, int(q.n), int(len(q.esrc)), ptrs[2], ptrs[3],
+                                            ptrs[4], c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                            ec.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        if rc != OR_OK:
+            raise OracleError(rc)
+        return ec[:len(q.esrc)]
 
 
 def graph_from_kg(kg) -> Graph:

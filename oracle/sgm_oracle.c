@@ -505,3 +505,321 @@ int oracle_match_budget(const oracle_graph *g, int32_t n, int32_t m, const int32
 }
 
 void oracle_free(void *p) { free(p); }
+
+/* ========================================================================
+ * Stage oracles: the query plan, the filtering phase and the candidate-edge
+ * counts of the thesis' method, written from its text (Ch. 3) in plain
+ * sequential C, for stage-by-stage checks of the GPU path. They share no
+ * code with the library.
+ * ===================================================================== */
+
+typedef struct {
+    int32_t n, m;
+    const int32_t *vlabel, *vpin, *esrc, *edst, *elabel;
+    uint32_t nbr[OR_MAXQ];  /* undirected neighbour masks */
+    int32_t deg[OR_MAXQ], qout[OR_MAXQ], qin[OR_MAXQ];
+} st_query;
+
+static void st_query_init(st_query *q, int32_t n, int32_t m, const int32_t *vlabel,
+                          const int32_t *vpin, const int32_t *esrc, const int32_t *edst,
+                          const int32_t *elabel) {
+    memset(q, 0, sizeof(*q));
+    q->n = n;
+    q->m = m;
+    q->vlabel = vlabel;
+    q->vpin = vpin;
+    q->esrc = esrc;
+    q->edst = edst;
+    q->elabel = elabel;
+    uint32_t outm[OR_MAXQ] = {0}, inm[OR_MAXQ] = {0};
+    for (int i = 0; i < m; i++) {
+        outm[esrc[i]] |= 1u << edst[i];
+        inm[edst[i]] |= 1u << esrc[i];
+    }
+    for (int u = 0; u < n; u++) {
+        q->nbr[u] = outm[u] | inm[u];
+        q->deg[u] = __builtin_popcount(q->nbr[u]);
+        q->qout[u] = __builtin_popcount(outm[u]);
+        q->qin[u] = __builtin_popcount(inm[u]);
+    }
+}
+
+/* f(u) = deg(u) / freq(u): a concept (pinned) node has frequency 1, a
+ * variable node the number of data vertices of its type (all V for -1). */
+static int64_t st_freq(const oracle_graph *g, const st_query *q, int u) {
+    if (q->vpin[u] >= 0) return 1;
+    if (q->vlabel[u] < 0) return g->V;
+    int64_t c = 0;
+    for (int32_t v = 0; v < g->V; v++) c += g->vtype[v] == q->vlabel[u];
+    return c > 0 ? c : 1;
+}
+
+/*
+ * Query plan (Ch. 3 Sec. "Query Plan Generation", commonsense variant of
+ * Sec. "GpSense"): the first query edge maximises f(a) + f(b) (lowest edge
+ * index on ties); its endpoint of larger f (lower id on ties) is expanded
+ * first; expanding a vertex adds its unreached neighbours to the spanning
+ * tree (parent edge = lowest-index edge between them); the next vertex to
+ * expand is the reached, unexpanded one with the most unreached neighbours
+ * (then larger f, then lower id), until every vertex is reached.
+ * visit[], init_order[]: -1 padded to OR_MAXQ... sized n by the caller.
+ */
+int oracle_plan(const oracle_graph *g, int32_t n, int32_t m, const int32_t *vlabel,
+                const int32_t *vpin, const int32_t *esrc, const int32_t *edst,
+                const int32_t *elabel, int32_t *visit, int32_t *parent, int32_t *parent_edge,
+                int32_t *init_order) {
+    if (!g || !query_ok(g->V, n, m, vpin, esrc, edst)) return OR_EINVAL;
+    st_query q;
+    st_query_init(&q, n, m, vlabel, vpin, esrc, edst, elabel);
+    int64_t fnum[OR_MAXQ], fden[OR_MAXQ];
+    for (int u = 0; u < n; u++) {
+        fnum[u] = q.deg[u];
+        fden[u] = st_freq(g, &q, u);
+        visit[u] = -1;
+        parent[u] = -1;
+        parent_edge[u] = -1;
+        init_order[u] = -1;
+    }
+    int nv = 0, ni = 0;
+    if (m == 0) {
+        visit[0] = 0;
+        init_order[0] = 0;
+        return OR_OK;
+    }
+    int best = 0;
+    for (int i = 1; i < m; i++) {
+        int a = esrc[best], b = edst[best], c = esrc[i], d = edst[i];
+        __int128 lhs = ((__int128)fnum[a] * fden[b] + (__int128)fnum[b] * fden[a]) *
+                       ((__int128)fden[c] * fden[d]);
+        __int128 rhs = ((__int128)fnum[c] * fden[d] + (__int128)fnum[d] * fden[c]) *
+                       ((__int128)fden[a] * fden[b]);
+        if (rhs > lhs) best = i;
+    }
+    int a = esrc[best], b = edst[best], root;
+    __int128 fa = (__int128)fnum[a] * fden[b], fb = (__int128)fnum[b] * fden[a];
+    root = fa > fb ? a : fb > fa ? b : (a < b ? a : b);
+    uint32_t reached = 1u << root, expanded = 0;
+    init_order[ni++] = root;
+    int u = root;
+    for (;;) {
+        expanded |= 1u << u;
+        visit[nv++] = u;
+        for (int x = 0; x < n; x++) {
+            if (!((q.nbr[u] >> x) & 1u) || ((reached >> x) & 1u)) continue;
+            reached |= 1u << x;
+            parent[x] = u;
+            for (int i = 0; i < m; i++)
+                if ((esrc[i] == u && edst[i] == x) || (esrc[i] == x && edst[i] == u)) {
+                    parent_edge[x] = i;
+                    break;
+                }
+            init_order[ni++] = x;
+        }
+        if (__builtin_popcount(reached) == n) break;
+        int nxt = -1, nn_best = 0;
+        for (int v = 0; v < n; v++) {
+            if (!((reached >> v) & 1u) || ((expanded >> v) & 1u)) continue;
+            int nn = __builtin_popcount(q.nbr[v] & ~reached);
+            if (nn == 0) continue;
+            int better = nxt < 0 || nn > nn_best;
+            if (!better && nn == nn_best) {
+                __int128 fv = (__int128)fnum[v] * fden[nxt], fx = (__int128)fnum[nxt] * fden[v];
+                better = fv > fx;
+            }
+            if (better) {
+                nxt = v;
+                nn_best = nn;
+            }
+        }
+        if (nxt < 0) return OR_EINVAL;
+        u = nxt;
+    }
+    return OR_OK;
+}
+
+/* Candidate predicate (Def. 3.3): type and pin, and at least as many data
+ * out-edges (in-edges) as the query vertex has distinct out-neighbours
+ * (in-neighbours). */
+static int st_pred(const oracle_graph *g, const st_query *q, int u, int32_t v) {
+    if (q->vpin[u] >= 0 && v != q->vpin[u]) return 0;
+    if (q->vlabel[u] >= 0 && g->vtype[v] != q->vlabel[u]) return 0;
+    if (g->out_off[v + 1] - g->out_off[v] < q->qout[u]) return 0;
+    if (g->in_off[v + 1] - g->in_off[v] < q->qin[u]) return 0;
+    return 1;
+}
+
+/* Does x have a neighbour y (out-neighbour for dir 0, in-neighbour for dir
+ * 1) joined by relation rho (-1: any) with ok[y]? ok == NULL: the predicate
+ * of query vertex w. When push != NULL, mark every such y instead and return
+ * whether any exists. */
+static int st_scan(const oracle_graph *g, const st_query *q, int32_t x, int dir, int32_t rho,
+                   const uint8_t *ok, int w, uint8_t *push) {
+    const int64_t *off = dir ? g->in_off : g->out_off;
+    const or_pair *arr = dir ? g->in : g->out;
+    int any = 0;
+    for (int64_t k = off[x]; k < off[x + 1]; k++) {
+        if (rho >= 0 && arr[k].rel != rho) continue;
+        int32_t y = arr[k].dst;
+        int good = ok ? ok[y] : st_pred(g, q, w, y);
+        if (!good) continue;
+        any = 1;
+        if (!push) return 1;
+        push[y] = 1;
+    }
+    return any;
+}
+
+/*
+ * Candidate sets after the filtering phase: the initialisation of Alg. 3.2
+ * along the plan's spanning tree (kernel_check for the first vertex of the
+ * visit order, then for each visited vertex u: prune the candidates u' of u
+ * lacking, for some tree neighbour w, a neighbour that is a candidate of w --
+ * w's set if already initialised, w's predicate otherwise -- and push the
+ * matching neighbours: an uninitialised w receives them as its set, an
+ * initialised one is intersected with them), followed by `rounds` rounds
+ * of refinement (Sec. "Candidate Nodes Refinement"; -1: until nothing is
+ * removed): every vertex of more than low_conn distinct neighbours, in
+ * reversed (or forward) order of initialisation, is pruned against every
+ * query edge to such a vertex.
+ * cand: out, [n][V] bytes (1 = candidate).
+ */
+int oracle_filter(const oracle_graph *g, int32_t n, int32_t m, const int32_t *vlabel,
+                  const int32_t *vpin, const int32_t *esrc, const int32_t *edst,
+                  const int32_t *elabel, int32_t rounds, int32_t reversed, int32_t low_conn,
+                  uint8_t *cand) {
+    int32_t visit[OR_MAXQ], parent[OR_MAXQ], pedge[OR_MAXQ], init[OR_MAXQ];
+    int rc = oracle_plan(g, n, m, vlabel, vpin, esrc, edst, elabel, visit, parent, pedge, init);
+    if (rc != OR_OK) return rc;
+    st_query q;
+    st_query_init(&q, n, m, vlabel, vpin, esrc, edst, elabel);
+    const int32_t V = g->V;
+    memset(cand, 0, (size_t)n * (size_t)V);
+    uint8_t *push = (uint8_t *)malloc((size_t)V);
+    uint8_t *alive = (uint8_t *)malloc((size_t)V);
+    if (!push || !alive) {
+        free(push);
+        free(alive);
+        return OR_ENOMEM;
+    }
+    int initialized[OR_MAXQ] = {0};
+    for (int oi = 0; oi < n && visit[oi] >= 0; oi++) {
+        const int u = visit[oi];
+        uint8_t *cu = cand + (size_t)u * V;
+        if (!initialized[u]) {
+            for (int32_t v = 0; v < V; v++) cu[v] = (uint8_t)st_pred(g, &q, u, v);
+            initialized[u] = 1;
+        }
+        /* tree neighbours: parent first, then children */
+        int tw[OR_MAXQ], te[OR_MAXQ], nt = 0;
+        if (parent[u] >= 0) {
+            tw[nt] = parent[u];
+            te[nt++] = pedge[u];
+        }
+        for (int x = 0; x < n; x++)
+            if (parent[x] == u) {
+                tw[nt] = x;
+                te[nt++] = pedge[x];
+            }
+        if (nt == 0) continue;
+        /* prune against the state at the start of the step */
+        for (int32_t v = 0; v < V; v++) {
+            alive[v] = cu[v];
+            if (!cu[v]) continue;
+            for (int t = 0; t < nt && alive[v]; t++) {
+                const int w = tw[t], e = te[t];
+                const int dir = esrc[e] == u ? 0 : 1;
+                alive[v] = (uint8_t)st_scan(g, &q, v, dir, elabel[e],
+                                            initialized[w] ? cand + (size_t)w * V : NULL, w, NULL);
+            }
+        }
+        for (int t = 0; t < nt; t++) {
+            const int w = tw[t], e = te[t];
+            const int dir = esrc[e] == u ? 0 : 1;
+            uint8_t *cw = cand + (size_t)w * V;
+            memset(push, 0, (size_t)V);
+            for (int32_t v = 0; v < V; v++)
+                if (alive[v])
+                    st_scan(g, &q, v, dir, elabel[e], initialized[w] ? cw : NULL, w, push);
+            if (initialized[w])
+                for (int32_t y = 0; y < V; y++) cw[y] &= push[y];
+            else
+                memcpy(cw, push, (size_t)V);
+        }
+        memcpy(cu, alive, (size_t)V);
+        for (int t = 0; t < nt; t++) initialized[tw[t]] = 1;
+    }
+    /* refinement */
+    int order[OR_MAXQ], no = 0;
+    for (int i = 0; i < n; i++) {
+        const int u = init[reversed ? n - 1 - i : i];
+        if (q.deg[u] > low_conn) order[no++] = u;
+    }
+    const int max_rounds = rounds < 0 ? 32 : rounds;
+    for (int r = 0; r < max_rounds; r++) {
+        int64_t removed = 0;
+        for (int oi = 0; oi < no; oi++) {
+            const int u = order[oi];
+            uint8_t *cu = cand + (size_t)u * V;
+            int ne = 0;
+            for (int e = 0; e < m; e++) {
+                const int w = esrc[e] == u ? edst[e] : edst[e] == u ? esrc[e] : -1;
+                if (w >= 0 && q.deg[w] > low_conn) ne++;
+            }
+            if (ne == 0) continue;
+            for (int32_t v = 0; v < V; v++) {
+                if (!cu[v]) continue;
+                int ok = 1;
+                for (int e = 0; e < m && ok; e++) {
+                    int w, dir;
+                    if (esrc[e] == u) {
+                        w = edst[e];
+                        dir = 0;
+                    } else if (edst[e] == u) {
+                        w = esrc[e];
+                        dir = 1;
+                    } else {
+                        continue;
+                    }
+                    if (q.deg[w] <= low_conn) continue;
+                    ok = st_scan(g, &q, v, dir, elabel[e], cand + (size_t)w * V, w, NULL);
+                }
+                if (!ok) {
+                    cu[v] = 0;
+                    removed++;
+                }
+            }
+        }
+        if (rounds < 0 && removed == 0) break;
+    }
+    free(push);
+    free(alive);
+    return OR_OK;
+}
+
+/* Candidate edges of every query edge (a, b, rho) given candidate sets:
+ * #{(x, y) : cand[a][x], cand[b][y], x != y, some data edge (x, y, r) with
+ * rho = -1 or r = rho} (Sec. "Joining Phase"). ec: out, [m]. */
+int oracle_edge_candidates(const oracle_graph *g, int32_t n, int32_t m, const int32_t *esrc,
+                           const int32_t *edst, const int32_t *elabel, const uint8_t *cand,
+                           int64_t *ec) {
+    if (!g) return OR_EINVAL;
+    const int32_t V = g->V;
+    for (int e = 0; e < m; e++) {
+        const int a = esrc[e], b = edst[e];
+        if (a < 0 || a >= n || b < 0 || b >= n) return OR_EINVAL;
+        int64_t c = 0;
+        for (int32_t x = 0; x < V; x++) {
+            if (!cand[(size_t)a * V + x]) continue;
+            int32_t prev = -1;
+            for (int64_t k = g->out_off[x]; k < g->out_off[x + 1]; k++) {
+                const int32_t y = g->out[k].dst;
+                if (elabel[e] >= 0 && g->out[k].rel != elabel[e]) continue;
+                if (y == prev) continue;
+                prev = y;
+                if (y != x && cand[(size_t)b * V + y]) c++;
+            }
+        }
+        ec[e] = c;
+    }
+    return OR_OK;
+}

@@ -56,7 +56,7 @@ class sgm_stats(ctypes.Structure):
                 ("ns_total", ctypes.c_int64), ("ns_filter", ctypes.c_int64),
                 ("ns_collect", ctypes.c_int64), ("ns_join", ctypes.c_int64),
                 ("ns_finish", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("path", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("path", ctypes.c_int32), ("fallback", ctypes.c_int32)]
 
 
 class sgm_result(ctypes.Structure):
@@ -98,6 +98,9 @@ EXPORTS = {
     "sgm_reset_kernel_stats": (ctypes.c_int, [ctypes.c_void_p]),
     "sgm_plan_query": (ctypes.c_int, [ctypes.POINTER(sgm_query), ctypes.c_int32, _i64p,
                                       ctypes.c_int32, _i32p, _i32p, _i32p, _i32p]),
+    "sgm_inspect_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query), _i64p,
+                                         ctypes.POINTER(_i32p), _i64p]),
+    "sgm_free_ids": (None, [_i32p]),
     "sgm_default_serve_options": (None, [ctypes.POINTER(sgm_serve_options)]),
     "sgm_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_serve_options),
                                          ctypes.POINTER(ctypes.c_void_p)]),
@@ -238,7 +241,7 @@ def stats_dict(st: sgm_stats, n: int, m: int) -> dict:
                 peak_rows=st.peak_rows, peak_bytes=st.peak_bytes, n_chunks=st.n_chunks,
                 n_launches=st.n_launches, ns_total=st.ns_total, ns_filter=st.ns_filter,
                 ns_collect=st.ns_collect, ns_join=st.ns_join, ns_finish=st.ns_finish,
-                device_bytes=st.device_bytes, path=st.path)
+                device_bytes=st.device_bytes, path=st.path, fallback=st.fallback)
 
 
 class Graph:
@@ -313,6 +316,28 @@ class Graph:
                 res.append(k if count_only else rows)
             sgm_free_result(r)
         return res
+
+    def inspect_query(self, q):
+        """(candidate lists per query vertex, candidate-edge counts) after the
+        filtering phase, through sgm_inspect_query."""
+        sq, keep = _make_query(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel)
+        counts = np.zeros(SGM_MAX_QV, np.int64)
+        ec = np.zeros(SGM_MAX_QE, np.int64)
+        ids = _i32p()
+        rc = lib().sgm_inspect_query(self._h, ctypes.byref(sq), counts.ctypes.data_as(_i64p),
+                                     ctypes.byref(ids), ec.ctypes.data_as(_i64p))
+        if rc != SGM_OK:
+            raise SGMError(rc, "sgm_inspect_query")
+        total = int(counts.sum())
+        flat = np.empty(total, np.int32)
+        if total:
+            ctypes.memmove(flat.ctypes.data, ids, total * 4)
+        lib().sgm_free_ids(ids)
+        lists, off = [], 0
+        for u in range(q.n):
+            lists.append(flat[off:off + counts[u]])
+            off += counts[u]
+        return lists, ec[:len(keep[2][0])]
 
     def kernel_stats(self):
         out = {}

@@ -906,6 +906,51 @@ struct Query {
         return done(R, t0);
     }
 
+    // Candidate sets after the filtering phase and candidate-edge counts.
+    int inspect(int64_t *counts, int32_t **ids, int64_t *ec_out) {
+        const int n = qi.n;
+        int rc = make_plan(qi, g->V, g->type_freq.data(), g->n_types, &pl);
+        if (rc) return rc;
+        rc = filter();
+        if (rc) return rc;
+        HIPX(hipMemcpyAsync(g->h_cnt->cand_count, g->d_cnt->cand_count, sizeof(int32_t) * n,
+                            hipMemcpyDeviceToHost, st()));
+        sync(g);
+        int64_t total = 0;
+        bool empty = false;
+        for (int u = 0; u < n; ++u) {
+            ccount[u] = g->h_cnt->cand_count[u];
+            counts[u] = ccount[u];
+            total += ccount[u];
+            empty |= ccount[u] == 0;
+        }
+        int32_t *h = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1));
+        if (!h) throw std::bad_alloc();
+        int64_t off = 0;
+        for (int u = 0; u < n; ++u) {
+            if (ccount[u])
+                HIPX(hipMemcpyAsync(h + off, list(u), sizeof(int32_t) * ccount[u],
+                                    hipMemcpyDeviceToHost, st()));
+            off += ccount[u];
+        }
+        sync(g);
+        *ids = h;
+        if (!empty && qi.m > 0) {
+            for (int e = 0; e < qi.m; ++e) {
+                ECTab &t = ec[e];
+                t.key = qi.esrc[e];
+                t.other = qi.edst[e];
+                t.dir = 0;
+                ec_count(t, e);
+            }
+            HIPX(hipMemcpyAsync(g->h_cnt->ec_total, g->d_cnt->ec_total,
+                                sizeof(unsigned long long) * qi.m, hipMemcpyDeviceToHost, st()));
+            sync(g);
+            for (int e = 0; e < qi.m; ++e) ec_out[e] = (int64_t)g->h_cnt->ec_total[e];
+        }
+        return SGM_OK;
+    }
+
     int done(int64_t R, int64_t t0) {
         res->n_rows = R;
         // rows is non-NULL for every successful SORTED result, also when empty
@@ -923,10 +968,17 @@ struct Query {
 // ---------------------------------------------------------------------------
 
 constexpr int kNarrowMaxSlots = 512;                 // 2 workgroups per CU
-constexpr int64_t kNarrowSlabBytes = 8ll << 20;      // per slot
+constexpr int64_t kNarrowSlabMin = 8ll << 20;        // per slot, small graphs
+constexpr int64_t kNarrowSlabMax = 32ll << 20;       // per slot, large graphs
 constexpr int32_t kNarrowListCap = 1 << 16;          // per query vertex
 constexpr int kNarrowQueryCap = 4096;                // queries per launch
-constexpr int64_t kNarrowOutCap = 64ll << 20;        // int32 elements (256 MB)
+constexpr int64_t kNarrowOutCap = 256ll << 20;       // int32 elements (1 GB) per context
+
+// slot memory for edge tables, join tables and sort buffers: 8 bytes per
+// data vertex, within [8 MB, 32 MB]
+int64_t narrow_slab_bytes(const sgm_graph *g) {
+    return std::min<int64_t>(kNarrowSlabMax, std::max<int64_t>(kNarrowSlabMin, 8ll * g->V));
+}
 
 template <class T>
 void dev_free(T *&p) {
@@ -963,7 +1015,7 @@ void narrow_free(NarrowCtx &nw) {
 void narrow_reserve(sgm_graph *g, NarrowCtx &nw, int slots, int nq, int nroot) {
     if (nw.lcap == 0) {
         nw.lcap = std::min<int32_t>(g->V, kNarrowListCap);
-        nw.slab_bytes = kNarrowSlabBytes;
+        nw.slab_bytes = narrow_slab_bytes(g);
         HIPX(hipMalloc(&nw.d_ctr, sizeof(unsigned long long) * 2));
         HIPX(hipHostMalloc(&nw.h_ctr, sizeof(unsigned long long) * 2, hipHostMallocDefault));
         nw.out_cap = kNarrowOutCap;
@@ -1014,7 +1066,7 @@ void narrow_reserve(sgm_graph *g, NarrowCtx &nw, int slots, int nq, int nroot) {
 int64_t narrow_slot_bytes(const sgm_graph *g) {
     const int64_t lcap = std::min<int32_t>(g->V, kNarrowListCap);
     return (int64_t)(SGM_MAX_QV + 1) * g->nwords * 8 + (int64_t)SGM_MAX_QV * lcap * 4 +
-           kNarrowSlabBytes;
+           narrow_slab_bytes(g);
 }
 
 // Pack one validated query and its plan; false if it exceeds the packed
@@ -1072,7 +1124,8 @@ struct NarrowJob {
 // asynchronously on nw.stream; queries that do not fit a descriptor go to
 // `wide`. Returns false when nothing was launched.
 bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, const int *which,
-                   int count, NarrowJob &job, std::vector<int> &wide, bool profiled) {
+                   int count, NarrowJob &job, std::vector<int> &wide,
+                   std::vector<sgm_result *> &res, bool profiled) {
     job.t0 = now_ns();
     job.packed.clear();
     job.plans.clear();
@@ -1088,6 +1141,7 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
             job.plans.push_back(pl);
         } else {
             wide.push_back(which[i]);
+            res[which[i]]->stats.fallback = 16;
         }
     }
     job.nroot = nroot;
@@ -1165,6 +1219,7 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         const int qi_idx = job.packed[i];
         if (r.status != SGM_OK) {
             wide.push_back(qi_idx);
+            res[qi_idx]->stats.fallback = r.status == kOutFull ? 8 : r.reason;
             continue;
         }
         sgm_result *out = res[qi_idx];
@@ -1211,7 +1266,7 @@ void narrow_batch(sgm_graph *g, const std::vector<QInfo> &qis, const std::vector
     for (size_t base = 0; base < which.size(); base += kNarrowQueryCap) {
         const int count = (int)std::min<size_t>(kNarrowQueryCap, which.size() - base);
         NarrowJob job;
-        if (narrow_launch(g, g->nw, qis, which.data() + base, count, job, wide, true))
+        if (narrow_launch(g, g->nw, qis, which.data() + base, count, job, wide, res, true))
             narrow_collect(g, g->nw, job, qis, flags, res, wide, true);
     }
 }
@@ -1266,8 +1321,10 @@ int run_queries(sgm_graph *g, const sgm_query *qs, int n, uint32_t flags,
             res[i]->status = SGM_EUNSUPPORTED;
             continue;
         }
+        const int32_t why = res[i]->stats.fallback;
         std::memset(&res[i]->stats, 0, sizeof(sgm_stats));
         res[i]->stats.path = SGM_PATH_WIDE;
+        res[i]->stats.fallback = why;
         res[i]->status = wide_locked(g, qis[i], flags, res[i]);
     }
     return SGM_OK;
@@ -1472,6 +1529,39 @@ int sgm_match_batch(sgm_graph *g, const sgm_query *qs, int32_t n, uint32_t flags
     return SGM_OK;
 }
 
+int sgm_inspect_query(sgm_graph *g, const sgm_query *q, int64_t *counts, int32_t **ids,
+                      int64_t *ec) {
+    if (!ids) return SGM_EINVAL;
+    *ids = nullptr;
+    if (!g || !q || !counts || !ec) return SGM_EINVAL;
+    QInfo qi;
+    int rc = check_query(q, g->V, &qi);
+    if (rc) return rc;
+    for (int u = 0; u < SGM_MAX_QV; ++u) counts[u] = 0;
+    for (int e = 0; e < SGM_MAX_QE; ++e) ec[e] = 0;
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (hipSetDevice(g->device) != hipSuccess) return SGM_EDEVICE;
+    sgm_result scratch_res{};
+    try {
+        Query Q(g, qi, &scratch_res, SGM_COUNT_ONLY);
+        rc = Q.inspect(counts, ids, ec);
+    } catch (const DeviceError &e) {
+        rc = e.code;
+        (void)hipStreamSynchronize(g->stream);
+        (void)hipGetLastError();
+        g->pending.clear();
+    } catch (const std::bad_alloc &) {
+        rc = SGM_ENOMEM;
+    }
+    if (rc != SGM_OK) {
+        std::free(*ids);
+        *ids = nullptr;
+    }
+    return rc;
+}
+
+void sgm_free_ids(int32_t *ids) { std::free(ids); }
+
 void sgm_free_result(sgm_result *r) {
     if (!r) return;
     std::free(r->rows);
@@ -1607,7 +1697,7 @@ void serve_dispatch(sgm_server *S) {
             if (b->res[i]->status == SGM_OK) b->which.push_back((int)i);
         try {
             b->launched = narrow_launch(g, S->ctx[ci], b->qis, b->which.data(),
-                                        (int)b->which.size(), b->job, b->wide, false);
+                                        (int)b->which.size(), b->job, b->wide, b->res, false);
         } catch (const DeviceError &e) {
             for (auto *r : b->res) r->status = e.code;
             b->which.clear();
@@ -1647,8 +1737,10 @@ void serve_complete(sgm_server *S) {
         // queries that outgrew their slot: the multi-kernel path
         for (int i : b->wide) {
             std::lock_guard<std::mutex> gl(g->mu);
+            const int32_t why = b->res[i]->stats.fallback;
             std::memset(&b->res[i]->stats, 0, sizeof(sgm_stats));
             b->res[i]->stats.path = SGM_PATH_WIDE;
+            b->res[i]->stats.fallback = why;
             b->res[i]->status = wide_locked(g, b->qis[i], b->flags, b->res[i]);
         }
         const int64_t t_done = now_ns();

@@ -46,7 +46,9 @@ struct NQuery {
 // Per-query outcome.
 struct NResult {
     int32_t status;        // SGM_OK, or kNeedWide / kOutFull (rerun on the multi-kernel path)
+    int32_t reason;        // kWhy* for kNeedWide
     int32_t n_cols;
+    int32_t pad;
     int64_t n_rows;
     int64_t offset;        // first int32 of the rows in the output arena
     int64_t cand[SGM_MAX_QV];
@@ -59,6 +61,10 @@ struct NResult {
 
 constexpr int32_t kNeedWide = 1;  // a capacity of the per-query slot was exceeded
 constexpr int32_t kOutFull = 2;   // the shared output arena was full
+// why a query left the persistent kernel
+constexpr int32_t kWhyList = 1;   // a candidate list outgrew its slot capacity
+constexpr int32_t kWhySlab = 2;   // edge tables / join tables / sort buffers outgrew the slab
+constexpr int32_t kWhyKey = 4;    // the ordering key would need more than 64 bits
 
 struct NArgs {
     DevGraph g;

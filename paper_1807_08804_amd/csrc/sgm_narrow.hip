@@ -28,7 +28,8 @@ constexpr int NT = kNarrowThreads;
 constexpr int NW = NT / 64;
 constexpr int kBigCap = 256;
 constexpr int kListSortCap = 8192;    // int32 entries sorted in LDS
-constexpr int kRowSortCap = 2048;     // final rows sorted in LDS (u64 key + int32 index)
+constexpr int kRowSortCap = 2048;     // final rows sorted in LDS (u64 key + int32 index);
+                                      // more rows use radix passes in the slab
 
 struct Smem {
     int64_t sh[NW + 1];
@@ -54,6 +55,7 @@ struct Smem {
     int32_t empty;
     // per-query outcome, written to global memory by thread 0 at the end
     int32_t status;
+    int32_t reason;
     int32_t cand[SGM_MAX_QV];
     int32_t bitsn[SGM_MAX_QV];
     int64_t level_rows[SGM_MAX_QV];
@@ -118,7 +120,7 @@ __device__ __forceinline__ char *slab_alloc(Ctx &c, int64_t bytes) {
     __syncthreads();
     if (threadIdx.x == 0) {
         if (p) c.s->slab_used = off + bytes;
-        else c.s->abort_ = 1;
+        else c.s->abort_ = kWhySlab;
     }
     __syncthreads();
     return p;
@@ -133,7 +135,7 @@ __device__ __forceinline__ void push_bit(Ctx &c, uint64_t *tb, int32_t *tl, int 
     if (tl && !(old & m)) {
         const int32_t p = atomicAdd(&c.s->cnt[v], 1);
         if (p < c.lcap) tl[p] = x;
-        else c.s->abort_ = 1;
+        else c.s->abort_ = kWhyList;
     }
 }
 
@@ -179,7 +181,7 @@ __device__ __forceinline__ void list_from_bits(Ctx &c, int u, const uint64_t *sr
         int64_t tot;
         const int64_t ex = block_excl_scan(__popcll(word), c.s->sh, &tot);
         if (out + tot > c.lcap) {
-            if (threadIdx.x == 0) c.s->abort_ = 1;
+            if (threadIdx.x == 0) c.s->abort_ = kWhyList;
             break;  // uniform: tot and out are block-uniform
         }
         int64_t p = out + ex;
@@ -626,6 +628,72 @@ __device__ __forceinline__ bool ec_contains(const Ctx &c, int e, int32_t keyval,
 }
 
 // ---------------------------------------------------------------------------
+// final ordering helpers
+// ---------------------------------------------------------------------------
+
+// Sort key of a row: the ranks of its values within their (sorted) candidate
+// lists, concatenated in query-vertex order (s.bitsn bits each).
+__device__ __forceinline__ uint64_t row_key(const Ctx &c, const int32_t *row) {
+    uint64_t key = 0;
+    for (int u = 0; u < c.Q->n; ++u) {
+        const int32_t rk = lower_bound_i32(c.L(u), 0, c.s->cnt[u], row[c.s->jpos[u]]);
+        key = (key << c.s->bitsn[u]) | (uint64_t)rk;
+    }
+    return key;
+}
+
+// One stable 8-bit LSD pass of the whole workgroup: histogram, scan, then
+// chunks of NT elements placed by wave-level digit matching.
+__device__ __forceinline__ void wg_radix_pass(Ctx &c, const uint64_t *kin, const int32_t *iin,
+                                              uint64_t *kout, int32_t *iout, int64_t n,
+                                              int shift) {
+    unsigned long long *base = (unsigned long long *)c.dyn;  // [256]
+    int32_t *wc = (int32_t *)(c.dyn + 256 * 8);              // [NW][256]
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    for (int i = threadIdx.x; i < 256; i += NT) base[i] = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += NT)
+        atomicAdd(&base[(kin[i] >> shift) & 255], 1ull);
+    __syncthreads();
+    const int64_t v = threadIdx.x < 256 ? (int64_t)base[threadIdx.x] : 0;
+    int64_t tot;
+    const int64_t ex = block_excl_scan(v, c.s->sh, &tot);
+    if (threadIdx.x < 256) base[threadIdx.x] = (unsigned long long)ex;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < n; c0 += NT) {
+        for (int i = threadIdx.x; i < NW * 256; i += NT) wc[i] = 0;
+        __syncthreads();
+        const int64_t i = c0 + threadIdx.x;
+        const bool valid = i < n;
+        const uint64_t kv = valid ? kin[i] : 0ull;
+        const int d = (int)((kv >> shift) & 255);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t m = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? m : ~m;
+        }
+        const int rk = __popcll(peers & lanemask_lt(lane));
+        if (valid && rk == 0) wc[wid * 256 + d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int64_t p = (int64_t)base[d] + rk;
+            for (int w = 0; w < wid; ++w) p += wc[w * 256 + d];
+            kout[p] = kv;
+            iout[p] = iin[i];
+        }
+        __syncthreads();
+        if (threadIdx.x < 256) {
+            int64_t add = 0;
+            for (int w = 0; w < NW; ++w) add += wc[w * 256 + threadIdx.x];
+            base[threadIdx.x] += (unsigned long long)add;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // one query
 // ---------------------------------------------------------------------------
 
@@ -666,6 +734,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         s.slab_used = 0;
         s.empty = 0;
         s.status = SGM_OK;
+        s.reason = 0;
         s.nrows = 0;
         s.offset = 0;
         s.bytes = 0;
@@ -703,7 +772,10 @@ __device__ __forceinline__ void run_query(Ctx &c) {
     mark(c, 1);
     if (aborted(c)) {
         clear_slot(c, true);
-        if (threadIdx.x == 0) s.status = kNeedWide;
+        if (threadIdx.x == 0) {
+            s.status = kNeedWide;
+            s.reason = s.abort_;
+        }
         return;
     }
     if (threadIdx.x == 0)
@@ -762,7 +834,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                     const int64_t cap = left / (4 * (k + 1));
                     int32_t *out = cap > 0 ? (int32_t *)slab_alloc(c, cap * 4 * (k + 1)) : nullptr;
                     if (!out) {
-                        if (threadIdx.x == 0) s.abort_ = 1;
+                        if (threadIdx.x == 0) s.abort_ = kWhySlab;
                         __syncthreads();
                         break;
                     }
@@ -826,7 +898,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                                     for (int cc = 0; cc < k; ++cc) dst[cc] = row[cc];
                                     dst[k] = x;
                                 } else {
-                                    s.abort_ = 1;
+                                    s.abort_ = kWhySlab;
                                 }
                             }
                         }
@@ -853,7 +925,10 @@ __device__ __forceinline__ void run_query(Ctx &c) {
     mark(c, 3);
     if (aborted(c)) {
         clear_slot(c, true);
-        if (threadIdx.x == 0) s.status = kNeedWide;
+        if (threadIdx.x == 0) {
+            s.status = kNeedWide;
+            s.reason = s.abort_;
+        }
         return;
     }
     if (threadIdx.x == 0) s.nrows = rows;
@@ -871,47 +946,77 @@ __device__ __forceinline__ void run_query(Ctx &c) {
             s.ctr = tb;
         }
         __syncthreads();
-        if (s.ctr > 64 || rows > kRowSortCap) {
+        if (s.ctr > 64) {
             clear_slot(c, false);
-            if (threadIdx.x == 0) s.status = kNeedWide;
+            if (threadIdx.x == 0) {
+                s.status = kNeedWide;
+                s.reason = kWhyKey;
+            }
             return;
         }
-        uint64_t *keys = (uint64_t *)c.dyn;
-        int32_t *idx = (int32_t *)(c.dyn + sizeof(uint64_t) * kRowSortCap);
+        const int tb = s.ctr;
         const int k = n;
-        int32_t N = 1;
-        while (N < rows) N <<= 1;
-        for (int32_t r = threadIdx.x; r < N; r += NT) {
-            uint64_t key = ~0ull;
-            if (r < rows) {
-                key = 0;
-                const int32_t *row = table + (int64_t)r * k;
-                for (int u = 0; u < n; ++u) {
-                    const int32_t rk = lower_bound_i32(c.L(u), 0, s.cnt[u], row[s.jpos[u]]);
-                    key = (key << s.bitsn[u]) | (uint64_t)rk;
-                }
+        const int32_t *idx;
+        if (rows <= kRowSortCap) {
+            // bitonic network in LDS
+            uint64_t *keys = (uint64_t *)c.dyn;
+            int32_t *ix = (int32_t *)(c.dyn + sizeof(uint64_t) * kRowSortCap);
+            int32_t N = 1;
+            while (N < rows) N <<= 1;
+            for (int32_t r = threadIdx.x; r < N; r += NT) {
+                keys[r] = r < rows ? row_key(c, table + (int64_t)r * k) : ~0ull;
+                ix[r] = r;
             }
-            keys[r] = key;
-            idx[r] = r;
-        }
-        __syncthreads();
-        for (int32_t size = 2; size <= N; size <<= 1) {
-            for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int32_t i = threadIdx.x; i < N / 2; i += NT) {
-                    const int32_t lo = 2 * i - (i & (stride - 1));
-                    const int32_t hi = lo + stride;
-                    const bool up = (lo & size) == 0;
-                    const uint64_t x = keys[lo], y = keys[hi];
-                    if ((x > y) == up) {
-                        keys[lo] = y;
-                        keys[hi] = x;
-                        const int32_t t = idx[lo];
-                        idx[lo] = idx[hi];
-                        idx[hi] = t;
+            __syncthreads();
+            for (int32_t size = 2; size <= N; size <<= 1) {
+                for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                    for (int32_t i = threadIdx.x; i < N / 2; i += NT) {
+                        const int32_t lo = 2 * i - (i & (stride - 1));
+                        const int32_t hi = lo + stride;
+                        const bool up = (lo & size) == 0;
+                        const uint64_t x = keys[lo], y = keys[hi];
+                        if ((x > y) == up) {
+                            keys[lo] = y;
+                            keys[hi] = x;
+                            const int32_t t = ix[lo];
+                            ix[lo] = ix[hi];
+                            ix[hi] = t;
+                        }
                     }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
+            idx = ix;
+        } else {
+            // LSD radix on (key, row) pairs in the slab, 8 bits per pass
+            uint64_t *ka = (uint64_t *)slab_alloc(c, 8 * rows);
+            uint64_t *kb = (uint64_t *)slab_alloc(c, 8 * rows);
+            int32_t *ia = (int32_t *)slab_alloc(c, 4 * rows);
+            int32_t *ib = (int32_t *)slab_alloc(c, 4 * rows);
+            if (!ka || !kb || !ia || !ib) {
+                clear_slot(c, false);
+                if (threadIdx.x == 0) {
+                    s.status = kNeedWide;
+                    s.reason = kWhySlab;
+                }
+                return;
+            }
+            for (int64_t r = threadIdx.x; r < rows; r += NT) {
+                ka[r] = row_key(c, table + r * k);
+                ia[r] = (int32_t)r;
+            }
+            __syncthreads();
+            for (int sh = 0; sh < tb; sh += 8) {
+                wg_radix_pass(c, ka, ia, kb, ib, rows, sh);
+                uint64_t *tk = ka;
+                ka = kb;
+                kb = tk;
+                int32_t *ti = ia;
+                ia = ib;
+                ib = ti;
+            }
+            if (threadIdx.x == 0) add_bytes(c, 24ull * rows * ((tb + 7) / 8));
+            idx = ia;
         }
         if (threadIdx.x == 0) {
             const unsigned long long need = (unsigned long long)rows * n;
@@ -956,6 +1061,7 @@ __global__ __launch_bounds__(NT) void k_narrow(NArgs a) {
         __syncthreads();
         if (threadIdx.x == 0) {
             R.status = s.status;
+            R.reason = s.reason;
             R.n_cols = Q.n;
             R.n_rows = s.status == SGM_OK ? s.nrows : 0;
             R.offset = s.offset;

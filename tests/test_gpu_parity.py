@@ -139,11 +139,26 @@ def any_query(n, edges, vlabel=None, vpin=None):
     ("star3-typed", any_query(4, [(1, 0, -1), (1, 2, -1), (1, 3, -1)], vlabel=[-1, -1, 3, 3])),
     ("square", any_query(4, [(0, 1, -1), (1, 2, -1), (3, 2, -1), (0, 3, -1)])),
 ])
-def test_tiny_large_outputs(name, q, g_tiny, oracle_tiny):
-    """Unlabelled queries with thousands of rows: multi-tile joins, the
-    radix-sorted final ordering and column permutations."""
-    say(f"case: tiny large-output {name}")
-    same(g_tiny.match_query(q), oracle_tiny.match_query(q))
+@pytest.mark.parametrize("path", PATHS)
+def test_tiny_large_outputs(name, q, path, tiny_kg, oracle_tiny):
+    """Unlabelled queries with thousands of rows: multi-tile joins, radix
+    ordering (multi-kernel and in-kernel) and column permutations."""
+    say(f"case: tiny large-output {name} path={path}")
+    g = P.Graph.from_kg(tiny_kg, path=path)
+    want = oracle_tiny.match_query(q)
+    try:
+        got, st = g.match_query(q, with_stats=True)
+    except P.SGMError as e:
+        # only a query that outgrows a persistent-kernel slot may be refused
+        assert path == P.SGM_PATH_NARROW and e.code == P.SGM_EUNSUPPORTED
+        ga = P.Graph.from_kg(tiny_kg)
+        got, st = ga.match_query(q, with_stats=True)
+        assert st["path"] == P.SGM_PATH_WIDE and st["fallback"] in (1, 2, 4, 8, 16)
+        ga.close()
+    same(got, want)
+    if path == P.SGM_PATH_NARROW and st["path"] == P.SGM_PATH_NARROW:
+        assert st["fallback"] == 0
+    g.close()
 
 
 def test_medium_large_output(g_medium, oracle_medium):
@@ -235,3 +250,62 @@ def test_repeat_is_deterministic(g_medium, medium_queries):
     b, sb = g_medium.match_query(q, with_stats=True)
     same(a, b)
     assert sa["cand"] == sb["cand"] and sa["level_rows"] == sb["level_rows"]
+
+
+# --------------------------------------------------------------------------
+# stage parity: candidate sets and candidate-edge counts
+# --------------------------------------------------------------------------
+
+def stage_check(g, og, q, opts):
+    lists, ec = g.inspect_query(q)
+    cand = og.filter(q, rounds=opts.get("refine_rounds", 1),
+                     reversed=opts.get("refine_reversed", 1),
+                     low_conn=opts.get("low_conn_degree", 1))
+    for u in range(q.n):
+        assert np.array_equal(lists[u], np.nonzero(cand[u])[0].astype(np.int32)), (q, u)
+    if q.m and all(len(x) for x in lists):
+        assert ec.tolist() == og.edge_candidates(q, cand).tolist()
+    return cand
+
+
+STAGE_OPTS = [dict(), dict(refine_rounds=0), dict(refine_rounds=-1), dict(refine_reversed=0),
+              dict(low_conn_degree=0)]
+
+
+@pytest.mark.parametrize("opts", STAGE_OPTS)
+@pytest.mark.parametrize("seed", range(6))
+def test_stage_parity_micro(seed, opts):
+    rng = np.random.default_rng(900 + seed)
+    V = int(rng.integers(3, 40))
+    mg = random_graph(rng, V, int(rng.integers(V, 4 * V)), n_types=3, n_rels=3)
+    rp, col, rel, typ = mg.csr()
+    say(f"case: stage micro seed={seed} opts={opts}")
+    g = P.Graph(rp, col, rel, typ, **opts)
+    og = oracle.Graph(V, mg.src, mg.dst, mg.rel, mg.vtype)
+    for _ in range(8):
+        q = random_query(rng, int(rng.integers(1, 7)), 3, 3, V, p_pin=0.15, extra=3)
+        stage_check(g, og, q, opts)
+    g.close()
+
+
+@pytest.mark.parametrize("opts", STAGE_OPTS)
+def test_stage_parity_medium(opts, medium_kg, oracle_medium, medium_queries):
+    """Candidate sets of every query vertex after filtering, and candidate
+    edge counts, equal the oracle's stage functions; the persistent kernel's
+    per-vertex counts and edge counts agree too."""
+    say(f"case: stage medium opts={opts}")
+    g = P.Graph.from_kg(medium_kg, **opts)
+    gn = P.Graph.from_kg(medium_kg, path=P.SGM_PATH_NARROW, **opts)
+    for i, q in enumerate(medium_queries[:40]):
+        cand = stage_check(g, oracle_medium, q, opts)
+        try:
+            _, st = gn.match_query(q, with_stats=True)
+        except P.SGMError as e:
+            assert e.code == P.SGM_EUNSUPPORTED
+            continue
+        counts = cand.sum(axis=1).tolist()
+        if all(counts):
+            assert st["cand"] == counts, (i, st["cand"], counts)
+            assert st["ec"] == oracle_medium.edge_candidates(q, cand).tolist()
+    g.close()
+    gn.close()
