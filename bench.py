@@ -74,21 +74,27 @@ def served_leg(P, kggen, g, queries, rates, arrivals):
 
 
 def cpu_leg(kg, queries, seconds):
+    """The oracle on a bounded sample of the same workload: the queries in
+    order, cycling, until `seconds` of wall time have passed (queries that
+    hit the oracle's work budget are counted as skipped, not as done)."""
     import oracle
     og = oracle.graph_from_kg(kg)
     cores = os.cpu_count() or 1
     cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
-    done, skipped, t = 0, 0, time.perf_counter()
-    while done + skipped < len(queries) and time.perf_counter() - t < seconds:
+    done, skipped, i, t = 0, 0, 0, time.perf_counter()
+    while time.perf_counter() - t < seconds:
         try:
-            og.match_query(queries[done + skipped], nthreads=cores, max_steps=200_000_000)
+            og.match_query(queries[i % len(queries)], nthreads=cores, max_steps=200_000_000)
             done += 1
         except oracle.OracleError:
             skipped += 1
+        i += 1
     el = time.perf_counter() - t
+    passes = f"{i / len(queries):.1f} passes over" if i >= len(queries) else f"the first {i} of"
     return {"value": round(done / el, 3), "unit": "queries/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {done + skipped} of the {len(queries)} queries one at a time "
-                      f"({skipped} stopped by the oracle's work budget), {el:.1f}s wall"}
+            "sample": f"{passes} the {len(queries)} queries one at a time, {i} calls "
+                      f"({skipped} stopped by the oracle's work budget of 2e8 candidate tests), "
+                      f"{el:.1f}s wall"}
 
 
 def bench_medium(args, P, kggen):

@@ -58,7 +58,9 @@ typedef struct {
     int64_t join_budget_bytes; /* > 0: bound on one join level's output table;
                                   larger levels are processed in chunks */
     int32_t profile;           /* 1: time every kernel launch with HIP events
-                                  (sgm_kernel_stats) */
+                                  (sgm_kernel_stats); 2: in addition record the
+                                  persistent kernel's per-step event trace
+                                  (sgm_trace_events) */
     int32_t path;              /* SGM_PATH_AUTO (default), SGM_PATH_WIDE or
                                   SGM_PATH_NARROW (see below) */
     int32_t reserved[6];
@@ -66,10 +68,12 @@ typedef struct {
 
 /* Execution paths. NARROW: one persistent kernel in which each workgroup
  * runs whole queries (used for batches and for single queries that fit a
- * workgroup's slot); WIDE: one multi-kernel pipeline per query using the
- * whole GPU for each phase. AUTO runs NARROW first and reruns on WIDE every
- * query that outgrows a slot; NARROW alone fails such a query with
- * SGM_EUNSUPPORTED. Results are identical on every path. */
+ * workgroup's slot); a query that outgrows its slot (candidate lists, slot
+ * memory, output arena) runs again in one of a few large slots. WIDE: one
+ * multi-kernel pipeline per query using the whole GPU for each phase. AUTO
+ * runs NARROW first and reruns on WIDE every query that fits no slot;
+ * NARROW alone fails such a query with SGM_EUNSUPPORTED. Results are
+ * identical on every path. */
 #define SGM_PATH_AUTO 0
 #define SGM_PATH_WIDE 1
 #define SGM_PATH_NARROW 2
@@ -110,10 +114,12 @@ typedef struct {
                                       persistent kernel */
     int64_t device_bytes;          /* persistent kernel: algorithmic bytes moved */
     int32_t path;                  /* SGM_PATH_WIDE or SGM_PATH_NARROW: where it ran */
-    int32_t fallback;              /* why a query left the persistent kernel for the
-                                      multi-kernel path: 1 candidate list capacity,
-                                      2 slot memory, 4 ordering key > 64 bits,
-                                      8 output arena full, 16 plan descriptor size */
+    int32_t fallback;              /* why a query outgrew a regular persistent-kernel
+                                      slot: 1 candidate list capacity, 2 slot
+                                      memory, 4 ordering key > 64 bits, 8 output
+                                      arena full, 16 plan descriptor size. With
+                                      path NARROW it then ran in a large slot;
+                                      with path WIDE on the multi-kernel path */
 } sgm_stats;
 
 typedef struct {
@@ -197,6 +203,30 @@ void sgm_free_graph(sgm_graph *g);
 const char *sgm_strerror(int code);
 /* Text of the last SGM_EDEVICE / SGM_EINVAL detail on this thread. */
 const char *sgm_last_error(void);
+
+/*
+ * Step trace of the persistent kernel (options.profile = 2). Events of query
+ * i (its index in the last sgm_match_query / sgm_match_batch call on this
+ * graph), oldest first; each is (device wall-clock tick << 8) | SGM_EV_*
+ * code, written by the workgroup that ran the query when the step ended.
+ * Copies at most cap events to out and returns the number recorded (0 for a
+ * query that did not run on the persistent kernel), or a negative SGM_E*
+ * code. *ns_per_tick (may be NULL) receives the clock period. Not for
+ * queries of a server; not thread-safe against concurrent match calls on the
+ * same graph.
+ */
+#define SGM_TRACE_CAP 256
+#define SGM_EV_START 1     /* query taken from the work queue */
+#define SGM_EV_ROOT 2      /* root candidates ready (Alg. 3.2 initialisation) */
+#define SGM_EV_EXPLORE 3   /* one kernel_explore step along the spanning tree */
+#define SGM_EV_REFINE 4    /* one refinement step */
+#define SGM_EV_LISTS 5     /* candidate lists sorted */
+#define SGM_EV_EDGES 6     /* one candidate-edge table built */
+#define SGM_EV_ORDER 7     /* join order chosen */
+#define SGM_EV_LEVEL 8     /* one join level written */
+#define SGM_EV_SORT 9      /* final rows ordered */
+#define SGM_EV_OUTPUT 10   /* rows copied to the output arena */
+int sgm_trace_events(sgm_graph *g, int32_t i, int64_t *out, int32_t cap, double *ns_per_tick);
 
 /* Graph properties after load (deduplicated edge count etc.). */
 int sgm_graph_info(const sgm_graph *g, int32_t *n_vertices, int64_t *n_edges,

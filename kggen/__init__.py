@@ -426,6 +426,29 @@ def draw_cyclic_dense(g: KG, rng, n: int, n_cycles: int, n_pins: int = 0,
 # acceptance bound H(q)
 # --------------------------------------------------------------------------
 
+def _rel_matrix(g: KG, lab: int, fwd: bool):
+    """Sparse 0/1 matrix M with (M h)(v) = sum of h(x) over the data edges
+    v -> x (fwd) or x -> v (not fwd) with relation lab (-1: any), cached on
+    the graph."""
+    import scipy.sparse as sp
+    cache = g.__dict__.setdefault("_relmat", {})
+    key = (lab, fwd)
+    if key not in cache:
+        ptr, nb, rl = (g.row_ptr, g.col, g.rel) if fwd else (g.in_ptr, g.in_col, g.in_rel)
+        ptr = np.asarray(ptr, np.int64)
+        if lab >= 0:
+            keep = rl == lab
+            rows = np.repeat(np.arange(g.V, dtype=np.int64), np.diff(ptr))
+            cnt = np.bincount(rows[keep], minlength=g.V)
+            nptr = np.zeros(g.V + 1, np.int64)
+            np.cumsum(cnt, out=nptr[1:])
+            nb = nb[keep]
+            ptr = nptr
+        cache[key] = sp.csr_matrix((np.ones(len(nb)), np.asarray(nb, np.int64), ptr),
+                                   shape=(g.V, g.V))
+    return cache[key]
+
+
 def tree_hom_bound(g: KG, q: Query) -> float:
     """H(q): homomorphisms of a BFS spanning tree of q (rooted at query vertex
     0) into g under the vertex-type, pin and relation constraints, by a sparse
@@ -484,6 +507,16 @@ def tree_hom_bound(g: KG, q: Query) -> float:
             if tot == 0:
                 sup, val = sup[:0], val[:0]
                 break
+            if tot > g.V:
+                # large push: one sparse matrix-vector product over the
+                # relation's adjacency (integer sums below 2^53 are exact in
+                # float64, so the result equals the gather path's)
+                hc = np.zeros(g.V)
+                hc[csup] = cval
+                val = val * (_rel_matrix(g, lab, fwd) @ hc)[sup]
+                keep = val > 0
+                sup, val = sup[keep], val[keep]
+                continue
             eidx = np.repeat(st - np.concatenate(([0], np.cumsum(ln)[:-1])), ln) + np.arange(tot)
             w = np.repeat(cval, ln)
             tgt = nb[eidx].astype(np.int64)
@@ -593,6 +626,23 @@ def poisson_arrivals(count: int, qps: float, seed: int = BASE_SEED + 4 + 200) ->
     """Arrival times (seconds from 0) of a Poisson stream of rate qps."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.cumsum(rng.exponential(1.0 / qps, size=count))
+
+
+LARGE_CYCLIC_RECIPE = ("large_queries(named_graph('large'), 50, seed=BASE_SEED+102, "
+                       "hmin=1e7, hmax=2e9, p_any=0.5)")
+
+
+def load_large_cyclic():
+    """The stored 50-query large-graph cyclic workload (written by
+    kggen/make_fixtures.py from ``large_queries``)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fixtures", "large_cyclic.json")
+    with open(path) as f:
+        doc = json.load(f)
+    if doc["recipe"] != LARGE_CYCLIC_RECIPE:
+        raise RuntimeError("large_cyclic.json was drawn from another recipe; rerun make_fixtures")
+    return [Query.from_dict(d) for d in doc["queries"]]
 
 
 def large_queries(g: KG, count: int = 50, seed: int = BASE_SEED + 2 + 100,

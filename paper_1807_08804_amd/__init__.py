@@ -23,6 +23,9 @@ SGM_OK, SGM_EINVAL, SGM_ENOMEM, SGM_EDEVICE, SGM_ETOOBIG, SGM_EUNSUPPORTED = 0, 
 SGM_MAX_QV, SGM_MAX_QE = 16, 64
 SGM_SORTED, SGM_COUNT_ONLY = 0, 1
 SGM_PATH_AUTO, SGM_PATH_WIDE, SGM_PATH_NARROW = 0, 1, 2
+SGM_TRACE_CAP = 256
+EVENT_NAMES = {1: "start", 2: "root", 3: "explore", 4: "refine", 5: "lists", 6: "edges",
+               7: "order", 8: "level", 9: "sort", 10: "output"}
 (SGM_K_CHECK, SGM_K_COLLECT, SGM_K_EXPLORE, SGM_K_REFINE, SGM_K_EC_COUNT, SGM_K_EC_WRITE,
  SGM_K_JOIN, SGM_K_SORT, SGM_K_OTHER, SGM_K_PERSIST, SGM_K_COUNT) = range(11)
 KERNEL_NAMES = ["check", "collect", "explore", "refine", "ec_count", "ec_write", "join",
@@ -94,6 +97,8 @@ EXPORTS = {
     "sgm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sgm_last_error": (ctypes.c_char_p, []),
     "sgm_graph_info": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i64p, _i32p, _i32p]),
+    "sgm_trace_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i64p, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_double)]),
     "sgm_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(sgm_kstat)]),
     "sgm_reset_kernel_stats": (ctypes.c_int, [ctypes.c_void_p]),
     "sgm_plan_query": (ctypes.c_int, [ctypes.POINTER(sgm_query), ctypes.c_int32, _i64p,
@@ -298,15 +303,16 @@ class Graph:
     def match_query(self, q, **kw):
         return self.match(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel, **kw)
 
-    def match_batch(self, queries, count_only=False):
+    def match_batch(self, queries, count_only=False, with_stats=False):
         """Results (arrays, counts, or SGMError instances) for a list of
-        kggen-style queries, through sgm_match_batch."""
+        kggen-style queries, through sgm_match_batch; with_stats=True also
+        returns each member's statistics as a dict."""
         built = [_make_query(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel) for q in queries]
         rc, outs = sgm_match_batch(self._h, [b[0] for b in built],
                                    SGM_COUNT_ONLY if count_only else SGM_SORTED)
         if rc != SGM_OK:
             raise SGMError(rc, "sgm_match_batch")
-        res = []
+        res, stats = [], []
         for q, r in zip(queries, outs):
             st = r.contents.status
             if st != SGM_OK:
@@ -314,8 +320,10 @@ class Graph:
             else:
                 k, rows = _result_to_numpy(r, q.n)
                 res.append(k if count_only else rows)
+            if with_stats:
+                stats.append(stats_dict(r.contents.stats, q.n, len(q.esrc)))
             sgm_free_result(r)
-        return res
+        return (res, stats) if with_stats else res
 
     def inspect_query(self, q):
         """(candidate lists per query vertex, candidate-edge counts) after the
@@ -338,6 +346,22 @@ class Graph:
             lists.append(flat[off:off + counts[u]])
             off += counts[u]
         return lists, ec[:len(keep[2][0])]
+
+    def trace(self, i=0):
+        """Step events of query i of the last match call (profile=2): a list
+        of (event name, microseconds since the query's start)."""
+        buf = np.zeros(SGM_TRACE_CAP, np.int64)
+        tick = ctypes.c_double()
+        n = lib().sgm_trace_events(self._h, i, buf.ctypes.data_as(_i64p), SGM_TRACE_CAP,
+                                   ctypes.byref(tick))
+        if n < 0:
+            raise SGMError(n, "sgm_trace_events")
+        ev = buf[:min(n, SGM_TRACE_CAP)]
+        if len(ev) == 0:
+            return []
+        t = (ev >> 8) - (ev[0] >> 8)
+        return [(EVENT_NAMES.get(int(c), str(int(c))), float(x) * tick.value / 1e3)
+                for c, x in zip(ev & 255, t)]
 
     def kernel_stats(self):
         out = {}

@@ -151,6 +151,10 @@ struct DevCounters {
 // descriptors, root sweep rows and the output arena.
 struct NarrowCtx {
     hipStream_t stream = nullptr;
+    // capacities of a context for queries that outgrew a regular slot (0:
+    // the regular ones)
+    int32_t lcap_want = 0;
+    int64_t slab_want = 0;
     int slots = 0;
     int32_t lcap = 0;
     int64_t slab_bytes = 0;
@@ -168,6 +172,8 @@ struct NarrowCtx {
     unsigned long long *d_ctr = nullptr, *h_ctr = nullptr;  // [0] queue, [1] out used
     int32_t *h_out = nullptr;
     int64_t h_out_cap = 0;
+    int64_t *d_trace = nullptr, *h_trace = nullptr;  // [trace_cap][SGM_TRACE_CAP]
+    int trace_cap = 0;
     hipEvent_t done = nullptr;
 };
 
@@ -183,11 +189,15 @@ struct sgm_graph {
     int32_t max_out = 0, max_in = 0;
     int32_t n_big = 0;  // vertices with a direction above kBigDegree
     double ns_per_tick = 10.0;  // device wall clock period
+    // step events of the last match call (options.profile = 2)
+    std::vector<int64_t> trace;  // [queries][SGM_TRACE_CAP]
+    std::vector<int32_t> trace_n;
     int32_t n_types = 0;
     std::vector<int64_t> type_freq;
     DevGraph dg{};
     // device memory owned by the graph
-    int32_t *d_out_off = nullptr, *d_in_off = nullptr, *d_vtype = nullptr;
+    int32_t *d_out_off = nullptr, *d_in_off = nullptr;
+    int2 *d_vinfo = nullptr;
     int2 *d_out_adj = nullptr, *d_in_adj = nullptr;
     uint64_t *d_bits = nullptr;   // [SGM_MAX_QV + 1][nwords] (last: push scratch)
     int32_t *d_lists = nullptr;   // [SGM_MAX_QV][V]
@@ -217,6 +227,7 @@ struct sgm_graph {
     std::atomic<int> launches{0};
     // persistent per-query kernel on the graph's own stream
     NarrowCtx nw;
+    NarrowCtx nwb;  // few large slots for queries that outgrow a regular one
 };
 
 namespace {
@@ -344,7 +355,7 @@ void free_graph_mem(sgm_graph *g) {
         g->ev_free.push_back(p.b);
     }
     for (hipEvent_t e : g->ev_free) (void)hipEventDestroy(e);
-    void *dp[] = {g->d_out_off, g->d_in_off, g->d_vtype, g->d_out_adj, g->d_in_adj, g->d_bits,
+    void *dp[] = {g->d_out_off, g->d_in_off, g->d_vinfo, g->d_out_adj, g->d_in_adj, g->d_bits,
                   g->d_lists,   g->d_prefix, g->d_big,   g->d_desc,    g->d_cnt,    g->d_slots};
     for (void *p : dp)
         if (p) (void)hipFree(p);
@@ -352,6 +363,7 @@ void free_graph_mem(sgm_graph *g) {
     for (void *p : hp)
         if (p) (void)hipHostFree(p);
     narrow_free(g->nw);
+    narrow_free(g->nwb);
     if (g->stream) (void)hipStreamDestroy(g->stream);
 }
 
@@ -462,10 +474,10 @@ struct Query {
         // root check (kernel_check): the first vertex of O
         const int root = pl.visit[0];
         if (qi.pin[root] >= 0) {
-            Prof p(g, SGM_K_CHECK, 12.0);
+            Prof p(g, SGM_K_CHECK, 8.0);
             launch_check_pin(st(), g->dg, pred(root), bits(root));
         } else {
-            Prof p(g, SGM_K_CHECK, 12.0 * g->V + g->nwords * 8.0);
+            Prof p(g, SGM_K_CHECK, 8.0 * g->V + g->nwords * 8.0);
             launch_check_sweep(st(), g->dg, pred(root), bits(root));
         }
         for (const PStep &s : pr.init) {
@@ -973,6 +985,9 @@ constexpr int64_t kNarrowSlabMax = 32ll << 20;       // per slot, large graphs
 constexpr int32_t kNarrowListCap = 1 << 16;          // per query vertex
 constexpr int kNarrowQueryCap = 4096;                // queries per launch
 constexpr int64_t kNarrowOutCap = 256ll << 20;       // int32 elements (1 GB) per context
+constexpr int kBigSlots = 4;                         // large slots of the retry context
+constexpr int32_t kBigListCap = 1 << 22;             // per query vertex, large slot
+constexpr int64_t kBigSlab = 256ll << 20;            // per large slot
 
 // slot memory for edge tables, join tables and sort buffers: 8 bytes per
 // data vertex, within [8 MB, 32 MB]
@@ -1007,15 +1022,21 @@ void narrow_free(NarrowCtx &nw) {
     host_free(nw.h_root_q);
     host_free(nw.h_ctr);
     host_free(nw.h_out);
+    dev_free(nw.d_trace);
+    host_free(nw.h_trace);
     if (nw.done) (void)hipEventDestroy(nw.done);
     nw.done = nullptr;
-    nw = NarrowCtx{nw.stream};
+    const NarrowCtx keep = nw;
+    nw = NarrowCtx{};
+    nw.stream = keep.stream;
+    nw.lcap_want = keep.lcap_want;
+    nw.slab_want = keep.slab_want;
 }
 
 void narrow_reserve(sgm_graph *g, NarrowCtx &nw, int slots, int nq, int nroot) {
     if (nw.lcap == 0) {
-        nw.lcap = std::min<int32_t>(g->V, kNarrowListCap);
-        nw.slab_bytes = narrow_slab_bytes(g);
+        nw.lcap = std::min<int32_t>(g->V, nw.lcap_want ? nw.lcap_want : kNarrowListCap);
+        nw.slab_bytes = nw.slab_want ? nw.slab_want : narrow_slab_bytes(g);
         HIPX(hipMalloc(&nw.d_ctr, sizeof(unsigned long long) * 2));
         HIPX(hipHostMalloc(&nw.h_ctr, sizeof(unsigned long long) * 2, hipHostMallocDefault));
         nw.out_cap = kNarrowOutCap;
@@ -1071,9 +1092,8 @@ int64_t narrow_slot_bytes(const sgm_graph *g) {
 
 // Pack one validated query and its plan; false if it exceeds the packed
 // descriptor's capacity (the query then runs on the multi-kernel path).
-bool pack_query(sgm_graph *g, const QInfo &qi, NQuery *nq, int *root_slot_next, Plan *pl_out) {
-    Plan pl;
-    if (make_plan(qi, g->V, g->type_freq.data(), g->n_types, &pl) != SGM_OK) return false;
+bool pack_query(sgm_graph *g, const QInfo &qi, const Plan &pl, NQuery *nq, int *root_slot_next,
+                Plan *pl_out) {
     Program pr;
     build_program(qi, pl, g->opts.low_conn_degree, g->opts.refine_reversed, &pr);
     if ((int)(pr.init.size() + pr.refine.size()) > kNMaxSteps || (int)pr.nbr.size() > kNMaxNbr)
@@ -1118,6 +1138,7 @@ struct NarrowJob {
     std::vector<Plan> plans;
     int nroot = 0;
     int64_t t0 = 0;
+    bool traced = false;
 };
 
 // Pack queries which[0..count) (validated into qis), upload and launch them
@@ -1129,13 +1150,37 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     job.t0 = now_ns();
     job.packed.clear();
     job.plans.clear();
-    narrow_reserve(g, nw, std::min(count, kNarrowMaxSlots), count, 0);
-    int nroot = 0;
+    const int max_slots = nw.slab_want ? kBigSlots : kNarrowMaxSlots;
+    narrow_reserve(g, nw, std::min(count, max_slots), count, 0);
+    // Longest first: the work queue hands out descriptors in order, so the
+    // queries expected to run longest (an unpinned root with many
+    // candidates of its type, then more query vertices) start first and
+    // the short ones fill the slots around them.
+    std::vector<Plan> plans((size_t)count);
+    std::vector<int64_t> cost((size_t)count, -1);
+    std::vector<int> order;
+    order.reserve((size_t)count);
     for (int i = 0; i < count; ++i) {
+        const QInfo &qi = qis[which[i]];
+        if (make_plan(qi, g->V, g->type_freq.data(), g->n_types, &plans[i]) != SGM_OK) {
+            wide.push_back(which[i]);
+            res[which[i]]->stats.fallback = 16;
+            continue;
+        }
+        const int r = plans[i].visit[0];
+        const int32_t lab = qi.label[r];
+        const int64_t rootc = qi.pin[r] >= 0 ? 1
+                              : (lab >= 0 && lab < g->n_types ? g->type_freq[lab] : g->V);
+        cost[i] = rootc * (SGM_MAX_QV + 1) + qi.n;
+        order.push_back(i);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    int nroot = 0;
+    for (int i : order) {
         Plan pl;
         NQuery *dst = &nw.h_q[job.packed.size()];
         int rs = nroot;
-        if (pack_query(g, qis[which[i]], dst, &rs, &pl)) {
+        if (pack_query(g, qis[which[i]], plans[i], dst, &rs, &pl)) {
             nroot = rs;
             job.packed.push_back(which[i]);
             job.plans.push_back(pl);
@@ -1147,7 +1192,7 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     job.nroot = nroot;
     const int np = (int)job.packed.size();
     if (np == 0) return false;
-    narrow_reserve(g, nw, std::min(np, kNarrowMaxSlots), np, nroot);
+    narrow_reserve(g, nw, std::min(np, max_slots), np, nroot);
     int k = 0;
     for (int i = 0; i < np; ++i)
         if (nw.h_q[i].root_slot >= 0) nw.h_root_q[k++] = i;
@@ -1158,7 +1203,7 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
                             hipMemcpyHostToDevice, st));
     HIPX(hipMemsetAsync(nw.d_ctr, 0, sizeof(unsigned long long) * 2, st));
     if (nroot) {
-        Prof p(g, SGM_K_CHECK, (12.0 + 0.125 * nroot) * g->V, profiled);
+        Prof p(g, SGM_K_CHECK, (8.0 + 0.125 * nroot) * g->V, profiled);
         launch_root_sweep(st, g->dg, nw.d_q, nw.d_root_q, nroot, nw.d_rootbits);
     }
     NArgs a{};
@@ -1176,10 +1221,28 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     a.out = nw.d_out;
     a.out_cap = nw.out_cap;
     a.out_used = nw.d_ctr + 1;
+    job.traced = profiled && g->opts.profile >= 2;
+    if (job.traced) {
+        if (np > nw.trace_cap) {
+            HIPX(hipStreamSynchronize(st));
+            dev_free(nw.d_trace);
+            host_free(nw.h_trace);
+            nw.trace_cap = 0;
+            HIPX(hipMalloc(&nw.d_trace, sizeof(int64_t) * SGM_TRACE_CAP * np));
+            HIPX(hipHostMalloc(&nw.h_trace, sizeof(int64_t) * SGM_TRACE_CAP * np,
+                               hipHostMallocDefault));
+            nw.trace_cap = np;
+        }
+        HIPX(hipMemsetAsync(nw.d_trace, 0, sizeof(int64_t) * SGM_TRACE_CAP * np, st));
+        a.trace = nw.d_trace;
+    }
     {
         Prof p(g, SGM_K_PERSIST, 0.0, profiled);
         launch_narrow(st, a, std::min(np, nw.slots));
     }
+    if (job.traced)
+        HIPX(hipMemcpyAsync(nw.h_trace, nw.d_trace, sizeof(int64_t) * SGM_TRACE_CAP * np,
+                            hipMemcpyDeviceToHost, st));
     HIPX(hipMemcpyAsync(nw.h_res, nw.d_res, sizeof(NResult) * np, hipMemcpyDeviceToHost, st));
     HIPX(hipMemcpyAsync(nw.h_ctr, nw.d_ctr, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost,
                         st));
@@ -1214,6 +1277,16 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         HIPX(hipStreamSynchronize(st));
     }
     const int64_t t1 = now_ns();
+    if (job.traced)
+        for (int i = 0; i < np; ++i) {
+            const size_t q = (size_t)job.packed[i];
+            if (q >= g->trace_n.size()) continue;
+            const int64_t *ev = nw.h_trace + (size_t)i * SGM_TRACE_CAP;
+            int32_t k = 0;
+            while (k < SGM_TRACE_CAP && ev[k] != 0) ++k;
+            std::memcpy(&g->trace[q * SGM_TRACE_CAP], ev, sizeof(int64_t) * k);
+            g->trace_n[q] = k;
+        }
     for (int i = 0; i < np; ++i) {
         const NResult &r = nw.h_res[i];
         const int qi_idx = job.packed[i];
@@ -1271,6 +1344,26 @@ void narrow_batch(sgm_graph *g, const std::vector<QInfo> &qis, const std::vector
     }
 }
 
+// Queries that outgrew a regular slot (candidate list, slot memory or the
+// output arena) run again in the large-slot context on the graph's stream;
+// what still does not fit stays in `wide`. Caller holds g->mu.
+void narrow_retry_large(sgm_graph *g, const std::vector<QInfo> &qis, uint32_t flags,
+                        std::vector<sgm_result *> &res, std::vector<int> &wide) {
+    std::vector<int> again, keep;
+    for (int i : wide) {
+        const int32_t why = res[i]->stats.fallback;
+        (why == kWhyList || why == kWhySlab || why == 8 ? again : keep).push_back(i);
+    }
+    if (again.empty()) return;
+    wide = keep;
+    for (size_t base = 0; base < again.size(); base += kNarrowQueryCap) {
+        const int count = (int)std::min<size_t>(kNarrowQueryCap, again.size() - base);
+        NarrowJob job;
+        if (narrow_launch(g, g->nwb, qis, again.data() + base, count, job, wide, res, true))
+            narrow_collect(g, g->nwb, job, qis, flags, res, wide, true);
+    }
+}
+
 // multi-kernel path for one validated query
 int wide_locked(sgm_graph *g, const QInfo &qi, uint32_t flags, sgm_result *res) {
     const int l0 = g->launches;
@@ -1297,6 +1390,10 @@ int run_queries(sgm_graph *g, const sgm_query *qs, int n, uint32_t flags,
                 std::vector<sgm_result *> &res) {
     std::vector<QInfo> qis((size_t)n);
     std::vector<int> valid, wide;
+    if (g->opts.profile >= 2) {
+        g->trace.assign((size_t)n * SGM_TRACE_CAP, 0);
+        g->trace_n.assign((size_t)n, 0);
+    }
     for (int i = 0; i < n; ++i) {
         const int rc = check_query(&qs[i], g->V, &qis[i]);
         res[i]->status = rc;
@@ -1307,6 +1404,7 @@ int run_queries(sgm_graph *g, const sgm_query *qs, int n, uint32_t flags,
     } else {
         try {
             narrow_batch(g, qis, valid, flags, res, wide);
+            narrow_retry_large(g, qis, flags, res, wide);
         } catch (const DeviceError &e) {
             (void)hipStreamSynchronize(g->stream);
             (void)hipGetLastError();
@@ -1412,6 +1510,9 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
         HIPX(hipSetDevice(g->device));
         HIPX(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
         g->nw.stream = g->stream;
+        g->nwb.stream = g->stream;
+        g->nwb.lcap_want = kBigListCap;
+        g->nwb.slab_want = kBigSlab;
         int khz = 0;
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device) == hipSuccess &&
             khz > 0)
@@ -1420,8 +1521,11 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
         g->d_in_off = dev_upload(in_off);
         g->d_out_adj = dev_upload(adj);
         g->d_in_adj = dev_upload(in_adj);
-        std::vector<int32_t> tv(type, type + n_vertices);
-        g->d_vtype = dev_upload(tv);
+        std::vector<int2> vi((size_t)n_vertices);
+        for (int32_t v = 0; v < n_vertices; ++v)
+            vi[v] = make_int2(type[v], std::min(off[v + 1] - off[v], 255) |
+                                           std::min(in_off[v + 1] - in_off[v], 255) << 8);
+        g->d_vinfo = dev_upload(vi);
         HIPX(hipMalloc(&g->d_bits, sizeof(uint64_t) * (size_t)(SGM_MAX_QV + 1) * g->nwords));
         HIPX(hipMalloc(&g->d_lists, sizeof(int32_t) * (size_t)SGM_MAX_QV * g->V));
         HIPX(hipMalloc(&g->d_prefix, sizeof(int32_t) * (size_t)SGM_MAX_QV * (g->nwords + 1)));
@@ -1439,7 +1543,7 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
         g->dg.in_off = g->d_in_off;
         g->dg.out_adj = g->d_out_adj;
         g->dg.in_adj = g->d_in_adj;
-        g->dg.vtype = g->d_vtype;
+        g->dg.vinfo = g->d_vinfo;
         HIPX(hipDeviceSynchronize());
     } catch (const DeviceError &e) {
         free_graph_mem(g);
@@ -1454,6 +1558,16 @@ void sgm_free_graph(sgm_graph *g) {
     if (!g) return;
     free_graph_mem(g);
     delete g;
+}
+
+int sgm_trace_events(sgm_graph *g, int32_t i, int64_t *out, int32_t cap, double *ns_per_tick) {
+    if (!g || i < 0 || cap < 0 || (cap > 0 && !out)) return SGM_EINVAL;
+    if (ns_per_tick) *ns_per_tick = g->ns_per_tick;
+    if ((size_t)i >= g->trace_n.size()) return SGM_EINVAL;
+    const int32_t n = g->trace_n[(size_t)i];
+    const int32_t k = std::min(n, cap);
+    if (k > 0) std::memcpy(out, &g->trace[(size_t)i * SGM_TRACE_CAP], sizeof(int64_t) * k);
+    return n;
 }
 
 int sgm_graph_info(const sgm_graph *g, int32_t *n_vertices, int64_t *n_edges,
@@ -1734,7 +1848,19 @@ void serve_complete(sgm_server *S) {
             for (int i : b->which) b->res[i]->status = SGM_ENOMEM;
             b->wide.clear();
         }
-        // queries that outgrew their slot: the multi-kernel path
+        // queries that outgrew their slot: a large slot, then the
+        // multi-kernel path
+        if (!b->wide.empty()) {
+            std::lock_guard<std::mutex> gl(g->mu);
+            try {
+                narrow_retry_large(g, b->qis, b->flags, b->res, b->wide);
+            } catch (const DeviceError &e) {
+                (void)hipStreamSynchronize(g->stream);
+                (void)hipGetLastError();
+                g->pending.clear();
+            } catch (const std::bad_alloc &) {
+            }
+        }
         for (int i : b->wide) {
             std::lock_guard<std::mutex> gl(g->mu);
             const int32_t why = b->res[i]->stats.fallback;

@@ -15,12 +15,13 @@ __device__ __forceinline__ bool bit_test(const uint64_t *bits, int32_t x) {
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
 
 // Candidate predicate (Def. 3.3 + pin + incoming degree).
+__device__ __forceinline__ bool vinfo_ok(const VPred &p, int2 vi) {
+    return (p.label < 0 || vi.x == p.label) && (vi.y & 255) >= p.qout && (vi.y >> 8) >= p.qin;
+}
+
 __device__ __forceinline__ bool vpred(const DevGraph &g, const VPred &p, int32_t v) {
     if (p.pin >= 0 && v != p.pin) return false;
-    if (p.label >= 0 && g.vtype[v] != p.label) return false;
-    if (p.qout > 0 && g.out_off[v + 1] - g.out_off[v] < p.qout) return false;
-    if (p.qin > 0 && g.in_off[v + 1] - g.in_off[v] < p.qin) return false;
-    return true;
+    return vinfo_ok(p, g.vinfo[v]);
 }
 
 __device__ __forceinline__ int64_t wave_incl_scan(int64_t x, int lane) {

@@ -27,7 +27,10 @@ struct DevGraph {
     const int32_t *in_off;   // [V+1]
     const int2 *out_adj;     // [E]
     const int2 *in_adj;      // [E]
-    const int32_t *vtype;    // [V]
+    // [V] per-vertex predicate inputs in one 8-byte word: x = type,
+    // y = min(out-degree, 255) | min(in-degree, 255) << 8 (a query vertex has
+    // at most 15 distinct neighbours per direction, so the clamp is exact)
+    const int2 *vinfo;
 };
 
 // Candidate predicate of one query vertex (thesis Def. 3.3 with pins and the

@@ -81,6 +81,7 @@ struct NArgs {
     int32_t *out;             // output arena (int32 rows)
     int64_t out_cap;          // in int32 elements
     unsigned long long *out_used;
+    int64_t *trace;           // [nq][SGM_TRACE_CAP] step events, or null
 };
 
 // root sweep: rootbits[j][w] for every query whose root is unpinned

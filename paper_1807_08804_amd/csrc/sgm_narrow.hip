@@ -26,7 +26,10 @@ namespace {
 
 constexpr int NT = kNarrowThreads;
 constexpr int NW = NT / 64;
-constexpr int kBigCap = 256;
+constexpr int kBigCap = 256;         // LDS list of items for the whole workgroup
+constexpr int32_t kWgDeg = 8192;      // rows longer than this get the whole workgroup
+constexpr int32_t kRevMin = 256;      // candidates of u before a reverse check can pay
+constexpr int32_t kRevMaxCand = 4096; // neighbours with at most this many candidates
 constexpr int kListSortCap = 8192;    // int32 entries sorted in LDS
 constexpr int kRowSortCap = 2048;     // final rows sorted in LDS (u64 key + int32 index);
                                       // more rows use radix passes in the slab
@@ -49,7 +52,12 @@ struct Smem {
     int32_t rowlo[NT];
     int32_t abort_;
     int32_t q;
+    int32_t nev;
     int32_t nbig;
+    int32_t ngiant;
+    int32_t nnbl;
+    uint64_t revmask;
+    NNbr nbl[SGM_MAX_QE];  // neighbours a step still tests per candidate
     int32_t removed;
     int32_t ctr;
     int32_t empty;
@@ -86,6 +94,7 @@ struct Ctx {
     int32_t *lists;     // slot lists [SGM_MAX_QV * lcap]
     char *slab;
     unsigned char *dyn;
+    int64_t *trace;     // this query's step events, or null
     __device__ uint64_t *B(int u) const { return bits + (int64_t)u * g.nwords; }
     __device__ int32_t *L(int u) const { return lists + (int64_t)u * lcap; }
 };
@@ -105,6 +114,14 @@ __device__ __forceinline__ void add_bytes_wave(Ctx &c, uint64_t b) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) b += __shfl_xor(b, o, 64);
     if ((threadIdx.x & 63) == 0) add_bytes(c, b);
+}
+
+// step event (uniform call; thread 0 records)
+__device__ __forceinline__ void ev(Ctx &c, int code) {
+    if (c.trace && threadIdx.x == 0) {
+        const int k = c.s->nev++;
+        if (k < SGM_TRACE_CAP) c.trace[k] = (int64_t)(wall_clock64() << 8) | code;
+    }
 }
 
 __device__ __forceinline__ void mark(Ctx &c, int i) {
@@ -137,6 +154,12 @@ __device__ __forceinline__ void push_bit(Ctx &c, uint64_t *tb, int32_t *tl, int 
         if (p < c.lcap) tl[p] = x;
         else c.s->abort_ = kWhyList;
     }
+}
+
+// entry i of a row ending at end, or an in-range dummy (vertex 0, no
+// relation) past the end
+__device__ __forceinline__ int2 adj_at(const int2 *adj, int32_t i, int32_t end) {
+    return i < end ? adj[i] : make_int2(0, -1);
 }
 
 __device__ __forceinline__ bool nbr_hit(const Ctx &c, const NNbr &d, int2 e) {
@@ -315,6 +338,78 @@ __device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb,
     if (threadIdx.x == 0) fb += 20ull + 12ull * seen;
 }
 
+// One wave on one candidate (wave-uniform call, no workgroup barrier), four
+// loads in flight per lane; same outcome as item_wg.
+__device__ __forceinline__ void item_wave(Ctx &c, const NStep &st, const NNbr *nb, int ncount,
+                                          int32_t up, uint64_t *ub, uint64_t &fb) {
+    const DevGraph &g = c.g;
+    const int lane = threadIdx.x & 63;
+    bool alive = true;
+    uint64_t seen = 0;
+    for (int j = 0; j < ncount && alive; ++j) {
+        const NNbr d = nb[j];
+        const int2 *adj = d.dir ? g.in_adj : g.out_adj;
+        int32_t beg, end;
+        row_of(g, up, d.dir, &beg, &end);
+        bool found = false;
+        for (int32_t base = beg; base < end; base += 256) {
+            const int32_t i = base + lane;
+            const int2 e0 = i < end ? adj[i] : make_int2(-1, -1);
+            const int2 e1 = i + 64 < end ? adj[i + 64] : make_int2(-1, -1);
+            const int2 e2 = i + 128 < end ? adj[i + 128] : make_int2(-1, -1);
+            const int2 e3 = i + 192 < end ? adj[i + 192] : make_int2(-1, -1);
+            const bool hit = (e0.x >= 0 && nbr_hit(c, d, e0)) || (e1.x >= 0 && nbr_hit(c, d, e1)) ||
+                             (e2.x >= 0 && nbr_hit(c, d, e2)) || (e3.x >= 0 && nbr_hit(c, d, e3));
+            seen += min(256, end - base);
+            if (__ballot(hit)) {
+                found = true;
+                break;
+            }
+        }
+        alive = found;
+    }
+    if (!alive) {
+        if (lane == 0) {
+            atomicAnd((unsigned long long *)&ub[up >> 6], ~(1ull << (up & 63)));
+            atomicAdd(&c.s->removed, 1);
+            fb += 20ull + 12ull * seen;
+        }
+        return;
+    }
+    if (st.push)
+        for (int j = 0; j < ncount; ++j) {
+            const NNbr d = nb[j];
+            const int2 *adj = d.dir ? g.in_adj : g.out_adj;
+            int32_t beg, end;
+            row_of(g, up, d.dir, &beg, &end);
+            uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
+            int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
+            seen += end - beg;
+            for (int32_t base = beg; base < end; base += 256) {
+                const int32_t i = base + lane;
+                const int2 e0 = i < end ? adj[i] : make_int2(-1, -1);
+                const int2 e1 = i + 64 < end ? adj[i + 64] : make_int2(-1, -1);
+                const int2 e2 = i + 128 < end ? adj[i + 128] : make_int2(-1, -1);
+                const int2 e3 = i + 192 < end ? adj[i + 192] : make_int2(-1, -1);
+                if (e0.x >= 0 && nbr_hit(c, d, e0)) push_bit(c, tb, tl, d.v, e0.x);
+                if (e1.x >= 0 && nbr_hit(c, d, e1)) push_bit(c, tb, tl, d.v, e1.x);
+                if (e2.x >= 0 && nbr_hit(c, d, e2)) push_bit(c, tb, tl, d.v, e2.x);
+                if (e3.x >= 0 && nbr_hit(c, d, e3)) push_bit(c, tb, tl, d.v, e3.x);
+            }
+        }
+    if (lane == 0) fb += 20ull + 12ull * seen;
+}
+
+// longest adjacency row a candidate scans for the listed query edges
+__device__ __forceinline__ int32_t max_row(const DevGraph &g, const NNbr *nb, int ncount, int32_t up) {
+    int32_t m = 0;
+    for (int j = 0; j < ncount; ++j) {
+        const int32_t *off = nb[j].dir ? g.in_off : g.out_off;
+        m = max(m, off[up + 1] - off[up]);
+    }
+    return m;
+}
+
 // lanes per candidate for n items: the whole workgroup for a handful,
 // otherwise a power of two in [1, 64] so that all lanes hold an item
 __device__ __forceinline__ int lanes_for(int32_t n) {
@@ -323,44 +418,151 @@ __device__ __forceinline__ int lanes_for(int32_t n) {
     return G;
 }
 
+// Reverse form of the prune test against one initialised neighbour v with
+// few candidates (prune-only steps): mark the candidates of u that have a
+// matching edge to some candidate of v, found in the rows of v's candidates
+// in the other direction, then drop the unmarked ones. The survivors are the
+// same as when each candidate of u scans its own row for a member of v's
+// bitmap. Marks go to the slot's scratch bitmap, which a prune-only step
+// does not otherwise use; they fall inside u's candidates, so clearing the
+// words of u's list leaves it zero again.
+__device__ __forceinline__ void prune_reverse(Ctx &c, int u, int v, int dir, int32_t rel,
+                                              uint64_t &fb) {
+    const DevGraph &g = c.g;
+    uint64_t *ub = c.B(u);
+    const int32_t *ul = c.L(u);
+    const int32_t n = c.s->cnt[u];
+    const int32_t *vl = c.L(v);
+    const int32_t nv = c.s->cnt[v];
+    // a candidate's out-edge (dir 0) is an in-edge of the neighbour, and so on
+    const int32_t *off = dir ? g.out_off : g.in_off;
+    const int2 *adj = dir ? g.out_adj : g.in_adj;
+    const int lane = threadIdx.x & 63;
+    uint64_t seen = 0;
+    for (int32_t i = threadIdx.x >> 6; i < nv; i += NW) {
+        const int32_t y = vl[i];
+        const int32_t beg = off[y], end = off[y + 1];
+        for (int32_t k = beg + lane; k < end; k += 64) {
+            const int2 e = adj[k];
+            if ((rel < 0 || e.y == rel) && bit_test(ub, e.x))
+                atomicOr((unsigned long long *)&c.scratch[e.x >> 6], 1ull << (e.x & 63));
+        }
+        if (lane == 0) seen += 12ull + 16ull * (end - beg);
+    }
+    fb += seen;
+    __syncthreads();
+    int32_t removed = 0;
+    for (int32_t i = threadIdx.x; i < n; i += NT) {
+        const int32_t x = ul[i];
+        if (bit_test(ub, x) && !bit_test(c.scratch, x)) {
+            atomicAnd((unsigned long long *)&ub[x >> 6], ~(1ull << (x & 63)));
+            ++removed;
+        }
+    }
+    if (removed) atomicAdd(&c.s->removed, removed);
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n; i += NT) c.scratch[ul[i] >> 6] = 0ull;
+    if (threadIdx.x == 0) fb += 28ull * n;
+    __syncthreads();
+}
+
 __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
     const DevGraph &g = c.g;
-    const NNbr *nb = c.Q->nbr + st.first;
-    const int ncount = st.count;
     const int u = st.u;
     uint64_t *ub = c.B(u);
     int32_t *ul = c.L(u);
     __syncthreads();
     if (threadIdx.x == 0) {
         c.s->nbig = 0;
+        c.s->ngiant = 0;
         c.s->removed = 0;
     }
     __syncthreads();
     const int32_t n_items = c.s->cnt[u];
     uint64_t fb = 0;  // algorithmic bytes of this thread's work
-    if (n_items <= NW) {
+    // The step's neighbour tests go to LDS. In prune-only steps over many
+    // candidates, a neighbour with few candidates whose rows together are
+    // shorter than u's list is instead checked from its side (prune_reverse).
+    const bool try_rev = !st.push && n_items >= kRevMin;
+    if (threadIdx.x < 64) {
+        const NNbr *src = c.Q->nbr + st.first;
+        int k = 0;
+        uint64_t rm = 0;
+        for (int j = 0; j < st.count; ++j) {
+            const int v = src[j].v, dir = src[j].dir, mode = src[j].mode;
+            const int32_t rel = src[j].rel;
+            bool rev = false;
+            const int32_t nv = c.s->cnt[v];
+            if (try_rev && mode == 0 && nv <= kRevMaxCand && nv < n_items) {
+                // reverse cost: v's list plus its rows, against at least one
+                // read per candidate of u forward
+                const int32_t *off = dir ? g.out_off : g.in_off;
+                const int32_t *vl = c.L(v);
+                int64_t sum = nv;
+                for (int32_t b = 0; b < nv && sum <= n_items; b += 64) {
+                    int32_t len = 0;
+                    if (b + (int32_t)threadIdx.x < nv) {
+                        const int32_t y = vl[b + threadIdx.x];
+                        len = off[y + 1] - off[y];
+                    }
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) len += __shfl_xor(len, o, 64);
+                    sum += len;
+                }
+                rev = sum <= n_items;
+            }
+            if (rev) {
+                rm |= 1ull << j;
+            } else {
+                if (threadIdx.x == 0) {
+                    NNbr &t = c.s->nbl[k];
+                    t.v = (int8_t)v;
+                    t.dir = (int8_t)dir;
+                    t.mode = (int8_t)mode;
+                    t.rel = rel;
+                }
+                ++k;
+            }
+        }
+        if (threadIdx.x == 0) {
+            c.s->revmask = rm;
+            c.s->nnbl = k;
+        }
+    }
+    __syncthreads();
+    const NNbr *nb = c.s->nbl;
+    const int ncount = c.s->nnbl;
+    const uint64_t rm = c.s->revmask;
+    const bool revd = rm != 0;
+    for (int j = 0; j < st.count && revd; ++j)
+        if ((rm >> j) & 1ull) {
+            const NNbr *d = c.Q->nbr + st.first + j;
+            prune_reverse(c, u, d->v, d->dir, d->rel, fb);
+        }
+    if (ncount == 0) {
+        // every test was done from the other side
+    } else if (n_items <= NW) {
         for (int32_t it = 0; it < n_items; ++it) item_wg(c, st, nb, ncount, ul[it], ub, fb);
     } else {
         const int G = lanes_for(n_items);
         const int NGr = NT / G;
         const int lane = threadIdx.x & 63, gl = lane & (G - 1), gb = lane & ~(G - 1);
         const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << gb;
-        const int32_t bigdeg = 64 * G;  // more than 64 strides: whole workgroup
+        const int32_t bigdeg = 64 * G;  // more than 64 strides: a wider tier
+        int32_t *ov = (int32_t *)c.slab;
         for (int32_t it = threadIdx.x / G; it < n_items; it += NGr) {
             const int32_t up = ul[it];
+            if (revd && !bit_test(ub, up)) continue;  // already dropped
             const int32_t ob = g.out_off[up], oe = g.out_off[up + 1];
             const int32_t ib = g.in_off[up], ie = g.in_off[up + 1];
             int32_t maxd = 0;
             for (int j = 0; j < ncount; ++j) maxd = max(maxd, nb[j].dir ? ie - ib : oe - ob);
             if (maxd > bigdeg) {
-                int32_t p = 0;
-                if (gl == 0) p = atomicAdd(&c.s->nbig, 1);
-                p = __shfl(p, gb, 64);
-                if (p < kBigCap) {
-                    if (gl == 0) c.s->big[p] = up;
-                    continue;
-                }
-                // LDS list full: this group handles the item itself
+                // long rows: a wider tier after this loop. The overflow list
+                // sits at the start of the slot's slab, which no phase uses
+                // while filtering (at most lcap entries, far below its size).
+                if (gl == 0) ov[atomicAdd(&c.s->nbig, 1)] = up;
+                continue;
             }
             bool alive = true;
             uint64_t seen = 0;
@@ -369,10 +571,17 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
                 const int2 *adj = d.dir ? g.in_adj : g.out_adj;
                 const int32_t beg = d.dir ? ib : ob, end = d.dir ? ie : oe;
                 bool found = false;
-                for (int32_t base = beg; base < end; base += G) {
+                // four entries per lane in flight; lanes past the row test an
+                // in-range dummy entry and discard the answer
+                for (int32_t base = beg; base < end; base += 4 * G) {
                     const int32_t i = base + gl;
-                    const bool hit = i < end && nbr_hit(c, d, adj[i]);
-                    seen += min(G, end - base);
+                    const int2 e0 = adj_at(adj, i, end), e1 = adj_at(adj, i + G, end);
+                    const int2 e2 = adj_at(adj, i + 2 * G, end), e3 = adj_at(adj, i + 3 * G, end);
+                    const bool hit = ((i < end) & nbr_hit(c, d, e0)) |
+                                     ((i + G < end) & nbr_hit(c, d, e1)) |
+                                     ((i + 2 * G < end) & nbr_hit(c, d, e2)) |
+                                     ((i + 3 * G < end) & nbr_hit(c, d, e3));
+                    seen += min(4 * G, end - base);
                     if (__ballot(hit) & gmask) {
                         found = true;
                         break;
@@ -396,16 +605,41 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
                     uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
                     int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
                     seen += end - beg;
-                    for (int32_t i = beg + gl; i < end; i += G) {
-                        const int2 e = adj[i];
-                        if (nbr_hit(c, d, e)) push_bit(c, tb, tl, d.v, e.x);
+                    for (int32_t i = beg + gl; i < end; i += 4 * G) {
+                        const int2 e0 = adj_at(adj, i, end), e1 = adj_at(adj, i + G, end);
+                        const int2 e2 = adj_at(adj, i + 2 * G, end), e3 = adj_at(adj, i + 3 * G, end);
+                        const bool h0 = (i < end) & nbr_hit(c, d, e0);
+                        const bool h1 = (i + G < end) & nbr_hit(c, d, e1);
+                        const bool h2 = (i + 2 * G < end) & nbr_hit(c, d, e2);
+                        const bool h3 = (i + 3 * G < end) & nbr_hit(c, d, e3);
+                        if (h0) push_bit(c, tb, tl, d.v, e0.x);
+                        if (h1) push_bit(c, tb, tl, d.v, e1.x);
+                        if (h2) push_bit(c, tb, tl, d.v, e2.x);
+                        if (h3) push_bit(c, tb, tl, d.v, e3.x);
                     }
                 }
             if (gl == 0) fb += 20ull + 12ull * seen;
         }
         __syncthreads();
-        const int32_t nbig = min(c.s->nbig, kBigCap);
-        for (int32_t b = 0; b < nbig; ++b) item_wg(c, st, nb, ncount, c.s->big[b], ub, fb);
+        // one wave per long row; rows above kWgDeg get the whole workgroup
+        const int32_t nbig = c.s->nbig;
+        for (int32_t b = threadIdx.x >> 6; b < nbig; b += NW) {
+            const int32_t up = ov[b];
+            if (max_row(g, nb, ncount, up) > kWgDeg) {
+                int32_t p = 0;
+                if (lane == 0) p = atomicAdd(&c.s->ngiant, 1);
+                p = __shfl(p, 0, 64);
+                if (p < kBigCap) {
+                    if (lane == 0) c.s->big[p] = up;
+                    continue;
+                }
+                // LDS list full: this wave handles the row itself
+            }
+            item_wave(c, st, nb, ncount, up, ub, fb);
+        }
+        __syncthreads();
+        const int32_t ngiant = min(c.s->ngiant, kBigCap);
+        for (int32_t b = 0; b < ngiant; ++b) item_wg(c, st, nb, ncount, c.s->big[b], ub, fb);
     }
     add_bytes_wave(c, fb);
     __syncthreads();
@@ -448,6 +682,71 @@ __device__ __forceinline__ bool ec_hit(int32_t rel, const uint64_t *other, const
     return e.x != key && bit_test(other, e.x);
 }
 
+// first position in row adj[beg, end) (sorted by neighbour id, then
+// relation) whose neighbour id is >= x
+__device__ __forceinline__ int32_t row_lower_bound(const int2 *adj, int32_t beg, int32_t end,
+                                                   int32_t x) {
+    while (beg < end) {
+        const int32_t mid = beg + ((end - beg) >> 1);
+        if (adj[mid].x < x) beg = mid + 1;
+        else end = mid;
+    }
+    return beg;
+}
+
+// does the row hold neighbour x under relation rel (-1: any relation)?
+__device__ __forceinline__ bool row_has(const int2 *adj, int32_t beg, int32_t end, int32_t x,
+                                        int32_t rel) {
+    for (int32_t i = row_lower_bound(adj, beg, end, x); i < end && adj[i].x == x; ++i)
+        if (rel < 0 || adj[i].y == rel) return true;
+    return false;
+}
+
+// Looking each of `no` candidates up in a row of `len` entries costs about
+// no * log2(len) reads against len for a scan of the row.
+__device__ __forceinline__ bool probe_cheaper(int32_t no, int32_t len) {
+    return (int64_t)no * (33 - __clz(len | 1)) < (int64_t)len;
+}
+
+__device__ __forceinline__ uint64_t probe_bytes(int32_t no, int32_t len) {
+    return (uint64_t)no * (4ull + 8ull * (uint64_t)(33 - __clz(len | 1)));
+}
+
+// one key, whole workgroup: the other endpoint's sorted candidates that the
+// key's row holds, in order (the lookup form of ec_key_wg)
+__device__ __forceinline__ int64_t ec_probe_wg(Ctx &c, int32_t rel, const int32_t *ol, int32_t no,
+                                               const int2 *adj, int32_t beg, int32_t end, int32_t k,
+                                               int32_t *dst) {
+    int64_t n = 0;
+    for (int32_t base = 0; base < no; base += NT) {
+        const int32_t i = base + threadIdx.x;
+        const int32_t x = i < no ? ol[i] : -1;
+        const bool hit = x >= 0 && x != k && row_has(adj, beg, end, x, rel);
+        int64_t tot;
+        const int64_t p = n + block_excl_scan(hit ? 1 : 0, c.s->sh, &tot);
+        if (hit) dst[p] = x;
+        n += tot;
+    }
+    return n;
+}
+
+// one key, one wave (wave-uniform call): lookup form of ec_key_wave
+__device__ __forceinline__ int64_t ec_probe_wave(int32_t rel, const int32_t *ol, int32_t no,
+                                                 const int2 *adj, int32_t beg, int32_t end,
+                                                 int32_t k, int32_t *dst) {
+    const int lane = threadIdx.x & 63;
+    int64_t n = 0;
+    for (int32_t base = 0; base < no; base += 64) {
+        const int32_t i = base + lane;
+        const int32_t x = i < no ? ol[i] : -1;
+        const bool hit = x >= 0 && x != k && row_has(adj, beg, end, x, rel);
+        const uint64_t bm = __ballot(hit);
+        if (hit) dst[n + __popcll(bm & lanemask_lt(lane))] = x;
+        n += __popcll(bm);
+    }
+    return n;
+}
+
 // one key, whole workgroup, ordered compaction in chunks of 4*NT entries
 __device__ __forceinline__ int64_t ec_key_wg(Ctx &c, int32_t rel, const uint64_t *ob, const int2 *adj,
                              int32_t beg, int32_t end, int32_t k, int32_t *dst) {
@@ -468,6 +767,27 @@ __device__ __forceinline__ int64_t ec_key_wg(Ctx &c, int32_t rel, const uint64_t
     return n;
 }
 
+// one key, one wave (wave-uniform call), same ordered output as ec_key_wg
+__device__ __forceinline__ int64_t ec_key_wave(int32_t rel, const uint64_t *ob, const int2 *adj,
+                                               int32_t beg, int32_t end, int32_t k, int32_t *dst) {
+    const int lane = threadIdx.x & 63;
+    int64_t n = 0;
+    for (int32_t base = beg; base < end; base += 256) {
+        const int32_t i0 = base + 4 * lane;
+        uint32_t h = 0;  // bit t: entry i0 + t matches
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (i0 + t < end && ec_hit(rel, ob, adj, beg, i0 + t, k)) h |= 1u << t;
+        const int32_t inc = wave_incl_scan32(__popc(h), lane);
+        int64_t p = n + inc - __popc(h);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if ((h >> t) & 1u) dst[p++] = adj[i0 + t].x;
+        n += __shfl(inc, 63, 64);
+    }
+    return n;
+}
+
 // Build the table of query edge e keyed by `key` (dir 0: keys are sources).
 // Sets s.ec_offs/ec_cnt/ec_vals[e], s.eckey[e] and s.ectot[e].
 __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int dir) {
@@ -475,6 +795,8 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
     const int32_t *keys = c.L(key);
     const int32_t nk = c.s->cnt[key];
     const uint64_t *ob = c.B(other);
+    const int32_t *ol = c.L(other);  // sorted
+    const int32_t no = c.s->cnt[other];
     const int32_t rel = c.Q->elabel[e];
     const int32_t *off = dir ? g.in_off : g.out_off;
     const int2 *adj = dir ? g.in_adj : g.out_adj;
@@ -493,6 +815,10 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
     }
     int32_t *vals = (int32_t *)slab_alloc(c, 4 * carry + 4);
     if (!vals) return;
+    // keys with long rows, for the wave and workgroup tiers; given back
+    // to the slab at the end
+    int32_t *ovl = (int32_t *)slab_alloc(c, 4ll * nk + 4);
+    if (!ovl) return;
     if (threadIdx.x == 0) {
         degoff[nk] = (int32_t)carry;
         c.s->ec_offs[e] = degoff;
@@ -500,6 +826,7 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
         c.s->ec_vals[e] = vals;
         c.s->eckey[e] = key;
         c.s->nbig = 0;
+        c.s->ngiant = 0;
     }
     __syncthreads();
     int64_t mytot = 0;
@@ -508,11 +835,13 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
         for (int32_t it = 0; it < nk; ++it) {
             const int32_t k = keys[it];
             const int32_t beg = off[k], end = off[k + 1];
-            const int64_t n = ec_key_wg(c, rel, ob, adj, beg, end, k, vals + degoff[it]);
+            const bool probe = probe_cheaper(no, end - beg);
+            const int64_t n = probe ? ec_probe_wg(c, rel, ol, no, adj, beg, end, k, vals + degoff[it])
+                                    : ec_key_wg(c, rel, ob, adj, beg, end, k, vals + degoff[it]);
             if (threadIdx.x == 0) {
                 num[it] = (int32_t)n;
                 mytot += n;
-                fb += 16ull + 12ull * (end - beg) + 4ull * n;
+                fb += 16ull + 4ull * n + (probe ? probe_bytes(no, end - beg) : 12ull * (end - beg));
             }
         }
     } else {
@@ -525,13 +854,8 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
             const int32_t k = keys[it];
             const int32_t beg = off[k], end = off[k + 1];
             if (end - beg > bigdeg) {
-                int32_t p = 0;
-                if (gl == 0) p = atomicAdd(&c.s->nbig, 1);
-                p = __shfl(p, gb, 64);
-                if (p < kBigCap) {
-                    if (gl == 0) c.s->big[p] = it;
-                    continue;
-                }
+                if (gl == 0) ovl[atomicAdd(&c.s->nbig, 1)] = it;
+                continue;
             }
             int32_t *dst = vals + degoff[it];
             int32_t n = 0;
@@ -549,23 +873,52 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
             }
         }
         __syncthreads();
-        const int32_t nbig = min(c.s->nbig, kBigCap);
-        for (int32_t b = 0; b < nbig; ++b) {
+        const int32_t nbig = c.s->nbig;
+        for (int32_t b = threadIdx.x >> 6; b < nbig; b += NW) {
+            const int32_t it = ovl[b];
+            const int32_t k = keys[it];
+            const int32_t beg = off[k], end = off[k + 1];
+            if (end - beg > kWgDeg) {
+                int32_t p = 0;
+                if (lane == 0) p = atomicAdd(&c.s->ngiant, 1);
+                p = __shfl(p, 0, 64);
+                if (p < kBigCap) {
+                    if (lane == 0) c.s->big[p] = it;
+                    continue;
+                }
+            }
+            const bool probe = probe_cheaper(no, end - beg);
+            const int64_t n = probe ? ec_probe_wave(rel, ol, no, adj, beg, end, k, vals + degoff[it])
+                                    : ec_key_wave(rel, ob, adj, beg, end, k, vals + degoff[it]);
+            if (lane == 0) {
+                num[it] = (int32_t)n;
+                mytot += n;
+                fb += 16ull + 4ull * n + (probe ? probe_bytes(no, end - beg) : 12ull * (end - beg));
+            }
+        }
+        __syncthreads();
+        const int32_t ngiant = min(c.s->ngiant, kBigCap);
+        for (int32_t b = 0; b < ngiant; ++b) {
             const int32_t it = c.s->big[b];
             const int32_t k = keys[it];
             const int32_t beg = off[k], end = off[k + 1];
-            const int64_t n = ec_key_wg(c, rel, ob, adj, beg, end, k, vals + degoff[it]);
+            const bool probe = probe_cheaper(no, end - beg);
+            const int64_t n = probe ? ec_probe_wg(c, rel, ol, no, adj, beg, end, k, vals + degoff[it])
+                                    : ec_key_wg(c, rel, ob, adj, beg, end, k, vals + degoff[it]);
             if (threadIdx.x == 0) {
                 num[it] = (int32_t)n;
                 mytot += n;
-                fb += 16ull + 12ull * (end - beg) + 4ull * n;
+                fb += 16ull + 4ull * n + (probe ? probe_bytes(no, end - beg) : 12ull * (end - beg));
             }
         }
     }
     add_bytes_wave(c, fb);
     int64_t tot;
     block_excl_scan(mytot, c.s->sh, &tot);
-    if (threadIdx.x == 0) c.s->ectot[e] = tot;
+    if (threadIdx.x == 0) {
+        c.s->ectot[e] = tot;
+        c.s->slab_used = (int64_t)((char *)ovl - c.slab);  // the last allocation
+    }
     __syncthreads();
 }
 
@@ -642,55 +995,75 @@ __device__ __forceinline__ uint64_t row_key(const Ctx &c, const int32_t *row) {
     return key;
 }
 
-// One stable 8-bit LSD pass of the whole workgroup: histogram, scan, then
-// chunks of NT elements placed by wave-level digit matching.
+// One stable 8-bit LSD pass of the whole workgroup. Wave w owns a contiguous
+// segment of the input: per-wave digit counts, one scan in (digit, wave)
+// order, then every wave places its segment in order without further
+// workgroup barriers (64 elements at a time, ranked within the wave by
+// matching digits through ballots; four chunks' loads in flight).
 __device__ __forceinline__ void wg_radix_pass(Ctx &c, const uint64_t *kin, const int32_t *iin,
                                               uint64_t *kout, int32_t *iout, int64_t n,
                                               int shift) {
-    unsigned long long *base = (unsigned long long *)c.dyn;  // [256]
-    int32_t *wc = (int32_t *)(c.dyn + 256 * 8);              // [NW][256]
+    int32_t *cnt = (int32_t *)c.dyn;  // [NW][256] counts, then running offsets
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t seg = ((n + NW - 1) / NW + 63) & ~(int64_t)63;
+    const int64_t lo = min(n, wid * seg), hi = min(n, lo + seg);
     __syncthreads();
-    for (int i = threadIdx.x; i < 256; i += NT) base[i] = 0;
+    for (int i = threadIdx.x; i < NW * 256; i += NT) cnt[i] = 0;
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < n; i += NT)
-        atomicAdd(&base[(kin[i] >> shift) & 255], 1ull);
+    for (int64_t i = lo + lane; i < hi; i += 64) atomicAdd(&cnt[wid * 256 + ((kin[i] >> shift) & 255)], 1);
     __syncthreads();
-    const int64_t v = threadIdx.x < 256 ? (int64_t)base[threadIdx.x] : 0;
-    int64_t tot;
-    const int64_t ex = block_excl_scan(v, c.s->sh, &tot);
-    if (threadIdx.x < 256) base[threadIdx.x] = (unsigned long long)ex;
-    __syncthreads();
-    for (int64_t c0 = 0; c0 < n; c0 += NT) {
-        for (int i = threadIdx.x; i < NW * 256; i += NT) wc[i] = 0;
-        __syncthreads();
-        const int64_t i = c0 + threadIdx.x;
-        const bool valid = i < n;
-        const uint64_t kv = valid ? kin[i] : 0ull;
-        const int d = (int)((kv >> shift) & 255);
-        uint64_t peers = __ballot(valid);
+    {
+        // digit-major exclusive scan; thread d < 256 owns digit d
+        int32_t col[NW];
+        int64_t sum = 0;
+        if (threadIdx.x < 256)
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const uint64_t m = __ballot((d >> b) & 1);
-            peers &= ((d >> b) & 1) ? m : ~m;
-        }
-        const int rk = __popcll(peers & lanemask_lt(lane));
-        if (valid && rk == 0) wc[wid * 256 + d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            int64_t p = (int64_t)base[d] + rk;
-            for (int w = 0; w < wid; ++w) p += wc[w * 256 + d];
-            kout[p] = kv;
-            iout[p] = iin[i];
-        }
-        __syncthreads();
-        if (threadIdx.x < 256) {
-            int64_t add = 0;
-            for (int w = 0; w < NW; ++w) add += wc[w * 256 + threadIdx.x];
-            base[threadIdx.x] += (unsigned long long)add;
-        }
-        __syncthreads();
+            for (int w = 0; w < NW; ++w) {
+                col[w] = cnt[w * 256 + threadIdx.x];
+                sum += col[w];
+            }
+        int64_t tot;
+        int64_t run = block_excl_scan(sum, c.s->sh, &tot);
+        if (threadIdx.x < 256)
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                cnt[w * 256 + threadIdx.x] = (int32_t)run;
+                run += col[w];
+            }
     }
+    __syncthreads();
+    int32_t *mine = cnt + wid * 256;
+    for (int64_t b = lo; b < hi; b += 256) {
+        uint64_t kv[4];
+        int32_t iv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = b + q * 64 + lane;
+            kv[q] = i < hi ? kin[i] : 0ull;
+            iv[q] = i < hi ? iin[i] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool valid = b + q * 64 + lane < hi;
+            const int d = (int)((kv[q] >> shift) & 255);
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const uint64_t m = __ballot((d >> t) & 1);
+                peers &= ((d >> t) & 1) ? m : ~m;
+            }
+            const int rk = __popcll(peers & lanemask_lt(lane));
+            if (valid) {
+                const int64_t p = (int64_t)mine[d] + rk;
+                kout[p] = kv[q];
+                iout[p] = iv[q];
+            }
+            // every lane has read its offset before the digit's first lane
+            // advances it (one wave, program order)
+            if (valid && rk == 0) mine[d] += __popcll(peers);
+        }
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -741,6 +1114,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
     }
     __syncthreads();
     mark(c, 0);
+    ev(c, SGM_EV_START);
     // root candidates
     const int root = Q.root;
     if (Q.root_slot < 0) {
@@ -756,13 +1130,18 @@ __device__ __forceinline__ void run_query(Ctx &c) {
     } else {
         list_from_bits(c, root, c.rootbits + (int64_t)Q.root_slot * g.nwords, true);
     }
+    ev(c, SGM_EV_ROOT);
     // explore along the spanning tree, then refinement rounds
-    for (int i = 0; i < Q.n_init && !aborted(c); ++i) filter_step(c, Q.steps[i]);
+    for (int i = 0; i < Q.n_init && !aborted(c); ++i) {
+        filter_step(c, Q.steps[i]);
+        ev(c, SGM_EV_EXPLORE);
+    }
     const int rounds = Q.refine_rounds < 0 ? 32 : Q.refine_rounds;
     for (int r = 0; r < rounds && !aborted(c) && Q.n_ref > 0; ++r) {
         int removed = 0;
         for (int i = 0; i < Q.n_ref && !aborted(c); ++i) {
             filter_step(c, Q.steps[Q.n_init + i]);
+            ev(c, SGM_EV_REFINE);
             removed += s.removed;  // read after the step's final barrier
             __syncthreads();
         }
@@ -788,6 +1167,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
     int32_t *table = nullptr;
     if (!s.empty) {
         for (int u = 0; u < n && !aborted(c); ++u) sort_list(c, u);
+        ev(c, SGM_EV_LISTS);
         if (Q.m == 0) {
             table = c.L(0);
             rows = s.cnt[0];
@@ -798,7 +1178,10 @@ __device__ __forceinline__ void run_query(Ctx &c) {
             __syncthreads();
         } else if (!aborted(c)) {
             // candidate edges keyed by each edge's source: totals for the order
-            for (int e = 0; e < Q.m && !aborted(c); ++e) ec_build(c, e, Q.esrc[e], Q.edst[e], 0);
+            for (int e = 0; e < Q.m && !aborted(c); ++e) {
+                ec_build(c, e, Q.esrc[e], Q.edst[e], 0);
+                ev(c, SGM_EV_EDGES);
+            }
             __syncthreads();
             bool none = false;
             for (int e = 0; e < Q.m; ++e) none |= s.ectot[e] == 0;
@@ -807,9 +1190,13 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                     for (int e = 0; e < Q.m; ++e) s.ecbuilt[e] = s.eckey[e];
                 join_order(c);
                 __syncthreads();
+                ev(c, SGM_EV_ORDER);
                 // edges the join looks up by their destination: rebuild keyed so
                 for (int e = 0; e < Q.m && !aborted(c); ++e)
-                    if (s.eckey[e] != s.ecbuilt[e]) ec_build(c, e, Q.edst[e], Q.esrc[e], 1);
+                    if (s.eckey[e] != s.ecbuilt[e]) {
+                        ec_build(c, e, Q.edst[e], Q.esrc[e], 1);
+                        ev(c, SGM_EV_EDGES);
+                    }
                 __syncthreads();
                 // join levels
                 mark(c, 2);
@@ -913,6 +1300,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                     if (threadIdx.x == 0 && !s.abort_)
                         s.slab_used = (int64_t)((char *)out - c.slab) + rows * 4 * (k + 1);
                     __syncthreads();
+                    ev(c, SGM_EV_LEVEL);
                     table = out;
                     ++k;
                 }
@@ -1018,6 +1406,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
             if (threadIdx.x == 0) add_bytes(c, 24ull * rows * ((tb + 7) / 8));
             idx = ia;
         }
+        ev(c, SGM_EV_SORT);
         if (threadIdx.x == 0) {
             const unsigned long long need = (unsigned long long)rows * n;
             const unsigned long long off = atomicAdd(c.out_used, need);
@@ -1028,14 +1417,21 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         if (off < 0) {
             if (threadIdx.x == 0) s.status = kOutFull;
         } else {
-            for (int64_t t = threadIdx.x; t < rows * n; t += NT) {
-                const int64_t i = t / n;
-                const int cc = (int)(t - i * n);
-                c.out[off + t] = table[(int64_t)idx[i] * k + s.jpos[cc]];
+            // one row per thread: its columns back in query-vertex order
+            int32_t jp[SGM_MAX_QV];
+#pragma unroll
+            for (int cc = 0; cc < SGM_MAX_QV; ++cc) jp[cc] = cc < n ? s.jpos[cc] : 0;
+            for (int64_t i = threadIdx.x; i < rows; i += NT) {
+                const int32_t *src = table + (int64_t)idx[i] * k;
+                int32_t *dst = c.out + off + i * n;
+#pragma unroll
+                for (int cc = 0; cc < SGM_MAX_QV; ++cc)
+                    if (cc < n) dst[cc] = src[jp[cc]];
             }
             if (threadIdx.x == 0) add_bytes(c, 20ull * rows * n);
         }
     }
+    ev(c, SGM_EV_OUTPUT);
     clear_slot(c, false);
     mark(c, 4);
 }
@@ -1056,7 +1452,9 @@ __global__ __launch_bounds__(NT) void k_narrow(NArgs a) {
         const NQuery &Q = a.qs[q];
         NResult &R = a.res[q];
         Ctx c{a.g,  a.lcap, a.slab_bytes, a.out, a.out_cap, a.out_used, a.rootbits, &Q, &s,
-              bits, bits + (int64_t)SGM_MAX_QV * nwords, lists, slab, dyn};
+              bits, bits + (int64_t)SGM_MAX_QV * nwords, lists, slab, dyn,
+              a.trace ? a.trace + (int64_t)q * SGM_TRACE_CAP : nullptr};
+        if (threadIdx.x == 0) s.nev = 0;
         run_query(c);
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1097,13 +1495,11 @@ __global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const NQuery *qs
     for (int32_t w = wave; w < g.nwords; w += nwaves) {
         const int32_t v = w * 64 + lane;
         const bool inr = v < g.V;
-        const int32_t t = inr ? g.vtype[v] : -2;
-        const int32_t od = inr ? g.out_off[v + 1] - g.out_off[v] : -1;
-        const int32_t id = inr ? g.in_off[v + 1] - g.in_off[v] : -1;
+        const int2 vi = inr ? g.vinfo[v] : make_int2(0, 0);
         for (int32_t j = 0; j < n_root; ++j) {
             const NQuery &Q = qs[root_q[j]];
             const VPred p = Q.pred[Q.root];
-            const bool ok = inr && (p.label < 0 || p.label == t) && od >= p.qout && id >= p.qin;
+            const bool ok = inr && vinfo_ok(p, vi);
             const uint64_t b = __ballot(ok);
             if (lane == 0) rootbits[(int64_t)j * g.nwords + w] = b;
         }

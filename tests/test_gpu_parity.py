@@ -156,8 +156,12 @@ def test_tiny_large_outputs(name, q, path, tiny_kg, oracle_tiny):
         assert st["path"] == P.SGM_PATH_WIDE and st["fallback"] in (1, 2, 4, 8, 16)
         ga.close()
     same(got, want)
-    if path == P.SGM_PATH_NARROW and st["path"] == P.SGM_PATH_NARROW:
-        assert st["fallback"] == 0
+    if st["path"] == P.SGM_PATH_NARROW:
+        # 0: a regular slot; otherwise the reason it moved to a large slot
+        assert st["fallback"] in (0, 1, 2, 8)
+    if name == "square" and path != P.SGM_PATH_WIDE:
+        # a 0.9M-row level outgrows the tiny graph's 8 MB slot, fits a large one
+        assert st["path"] == P.SGM_PATH_NARROW and st["fallback"] == 2
     g.close()
 
 
