@@ -140,6 +140,14 @@ def bench_medium(args, P, kggen):
         g.match_batch(queries)
     el_b = time.perf_counter() - t
     log(f"batch path {el_b:.3f}s")
+    # the same batches with separate launches instead of one HIP graph
+    gd = P.Graph.from_kg(kg, graphs=0)
+    gd.match_batch(queries)
+    t = time.perf_counter()
+    for i in range(args.steps):
+        gd.match_batch(queries)
+    el_bd = time.perf_counter() - t
+    gd.close()
 
     served = served_leg(P, kggen, g, queries,
                         [float(x) for x in args.serve_rates.split(",") if x],
@@ -181,6 +189,7 @@ def bench_medium(args, P, kggen):
         "embeddings_per_s": round(rows / el, 1),
         "latency_ms": {"p50": round(p50, 3), "p99": round(p99, 3)},
         "batch_api_queries_per_s": round(nq / el_b, 3),
+        "batch_api_queries_per_s_no_graph": round(nq / el_bd, 3),
         "served": served,
         "persistent_kernel_phase_us": phases,
         "roofline": roofline(ks),

@@ -63,7 +63,11 @@ typedef struct {
                                   (sgm_trace_events) */
     int32_t path;              /* SGM_PATH_AUTO (default), SGM_PATH_WIDE or
                                   SGM_PATH_NARROW (see below) */
-    int32_t reserved[6];
+    int32_t graphs;            /* 1 (default): a persistent-kernel batch (upload,
+                                  root sweep, kernel, readback) is one HIP graph
+                                  launch; 0: separate launches. Not used while
+                                  profile != 0 (kernels are timed one by one) */
+    int32_t reserved[5];
 } sgm_options;
 
 /* Execution paths. NARROW: one persistent kernel in which each workgroup

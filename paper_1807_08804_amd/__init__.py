@@ -40,7 +40,7 @@ class sgm_options(ctypes.Structure):
                 ("refine_reversed", ctypes.c_int32), ("low_conn_degree", ctypes.c_int32),
                 ("result_cap_rows", ctypes.c_int64), ("join_budget_bytes", ctypes.c_int64),
                 ("profile", ctypes.c_int32), ("path", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("graphs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class sgm_query(ctypes.Structure):
@@ -227,16 +227,38 @@ def sgm_plan_query(n, vlabel, vpin, esrc, edst, elabel, n_vertices, type_freq):
 
 # --- numpy convenience ----------------------------------------------------------------
 
-def _result_to_numpy(r, n):
+class _ResultOwner:
+    """Keeps one library result alive while numpy arrays view its rows."""
+
+    __slots__ = ("r",)
+
+    def __init__(self, r):
+        self.r = r
+
+    def __del__(self):
+        r, self.r = self.r, None
+        if r is not None:
+            try:
+                sgm_free_result(r)
+            except Exception:  # interpreter shutdown
+                pass
+
+
+def _take_rows(r, n):
+    """(row count, rows) of a result, taking ownership of r: rows is an
+    (n_rows, n) int32 array viewing the library's buffer without a copy (the
+    result is freed when the last view of it goes), or None for count-only
+    results."""
     res = r.contents
     k = int(res.n_rows)
-    if res.rows:
-        out = np.empty((k, n), np.int32)
-        if k:
-            ctypes.memmove(out.ctypes.data, res.rows, k * n * 4)
-    else:
-        out = None
-    return k, out
+    if not res.rows or k == 0:
+        out = np.empty((k, n), np.int32) if res.rows else None
+        sgm_free_result(r)
+        return k, out
+    addr = ctypes.cast(res.rows, ctypes.c_void_p).value
+    buf = (ctypes.c_int32 * (k * n)).from_address(addr)
+    buf._owner = _ResultOwner(r)
+    return k, np.frombuffer(buf, np.int32).reshape(k, n)
 
 
 def stats_dict(st: sgm_stats, n: int, m: int) -> dict:
@@ -293,10 +315,11 @@ class Graph:
                 sgm_free_result(r)
             raise err
         try:
-            k, rows = _result_to_numpy(r, n)
             st = stats_dict(r.contents.stats, n, len(keep[2][0]))
-        finally:
+        except Exception:
             sgm_free_result(r)
+            raise
+        k, rows = _take_rows(r, n)
         out = k if count_only else rows
         return (out, st) if with_stats else out
 
@@ -315,14 +338,14 @@ class Graph:
         res, stats = [], []
         for q, r in zip(queries, outs):
             st = r.contents.status
-            if st != SGM_OK:
-                res.append(SGMError(st, "batch member"))
-            else:
-                k, rows = _result_to_numpy(r, q.n)
-                res.append(k if count_only else rows)
             if with_stats:
                 stats.append(stats_dict(r.contents.stats, q.n, len(q.esrc)))
-            sgm_free_result(r)
+            if st != SGM_OK:
+                res.append(SGMError(st, "batch member"))
+                sgm_free_result(r)
+            else:
+                k, rows = _take_rows(r, q.n)
+                res.append(k if count_only else rows)
         return (res, stats) if with_stats else res
 
     def inspect_query(self, q):
@@ -417,13 +440,13 @@ class Server:
         rc = lib().sgm_wait(self._h, ticket, timeout_ns, ctypes.byref(out))
         if rc != SGM_OK:
             raise SGMError(rc, "sgm_wait")
-        try:
-            st = out.contents.status
-            k, rows = _result_to_numpy(out, n_cols)
-            stats = stats_dict(out.contents.stats, n_cols, 0)
-        finally:
+        st = out.contents.status
+        stats = stats_dict(out.contents.stats, n_cols, 0)
+        if st != SGM_OK:
             sgm_free_result(out)
-        return st, (rows if st == SGM_OK else None), stats
+            return st, None, stats
+        k, rows = _take_rows(out, n_cols)
+        return st, rows, stats
 
     def stats(self) -> dict:
         s = sgm_serve_stats()
@@ -451,11 +474,11 @@ class Server:
                     continue
                 st = r.contents.status
                 if st == SGM_OK:
-                    k, rows = _result_to_numpy(r, q.n)
+                    k, rows = _take_rows(r, q.n)
                     res.append(k if count_only else rows)
                 else:
                     res.append(SGMError(st, "served query"))
-                sgm_free_result(r)
+                    sgm_free_result(r)
         if rc != SGM_OK:
             raise SGMError(rc, "sgm_serve_replay")
         return lat, res

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -164,7 +165,7 @@ struct NarrowCtx {
     int qcap = 0;
     NQuery *d_q = nullptr, *h_q = nullptr;
     NResult *d_res = nullptr, *h_res = nullptr;
-    int32_t *d_root_q = nullptr, *h_root_q = nullptr;
+    VPred *d_preds = nullptr, *h_preds = nullptr;  // distinct root predicates
     int root_cap = 0;
     uint64_t *d_rootbits = nullptr;
     int32_t *d_out = nullptr;
@@ -175,6 +176,15 @@ struct NarrowCtx {
     int64_t *d_trace = nullptr, *h_trace = nullptr;  // [trace_cap][SGM_TRACE_CAP]
     int trace_cap = 0;
     hipEvent_t done = nullptr;
+    // one batch as a HIP graph: upload descriptors, upload root predicates,
+    // root sweep, persistent kernel, read back results, read back counters.
+    // Built on first use; every launch updates all node parameters.
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipGraphNode_t gn[6] = {};
+    SweepArgs sa{};
+    NArgs na{};
+    void *kargs[7] = {};
 };
 
 }  // namespace
@@ -1013,19 +1023,23 @@ void narrow_free(NarrowCtx &nw) {
     dev_free(nw.slab);
     dev_free(nw.d_q);
     dev_free(nw.d_res);
-    dev_free(nw.d_root_q);
+    dev_free(nw.d_preds);
     dev_free(nw.d_rootbits);
     dev_free(nw.d_out);
     dev_free(nw.d_ctr);
     host_free(nw.h_q);
     host_free(nw.h_res);
-    host_free(nw.h_root_q);
+    host_free(nw.h_preds);
     host_free(nw.h_ctr);
     host_free(nw.h_out);
     dev_free(nw.d_trace);
     host_free(nw.h_trace);
     if (nw.done) (void)hipEventDestroy(nw.done);
     nw.done = nullptr;
+    if (nw.gexec) (void)hipGraphExecDestroy(nw.gexec);
+    if (nw.graph) (void)hipGraphDestroy(nw.graph);
+    nw.gexec = nullptr;
+    nw.graph = nullptr;
     const NarrowCtx keep = nw;
     nw = NarrowCtx{};
     nw.stream = keep.stream;
@@ -1071,12 +1085,12 @@ void narrow_reserve(sgm_graph *g, NarrowCtx &nw, int slots, int nq, int nroot) {
     }
     if (nroot > nw.root_cap) {
         HIPX(hipStreamSynchronize(nw.stream));
-        dev_free(nw.d_root_q);
+        dev_free(nw.d_preds);
         dev_free(nw.d_rootbits);
-        host_free(nw.h_root_q);
+        host_free(nw.h_preds);
         nw.root_cap = 0;
-        HIPX(hipMalloc(&nw.d_root_q, sizeof(int32_t) * nroot));
-        HIPX(hipHostMalloc(&nw.h_root_q, sizeof(int32_t) * nroot, hipHostMallocDefault));
+        HIPX(hipMalloc(&nw.d_preds, sizeof(VPred) * nroot));
+        HIPX(hipHostMalloc(&nw.h_preds, sizeof(VPred) * nroot, hipHostMallocDefault));
         HIPX(hipMalloc(&nw.d_rootbits, sizeof(uint64_t) * (size_t)g->nwords * nroot));
         nw.root_cap = nroot;
     }
@@ -1108,6 +1122,8 @@ bool pack_query(sgm_graph *g, const QInfo &qi, const Plan &pl, NQuery *nq, int *
         nq->elabel[e] = qi.elabel[e];
     }
     nq->root = pl.visit[0];
+    // unpinned roots get their bitmap row from the batch's root sweep; the
+    // row is assigned per distinct predicate after packing
     nq->root_slot = qi.pin[nq->root] >= 0 ? -1 : (*root_slot_next)++;
     nq->n_init = (int)pr.init.size();
     nq->n_ref = (int)pr.refine.size();
@@ -1189,23 +1205,38 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
             res[which[i]]->stats.fallback = 16;
         }
     }
-    job.nroot = nroot;
     const int np = (int)job.packed.size();
     if (np == 0) return false;
-    narrow_reserve(g, nw, std::min(np, max_slots), np, nroot);
-    int k = 0;
-    for (int i = 0; i < np; ++i)
-        if (nw.h_q[i].root_slot >= 0) nw.h_root_q[k++] = i;
-    hipStream_t st = nw.stream;
-    HIPX(hipMemcpyAsync(nw.d_q, nw.h_q, sizeof(NQuery) * np, hipMemcpyHostToDevice, st));
-    if (nroot)
-        HIPX(hipMemcpyAsync(nw.d_root_q, nw.h_root_q, sizeof(int32_t) * nroot,
-                            hipMemcpyHostToDevice, st));
-    HIPX(hipMemsetAsync(nw.d_ctr, 0, sizeof(unsigned long long) * 2, st));
-    if (nroot) {
-        Prof p(g, SGM_K_CHECK, (8.0 + 0.125 * nroot) * g->V, profiled);
-        launch_root_sweep(st, g->dg, nw.d_q, nw.d_root_q, nroot, nw.d_rootbits);
+    // one sweep row per distinct root predicate (type, degree bounds), rows
+    // in (type, bounds) order with the untyped (-1) ones first, as the
+    // sweep expects
+    std::map<std::array<int32_t, 3>, int> row_of;
+    for (int i = 0; i < np; ++i) {
+        const NQuery &q = nw.h_q[i];
+        if (q.root_slot < 0) continue;
+        const VPred &p = q.pred[q.root];
+        row_of.emplace(std::array<int32_t, 3>{p.label, p.qout, p.qin}, 0);
     }
+    std::vector<VPred> preds;
+    int n_any = 0;
+    for (auto &kv : row_of) {
+        kv.second = (int)preds.size();
+        preds.push_back(VPred{kv.first[0], -1, kv.first[1], kv.first[2]});
+        if (kv.first[0] < 0) ++n_any;
+    }
+    for (int i = 0; i < np; ++i) {
+        NQuery &q = nw.h_q[i];
+        if (q.root_slot < 0) continue;
+        const VPred &p = q.pred[q.root];
+        q.root_slot = row_of[std::array<int32_t, 3>{p.label, p.qout, p.qin}];
+    }
+    nroot = (int)preds.size();
+    job.nroot = nroot;
+    // at least one predicate row, so that a graph's copy node never has size 0
+    narrow_reserve(g, nw, std::min(np, max_slots), np, std::max(nroot, 1));
+    if (nroot) std::memcpy(nw.h_preds, preds.data(), sizeof(VPred) * nroot);
+    else nw.h_preds[0] = VPred{-1, -1, 0, 0};
+    hipStream_t st = nw.stream;
     NArgs a{};
     a.g = g->dg;
     a.qs = nw.d_q;
@@ -1221,7 +1252,49 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     a.out = nw.d_out;
     a.out_cap = nw.out_cap;
     a.out_used = nw.d_ctr + 1;
+    nw.sa = SweepArgs{g->dg, nw.d_preds, nroot, n_any, nw.d_rootbits, nw.d_ctr};
+    const int grid = std::min(np, nw.slots);
     job.traced = profiled && g->opts.profile >= 2;
+    if (g->opts.graphs && !(profiled && g->opts.profile)) {
+        nw.na = a;
+        hipKernelNodeParams ps, pn;
+        narrow_node_params(&nw.sa, &nw.na, grid, nw.kargs, &ps, &pn);
+        const size_t qb = sizeof(NQuery) * np, pb = sizeof(VPred) * std::max(nroot, 1);
+        const size_t rb = sizeof(NResult) * np, cb = sizeof(unsigned long long) * 2;
+        const auto H2D = hipMemcpyHostToDevice, D2H = hipMemcpyDeviceToHost;
+        if (!nw.gexec) {
+            HIPX(hipGraphCreate(&nw.graph, 0));
+            HIPX(hipGraphAddMemcpyNode1D(&nw.gn[0], nw.graph, nullptr, 0, nw.d_q, nw.h_q, qb, H2D));
+            HIPX(hipGraphAddMemcpyNode1D(&nw.gn[1], nw.graph, &nw.gn[0], 1, nw.d_preds, nw.h_preds,
+                                         pb, H2D));
+            HIPX(hipGraphAddKernelNode(&nw.gn[2], nw.graph, &nw.gn[1], 1, &ps));
+            HIPX(hipGraphAddKernelNode(&nw.gn[3], nw.graph, &nw.gn[2], 1, &pn));
+            HIPX(hipGraphAddMemcpyNode1D(&nw.gn[4], nw.graph, &nw.gn[3], 1, nw.h_res, nw.d_res, rb,
+                                         D2H));
+            HIPX(hipGraphAddMemcpyNode1D(&nw.gn[5], nw.graph, &nw.gn[4], 1, nw.h_ctr, nw.d_ctr, cb,
+                                         D2H));
+            HIPX(hipGraphInstantiate(&nw.gexec, nw.graph, nullptr, nullptr, 0));
+        } else {
+            HIPX(hipGraphExecMemcpyNodeSetParams1D(nw.gexec, nw.gn[0], nw.d_q, nw.h_q, qb, H2D));
+            HIPX(hipGraphExecMemcpyNodeSetParams1D(nw.gexec, nw.gn[1], nw.d_preds, nw.h_preds, pb,
+                                                   H2D));
+            HIPX(hipGraphExecKernelNodeSetParams(nw.gexec, nw.gn[2], &ps));
+            HIPX(hipGraphExecKernelNodeSetParams(nw.gexec, nw.gn[3], &pn));
+            HIPX(hipGraphExecMemcpyNodeSetParams1D(nw.gexec, nw.gn[4], nw.h_res, nw.d_res, rb, D2H));
+            HIPX(hipGraphExecMemcpyNodeSetParams1D(nw.gexec, nw.gn[5], nw.h_ctr, nw.d_ctr, cb, D2H));
+        }
+        HIPX(hipGraphLaunch(nw.gexec, st));
+        HIPX(hipEventRecord(nw.done, st));
+        return true;
+    }
+    HIPX(hipMemcpyAsync(nw.d_q, nw.h_q, sizeof(NQuery) * np, hipMemcpyHostToDevice, st));
+    if (nroot)
+        HIPX(hipMemcpyAsync(nw.d_preds, nw.h_preds, sizeof(VPred) * nroot, hipMemcpyHostToDevice,
+                            st));
+    {
+        Prof p(g, SGM_K_CHECK, nroot ? (8.0 + 0.125 * nroot) * g->V : 0.0, profiled && nroot > 0);
+        launch_root_sweep(st, nw.sa);
+    }
     if (job.traced) {
         if (np > nw.trace_cap) {
             HIPX(hipStreamSynchronize(st));
@@ -1238,7 +1311,7 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     }
     {
         Prof p(g, SGM_K_PERSIST, 0.0, profiled);
-        launch_narrow(st, a, std::min(np, nw.slots));
+        launch_narrow(st, a, grid);
     }
     if (job.traced)
         HIPX(hipMemcpyAsync(nw.h_trace, nw.d_trace, sizeof(int64_t) * SGM_TRACE_CAP * np,
@@ -1248,6 +1321,41 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
                         st));
     HIPX(hipEventRecord(nw.done, st));
     return true;
+}
+
+struct HostCopy {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+
+// Host copies of a batch's result tables out of the pinned staging buffer;
+// large totals are split over threads (first touch of the fresh result
+// buffers is part of the cost).
+void parallel_copy(const std::vector<HostCopy> &cs) {
+    size_t total = 0;
+    for (const HostCopy &c : cs) total += c.bytes;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nt = (int)std::min<size_t>({(size_t)8, (size_t)hw, total >> 23});  // 8 MB each
+    if (nt <= 1) {
+        for (const HostCopy &c : cs) std::memcpy(c.dst, c.src, c.bytes);
+        return;
+    }
+    // cut the concatenated bytes into nt equal ranges
+    const size_t per = (total + nt - 1) / nt;
+    auto work = [&](size_t lo, size_t hi) {
+        size_t pos = 0;
+        for (const HostCopy &c : cs) {
+            const size_t a = std::max(lo, pos), b = std::min(hi, pos + c.bytes);
+            if (a < b) std::memcpy((char *)c.dst + (a - pos), (const char *)c.src + (a - pos), b - a);
+            pos += c.bytes;
+            if (pos >= hi) break;
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work, per * t, std::min(total, per * (t + 1)));
+    work(0, std::min(total, per));
+    for (auto &x : th) x.join();
 }
 
 // Wait for a launched job and fill the results of its finished queries;
@@ -1277,6 +1385,7 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         HIPX(hipStreamSynchronize(st));
     }
     const int64_t t1 = now_ns();
+    std::vector<HostCopy> copies;
     if (job.traced)
         for (int i = 0; i < np; ++i) {
             const size_t q = (size_t)job.packed[i];
@@ -1327,9 +1436,10 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
             const size_t bytes = sizeof(int32_t) * (size_t)r.n_rows * qi.n;
             out->rows = (int32_t *)std::malloc(std::max<size_t>(bytes, 4));
             if (!out->rows) throw std::bad_alloc();
-            if (bytes) std::memcpy(out->rows, nw.h_out + r.offset, bytes);
+            if (bytes) copies.push_back({out->rows, nw.h_out + r.offset, bytes});
         }
     }
+    parallel_copy(copies);
 }
 
 // Run queries `which` (validated into qis) through the persistent kernel on
@@ -1446,6 +1556,7 @@ void sgm_default_options(sgm_options *o) {
     o->result_cap_rows = 0;
     o->join_budget_bytes = 0;
     o->profile = 0;
+    o->graphs = 1;
 }
 
 const char *sgm_strerror(int code) {

@@ -84,10 +84,25 @@ struct NArgs {
     int64_t *trace;           // [nq][SGM_TRACE_CAP] step events, or null
 };
 
-// root sweep: rootbits[j][w] for every query whose root is unpinned
-void launch_root_sweep(hipStream_t s, const DevGraph &g, const NQuery *qs, const int32_t *root_q,
-                       int32_t n_root, uint64_t *rootbits);
+// Root sweep: rootbits[j][w] = vertices satisfying predicate j, for the
+// distinct predicates of a batch's unpinned roots. It also zeroes ctr[0..1]
+// (the persistent kernel's work queue and output-arena use), so it runs
+// before every persistent launch, with n_pred = 0 when no root needs it.
+struct SweepArgs {
+    DevGraph g;
+    const VPred *preds;   // untyped first, then by type
+    int32_t n_pred;
+    int32_t n_any;        // predicates without a type
+    uint64_t *rootbits;
+    unsigned long long *ctr;
+};
+void launch_root_sweep(hipStream_t s, const SweepArgs &a);
 void launch_narrow(hipStream_t s, const NArgs &a, int grid);
+// Kernel-node parameters of the sweep and of the persistent kernel for a
+// HIP graph. The argument pointers refer to *sa, *na and args[0..6], which
+// must stay valid until the parameters have been handed to HIP.
+void narrow_node_params(SweepArgs *sa, NArgs *na, int narrow_grid, void **args,
+                        hipKernelNodeParams *sweep, hipKernelNodeParams *narrow);
 size_t narrow_lds_bytes();
 
 }  // namespace sgm

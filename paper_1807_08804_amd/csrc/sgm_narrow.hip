@@ -18,6 +18,8 @@
 // slot and reports kNeedWide; the host then runs the multi-kernel path.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sgm_device.h"
 #include "sgm_narrow.h"
 
@@ -1486,23 +1488,73 @@ __global__ __launch_bounds__(NT) void k_narrow(NArgs a) {
 // unpinned root
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const NQuery *qs,
-                                                    const int32_t *root_q, int32_t n_root,
-                                                    uint64_t *rootbits) {
-    const int lane = threadIdx.x & 63;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
-    for (int32_t w = wave; w < g.nwords; w += nwaves) {
-        const int32_t v = w * 64 + lane;
-        const bool inr = v < g.V;
-        const int2 vi = inr ? g.vinfo[v] : make_int2(0, 0);
-        for (int32_t j = 0; j < n_root; ++j) {
-            const NQuery &Q = qs[root_q[j]];
-            const VPred p = Q.pred[Q.root];
-            const bool ok = inr && vinfo_ok(p, vi);
-            const uint64_t b = __ballot(ok);
-            if (lane == 0) rootbits[(int64_t)j * g.nwords + w] = b;
+// Candidate initialisation for the unpinned roots of a batch (Alg. 3.2
+// kernel_check, one sweep for all of them): bitmap row j holds the vertices
+// that satisfy root predicate j. Predicates come sorted: the n_any of them
+// without a type first, the typed ones by type. A block owns a tile of 64
+// bitmap words (4096 vertices, 16 per thread, kept in registers after one
+// coalesced read). Per chunk of predicates the tile's rows are built in LDS:
+// untyped predicates by ballot, typed ones by each vertex OR-ing its bit
+// into the rows of the predicates of its own type only (found by binary
+// search), so a vertex is tested against about n_pred / (number of types)
+// predicates instead of all of them. Rows then leave as 512-byte runs.
+constexpr int kSweepTile = 64;    // bitmap words per block
+constexpr int kSweepChunk = 64;   // predicates per LDS pass (32 KB of rows)
+
+__global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *preds, int32_t n_pred,
+                                                    int32_t n_any, uint64_t *rootbits,
+                                                    unsigned long long *ctr) {
+    if (blockIdx.x == 0 && threadIdx.x < 2) ctr[threadIdx.x] = 0ull;
+    if (n_pred == 0) return;
+    __shared__ uint64_t rows[kSweepChunk * kSweepTile];
+    __shared__ VPred pl[kSweepChunk];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int32_t w0 = blockIdx.x * kSweepTile;
+    // vertex of slot i: word w0 + 16 * wid + i, bit lane
+    int2 vi[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int64_t v = (int64_t)(w0 + 16 * wid + i) * 64 + lane;
+        vi[i] = v < g.V ? g.vinfo[v] : make_int2(-1, -1);  // type -1: past the end
+    }
+    for (int32_t c0 = 0; c0 < n_pred; c0 += kSweepChunk) {
+        const int cn = min(kSweepChunk, n_pred - c0);
+        for (int i = threadIdx.x; i < cn * kSweepTile; i += 256) rows[i] = 0ull;
+        if ((int)threadIdx.x < cn) pl[threadIdx.x] = preds[c0 + threadIdx.x];
+        __syncthreads();
+        // untyped predicates: the same test for every lane
+        for (int j = 0; j < min(n_any - c0, cn); ++j) {
+            const VPred p = pl[j];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const bool ok = vi[i].x >= 0 && (vi[i].y & 255) >= p.qout && (vi[i].y >> 8) >= p.qin;
+                const uint64_t b = __ballot(ok);
+                if (lane == 0) rows[j * kSweepTile + 16 * wid + i] = b;
+            }
         }
+        // typed predicates of this chunk: [t0, cn), sorted by type
+        const int t0 = max(0, n_any - c0);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int32_t t = vi[i].x;
+            if (t < 0 || t0 >= cn) continue;
+            int lo = t0, hi = cn;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (pl[mid].label < t) lo = mid + 1;
+                else hi = mid;
+            }
+            const int od = vi[i].y & 255, id = vi[i].y >> 8;
+            for (int j = lo; j < cn && pl[j].label == t; ++j)
+                if (od >= pl[j].qout && id >= pl[j].qin)
+                    atomicOr((unsigned long long *)&rows[j * kSweepTile + 16 * wid + i], 1ull << lane);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < cn * kSweepTile; k += 256) {
+            const int j = k / kSweepTile, w = k % kSweepTile;
+            if (w0 + w < g.nwords) rootbits[(int64_t)(c0 + j) * g.nwords + w0 + w] = rows[k];
+        }
+        __syncthreads();
     }
 }
 
@@ -1514,12 +1566,41 @@ void launch_narrow(hipStream_t s, const NArgs &a, int grid) {
     hipLaunchKernelGGL(k_narrow, dim3(grid), dim3(NT), kDynLds, s, a);
 }
 
-void launch_root_sweep(hipStream_t s, const DevGraph &g, const NQuery *qs, const int32_t *root_q,
-                       int32_t n_root, uint64_t *rootbits) {
-    int grid = (g.nwords + 3) / 4;
-    if (grid > 4096) grid = 4096;
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_root_sweep, dim3(grid), dim3(256), 0, s, g, qs, root_q, n_root, rootbits);
+namespace {
+int sweep_grid(const SweepArgs &a) {
+    if (a.n_pred == 0) return 1;
+    return std::max(1, (a.g.nwords + kSweepTile - 1) / kSweepTile);
+}
+}  // namespace
+
+void launch_root_sweep(hipStream_t s, const SweepArgs &a) {
+    hipLaunchKernelGGL(k_root_sweep, dim3(sweep_grid(a)), dim3(256), 0, s, a.g, a.preds, a.n_pred,
+                       a.n_any, a.rootbits, a.ctr);
+}
+
+void narrow_node_params(SweepArgs *sa, NArgs *na, int narrow_grid, void **args,
+                        hipKernelNodeParams *sweep, hipKernelNodeParams *narrow) {
+    args[0] = &sa->g;
+    args[1] = &sa->preds;
+    args[2] = &sa->n_pred;
+    args[3] = &sa->n_any;
+    args[4] = &sa->rootbits;
+    args[5] = &sa->ctr;
+    args[6] = na;
+    *sweep = hipKernelNodeParams{};
+    sweep->func = reinterpret_cast<void *>(&k_root_sweep);
+    sweep->gridDim = dim3(sweep_grid(*sa));
+    sweep->blockDim = dim3(256);
+    sweep->sharedMemBytes = 0;
+    sweep->kernelParams = args;
+    sweep->extra = nullptr;
+    *narrow = hipKernelNodeParams{};
+    narrow->func = reinterpret_cast<void *>(&k_narrow);
+    narrow->gridDim = dim3(narrow_grid);
+    narrow->blockDim = dim3(NT);
+    narrow->sharedMemBytes = kDynLds;
+    narrow->kernelParams = args + 6;
+    narrow->extra = nullptr;
 }
 
 }  // namespace sgm

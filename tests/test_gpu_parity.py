@@ -125,6 +125,35 @@ def test_medium_batch(medium_kg, g_medium, medium_queries, medium_expected):
         same(got, want)
 
 
+def test_batch_graph_replays(medium_kg, medium_queries, medium_expected):
+    """Batches launched as HIP graphs (options.graphs = 1, the default) equal
+    separate launches (graphs = 0) and the oracle on every replay, with
+    batches of different sizes and root-sweep needs (node parameters change
+    on each replay) and eager work on the same graph between replays."""
+    say("case: batch graph replays")
+    gg = P.Graph.from_kg(medium_kg, graphs=1)
+    gd = P.Graph.from_kg(medium_kg, graphs=0)
+    pinned_root = [i for i, q in enumerate(medium_queries) if (np.asarray(q.vpin) >= 0).any()]
+    subsets = [list(range(100)), list(range(7)), pinned_root[:10], list(range(50, 100)), [3],
+               list(range(100))]
+    for rep, idx in enumerate(subsets):
+        qs = [medium_queries[i] for i in idx]
+        got = gg.match_batch(qs)
+        direct = gd.match_batch(qs)
+        for i, a, b in zip(idx, got, direct):
+            same(a, medium_expected[i])
+            same(b, medium_expected[i])
+        # eager work between replays: a multi-kernel query and a count-only
+        # single query on the graph that replays
+        q = medium_queries[rep]
+        same(gg.match_query(q), medium_expected[rep])
+        wide = P.Graph.from_kg(medium_kg, path=P.SGM_PATH_WIDE)
+        same(wide.match_query(q), medium_expected[rep])
+        wide.close()
+    gg.close()
+    gd.close()
+
+
 def any_query(n, edges, vlabel=None, vpin=None):
     return MicroQuery(n, [-1] * n if vlabel is None else vlabel,
                       [-1] * n if vpin is None else vpin,
