@@ -149,9 +149,9 @@ def bench_medium(args, P, kggen):
     el_bd = time.perf_counter() - t
     gd.close()
 
-    served = served_leg(P, kggen, g, queries,
-                        [float(x) for x in args.serve_rates.split(",") if x],
-                        args.serve_arrivals)
+    served = None if args.no_serve else served_leg(
+        P, kggen, g, queries, [float(x) for x in args.serve_rates.split(",") if x],
+        args.serve_arrivals)
 
     stl = []
     one_step(g, stats=stl)
@@ -229,9 +229,11 @@ def bench_large(args, P, kggen):
     log("kernel classes (profiled region): " + json.dumps(
         {k: dict(launches=v["launches"], ms=round(v["ms"], 3)) for k, v in ks.items()}))
 
-    sq, _ = kggen.serve_queries(kg, args.serve_queries)
-    log("serve inputs ready")
-    served = served_leg(P, kggen, g, sq, [200.0, 1000.0, 5000.0], args.serve_arrivals)
+    served = None
+    if not args.no_serve:
+        sq, _ = kggen.serve_queries(kg, args.serve_queries)
+        log("serve inputs ready")
+        served = served_leg(P, kggen, g, sq, [200.0, 1000.0, 5000.0], args.serve_arrivals)
     cpu = None if args.no_cpu else cpu_leg(kg, queries, args.cpu_seconds)
     nq = args.steps * len(queries)
     return {
@@ -273,7 +275,21 @@ def main():
     ap.add_argument("--serve-rates", default="1000,5000,20000",
                     help="arrival rates (qps) of the medium served-form measurement")
     ap.add_argument("--serve-arrivals", type=int, default=2000)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-form legs")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (torch), the known-size "
+                         "reference for HBM byte counters, and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe << 18  # int32 elements
+        x = torch.ones(n, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the matcher "
               "has no multi-GPU path in this build.", file=sys.stderr)

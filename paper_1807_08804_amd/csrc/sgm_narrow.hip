@@ -68,6 +68,7 @@ struct Smem {
     int32_t reason;
     int32_t cand[SGM_MAX_QV];
     int32_t bitsn[SGM_MAX_QV];
+    const int32_t *rkl[SGM_MAX_QV];  // list each key column ranks into (LDS copy if it fits)
     int64_t level_rows[SGM_MAX_QV];
     int64_t nrows;
     int64_t offset;
@@ -75,11 +76,18 @@ struct Smem {
     int64_t t[5];              // wall clock at the phase boundaries
 };
 
-// dynamic LDS: sort space
-constexpr size_t kDynLds = sizeof(uint64_t) * kRowSortCap + sizeof(int32_t) * kRowSortCap >
-                                   sizeof(int32_t) * kListSortCap
-                               ? sizeof(uint64_t) * kRowSortCap + sizeof(int32_t) * kRowSortCap
-                               : sizeof(int32_t) * kListSortCap;
+// Dynamic LDS, 54 KB: with the static part a workgroup stays within 64 KB,
+// and two workgroups per CU remain resident (registers allow no more). List
+// sorting uses [0, 32 KB); the final ordering keeps keys and indices
+// (bitonic) or digit counts (radix) in [0, 24 KB) and stages the candidate
+// lists its keys rank into at [24 KB, 54 KB).
+constexpr size_t kDynLds = 54 << 10;
+constexpr size_t kStageOff = 24 << 10;
+constexpr int32_t kStageInts = (int32_t)((kDynLds - kStageOff) / sizeof(int32_t));
+static_assert(sizeof(int32_t) * kListSortCap <= kDynLds, "list sort space");
+static_assert((sizeof(uint64_t) + sizeof(int32_t)) * kRowSortCap <= kStageOff, "row sort space");
+static_assert(kDynLds + sizeof(Smem) <= (64 << 10), "LDS per workgroup");
+static_assert(8 * 256 * sizeof(int32_t) <= kStageOff, "radix counts");
 
 struct Ctx {
     DevGraph g;
@@ -991,10 +999,39 @@ __device__ __forceinline__ bool ec_contains(const Ctx &c, int e, int32_t keyval,
 __device__ __forceinline__ uint64_t row_key(const Ctx &c, const int32_t *row) {
     uint64_t key = 0;
     for (int u = 0; u < c.Q->n; ++u) {
-        const int32_t rk = lower_bound_i32(c.L(u), 0, c.s->cnt[u], row[c.s->jpos[u]]);
-        key = (key << c.s->bitsn[u]) | (uint64_t)rk;
+        const int b = c.s->bitsn[u];
+        if (b == 0) continue;  // a single candidate: rank 0, no bits
+        const int32_t rk = lower_bound_i32(c.s->rkl[u], 0, c.s->cnt[u], row[c.s->jpos[u]]);
+        key = (key << b) | (uint64_t)rk;
     }
     return key;
+}
+
+// Point rkl[u] at the sorted candidate list of every key column, copying
+// the lists into LDS while they fit (binary searches then stay on chip).
+__device__ __forceinline__ void stage_key_lists(Ctx &c) {
+    int32_t *stage = (int32_t *)(c.dyn + kStageOff);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t used = 0;
+        for (int u = 0; u < c.Q->n; ++u) {
+            const int32_t m = c.s->cnt[u];
+            if (c.s->bitsn[u] > 0 && used + m <= kStageInts) {
+                c.s->rkl[u] = stage + used;
+                used += m;
+            } else {
+                c.s->rkl[u] = c.L(u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int u = 0; u < c.Q->n; ++u) {
+        int32_t *dst = const_cast<int32_t *>(c.s->rkl[u]);
+        if (dst == c.L(u)) continue;
+        const int32_t *src = c.L(u);
+        for (int32_t i = threadIdx.x; i < c.s->cnt[u]; i += NT) dst[i] = src[i];
+    }
+    __syncthreads();
 }
 
 // One stable 8-bit LSD pass of the whole workgroup. Wave w owns a contiguous
@@ -1229,7 +1266,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                     }
                     if (threadIdx.x == 0) s.ctr = 0;
                     __syncthreads();
-                    const int lane = threadIdx.x & 63;
+                    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
                     uint64_t jb = 0;  // algorithmic bytes of this thread's rows and pairs
                     for (int64_t rbase = 0; rbase < rows; rbase += NT) {
                         const int64_t r = rbase + threadIdx.x;
@@ -1275,21 +1312,39 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                             }
                             if (pi < tot) jb += 4ull + 4ull * k + 24ull * nchk + (ok ? 4ull * (k + 1) : 0ull);
                             const uint64_t bm = __ballot(ok);
+                            const int nok = __popcll(bm);
                             int32_t base = 0;
                             const int leader = bm ? __builtin_ctzll(bm) : 0;
-                            if (bm && lane == leader) base = atomicAdd(&s.ctr, __popcll(bm));
+                            if (bm && lane == leader) base = atomicAdd(&s.ctr, nok);
                             base = __shfl(base, leader, 64);
+                            // the wave's accepted rows are out[base, base + nok):
+                            // list (parent row, new value) per output row in
+                            // LDS, then copy the rows with consecutive lanes on
+                            // consecutive ints
+                            int32_t *wrr = (int32_t *)c.dyn + wid * 128;
+                            int32_t *wx = wrr + 64;
                             if (ok) {
-                                const int64_t pos = (int64_t)base + __popcll(bm & lanemask_lt(lane));
-                                if (pos < cap) {
-                                    int32_t *dst = out + pos * (k + 1);
-                                    const int32_t *row = table + (rbase + rr) * k;
-                                    for (int cc = 0; cc < k; ++cc) dst[cc] = row[cc];
-                                    dst[k] = x;
-                                } else {
-                                    s.abort_ = kWhySlab;
+                                const int j = __popcll(bm & lanemask_lt(lane));
+                                wrr[j] = rr;
+                                wx[j] = x;
+                            }
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                            __builtin_amdgcn_wave_barrier();
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                            if ((int64_t)base + nok > cap) {
+                                if (lane == 0) s.abort_ = kWhySlab;
+                            } else {
+                                const int w = k + 1;
+                                // e / w by a 16-bit reciprocal: exact for e < 64 w, w <= 16
+                                const uint32_t inv = (65536u + (uint32_t)w - 1u) / (uint32_t)w;
+                                int32_t *dst = out + (int64_t)base * w;
+                                for (int e = lane; e < nok * w; e += 64) {
+                                    const int r = (int)(((uint32_t)e * inv) >> 16);
+                                    const int cc = e - r * w;
+                                    dst[e] = cc < k ? table[(rbase + wrr[r]) * k + cc] : wx[r];
                                 }
                             }
+                            __builtin_amdgcn_wave_barrier();
                         }
                         __syncthreads();
                     }
@@ -1347,6 +1402,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         const int tb = s.ctr;
         const int k = n;
         const int32_t *idx;
+        stage_key_lists(c);
         if (rows <= kRowSortCap) {
             // bitonic network in LDS
             uint64_t *keys = (uint64_t *)c.dyn;
@@ -1419,16 +1475,31 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         if (off < 0) {
             if (threadIdx.x == 0) s.status = kOutFull;
         } else {
-            // one row per thread: its columns back in query-vertex order
-            int32_t jp[SGM_MAX_QV];
+            // one wave per 64 output rows: consecutive lanes write
+            // consecutive ints of the rows, columns back in query-vertex
+            // order; e / n by a 16-bit reciprocal (exact for e < 64 n, n <= 16)
+            const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+            const uint32_t inv = (65536u + (uint32_t)n - 1u) / (uint32_t)n;
+            for (int64_t r0 = (int64_t)wid * 64; r0 < rows; r0 += NT) {
+                const int32_t my = r0 + lane < rows ? idx[r0 + lane] : 0;
+                const int nr = (int)min((int64_t)64, rows - r0);
+                int32_t *dst = c.out + off + r0 * n;
+                const int ne = nr * n;
+                for (int e0 = 0; e0 < ne; e0 += 256) {
+                    // four gathers in flight per lane; every lane takes part
+                    // in the shuffles
+                    int32_t v[4];
 #pragma unroll
-            for (int cc = 0; cc < SGM_MAX_QV; ++cc) jp[cc] = cc < n ? s.jpos[cc] : 0;
-            for (int64_t i = threadIdx.x; i < rows; i += NT) {
-                const int32_t *src = table + (int64_t)idx[i] * k;
-                int32_t *dst = c.out + off + i * n;
+                    for (int q = 0; q < 4; ++q) {
+                        const int e = e0 + q * 64 + lane;
+                        const int r = min(63, (int)(((uint32_t)e * inv) >> 16));
+                        const int32_t src = __shfl(my, r, 64);
+                        v[q] = e < ne ? table[(int64_t)src * k + s.jpos[e - r * n]] : 0;
+                    }
 #pragma unroll
-                for (int cc = 0; cc < SGM_MAX_QV; ++cc)
-                    if (cc < n) dst[cc] = src[jp[cc]];
+                    for (int q = 0; q < 4; ++q)
+                        if (e0 + q * 64 + lane < ne) dst[e0 + q * 64 + lane] = v[q];
+                }
             }
             if (threadIdx.x == 0) add_bytes(c, 20ull * rows * n);
         }
@@ -1438,7 +1509,8 @@ __device__ __forceinline__ void run_query(Ctx &c) {
     mark(c, 4);
 }
 
-__global__ __launch_bounds__(NT) void k_narrow(NArgs a) {
+// at least 4 waves per SIMD (registers <= 128): two workgroups per CU
+__global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
     __shared__ Smem s;
     extern __shared__ unsigned char dyn[];
     const int32_t nwords = a.g.nwords;
