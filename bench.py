@@ -36,7 +36,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def roofline(ks, kernel=None):
+def recorded_traffic(key):
+    """HBM bytes per launch measured with rocprofv3 counters for this
+    workload and kernel (profiles/hbm_traffic.json), or None when there is no
+    record or the kernel sources changed since it was taken."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as f:
+            rec = json.load(f)
+        from paper_1807_08804_amd.prof_summary import kernel_source_hash
+    except (OSError, ValueError, ImportError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    e = rec.get("entries", {}).get(key)
+    return e["bytes_per_launch"] if e else None
+
+
+def roofline(ks, kernel=None, traffic_key=None):
     """Roofline of one kernel class (the dominant one with byte accounting
     if not named) from HIP-event times and algorithmic bytes."""
     if kernel is None:
@@ -45,7 +61,8 @@ def roofline(ks, kernel=None):
     achieved = d["bytes"] / (d["ms"] / 1e3) / 1e9 if d["ms"] > 0 else 0.0
     return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": None, "launches": d["launches"],
+            "traffic": recorded_traffic(traffic_key) if traffic_key else None,
+            "launches": d["launches"],
             "avg_launch_us": round(d["ms"] * 1e3 / max(d["launches"], 1), 3),
             "bytes_per_launch": round(d["bytes"] / max(d["launches"], 1), 1)}
 
@@ -192,7 +209,7 @@ def bench_medium(args, P, kggen):
         "batch_api_queries_per_s_no_graph": round(nq / el_bd, 3),
         "served": served,
         "persistent_kernel_phase_us": phases,
-        "roofline": roofline(ks),
+        "roofline": roofline(ks, "persist", "medium:persist"),
         "cpu_baseline": cpu,
     }
 
@@ -255,8 +272,8 @@ def bench_large(args, P, kggen):
         "embeddings_per_s": round(rows * args.steps / el_b, 1),
         "single_query_queries_per_s": round(len(queries) / el_1, 3),
         "served": served,
-        "roofline": roofline(ks),
-        "roofline_root_sweep": roofline(ks, "check"),
+        "roofline": roofline(ks, "persist", "large:persist"),
+        "roofline_root_sweep": roofline(ks, "check", "large:check"),
         "cpu_baseline": cpu,
     }
 
