@@ -4,6 +4,8 @@
 // only validates, plans, sizes buffers and launches.
 #include <hip/hip_runtime.h>
 
+#include <sys/mman.h>
+
 #include <algorithm>
 #include <array>
 #include <atomic>
@@ -223,6 +225,7 @@ struct sgm_graph {
     int64_t *h_small = nullptr;   // [64] small readbacks
     void *h_rows = nullptr;
     size_t h_rows_cap = 0;
+    hipEvent_t ev_rows[2] = {nullptr, nullptr};  // staging halves of result readback
     DevPool pool;
     std::mutex mu;
     // profiling
@@ -365,6 +368,8 @@ void free_graph_mem(sgm_graph *g) {
         g->ev_free.push_back(p.b);
     }
     for (hipEvent_t e : g->ev_free) (void)hipEventDestroy(e);
+    for (hipEvent_t e : g->ev_rows)
+        if (e) (void)hipEventDestroy(e);
     void *dp[] = {g->d_out_off, g->d_in_off, g->d_vinfo, g->d_out_adj, g->d_in_adj, g->d_bits,
                   g->d_lists,   g->d_prefix, g->d_big,   g->d_desc,    g->d_cnt,    g->d_slots};
     for (void *p : dp)
@@ -392,6 +397,56 @@ struct ECTab {
     int32_t *big = nullptr;
     int64_t n = 0;
 };
+
+struct HostCopy {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+
+// Host copies of a batch's result tables out of the pinned staging buffer;
+// large totals are split over threads (first touch of the fresh result
+// buffers is part of the cost).
+void parallel_copy(const std::vector<HostCopy> &cs) {
+    size_t total = 0;
+    for (const HostCopy &c : cs) total += c.bytes;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nt = (int)std::min<size_t>({(size_t)8, (size_t)hw, total >> 23});  // 8 MB each
+    if (nt <= 1) {
+        for (const HostCopy &c : cs) std::memcpy(c.dst, c.src, c.bytes);
+        return;
+    }
+    // cut the concatenated bytes into nt equal ranges
+    const size_t per = (total + nt - 1) / nt;
+    auto work = [&](size_t lo, size_t hi) {
+        size_t pos = 0;
+        for (const HostCopy &c : cs) {
+            const size_t a = std::max(lo, pos), b = std::min(hi, pos + c.bytes);
+            if (a < b) std::memcpy((char *)c.dst + (a - pos), (const char *)c.src + (a - pos), b - a);
+            pos += c.bytes;
+            if (pos >= hi) break;
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work, per * t, std::min(total, per * (t + 1)));
+    work(0, std::min(total, per));
+    for (auto &x : th) x.join();
+}
+
+constexpr size_t kStageBytes = (size_t)256 << 20;  // multi-kernel readback chunk
+
+// Host buffer of a result table. Large tables get 2 MB-aligned memory with
+// transparent huge pages requested, which cuts page faults on first touch;
+// freed with free() either way.
+int32_t *alloc_rows(size_t bytes) {
+    if (bytes >= ((size_t)64 << 20)) {
+        void *p = nullptr;
+        if (posix_memalign(&p, (size_t)2 << 20, bytes) != 0) return nullptr;
+        (void)madvise(p, bytes, MADV_HUGEPAGE);
+        return (int32_t *)p;
+    }
+    return (int32_t *)std::malloc(std::max<size_t>(bytes, 4));
+}
 
 struct Query {
     sgm_graph *g;
@@ -833,7 +888,44 @@ struct Query {
                     Prof p(g, SGM_K_SORT, 4.0 * R);
                     launch_iota(st(), ia, R);
                 }
-                for (int u = n - 1; u >= 0; --u) {
+                // candidate ranks packed into one key of at most 64 bits:
+                // ceil(bits / 8) passes instead of a pass set per column
+                KeyCols kc{};
+                kc.n = n;
+                int tb = 0;
+                for (int u = 0; u < n; ++u) {
+                    int b = 0;
+                    while ((1ll << b) < ccount[u]) ++b;
+                    kc.bits[u] = bits(u);
+                    kc.prefix[u] = prefix(u);
+                    kc.col[u] = colpos[u];
+                    kc.nbits[u] = b;
+                    tb += b;
+                }
+                if (tb <= 64) {
+                    uint64_t *keys = sc.get<uint64_t>(R);
+                    {
+                        Prof p(g, SGM_K_SORT, 4.0 * R * n + 8.0 * R);
+                        launch_row_keys(st(), table, n, kc, R, keys);
+                    }
+                    for (int half = 0; half < 2; ++half) {
+                        const int hb = half == 0 ? std::min(tb, 32) : tb - 32;
+                        if (hb <= 0) break;
+                        {
+                            Prof p(g, SGM_K_SORT, 16.0 * R);
+                            launch_key_half(st(), keys, ia, R, half, ka);
+                        }
+                        for (int sh = 0; sh < hb; sh += 8) {
+                            Prof p(g, SGM_K_SORT, 20.0 * R);
+                            launch_radix_hist(st(), ka, R, sh, hist);
+                            launch_scan_i64(st(), hist, 256 * tiles, hoff, tmp);
+                            launch_radix_scatter(st(), ka, ia, R, sh, hoff, kb, ib);
+                            std::swap(ka, kb);
+                            std::swap(ia, ib);
+                        }
+                    }
+                }
+                for (int u = n - 1; u >= 0 && tb > 64; --u) {
                     {
                         Prof p(g, SGM_K_SORT, 12.0 * R);
                         launch_gather_key(st(), table, n, colpos[u], ia, R, ka);
@@ -856,19 +948,36 @@ struct Query {
             launch_gather_rows(st(), table, n, idx, R, colpos, out);
         }
         const size_t bytes = sizeof(int32_t) * (size_t)R * n;
-        if (g->h_rows_cap < bytes) {
+        // readback through two pinned staging halves of kStageBytes: the
+        // host copy of one chunk overlaps the transfer of the next
+        const size_t half = std::min(bytes, kStageBytes);
+        if (g->h_rows_cap < 2 * half) {
             if (g->h_rows) (void)hipHostFree(g->h_rows);
             g->h_rows = nullptr;
             g->h_rows_cap = 0;
-            size_t cap = std::max<size_t>(bytes, 1 << 20);
+            const size_t cap = std::max<size_t>(2 * half, 1 << 20);
             HIPX(hipHostMalloc(&g->h_rows, cap, hipHostMallocDefault));
             g->h_rows_cap = cap;
         }
-        HIPX(hipMemcpyAsync(g->h_rows, out, bytes, hipMemcpyDeviceToHost, st()));
-        sync(g);
-        res->rows = (int32_t *)std::malloc(std::max<size_t>(bytes, 1));
+        for (hipEvent_t &e : g->ev_rows)
+            if (!e) HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        res->rows = alloc_rows(bytes);
         if (!res->rows) throw DeviceError{SGM_ENOMEM};
-        std::memcpy(res->rows, g->h_rows, bytes);
+        char *stage[2] = {(char *)g->h_rows, (char *)g->h_rows + half};
+        const size_t nch = (bytes + half - 1) / half;
+        auto issue = [&](size_t i) {
+            const size_t off = i * half, len = std::min(half, bytes - off);
+            HIPX(hipMemcpyAsync(stage[i & 1], (const char *)out + off, len, hipMemcpyDeviceToHost,
+                                st()));
+            HIPX(hipEventRecord(g->ev_rows[i & 1], st()));
+        };
+        issue(0);
+        for (size_t i = 0; i < nch; ++i) {
+            if (i + 1 < nch) issue(i + 1);  // its half was copied out last round
+            HIPX(hipEventSynchronize(g->ev_rows[i & 1]));
+            const size_t off = i * half, len = std::min(half, bytes - off);
+            parallel_copy({HostCopy{(char *)res->rows + off, stage[i & 1], len}});
+        }
     }
 
     int run() {
@@ -1323,41 +1432,6 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     return true;
 }
 
-struct HostCopy {
-    void *dst;
-    const void *src;
-    size_t bytes;
-};
-
-// Host copies of a batch's result tables out of the pinned staging buffer;
-// large totals are split over threads (first touch of the fresh result
-// buffers is part of the cost).
-void parallel_copy(const std::vector<HostCopy> &cs) {
-    size_t total = 0;
-    for (const HostCopy &c : cs) total += c.bytes;
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const int nt = (int)std::min<size_t>({(size_t)8, (size_t)hw, total >> 23});  // 8 MB each
-    if (nt <= 1) {
-        for (const HostCopy &c : cs) std::memcpy(c.dst, c.src, c.bytes);
-        return;
-    }
-    // cut the concatenated bytes into nt equal ranges
-    const size_t per = (total + nt - 1) / nt;
-    auto work = [&](size_t lo, size_t hi) {
-        size_t pos = 0;
-        for (const HostCopy &c : cs) {
-            const size_t a = std::max(lo, pos), b = std::min(hi, pos + c.bytes);
-            if (a < b) std::memcpy((char *)c.dst + (a - pos), (const char *)c.src + (a - pos), b - a);
-            pos += c.bytes;
-            if (pos >= hi) break;
-        }
-    };
-    std::vector<std::thread> th;
-    for (int t = 1; t < nt; ++t) th.emplace_back(work, per * t, std::min(total, per * (t + 1)));
-    work(0, std::min(total, per));
-    for (auto &x : th) x.join();
-}
-
 // Wait for a launched job and fill the results of its finished queries;
 // queries that outgrew their slot are appended to `wide`.
 void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vector<QInfo> &qis,
@@ -1402,6 +1476,7 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         if (r.status != SGM_OK) {
             wide.push_back(qi_idx);
             res[qi_idx]->stats.fallback = r.status == kOutFull ? 8 : r.reason;
+            res[qi_idx]->stats.peak_bytes = r.need;  // slot memory a join level could need
             continue;
         }
         sgm_result *out = res[qi_idx];
@@ -1434,7 +1509,7 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         out->status = SGM_OK;
         if (!(flags & SGM_COUNT_ONLY)) {
             const size_t bytes = sizeof(int32_t) * (size_t)r.n_rows * qi.n;
-            out->rows = (int32_t *)std::malloc(std::max<size_t>(bytes, 4));
+            out->rows = alloc_rows(bytes);
             if (!out->rows) throw std::bad_alloc();
             if (bytes) copies.push_back({out->rows, nw.h_out + r.offset, bytes});
         }
@@ -1462,7 +1537,10 @@ void narrow_retry_large(sgm_graph *g, const std::vector<QInfo> &qis, uint32_t fl
     std::vector<int> again, keep;
     for (int i : wide) {
         const int32_t why = res[i]->stats.fallback;
-        (why == kWhyList || why == kWhySlab || why == 8 ? again : keep).push_back(i);
+        // a join level that stopped early for want of memory reports what
+        // its pairs could take; far beyond a large slot it goes wide at once
+        const bool fits = why != kWhySlab || res[i]->stats.peak_bytes <= kPairSlack * kBigSlab;
+        ((why == kWhyList || why == kWhySlab || why == 8) && fits ? again : keep).push_back(i);
     }
     if (again.empty()) return;
     wide = keep;

@@ -155,4 +155,21 @@ void launch_radix_scatter(hipStream_t s, const int32_t *key_in, const int32_t *i
 void launch_gather_rows(hipStream_t s, const int32_t *table, int32_t k, const int32_t *idx,
                         int64_t n, const int32_t *colpos, int32_t *out);
 
+// Ordering key of a row: the ranks of its values among the candidates of
+// their query vertices, concatenated in query-vertex order (nbits[u] bits
+// each, 64 in total at most). A rank comes from the vertex's candidate
+// bitmap and its per-word prefix counts.
+struct KeyCols {
+    const uint64_t *bits[SGM_MAX_QV];
+    const int32_t *prefix[SGM_MAX_QV];
+    int32_t col[SGM_MAX_QV];    // table column of query vertex u
+    int32_t nbits[SGM_MAX_QV];
+    int32_t n;
+};
+void launch_row_keys(hipStream_t s, const int32_t *table, int32_t k, const KeyCols &kc, int64_t n,
+                     uint64_t *keys);
+// key[i] = 32-bit half (hi = 0: low, 1: high) of keys[idx[i]]
+void launch_key_half(hipStream_t s, const uint64_t *keys, const int32_t *idx, int64_t n, int hi,
+                     int32_t *key);
+
 }  // namespace sgm

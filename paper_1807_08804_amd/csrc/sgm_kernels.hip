@@ -587,6 +587,31 @@ __global__ __launch_bounds__(kBlock) void k_gather_key(const int32_t *table, int
         key[i] = table[(int64_t)idx[i] * k + col];
 }
 
+__global__ __launch_bounds__(kBlock) void k_row_keys(const int32_t *table, int32_t k, KeyCols kc,
+                                                     int64_t n, uint64_t *keys) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t *row = table + i * k;
+        uint64_t key = 0;
+        for (int u = 0; u < kc.n; ++u) {
+            const int b = kc.nbits[u];
+            if (b == 0) continue;
+            const int32_t x = row[kc.col[u]];
+            const uint64_t w = kc.bits[u][x >> 6];
+            const int32_t rk = kc.prefix[u][x >> 6] + __popcll(w & ((1ull << (x & 63)) - 1ull));
+            key = (key << b) | (uint64_t)rk;
+        }
+        keys[i] = key;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_key_half(const uint64_t *keys, const int32_t *idx,
+                                                     int64_t n, int hi, int32_t *key) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        key[i] = (int32_t)(uint32_t)(keys[idx[i]] >> (hi ? 32 : 0));
+}
+
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const int32_t *key, int64_t n, int shift,
                                                        int64_t *hist /* [256][nblocks] */) {
     __shared__ int32_t h[256];
@@ -764,6 +789,18 @@ void launch_gather_key(hipStream_t s, const int32_t *table, int32_t k, int32_t c
                        const int32_t *idx, int64_t n, int32_t *key) {
     hipLaunchKernelGGL(k_gather_key, dim3(grid_for(n, kBlock, kGridCap)), dim3(kBlock), 0, s,
                        table, k, col, idx, n, key);
+}
+
+void launch_row_keys(hipStream_t s, const int32_t *table, int32_t k, const KeyCols &kc, int64_t n,
+                     uint64_t *keys) {
+    hipLaunchKernelGGL(k_row_keys, dim3(grid_for(n, kBlock, kGridCap)), dim3(kBlock), 0, s, table,
+                       k, kc, n, keys);
+}
+
+void launch_key_half(hipStream_t s, const uint64_t *keys, const int32_t *idx, int64_t n, int hi,
+                     int32_t *key) {
+    hipLaunchKernelGGL(k_key_half, dim3(grid_for(n, kBlock, kGridCap)), dim3(kBlock), 0, s, keys,
+                       idx, n, hi, key);
 }
 
 void launch_radix_hist(hipStream_t s, const int32_t *key, int64_t n, int shift, int64_t *hist) {

@@ -57,6 +57,7 @@ struct NResult {
     int32_t join_order[SGM_MAX_QV];
     int64_t bytes;         // algorithmic bytes the query's phases moved
     int64_t ticks[4];      // device wall-clock ticks: filter, edges, join, ordering
+    int64_t need;          // kWhySlab at a join level: slab bytes its pairs could take
 };
 
 constexpr int32_t kNeedWide = 1;  // a capacity of the per-query slot was exceeded
@@ -65,6 +66,9 @@ constexpr int32_t kOutFull = 2;   // the shared output arena was full
 constexpr int32_t kWhyList = 1;   // a candidate list outgrew its slot capacity
 constexpr int32_t kWhySlab = 2;   // edge tables / join tables / sort buffers outgrew the slab
 constexpr int32_t kWhyKey = 4;    // the ordering key would need more than 64 bits
+// A join level whose pairs (an upper bound on its rows) would need more than
+// this many times the slab left stops at once instead of filling the slab.
+constexpr int64_t kPairSlack = 8;
 
 struct NArgs {
     DevGraph g;

@@ -72,6 +72,7 @@ struct Smem {
     int64_t level_rows[SGM_MAX_QV];
     int64_t nrows;
     int64_t offset;
+    int64_t need;
     unsigned long long bytes;  // algorithmic bytes moved (see add_bytes)
     int64_t t[5];              // wall clock at the phase boundaries
 };
@@ -1149,6 +1150,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         s.reason = 0;
         s.nrows = 0;
         s.offset = 0;
+        s.need = 0;
         s.bytes = 0;
     }
     __syncthreads();
@@ -1266,6 +1268,27 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                     }
                     if (threadIdx.x == 0) s.ctr = 0;
                     __syncthreads();
+                    // the level's pairs bound its rows: a level that could not
+                    // fit even a much larger slot stops here rather than
+                    // after filling this one
+                    {
+                        int64_t mp = 0;
+                        for (int64_t r = threadIdx.x; r < rows; r += NT) {
+                            const int32_t pv = table[r * k + cp];
+                            const int32_t i = lower_bound_i32(pk, 0, npk, pv);
+                            if (i < npk && pk[i] == pv) mp += ecnt[i];
+                        }
+                        int64_t pairs;
+                        block_excl_scan(mp, s.sh, &pairs);
+                        if (pairs > kPairSlack * cap) {
+                            if (threadIdx.x == 0) {
+                                s.abort_ = kWhySlab;
+                                s.need = (s.slab_used - cap * 4 * (k + 1)) + pairs * 4 * (k + 1);
+                            }
+                            __syncthreads();
+                            break;
+                        }
+                    }
                     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
                     uint64_t jb = 0;  // algorithmic bytes of this thread's rows and pairs
                     for (int64_t rbase = 0; rbase < rows; rbase += NT) {
@@ -1544,6 +1567,7 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
             }
             for (int e = 0; e < SGM_MAX_QE; ++e) R.ec[e] = e < Q.m ? s.ectot[e] : 0;
             R.bytes = (int64_t)s.bytes;
+            R.need = s.need;
             // phases a query skipped carry the time of the previous mark
             int64_t prev = s.t[0];
             for (int i = 1; i < 5; ++i) {
