@@ -232,6 +232,44 @@ const char *sgm_last_error(void);
 #define SGM_EV_OUTPUT 10   /* rows copied to the output arena */
 int sgm_trace_events(sgm_graph *g, int32_t i, int64_t *out, int32_t cap, double *ns_per_tick);
 
+/*
+ * Work division and join schedule of the persistent kernel (the batched
+ * form). Results never depend on these; speed does. Defaults: slots 512,
+ * group_lanes 64, wg_rows 8192, join_policy 0.
+ *   slots        workgroups of one persistent launch (1..512; two per CU fit)
+ *   group_lanes  most lanes working on one candidate's rows (1, 2, 4, ..., 64)
+ *   wg_rows      rows longer than this are scanned by the whole workgroup
+ *                (>= 64; shorter long rows get one wave)
+ *   join_policy  0: bind the vertex of the cheapest candidate-edge table
+ *                next (thesis Sec. "Joining Phase"); 1: bind the vertex with
+ *                the most edges to bound vertices first, cheapest on ties
+ * The multi-kernel path keeps the thesis order.
+ */
+typedef struct {
+    int32_t slots;
+    int32_t group_lanes;
+    int32_t wg_rows;
+    int32_t join_policy;
+    int32_t reserved[4];
+} sgm_tuning;
+
+void sgm_default_tuning(sgm_tuning *t);
+/* Current tuning of a graph. */
+int sgm_get_tuning(const sgm_graph *g, sgm_tuning *t);
+/* Set a graph's tuning (SGM_EINVAL for values out of range). Not while a
+ * server of the graph runs or another match call is in flight. */
+int sgm_set_tuning(sgm_graph *g, const sgm_tuning *t);
+/*
+ * Autotuner: runs the n sample queries as persistent-kernel batches (count
+ * only, reps times each) under every tuning of a small grid (slots 256/512,
+ * group_lanes 16/64, wg_rows 2048/8192/32768, join_policy 0/1), keeps the
+ * one with the lowest median batch time, sets it on the graph and returns it
+ * in *best (may be NULL). Every tuning must give the same per-query row
+ * counts; otherwise the previous tuning is restored and SGM_EDEVICE
+ * returned. Same threading rule as sgm_set_tuning.
+ */
+int sgm_autotune(sgm_graph *g, const sgm_query *qs, int32_t n, int32_t reps, sgm_tuning *best);
+
 /* Graph properties after load (deduplicated edge count etc.). */
 int sgm_graph_info(const sgm_graph *g, int32_t *n_vertices, int64_t *n_edges,
                    int32_t *max_out_degree, int32_t *max_in_degree);

@@ -79,6 +79,12 @@ class sgm_serve_stats(ctypes.Structure):
                 ("max_in_flight", ctypes.c_int64), ("wide_fallbacks", ctypes.c_int64)]
 
 
+class sgm_tuning(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("group_lanes", ctypes.c_int32),
+                ("wg_rows", ctypes.c_int32), ("join_policy", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
 class sgm_kstat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("bytes_total", ctypes.c_double)]
@@ -100,6 +106,11 @@ EXPORTS = {
     "sgm_trace_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i64p, ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_double)]),
     "sgm_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(sgm_kstat)]),
+    "sgm_default_tuning": (None, [ctypes.POINTER(sgm_tuning)]),
+    "sgm_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_tuning)]),
+    "sgm_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_tuning)]),
+    "sgm_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query), ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.POINTER(sgm_tuning)]),
     "sgm_reset_kernel_stats": (ctypes.c_int, [ctypes.c_void_p]),
     "sgm_plan_query": (ctypes.c_int, [ctypes.POINTER(sgm_query), ctypes.c_int32, _i64p,
                                       ctypes.c_int32, _i32p, _i32p, _i32p, _i32p]),
@@ -385,6 +396,34 @@ class Graph:
         t = (ev >> 8) - (ev[0] >> 8)
         return [(EVENT_NAMES.get(int(c), str(int(c))), float(x) * tick.value / 1e3)
                 for c, x in zip(ev & 255, t)]
+
+    def tuning(self) -> dict:
+        """The persistent kernel's tuning (sgm_get_tuning)."""
+        t = sgm_tuning()
+        rc = lib().sgm_get_tuning(self._h, ctypes.byref(t))
+        if rc != SGM_OK:
+            raise SGMError(rc, "sgm_get_tuning")
+        return {k: getattr(t, k) for k in ("slots", "group_lanes", "wg_rows", "join_policy")}
+
+    def set_tuning(self, **kw):
+        """Change tuning fields (sgm_set_tuning); results do not depend on them."""
+        t = sgm_tuning()
+        lib().sgm_get_tuning(self._h, ctypes.byref(t))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        rc = lib().sgm_set_tuning(self._h, ctypes.byref(t))
+        if rc != SGM_OK:
+            raise SGMError(rc, "sgm_set_tuning")
+
+    def autotune(self, queries, reps: int = 3) -> dict:
+        """Pick the fastest tuning for a sample batch (sgm_autotune)."""
+        built = [_make_query(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel) for q in queries]
+        arr = (sgm_query * len(built))(*[b[0] for b in built])
+        t = sgm_tuning()
+        rc = lib().sgm_autotune(self._h, arr, len(built), int(reps), ctypes.byref(t))
+        if rc != SGM_OK:
+            raise SGMError(rc, "sgm_autotune")
+        return {k: getattr(t, k) for k in ("slots", "group_lanes", "wg_rows", "join_policy")}
 
     def kernel_stats(self):
         out = {}

@@ -241,6 +241,7 @@ struct sgm_graph {
     // persistent per-query kernel on the graph's own stream
     NarrowCtx nw;
     NarrowCtx nwb;  // few large slots for queries that outgrow a regular one
+    sgm_tuning tune{512, 64, 8192, 0, {0, 0, 0, 0}};
 };
 
 namespace {
@@ -1361,8 +1362,11 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     a.out = nw.d_out;
     a.out_cap = nw.out_cap;
     a.out_used = nw.d_ctr + 1;
+    a.group_lanes = g->tune.group_lanes;
+    a.wg_rows = g->tune.wg_rows;
+    a.join_policy = g->tune.join_policy;
     nw.sa = SweepArgs{g->dg, nw.d_preds, nroot, n_any, nw.d_rootbits, nw.d_ctr};
-    const int grid = std::min(np, nw.slots);
+    const int grid = std::min(np, nw.slab_want ? nw.slots : std::min(nw.slots, g->tune.slots));
     job.traced = profiled && g->opts.profile >= 2;
     if (g->opts.graphs && !(profiled && g->opts.profile)) {
         nw.na = a;
@@ -1747,6 +1751,96 @@ void sgm_free_graph(sgm_graph *g) {
     if (!g) return;
     free_graph_mem(g);
     delete g;
+}
+
+void sgm_default_tuning(sgm_tuning *t) {
+    if (!t) return;
+    *t = sgm_tuning{512, 64, 8192, 0, {0, 0, 0, 0}};
+}
+
+int sgm_get_tuning(const sgm_graph *g, sgm_tuning *t) {
+    if (!g || !t) return SGM_EINVAL;
+    *t = g->tune;
+    return SGM_OK;
+}
+
+static bool tuning_ok(const sgm_tuning &t) {
+    const bool pow2 = t.group_lanes > 0 && (t.group_lanes & (t.group_lanes - 1)) == 0;
+    return t.slots >= 1 && t.slots <= 512 && pow2 && t.group_lanes <= 64 && t.wg_rows >= 64 &&
+           (t.join_policy == 0 || t.join_policy == 1);
+}
+
+int sgm_set_tuning(sgm_graph *g, const sgm_tuning *t) {
+    if (!g || !t || !tuning_ok(*t)) return SGM_EINVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->tune = *t;
+    g->tune.reserved[0] = g->tune.reserved[1] = g->tune.reserved[2] = g->tune.reserved[3] = 0;
+    return SGM_OK;
+}
+
+int sgm_autotune(sgm_graph *g, const sgm_query *qs, int32_t n, int32_t reps, sgm_tuning *best) {
+    if (!g || n <= 0 || !qs || reps < 1) return SGM_EINVAL;
+    reps = std::min(reps, 16);
+    std::lock_guard<std::mutex> lk(g->mu);
+    std::vector<QInfo> qis((size_t)n);
+    std::vector<int> valid;
+    for (int i = 0; i < n; ++i)
+        if (check_query(&qs[i], g->V, &qis[i]) == SGM_OK) valid.push_back(i);
+    if (valid.empty()) return SGM_EINVAL;
+    const sgm_tuning saved = g->tune;
+    std::vector<sgm_tuning> grid;
+    for (int sl : {256, 512})
+        for (int gl : {16, 64})
+            for (int wr : {2048, 8192, 32768})
+                for (int jp : {0, 1}) grid.push_back(sgm_tuning{sl, gl, wr, jp, {0, 0, 0, 0}});
+    std::vector<sgm_result> store((size_t)n);
+    std::vector<sgm_result *> res((size_t)n);
+    for (int i = 0; i < n; ++i) res[i] = &store[i];
+    std::vector<int64_t> rows_ref;
+    double best_t = 1e300;
+    sgm_tuning pick = saved;
+    try {
+        for (const sgm_tuning &t : grid) {
+            g->tune = t;
+            std::vector<double> ts;
+            for (int r = 0; r <= reps; ++r) {  // the first run warms up
+                for (sgm_result &x : store) x = sgm_result{};
+                std::vector<int> wide;
+                const int64_t t0 = now_ns();
+                narrow_batch(g, qis, valid, SGM_COUNT_ONLY, res, wide);
+                const double el = (double)(now_ns() - t0);
+                if (r > 0) ts.push_back(el);
+                std::vector<int64_t> rows((size_t)n, -1);
+                for (int i : valid)
+                    if (std::find(wide.begin(), wide.end(), i) == wide.end()) rows[i] = store[i].n_rows;
+                if (rows_ref.empty()) rows_ref = rows;
+                for (int i : valid)
+                    if (rows[i] >= 0 && rows_ref[i] >= 0 && rows[i] != rows_ref[i]) {
+                        g->tune = saved;
+                        g_last_error = "autotune: a tuning changed a result";
+                        return SGM_EDEVICE;
+                    }
+            }
+            std::sort(ts.begin(), ts.end());
+            const double med = ts[ts.size() / 2];
+            if (med < best_t) {
+                best_t = med;
+                pick = t;
+            }
+        }
+    } catch (const DeviceError &e) {
+        (void)hipStreamSynchronize(g->stream);
+        (void)hipGetLastError();
+        g->pending.clear();
+        g->tune = saved;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g->tune = saved;
+        return SGM_ENOMEM;
+    }
+    g->tune = pick;
+    if (best) *best = pick;
+    return SGM_OK;
 }
 
 int sgm_trace_events(sgm_graph *g, int32_t i, int64_t *out, int32_t cap, double *ns_per_tick) {

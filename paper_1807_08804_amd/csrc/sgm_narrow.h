@@ -86,6 +86,11 @@ struct NArgs {
     int64_t out_cap;          // in int32 elements
     unsigned long long *out_used;
     int64_t *trace;           // [nq][SGM_TRACE_CAP] step events, or null
+    // work-division and schedule knobs (sgm_tuning); results do not depend
+    // on them
+    int32_t group_lanes;      // most lanes per candidate group (power of two, 1..64)
+    int32_t wg_rows;          // rows longer than this get the whole workgroup
+    int32_t join_policy;      // 0: cheapest edge first; 1: most-constrained vertex first
 };
 
 // Root sweep: rootbits[j][w] = vertices satisfying predicate j, for the

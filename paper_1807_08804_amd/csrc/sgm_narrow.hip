@@ -29,7 +29,6 @@ namespace {
 constexpr int NT = kNarrowThreads;
 constexpr int NW = NT / 64;
 constexpr int kBigCap = 256;         // LDS list of items for the whole workgroup
-constexpr int32_t kWgDeg = 8192;      // rows longer than this get the whole workgroup
 constexpr int32_t kRevMin = 256;      // candidates of u before a reverse check can pay
 constexpr int32_t kRevMaxCand = 4096; // neighbours with at most this many candidates
 constexpr int kListSortCap = 8192;    // int32 entries sorted in LDS
@@ -106,6 +105,9 @@ struct Ctx {
     char *slab;
     unsigned char *dyn;
     int64_t *trace;     // this query's step events, or null
+    int32_t gmax;       // most lanes per candidate group
+    int32_t wg_rows;    // rows longer than this get the whole workgroup
+    int32_t join_policy;
     __device__ uint64_t *B(int u) const { return bits + (int64_t)u * g.nwords; }
     __device__ int32_t *L(int u) const { return lists + (int64_t)u * lcap; }
 };
@@ -423,8 +425,8 @@ __device__ __forceinline__ int32_t max_row(const DevGraph &g, const NNbr *nb, in
 
 // lanes per candidate for n items: the whole workgroup for a handful,
 // otherwise a power of two in [1, 64] so that all lanes hold an item
-__device__ __forceinline__ int lanes_for(int32_t n) {
-    int G = 64;
+__device__ __forceinline__ int lanes_for(int32_t n, int gmax) {
+    int G = gmax;
     while (G > 1 && (int64_t)G * n > NT) G >>= 1;
     return G;
 }
@@ -555,7 +557,7 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
     } else if (n_items <= NW) {
         for (int32_t it = 0; it < n_items; ++it) item_wg(c, st, nb, ncount, ul[it], ub, fb);
     } else {
-        const int G = lanes_for(n_items);
+        const int G = lanes_for(n_items, c.gmax);
         const int NGr = NT / G;
         const int lane = threadIdx.x & 63, gl = lane & (G - 1), gb = lane & ~(G - 1);
         const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << gb;
@@ -632,11 +634,11 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
             if (gl == 0) fb += 20ull + 12ull * seen;
         }
         __syncthreads();
-        // one wave per long row; rows above kWgDeg get the whole workgroup
+        // one wave per long row; rows above wg_rows get the whole workgroup
         const int32_t nbig = c.s->nbig;
         for (int32_t b = threadIdx.x >> 6; b < nbig; b += NW) {
             const int32_t up = ov[b];
-            if (max_row(g, nb, ncount, up) > kWgDeg) {
+            if (max_row(g, nb, ncount, up) > c.wg_rows) {
                 int32_t p = 0;
                 if (lane == 0) p = atomicAdd(&c.s->ngiant, 1);
                 p = __shfl(p, 0, 64);
@@ -856,7 +858,7 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
             }
         }
     } else {
-        const int G = lanes_for(nk);
+        const int G = lanes_for(nk, c.gmax);
         const int NGr = NT / G;
         const int lane = threadIdx.x & 63, gl = lane & (G - 1), gb = lane & ~(G - 1);
         const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << gb;
@@ -889,7 +891,7 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
             const int32_t it = ovl[b];
             const int32_t k = keys[it];
             const int32_t beg = off[k], end = off[k + 1];
-            if (end - beg > kWgDeg) {
+            if (end - beg > c.wg_rows) {
                 int32_t p = 0;
                 if (lane == 0) p = atomicAdd(&c.s->ngiant, 1);
                 p = __shfl(p, 0, 64);
@@ -952,12 +954,29 @@ __device__ __forceinline__ void join_order(Ctx &c) {
     int ext = e0;
     for (int lv = 0; lv < Q.n - 1; ++lv) {
         if (lv > 0) {
+            // policy 0: the cheapest edge with one bound endpoint. Policy 1:
+            // first the new vertex with the most edges to bound vertices
+            // (its level then checks the most), then the cheapest edge.
             ext = -1;
+            int ext_links = 0;
             for (int e = 0; e < Q.m; ++e) {
                 if ((used >> e) & 1ull) continue;
                 const bool va = (vis >> Q.esrc[e]) & 1u, vb = (vis >> Q.edst[e]) & 1u;
                 if (va == vb) continue;
-                if (ext < 0 || s.ectot[e] < s.ectot[ext]) ext = e;
+                int links = 0;
+                if (c.join_policy == 1) {
+                    const int w = va ? Q.edst[e] : Q.esrc[e];
+                    for (int f = 0; f < Q.m; ++f) {
+                        if ((used >> f) & 1ull) continue;
+                        const int x = Q.esrc[f], y = Q.edst[f];
+                        links += (x == w && ((vis >> y) & 1u)) || (y == w && ((vis >> x) & 1u));
+                    }
+                }
+                if (ext < 0 || links > ext_links ||
+                    (links == ext_links && s.ectot[e] < s.ectot[ext])) {
+                    ext = e;
+                    ext_links = links;
+                }
             }
         }
         const int w = ((vis >> Q.esrc[ext]) & 1u) ? Q.edst[ext] : Q.esrc[ext];
@@ -1550,7 +1569,8 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
         NResult &R = a.res[q];
         Ctx c{a.g,  a.lcap, a.slab_bytes, a.out, a.out_cap, a.out_used, a.rootbits, &Q, &s,
               bits, bits + (int64_t)SGM_MAX_QV * nwords, lists, slab, dyn,
-              a.trace ? a.trace + (int64_t)q * SGM_TRACE_CAP : nullptr};
+              a.trace ? a.trace + (int64_t)q * SGM_TRACE_CAP : nullptr, a.group_lanes,
+              a.wg_rows, a.join_policy};
         if (threadIdx.x == 0) s.nev = 0;
         run_query(c);
         __syncthreads();

@@ -1,0 +1,75 @@
+"""Work division and join schedule of the persistent kernel (sgm_tuning) and
+the autotuner: results are identical under every tuning, bit for bit, and
+equal to the oracle's."""
+import sys
+
+import numpy as np
+import pytest
+
+import kggen
+import paper_1807_08804_amd as P
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def same(a, b):
+    assert a.shape == b.shape, (a.shape, b.shape)
+    assert np.array_equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def medium_set(medium_kg, oracle_medium):
+    qs, _ = kggen.medium_queries(medium_kg, 100)
+    return qs[:40], [oracle_medium.match_query(q) for q in qs[:40]]
+
+
+TUNINGS = [
+    dict(slots=512, group_lanes=64, wg_rows=8192, join_policy=0),
+    dict(slots=7, group_lanes=1, wg_rows=64, join_policy=1),
+    dict(slots=256, group_lanes=16, wg_rows=32768, join_policy=1),
+    dict(slots=1, group_lanes=4, wg_rows=2048, join_policy=0),
+]
+
+
+@pytest.mark.parametrize("tune", TUNINGS)
+def test_results_do_not_depend_on_tuning(tune, medium_kg, medium_set):
+    qs, want = medium_set
+    say(f"case: tuning {tune}")
+    g = P.Graph.from_kg(medium_kg, path=P.SGM_PATH_NARROW)
+    g.set_tuning(**tune)
+    assert g.tuning() == tune
+    for r, w in zip(g.match_batch(qs), want):
+        same(r, w)
+    for q, w in zip(qs[:10], want[:10]):
+        same(g.match_query(q), w)
+    g.close()
+
+
+def test_tuning_validation(medium_kg):
+    g = P.Graph.from_kg(medium_kg)
+    for bad in (dict(slots=0), dict(slots=513), dict(group_lanes=3), dict(group_lanes=128),
+                dict(wg_rows=32), dict(join_policy=2)):
+        with pytest.raises(P.SGMError) as e:
+            g.set_tuning(**bad)
+        assert e.value.code == P.SGM_EINVAL
+    assert g.tuning() == TUNINGS[0]
+    g.close()
+
+
+def test_autotune_keeps_results(medium_kg, medium_set):
+    qs, want = medium_set
+    say("case: autotune")
+    g = P.Graph.from_kg(medium_kg)
+    best = g.autotune(qs, reps=1)
+    assert best["slots"] in (256, 512) and best["group_lanes"] in (16, 64)
+    assert best["wg_rows"] in (2048, 8192, 32768) and best["join_policy"] in (0, 1)
+    assert g.tuning() == best
+    for r, w in zip(g.match_batch(qs), want):
+        same(r, w)
+    say(f"  picked {best}")
+    g.close()
