@@ -186,7 +186,7 @@ struct NarrowCtx {
     hipGraphNode_t gn[6] = {};
     SweepArgs sa{};
     NArgs na{};
-    void *kargs[7] = {};
+    void *kargs[9] = {};
 };
 
 }  // namespace
@@ -1100,6 +1100,7 @@ struct Query {
 // ---------------------------------------------------------------------------
 
 constexpr int kNarrowMaxSlots = 512;                 // 2 workgroups per CU
+constexpr int32_t kTypeTable = 1024;                 // vertex types covered by the sweep's table
 constexpr int64_t kNarrowSlabMin = 8ll << 20;        // per slot, small graphs
 constexpr int64_t kNarrowSlabMax = 32ll << 20;       // per slot, large graphs
 constexpr int32_t kNarrowListCap = 1 << 16;          // per query vertex
@@ -1199,8 +1200,11 @@ void narrow_reserve(sgm_graph *g, NarrowCtx &nw, int slots, int nq, int nroot) {
         dev_free(nw.d_rootbits);
         host_free(nw.h_preds);
         nw.root_cap = 0;
-        HIPX(hipMalloc(&nw.d_preds, sizeof(VPred) * nroot));
-        HIPX(hipHostMalloc(&nw.h_preds, sizeof(VPred) * nroot, hipHostMallocDefault));
+        // root predicates, then the sweep's type-offset table (at most
+        // kTypeTable + 1 ints)
+        const size_t pb = sizeof(VPred) * nroot + sizeof(int32_t) * (kTypeTable + 1);
+        HIPX(hipMalloc(&nw.d_preds, pb));
+        HIPX(hipHostMalloc(&nw.h_preds, pb, hipHostMallocDefault));
         HIPX(hipMalloc(&nw.d_rootbits, sizeof(uint64_t) * (size_t)g->nwords * nroot));
         nw.root_cap = nroot;
     }
@@ -1346,6 +1350,13 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     narrow_reserve(g, nw, std::min(np, max_slots), np, std::max(nroot, 1));
     if (nroot) std::memcpy(nw.h_preds, preds.data(), sizeof(VPred) * nroot);
     else nw.h_preds[0] = VPred{-1, -1, 0, 0};
+    // type_off[t] = first predicate of type >= t (predicates are sorted)
+    const int32_t n_types = nroot && g->n_types <= kTypeTable ? g->n_types : 0;
+    int32_t *type_off = (int32_t *)(nw.h_preds + std::max(nroot, 1));
+    for (int32_t t = 0, j = 0; t <= n_types && n_types > 0; ++t) {
+        while (j < nroot && preds[j].label < t) ++j;
+        type_off[t] = j;
+    }
     hipStream_t st = nw.stream;
     NArgs a{};
     a.g = g->dg;
@@ -1365,14 +1376,16 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     a.group_lanes = g->tune.group_lanes;
     a.wg_rows = g->tune.wg_rows;
     a.join_policy = g->tune.join_policy;
-    nw.sa = SweepArgs{g->dg, nw.d_preds, nroot, n_any, nw.d_rootbits, nw.d_ctr};
+    nw.sa = SweepArgs{g->dg,       nw.d_preds, nroot, n_any, nw.d_rootbits, nw.d_ctr,
+                      (const int32_t *)(nw.d_preds + std::max(nroot, 1)), n_types};
     const int grid = std::min(np, nw.slab_want ? nw.slots : std::min(nw.slots, g->tune.slots));
     job.traced = profiled && g->opts.profile >= 2;
     if (g->opts.graphs && !(profiled && g->opts.profile)) {
         nw.na = a;
         hipKernelNodeParams ps, pn;
         narrow_node_params(&nw.sa, &nw.na, grid, nw.kargs, &ps, &pn);
-        const size_t qb = sizeof(NQuery) * np, pb = sizeof(VPred) * std::max(nroot, 1);
+        const size_t qb = sizeof(NQuery) * np,
+                     pb = sizeof(VPred) * std::max(nroot, 1) + sizeof(int32_t) * (n_types + 1);
         const size_t rb = sizeof(NResult) * np, cb = sizeof(unsigned long long) * 2;
         const auto H2D = hipMemcpyHostToDevice, D2H = hipMemcpyDeviceToHost;
         if (!nw.gexec) {
@@ -1402,8 +1415,9 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     }
     HIPX(hipMemcpyAsync(nw.d_q, nw.h_q, sizeof(NQuery) * np, hipMemcpyHostToDevice, st));
     if (nroot)
-        HIPX(hipMemcpyAsync(nw.d_preds, nw.h_preds, sizeof(VPred) * nroot, hipMemcpyHostToDevice,
-                            st));
+        HIPX(hipMemcpyAsync(nw.d_preds, nw.h_preds,
+                            sizeof(VPred) * nroot + sizeof(int32_t) * (n_types + 1),
+                            hipMemcpyHostToDevice, st));
     {
         Prof p(g, SGM_K_CHECK, nroot ? (8.0 + 0.125 * nroot) * g->V : 0.0, profiled && nroot > 0);
         launch_root_sweep(st, nw.sa);

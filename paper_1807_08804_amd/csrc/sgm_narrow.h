@@ -104,11 +104,15 @@ struct SweepArgs {
     int32_t n_any;        // predicates without a type
     uint64_t *rootbits;
     unsigned long long *ctr;
+    // type_off[t] = first predicate with type >= t, for t in [0, n_types];
+    // n_types = 0: no table (types found by binary search)
+    const int32_t *type_off;
+    int32_t n_types;
 };
 void launch_root_sweep(hipStream_t s, const SweepArgs &a);
 void launch_narrow(hipStream_t s, const NArgs &a, int grid);
 // Kernel-node parameters of the sweep and of the persistent kernel for a
-// HIP graph. The argument pointers refer to *sa, *na and args[0..6], which
+// HIP graph. The argument pointers refer to *sa, *na and args[0..8], which
 // must stay valid until the parameters have been handed to HIP.
 void narrow_node_params(SweepArgs *sa, NArgs *na, int narrow_grid, void **args,
                         hipKernelNodeParams *sweep, hipKernelNodeParams *narrow);

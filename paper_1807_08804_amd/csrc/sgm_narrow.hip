@@ -1617,14 +1617,21 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
 constexpr int kSweepTile = 64;    // bitmap words per block
 constexpr int kSweepChunk = 64;   // predicates per LDS pass (32 KB of rows)
 
+constexpr int kSweepTypes = 1024;  // type tables up to this size are staged in LDS
+
 __global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *preds, int32_t n_pred,
                                                     int32_t n_any, uint64_t *rootbits,
-                                                    unsigned long long *ctr) {
+                                                    unsigned long long *ctr,
+                                                    const int32_t *type_off, int32_t n_types) {
     if (blockIdx.x == 0 && threadIdx.x < 2) ctr[threadIdx.x] = 0ull;
     if (n_pred == 0) return;
     __shared__ uint64_t rows[kSweepChunk * kSweepTile];
     __shared__ VPred pl[kSweepChunk];
+    __shared__ int32_t toff[kSweepTypes + 1];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const bool table = n_types > 0 && n_types <= kSweepTypes;
+    if (table)
+        for (int t = threadIdx.x; t <= n_types; t += 256) toff[t] = type_off[t];
     const int32_t w0 = blockIdx.x * kSweepTile;
     // vertex of slot i: word w0 + 16 * wid + i, bit lane
     int2 vi[16];
@@ -1654,14 +1661,24 @@ __global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *pre
         for (int i = 0; i < 16; ++i) {
             const int32_t t = vi[i].x;
             if (t < 0 || t0 >= cn) continue;
-            int lo = t0, hi = cn;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (pl[mid].label < t) lo = mid + 1;
-                else hi = mid;
+            int lo, end;
+            if (table) {
+                // the predicates of type t, clipped to this chunk
+                if (t >= n_types) continue;
+                lo = max(t0, toff[t] - c0);
+                end = min(cn, toff[t + 1] - c0);
+            } else {
+                lo = t0;
+                int hi = cn;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (pl[mid].label < t) lo = mid + 1;
+                    else hi = mid;
+                }
+                end = cn;
             }
             const int od = vi[i].y & 255, id = vi[i].y >> 8;
-            for (int j = lo; j < cn && pl[j].label == t; ++j)
+            for (int j = lo; j < end && pl[j].label == t; ++j)
                 if (od >= pl[j].qout && id >= pl[j].qin)
                     atomicOr((unsigned long long *)&rows[j * kSweepTile + 16 * wid + i], 1ull << lane);
         }
@@ -1691,7 +1708,7 @@ int sweep_grid(const SweepArgs &a) {
 
 void launch_root_sweep(hipStream_t s, const SweepArgs &a) {
     hipLaunchKernelGGL(k_root_sweep, dim3(sweep_grid(a)), dim3(256), 0, s, a.g, a.preds, a.n_pred,
-                       a.n_any, a.rootbits, a.ctr);
+                       a.n_any, a.rootbits, a.ctr, a.type_off, a.n_types);
 }
 
 void narrow_node_params(SweepArgs *sa, NArgs *na, int narrow_grid, void **args,
@@ -1702,7 +1719,9 @@ void narrow_node_params(SweepArgs *sa, NArgs *na, int narrow_grid, void **args,
     args[3] = &sa->n_any;
     args[4] = &sa->rootbits;
     args[5] = &sa->ctr;
-    args[6] = na;
+    args[6] = &sa->type_off;
+    args[7] = &sa->n_types;
+    args[8] = na;
     *sweep = hipKernelNodeParams{};
     sweep->func = reinterpret_cast<void *>(&k_root_sweep);
     sweep->gridDim = dim3(sweep_grid(*sa));
@@ -1715,7 +1734,7 @@ void narrow_node_params(SweepArgs *sa, NArgs *na, int narrow_grid, void **args,
     narrow->gridDim = dim3(narrow_grid);
     narrow->blockDim = dim3(NT);
     narrow->sharedMemBytes = kDynLds;
-    narrow->kernelParams = args + 6;
+    narrow->kernelParams = args + 8;
     narrow->extra = nullptr;
 }
 
