@@ -1162,6 +1162,8 @@ void narrow_reserve(sgm_graph *g, NarrowCtx &nw, int slots, int nq, int nroot) {
     if (nw.lcap == 0) {
         nw.lcap = std::min<int32_t>(g->V, nw.lcap_want ? nw.lcap_want : kNarrowListCap);
         nw.slab_bytes = nw.slab_want ? nw.slab_want : narrow_slab_bytes(g);
+        // while filtering, a slot's slab holds two lists of up to lcap ints
+        if (nw.slab_bytes < 8ll * nw.lcap) throw DeviceError{SGM_EUNSUPPORTED};
         HIPX(hipMalloc(&nw.d_ctr, sizeof(unsigned long long) * 2));
         HIPX(hipHostMalloc(&nw.h_ctr, sizeof(unsigned long long) * 2, hipHostMallocDefault));
         nw.out_cap = kNarrowOutCap;

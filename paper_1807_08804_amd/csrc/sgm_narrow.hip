@@ -57,6 +57,9 @@ struct Smem {
     int32_t nbig;
     int32_t ngiant;
     int32_t nnbl;
+    int32_t nmarks;
+    unsigned long long rowhit;  // item_wg: listed rows with a matching entry
+    int8_t qsrc[SGM_MAX_QE], qdst[SGM_MAX_QE];  // the query's edges, staged for join_order
     uint64_t revmask;
     NNbr nbl[SGM_MAX_QE];  // neighbours a step still tests per candidate
     int32_t removed;
@@ -108,6 +111,7 @@ struct Ctx {
     int32_t gmax;       // most lanes per candidate group
     int32_t wg_rows;    // rows longer than this get the whole workgroup
     int32_t join_policy;
+    int32_t *marks;     // pushes into the scratch bitmap, while filtering (slab)
     __device__ uint64_t *B(int u) const { return bits + (int64_t)u * g.nwords; }
     __device__ int32_t *L(int u) const { return lists + (int64_t)u * lcap; }
 };
@@ -156,16 +160,21 @@ __device__ __forceinline__ char *slab_alloc(Ctx &c, int64_t bytes) {
     return p;
 }
 
-// Set bit x; on a newly set bit append x to list (when list != nullptr).
+// Set bit x; on a newly set bit append x to list tl, or, for a push into
+// the scratch bitmap (tl == nullptr: the parent's marks), to the marks list.
 __device__ __forceinline__ void push_bit(Ctx &c, uint64_t *tb, int32_t *tl, int v, int32_t x) {
     const uint64_t m = 1ull << (x & 63);
     uint64_t *w = tb + (x >> 6);
     if (__atomic_load_n(w, __ATOMIC_RELAXED) & m) return;
     const uint64_t old = atomicOr((unsigned long long *)w, m);
-    if (tl && !(old & m)) {
+    if (old & m) return;
+    if (tl) {
         const int32_t p = atomicAdd(&c.s->cnt[v], 1);
         if (p < c.lcap) tl[p] = x;
         else c.s->abort_ = kWhyList;
+    } else {
+        // marks are parent candidates, so at most lcap of them
+        c.marks[atomicAdd(&c.s->nmarks, 1)] = x;
     }
 }
 
@@ -291,9 +300,63 @@ __device__ __forceinline__ void row_of(const DevGraph &g, int32_t up, int dir, i
 // Whole workgroup on one candidate (uniform call). Prune: the candidate
 // survives if every listed query edge has a matching neighbour; explore
 // then pushes every matching neighbour.
+__device__ __forceinline__ int32_t max_row(const DevGraph &g, const NNbr *nb, int ncount, int32_t up);
+
 __device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb, int ncount, int32_t up,
                         uint64_t *ub, uint64_t &fb) {
     const DevGraph &g = c.g;
+    if (ncount <= 16 && max_row(g, nb, ncount, up) <= 4 * NT) {
+        // Every listed row fits one pass: all rows are read and tested at
+        // once (bit 4j + k of `hits`: entry threadIdx.x + k NT of row j
+        // matches), one barrier decides whether the candidate lives, and
+        // pushes replay the recorded hits.
+        if (threadIdx.x == 0) c.s->rowhit = 0ull;
+        __syncthreads();
+        uint64_t hits = 0, seen = 0;
+        for (int j = 0; j < ncount; ++j) {
+            const NNbr d = nb[j];
+            const int2 *adj = d.dir ? g.in_adj : g.out_adj;
+            int32_t beg, end;
+            row_of(g, up, d.dir, &beg, &end);
+            const int32_t i = beg + threadIdx.x;
+            const int2 e0 = adj_at(adj, i, end), e1 = adj_at(adj, i + NT, end);
+            const int2 e2 = adj_at(adj, i + 2 * NT, end), e3 = adj_at(adj, i + 3 * NT, end);
+            const uint64_t h = (uint64_t)((i < end) & nbr_hit(c, d, e0)) |
+                               (uint64_t)((i + NT < end) & nbr_hit(c, d, e1)) << 1 |
+                               (uint64_t)((i + 2 * NT < end) & nbr_hit(c, d, e2)) << 2 |
+                               (uint64_t)((i + 3 * NT < end) & nbr_hit(c, d, e3)) << 3;
+            if (h) atomicOr(&c.s->rowhit, 1ull << j);
+            hits |= h << (4 * j);
+            seen += end - beg;
+        }
+        __syncthreads();
+        const bool alive = __popcll(c.s->rowhit) == ncount;
+        __syncthreads();  // rowhit is read by all before the next candidate clears it
+        if (!alive) {
+            if (threadIdx.x == 0) {
+                atomicAnd((unsigned long long *)&ub[up >> 6], ~(1ull << (up & 63)));
+                atomicAdd(&c.s->removed, 1);
+                fb += 20ull + 12ull * seen;
+            }
+            return;
+        }
+        if (st.push)
+            for (int j = 0; j < ncount; ++j) {
+                const uint32_t hj = (uint32_t)(hits >> (4 * j)) & 15u;
+                if (!hj) continue;
+                const NNbr d = nb[j];
+                const int2 *adj = d.dir ? g.in_adj : g.out_adj;
+                int32_t beg, end;
+                row_of(g, up, d.dir, &beg, &end);
+                uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
+                int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if ((hj >> k) & 1u) push_bit(c, tb, tl, d.v, adj[beg + threadIdx.x + k * NT].x);
+            }
+        if (threadIdx.x == 0) fb += 20ull + 12ull * seen;
+        return;
+    }
     bool alive = true;
     uint64_t seen = 0;
     for (int j = 0; j < ncount && alive; ++j) {
@@ -489,6 +552,7 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
         c.s->nbig = 0;
         c.s->ngiant = 0;
         c.s->removed = 0;
+        c.s->nmarks = 0;
     }
     __syncthreads();
     const int32_t n_items = c.s->cnt[u];
@@ -657,7 +721,30 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
     add_bytes_wave(c, fb);
     __syncthreads();
     if (c.s->removed) compact_list(c, u);
-    if (st.parent >= 0) {
+    if (st.parent >= 0 && 4 * c.s->nmarks < c.s->cnt[st.parent]) {
+        // Intersect the parent's candidates with the pushed marks. The marks
+        // are parent candidates, so the intersection is the marks
+        // themselves: with few of them, clear the parent's old words and
+        // rebuild its bitmap and list from the marks.
+        const int p = st.parent;
+        uint64_t *pb = c.B(p);
+        int32_t *pl = c.L(p);
+        const int32_t n = c.s->cnt[p], nm = c.s->nmarks;
+        for (int32_t i = threadIdx.x; i < n; i += NT) pb[pl[i] >> 6] = 0ull;
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < nm; i += NT) {
+            const int32_t x = c.marks[i];
+            atomicOr((unsigned long long *)&pb[x >> 6], 1ull << (x & 63));
+            pl[i] = x;
+        }
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < nm; i += NT) c.scratch[pl[i] >> 6] = 0ull;
+        if (threadIdx.x == 0) {
+            c.s->cnt[p] = nm;
+            add_bytes(c, 12ull * n + 24ull * nm);
+        }
+        __syncthreads();
+    } else if (st.parent >= 0) {
         // intersect the parent's candidates with the pushed scratch bitmap
         const int p = st.parent;
         uint64_t *pb = c.B(p);
@@ -845,7 +932,29 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
     int64_t mytot = 0;
     uint64_t fb = 0;
     if (nk <= NW) {
-        for (int32_t it = 0; it < nk; ++it) {
+        // a handful of keys: one wave each, rows above wg_rows get the
+        // whole workgroup
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (wave < nk) {
+            const int32_t k = keys[wave];
+            const int32_t beg = off[k], end = off[k + 1];
+            if (end - beg > c.wg_rows) {
+                if (lane == 0) c.s->big[atomicAdd(&c.s->ngiant, 1)] = wave;  // at most NW
+            } else {
+                const bool probe = probe_cheaper(no, end - beg);
+                const int64_t n = probe ? ec_probe_wave(rel, ol, no, adj, beg, end, k, vals + degoff[wave])
+                                        : ec_key_wave(rel, ob, adj, beg, end, k, vals + degoff[wave]);
+                if (lane == 0) {
+                    num[wave] = (int32_t)n;
+                    mytot += n;
+                    fb += 16ull + 4ull * n + (probe ? probe_bytes(no, end - beg) : 12ull * (end - beg));
+                }
+            }
+        }
+        __syncthreads();
+        const int32_t ngiant = c.s->ngiant;
+        for (int32_t b = 0; b < ngiant; ++b) {
+            const int32_t it = c.s->big[b];
             const int32_t k = keys[it];
             const int32_t beg = off[k], end = off[k + 1];
             const bool probe = probe_cheaper(no, end - beg);
@@ -949,8 +1058,8 @@ __device__ __forceinline__ void join_order(Ctx &c) {
     for (int e = 1; e < Q.m; ++e)
         if (s.ectot[e] < s.ectot[e0]) e0 = e;
     int nj = 0, nc = 0;
-    s.jorder[nj++] = Q.esrc[e0];
-    vis |= 1u << Q.esrc[e0];
+    s.jorder[nj++] = s.qsrc[e0];
+    vis |= 1u << s.qsrc[e0];
     int ext = e0;
     for (int lv = 0; lv < Q.n - 1; ++lv) {
         if (lv > 0) {
@@ -961,14 +1070,14 @@ __device__ __forceinline__ void join_order(Ctx &c) {
             int ext_links = 0;
             for (int e = 0; e < Q.m; ++e) {
                 if ((used >> e) & 1ull) continue;
-                const bool va = (vis >> Q.esrc[e]) & 1u, vb = (vis >> Q.edst[e]) & 1u;
+                const bool va = (vis >> s.qsrc[e]) & 1u, vb = (vis >> s.qdst[e]) & 1u;
                 if (va == vb) continue;
                 int links = 0;
                 if (c.join_policy == 1) {
-                    const int w = va ? Q.edst[e] : Q.esrc[e];
+                    const int w = va ? s.qdst[e] : s.qsrc[e];
                     for (int f = 0; f < Q.m; ++f) {
                         if ((used >> f) & 1ull) continue;
-                        const int x = Q.esrc[f], y = Q.edst[f];
+                        const int x = s.qsrc[f], y = s.qdst[f];
                         links += (x == w && ((vis >> y) & 1u)) || (y == w && ((vis >> x) & 1u));
                     }
                 }
@@ -979,13 +1088,13 @@ __device__ __forceinline__ void join_order(Ctx &c) {
                 }
             }
         }
-        const int w = ((vis >> Q.esrc[ext]) & 1u) ? Q.edst[ext] : Q.esrc[ext];
+        const int w = ((vis >> s.qsrc[ext]) & 1u) ? s.qdst[ext] : s.qsrc[ext];
         used |= 1ull << ext;
         s.lv_ext[lv] = ext;
         s.lv_first[lv] = nc;
         for (int e = 0; e < Q.m; ++e) {
             if ((used >> e) & 1ull) continue;
-            const int x = Q.esrc[e], y = Q.edst[e];
+            const int x = s.qsrc[e], y = s.qdst[e];
             if ((x == w && ((vis >> y) & 1u)) || (y == w && ((vis >> x) & 1u))) {
                 s.chk[nc++] = e;
                 used |= 1ull << e;
@@ -997,7 +1106,7 @@ __device__ __forceinline__ void join_order(Ctx &c) {
     }
     for (int j = 0; j < Q.n; ++j) s.jpos[s.jorder[j]] = j;
     for (int e = 0; e < Q.m; ++e)
-        s.eckey[e] = s.jpos[Q.esrc[e]] < s.jpos[Q.edst[e]] ? Q.esrc[e] : Q.edst[e];
+        s.eckey[e] = s.jpos[s.qsrc[e]] < s.jpos[s.qdst[e]] ? s.qsrc[e] : s.qdst[e];
 }
 
 __device__ __forceinline__ bool ec_contains(const Ctx &c, int e, int32_t keyval, int32_t x) {
@@ -1159,7 +1268,11 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         s.level_rows[threadIdx.x] = 0;
         s.jorder[threadIdx.x] = -1;
     }
-    if (threadIdx.x < SGM_MAX_QE) s.ectot[threadIdx.x] = 0;
+    if (threadIdx.x < SGM_MAX_QE) {
+        s.ectot[threadIdx.x] = 0;
+        s.qsrc[threadIdx.x] = threadIdx.x < Q.m ? (int8_t)Q.esrc[threadIdx.x] : 0;
+        s.qdst[threadIdx.x] = threadIdx.x < Q.m ? (int8_t)Q.edst[threadIdx.x] : 0;
+    }
     if (threadIdx.x < 5) s.t[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         s.abort_ = 0;
@@ -1290,7 +1403,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                     // the level's pairs bound its rows: a level that could not
                     // fit even a much larger slot stops here rather than
                     // after filling this one
-                    {
+                    if (rows > NT) {  // one chunk learns its pair count below
                         int64_t mp = 0;
                         for (int64_t r = threadIdx.x; r < rows; r += NT) {
                             const int32_t pv = table[r * k + cp];
@@ -1324,6 +1437,15 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                         if (r < rows) jb += 16ull + 4ull * (32 - __clz(npk | 1));
                         int64_t tot;
                         const int64_t ex = block_excl_scan(fan, s.sh, &tot);
+                        if (rows <= NT && tot > kPairSlack * cap) {
+                            // the single chunk's pairs: same early stop
+                            if (threadIdx.x == 0) {
+                                s.abort_ = kWhySlab;
+                                s.need = (s.slab_used - cap * 4 * (k + 1)) + tot * 4 * (k + 1);
+                            }
+                            __syncthreads();
+                            break;
+                        }
                         s.pairoff[threadIdx.x] = (int32_t)ex;
                         s.rowlo[threadIdx.x] = lo;
                         __syncthreads();
@@ -1570,7 +1692,10 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
         Ctx c{a.g,  a.lcap, a.slab_bytes, a.out, a.out_cap, a.out_used, a.rootbits, &Q, &s,
               bits, bits + (int64_t)SGM_MAX_QV * nwords, lists, slab, dyn,
               a.trace ? a.trace + (int64_t)q * SGM_TRACE_CAP : nullptr, a.group_lanes,
-              a.wg_rows, a.join_policy};
+              a.wg_rows, a.join_policy,
+              // while filtering the slab holds the long-row overflow list in
+              // [0, 4 lcap) bytes and the marks in [4 lcap, 8 lcap)
+              (int32_t *)(slab + 4 * (int64_t)a.lcap)};
         if (threadIdx.x == 0) s.nev = 0;
         run_query(c);
         __syncthreads();
