@@ -154,6 +154,32 @@ def test_batch_graph_replays(medium_kg, medium_queries, medium_expected):
     gd.close()
 
 
+def test_vertex_renaming_medium(medium_kg, medium_queries, medium_expected):
+    """The medium graph with its vertices renamed by a random permutation (a
+    different CSR layout, root sweep and hub placement): every result, renamed
+    back and re-sorted, equals the oracle's on the original graph."""
+    say("case: medium graph with renamed vertices")
+    kg = medium_kg
+    rng = np.random.default_rng(77)
+    perm = rng.permutation(kg.V).astype(np.int32)
+    inv = np.argsort(perm).astype(np.int32)
+    ns, nd = perm[kg.src()], perm[kg.col]
+    order = np.lexsort((kg.rel, nd, ns))
+    row_ptr = np.zeros(kg.V + 1, np.int64)
+    np.cumsum(np.bincount(ns, minlength=kg.V), out=row_ptr[1:])
+    vt = np.empty_like(kg.vtype)
+    vt[perm] = kg.vtype
+    gp = P.Graph(row_ptr.astype(np.int32), nd[order], kg.rel[order], vt)
+    qs = medium_queries[:40]
+    renamed = [MicroQuery(q.n, q.vlabel, np.where(q.vpin >= 0, perm[np.maximum(q.vpin, 0)], -1),
+                          q.esrc, q.edst, q.elabel) for q in qs]
+    for got, want in zip(gp.match_batch(renamed), medium_expected[:40]):
+        back = inv[got]
+        back = back[np.lexsort(back.T[::-1])] if len(back) else back
+        same(back, want)
+    gp.close()
+
+
 def any_query(n, edges, vlabel=None, vpin=None):
     return MicroQuery(n, [-1] * n if vlabel is None else vlabel,
                       [-1] * n if vpin is None else vpin,

@@ -260,3 +260,70 @@ def test_oracle_rejects_bad_queries(oracle_tiny):
     with pytest.raises(oracle.OracleError) as e:
         oracle_tiny.match(2, [-1, -1], [-1, -1], [0], [1], [-1], max_rows=10)
     assert e.value.code == oracle.OR_ETOOBIG
+
+
+# --------------------------------------------------------------------------
+# P4: metamorphic invariants (the definition is invariant under renaming)
+# --------------------------------------------------------------------------
+
+def _permuted_graph(g: MicroGraph, perm):
+    """Data vertex v becomes perm[v]."""
+    vtype = np.empty_like(g.vtype)
+    vtype[perm] = g.vtype
+    return MicroGraph(g.V, perm[g.src], perm[g.dst], g.rel, vtype)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_vertex_renaming_permutes_rows(seed):
+    """Renaming data vertices renames the values of every row; renumbering
+    query vertices permutes the columns. Rows are then re-sorted."""
+    rng = np.random.default_rng(5000 + seed)
+    V = int(rng.integers(4, 10))
+    g = random_graph(rng, V, 3 * V, n_types=2, n_rels=2)
+    perm = rng.permutation(V).astype(np.int32)
+    gp = _permuted_graph(g, perm)
+    og, ogp = og_of(g), og_of(gp)
+    for _ in range(4):
+        q = random_query(rng, int(rng.integers(2, 5)), 2, 2, V, p_pin=0.2)
+        base = og.match_query(q)
+        # data renaming: pins follow the renaming
+        qp = MicroQuery(q.n, q.vlabel, np.where(q.vpin >= 0, perm[np.maximum(q.vpin, 0)], -1),
+                        q.esrc, q.edst, q.elabel)
+        got = ogp.match_query(qp)
+        want = np.array(sorted(tuple(int(perm[x]) for x in r) for r in base), np.int32)
+        assert np.array_equal(got.reshape(-1, q.n), want.reshape(-1, q.n))
+        # query renumbering: query vertex u becomes sigma[u]
+        sigma = rng.permutation(q.n)
+        inv = np.argsort(sigma)
+        qs = MicroQuery(q.n, q.vlabel[inv], q.vpin[inv], sigma[q.esrc], sigma[q.edst], q.elabel)
+        got = og.match_query(qs)
+        want = np.array(sorted(tuple(int(r[inv[c]]) for c in range(q.n)) for r in base), np.int32)
+        assert np.array_equal(got.reshape(-1, q.n), want.reshape(-1, q.n))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_more_constraints_give_subsets(seed):
+    """Adding a query edge between matched vertices, or pinning a vertex,
+    keeps exactly the rows that satisfy the new constraint."""
+    rng = np.random.default_rng(6000 + seed)
+    V = int(rng.integers(4, 9))
+    g = random_graph(rng, V, 3 * V, n_types=2, n_rels=2)
+    og = og_of(g)
+    E = g.edge_set()
+    for _ in range(4):
+        q = random_query(rng, int(rng.integers(2, 5)), 2, 2, V, p_pin=0.0)
+        base = rows_of(og.match_query(q))
+        # a pin on vertex u to x keeps the rows with f(u) = x
+        u, x = int(rng.integers(0, q.n)), int(rng.integers(0, V))
+        qp = MicroQuery(q.n, q.vlabel, np.where(np.arange(q.n) == u, x, q.vpin), q.esrc, q.edst,
+                        q.elabel)
+        assert rows_of(og.match_query(qp)) == [r for r in base if r[u] == x]
+        # a new edge a -> b (any relation) keeps the rows with a data edge f(a) -> f(b)
+        a, b = (int(t) for t in rng.choice(q.n, 2, replace=False))
+        if any(int(s) == a and int(d) == b and int(r) == -1
+               for s, d, r in zip(q.esrc, q.edst, q.elabel)):
+            continue
+        qe = MicroQuery(q.n, q.vlabel, q.vpin, np.append(q.esrc, a), np.append(q.edst, b),
+                        np.append(q.elabel, -1))
+        pairs = {(s, d) for s, d, _ in E}
+        assert rows_of(og.match_query(qe)) == [r for r in base if (r[a], r[b]) in pairs]
