@@ -165,3 +165,58 @@ def test_large_cyclic_queries(large_kg, g_large, oracle_large):
             same(rows, oracle_large.match_query(q, max_steps=BUDGET))
         except oracle.OracleError as e:
             assert e.code == oracle.OR_EBUDGET
+
+
+def test_large_cyclic_fixture(large_kg, g_large, oracle_large):
+    """The stored 50-query large cyclic workload (8-16 vertices, 1-3 cycles,
+    no pins): exact counts for all; where the oracle finishes within its
+    budget, its table equals the library's element by element (full tables
+    on the persistent or multi-kernel path as each query needs)."""
+    qs = kggen.load_large_cyclic()
+    rng = np.random.default_rng(21)
+    full = 0
+    for i, q in enumerate(qs):
+        n, st = g_large.match_query(q, count_only=True, with_stats=True)
+        say(f"case: cyclic fixture {i} n={q.n} m={q.m} rows={n} path={st['path']} "
+            f"chunks={st['n_chunks']}")
+        try:
+            want = oracle_large.match_query(q, max_steps=BUDGET)
+        except oracle.OracleError as e:
+            assert e.code == oracle.OR_EBUDGET
+            if n <= 2_000_000:
+                rows = g_large.match_query(q)
+                assert len(rows) == n
+                check_rows_valid(rows, q, large_kg)
+                check_slices(rows, q, oracle_large, rng, n_present=2, n_absent=1, col=0)
+            continue
+        assert n == len(want)
+        same(g_large.match_query(q), want)
+        full += 1
+    say(f"  {full} of {len(qs)} compared in full")
+    assert full >= 10
+
+
+def test_large_batch_full_size(large_kg, g_large, oracle_large):
+    """The full 1024-query batch of the batched form (one persistent launch,
+    large-slot reruns as needed): every count equals the multi-kernel path's
+    (different kernels, same definition), and a sample of 64 queries equals
+    the oracle element by element."""
+    qs, _ = kggen.batch_queries(large_kg, 1024)
+    say("case: large batch of 1024")
+    got = g_large.match_batch(qs)
+    gw = P.Graph.from_kg(large_kg, path=P.SGM_PATH_WIDE)
+    for i, (q, r) in enumerate(zip(qs, got)):
+        assert len(r) == gw.match_query(q, count_only=True), i
+    gw.close()
+    rng = np.random.default_rng(5)
+    compared = 0
+    for i in rng.choice(len(qs), 64, replace=False):
+        try:
+            want = oracle_large.match_query(qs[i], max_steps=BUDGET)
+        except oracle.OracleError as e:
+            assert e.code == oracle.OR_EBUDGET
+            continue
+        same(got[i], want)
+        compared += 1
+    say(f"  {compared} of 64 sampled compared with the oracle")
+    assert compared >= 40
