@@ -235,14 +235,21 @@ int sgm_trace_events(sgm_graph *g, int32_t i, int64_t *out, int32_t cap, double 
 /*
  * Work division and join schedule of the persistent kernel (the batched
  * form). Results never depend on these; speed does. Defaults: slots 512,
- * group_lanes 64, wg_rows 8192, join_policy 0.
- *   slots        workgroups of one persistent launch (1..512; two per CU fit)
+ * group_lanes 64, wg_rows 8192, join_policy 0, help_items 1024, helpers 256.
+ *   slots        workgroups of one persistent launch that take queries
+ *                (1..512; two per CU fit)
  *   group_lanes  most lanes working on one candidate's rows (1, 2, 4, ..., 64)
  *   wg_rows      rows longer than this are scanned by the whole workgroup
  *                (>= 64; shorter long rows get one wave)
  *   join_policy  0: bind the vertex of the cheapest candidate-edge table
  *                next (thesis Sec. "Joining Phase"); 1: bind the vertex with
  *                the most edges to bound vertices first, cheapest on ties
+ *   help_items   a filter step over at least this many candidates is shared
+ *                with the launch's idle workgroups, which claim chunks of
+ *                its candidate list (0: never; else >= 64)
+ *   helpers      a launch with fewer queries than this adds workgroups that
+ *                only help, up to this many workgroups in all (0..512; used
+ *                only with help_items > 0; the served form adds none)
  * The multi-kernel path keeps the thesis order.
  */
 typedef struct {
@@ -250,7 +257,9 @@ typedef struct {
     int32_t group_lanes;
     int32_t wg_rows;
     int32_t join_policy;
-    int32_t reserved[4];
+    int32_t help_items;
+    int32_t helpers;
+    int32_t reserved[2];
 } sgm_tuning;
 
 void sgm_default_tuning(sgm_tuning *t);
@@ -262,7 +271,8 @@ int sgm_set_tuning(sgm_graph *g, const sgm_tuning *t);
 /*
  * Autotuner: runs the n sample queries as persistent-kernel batches (count
  * only, reps times each) under every tuning of a small grid (slots 256/512,
- * group_lanes 16/64, wg_rows 2048/8192/32768, join_policy 0/1), keeps the
+ * group_lanes 16/64, wg_rows 2048/8192/32768, join_policy 0/1, help_items
+ * 0/1024; helpers as set), keeps the
  * one with the lowest median batch time, sets it on the graph and returns it
  * in *best (may be NULL). Every tuning must give the same per-query row
  * counts; otherwise the previous tuning is restored and SGM_EDEVICE

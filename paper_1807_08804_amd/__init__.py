@@ -82,7 +82,10 @@ class sgm_serve_stats(ctypes.Structure):
 class sgm_tuning(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("group_lanes", ctypes.c_int32),
                 ("wg_rows", ctypes.c_int32), ("join_policy", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("help_items", ctypes.c_int32), ("helpers", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+TUNING_FIELDS = ("slots", "group_lanes", "wg_rows", "join_policy", "help_items", "helpers")
 
 
 class sgm_kstat(ctypes.Structure):
@@ -403,13 +406,15 @@ class Graph:
         rc = lib().sgm_get_tuning(self._h, ctypes.byref(t))
         if rc != SGM_OK:
             raise SGMError(rc, "sgm_get_tuning")
-        return {k: getattr(t, k) for k in ("slots", "group_lanes", "wg_rows", "join_policy")}
+        return {k: getattr(t, k) for k in TUNING_FIELDS}
 
     def set_tuning(self, **kw):
         """Change tuning fields (sgm_set_tuning); results do not depend on them."""
         t = sgm_tuning()
         lib().sgm_get_tuning(self._h, ctypes.byref(t))
         for k, v in kw.items():
+            if k not in TUNING_FIELDS:
+                raise TypeError(f"unknown tuning field {k!r}")
             setattr(t, k, int(v))
         rc = lib().sgm_set_tuning(self._h, ctypes.byref(t))
         if rc != SGM_OK:
@@ -423,7 +428,7 @@ class Graph:
         rc = lib().sgm_autotune(self._h, arr, len(built), int(reps), ctypes.byref(t))
         if rc != SGM_OK:
             raise SGMError(rc, "sgm_autotune")
-        return {k: getattr(t, k) for k in ("slots", "group_lanes", "wg_rows", "join_policy")}
+        return {k: getattr(t, k) for k in TUNING_FIELDS}
 
     def kernel_stats(self):
         out = {}

@@ -172,7 +172,11 @@ struct NarrowCtx {
     uint64_t *d_rootbits = nullptr;
     int32_t *d_out = nullptr;
     int64_t out_cap = 0;
-    unsigned long long *d_ctr = nullptr, *h_ctr = nullptr;  // [0] queue, [1] out used
+    // [0] queue, [1] out used, [2] helper counters (posted steps, slot
+    // workgroups done)
+    unsigned long long *d_ctr = nullptr, *h_ctr = nullptr;
+    HelpJob *d_board = nullptr;  // [kNarrowMaxSlots] shared filter steps
+    bool serve = false;          // a server's context: no shared steps
     int32_t *h_out = nullptr;
     int64_t h_out_cap = 0;
     int64_t *d_trace = nullptr, *h_trace = nullptr;  // [trace_cap][SGM_TRACE_CAP]
@@ -241,7 +245,7 @@ struct sgm_graph {
     // persistent per-query kernel on the graph's own stream
     NarrowCtx nw;
     NarrowCtx nwb;  // few large slots for queries that outgrow a regular one
-    sgm_tuning tune{512, 64, 8192, 0, {0, 0, 0, 0}};
+    sgm_tuning tune{512, 64, 8192, 0, 1024, 256, {0, 0}};
 };
 
 namespace {
@@ -1138,6 +1142,7 @@ void narrow_free(NarrowCtx &nw) {
     dev_free(nw.d_rootbits);
     dev_free(nw.d_out);
     dev_free(nw.d_ctr);
+    dev_free(nw.d_board);
     host_free(nw.h_q);
     host_free(nw.h_res);
     host_free(nw.h_preds);
@@ -1154,6 +1159,7 @@ void narrow_free(NarrowCtx &nw) {
     const NarrowCtx keep = nw;
     nw = NarrowCtx{};
     nw.stream = keep.stream;
+    nw.serve = keep.serve;
     nw.lcap_want = keep.lcap_want;
     nw.slab_want = keep.slab_want;
 }
@@ -1164,8 +1170,12 @@ void narrow_reserve(sgm_graph *g, NarrowCtx &nw, int slots, int nq, int nroot) {
         nw.slab_bytes = nw.slab_want ? nw.slab_want : narrow_slab_bytes(g);
         // while filtering, a slot's slab holds two lists of up to lcap ints
         if (nw.slab_bytes < 8ll * nw.lcap) throw DeviceError{SGM_EUNSUPPORTED};
-        HIPX(hipMalloc(&nw.d_ctr, sizeof(unsigned long long) * 2));
+        HIPX(hipMalloc(&nw.d_ctr, sizeof(unsigned long long) * 3));
         HIPX(hipHostMalloc(&nw.h_ctr, sizeof(unsigned long long) * 2, hipHostMallocDefault));
+        // board entries start at sequence 0 with no chunks; the kernel
+        // retires every step it posts, so they need no clearing later
+        HIPX(hipMalloc(&nw.d_board, sizeof(HelpJob) * kNarrowMaxSlots));
+        HIPX(hipMemsetAsync(nw.d_board, 0, sizeof(HelpJob) * kNarrowMaxSlots, nw.stream));
         nw.out_cap = kNarrowOutCap;
         HIPX(hipMalloc(&nw.d_out, sizeof(int32_t) * nw.out_cap));
         HIPX(hipEventCreateWithFlags(&nw.done, hipEventDisableTiming));
@@ -1380,7 +1390,19 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     a.join_policy = g->tune.join_policy;
     nw.sa = SweepArgs{g->dg,       nw.d_preds, nroot, n_any, nw.d_rootbits, nw.d_ctr,
                       (const int32_t *)(nw.d_preds + std::max(nroot, 1)), n_types};
-    const int grid = std::min(np, nw.slab_want ? nw.slots : std::min(nw.slots, g->tune.slots));
+    const int slot_grid =
+        std::min(np, nw.slab_want ? nw.slots : std::min(nw.slots, g->tune.slots));
+    // Shared filter steps need every workgroup of the launch resident at
+    // once (two per CU): helpers then wait only for work that exists. A
+    // server's contexts launch side by side, so they share no steps.
+    const bool help = !nw.serve && g->tune.help_items > 0;
+    a.nslot = slot_grid;
+    a.help_items = help ? g->tune.help_items : 0;
+    a.board = nw.d_board;
+    a.hctr = (int32_t *)(nw.d_ctr + 2);
+    const int grid =
+        help ? std::min(kNarrowMaxSlots, std::max(slot_grid, g->tune.helpers)) : slot_grid;
+    a.ngrid = grid;
     job.traced = profiled && g->opts.profile >= 2;
     if (g->opts.graphs && !(profiled && g->opts.profile)) {
         nw.na = a;
@@ -1771,7 +1793,7 @@ void sgm_free_graph(sgm_graph *g) {
 
 void sgm_default_tuning(sgm_tuning *t) {
     if (!t) return;
-    *t = sgm_tuning{512, 64, 8192, 0, {0, 0, 0, 0}};
+    *t = sgm_tuning{512, 64, 8192, 0, 1024, 256, {0, 0}};
 }
 
 int sgm_get_tuning(const sgm_graph *g, sgm_tuning *t) {
@@ -1783,14 +1805,15 @@ int sgm_get_tuning(const sgm_graph *g, sgm_tuning *t) {
 static bool tuning_ok(const sgm_tuning &t) {
     const bool pow2 = t.group_lanes > 0 && (t.group_lanes & (t.group_lanes - 1)) == 0;
     return t.slots >= 1 && t.slots <= 512 && pow2 && t.group_lanes <= 64 && t.wg_rows >= 64 &&
-           (t.join_policy == 0 || t.join_policy == 1);
+           (t.join_policy == 0 || t.join_policy == 1) &&
+           (t.help_items == 0 || t.help_items >= 64) && t.helpers >= 0 && t.helpers <= 512;
 }
 
 int sgm_set_tuning(sgm_graph *g, const sgm_tuning *t) {
     if (!g || !t || !tuning_ok(*t)) return SGM_EINVAL;
     std::lock_guard<std::mutex> lk(g->mu);
     g->tune = *t;
-    g->tune.reserved[0] = g->tune.reserved[1] = g->tune.reserved[2] = g->tune.reserved[3] = 0;
+    g->tune.reserved[0] = g->tune.reserved[1] = 0;
     return SGM_OK;
 }
 
@@ -1808,7 +1831,9 @@ int sgm_autotune(sgm_graph *g, const sgm_query *qs, int32_t n, int32_t reps, sgm
     for (int sl : {256, 512})
         for (int gl : {16, 64})
             for (int wr : {2048, 8192, 32768})
-                for (int jp : {0, 1}) grid.push_back(sgm_tuning{sl, gl, wr, jp, {0, 0, 0, 0}});
+                for (int jp : {0, 1})
+                    for (int hi : {0, 1024})
+                        grid.push_back(sgm_tuning{sl, gl, wr, jp, hi, saved.helpers, {0, 0}});
     std::vector<sgm_result> store((size_t)n);
     std::vector<sgm_result *> res((size_t)n);
     for (int i = 0; i < n; ++i) res[i] = &store[i];
@@ -2228,6 +2253,7 @@ int sgm_server_create(sgm_graph *g, const sgm_serve_options *opts, sgm_server **
         HIPX(hipSetDevice(g->device));
         for (auto &c : S->ctx) {
             HIPX(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+            c.serve = true;
             narrow_reserve(g, c, std::min(o.max_batch, kNarrowMaxSlots), o.max_batch, 0);
         }
     } catch (const DeviceError &e) {

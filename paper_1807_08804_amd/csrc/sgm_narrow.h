@@ -66,9 +66,28 @@ constexpr int32_t kOutFull = 2;   // the shared output arena was full
 constexpr int32_t kWhyList = 1;   // a candidate list outgrew its slot capacity
 constexpr int32_t kWhySlab = 2;   // edge tables / join tables / sort buffers outgrew the slab
 constexpr int32_t kWhyKey = 4;    // the ordering key would need more than 64 bits
+constexpr int32_t kWhyHelp = 8;   // shared filter step not finished by its helpers in time
 // A join level whose pairs (an upper bound on its rows) would need more than
 // this many times the slab left stops at once instead of filling the slab.
 constexpr int64_t kPairSlack = 8;
+
+// One filter step shared by several workgroups: the owner of a query posts
+// the step here, and idle workgroups of the same launch claim chunks of its
+// candidate list. During the step its counters live here instead of in the
+// owner's LDS. One entry per slot workgroup; entries are zeroed when
+// allocated and every posted step is retired before its owner moves on.
+// claim packs (sequence:24 | chunks:20 | next chunk:20): one atomic add
+// claims a chunk and returns which step it belongs to and whether it exists.
+struct HelpJob {
+    unsigned long long claim;
+    unsigned long long bytes;  // algorithmic bytes of the helpers' chunks
+    int32_t chunk, done, q, pad;
+    int32_t n_items, G, ncount, revd;
+    NStep st;
+    int32_t nbig, removed, nmarks, abort_;
+    int32_t cnt[SGM_MAX_QV];
+    NNbr nbl[SGM_MAX_QE];
+};
 
 struct NArgs {
     DevGraph g;
@@ -91,11 +110,20 @@ struct NArgs {
     int32_t group_lanes;      // most lanes per candidate group (power of two, 1..64)
     int32_t wg_rows;          // rows longer than this get the whole workgroup
     int32_t join_policy;      // 0: cheapest edge first; 1: most-constrained vertex first
+    // shared filter steps: workgroups [0, nslot) own slots and take queries;
+    // the others, and slot workgroups whose queue ran dry, help. A step of
+    // at least help_items candidates is shared (0: never).
+    int32_t nslot;
+    int32_t ngrid;            // workgroups of the launch (>= nslot)
+    int32_t help_items;
+    HelpJob *board;           // [nslot]
+    int32_t *hctr;            // [0] posted steps, [1] slot workgroups done
 };
 
 // Root sweep: rootbits[j][w] = vertices satisfying predicate j, for the
-// distinct predicates of a batch's unpinned roots. It also zeroes ctr[0..1]
-// (the persistent kernel's work queue and output-arena use), so it runs
+// distinct predicates of a batch's unpinned roots. It also zeroes ctr[0..2]
+// (the persistent kernel's work queue, output-arena use and helper
+// counters), so it runs
 // before every persistent launch, with n_pred = 0 when no root needs it.
 struct SweepArgs {
     DevGraph g;

@@ -59,6 +59,8 @@ struct Smem {
     int32_t nnbl;
     int32_t nmarks;
     unsigned long long rowhit;  // item_wg: listed rows with a matching entry
+    unsigned long long hseq;    // sequence number of the step this workgroup posted
+    int32_t hq, hch;            // helper: board entry and chunk claimed (-1: none)
     int8_t qsrc[SGM_MAX_QE], qdst[SGM_MAX_QE];  // the query's edges, staged for join_order
     uint64_t revmask;
     NNbr nbl[SGM_MAX_QE];  // neighbours a step still tests per candidate
@@ -112,6 +114,11 @@ struct Ctx {
     int32_t wg_rows;    // rows longer than this get the whole workgroup
     int32_t join_policy;
     int32_t *marks;     // pushes into the scratch bitmap, while filtering (slab)
+    HelpJob *job;       // this slot's entry on the helper board
+    int32_t *hctr;      // posted shared steps, slot workgroups done
+    int32_t help_items; // share filter steps of at least this many candidates (0: never)
+    int32_t q;          // index of the query in the batch
+    int32_t nslot, ngrid;  // slot workgroups, all workgroups of the launch
     __device__ uint64_t *B(int u) const { return bits + (int64_t)u * g.nwords; }
     __device__ int32_t *L(int u) const { return lists + (int64_t)u * lcap; }
 };
@@ -160,21 +167,89 @@ __device__ __forceinline__ char *slab_alloc(Ctx &c, int64_t bytes) {
     return p;
 }
 
+// Counters a filter step updates: in the workgroup's LDS, or on the helper
+// board while several workgroups share the step.
+struct LdsCtr {
+    Smem *s;
+    __device__ int32_t *cnt(int v) const { return &s->cnt[v]; }
+    __device__ int32_t *nbig() const { return &s->nbig; }
+    __device__ int32_t *removed() const { return &s->removed; }
+    __device__ int32_t *nmarks() const { return &s->nmarks; }
+    __device__ int32_t *abort_() const { return &s->abort_; }
+};
+struct BoardCtr {
+    HelpJob *j;
+    __device__ int32_t *cnt(int v) const { return &j->cnt[v]; }
+    __device__ int32_t *nbig() const { return &j->nbig; }
+    __device__ int32_t *removed() const { return &j->removed; }
+    __device__ int32_t *nmarks() const { return &j->nmarks; }
+    __device__ int32_t *abort_() const { return &j->abort_; }
+};
+
 // Set bit x; on a newly set bit append x to list tl, or, for a push into
 // the scratch bitmap (tl == nullptr: the parent's marks), to the marks list.
-__device__ __forceinline__ void push_bit(Ctx &c, uint64_t *tb, int32_t *tl, int v, int32_t x) {
+template <class K>
+__device__ __forceinline__ void push_bit(Ctx &c, const K &k, uint64_t *tb, int32_t *tl, int v,
+                                         int32_t x) {
     const uint64_t m = 1ull << (x & 63);
     uint64_t *w = tb + (x >> 6);
     if (__atomic_load_n(w, __ATOMIC_RELAXED) & m) return;
     const uint64_t old = atomicOr((unsigned long long *)w, m);
     if (old & m) return;
     if (tl) {
-        const int32_t p = atomicAdd(&c.s->cnt[v], 1);
+        const int32_t p = atomicAdd(k.cnt(v), 1);
         if (p < c.lcap) tl[p] = x;
-        else c.s->abort_ = kWhyList;
+        else *k.abort_() = kWhyList;
     } else {
         // marks are parent candidates, so at most lcap of them
-        c.marks[atomicAdd(&c.s->nmarks, 1)] = x;
+        c.marks[atomicAdd(k.nmarks(), 1)] = x;
+    }
+}
+
+__device__ __forceinline__ void push_bit(Ctx &c, uint64_t *tb, int32_t *tl, int v, int32_t x) {
+    push_bit(c, LdsCtr{c.s}, tb, tl, v, x);
+}
+
+// Set bit x in tb; true if it was clear.
+__device__ __forceinline__ bool set_new(uint64_t *tb, int32_t x) {
+    const uint64_t m = 1ull << (x & 63);
+    uint64_t *w = tb + (x >> 6);
+    if (__atomic_load_n(w, __ATOMIC_RELAXED) & m) return false;
+    return (atomicOr((unsigned long long *)w, m) & m) == 0;
+}
+
+// push_bit for up to four entries per lane (hk: push xk), appending the
+// newly set ones with one counter update per wave: the lanes that reach
+// this call take consecutive places in the order of their lane index.
+template <class K>
+__device__ __forceinline__ void push4(Ctx &c, const K &k, uint64_t *tb, int32_t *tl, int v,
+                                      bool h0, int32_t x0, bool h1, int32_t x1, bool h2,
+                                      int32_t x2, bool h3, int32_t x3) {
+    const bool n0 = h0 && set_new(tb, x0), n1 = h1 && set_new(tb, x1);
+    const bool n2 = h2 && set_new(tb, x2), n3 = h3 && set_new(tb, x3);
+    const int cnt = (int)n0 + (int)n1 + (int)n2 + (int)n3;
+    const uint64_t b0 = __ballot(cnt & 1), b1 = __ballot(cnt & 2), b2 = __ballot(cnt & 4);
+    const int tot = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
+    if (tot == 0) return;
+    const uint64_t lt = lanemask_lt(threadIdx.x & 63);
+    const int pre = __popcll(b0 & lt) + 2 * __popcll(b1 & lt) + 4 * __popcll(b2 & lt);
+    const int leader = __ffsll((unsigned long long)__ballot(1)) - 1;
+    int32_t base = 0;
+    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(tl ? k.cnt(v) : k.nmarks(), tot);
+    base = __builtin_amdgcn_readlane(base, leader);
+    int32_t p = base + pre;
+    if (tl) {
+        // a list may outgrow its capacity: the query then leaves the slot
+        if (n0) { if (p < c.lcap) tl[p] = x0; else *k.abort_() = kWhyList; ++p; }
+        if (n1) { if (p < c.lcap) tl[p] = x1; else *k.abort_() = kWhyList; ++p; }
+        if (n2) { if (p < c.lcap) tl[p] = x2; else *k.abort_() = kWhyList; ++p; }
+        if (n3) { if (p < c.lcap) tl[p] = x3; else *k.abort_() = kWhyList; }
+    } else {
+        // marks are parent candidates, so at most lcap of them
+        if (n0) c.marks[p++] = x0;
+        if (n1) c.marks[p++] = x1;
+        if (n2) c.marks[p++] = x2;
+        if (n3) c.marks[p] = x3;
     }
 }
 
@@ -542,6 +617,205 @@ __device__ __forceinline__ void prune_reverse(Ctx &c, int u, int v, int dir, int
     __syncthreads();
 }
 
+// Candidates [it0, it1) of u's list (ul, bitmap ub), G lanes each: a
+// candidate lacking a matching neighbour for one of the ncount tests is
+// dropped; with push, the neighbours of the others that pass a test are
+// pushed. Candidates with a row longer than 64 G entries go to the overflow
+// list at the start of the slab for a wider tier. Counters go to k.
+template <class K>
+__device__ __forceinline__ void filter_items(Ctx &c, const K &k, bool push, const NNbr *nb,
+                                             int ncount, const int32_t *ul, uint64_t *ub,
+                                             bool revd, int G, int32_t it0, int32_t it1,
+                                             uint64_t &fb) {
+    const DevGraph &g = c.g;
+    const int NGr = NT / G;
+    const int lane = threadIdx.x & 63, gl = lane & (G - 1), gb = lane & ~(G - 1);
+    const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << gb;
+    const int32_t bigdeg = 64 * G;  // more than 64 strides: a wider tier
+    // The overflow list sits at the start of the slot's slab, which no phase
+    // uses while filtering (at most lcap entries, far below its size).
+    int32_t *ov = (int32_t *)c.slab;
+    for (int32_t it = it0 + threadIdx.x / G; it < it1; it += NGr) {
+        const int32_t up = ul[it];
+        if (revd && !bit_test(ub, up)) continue;  // already dropped
+        const int32_t ob = g.out_off[up], oe = g.out_off[up + 1];
+        const int32_t ib = g.in_off[up], ie = g.in_off[up + 1];
+        int32_t maxd = 0;
+        for (int j = 0; j < ncount; ++j) maxd = max(maxd, nb[j].dir ? ie - ib : oe - ob);
+        if (maxd > bigdeg) {
+            // long rows: a wider tier after this loop. The overflow list
+            // sits at the start of the slot's slab, which no phase uses
+            // while filtering (at most lcap entries, far below its size).
+            if (gl == 0) ov[atomicAdd(k.nbig(), 1)] = up;
+            continue;
+        }
+        bool alive = true;
+        uint64_t seen = 0;
+        for (int j = 0; j < ncount && alive; ++j) {
+            const NNbr d = nb[j];
+            const int2 *adj = d.dir ? g.in_adj : g.out_adj;
+            const int32_t beg = d.dir ? ib : ob, end = d.dir ? ie : oe;
+            bool found = false;
+            // four entries per lane in flight; lanes past the row test an
+            // in-range dummy entry and discard the answer
+            for (int32_t base = beg; base < end; base += 4 * G) {
+                const int32_t i = base + gl;
+                const int2 e0 = adj_at(adj, i, end), e1 = adj_at(adj, i + G, end);
+                const int2 e2 = adj_at(adj, i + 2 * G, end), e3 = adj_at(adj, i + 3 * G, end);
+                const bool hit = ((i < end) & nbr_hit(c, d, e0)) |
+                                 ((i + G < end) & nbr_hit(c, d, e1)) |
+                                 ((i + 2 * G < end) & nbr_hit(c, d, e2)) |
+                                 ((i + 3 * G < end) & nbr_hit(c, d, e3));
+                seen += min(4 * G, end - base);
+                if (__ballot(hit) & gmask) {
+                    found = true;
+                    break;
+                }
+            }
+            alive = found;
+        }
+        if (!alive) {
+            if (gl == 0) {
+                atomicAnd((unsigned long long *)&ub[up >> 6], ~(1ull << (up & 63)));
+                atomicAdd(k.removed(), 1);
+                fb += 20ull + 12ull * seen;
+            }
+            continue;
+        }
+        if (push)
+            for (int j = 0; j < ncount; ++j) {
+                const NNbr d = nb[j];
+                const int2 *adj = d.dir ? g.in_adj : g.out_adj;
+                const int32_t beg = d.dir ? ib : ob, end = d.dir ? ie : oe;
+                uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
+                int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
+                seen += end - beg;
+                for (int32_t i = beg + gl; i < end; i += 4 * G) {
+                    const int2 e0 = adj_at(adj, i, end), e1 = adj_at(adj, i + G, end);
+                    const int2 e2 = adj_at(adj, i + 2 * G, end), e3 = adj_at(adj, i + 3 * G, end);
+                    const bool h0 = (i < end) & nbr_hit(c, d, e0);
+                    const bool h1 = (i + G < end) & nbr_hit(c, d, e1);
+                    const bool h2 = (i + 2 * G < end) & nbr_hit(c, d, e2);
+                    const bool h3 = (i + 3 * G < end) & nbr_hit(c, d, e3);
+                    push4(c, k, tb, tl, d.v, h0, e0.x, h1, e1.x, h2, e2.x, h3, e3.x);
+                }
+            }
+        if (gl == 0) fb += 20ull + 12ull * seen;
+    }
+}
+
+// Polls of a posted step's completion count before its owner gives up (an
+// error: every claimed chunk finishes in bounded time), and empty polls in
+// a row before a helper leaves (helping is optional, so leaving early only
+// costs speed; about a second of polling).
+constexpr int64_t kHelpWait = 1ll << 22;
+constexpr int64_t kHelpIdle = 1ll << 20;
+
+// Claim word of a posted step, and a claim's outcome.
+__device__ __forceinline__ unsigned long long claim_word(uint32_t seq, int32_t nch) {
+    return ((unsigned long long)(seq & 0xffffffu) << 40) | ((unsigned long long)nch << 20);
+}
+__device__ __forceinline__ uint32_t claim_seq(unsigned long long w) { return (uint32_t)(w >> 40); }
+__device__ __forceinline__ int32_t claim_nch(unsigned long long w) {
+    return (int32_t)((w >> 20) & 0xfffffull);
+}
+__device__ __forceinline__ int32_t claim_next(unsigned long long w) {
+    return (int32_t)(w & 0xfffffull);
+}
+// A step has at most this many chunks; unsuccessful claims raise the next
+// field past the chunk count by at most one per workgroup of the launch, so
+// it never reaches the chunk field.
+constexpr int32_t kMaxChunks = 1 << 19;
+
+// Take one chunk of board entry j (thread 0): the returned claim word's next
+// field is the chunk, which exists if it is below the chunk field. The step
+// named by the word stays posted, with fixed parameters, until every chunk
+// taken from it is reported done.
+__device__ __forceinline__ unsigned long long take_chunk(HelpJob *j) {
+    return atomicAdd(&j->claim, 1ull);
+}
+
+// A filter step over many candidates, shared with the launch's idle
+// workgroups through this slot's board entry: the counters move to the
+// entry, the candidate list is cut into chunks that the owner and its
+// helpers claim, and the owner waits for the chunks its helpers claimed
+// before taking the counters back.
+__device__ __forceinline__ void shared_items(Ctx &c, const NStep &st, const NNbr *nb, int ncount,
+                                             const int32_t *ul, uint64_t *ub, bool revd,
+                                             int32_t n_items, int32_t helpers, uint64_t &fb) {
+    HelpJob *j = c.job;
+    const int32_t K = min(512, max(64, max((n_items + helpers) / (helpers + 1),
+                                           (n_items + kMaxChunks - 1) / kMaxChunks)));
+    const int G = lanes_for(K, c.gmax);
+    const int32_t nch = (n_items + K - 1) / K;
+    if (threadIdx.x == 0) {
+        for (int v = 0; v < SGM_MAX_QV; ++v) j->cnt[v] = c.s->cnt[v];
+        j->nbig = 0;
+        j->removed = 0;
+        j->nmarks = 0;
+        j->abort_ = 0;
+        j->bytes = 0ull;
+        j->done = 0;
+        j->chunk = K;
+        j->q = c.q;
+        j->n_items = n_items;
+        j->G = G;
+        j->ncount = ncount;
+        j->revd = revd;
+        j->st = st;
+        for (int i = 0; i < ncount; ++i) {
+            j->nbl[i].v = nb[i].v;
+            j->nbl[i].dir = nb[i].dir;
+            j->nbl[i].mode = nb[i].mode;
+            j->nbl[i].rel = nb[i].rel;
+        }
+        const uint32_t seq =
+            claim_seq(__hip_atomic_load(&j->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) + 1u;
+        // parameters, and the slot's lists and bitmaps, before the claim word
+        __threadfence();
+        atomicExch(&j->claim, claim_word(seq, nch));
+        atomicAdd(&c.hctr[0], 1);
+    }
+    __syncthreads();
+    int32_t own = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const unsigned long long w = take_chunk(j);
+            c.s->hch = claim_next(w) < claim_nch(w) ? claim_next(w) : -1;
+        }
+        __syncthreads();
+        const int32_t ch = c.s->hch;
+        __syncthreads();
+        if (ch < 0) break;
+        filter_items(c, BoardCtr{j}, st.push != 0, nb, ncount, ul, ub, revd, G, ch * K,
+                     min(n_items, ch * K + K), fb);
+        ++own;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // the owner's own chunks need no fence: it reads them itself
+        int32_t got = atomicAdd(&j->done, own) + own;
+        int64_t n = 0;
+        while (got < nch && n < kHelpWait) {
+            __builtin_amdgcn_s_sleep(1);
+            got = __hip_atomic_load(&j->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ++n;
+        }
+        __threadfence();
+        atomicSub(&c.hctr[0], 1);
+        for (int v = 0; v < SGM_MAX_QV; ++v)
+            c.s->cnt[v] = __hip_atomic_load(&j->cnt[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        c.s->nbig = __hip_atomic_load(&j->nbig, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        c.s->removed = __hip_atomic_load(&j->removed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        c.s->nmarks = __hip_atomic_load(&j->nmarks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t ab = __hip_atomic_load(&j->abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ab) c.s->abort_ = ab;
+        if (got < nch) c.s->abort_ = kWhyHelp;
+        add_bytes(c, __hip_atomic_load(&j->bytes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
     const DevGraph &g = c.g;
     const int u = st.u;
@@ -621,82 +895,24 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
     } else if (n_items <= NW) {
         for (int32_t it = 0; it < n_items; ++it) item_wg(c, st, nb, ncount, ul[it], ub, fb);
     } else {
-        const int G = lanes_for(n_items, c.gmax);
-        const int NGr = NT / G;
-        const int lane = threadIdx.x & 63, gl = lane & (G - 1), gb = lane & ~(G - 1);
-        const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << gb;
-        const int32_t bigdeg = 64 * G;  // more than 64 strides: a wider tier
-        int32_t *ov = (int32_t *)c.slab;
-        for (int32_t it = threadIdx.x / G; it < n_items; it += NGr) {
-            const int32_t up = ul[it];
-            if (revd && !bit_test(ub, up)) continue;  // already dropped
-            const int32_t ob = g.out_off[up], oe = g.out_off[up + 1];
-            const int32_t ib = g.in_off[up], ie = g.in_off[up + 1];
-            int32_t maxd = 0;
-            for (int j = 0; j < ncount; ++j) maxd = max(maxd, nb[j].dir ? ie - ib : oe - ob);
-            if (maxd > bigdeg) {
-                // long rows: a wider tier after this loop. The overflow list
-                // sits at the start of the slot's slab, which no phase uses
-                // while filtering (at most lcap entries, far below its size).
-                if (gl == 0) ov[atomicAdd(&c.s->nbig, 1)] = up;
-                continue;
-            }
-            bool alive = true;
-            uint64_t seen = 0;
-            for (int j = 0; j < ncount && alive; ++j) {
-                const NNbr d = nb[j];
-                const int2 *adj = d.dir ? g.in_adj : g.out_adj;
-                const int32_t beg = d.dir ? ib : ob, end = d.dir ? ie : oe;
-                bool found = false;
-                // four entries per lane in flight; lanes past the row test an
-                // in-range dummy entry and discard the answer
-                for (int32_t base = beg; base < end; base += 4 * G) {
-                    const int32_t i = base + gl;
-                    const int2 e0 = adj_at(adj, i, end), e1 = adj_at(adj, i + G, end);
-                    const int2 e2 = adj_at(adj, i + 2 * G, end), e3 = adj_at(adj, i + 3 * G, end);
-                    const bool hit = ((i < end) & nbr_hit(c, d, e0)) |
-                                     ((i + G < end) & nbr_hit(c, d, e1)) |
-                                     ((i + 2 * G < end) & nbr_hit(c, d, e2)) |
-                                     ((i + 3 * G < end) & nbr_hit(c, d, e3));
-                    seen += min(4 * G, end - base);
-                    if (__ballot(hit) & gmask) {
-                        found = true;
-                        break;
-                    }
-                }
-                alive = found;
-            }
-            if (!alive) {
-                if (gl == 0) {
-                    atomicAnd((unsigned long long *)&ub[up >> 6], ~(1ull << (up & 63)));
-                    atomicAdd(&c.s->removed, 1);
-                    fb += 20ull + 12ull * seen;
-                }
-                continue;
-            }
-            if (st.push)
-                for (int j = 0; j < ncount; ++j) {
-                    const NNbr d = nb[j];
-                    const int2 *adj = d.dir ? g.in_adj : g.out_adj;
-                    const int32_t beg = d.dir ? ib : ob, end = d.dir ? ie : oe;
-                    uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
-                    int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
-                    seen += end - beg;
-                    for (int32_t i = beg + gl; i < end; i += 4 * G) {
-                        const int2 e0 = adj_at(adj, i, end), e1 = adj_at(adj, i + G, end);
-                        const int2 e2 = adj_at(adj, i + 2 * G, end), e3 = adj_at(adj, i + 3 * G, end);
-                        const bool h0 = (i < end) & nbr_hit(c, d, e0);
-                        const bool h1 = (i + G < end) & nbr_hit(c, d, e1);
-                        const bool h2 = (i + 2 * G < end) & nbr_hit(c, d, e2);
-                        const bool h3 = (i + 3 * G < end) & nbr_hit(c, d, e3);
-                        if (h0) push_bit(c, tb, tl, d.v, e0.x);
-                        if (h1) push_bit(c, tb, tl, d.v, e1.x);
-                        if (h2) push_bit(c, tb, tl, d.v, e2.x);
-                        if (h3) push_bit(c, tb, tl, d.v, e3.x);
-                    }
-                }
-            if (gl == 0) fb += 20ull + 12ull * seen;
+        // helpers: the launch's extra workgroups and the slot workgroups
+        // whose queue ran dry
+        int32_t helpers = 0;
+        if (c.help_items > 0 && n_items >= c.help_items) {
+            if (threadIdx.x == 0)
+                c.s->hch = c.ngrid - c.nslot +
+                           __hip_atomic_load(&c.hctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            helpers = c.s->hch;
+            __syncthreads();
         }
+        if (helpers > 0)
+            shared_items(c, st, nb, ncount, ul, ub, revd, n_items, helpers, fb);
+        else
+            filter_items(c, LdsCtr{c.s}, st.push != 0, nb, ncount, ul, ub, revd,
+                         lanes_for(n_items, c.gmax), 0, n_items, fb);
+        const int lane = threadIdx.x & 63;
+        int32_t *ov = (int32_t *)c.slab;
         __syncthreads();
         // one wave per long row; rows above wg_rows get the whole workgroup
         const int32_t nbig = c.s->nbig;
@@ -1048,6 +1264,88 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
 // the fewest candidate edges; bind one new vertex per level through the
 // cheapest edge with exactly one bound endpoint; all other edges between the
 // new vertex and bound vertices are checks of that level.
+// Tables of the edges in `mask` whose key vertex has a single candidate with
+// a row of at most wg_rows entries (dir as in ec_build), built together: one
+// wave per edge and one slab allocation for all of them, instead of the
+// barriers and allocations of a full build per edge. Returns the edges built
+// (uniform). Uses the dynamic LDS, which no other phase holds meanwhile.
+__device__ __forceinline__ uint64_t ec_build_single(Ctx &c, uint64_t mask, int dir) {
+    const DevGraph &g = c.g;
+    const NQuery &Q = *c.Q;
+    const int32_t *off = dir ? g.in_off : g.out_off;
+    const int2 *adj = dir ? g.in_adj : g.out_adj;
+    int32_t *dsz = (int32_t *)c.dyn;  // [SGM_MAX_QE] bytes of each table, 0: not here
+    int32_t *dk = dsz + SGM_MAX_QE;   // [SGM_MAX_QE] the key's candidate
+    int32_t *dpos = dk + SGM_MAX_QE;  // [SGM_MAX_QE] byte offset in the allocation
+    int32_t *ql = dpos + SGM_MAX_QE;  // [SGM_MAX_QE] edges built here
+    int32_t *meta = ql + SGM_MAX_QE;  // [0] edges, [1] bytes
+    const int e = threadIdx.x;
+    if (e < Q.m) {
+        int32_t sz = 0, k = -1;
+        if ((mask >> e) & 1ull) {
+            const int key = dir ? Q.edst[e] : Q.esrc[e];
+            if (c.s->cnt[key] == 1) {
+                k = c.L(key)[0];
+                const int32_t deg = off[k + 1] - off[k];
+                // offsets [2], count [1], values [deg], rounded to 16 bytes
+                if (deg <= c.wg_rows) sz = (4 * (3 + deg) + 15) & ~15;
+            }
+        }
+        dsz[e] = sz;
+        dk[e] = k;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t nq = 0, tot = 0;
+        for (int i = 0; i < Q.m; ++i)
+            if (dsz[i]) {
+                dpos[i] = tot;
+                tot += dsz[i];
+                ql[nq++] = i;
+            }
+        meta[0] = nq;
+        meta[1] = tot;
+    }
+    __syncthreads();
+    const int32_t nq = meta[0];
+    if (nq == 0) return 0ull;
+    char *base = slab_alloc(c, meta[1]);
+    if (!base) return 0ull;
+    const int lane = threadIdx.x & 63;
+    uint64_t fb = 0;
+    for (int i = threadIdx.x >> 6; i < nq; i += NW) {
+        const int ed = ql[i];
+        const int key = dir ? Q.edst[ed] : Q.esrc[ed];
+        const int other = dir ? Q.esrc[ed] : Q.edst[ed];
+        const int32_t k = dk[ed];
+        const int32_t beg = off[k], end = off[k + 1];
+        int32_t *degoff = (int32_t *)(base + dpos[ed]);
+        int32_t *num = degoff + 2;
+        int32_t *vals = degoff + 3;
+        const int32_t no = c.s->cnt[other];
+        const int32_t rel = Q.elabel[ed];
+        const bool probe = probe_cheaper(no, end - beg);
+        const int64_t n = probe ? ec_probe_wave(rel, c.L(other), no, adj, beg, end, k, vals)
+                                : ec_key_wave(rel, c.B(other), adj, beg, end, k, vals);
+        if (lane == 0) {
+            degoff[0] = 0;
+            degoff[1] = end - beg;
+            num[0] = (int32_t)n;
+            c.s->ec_offs[ed] = degoff;
+            c.s->ec_cnt[ed] = num;
+            c.s->ec_vals[ed] = vals;
+            c.s->eckey[ed] = key;
+            c.s->ectot[ed] = n;
+            fb += 28ull + 4ull * n + (probe ? probe_bytes(no, end - beg) : 12ull * (end - beg));
+        }
+    }
+    add_bytes_wave(c, fb);
+    uint64_t built = 0;
+    for (int i = 0; i < nq; ++i) built |= 1ull << ql[i];
+    __syncthreads();
+    return built;
+}
+
 __device__ __forceinline__ void join_order(Ctx &c) {
     if (threadIdx.x != 0) return;
     const NQuery &Q = *c.Q;
@@ -1351,7 +1649,11 @@ __device__ __forceinline__ void run_query(Ctx &c) {
             __syncthreads();
         } else if (!aborted(c)) {
             // candidate edges keyed by each edge's source: totals for the order
+            const uint64_t all = Q.m == 64 ? ~0ull : (1ull << Q.m) - 1ull;
+            const uint64_t one = ec_build_single(c, all, 0);
+            if (one) ev(c, SGM_EV_EDGES);
             for (int e = 0; e < Q.m && !aborted(c); ++e) {
+                if ((one >> e) & 1ull) continue;
                 ec_build(c, e, Q.esrc[e], Q.edst[e], 0);
                 ev(c, SGM_EV_EDGES);
             }
@@ -1365,8 +1667,13 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                 __syncthreads();
                 ev(c, SGM_EV_ORDER);
                 // edges the join looks up by their destination: rebuild keyed so
+                uint64_t redo = 0;
+                for (int e = 0; e < Q.m; ++e)
+                    if (s.eckey[e] != s.ecbuilt[e]) redo |= 1ull << e;
+                const uint64_t one2 = aborted(c) ? 0ull : ec_build_single(c, redo, 1);
+                if (one2) ev(c, SGM_EV_EDGES);
                 for (int e = 0; e < Q.m && !aborted(c); ++e)
-                    if (s.eckey[e] != s.ecbuilt[e]) {
+                    if (((redo & ~one2) >> e) & 1ull) {
                         ec_build(c, e, Q.edst[e], Q.esrc[e], 1);
                         ev(c, SGM_EV_EDGES);
                     }
@@ -1674,13 +1981,142 @@ __device__ __forceinline__ void run_query(Ctx &c) {
 }
 
 // at least 4 waves per SIMD (registers <= 128): two workgroups per CU
+__device__ __forceinline__ Ctx slot_ctx(const NArgs &a, Smem &s, unsigned char *dyn, int slot,
+                                        int32_t q) {
+    const int32_t nwords = a.g.nwords;
+    uint64_t *bits = a.bits + (int64_t)slot * (SGM_MAX_QV + 1) * nwords;
+    int32_t *lists = a.lists + (int64_t)slot * SGM_MAX_QV * a.lcap;
+    char *slab = a.slab + (int64_t)slot * a.slab_bytes;
+    return Ctx{a.g,  a.lcap, a.slab_bytes, a.out, a.out_cap, a.out_used, a.rootbits, &a.qs[q], &s,
+               bits, bits + (int64_t)SGM_MAX_QV * nwords, lists, slab, dyn,
+               a.trace ? a.trace + (int64_t)q * SGM_TRACE_CAP : nullptr, a.group_lanes,
+               a.wg_rows, a.join_policy,
+               // while filtering the slab holds the long-row overflow list in
+               // [0, 4 lcap) bytes and the marks in [4 lcap, 8 lcap)
+               (int32_t *)(slab + 4 * (int64_t)a.lcap), a.board ? a.board + slot : nullptr, a.hctr,
+               a.help_items, q, a.nslot, a.ngrid};
+}
+
+// Chunks of the step posted on board entry e, starting with chunk ch, until
+// the step has none left; then the chunks are reported done (one release
+// fence for all of them).
+__device__ __forceinline__ void help_step(const NArgs &a, Smem &s, unsigned char *dyn, int e,
+                                          int32_t ch) {
+    HelpJob *j = a.board + e;
+    // the parameters stay fixed while this workgroup holds unreported chunks
+    const NStep st = j->st;
+    const int32_t K = j->chunk, G = j->G, n_items = j->n_items, ncount = j->ncount;
+    const bool revd = j->revd != 0;
+    if ((int)threadIdx.x < ncount) {
+        s.nbl[threadIdx.x].v = j->nbl[threadIdx.x].v;
+        s.nbl[threadIdx.x].dir = j->nbl[threadIdx.x].dir;
+        s.nbl[threadIdx.x].mode = j->nbl[threadIdx.x].mode;
+        s.nbl[threadIdx.x].rel = j->nbl[threadIdx.x].rel;
+    }
+    __syncthreads();
+    Ctx c = slot_ctx(a, s, dyn, e, j->q);
+    c.trace = nullptr;
+    uint64_t fb = 0;
+    int32_t n = 0;
+    while (ch >= 0) {
+        filter_items(c, BoardCtr{j}, st.push != 0, s.nbl, ncount, c.L(st.u), c.B(st.u), revd, G,
+                     ch * K, min(n_items, ch * K + K), fb);
+        ++n;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long w = take_chunk(j);
+            s.hch = claim_next(w) < claim_nch(w) ? claim_next(w) : -1;
+        }
+        __syncthreads();
+        ch = s.hch;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) fb += __shfl_xor(fb, o, 64);
+    if ((threadIdx.x & 63) == 0 && fb) atomicAdd(&j->bytes, (unsigned long long)fb);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(&j->done, n);
+    }
+}
+
+// Helpers: claim chunks of posted steps until every slot workgroup has run
+// out of queries (or after kHelpIdle empty polls in a row).
+__device__ __forceinline__ void help_loop(const NArgs &a, Smem &s, unsigned char *dyn) {
+    const int lane = threadIdx.x & 63;
+    int64_t idle = 0;
+    for (;;) {
+        if (threadIdx.x < 64) {
+            int32_t e = -2, ch = -1;  // e: -2 nothing found, -1 leave
+            const int32_t done =
+                __hip_atomic_load(&a.hctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int32_t posted =
+                __hip_atomic_load(&a.hctr[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (done >= a.nslot) e = -1;
+            else if (posted > 0) {
+                // entries with an open chunk, 64 at a time from a rotating start
+                for (int base = 0; base < a.nslot && e == -2; base += 64) {
+                    const int k = base + lane;
+                    const int en = (k + (int)blockIdx.x) % a.nslot;
+                    bool open = false;
+                    if (k < a.nslot) {
+                        const unsigned long long w = __hip_atomic_load(
+                            &a.board[en].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        open = claim_next(w) < claim_nch(w);
+                    }
+                    uint64_t m = __ballot(open);
+                    while (m && e == -2) {
+                        const int l = __ffsll((unsigned long long)m) - 1;
+                        m &= m - 1;
+                        const int cand = (base + l + (int)blockIdx.x) % a.nslot;
+                        int32_t got = -1;
+                        if (lane == 0) {
+                            const unsigned long long w = take_chunk(a.board + cand);
+                            if (claim_next(w) < claim_nch(w)) {
+                                got = claim_next(w);
+                                // the step's parameters and the owner's data
+                                __threadfence();
+                            }
+                        }
+                        got = __shfl(got, 0, 64);
+                        if (got >= 0) {
+                            e = cand;
+                            ch = got;
+                        }
+                    }
+                }
+            }
+            if (lane == 0) {
+                s.hq = e;
+                s.hch = ch;
+            }
+        }
+        __syncthreads();
+        const int32_t e = s.hq, ch = s.hch;
+        __syncthreads();
+        if (e == -1) break;
+        if (e < 0) {
+            if (++idle > kHelpIdle) break;
+            // quick polls right after work, slower ones while owners run
+            // phases they do not share
+            if (idle < 64) __builtin_amdgcn_s_sleep(2);
+            else __builtin_amdgcn_s_sleep(32);
+            continue;
+        }
+        idle = 0;
+        help_step(a, s, dyn, e, ch);
+    }
+}
+
 __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
     __shared__ Smem s;
     extern __shared__ unsigned char dyn[];
-    const int32_t nwords = a.g.nwords;
-    uint64_t *bits = a.bits + (int64_t)blockIdx.x * (SGM_MAX_QV + 1) * nwords;
-    int32_t *lists = a.lists + (int64_t)blockIdx.x * SGM_MAX_QV * a.lcap;
-    char *slab = a.slab + (int64_t)blockIdx.x * a.slab_bytes;
+    const bool help = a.help_items > 0 && a.board != nullptr;
+    if ((int)blockIdx.x >= a.nslot) {
+        if (help) help_loop(a, s, dyn);
+        return;
+    }
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s.q = atomicAdd(a.queue, 1);
@@ -1689,13 +2125,7 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
         if (q >= a.nq) break;
         const NQuery &Q = a.qs[q];
         NResult &R = a.res[q];
-        Ctx c{a.g,  a.lcap, a.slab_bytes, a.out, a.out_cap, a.out_used, a.rootbits, &Q, &s,
-              bits, bits + (int64_t)SGM_MAX_QV * nwords, lists, slab, dyn,
-              a.trace ? a.trace + (int64_t)q * SGM_TRACE_CAP : nullptr, a.group_lanes,
-              a.wg_rows, a.join_policy,
-              // while filtering the slab holds the long-row overflow list in
-              // [0, 4 lcap) bytes and the marks in [4 lcap, 8 lcap)
-              (int32_t *)(slab + 4 * (int64_t)a.lcap)};
+        Ctx c = slot_ctx(a, s, dyn, blockIdx.x, q);
         if (threadIdx.x == 0) s.nev = 0;
         run_query(c);
         __syncthreads();
@@ -1722,6 +2152,10 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
             }
         }
     }
+    if (help) {
+        if (threadIdx.x == 0) atomicAdd(&a.hctr[1], 1);
+        help_loop(a, s, dyn);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1741,6 +2175,10 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
 // predicates instead of all of them. Rows then leave as 512-byte runs.
 constexpr int kSweepTile = 64;    // bitmap words per block
 constexpr int kSweepChunk = 64;   // predicates per LDS pass (32 KB of rows)
+// LDS row stride in words. Lanes of one wave OR into the same word of the
+// rows of different predicates; an unpadded stride of 512 bytes would put all
+// of them in one bank, one more word spreads them over the banks.
+constexpr int kSweepStride = kSweepTile + 1;
 
 constexpr int kSweepTypes = 1024;  // type tables up to this size are staged in LDS
 
@@ -1748,9 +2186,9 @@ __global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *pre
                                                     int32_t n_any, uint64_t *rootbits,
                                                     unsigned long long *ctr,
                                                     const int32_t *type_off, int32_t n_types) {
-    if (blockIdx.x == 0 && threadIdx.x < 2) ctr[threadIdx.x] = 0ull;
+    if (blockIdx.x == 0 && threadIdx.x < 3) ctr[threadIdx.x] = 0ull;
     if (n_pred == 0) return;
-    __shared__ uint64_t rows[kSweepChunk * kSweepTile];
+    __shared__ uint64_t rows[kSweepChunk * kSweepStride];
     __shared__ VPred pl[kSweepChunk];
     __shared__ int32_t toff[kSweepTypes + 1];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1767,7 +2205,7 @@ __global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *pre
     }
     for (int32_t c0 = 0; c0 < n_pred; c0 += kSweepChunk) {
         const int cn = min(kSweepChunk, n_pred - c0);
-        for (int i = threadIdx.x; i < cn * kSweepTile; i += 256) rows[i] = 0ull;
+        for (int i = threadIdx.x; i < cn * kSweepStride; i += 256) rows[i] = 0ull;
         if ((int)threadIdx.x < cn) pl[threadIdx.x] = preds[c0 + threadIdx.x];
         __syncthreads();
         // untyped predicates: the same test for every lane
@@ -1777,7 +2215,7 @@ __global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *pre
             for (int i = 0; i < 16; ++i) {
                 const bool ok = vi[i].x >= 0 && (vi[i].y & 255) >= p.qout && (vi[i].y >> 8) >= p.qin;
                 const uint64_t b = __ballot(ok);
-                if (lane == 0) rows[j * kSweepTile + 16 * wid + i] = b;
+                if (lane == 0) rows[j * kSweepStride + 16 * wid + i] = b;
             }
         }
         // typed predicates of this chunk: [t0, cn), sorted by type
@@ -1805,12 +2243,12 @@ __global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *pre
             const int od = vi[i].y & 255, id = vi[i].y >> 8;
             for (int j = lo; j < end && pl[j].label == t; ++j)
                 if (od >= pl[j].qout && id >= pl[j].qin)
-                    atomicOr((unsigned long long *)&rows[j * kSweepTile + 16 * wid + i], 1ull << lane);
+                    atomicOr((unsigned long long *)&rows[j * kSweepStride + 16 * wid + i], 1ull << lane);
         }
         __syncthreads();
         for (int k = threadIdx.x; k < cn * kSweepTile; k += 256) {
             const int j = k / kSweepTile, w = k % kSweepTile;
-            if (w0 + w < g.nwords) rootbits[(int64_t)(c0 + j) * g.nwords + w0 + w] = rows[k];
+            if (w0 + w < g.nwords) rootbits[(int64_t)(c0 + j) * g.nwords + w0 + w] = rows[j * kSweepStride + w];
         }
         __syncthreads();
     }
