@@ -235,7 +235,7 @@ int sgm_trace_events(sgm_graph *g, int32_t i, int64_t *out, int32_t cap, double 
 /*
  * Work division and join schedule of the persistent kernel (the batched
  * form). Results never depend on these; speed does. Defaults: slots 512,
- * group_lanes 64, wg_rows 8192, join_policy 0, help_items 1024, helpers 256.
+ * group_lanes 64, wg_rows 8192, join_policy 0, help_items 1024, helpers 64.
  *   slots        workgroups of one persistent launch that take queries
  *                (1..512; two per CU fit)
  *   group_lanes  most lanes working on one candidate's rows (1, 2, 4, ..., 64)

@@ -245,7 +245,7 @@ struct sgm_graph {
     // persistent per-query kernel on the graph's own stream
     NarrowCtx nw;
     NarrowCtx nwb;  // few large slots for queries that outgrow a regular one
-    sgm_tuning tune{512, 64, 8192, 0, 1024, 256, {0, 0}};
+    sgm_tuning tune{512, 64, 8192, 0, 1024, 64, {0, 0}};
 };
 
 namespace {
@@ -1793,7 +1793,7 @@ void sgm_free_graph(sgm_graph *g) {
 
 void sgm_default_tuning(sgm_tuning *t) {
     if (!t) return;
-    *t = sgm_tuning{512, 64, 8192, 0, 1024, 256, {0, 0}};
+    *t = sgm_tuning{512, 64, 8192, 0, 1024, 64, {0, 0}};
 }
 
 int sgm_get_tuning(const sgm_graph *g, sgm_tuning *t) {

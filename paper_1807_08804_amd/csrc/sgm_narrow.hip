@@ -1260,10 +1260,6 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
     __syncthreads();
 }
 
-// Join order of Sec. "Joining Phase" (one thread): start from the edge with
-// the fewest candidate edges; bind one new vertex per level through the
-// cheapest edge with exactly one bound endpoint; all other edges between the
-// new vertex and bound vertices are checks of that level.
 // Tables of the edges in `mask` whose key vertex has a single candidate with
 // a row of at most wg_rows entries (dir as in ec_build), built together: one
 // wave per edge and one slab allocation for all of them, instead of the
@@ -1346,65 +1342,72 @@ __device__ __forceinline__ uint64_t ec_build_single(Ctx &c, uint64_t mask, int d
     return built;
 }
 
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = min(x, (uint64_t)__shfl_xor(x, o, 64));
+    return x;
+}
+
+// Join order of Sec. "Joining Phase", by wave 0 with one query edge per
+// lane: start from the source of the edge with the fewest candidate edges;
+// bind one new vertex per level through the cheapest edge with exactly one
+// bound endpoint (policy 1: first the new vertex with the most edges to
+// bound vertices), the earliest edge on ties; all other unused edges between
+// the new vertex and bound vertices are checks of that level.
 __device__ __forceinline__ void join_order(Ctx &c) {
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x >= 64) return;
     const NQuery &Q = *c.Q;
     Smem &s = *c.s;
+    const int lane = threadIdx.x;
+    const bool has = lane < Q.m;
+    const int xs = has ? s.qsrc[lane] : 0, xd = has ? s.qdst[lane] : 0;
+    const uint64_t cost = has ? (uint64_t)min(s.ectot[lane], (int64_t)((1ll << 52) - 1)) : 0ull;
     uint32_t vis = 0;   // bound query vertices
     uint64_t used = 0;  // consumed query edges
-    int e0 = 0;
-    for (int e = 1; e < Q.m; ++e)
-        if (s.ectot[e] < s.ectot[e0]) e0 = e;
-    int nj = 0, nc = 0;
-    s.jorder[nj++] = s.qsrc[e0];
-    vis |= 1u << s.qsrc[e0];
-    int ext = e0;
+    int ext = (int)(wave_min_u64(has ? (cost << 6) | (uint64_t)lane : ~0ull) & 63);
+    int w = s.qsrc[ext];
+    if (lane == 0) s.jorder[0] = w;
+    vis |= 1u << w;
+    int nc = 0;
     for (int lv = 0; lv < Q.n - 1; ++lv) {
+        const bool va = (vis >> xs) & 1u, vb = (vis >> xd) & 1u;
         if (lv > 0) {
-            // policy 0: the cheapest edge with one bound endpoint. Policy 1:
-            // first the new vertex with the most edges to bound vertices
-            // (its level then checks the most), then the cheapest edge.
-            ext = -1;
-            int ext_links = 0;
-            for (int e = 0; e < Q.m; ++e) {
-                if ((used >> e) & 1ull) continue;
-                const bool va = (vis >> s.qsrc[e]) & 1u, vb = (vis >> s.qdst[e]) & 1u;
-                if (va == vb) continue;
-                int links = 0;
-                if (c.join_policy == 1) {
-                    const int w = va ? s.qdst[e] : s.qsrc[e];
-                    for (int f = 0; f < Q.m; ++f) {
-                        if ((used >> f) & 1ull) continue;
-                        const int x = s.qsrc[f], y = s.qdst[f];
-                        links += (x == w && ((vis >> y) & 1u)) || (y == w && ((vis >> x) & 1u));
-                    }
+            const bool cand = has && !((used >> lane) & 1ull) && va != vb;
+            const int wv = va ? xd : xs;  // the endpoint a candidate would bind
+            int links = 0;
+            if (c.join_policy == 1)
+                for (int x = 0; x < Q.n; ++x) {
+                    const uint64_t m = __ballot(cand && wv == x);
+                    if (wv == x) links = __popcll(m);
                 }
-                if (ext < 0 || links > ext_links ||
-                    (links == ext_links && s.ectot[e] < s.ectot[ext])) {
-                    ext = e;
-                    ext_links = links;
-                }
-            }
+            const uint64_t key =
+                cand ? ((uint64_t)(63 - links) << 58) | (cost << 6) | (uint64_t)lane : ~0ull;
+            ext = (int)(wave_min_u64(key) & 63);
         }
-        const int w = ((vis >> s.qsrc[ext]) & 1u) ? s.qdst[ext] : s.qsrc[ext];
+        w = ((vis >> s.qsrc[ext]) & 1u) ? s.qdst[ext] : s.qsrc[ext];
         used |= 1ull << ext;
-        s.lv_ext[lv] = ext;
-        s.lv_first[lv] = nc;
-        for (int e = 0; e < Q.m; ++e) {
-            if ((used >> e) & 1ull) continue;
-            const int x = s.qsrc[e], y = s.qdst[e];
-            if ((x == w && ((vis >> y) & 1u)) || (y == w && ((vis >> x) & 1u))) {
-                s.chk[nc++] = e;
-                used |= 1ull << e;
-            }
+        const bool chk = has && !((used >> lane) & 1ull) &&
+                         ((xs == w && ((vis >> xd) & 1u)) || (xd == w && ((vis >> xs) & 1u)));
+        const uint64_t cm = __ballot(chk);
+        if (chk) s.chk[nc + __popcll(cm & lanemask_lt(lane))] = lane;
+        if (lane == 0) {
+            s.lv_ext[lv] = ext;
+            s.lv_first[lv] = nc;
+            s.lv_nchk[lv] = __popcll(cm);
+            s.jorder[lv + 1] = w;
         }
-        s.lv_nchk[lv] = nc - s.lv_first[lv];
+        nc += __popcll(cm);
+        used |= cm;
         vis |= 1u << w;
-        s.jorder[nj++] = w;
     }
-    for (int j = 0; j < Q.n; ++j) s.jpos[s.jorder[j]] = j;
-    for (int e = 0; e < Q.m; ++e)
-        s.eckey[e] = s.jpos[s.qsrc[e]] < s.jpos[s.qdst[e]] ? s.qsrc[e] : s.qdst[e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < Q.n) s.jpos[s.jorder[lane]] = lane;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (has) s.eckey[lane] = s.jpos[xs] < s.jpos[xd] ? xs : xd;
 }
 
 __device__ __forceinline__ bool ec_contains(const Ctx &c, int e, int32_t keyval, int32_t x) {
@@ -1658,9 +1661,35 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                 ev(c, SGM_EV_EDGES);
             }
             __syncthreads();
-            bool none = false;
+            bool none = false, single = true;
             for (int e = 0; e < Q.m; ++e) none |= s.ectot[e] == 0;
-            if (!aborted(c) && !none) {
+            for (int u = 0; u < n; ++u) single &= s.cnt[u] == 1;
+            int32_t *one_row = nullptr;
+            if (!aborted(c) && !none && single) one_row = (int32_t *)slab_alloc(c, 4ll * n);
+            if (one_row) {
+                // One candidate per query vertex and its pair in every edge
+                // table: those candidates are the only possible row, and a
+                // match exactly when they are distinct. The join binds the
+                // vertices in index order.
+                mark(c, 2);
+                if (threadIdx.x == 0) {
+                    int64_t r = 1;
+                    for (int u = 0; u < n; ++u) {
+                        const int32_t x = c.L(u)[0];
+                        for (int w = 0; w < u; ++w) r &= (int64_t)(one_row[w] != x);
+                        one_row[u] = x;
+                        s.jorder[u] = u;
+                        s.jpos[u] = u;
+                        s.level_rows[u] = r;
+                    }
+                    s.nrows = r;
+                    add_bytes(c, 8ull * n);
+                }
+                __syncthreads();
+                table = one_row;
+                rows = s.nrows;
+                ev(c, SGM_EV_LEVEL);
+            } else if (!aborted(c) && !none) {
                 if (threadIdx.x == 0)
                     for (int e = 0; e < Q.m; ++e) s.ecbuilt[e] = s.eckey[e];
                 join_order(c);
@@ -1862,7 +1891,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
             s.ctr = tb;
         }
         __syncthreads();
-        if (s.ctr > 64) {
+        if (s.ctr > 64 && rows > 1) {
             clear_slot(c, false);
             if (threadIdx.x == 0) {
                 s.status = kNeedWide;
@@ -1873,8 +1902,13 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         const int tb = s.ctr;
         const int k = n;
         const int32_t *idx;
-        stage_key_lists(c);
-        if (rows <= kRowSortCap) {
+        if (rows > 1) stage_key_lists(c);
+        if (rows == 1) {
+            int32_t *ix = (int32_t *)c.dyn;
+            if (threadIdx.x == 0) ix[0] = 0;
+            __syncthreads();
+            idx = ix;
+        } else if (rows <= kRowSortCap) {
             // bitonic network in LDS
             uint64_t *keys = (uint64_t *)c.dyn;
             int32_t *ix = (int32_t *)(c.dyn + sizeof(uint64_t) * kRowSortCap);

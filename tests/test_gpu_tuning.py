@@ -31,7 +31,7 @@ def medium_set(medium_kg, oracle_medium):
 # the second and fourth share every filter step of 64 or more candidates
 # with helper workgroups (many helpers, and only three)
 TUNINGS = [
-    dict(slots=512, group_lanes=64, wg_rows=8192, join_policy=0, help_items=1024, helpers=256),
+    dict(slots=512, group_lanes=64, wg_rows=8192, join_policy=0, help_items=1024, helpers=64),
     dict(slots=7, group_lanes=1, wg_rows=64, join_policy=1, help_items=64, helpers=512),
     dict(slots=256, group_lanes=16, wg_rows=32768, join_policy=1, help_items=0, helpers=0),
     dict(slots=1, group_lanes=4, wg_rows=2048, join_policy=0, help_items=64, helpers=3),
@@ -71,7 +71,7 @@ def test_autotune_keeps_results(medium_kg, medium_set):
     best = g.autotune(qs, reps=1)
     assert best["slots"] in (256, 512) and best["group_lanes"] in (16, 64)
     assert best["wg_rows"] in (2048, 8192, 32768) and best["join_policy"] in (0, 1)
-    assert best["help_items"] in (0, 1024) and best["helpers"] == 256
+    assert best["help_items"] in (0, 1024) and best["helpers"] == 64
     assert g.tuning() == best
     for r, w in zip(g.match_batch(qs), want):
         same(r, w)
