@@ -44,9 +44,11 @@ class sgm_options(ctypes.Structure):
 
 
 class sgm_query(ctypes.Structure):
+    # the five int32 array pointers of the C struct, held as addresses
     _fields_ = [("n_vertices", ctypes.c_int32), ("n_edges", ctypes.c_int32),
-                ("vertex_label", _i32p), ("vertex_pin", _i32p), ("edge_src", _i32p),
-                ("edge_dst", _i32p), ("edge_label", _i32p)]
+                ("vertex_label", ctypes.c_void_p), ("vertex_pin", ctypes.c_void_p),
+                ("edge_src", ctypes.c_void_p), ("edge_dst", ctypes.c_void_p),
+                ("edge_label", ctypes.c_void_p)]
 
 
 class sgm_stats(ctypes.Structure):
@@ -192,10 +194,16 @@ def sgm_load_graph(n_vertices, n_edges, row_ptr, col, rel, vtype, opts=None):
 
 
 def _make_query(n, vlabel, vpin, esrc, edst, elabel):
-    keep = [_arr(vlabel), _arr(vpin), _arr(esrc), _arr(edst), _arr(elabel)]
-    q = sgm_query(int(n), int(len(keep[2][0])), keep[0][1], keep[1][1], keep[2][1], keep[3][1],
-                  keep[4][1])
-    return q, keep
+    """The C query struct and the buffer its pointers refer to (keep it alive
+    as long as the struct is used): all five arrays in one int32 block."""
+    nv, m = len(vlabel), len(esrc)
+    if len(vpin) != nv or len(edst) != m or len(elabel) != m:
+        raise ValueError("vertex arrays and edge arrays must have matching lengths")
+    buf = np.concatenate((vlabel, vpin, esrc, edst, elabel)).astype(np.int32, copy=False)
+    base = buf.__array_interface__["data"][0]
+    q = sgm_query(int(n), m, base, base + 4 * nv, base + 8 * nv, base + 8 * nv + 4 * m,
+                  base + 8 * nv + 8 * m)
+    return q, buf
 
 
 def sgm_match_query(g, q: sgm_query, flags: int = SGM_SORTED):
@@ -328,11 +336,13 @@ class Graph:
                 err.n_rows = int(r.contents.n_rows)
                 sgm_free_result(r)
             raise err
-        try:
-            st = stats_dict(r.contents.stats, n, len(keep[2][0]))
-        except Exception:
-            sgm_free_result(r)
-            raise
+        st = None
+        if with_stats:
+            try:
+                st = stats_dict(r.contents.stats, n, q.n_edges)
+            except Exception:
+                sgm_free_result(r)
+                raise
         k, rows = _take_rows(r, n)
         out = k if count_only else rows
         return (out, st) if with_stats else out
@@ -382,7 +392,7 @@ class Graph:
         for u in range(q.n):
             lists.append(flat[off:off + counts[u]])
             off += counts[u]
-        return lists, ec[:len(keep[2][0])]
+        return lists, ec[:sq.n_edges]
 
     def trace(self, i=0):
         """Step events of query i of the last match call (profile=2): a list

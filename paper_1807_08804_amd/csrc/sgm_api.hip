@@ -187,9 +187,16 @@ struct NarrowCtx {
     // Built on first use; every launch updates all node parameters.
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    hipGraphNode_t gn[6] = {};
+    hipGraphNode_t gn[7] = {};
     SweepArgs sa{};
     NArgs na{};
+    // parameters of the instantiated graph's last launch: nodes whose
+    // parameters did not change are not updated again
+    SweepArgs last_sa{};
+    NArgs last_na{};
+    int last_grid = -1, last_sweep_grid = -1;
+    size_t last_qb = 0, last_pb = 0, last_rb = 0;
+    const void *last_hout = nullptr;
     void *kargs[9] = {};
 };
 
@@ -1110,6 +1117,9 @@ constexpr int64_t kNarrowSlabMax = 32ll << 20;       // per slot, large graphs
 constexpr int32_t kNarrowListCap = 1 << 16;          // per query vertex
 constexpr int kNarrowQueryCap = 4096;                // queries per launch
 constexpr int64_t kNarrowOutCap = 256ll << 20;       // int32 elements (1 GB) per context
+// Every launch also reads back this many leading ints of the output arena,
+// so that small results need no second copy and wait.
+constexpr int64_t kOutPrefix = 16384;
 constexpr int kBigSlots = 4;                         // large slots of the retry context
 constexpr int32_t kBigListCap = 1 << 22;             // per query vertex, large slot
 constexpr int64_t kBigSlab = 256ll << 20;            // per large slot
@@ -1178,6 +1188,8 @@ void narrow_reserve(sgm_graph *g, NarrowCtx &nw, int slots, int nq, int nroot) {
         HIPX(hipMemsetAsync(nw.d_board, 0, sizeof(HelpJob) * kNarrowMaxSlots, nw.stream));
         nw.out_cap = kNarrowOutCap;
         HIPX(hipMalloc(&nw.d_out, sizeof(int32_t) * nw.out_cap));
+        HIPX(hipHostMalloc(&nw.h_out, sizeof(int32_t) * (1 << 20), hipHostMallocDefault));
+        nw.h_out_cap = 1 << 20;
         HIPX(hipEventCreateWithFlags(&nw.done, hipEventDisableTiming));
     }
     if (slots > nw.slots) {
@@ -1411,6 +1423,7 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
         const size_t qb = sizeof(NQuery) * np,
                      pb = sizeof(VPred) * std::max(nroot, 1) + sizeof(int32_t) * (n_types + 1);
         const size_t rb = sizeof(NResult) * np, cb = sizeof(unsigned long long) * 2;
+        const size_t ob = sizeof(int32_t) * kOutPrefix;
         const auto H2D = hipMemcpyHostToDevice, D2H = hipMemcpyDeviceToHost;
         if (!nw.gexec) {
             HIPX(hipGraphCreate(&nw.graph, 0));
@@ -1423,16 +1436,40 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
                                          D2H));
             HIPX(hipGraphAddMemcpyNode1D(&nw.gn[5], nw.graph, &nw.gn[4], 1, nw.h_ctr, nw.d_ctr, cb,
                                          D2H));
+            HIPX(hipGraphAddMemcpyNode1D(&nw.gn[6], nw.graph, &nw.gn[5], 1, nw.h_out, nw.d_out, ob,
+                                         D2H));
             HIPX(hipGraphInstantiate(&nw.gexec, nw.graph, nullptr, nullptr, 0));
         } else {
-            HIPX(hipGraphExecMemcpyNodeSetParams1D(nw.gexec, nw.gn[0], nw.d_q, nw.h_q, qb, H2D));
-            HIPX(hipGraphExecMemcpyNodeSetParams1D(nw.gexec, nw.gn[1], nw.d_preds, nw.h_preds, pb,
-                                                   H2D));
-            HIPX(hipGraphExecKernelNodeSetParams(nw.gexec, nw.gn[2], &ps));
-            HIPX(hipGraphExecKernelNodeSetParams(nw.gexec, nw.gn[3], &pn));
-            HIPX(hipGraphExecMemcpyNodeSetParams1D(nw.gexec, nw.gn[4], nw.h_res, nw.d_res, rb, D2H));
-            HIPX(hipGraphExecMemcpyNodeSetParams1D(nw.gexec, nw.gn[5], nw.h_ctr, nw.d_ctr, cb, D2H));
+            // buffers are reallocated only while no launch is in flight, and
+            // every pointer a node uses is compared here
+            if (qb != nw.last_qb || nw.na.qs != nw.last_na.qs)
+                HIPX(hipGraphExecMemcpyNodeSetParams1D(nw.gexec, nw.gn[0], nw.d_q, nw.h_q, qb, H2D));
+            if (pb != nw.last_pb || nw.sa.preds != nw.last_sa.preds)
+                HIPX(hipGraphExecMemcpyNodeSetParams1D(nw.gexec, nw.gn[1], nw.d_preds, nw.h_preds,
+                                                       pb, H2D));
+            if (std::memcmp(&nw.sa, &nw.last_sa, sizeof(SweepArgs)) != 0 ||
+                (int)ps.gridDim.x != nw.last_sweep_grid)
+                HIPX(hipGraphExecKernelNodeSetParams(nw.gexec, nw.gn[2], &ps));
+            if (std::memcmp(&nw.na, &nw.last_na, sizeof(NArgs)) != 0 || grid != nw.last_grid)
+                HIPX(hipGraphExecKernelNodeSetParams(nw.gexec, nw.gn[3], &pn));
+            if (rb != nw.last_rb || nw.na.res != nw.last_na.res)
+                HIPX(hipGraphExecMemcpyNodeSetParams1D(nw.gexec, nw.gn[4], nw.h_res, nw.d_res, rb,
+                                                       D2H));
+            if (nw.na.queue != nw.last_na.queue)
+                HIPX(hipGraphExecMemcpyNodeSetParams1D(nw.gexec, nw.gn[5], nw.h_ctr, nw.d_ctr, cb,
+                                                       D2H));
+            if (nw.h_out != nw.last_hout || nw.na.out != nw.last_na.out)
+                HIPX(hipGraphExecMemcpyNodeSetParams1D(nw.gexec, nw.gn[6], nw.h_out, nw.d_out, ob,
+                                                       D2H));
         }
+        nw.last_sa = nw.sa;
+        nw.last_na = nw.na;
+        nw.last_grid = grid;
+        nw.last_sweep_grid = (int)ps.gridDim.x;
+        nw.last_qb = qb;
+        nw.last_pb = pb;
+        nw.last_rb = rb;
+        nw.last_hout = nw.h_out;
         HIPX(hipGraphLaunch(nw.gexec, st));
         HIPX(hipEventRecord(nw.done, st));
         return true;
@@ -1470,6 +1507,7 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     HIPX(hipMemcpyAsync(nw.h_res, nw.d_res, sizeof(NResult) * np, hipMemcpyDeviceToHost, st));
     HIPX(hipMemcpyAsync(nw.h_ctr, nw.d_ctr, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost,
                         st));
+    HIPX(hipMemcpyAsync(nw.h_out, nw.d_out, sizeof(int32_t) * kOutPrefix, hipMemcpyDeviceToHost, st));
     HIPX(hipEventRecord(nw.done, st));
     return true;
 }
@@ -1489,15 +1527,19 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         g->kstat[SGM_K_PERSIST].bytes_total += b;
     }
     const int64_t used = std::min<int64_t>((int64_t)nw.h_ctr[1], nw.out_cap);
-    if (!(flags & SGM_COUNT_ONLY) && used > 0) {
+    if (!(flags & SGM_COUNT_ONLY) && used > kOutPrefix) {
+        // the launch read back the first kOutPrefix ints; the rest now
+        int64_t from = kOutPrefix;
         if (nw.h_out_cap < used) {
             host_free(nw.h_out);
             nw.h_out_cap = 0;
             const int64_t cap = std::max<int64_t>(used, 1 << 20);
             HIPX(hipHostMalloc(&nw.h_out, sizeof(int32_t) * cap, hipHostMallocDefault));
             nw.h_out_cap = cap;
+            from = 0;
         }
-        HIPX(hipMemcpyAsync(nw.h_out, nw.d_out, sizeof(int32_t) * used, hipMemcpyDeviceToHost, st));
+        HIPX(hipMemcpyAsync(nw.h_out + from, nw.d_out + from, sizeof(int32_t) * (used - from),
+                            hipMemcpyDeviceToHost, st));
         HIPX(hipStreamSynchronize(st));
     }
     const int64_t t1 = now_ns();

@@ -210,23 +210,26 @@ __device__ __forceinline__ void push_bit(Ctx &c, uint64_t *tb, int32_t *tl, int 
     push_bit(c, LdsCtr{c.s}, tb, tl, v, x);
 }
 
-// Set bit x in tb; true if it was clear.
+// Set bit x in tb; true if it was clear. With `look`, a plain read first
+// skips the atomic for a bit already set (pushes from many candidates that
+// share neighbours); without, the atomic alone saves a round trip.
+template <bool look>
 __device__ __forceinline__ bool set_new(uint64_t *tb, int32_t x) {
     const uint64_t m = 1ull << (x & 63);
     uint64_t *w = tb + (x >> 6);
-    if (__atomic_load_n(w, __ATOMIC_RELAXED) & m) return false;
+    if (look && (__atomic_load_n(w, __ATOMIC_RELAXED) & m)) return false;
     return (atomicOr((unsigned long long *)w, m) & m) == 0;
 }
 
 // push_bit for up to four entries per lane (hk: push xk), appending the
 // newly set ones with one counter update per wave: the lanes that reach
 // this call take consecutive places in the order of their lane index.
-template <class K>
+template <class K, bool look = true>
 __device__ __forceinline__ void push4(Ctx &c, const K &k, uint64_t *tb, int32_t *tl, int v,
                                       bool h0, int32_t x0, bool h1, int32_t x1, bool h2,
                                       int32_t x2, bool h3, int32_t x3) {
-    const bool n0 = h0 && set_new(tb, x0), n1 = h1 && set_new(tb, x1);
-    const bool n2 = h2 && set_new(tb, x2), n3 = h3 && set_new(tb, x3);
+    const bool n0 = h0 && set_new<look>(tb, x0), n1 = h1 && set_new<look>(tb, x1);
+    const bool n2 = h2 && set_new<look>(tb, x2), n3 = h3 && set_new<look>(tb, x3);
     const int cnt = (int)n0 + (int)n1 + (int)n2 + (int)n3;
     const uint64_t b0 = __ballot(cnt & 1), b1 = __ballot(cnt & 2), b2 = __ballot(cnt & 4);
     const int tot = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
@@ -472,17 +475,21 @@ __device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb,
             uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
             int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
             seen += end - beg;
-            for (int32_t base = beg; base < end; base += 4 * NT) {
-                // four independent loads in flight per thread
+            for (int32_t base = beg; base < end; base += 8 * NT) {
+                // eight independent loads in flight per thread; a row's
+                // neighbours are distinct, so their bits are set without a
+                // look first
                 const int32_t i = base + threadIdx.x;
-                const int2 e0 = i < end ? adj[i] : make_int2(-1, -1);
-                const int2 e1 = i + NT < end ? adj[i + NT] : make_int2(-1, -1);
-                const int2 e2 = i + 2 * NT < end ? adj[i + 2 * NT] : make_int2(-1, -1);
-                const int2 e3 = i + 3 * NT < end ? adj[i + 3 * NT] : make_int2(-1, -1);
-                if (e0.x >= 0 && nbr_hit(c, d, e0)) push_bit(c, tb, tl, d.v, e0.x);
-                if (e1.x >= 0 && nbr_hit(c, d, e1)) push_bit(c, tb, tl, d.v, e1.x);
-                if (e2.x >= 0 && nbr_hit(c, d, e2)) push_bit(c, tb, tl, d.v, e2.x);
-                if (e3.x >= 0 && nbr_hit(c, d, e3)) push_bit(c, tb, tl, d.v, e3.x);
+                int2 e[8];
+                bool h[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) e[q] = adj_at(adj, i + q * NT, end);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) h[q] = (i + q * NT < end) && nbr_hit(c, d, e[q]);
+                push4<LdsCtr, false>(c, LdsCtr{c.s}, tb, tl, d.v, h[0], e[0].x, h[1], e[1].x,
+                                     h[2], e[2].x, h[3], e[3].x);
+                push4<LdsCtr, false>(c, LdsCtr{c.s}, tb, tl, d.v, h[4], e[4].x, h[5], e[5].x,
+                                     h[6], e[6].x, h[7], e[7].x);
             }
         }
     }
