@@ -81,7 +81,8 @@ constexpr int64_t kPairSlack = 8;
 struct HelpJob {
     unsigned long long claim;
     unsigned long long bytes;  // algorithmic bytes of the helpers' chunks
-    int32_t chunk, done, q, pad;
+    const int4 *seg;           // kind 1: the row segments, one per chunk
+    int32_t chunk, done, q, kind;  // kind 0: chunks of the candidate list; 1: row segments
     int32_t n_items, G, ncount, revd;
     NStep st;
     int32_t nbig, removed, nmarks, abort_;

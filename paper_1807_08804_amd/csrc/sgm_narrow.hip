@@ -58,6 +58,7 @@ struct Smem {
     int32_t ngiant;
     int32_t nnbl;
     int32_t nmarks;
+    int32_t ndef;  // candidates whose pushes go to row segments
     unsigned long long rowhit;  // item_wg: listed rows with a matching entry
     unsigned long long hseq;    // sequence number of the step this workgroup posted
     int32_t hq, hch;            // helper: board entry and chunk claimed (-1: none)
@@ -381,7 +382,7 @@ __device__ __forceinline__ void row_of(const DevGraph &g, int32_t up, int dir, i
 __device__ __forceinline__ int32_t max_row(const DevGraph &g, const NNbr *nb, int ncount, int32_t up);
 
 __device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb, int ncount, int32_t up,
-                        uint64_t *ub, uint64_t &fb) {
+                        uint64_t *ub, uint64_t &fb, int32_t *defer = nullptr) {
     const DevGraph &g = c.g;
     if (ncount <= 16 && max_row(g, nb, ncount, up) <= 4 * NT) {
         // Every listed row fits one pass: all rows are read and tested at
@@ -466,6 +467,13 @@ __device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb,
         }
         return;
     }
+    if (st.push && defer) {
+        if (threadIdx.x == 0) {
+            defer[c.s->ndef++] = up;
+            fb += 20ull + 12ull * seen;
+        }
+        return;
+    }
     if (st.push) {
         for (int j = 0; j < ncount; ++j) {
             const NNbr d = nb[j];
@@ -499,7 +507,8 @@ __device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb,
 // One wave on one candidate (wave-uniform call, no workgroup barrier), four
 // loads in flight per lane; same outcome as item_wg.
 __device__ __forceinline__ void item_wave(Ctx &c, const NStep &st, const NNbr *nb, int ncount,
-                                          int32_t up, uint64_t *ub, uint64_t &fb) {
+                                          int32_t up, uint64_t *ub, uint64_t &fb,
+                                          int32_t *defer = nullptr) {
     const DevGraph &g = c.g;
     const int lane = threadIdx.x & 63;
     bool alive = true;
@@ -530,6 +539,14 @@ __device__ __forceinline__ void item_wave(Ctx &c, const NStep &st, const NNbr *n
         if (lane == 0) {
             atomicAnd((unsigned long long *)&ub[up >> 6], ~(1ull << (up & 63)));
             atomicAdd(&c.s->removed, 1);
+            fb += 20ull + 12ull * seen;
+        }
+        return;
+    }
+    if (st.push && defer) {
+        // the pushes go to row segments that several workgroups share
+        if (lane == 0) {
+            defer[atomicAdd(&c.s->ndef, 1)] = up;
             fb += 20ull + 12ull * seen;
         }
         return;
@@ -742,27 +759,87 @@ __device__ __forceinline__ unsigned long long take_chunk(HelpJob *j) {
     return atomicAdd(&j->claim, 1ull);
 }
 
-// A filter step over many candidates, shared with the launch's idle
-// workgroups through this slot's board entry: the counters move to the
-// entry, the candidate list is cut into chunks that the owner and its
-// helpers claim, and the owner waits for the chunks its helpers claimed
-// before taking the counters back.
-__device__ __forceinline__ void shared_items(Ctx &c, const NStep &st, const NNbr *nb, int ncount,
-                                             const int32_t *ul, uint64_t *ub, bool revd,
-                                             int32_t n_items, int32_t helpers, uint64_t &fb) {
+// Row segments: pushes of long rows of surviving candidates, kSegEntries
+// entries of one row and one neighbour test per segment, one pass of a
+// whole workgroup each.
+constexpr int32_t kSegEntries = 8 * NT;
+
+// The pushes of segment sg = (candidate, test index, first entry, end) of a
+// row (whole workgroup). A row's neighbours are distinct, so bits are set
+// without a look first.
+template <class K>
+__device__ __forceinline__ void push_segment(Ctx &c, const K &k, const NNbr *nb, int4 sg,
+                                             uint64_t &fb) {
+    const NNbr d = nb[sg.y];
+    const int2 *adj = d.dir ? c.g.in_adj : c.g.out_adj;
+    uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
+    int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
+    for (int32_t base = sg.z; base < sg.w; base += kSegEntries) {
+        const int32_t i = base + threadIdx.x;
+        int2 e[8];
+        bool h[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = adj_at(adj, i + q * NT, sg.w);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) h[q] = (i + q * NT < sg.w) && nbr_hit(c, d, e[q]);
+        push4<K, false>(c, k, tb, tl, d.v, h[0], e[0].x, h[1], e[1].x, h[2], e[2].x, h[3], e[3].x);
+        push4<K, false>(c, k, tb, tl, d.v, h[4], e[4].x, h[5], e[5].x, h[6], e[6].x, h[7], e[7].x);
+    }
+    if (threadIdx.x == 0) fb += 12ull * (uint64_t)(sg.w - sg.z);
+}
+
+// Segments of the rows of the nd deferred candidates into seg (at most cap);
+// the count, or -1 if they do not fit (uniform).
+__device__ __forceinline__ int32_t build_segments(Ctx &c, const NNbr *nb, int ncount,
+                                                  const int32_t *def, int32_t nd, int4 *seg,
+                                                  int64_t cap) {
+    int64_t carry = 0;
+    for (int32_t base = 0; base < nd; base += NT) {
+        const int32_t i = base + threadIdx.x;
+        int32_t cnt = 0;
+        if (i < nd)
+            for (int j = 0; j < ncount; ++j) {
+                int32_t b, e;
+                row_of(c.g, def[i], nb[j].dir, &b, &e);
+                cnt += (e - b + kSegEntries - 1) / kSegEntries;
+            }
+        int64_t tot;
+        const int64_t ex = block_excl_scan(cnt, c.s->sh, &tot);
+        if (i < nd && carry + tot <= cap) {
+            int64_t p = carry + ex;
+            for (int j = 0; j < ncount; ++j) {
+                int32_t b, e;
+                row_of(c.g, def[i], nb[j].dir, &b, &e);
+                for (int32_t x = b; x < e; x += kSegEntries)
+                    seg[p++] = make_int4(def[i], j, x, min(e, x + kSegEntries));
+            }
+        }
+        carry += tot;
+    }
+    __syncthreads();
+    return carry <= cap ? (int32_t)carry : -1;
+}
+
+// A filter step shared with the launch's idle workgroups through this
+// slot's board entry: the counters move to the entry, the work is cut into
+// nch chunks that the owner and its helpers claim (kind 0: K candidates of
+// u's list, G lanes each; kind 1: one row segment each), and the owner waits
+// for the chunks its helpers claimed before taking the counters back.
+__device__ __forceinline__ void shared_job(Ctx &c, int kind, const NStep &st, const NNbr *nb,
+                                           int ncount, const int32_t *ul, uint64_t *ub, bool revd,
+                                           int32_t n_items, int32_t K, int G, int32_t nch,
+                                           const int4 *seg, uint64_t &fb) {
     HelpJob *j = c.job;
-    const int32_t K = min(512, max(64, max((n_items + helpers) / (helpers + 1),
-                                           (n_items + kMaxChunks - 1) / kMaxChunks)));
-    const int G = lanes_for(K, c.gmax);
-    const int32_t nch = (n_items + K - 1) / K;
     if (threadIdx.x == 0) {
         for (int v = 0; v < SGM_MAX_QV; ++v) j->cnt[v] = c.s->cnt[v];
         j->nbig = 0;
         j->removed = 0;
-        j->nmarks = 0;
+        j->nmarks = c.s->nmarks;
         j->abort_ = 0;
         j->bytes = 0ull;
         j->done = 0;
+        j->kind = kind;
+        j->seg = seg;
         j->chunk = K;
         j->q = c.q;
         j->n_items = n_items;
@@ -794,8 +871,11 @@ __device__ __forceinline__ void shared_items(Ctx &c, const NStep &st, const NNbr
         const int32_t ch = c.s->hch;
         __syncthreads();
         if (ch < 0) break;
-        filter_items(c, BoardCtr{j}, st.push != 0, nb, ncount, ul, ub, revd, G, ch * K,
-                     min(n_items, ch * K + K), fb);
+        if (kind == 0)
+            filter_items(c, BoardCtr{j}, st.push != 0, nb, ncount, ul, ub, revd, G, ch * K,
+                         min(n_items, ch * K + K), fb);
+        else
+            push_segment(c, BoardCtr{j}, nb, seg[ch], fb);
         ++own;
     }
     __syncthreads();
@@ -812,8 +892,8 @@ __device__ __forceinline__ void shared_items(Ctx &c, const NStep &st, const NNbr
         atomicSub(&c.hctr[0], 1);
         for (int v = 0; v < SGM_MAX_QV; ++v)
             c.s->cnt[v] = __hip_atomic_load(&j->cnt[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        c.s->nbig = __hip_atomic_load(&j->nbig, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        c.s->removed = __hip_atomic_load(&j->removed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        c.s->nbig += __hip_atomic_load(&j->nbig, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        c.s->removed += __hip_atomic_load(&j->removed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         c.s->nmarks = __hip_atomic_load(&j->nmarks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int32_t ab = __hip_atomic_load(&j->abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (ab) c.s->abort_ = ab;
@@ -821,6 +901,65 @@ __device__ __forceinline__ void shared_items(Ctx &c, const NStep &st, const NNbr
         add_bytes(c, __hip_atomic_load(&j->bytes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     }
     __syncthreads();
+}
+
+// Chunks of u's candidate list shared as above.
+__device__ __forceinline__ void shared_items(Ctx &c, const NStep &st, const NNbr *nb, int ncount,
+                                             const int32_t *ul, uint64_t *ub, bool revd,
+                                             int32_t n_items, int32_t helpers, uint64_t &fb) {
+    const int32_t K = min(512, max(64, max((n_items + helpers) / (helpers + 1),
+                                           (n_items + kMaxChunks - 1) / kMaxChunks)));
+    const int G = lanes_for(K, c.gmax);
+    const int32_t nch = (n_items + K - 1) / K;
+    shared_job(c, 0, st, nb, ncount, ul, ub, revd, n_items, K, G, nch, nullptr, fb);
+}
+
+// Workgroups that can help this slot now: the launch's extra ones and the
+// slot workgroups whose queue ran dry (uniform).
+__device__ __forceinline__ int32_t helpers_now(Ctx &c) {
+    if (c.help_items <= 0) return 0;
+    if (c.ngrid > c.nslot) return c.ngrid - c.nslot;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        c.s->hch = c.ngrid - c.nslot +
+                   __hip_atomic_load(&c.hctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int32_t h = c.s->hch;
+    __syncthreads();
+    return h;
+}
+
+// The pushes deferred by the wave and workgroup tiers, as shared row
+// segments (or by this workgroup alone when they do not fit the slab).
+__device__ __forceinline__ void push_deferred(Ctx &c, const NStep &st, const NNbr *nb, int ncount,
+                                              const int32_t *def, uint64_t &fb) {
+    __syncthreads();
+    const int32_t nd = c.s->ndef;
+    if (nd == 0) return;
+    int4 *seg = (int4 *)(c.slab + 12 * (int64_t)c.lcap);
+    const int64_t cap = (c.slab_bytes - 12 * (int64_t)c.lcap) / (int64_t)sizeof(int4);
+    const int32_t nseg = build_segments(c, nb, ncount, def, nd, seg, cap);
+    if (nseg > 0) {
+        shared_job(c, 1, st, nb, ncount, nullptr, nullptr, false, 0, 1, NT, nseg, seg, fb);
+    } else {
+        for (int32_t i = 0; i < nd; ++i)
+            for (int j = 0; j < ncount; ++j) {
+                int32_t b, e;
+                row_of(c.g, def[i], nb[j].dir, &b, &e);
+                push_segment(c, LdsCtr{c.s}, nb, make_int4(def[i], j, b, e), fb);
+            }
+        __syncthreads();
+    }
+}
+
+// Where the wave and workgroup tiers of a pushing step list the candidates
+// whose pushes become shared row segments, when helpers exist and the slab
+// has room beyond the overflow list and the marks; else nullptr (uniform).
+__device__ __forceinline__ int32_t *defer_list(Ctx &c, const NStep &st) {
+    if (!st.push || c.help_items <= 0) return nullptr;
+    if (c.slab_bytes < 12 * (int64_t)c.lcap + 64 * (int64_t)sizeof(int4)) return nullptr;
+    if (helpers_now(c) <= 0) return nullptr;
+    return (int32_t *)(c.slab + 8 * (int64_t)c.lcap);
 }
 
 __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
@@ -834,6 +973,7 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
         c.s->ngiant = 0;
         c.s->removed = 0;
         c.s->nmarks = 0;
+        c.s->ndef = 0;
     }
     __syncthreads();
     const int32_t n_items = c.s->cnt[u];
@@ -900,19 +1040,11 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
     if (ncount == 0) {
         // every test was done from the other side
     } else if (n_items <= NW) {
-        for (int32_t it = 0; it < n_items; ++it) item_wg(c, st, nb, ncount, ul[it], ub, fb);
+        int32_t *def = defer_list(c, st);
+        for (int32_t it = 0; it < n_items; ++it) item_wg(c, st, nb, ncount, ul[it], ub, fb, def);
+        if (def) push_deferred(c, st, nb, ncount, def, fb);
     } else {
-        // helpers: the launch's extra workgroups and the slot workgroups
-        // whose queue ran dry
-        int32_t helpers = 0;
-        if (c.help_items > 0 && n_items >= c.help_items) {
-            if (threadIdx.x == 0)
-                c.s->hch = c.ngrid - c.nslot +
-                           __hip_atomic_load(&c.hctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __syncthreads();
-            helpers = c.s->hch;
-            __syncthreads();
-        }
+        const int32_t helpers = n_items >= c.help_items ? helpers_now(c) : 0;
         if (helpers > 0)
             shared_items(c, st, nb, ncount, ul, ub, revd, n_items, helpers, fb);
         else
@@ -923,6 +1055,7 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
         __syncthreads();
         // one wave per long row; rows above wg_rows get the whole workgroup
         const int32_t nbig = c.s->nbig;
+        int32_t *def = nbig > 0 ? defer_list(c, st) : nullptr;
         for (int32_t b = threadIdx.x >> 6; b < nbig; b += NW) {
             const int32_t up = ov[b];
             if (max_row(g, nb, ncount, up) > c.wg_rows) {
@@ -935,11 +1068,12 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
                 }
                 // LDS list full: this wave handles the row itself
             }
-            item_wave(c, st, nb, ncount, up, ub, fb);
+            item_wave(c, st, nb, ncount, up, ub, fb, def);
         }
         __syncthreads();
         const int32_t ngiant = min(c.s->ngiant, kBigCap);
-        for (int32_t b = 0; b < ngiant; ++b) item_wg(c, st, nb, ncount, c.s->big[b], ub, fb);
+        for (int32_t b = 0; b < ngiant; ++b) item_wg(c, st, nb, ncount, c.s->big[b], ub, fb, def);
+        if (def) push_deferred(c, st, nb, ncount, def, fb);
     }
     add_bytes_wave(c, fb);
     __syncthreads();
@@ -2048,6 +2182,8 @@ __device__ __forceinline__ void help_step(const NArgs &a, Smem &s, unsigned char
     const NStep st = j->st;
     const int32_t K = j->chunk, G = j->G, n_items = j->n_items, ncount = j->ncount;
     const bool revd = j->revd != 0;
+    const int kind = j->kind;
+    const int4 *seg = j->seg;
     if ((int)threadIdx.x < ncount) {
         s.nbl[threadIdx.x].v = j->nbl[threadIdx.x].v;
         s.nbl[threadIdx.x].dir = j->nbl[threadIdx.x].dir;
@@ -2060,8 +2196,11 @@ __device__ __forceinline__ void help_step(const NArgs &a, Smem &s, unsigned char
     uint64_t fb = 0;
     int32_t n = 0;
     while (ch >= 0) {
-        filter_items(c, BoardCtr{j}, st.push != 0, s.nbl, ncount, c.L(st.u), c.B(st.u), revd, G,
-                     ch * K, min(n_items, ch * K + K), fb);
+        if (kind == 0)
+            filter_items(c, BoardCtr{j}, st.push != 0, s.nbl, ncount, c.L(st.u), c.B(st.u), revd,
+                         G, ch * K, min(n_items, ch * K + K), fb);
+        else
+            push_segment(c, BoardCtr{j}, s.nbl, seg[ch], fb);
         ++n;
         __syncthreads();
         if (threadIdx.x == 0) {
