@@ -77,3 +77,35 @@ def test_autotune_keeps_results(medium_kg, medium_set):
         same(r, w)
     say(f"  picked {best}")
     g.close()
+
+
+@pytest.fixture(scope="module")
+def medium_filter(oracle_medium, medium_set):
+    """The oracle's candidate counts per query vertex after filtering, and
+    its candidate-edge counts when no set is empty."""
+    qs, _ = medium_set
+    out = []
+    for q in qs:
+        cand = oracle_medium.filter(q)
+        ec = None
+        if len(q.esrc) and cand.any(axis=1).all():
+            ec = oracle_medium.edge_candidates(q, cand).tolist()
+        out.append((cand.sum(axis=1).tolist(), ec))
+    return out
+
+
+@pytest.mark.parametrize("tune", TUNINGS)
+def test_candidates_match_oracle_filter(tune, medium_kg, medium_set, medium_filter):
+    """Final candidate sets and candidate-edge counts of the persistent
+    kernel equal the oracle's under every tuning, shared filter steps
+    included (a step's removals must all reach the compaction)."""
+    qs, _ = medium_set
+    say(f"case: candidates under tuning {tune}")
+    g = P.Graph.from_kg(medium_kg, path=P.SGM_PATH_NARROW)
+    g.set_tuning(**tune)
+    for i, (q, (cnt, ec)) in enumerate(zip(qs, medium_filter)):
+        _, st = g.match_query(q, with_stats=True)
+        assert st["cand"] == cnt, (i, st["cand"], cnt)
+        if ec is not None:
+            assert st["ec"] == ec, (i, st["ec"], ec)
+    g.close()
