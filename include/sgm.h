@@ -244,9 +244,11 @@ int sgm_trace_events(sgm_graph *g, int32_t i, int64_t *out, int32_t cap, double 
  *   join_policy  0: bind the vertex of the cheapest candidate-edge table
  *                next (thesis Sec. "Joining Phase"); 1: bind the vertex with
  *                the most edges to bound vertices first, cheapest on ties
- *   help_items   a filter step over at least this many candidates is shared
+ *   help_items   work sharing inside a launch (0: none; else >= 64): a
+ *                filter step over at least this many candidates is shared
  *                with the launch's idle workgroups, which claim chunks of
- *                its candidate list (0: never; else >= 64)
+ *                its candidate list, and the pushes of candidates with long
+ *                rows are shared as row segments in any filter step
  *   helpers      a launch with fewer queries than this adds workgroups that
  *                only help, up to this many workgroups in all (0..512; used
  *                only with help_items > 0; the served form adds none)
