@@ -2370,6 +2370,7 @@ __global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *pre
     if (n_pred == 0) return;
     __shared__ uint64_t rows[kSweepChunk * kSweepStride];
     __shared__ VPred pl[kSweepChunk];
+    __shared__ int2 pq[kSweepChunk];  // (qout, qin) of the chunk's predicates
     __shared__ int32_t toff[kSweepTypes + 1];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const bool table = n_types > 0 && n_types <= kSweepTypes;
@@ -2386,44 +2387,68 @@ __global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *pre
     for (int32_t c0 = 0; c0 < n_pred; c0 += kSweepChunk) {
         const int cn = min(kSweepChunk, n_pred - c0);
         for (int i = threadIdx.x; i < cn * kSweepStride; i += 256) rows[i] = 0ull;
-        if ((int)threadIdx.x < cn) pl[threadIdx.x] = preds[c0 + threadIdx.x];
+        if ((int)threadIdx.x < cn) {
+            const VPred p = preds[c0 + threadIdx.x];
+            pl[threadIdx.x] = p;
+            pq[threadIdx.x] = make_int2(p.qout, p.qin);
+        }
         __syncthreads();
-        // untyped predicates: the same test for every lane
+        // untyped predicates: the same test for every lane; lane i keeps
+        // the ballot of slot i and lanes 0..15 store the wave's 16 words
         for (int j = 0; j < min(n_any - c0, cn); ++j) {
-            const VPred p = pl[j];
+            const int2 q = pq[j];
+            uint64_t mine = 0;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const bool ok = vi[i].x >= 0 && (vi[i].y & 255) >= p.qout && (vi[i].y >> 8) >= p.qin;
+                const bool ok = vi[i].x >= 0 && (vi[i].y & 255) >= q.x && (vi[i].y >> 8) >= q.y;
                 const uint64_t b = __ballot(ok);
-                if (lane == 0) rows[j * kSweepStride + 16 * wid + i] = b;
+                mine = lane == i ? b : mine;
             }
+            if (lane < 16) rows[j * kSweepStride + 16 * wid + lane] = mine;
         }
         // typed predicates of this chunk: [t0, cn), sorted by type
         const int t0 = max(0, n_any - c0);
+        if (table) {
+            // each vertex's range of predicates of its type, all 16 read
+            // before any is used (independent LDS reads), packed lo | hi << 16
+            int32_t r[16];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int32_t t = vi[i].x;
-            if (t < 0 || t0 >= cn) continue;
-            int lo, end;
-            if (table) {
-                // the predicates of type t, clipped to this chunk
-                if (t >= n_types) continue;
-                lo = max(t0, toff[t] - c0);
-                end = min(cn, toff[t + 1] - c0);
-            } else {
-                lo = t0;
-                int hi = cn;
+            for (int i = 0; i < 16; ++i) {
+                const int32_t t = vi[i].x;
+                const bool ok = t >= 0 && t < n_types && t0 < cn;
+                const int32_t tc = ok ? t : 0;
+                const int32_t lo = max(t0, toff[tc] - c0), hi = min(cn, toff[tc + 1] - c0);
+                r[i] = ok && lo < hi ? (lo | (hi << 16)) : 0;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int od = vi[i].y & 255, id = vi[i].y >> 8;
+                const int hi = r[i] >> 16;
+                for (int j = r[i] & 0xffff; j < hi; ++j) {
+                    const int2 q = pq[j];
+                    if (od >= q.x && id >= q.y)
+                        atomicOr((unsigned long long *)&rows[j * kSweepStride + 16 * wid + i],
+                                 1ull << lane);
+                }
+            }
+        } else {
+            // more types than the table holds: binary search per vertex
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int32_t t = vi[i].x;
+                if (t < 0 || t0 >= cn) continue;
+                int lo = t0, hi = cn;
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
                     if (pl[mid].label < t) lo = mid + 1;
                     else hi = mid;
                 }
-                end = cn;
+                const int od = vi[i].y & 255, id = vi[i].y >> 8;
+                for (int j = lo; j < cn && pl[j].label == t; ++j)
+                    if (od >= pq[j].x && id >= pq[j].y)
+                        atomicOr((unsigned long long *)&rows[j * kSweepStride + 16 * wid + i],
+                                 1ull << lane);
             }
-            const int od = vi[i].y & 255, id = vi[i].y >> 8;
-            for (int j = lo; j < end && pl[j].label == t; ++j)
-                if (od >= pl[j].qout && id >= pl[j].qin)
-                    atomicOr((unsigned long long *)&rows[j * kSweepStride + 16 * wid + i], 1ull << lane);
         }
         __syncthreads();
         for (int k = threadIdx.x; k < cn * kSweepTile; k += 256) {
