@@ -937,7 +937,9 @@ __device__ __forceinline__ void push_deferred(Ctx &c, const NStep &st, const NNb
     const int32_t nd = c.s->ndef;
     if (nd == 0) return;
     int4 *seg = (int4 *)(c.slab + 12 * (int64_t)c.lcap);
-    const int64_t cap = (c.slab_bytes - 12 * (int64_t)c.lcap) / (int64_t)sizeof(int4);
+    // room in the slab, and no more chunks than a claim word can count
+    const int64_t cap = min((c.slab_bytes - 12 * (int64_t)c.lcap) / (int64_t)sizeof(int4),
+                            (int64_t)kMaxChunks);
     const int32_t nseg = build_segments(c, nb, ncount, def, nd, seg, cap);
     if (nseg > 0) {
         shared_job(c, 1, st, nb, ncount, nullptr, nullptr, false, 0, 1, NT, nseg, seg, fb);
