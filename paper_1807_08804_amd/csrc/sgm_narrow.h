@@ -1,6 +1,7 @@
 // Persistent per-query kernel of the sgm library (internal): one workgroup
 // runs a whole query -- filtering, candidate edges, join, ordering -- out of
-// its own slot of device memory, then takes the next query from a queue.
+// its own slot of device memory, then takes the next query from a queue;
+// idle workgroups of the launch help with large filter steps.
 #pragma once
 
 #include <stdint.h>

@@ -1,7 +1,10 @@
-// Persistent per-query kernel (gfx950): each workgroup takes queries from a
-// queue and runs the whole filtering-and-joining pipeline of one query
+// Persistent per-query kernel (gfx950): each slot workgroup takes queries
+// from a queue and runs the whole filtering-and-joining pipeline of one query
 // (thesis Alg. 3.1) with barrier-separated phases, in its own slot of device
-// memory, then leaves the slot's bitmaps zeroed for the next query.
+// memory, then leaves the slot's bitmaps zeroed for the next query. Filter
+// steps over many candidates or long rows are shared: the owner posts them on
+// a board and the launch's idle workgroups (extra ones, and slot workgroups
+// whose queue ran dry) claim chunks of them.
 //
 // Phases (thesis Ch. 3):
 //   root candidates  -- kernel_check / kernel_collect of Alg. 3.2 (the sweep

@@ -28,6 +28,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,11 +37,24 @@ KERNEL_SOURCES = ["csrc/sgm_narrow.hip", "csrc/sgm_narrow.h", "csrc/sgm_device.h
                   "csrc/sgm_internal.h"]
 
 
-def kernel_source_hash() -> str:
+def _code_only(text: str) -> str:
+    """Source text without comments, trailing blanks and empty lines: the
+    hash follows the code, not its documentation."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
+def kernel_source_hash(read=None) -> str:
+    """Hash of the kernel sources' code (read(rel) -> text; default: the
+    files beside this module)."""
+    if read is None:
+        def read(rel):
+            with open(os.path.join(HERE, rel), encoding="utf-8") as f:
+                return f.read()
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as f:
-            h.update(f.read())
+        h.update(_code_only(read(rel)).encode())
     return h.hexdigest()
 
 

@@ -126,3 +126,29 @@ def test_load_graph_rejects_malformed_csr_before_touching_device():
 def test_strerror():
     assert P.sgm_strerror(P.SGM_ETOOBIG)
     assert P.sgm_strerror(12345) == "unknown error"
+
+
+def test_query_marshalling_points_at_the_arrays():
+    """The binding packs a query's five arrays into one int32 block; every
+    pointer of the C struct must address its own array."""
+    import ctypes
+
+    def read(addr, k):
+        return list((ctypes.c_int32 * k).from_address(addr)) if k else []
+
+    cases = [(3, [1, -1, 7], [-1, 5, -1], [0, 1], [1, 2], [4, -1]),
+             (1, [2], [-1], [], [], []),
+             (4, np.array([0, 1, 2, 3], np.int64), [9, -1, -1, -1], [0, 1, 2, 3, 0],
+              [1, 2, 3, 0, 2], [0, 1, 2, 3, -1])]
+    for n, vl, vp, es, ed, el in cases:
+        q, keep = P._make_query(n, vl, vp, es, ed, el)
+        assert q.n_vertices == n and q.n_edges == len(es)
+        assert read(q.vertex_label, n) == [int(x) for x in vl]
+        assert read(q.vertex_pin, n) == [int(x) for x in vp]
+        assert read(q.edge_src, len(es)) == list(es)
+        assert read(q.edge_dst, len(es)) == list(ed)
+        assert read(q.edge_label, len(es)) == list(el)
+    with pytest.raises(ValueError):
+        P._make_query(2, [0, 0], [-1], [0], [1], [0])
+    with pytest.raises(ValueError):
+        P._make_query(2, [0, 0], [-1, -1], [0], [1, 0], [0])
