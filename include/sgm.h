@@ -121,9 +121,12 @@ typedef struct {
     int32_t fallback;              /* why a query outgrew a regular persistent-kernel
                                       slot: 1 candidate list capacity, 2 slot
                                       memory, 4 ordering key > 64 bits, 8 output
-                                      arena full, 16 plan descriptor size. With
-                                      path NARROW it then ran in a large slot;
-                                      with path WIDE on the multi-kernel path */
+                                      arena full, 16 plan descriptor size, 32 a
+                                      shared filter step not finished by its
+                                      helpers in time (an internal error; the
+                                      query is rerun). With path NARROW it then
+                                      ran in a large slot; with path WIDE on the
+                                      multi-kernel path */
 } sgm_stats;
 
 typedef struct {

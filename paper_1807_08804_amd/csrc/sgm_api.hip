@@ -1559,7 +1559,11 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         const int qi_idx = job.packed[i];
         if (r.status != SGM_OK) {
             wide.push_back(qi_idx);
-            res[qi_idx]->stats.fallback = r.status == kOutFull ? 8 : r.reason;
+            // sgm_stats.fallback codes: the kernel's reasons 1, 2, 4; 8 for a
+            // full output arena; 32 for a shared step its helpers left
+            // unfinished (kernel reason kWhyHelp)
+            res[qi_idx]->stats.fallback =
+                r.status == kOutFull ? 8 : (r.reason == kWhyHelp ? 32 : r.reason);
             res[qi_idx]->stats.peak_bytes = r.need;  // slot memory a join level could need
             continue;
         }
