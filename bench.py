@@ -401,7 +401,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the matcher "
-              "has no multi-GPU path in this build.", file=sys.stderr)
+              "has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import kggen
     import paper_1807_08804_amd as P
