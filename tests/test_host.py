@@ -1,6 +1,7 @@
 """CPU-only checks of the library: it loads, exports every declared symbol,
 and its host logic (query checks, query plan, CSR checks) behaves as the
 thesis describes. No kernel is launched here."""
+import ctypes
 import os
 import re
 
@@ -131,7 +132,6 @@ def test_strerror():
 def test_query_marshalling_points_at_the_arrays():
     """The binding packs a query's five arrays into one int32 block; every
     pointer of the C struct must address its own array."""
-    import ctypes
 
     def read(addr, k):
         return list((ctypes.c_int32 * k).from_address(addr)) if k else []
@@ -152,3 +152,31 @@ def test_query_marshalling_points_at_the_arrays():
         P._make_query(2, [0, 0], [-1], [0], [1], [0])
     with pytest.raises(ValueError):
         P._make_query(2, [0, 0], [-1, -1], [0], [1, 0], [0])
+
+
+def test_default_tuning_matches_the_header():
+    """sgm_default_tuning fills the defaults sgm.h documents (no device)."""
+    t = P.sgm_tuning()
+    P.lib().sgm_default_tuning(ctypes.byref(t))
+    assert {k: getattr(t, k) for k in P.TUNING_FIELDS} == dict(
+        slots=512, group_lanes=64, wg_rows=8192, join_policy=0, help_items=1024, helpers=64)
+    header = open(os.path.join(os.path.dirname(__file__), "..", "include", "sgm.h")).read()
+    assert "help_items 1024, helpers 64" in header
+
+
+def test_traffic_record_hash_follows_code_only():
+    """The kernel-source hash that guards recorded counter traffic ignores
+    comments and blank lines but not code."""
+    from paper_1807_08804_amd import prof_summary as ps
+    base = {rel: "int f(int x) {\n    return x + 1;\n}\n" for rel in ps.KERNEL_SOURCES}
+    h0 = ps.kernel_source_hash(lambda rel: base[rel])
+    noted = dict(base)
+    first = ps.KERNEL_SOURCES[0]
+    noted[first] = "// a note\n/* a block\n   comment */\n" + base[first].replace(
+        "return x + 1;", "return x + 1;  // trailing note") + "\n\n"
+    assert ps.kernel_source_hash(lambda rel: noted[rel]) == h0
+    changed = dict(base)
+    changed[first] = base[first].replace("x + 1", "x + 2")
+    assert ps.kernel_source_hash(lambda rel: changed[rel]) != h0
+    assert ps.kernel_source_hash() == ps.kernel_source_hash(
+        lambda rel: open(os.path.join(os.path.dirname(ps.__file__), rel)).read())
