@@ -209,6 +209,18 @@ static int consistent(const oracle_graph *g, const or_query *q, const int32_t *f
     return 1;
 }
 
+/* A unit of the parallel search: root candidate x, and either the whole
+ * search below it (hi < 0) or the second vertex's candidates from entries
+ * [lo, hi) of row array arr. */
+typedef struct {
+    int32_t x;
+    int64_t lo, hi;
+    const or_pair *arr;
+} or_item;
+
+/* Row entries per work item of a split root. */
+#define OR_PIECE 4096
+
 typedef struct {
     const oracle_graph *g;
     const or_query *q;
@@ -235,6 +247,11 @@ static int over_budget(or_ctx *c) {
     return 0;
 }
 
+static void dfs_range(or_ctx *c, int32_t *f, int depth, int64_t lo, int64_t hi,
+                      const or_pair *arr);
+static int gen_range(const oracle_graph *g, const or_query *q, const int32_t *f, int depth,
+                     int32_t u, int64_t *lo_out, int64_t *hi_out, const or_pair **arr_out);
+
 static void dfs(or_ctx *c, int32_t *f, int depth) {
     const or_query *q = c->q;
     const oracle_graph *g = c->g;
@@ -260,7 +277,40 @@ static void dfs(or_ctx *c, int32_t *f, int depth) {
         }
         return;
     }
-    /* generate from the already-placed neighbour with the shortest data row */
+    int64_t lo, hi;
+    const or_pair *arr;
+    if (!gen_range(g, q, f, depth, u, &lo, &hi, &arr)) return; /* unreachable past depth 0 */
+    dfs_range(c, f, depth, lo, hi, arr);
+}
+
+/* Candidates of vertex order[depth] from entries [lo, hi) of the data row
+ * gen_range chose (a row is sorted by destination; repeated destinations,
+ * i.e. other relations, are one candidate). */
+static void dfs_range(or_ctx *c, int32_t *f, int depth, int64_t lo, int64_t hi,
+                      const or_pair *arr) {
+    const or_query *q = c->q;
+    const oracle_graph *g = c->g;
+    int32_t u = q->order[depth];
+    int32_t prev = -1; /* pieces of a row never split a run of equal destinations */
+    for (int64_t k = lo; k < hi; k++) {
+        int32_t x = arr[k].dst;
+        if (x == prev) continue; /* same neighbour, other relation */
+        prev = x;
+        if (over_budget(c)) return;
+        if (consistent(g, q, f, depth, u, x)) {
+            f[u] = x;
+            dfs(c, f, depth + 1);
+            if (__atomic_load_n(c->abort_flag, __ATOMIC_RELAXED)) return;
+        }
+    }
+}
+
+/* The data row that generates the candidates of vertex u at this depth: the
+ * row of the already-placed neighbour with the fewest entries (out-row of
+ * f(a) for a query edge a -> u, in-row of f(b) for u -> b). 0 if u has no
+ * placed neighbour. */
+static int gen_range(const oracle_graph *g, const or_query *q, const int32_t *f, int depth,
+                     int32_t u, int64_t *lo_out, int64_t *hi_out, const or_pair **arr_out) {
     int best_len_set = 0;
     int64_t best_lo = 0, best_hi = 0;
     const or_pair *best_arr = NULL;
@@ -286,19 +336,10 @@ static void dfs(or_ctx *c, int32_t *f, int depth) {
             best_arr = arr;
         }
     }
-    if (!best_len_set) return; /* unreachable for connected queries past depth 0 */
-    int32_t prev = -1;
-    for (int64_t k = best_lo; k < best_hi; k++) {
-        int32_t x = best_arr[k].dst;
-        if (x == prev) continue; /* same neighbour, other relation */
-        prev = x;
-        if (over_budget(c)) return;
-        if (consistent(g, q, f, depth, u, x)) {
-            f[u] = x;
-            dfs(c, f, depth + 1);
-            if (__atomic_load_n(c->abort_flag, __ATOMIC_RELAXED)) return;
-        }
-    }
+    *lo_out = best_lo;
+    *hi_out = best_hi;
+    *arr_out = best_arr;
+    return best_len_set;
 }
 
 static int row_cmp(const void *a, const void *b, void *arg) {
@@ -432,10 +473,54 @@ int oracle_match_budget(const oracle_graph *g, int32_t n, int32_t m, const int32
             if (vlabel[root] < 0 || g->vtype[v] == vlabel[root]) roots[n_roots++] = v;
     }
 
+    /* Work items for the threads: a root candidate with the whole search
+     * below it, or, when the second vertex in the order is generated from a
+     * data row, a root candidate with a piece of that row (so that a hub
+     * root's search is spread over threads). Pieces never split a run of
+     * equal destinations. Every item is an independent part of the same
+     * depth-first search; rows are sorted at the end, so the split does not
+     * change the result. */
+    or_item *items = NULL;
+    int64_t n_items = 0, cap_items = 0;
+    {
+        int32_t f0[OR_MAXQ];
+        for (int64_t i = 0; i < n_roots; i++) {
+            int32_t x = roots[i];
+            if (!consistent(g, &q, f0, 0, root, x)) continue;
+            f0[root] = x;
+            int64_t lo = 0, hi = -1;
+            const or_pair *arr = NULL;
+            int split = n > 1 && vpin[q.order[1]] < 0 &&
+                        gen_range(g, &q, f0, 1, q.order[1], &lo, &hi, &arr);
+            int64_t a = split ? lo : 0, end = split ? hi : 0;
+            do {
+                int64_t b = split ? (end - a > OR_PIECE ? a + OR_PIECE : end) : 0;
+                while (split && b < end && arr[b].dst == arr[b - 1].dst) b++;
+                if (n_items == cap_items) {
+                    cap_items = cap_items ? 2 * cap_items : 1024;
+                    or_item *t = (or_item *)realloc(items, sizeof(or_item) * (size_t)cap_items);
+                    if (!t) {
+                        free(items);
+                        free(roots);
+                        return OR_ENOMEM;
+                    }
+                    items = t;
+                }
+                items[n_items].x = x;
+                items[n_items].lo = split ? a : 0;
+                items[n_items].hi = split ? b : -1;
+                items[n_items].arr = arr;
+                n_items++;
+                a = b;
+            } while (split && a < end);
+        }
+    }
+    free(roots);
+
     int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
     or_buf *bufs = (or_buf *)calloc((size_t)nt, sizeof(or_buf));
     if (!bufs) {
-        free(roots);
+        free(items);
         return OR_ENOMEM;
     }
     int64_t total = 0;
@@ -457,16 +542,15 @@ int oracle_match_budget(const oracle_graph *g, int32_t n, int32_t m, const int32
         c.local_steps = 0;
         int32_t f[OR_MAXQ];
 #pragma omp for schedule(dynamic, 1)
-        for (int64_t i = 0; i < n_roots; i++) {
+        for (int64_t i = 0; i < n_items; i++) {
             if (__atomic_load_n(&abort_flag, __ATOMIC_RELAXED)) continue;
             if (over_budget(&c)) continue;
-            int32_t x = roots[i];
-            if (!consistent(g, &q, f, 0, root, x)) continue;
-            f[root] = x;
-            dfs(&c, f, 1);
+            f[root] = items[i].x;
+            if (items[i].hi < 0) dfs(&c, f, 1);
+            else dfs_range(&c, f, 1, items[i].lo, items[i].hi, items[i].arr);
         }
     }
-    free(roots);
+    free(items);
     int failed = 0;
     for (int t = 0; t < nt; t++) failed |= bufs[t].failed;
     if (failed) {

@@ -122,6 +122,31 @@ def test_out_star_counts(k):
     assert g.match_query(wrong_rel, count_only=True) == 0
 
 
+@pytest.mark.parametrize("pin", [True, False])
+def test_hub_row_with_repeated_destinations(pin):
+    """A hub with 5,000 out-neighbours, all but one reached by two relations,
+    so its row (9,999 entries) is longer than the oracle's work pieces and runs of
+    one destination cross piece boundaries: a one-edge variable query from
+    the hub has exactly one row per neighbour (out-star, k = 1), and a
+    two-leaf query with one leaf typed d!/(d-2)! restricted as counted."""
+    d = 5000
+    # neighbour 1 by one relation, the others by two: runs start at odd entries
+    dst = [1] + [2 + i // 2 for i in range(2 * (d - 1))]
+    rel = [1] + [i % 2 for i in range(2 * (d - 1))]
+    src = [0] * len(dst)
+    vtype = [1] + [0] * d
+    vtype[7] = 2
+    g = og_of(MicroGraph(d + 1, src, dst, rel, vtype))
+    vpin = [0, -1] if pin else [-1, -1]
+    vlab = [-1, -1] if pin else [1, -1]
+    rows = g.match_query(MicroQuery(2, vlab, vpin, [0], [1], [-1]))
+    assert rows.tolist() == [[0, x] for x in range(1, d + 1)]
+    assert g.match_query(MicroQuery(2, vlab, vpin, [0], [1], [1]), count_only=True) == d
+    # centre, a typed-2 leaf (vertex 7 only) and any other leaf
+    q3 = MicroQuery(3, vlab + [2], vpin + [-1], [0, 0], [1, 2], [-1, -1])
+    assert g.match_query(q3, count_only=True) == d - 1
+
+
 def test_disjoint_labels_zero():
     g = complete_digraph(5)
     og = og_of(g)
