@@ -632,17 +632,46 @@ LARGE_CYCLIC_RECIPE = ("large_queries(named_graph('large'), 50, seed=BASE_SEED+1
                        "hmin=1e7, hmax=2e9, p_any=0.5)")
 
 
+LARGE_BATCH_RECIPE = ("batch_queries(named_graph('large'), 1024, seed=BASE_SEED+103, "
+                      "hmax=1e6)")
+LARGE_SERVE_RECIPE = ("serve_queries(named_graph('large'), 512, seed=BASE_SEED+104, "
+                      "hmax=1e6)")
+
+
+def _load_fixture(name, recipe):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fixtures", name)
+    with open(path) as f:
+        doc = json.load(f)
+    if doc["recipe"] != recipe:
+        raise RuntimeError(f"{name} was drawn from another recipe; rerun make_fixtures")
+    return [Query.from_dict(d) for d in doc["queries"]], int(doc.get("rejected", 0))
+
+
 def load_large_cyclic():
     """The stored 50-query large-graph cyclic workload (written by
     kggen/make_fixtures.py from ``large_queries``)."""
-    import json
-    import os
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fixtures", "large_cyclic.json")
-    with open(path) as f:
-        doc = json.load(f)
-    if doc["recipe"] != LARGE_CYCLIC_RECIPE:
-        raise RuntimeError("large_cyclic.json was drawn from another recipe; rerun make_fixtures")
-    return [Query.from_dict(d) for d in doc["queries"]]
+    return _load_fixture("large_cyclic.json", LARGE_CYCLIC_RECIPE)[0]
+
+
+def load_large_batch(count: int = 1024):
+    """The stored 1,024-query mixed batch of the large graph (written by
+    kggen/make_fixtures.py from ``batch_queries``; the first ``count``, which
+    are what ``batch_queries(g, count)`` draws) and the rejection count."""
+    qs, rej = _load_fixture("large_batch.json", LARGE_BATCH_RECIPE)
+    if count > len(qs):
+        raise ValueError(f"the stored batch holds {len(qs)} queries")
+    return qs[:count], rej
+
+
+def load_large_serve(count: int = 512):
+    """The stored 512 served-stream queries of the large graph (written by
+    kggen/make_fixtures.py from ``serve_queries``; the first ``count``)."""
+    qs, rej = _load_fixture("large_serve.json", LARGE_SERVE_RECIPE)
+    if count > len(qs):
+        raise ValueError(f"the stored serve set holds {len(qs)} queries")
+    return qs[:count], rej
 
 
 def large_queries(g: KG, count: int = 50, seed: int = BASE_SEED + 2 + 100,
