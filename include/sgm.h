@@ -238,7 +238,8 @@ int sgm_trace_events(sgm_graph *g, int32_t i, int64_t *out, int32_t cap, double 
 /*
  * Work division and join schedule of the persistent kernel (the batched
  * form). Results never depend on these; speed does. Defaults: slots 512,
- * group_lanes 64, wg_rows 8192, join_policy 0, help_items 1024, helpers 64.
+ * group_lanes 64, wg_rows 8192, join_policy 0, help_items 1024, helpers 64,
+ * help_wait 0.
  *   slots        workgroups of one persistent launch that take queries
  *                (1..512; two per CU fit)
  *   group_lanes  most lanes working on one candidate's rows (1, 2, 4, ..., 64)
@@ -255,6 +256,14 @@ int sgm_trace_events(sgm_graph *g, int32_t i, int64_t *out, int32_t cap, double 
  *   helpers      a launch with fewer queries than this adds workgroups that
  *                only help, up to this many workgroups in all (0..512; used
  *                only with help_items > 0; the served form adds none)
+ *   help_wait    polls of a shared step's completion count before its owner
+ *                gives up (0: the default, 4,194,304; >= 0). Giving up is an
+ *                error path (claimed chunks always finish in bounded time):
+ *                the query is rerun outside the launch's regular slots, and
+ *                the slot takes no further query in that launch, since
+ *                chunks its helpers claimed may still write it; the next
+ *                launch clears the whole slot first. Small values exercise
+ *                that path in tests.
  * The multi-kernel path keeps the thesis order.
  */
 typedef struct {
@@ -264,7 +273,8 @@ typedef struct {
     int32_t join_policy;
     int32_t help_items;
     int32_t helpers;
-    int32_t reserved[2];
+    int32_t help_wait;
+    int32_t reserved[1];
 } sgm_tuning;
 
 void sgm_default_tuning(sgm_tuning *t);
@@ -312,6 +322,30 @@ int sgm_plan_query(const sgm_query *q, int32_t n_vertices, const int64_t *type_f
                    int32_t *parent_edge, int32_t *init_order);
 
 /*
+ * Admission estimate of the served form, on the host only (no device
+ * needed): estimated device bytes of a query's intermediate tables. The
+ * thesis ties the join's running time and partial-solution memory to
+ * candidate counts (Ch. 3, Sec. "Joining Phase"); this estimate takes that
+ * dependence from graph statistics alone. Along the spanning tree of the
+ * query plan (as sgm_plan_query), in the order vertices enter it: the root
+ * starts with the number of data vertices its label admits (1 if pinned, V
+ * for any type); a vertex reached over a tree edge of relation r multiplies
+ * the rows by rel_freq[r] / V (E / V for a variable edge) and by the
+ * fraction of data vertices its label admits (1 / V if pinned); each further
+ * query edge between placed vertices multiplies by min(1, that per-vertex
+ * edge count / V). Level k's table has k + 1 int32 columns, and a level's
+ * input and output tables count together; the estimate is the largest such
+ * pair plus one V-bit candidate bitmap per query vertex.
+ *   type_freq[n_types]: data vertices per type;
+ *   rel_freq[n_rels]:   data edges per relation (after dropping duplicate
+ *                       triples); n_edges = their sum.
+ * Errors as for sgm_match_query's query checks; SGM_EINVAL for bad sizes.
+ */
+int sgm_estimate_query(const sgm_query *q, int32_t n_vertices, int64_t n_edges,
+                       const int64_t *type_freq, int32_t n_types, const int64_t *rel_freq,
+                       int32_t n_rels, int64_t *est_bytes);
+
+/*
  * Verification entry point: the candidate set of every query vertex after
  * the filtering phase (thesis Alg. 3.2 initialisation along the plan's
  * spanning tree, then the configured refinement, Sec. "Candidate Nodes
@@ -342,7 +376,8 @@ typedef struct {
     int32_t max_batch;            /* queries per batch (default 256) */
     int64_t max_wait_ns;          /* a batch closes this long after its first
                                      query arrived (default 100 us) */
-    int64_t admission_cap_bytes;  /* estimated intermediate bytes of admitted,
+    int64_t admission_cap_bytes;  /* cap on the summed admission estimates
+                                     (sgm_estimate_query) of admitted,
                                      unfinished queries (default 64 GiB); one
                                      query is always admitted when none runs */
     int32_t reserved[8];
@@ -358,7 +393,12 @@ typedef struct {
 void sgm_default_serve_options(sgm_serve_options *o);
 
 /* Start a server on g (g must outlive it). Errors: SGM_EINVAL, SGM_ENOMEM,
- * SGM_EDEVICE. The server owns its streams and two host threads. */
+ * SGM_EDEVICE. The server owns its streams and its host threads: a
+ * dispatcher (batching and admission), one completer per stream (each
+ * completes the batch of its stream as soon as that batch ends, whatever
+ * runs on the others) and a rerun thread (queries that outgrew their slot
+ * run again in a large slot or on the multi-kernel path without holding up
+ * the completers). */
 int sgm_server_create(sgm_graph *g, const sgm_serve_options *opts, sgm_server **out);
 
 /* Queue one query (copied; the caller may free it on return); *ticket

@@ -85,9 +85,10 @@ class sgm_tuning(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("group_lanes", ctypes.c_int32),
                 ("wg_rows", ctypes.c_int32), ("join_policy", ctypes.c_int32),
                 ("help_items", ctypes.c_int32), ("helpers", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("help_wait", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
-TUNING_FIELDS = ("slots", "group_lanes", "wg_rows", "join_policy", "help_items", "helpers")
+TUNING_FIELDS = ("slots", "group_lanes", "wg_rows", "join_policy", "help_items", "helpers",
+                 "help_wait")
 
 
 class sgm_kstat(ctypes.Structure):
@@ -119,6 +120,8 @@ EXPORTS = {
     "sgm_reset_kernel_stats": (ctypes.c_int, [ctypes.c_void_p]),
     "sgm_plan_query": (ctypes.c_int, [ctypes.POINTER(sgm_query), ctypes.c_int32, _i64p,
                                       ctypes.c_int32, _i32p, _i32p, _i32p, _i32p]),
+    "sgm_estimate_query": (ctypes.c_int, [ctypes.POINTER(sgm_query), ctypes.c_int32, ctypes.c_int64,
+                                          _i64p, ctypes.c_int32, _i64p, ctypes.c_int32, _i64p]),
     "sgm_inspect_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query), _i64p,
                                          ctypes.POINTER(_i32p), _i64p]),
     "sgm_free_ids": (None, [_i32p]),
@@ -245,6 +248,20 @@ def sgm_plan_query(n, vlabel, vpin, esrc, edst, elabel, n_vertices, type_freq):
     vo, par, pe, io = outs
     return dict(visit_order=[int(x) for x in vo if x >= 0], parent=par[:n].tolist(),
                 parent_edge=pe[:n].tolist(), init_order=[int(x) for x in io if x >= 0])
+
+
+def sgm_estimate_query(n, vlabel, vpin, esrc, edst, elabel, n_vertices, type_freq, rel_freq):
+    """Host-only admission estimate of the served form (bytes)."""
+    q, keep = _make_query(n, vlabel, vpin, esrc, edst, elabel)
+    tf = np.ascontiguousarray(np.asarray(type_freq, np.int64))
+    rf = np.ascontiguousarray(np.asarray(rel_freq, np.int64))
+    est = ctypes.c_int64(0)
+    rc = lib().sgm_estimate_query(ctypes.byref(q), int(n_vertices), int(rf.sum()),
+                                  tf.ctypes.data_as(_i64p), int(len(tf)), rf.ctypes.data_as(_i64p),
+                                  int(len(rf)), ctypes.byref(est))
+    if rc != SGM_OK:
+        raise SGMError(rc, "sgm_estimate_query")
+    return int(est.value)
 
 
 # --- numpy convenience ----------------------------------------------------------------

@@ -217,6 +217,8 @@ struct sgm_graph {
     std::vector<int32_t> trace_n;
     int32_t n_types = 0;
     std::vector<int64_t> type_freq;
+    int32_t n_rels = 0;
+    std::vector<int64_t> rel_freq;  // edges per relation (after dedupe)
     DevGraph dg{};
     // device memory owned by the graph
     int32_t *d_out_off = nullptr, *d_in_off = nullptr;
@@ -252,7 +254,7 @@ struct sgm_graph {
     // persistent per-query kernel on the graph's own stream
     NarrowCtx nw;
     NarrowCtx nwb;  // few large slots for queries that outgrow a regular one
-    sgm_tuning tune{512, 64, 8192, 0, 1024, 64, {0, 0}};
+    sgm_tuning tune{512, 64, 8192, 0, 1024, 64, 0, {0}};
 };
 
 namespace {
@@ -1234,14 +1236,6 @@ void narrow_reserve(sgm_graph *g, NarrowCtx &nw, int slots, int nq, int nroot) {
     }
 }
 
-// Device memory one persistent-kernel slot holds while a query runs in it:
-// the unit of the served form's admission control.
-int64_t narrow_slot_bytes(const sgm_graph *g) {
-    const int64_t lcap = std::min<int32_t>(g->V, kNarrowListCap);
-    return (int64_t)(SGM_MAX_QV + 1) * g->nwords * 8 + (int64_t)SGM_MAX_QV * lcap * 4 +
-           narrow_slab_bytes(g);
-}
-
 // Pack one validated query and its plan; false if it exceeds the packed
 // descriptor's capacity (the query then runs on the multi-kernel path).
 bool pack_query(sgm_graph *g, const QInfo &qi, const Plan &pl, NQuery *nq, int *root_slot_next,
@@ -1412,6 +1406,7 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     a.help_items = help ? g->tune.help_items : 0;
     a.board = nw.d_board;
     a.hctr = (int32_t *)(nw.d_ctr + 2);
+    a.help_wait = g->tune.help_wait > 0 ? g->tune.help_wait : kHelpWaitDefault;
     const int grid =
         help ? std::min(kNarrowMaxSlots, std::max(slot_grid, g->tune.helpers)) : slot_grid;
     a.ngrid = grid;
@@ -1775,6 +1770,11 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
     g->n_types = maxt + 1;
     g->type_freq.assign((size_t)g->n_types, 0);
     for (int32_t v = 0; v < n_vertices; ++v) g->type_freq[type[v]]++;
+    int32_t maxr = -1;
+    for (const int2 &e : adj) maxr = std::max(maxr, e.y);
+    g->n_rels = maxr + 1;
+    g->rel_freq.assign((size_t)g->n_rels, 0);
+    for (const int2 &e : adj) g->rel_freq[e.y]++;
     int nbig = 0;
     for (int32_t v = 0; v < n_vertices; ++v) {
         const int32_t od = off[v + 1] - off[v], id = in_off[v + 1] - in_off[v];
@@ -1839,7 +1839,7 @@ void sgm_free_graph(sgm_graph *g) {
 
 void sgm_default_tuning(sgm_tuning *t) {
     if (!t) return;
-    *t = sgm_tuning{512, 64, 8192, 0, 1024, 64, {0, 0}};
+    *t = sgm_tuning{512, 64, 8192, 0, 1024, 64, 0, {0}};
 }
 
 int sgm_get_tuning(const sgm_graph *g, sgm_tuning *t) {
@@ -1852,14 +1852,15 @@ static bool tuning_ok(const sgm_tuning &t) {
     const bool pow2 = t.group_lanes > 0 && (t.group_lanes & (t.group_lanes - 1)) == 0;
     return t.slots >= 1 && t.slots <= 512 && pow2 && t.group_lanes <= 64 && t.wg_rows >= 64 &&
            (t.join_policy == 0 || t.join_policy == 1) &&
-           (t.help_items == 0 || t.help_items >= 64) && t.helpers >= 0 && t.helpers <= 512;
+           (t.help_items == 0 || t.help_items >= 64) && t.helpers >= 0 && t.helpers <= 512 &&
+           t.help_wait >= 0;
 }
 
 int sgm_set_tuning(sgm_graph *g, const sgm_tuning *t) {
     if (!g || !t || !tuning_ok(*t)) return SGM_EINVAL;
     std::lock_guard<std::mutex> lk(g->mu);
     g->tune = *t;
-    g->tune.reserved[0] = g->tune.reserved[1] = 0;
+    g->tune.reserved[0] = 0;
     return SGM_OK;
 }
 
@@ -1879,7 +1880,8 @@ int sgm_autotune(sgm_graph *g, const sgm_query *qs, int32_t n, int32_t reps, sgm
             for (int wr : {2048, 8192, 32768})
                 for (int jp : {0, 1})
                     for (int hi : {0, 1024})
-                        grid.push_back(sgm_tuning{sl, gl, wr, jp, hi, saved.helpers, {0, 0}});
+                        grid.push_back(
+                            sgm_tuning{sl, gl, wr, jp, hi, saved.helpers, saved.help_wait, {0}});
     std::vector<sgm_result> store((size_t)n);
     std::vector<sgm_result *> res((size_t)n);
     for (int i = 0; i < n; ++i) res[i] = &store[i];
@@ -2075,15 +2077,13 @@ int sgm_reset_kernel_stats(sgm_graph *g) {
 struct sgm_server {
     sgm_graph *g = nullptr;
     sgm_serve_options o{};
-    int64_t slot_bytes = 0;
     std::vector<NarrowCtx> ctx;
-    std::vector<char> ctx_busy;
     struct Ticket {
         QInfo qi;
         int status = SGM_OK;  // of the query check
         uint32_t flags = 0;
         int64_t t_submit = 0, t_done = 0;
-        int64_t est = 0;
+        int64_t est = 0;      // admission estimate (estimate_bytes)
         sgm_result *res = nullptr;
         bool done = false;
     };
@@ -2092,27 +2092,44 @@ struct sgm_server {
         std::vector<uint64_t> ids;
         std::vector<QInfo> qis;
         std::vector<sgm_result *> res;
+        std::vector<int64_t> est;
         std::vector<int> which, wide;
         NarrowJob job;
         bool launched = false;
-        int64_t est = 0;
         uint32_t flags = 0;
     };
+    // a query that outgrew its slot, waiting for the rerun thread
+    struct Rerun {
+        uint64_t id;
+        QInfo qi;
+        sgm_result *res;
+        uint32_t flags;
+        int64_t est;
+    };
     std::mutex mu;
-    std::condition_variable cv_in, cv_out, cv_ctx, cv_done;
+    std::condition_variable cv_in, cv_out, cv_ctx, cv_done, cv_rerun;
     std::deque<uint64_t> pending;
     std::unordered_map<uint64_t, Ticket> tickets;
-    std::deque<Batch *> inflight;
+    std::vector<char> ctx_busy;   // a batch is being launched or runs on the context
+    std::vector<Batch *> on_ctx;  // launched batch of each context, for its completer
+    std::deque<Rerun> reruns;
     uint64_t next_id = 1;
     int64_t bytes_in_flight = 0, queries_in_flight = 0;
     bool stop = false;
     bool dispatcher_done = false;
+    int completers_left = 0;
     sgm_serve_stats st{};
-    std::thread dispatcher, completer;
+    std::thread dispatcher, rerunner;
+    std::vector<std::thread> completers;
 };
 
 namespace {
 
+// Dispatcher: closes a micro-batch (max_batch queries, or max_wait_ns after
+// its first query arrived), takes a free stream context, admits queries in
+// arrival order while the admission estimates of everything admitted and
+// unfinished stay under the cap (one query is always admitted when nothing
+// runs), and launches the batch; batches on other contexts keep running.
 void serve_dispatch(sgm_server *S) {
     sgm_graph *g = S->g;
     (void)hipSetDevice(g->device);
@@ -2134,40 +2151,40 @@ void serve_dispatch(sgm_server *S) {
         // a free stream context
         int ci = -1;
         S->cv_ctx.wait(lk, [&] {
-            for (size_t i = 0; i < S->ctx.size(); ++i)
+            for (size_t i = 0; i < S->ctx_busy.size(); ++i)
                 if (!S->ctx_busy[i]) {
                     ci = (int)i;
                     return true;
                 }
             return false;
         });
-        // admission: estimated intermediate bytes against the cap; the flags
-        // of a batch are those of its first query
+        // admission; the flags of a batch are those of its first query
         sgm_server::Batch *b = new sgm_server::Batch();
         b->ctx = ci;
         b->flags = S->tickets[S->pending.front()].flags;
         bool stalled = false;
+        int64_t add = 0;
         while (!S->pending.empty() && (int)b->ids.size() < S->o.max_batch) {
             sgm_server::Ticket &t = S->tickets[S->pending.front()];
             if (t.flags != b->flags) break;
             const bool nothing_running = S->queries_in_flight == 0 && b->ids.empty();
-            if (!nothing_running && S->bytes_in_flight + b->est + t.est > S->o.admission_cap_bytes) {
+            if (!nothing_running && S->bytes_in_flight + add + t.est > S->o.admission_cap_bytes) {
                 stalled = true;
                 break;
             }
             b->ids.push_back(S->pending.front());
-            b->est += t.est;
+            add += t.est;
             S->pending.pop_front();
         }
         if (stalled) S->st.admission_stalls++;
         if (b->ids.empty()) {
             delete b;
-            // wait for running work to free memory
+            // wait for running work to release its estimate
             S->cv_done.wait(lk);
             continue;
         }
         S->ctx_busy[ci] = 1;
-        S->bytes_in_flight += b->est;
+        S->bytes_in_flight += add;
         S->queries_in_flight += (int64_t)b->ids.size();
         S->st.max_in_flight = std::max(S->st.max_in_flight, S->queries_in_flight);
         S->st.batches++;
@@ -2175,6 +2192,7 @@ void serve_dispatch(sgm_server *S) {
             sgm_server::Ticket &t = S->tickets[id];
             b->qis.push_back(t.qi);
             b->res.push_back(t.res);
+            b->est.push_back(t.est);
         }
         lk.unlock();
         for (size_t i = 0; i < b->ids.size(); ++i)
@@ -2189,28 +2207,51 @@ void serve_dispatch(sgm_server *S) {
             b->launched = false;
         }
         lk.lock();
-        S->inflight.push_back(b);
-        S->cv_out.notify_one();
+        S->on_ctx[ci] = b;
+        S->cv_out.notify_all();
     }
     S->dispatcher_done = true;
     S->cv_out.notify_all();
 }
 
-void serve_complete(sgm_server *S) {
+// Mark ticket id done at t_done (caller holds S->mu) and release its
+// estimate.
+void serve_finish(sgm_server *S, uint64_t id, int64_t est, int64_t t_done) {
+    auto it = S->tickets.find(id);
+    sgm_server::Ticket &t = it->second;
+    t.t_done = t_done;
+    t.done = true;
+    sgm_result *r = t.res;
+    if (r->status != SGM_OK && r->status != SGM_ETOOBIG) {
+        std::free(r->rows);
+        r->rows = nullptr;
+    }
+    r->stats.ns_total = t_done - t.t_submit;
+    S->st.completed++;
+    S->bytes_in_flight -= est;
+    S->queries_in_flight--;
+}
+
+// Completer of context ci: waits for the batch launched there (its own
+// stream and event), completes its finished queries at once, hands the ones
+// that outgrew their slot to the rerun thread and frees the context. Each
+// context has its own completer, so a batch that ends early is completed
+// while a longer one still runs on another stream.
+void serve_complete(sgm_server *S, int ci) {
     sgm_graph *g = S->g;
     (void)hipSetDevice(g->device);
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
-        S->cv_out.wait(lk, [&] { return !S->inflight.empty() || S->dispatcher_done; });
-        if (S->inflight.empty()) {
+        S->cv_out.wait(lk, [&] { return S->on_ctx[ci] != nullptr || S->dispatcher_done; });
+        sgm_server::Batch *b = S->on_ctx[ci];
+        if (!b) {
             if (S->dispatcher_done) break;
             continue;
         }
-        sgm_server::Batch *b = S->inflight.front();
         lk.unlock();
         try {
             if (b->launched)
-                narrow_collect(g, S->ctx[b->ctx], b->job, b->qis, b->flags, b->res, b->wide, false);
+                narrow_collect(g, S->ctx[ci], b->job, b->qis, b->flags, b->res, b->wide, false);
         } catch (const DeviceError &e) {
             for (int i : b->which) b->res[i]->status = e.code;
             b->wide.clear();
@@ -2218,49 +2259,82 @@ void serve_complete(sgm_server *S) {
             for (int i : b->which) b->res[i]->status = SGM_ENOMEM;
             b->wide.clear();
         }
-        // queries that outgrew their slot: a large slot, then the
-        // multi-kernel path
-        if (!b->wide.empty()) {
+        const int64_t t_done = now_ns();
+        std::vector<char> rerun(b->ids.size(), 0);
+        for (int i : b->wide) rerun[(size_t)i] = 1;
+        lk.lock();
+        for (size_t i = 0; i < b->ids.size(); ++i) {
+            if (rerun[i])
+                S->reruns.push_back(
+                    sgm_server::Rerun{b->ids[i], b->qis[i], b->res[i], b->flags, b->est[i]});
+            else
+                serve_finish(S, b->ids[i], b->est[i], t_done);
+        }
+        S->on_ctx[ci] = nullptr;
+        S->ctx_busy[ci] = 0;
+        delete b;
+        S->cv_ctx.notify_all();
+        S->cv_done.notify_all();
+        S->cv_rerun.notify_one();
+    }
+    if (--S->completers_left == 0) S->cv_rerun.notify_all();
+}
+
+// Rerun thread: queries that outgrew a regular slot run again in a large
+// slot, then on the multi-kernel path, on the graph's own stream, so the
+// completers never wait for them.
+void serve_rerun(sgm_server *S) {
+    sgm_graph *g = S->g;
+    (void)hipSetDevice(g->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        S->cv_rerun.wait(lk, [&] { return !S->reruns.empty() || S->completers_left == 0; });
+        if (S->reruns.empty()) {
+            if (S->completers_left == 0) break;
+            continue;
+        }
+        // every waiting query with the flags of the first
+        const uint32_t flags = S->reruns.front().flags;
+        std::vector<sgm_server::Rerun> take;
+        for (auto it = S->reruns.begin(); it != S->reruns.end();) {
+            if (it->flags == flags) {
+                take.push_back(*it);
+                it = S->reruns.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        lk.unlock();
+        std::vector<QInfo> qis;
+        std::vector<sgm_result *> res;
+        std::vector<int> wide;
+        for (size_t i = 0; i < take.size(); ++i) {
+            qis.push_back(take[i].qi);
+            res.push_back(take[i].res);
+            wide.push_back((int)i);
+        }
+        {
             std::lock_guard<std::mutex> gl(g->mu);
             try {
-                narrow_retry_large(g, b->qis, b->flags, b->res, b->wide);
+                narrow_retry_large(g, qis, flags, res, wide);
             } catch (const DeviceError &e) {
                 (void)hipStreamSynchronize(g->stream);
                 (void)hipGetLastError();
                 g->pending.clear();
             } catch (const std::bad_alloc &) {
             }
-        }
-        for (int i : b->wide) {
-            std::lock_guard<std::mutex> gl(g->mu);
-            const int32_t why = b->res[i]->stats.fallback;
-            std::memset(&b->res[i]->stats, 0, sizeof(sgm_stats));
-            b->res[i]->stats.path = SGM_PATH_WIDE;
-            b->res[i]->stats.fallback = why;
-            b->res[i]->status = wide_locked(g, b->qis[i], b->flags, b->res[i]);
+            for (int i : wide) {
+                const int32_t why = res[i]->stats.fallback;
+                std::memset(&res[i]->stats, 0, sizeof(sgm_stats));
+                res[i]->stats.path = SGM_PATH_WIDE;
+                res[i]->stats.fallback = why;
+                res[i]->status = wide_locked(g, qis[i], flags, res[i]);
+            }
         }
         const int64_t t_done = now_ns();
         lk.lock();
-        S->st.wide_fallbacks += (int64_t)b->wide.size();
-        for (size_t i = 0; i < b->ids.size(); ++i) {
-            auto it = S->tickets.find(b->ids[i]);
-            sgm_server::Ticket &t = it->second;
-            t.t_done = t_done;
-            t.done = true;
-            sgm_result *r = t.res;
-            if (r->status != SGM_OK && r->status != SGM_ETOOBIG) {
-                std::free(r->rows);
-                r->rows = nullptr;
-            }
-            r->stats.ns_total = t_done - t.t_submit;
-        }
-        S->st.completed += (int64_t)b->ids.size();
-        S->bytes_in_flight -= b->est;
-        S->queries_in_flight -= (int64_t)b->ids.size();
-        S->ctx_busy[b->ctx] = 0;
-        S->inflight.pop_front();
-        delete b;
-        S->cv_ctx.notify_all();
+        S->st.wide_fallbacks += (int64_t)wide.size();
+        for (const auto &r : take) serve_finish(S, r.id, r.est, t_done);
         S->cv_done.notify_all();
     }
 }
@@ -2292,8 +2366,8 @@ int sgm_server_create(sgm_graph *g, const sgm_serve_options *opts, sgm_server **
     if (!S) return SGM_ENOMEM;
     S->g = g;
     S->o = o;
-    S->slot_bytes = narrow_slot_bytes(g);
     S->ctx.resize((size_t)o.streams);
+    S->on_ctx.assign((size_t)o.streams, nullptr);
     S->ctx_busy.assign((size_t)o.streams, 0);
     try {
         HIPX(hipSetDevice(g->device));
@@ -2310,8 +2384,10 @@ int sgm_server_create(sgm_graph *g, const sgm_serve_options *opts, sgm_server **
         delete S;
         return e.code;
     }
+    S->completers_left = o.streams;
     S->dispatcher = std::thread(serve_dispatch, S);
-    S->completer = std::thread(serve_complete, S);
+    for (int i = 0; i < o.streams; ++i) S->completers.emplace_back(serve_complete, S, i);
+    S->rerunner = std::thread(serve_rerun, S);
     *out = S;
     return SGM_OK;
 }
@@ -2325,7 +2401,13 @@ int sgm_submit(sgm_server *s, const sgm_query *q, uint32_t flags, uint64_t *tick
     res->status = t.status;
     t.flags = flags;
     t.res = res;
-    t.est = s->slot_bytes;
+    if (t.status == SGM_OK) {
+        Plan pl;
+        const sgm_graph *g = s->g;
+        if (make_plan(t.qi, g->V, g->type_freq.data(), g->n_types, &pl) == SGM_OK)
+            t.est = estimate_bytes(t.qi, pl, g->V, g->E, g->type_freq.data(), g->n_types,
+                                   g->rel_freq.data(), g->n_rels);
+    }
     t.t_submit = now_ns();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) {
@@ -2387,7 +2469,13 @@ void sgm_server_destroy(sgm_server *s) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->cv_out.notify_all();
     }
-    if (s->completer.joinable()) s->completer.join();
+    for (auto &t : s->completers)
+        if (t.joinable()) t.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->cv_rerun.notify_all();
+    }
+    if (s->rerunner.joinable()) s->rerunner.join();
     (void)hipSetDevice(s->g->device);
     for (auto &c : s->ctx) {
         narrow_free(c);

@@ -71,6 +71,9 @@ constexpr int32_t kWhyHelp = 8;   // shared filter step not finished by its help
 // A join level whose pairs (an upper bound on its rows) would need more than
 // this many times the slab left stops at once instead of filling the slab.
 constexpr int64_t kPairSlack = 8;
+// Polls of a shared step's completion count before its owner gives up
+// (sgm_tuning.help_wait = 0).
+constexpr int64_t kHelpWaitDefault = 1ll << 22;
 
 // One filter step shared by several workgroups: the owner of a query posts
 // the step here, and idle workgroups of the same launch claim chunks of its
@@ -87,6 +90,11 @@ struct HelpJob {
     int32_t n_items, G, ncount, revd;
     NStep st;
     int32_t nbig, removed, nmarks, abort_;
+    // 1 after the owner gave up on a step whose claimed chunks had not all
+    // been reported: helpers may still write the slot's bitmaps, so its
+    // workgroup takes no more queries in that launch and the next launch
+    // clears the whole slot before using it
+    int32_t dirty;
     int32_t cnt[SGM_MAX_QV];
     NNbr nbl[SGM_MAX_QE];
 };
@@ -120,6 +128,7 @@ struct NArgs {
     int32_t help_items;
     HelpJob *board;           // [nslot]
     int32_t *hctr;            // [0] posted steps, [1] slot workgroups done
+    int64_t help_wait;        // polls of a shared step's completion before its owner gives up
 };
 
 // Root sweep: rootbits[j][w] = vertices satisfying predicate j, for the

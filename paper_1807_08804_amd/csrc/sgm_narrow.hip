@@ -62,6 +62,7 @@ struct Smem {
     int32_t nnbl;
     int32_t nmarks;
     int32_t ndef;  // candidates whose pushes go to row segments
+    int32_t retired;  // this slot gave up on a shared step (see HelpJob::dirty)
     unsigned long long rowhit;  // item_wg: listed rows with a matching entry
     unsigned long long hseq;    // sequence number of the step this workgroup posted
     int32_t hq, hch;            // helper: board entry and chunk claimed (-1: none)
@@ -123,6 +124,7 @@ struct Ctx {
     int32_t help_items; // share filter steps of at least this many candidates (0: never)
     int32_t q;          // index of the query in the batch
     int32_t nslot, ngrid;  // slot workgroups, all workgroups of the launch
+    int64_t help_wait;  // polls of a shared step's completion before giving up
     __device__ uint64_t *B(int u) const { return bits + (int64_t)u * g.nwords; }
     __device__ int32_t *L(int u) const { return lists + (int64_t)u * lcap; }
 };
@@ -731,11 +733,11 @@ __device__ __forceinline__ void filter_items(Ctx &c, const K &k, bool push, cons
     }
 }
 
-// Polls of a posted step's completion count before its owner gives up (an
-// error: every claimed chunk finishes in bounded time), and empty polls in
-// a row before a helper leaves (helping is optional, so leaving early only
-// costs speed; about a second of polling).
-constexpr int64_t kHelpWait = 1ll << 22;
+// Empty polls in a row before a helper leaves (helping is optional, so
+// leaving early only costs speed; about a second of polling). The owner of
+// a shared step polls its completion count at most NArgs::help_wait times
+// (default 4M) before it gives up: an error, since every claimed chunk
+// finishes in bounded time.
 constexpr int64_t kHelpIdle = 1ll << 20;
 
 // Claim word of a posted step, and a claim's outcome.
@@ -886,10 +888,21 @@ __device__ __forceinline__ void shared_job(Ctx &c, int kind, const NStep &st, co
         // the owner's own chunks need no fence: it reads them itself
         int32_t got = atomicAdd(&j->done, own) + own;
         int64_t n = 0;
-        while (got < nch && n < kHelpWait) {
+        while (got < nch && n < c.help_wait) {
             __builtin_amdgcn_s_sleep(1);
             got = __hip_atomic_load(&j->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ++n;
+        }
+        if (got < nch) {
+            // give up: no further claims on the step (a claim against zero
+            // chunks fails), and the slot stays out of use until the next
+            // launch clears it, since chunks claimed earlier may still write
+            // its bitmaps and lists
+            const uint32_t seq = claim_seq(
+                __hip_atomic_load(&j->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            atomicExch(&j->claim, claim_word(seq, 0));
+            atomicExch(&j->dirty, 1);
+            c.s->retired = 1;
         }
         __threadfence();
         atomicSub(&c.hctr[0], 1);
@@ -2174,7 +2187,7 @@ __device__ __forceinline__ Ctx slot_ctx(const NArgs &a, Smem &s, unsigned char *
                // while filtering the slab holds the long-row overflow list in
                // [0, 4 lcap) bytes and the marks in [4 lcap, 8 lcap)
                (int32_t *)(slab + 4 * (int64_t)a.lcap), a.board ? a.board + slot : nullptr, a.hctr,
-               a.help_items, q, a.nslot, a.ngrid};
+               a.help_items, q, a.nslot, a.ngrid, a.help_wait};
 }
 
 // Chunks of the step posted on board entry e, starting with chunk ch, until
@@ -2302,6 +2315,25 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
         if (help) help_loop(a, s, dyn);
         return;
     }
+    if (threadIdx.x == 0) {
+        s.retired = 0;
+        s.hq = a.board ? __hip_atomic_load(&a.board[blockIdx.x].dirty, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT)
+                       : 0;
+    }
+    __syncthreads();
+    if (s.hq) {
+        // an earlier launch left this slot after giving up on a shared step
+        // (helpers may have written any of its bitmaps since): clear it all
+        uint64_t *bits = a.bits + (int64_t)blockIdx.x * (SGM_MAX_QV + 1) * a.g.nwords;
+        const int64_t nb = (int64_t)(SGM_MAX_QV + 1) * a.g.nwords;
+        for (int64_t w = threadIdx.x; w < nb; w += NT) bits[w] = 0ull;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            atomicExch(&a.board[blockIdx.x].dirty, 0);
+        }
+    }
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s.q = atomicAdd(a.queue, 1);
@@ -2310,6 +2342,26 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
         if (q >= a.nq) break;
         const NQuery &Q = a.qs[q];
         NResult &R = a.res[q];
+        if (s.retired) {
+            // the slot is out of use: the query is reported for a rerun
+            if (threadIdx.x == 0) {
+                R.status = kNeedWide;
+                R.reason = kWhyHelp;
+                R.n_cols = Q.n;
+                R.n_rows = 0;
+                R.offset = 0;
+                for (int u = 0; u < SGM_MAX_QV; ++u) {
+                    R.cand[u] = 0;
+                    R.level_rows[u] = 0;
+                    R.join_order[u] = -1;
+                }
+                for (int e = 0; e < SGM_MAX_QE; ++e) R.ec[e] = 0;
+                R.bytes = 0;
+                R.need = 0;
+                for (int i = 0; i < 4; ++i) R.ticks[i] = 0;
+            }
+            continue;
+        }
         Ctx c = slot_ctx(a, s, dyn, blockIdx.x, q);
         if (threadIdx.x == 0) s.nev = 0;
         run_query(c);

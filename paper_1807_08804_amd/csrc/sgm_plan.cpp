@@ -9,6 +9,7 @@
 #include "sgm_plan.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 namespace sgm {
@@ -218,6 +219,78 @@ void build_program(const QInfo &qi, const Plan &pl, int low_conn_degree, int ref
 }
 
 }  // namespace sgm
+
+namespace sgm {
+
+// Rows of the join levels estimated along the spanning tree of the plan, in
+// the order its vertices enter the tree: the root starts with as many rows
+// as it has candidates by label (1 if pinned); a vertex reached over a tree
+// edge of relation r multiplies the rows by the average number of r-edges
+// per data vertex and by the fraction of data vertices its label admits (1/V
+// if pinned); every further query edge between vertices already placed
+// multiplies them by the chance that a given ordered pair carries such an
+// edge. Level k's table holds k + 1 int32 columns; a level's input and
+// output tables are live together. The thesis ties the join's running time
+// and partial-solution memory to candidate counts (Sec. "Joining Phase");
+// this is the cheap, graph-statistics form of that dependence.
+int64_t estimate_bytes(const QInfo &qi, const Plan &pl, int32_t V, int64_t E,
+                       const int64_t *type_freq, int32_t n_types, const int64_t *rel_freq,
+                       int32_t n_rels) {
+    const double dV = std::max<double>(V, 1);
+    auto admitted = [&](int u) -> double {
+        if (qi.pin[u] >= 0) return 1.0;
+        if (qi.label[u] < 0) return dV;
+        return qi.label[u] < n_types ? (double)type_freq[qi.label[u]] : 0.0;
+    };
+    auto per_vertex = [&](int32_t r) -> double {
+        const double cnt = r < 0 ? (double)E : (r < n_rels ? (double)rel_freq[r] : 0.0);
+        return cnt / dV;
+    };
+    bool placed[SGM_MAX_QV] = {};
+    double rows = 0, prev_bytes = 0, peak = 0;
+    for (int k = 0; k < pl.n_init; ++k) {
+        const int u = pl.init[k];
+        if (k == 0) {
+            rows = admitted(u);
+        } else {
+            const int e = pl.parent_edge[u];
+            rows *= per_vertex(qi.elabel[e]) * admitted(u) / dV;
+        }
+        placed[u] = true;
+        for (int i = 0; i < qi.m; ++i) {
+            if (k > 0 && i == pl.parent_edge[u]) continue;
+            const int a = qi.esrc[i], b = qi.edst[i];
+            if ((a == u && placed[b]) || (b == u && placed[a]))
+                rows *= std::min(1.0, per_vertex(qi.elabel[i]) / dV);
+        }
+        const double bytes = rows * 4.0 * (k + 1);
+        peak = std::max(peak, prev_bytes + bytes);
+        prev_bytes = bytes;
+    }
+    const double bitmaps = (double)qi.n * 8.0 * std::ceil(dV / 64.0);
+    const double est = bitmaps + peak;
+    return est >= 9.0e18 ? INT64_MAX : (int64_t)std::ceil(est);
+}
+
+}  // namespace sgm
+
+extern "C" int sgm_estimate_query(const sgm_query *q, int32_t n_vertices, int64_t n_edges,
+                                  const int64_t *type_freq, int32_t n_types,
+                                  const int64_t *rel_freq, int32_t n_rels, int64_t *est_bytes) {
+    if (!est_bytes || n_vertices < 1 || n_edges < 0 || n_types < 0 || n_rels < 0 ||
+        (n_types > 0 && !type_freq) || (n_rels > 0 && !rel_freq))
+        return SGM_EINVAL;
+    *est_bytes = 0;
+    sgm::QInfo qi;
+    int rc = sgm::check_query(q, n_vertices, &qi);
+    if (rc != SGM_OK) return rc;
+    sgm::Plan p;
+    rc = sgm::make_plan(qi, n_vertices, type_freq, n_types, &p);
+    if (rc != SGM_OK) return rc;
+    *est_bytes = sgm::estimate_bytes(qi, p, n_vertices, n_edges, type_freq, n_types, rel_freq,
+                                     n_rels);
+    return SGM_OK;
+}
 
 extern "C" int sgm_plan_query(const sgm_query *q, int32_t n_vertices, const int64_t *type_freq,
                               int32_t n_types, int32_t *visit_order, int32_t *parent,

@@ -51,6 +51,14 @@ struct Program {
 void build_program(const QInfo &qi, const Plan &pl, int low_conn_degree, int refine_reversed,
                    Program *pr);
 
+// Estimated device bytes of a query's intermediate tables (the served
+// form's admission unit): candidate bitmaps of its vertices plus the largest
+// pair of consecutive join tables, with the rows of each level estimated
+// along the plan's spanning tree under independence (see the definition).
+int64_t estimate_bytes(const QInfo &qi, const Plan &pl, int32_t V, int64_t E,
+                       const int64_t *type_freq, int32_t n_types, const int64_t *rel_freq,
+                       int32_t n_rels);
+
 // SGM_OK, SGM_EINVAL or SGM_EUNSUPPORTED (see sgm_match_query).
 int check_query(const sgm_query *q, int32_t V, QInfo *qi);
 int make_plan(const QInfo &qi, int32_t V, const int64_t *type_freq, int32_t n_types, Plan *p);

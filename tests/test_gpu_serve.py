@@ -75,6 +75,32 @@ def test_served_tiny_cap_and_errors(g_medium_s, medium_alone):
     assert st["admission_stalls"] >= 1
 
 
+def test_served_admission_cap_admits_some(g_medium_s, medium_kg, oracle_medium):
+    """Admission by per-query estimates (sgm_estimate_query): with a cap
+    worth about six typical queries, a burst of 100 queries runs several at
+    a time but never all at once (admission stalls occur), and every result
+    equals the oracle's."""
+    qs, _ = kggen.medium_queries(medium_kg, 100)
+    tf = np.bincount(medium_kg.vtype, minlength=64)
+    rf = np.bincount(medium_kg.rel, minlength=32)
+    est = np.array([P.sgm_estimate_query(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel,
+                                         medium_kg.V, tf, rf) for q in qs])
+    cap = int(6 * np.median(est))
+    say(f"case: admission cap {cap} bytes (estimates {est.min()}..{est.max()})")
+    srv = P.Server(g_medium_s, streams=4, max_batch=16, max_wait_ns=0, admission_cap_bytes=cap)
+    tickets = [srv.submit(q) for q in qs]
+    outs = [srv.wait(t, q.n) for t, q in zip(tickets, qs)]
+    st = srv.stats()
+    srv.close()
+    for q, (status, rows, _) in zip(qs, outs):
+        assert status == P.SGM_OK
+        same(rows, oracle_medium.match_query(q))
+    say(f"  stalls={st['admission_stalls']} max_in_flight={st['max_in_flight']} "
+        f"batches={st['batches']}")
+    assert st["admission_stalls"] > 0
+    assert 1 < st["max_in_flight"] < len(qs)
+
+
 def test_served_large_graph(large_kg_serve):
     """Walk queries on the 4M/20M graph at 5000 qps: served == alone."""
     g, qs, alone = large_kg_serve
@@ -91,6 +117,6 @@ def large_kg_serve():
     kg = kggen.named_graph("large")
     kg.ensure_in()
     g = P.Graph.from_kg(kg)
-    qs, _ = kggen.serve_queries(kg, 128)
+    qs, _ = kggen.load_large_serve(128)
     say("case: large serve set ready")
     return g, qs, [g.match_query(q) for q in qs]

@@ -31,10 +31,12 @@ def medium_set(medium_kg, oracle_medium):
 # the second and fourth share every filter step of 64 or more candidates
 # with helper workgroups (many helpers, and only three)
 TUNINGS = [
-    dict(slots=512, group_lanes=64, wg_rows=8192, join_policy=0, help_items=1024, helpers=64),
-    dict(slots=7, group_lanes=1, wg_rows=64, join_policy=1, help_items=64, helpers=512),
-    dict(slots=256, group_lanes=16, wg_rows=32768, join_policy=1, help_items=0, helpers=0),
-    dict(slots=1, group_lanes=4, wg_rows=2048, join_policy=0, help_items=64, helpers=3),
+    dict(slots=512, group_lanes=64, wg_rows=8192, join_policy=0, help_items=1024, helpers=64,
+         help_wait=0),
+    dict(slots=7, group_lanes=1, wg_rows=64, join_policy=1, help_items=64, helpers=512, help_wait=0),
+    dict(slots=256, group_lanes=16, wg_rows=32768, join_policy=1, help_items=0, helpers=0,
+         help_wait=0),
+    dict(slots=1, group_lanes=4, wg_rows=2048, join_policy=0, help_items=64, helpers=3, help_wait=0),
 ]
 
 
@@ -56,7 +58,7 @@ def test_tuning_validation(medium_kg):
     g = P.Graph.from_kg(medium_kg)
     for bad in (dict(slots=0), dict(slots=513), dict(group_lanes=3), dict(group_lanes=128),
                 dict(wg_rows=32), dict(join_policy=2), dict(help_items=63), dict(help_items=-1),
-                dict(helpers=-1), dict(helpers=513)):
+                dict(helpers=-1), dict(helpers=513), dict(help_wait=-1)):
         with pytest.raises(P.SGMError) as e:
             g.set_tuning(**bad)
         assert e.value.code == P.SGM_EINVAL
@@ -108,4 +110,39 @@ def test_candidates_match_oracle_filter(tune, medium_kg, medium_set, medium_filt
         assert st["cand"] == cnt, (i, st["cand"], cnt)
         if ec is not None:
             assert st["ec"] == ec, (i, st["ec"], ec)
+    g.close()
+
+
+def test_helper_give_up_retires_slot(medium_kg, medium_set):
+    """The owner of a shared step may give up waiting for its helpers (an
+    error path, forced here from the host with a wait bound of one poll, so
+    every kernel still exits normally). Such a query is rerun outside the
+    launch's slots, its slot takes no further query in that launch (helpers
+    may still be writing it) and the next launch clears the slot before use.
+    Every table of this launch and of the following ones, on the same slots,
+    equals the oracle's."""
+    qs, want = medium_set
+    say("case: shared steps given up after one poll")
+    g = P.Graph.from_kg(medium_kg)
+    g.set_tuning(slots=8, group_lanes=64, wg_rows=8192, join_policy=0, help_items=64,
+                 helpers=512, help_wait=1)
+    gave_up = 0
+    for rep in range(3):
+        got, stats = g.match_batch(qs, with_stats=True)
+        for i, (r, w) in enumerate(zip(got, want)):
+            same(r, w)
+        gave_up += sum(st["fallback"] == 32 for st in stats)
+        say(f"  launch {rep}: {sum(st['fallback'] == 32 for st in stats)} queries rerun")
+    # single queries: one slot and many helper workgroups
+    for q, w in zip(qs[:10], want[:10]):
+        same(g.match_query(q), w)
+    # back to the default wait: the slots left dirty are cleared and reused
+    g.set_tuning(help_wait=0)
+    for rep in range(2):
+        got, stats = g.match_batch(qs, with_stats=True)
+        for r, w in zip(got, want):
+            same(r, w)
+        assert not any(st["fallback"] == 32 for st in stats)
+    say(f"  {gave_up} queries given up in all")
+    assert gave_up > 0
     g.close()

@@ -159,9 +159,10 @@ def test_default_tuning_matches_the_header():
     t = P.sgm_tuning()
     P.lib().sgm_default_tuning(ctypes.byref(t))
     assert {k: getattr(t, k) for k in P.TUNING_FIELDS} == dict(
-        slots=512, group_lanes=64, wg_rows=8192, join_policy=0, help_items=1024, helpers=64)
+        slots=512, group_lanes=64, wg_rows=8192, join_policy=0, help_items=1024, helpers=64,
+        help_wait=0)
     header = open(os.path.join(os.path.dirname(__file__), "..", "include", "sgm.h")).read()
-    assert "help_items 1024, helpers 64" in header
+    assert "help_items 1024, helpers 64,\n * help_wait 0." in header
 
 
 def test_traffic_record_hash_follows_code_only():
@@ -180,3 +181,46 @@ def test_traffic_record_hash_follows_code_only():
     assert ps.kernel_source_hash(lambda rel: changed[rel]) != h0
     assert ps.kernel_source_hash() == ps.kernel_source_hash(
         lambda rel: open(os.path.join(os.path.dirname(ps.__file__), rel)).read())
+
+
+def _est(n, vl, vp, es, ed, el, V, tf, rf):
+    return P.sgm_estimate_query(n, vl, vp, es, ed, el, V, tf, rf)
+
+
+def test_admission_estimate_closed_forms():
+    """The served form's admission estimate (host only) on cases with a
+    closed form: one typed vertex holds its type's count of rows; an
+    unlabelled one-edge query holds V rows, then E (two columns); a pinned
+    root starts from one row."""
+    V, tf, rf = 1000, [600, 400], [3000, 1000]
+    E = sum(rf)
+    bitmap = 8 * ((V + 63) // 64)
+    assert _est(1, [1], [-1], [], [], [], V, tf, rf) == bitmap + 4 * 400
+    assert _est(2, [-1, -1], [-1, -1], [0], [1], [-1], V, tf, rf) == 2 * bitmap + 4 * V + 8 * E
+    # relation 1 from a pinned vertex: 1 row, then 1000 / V per vertex, all types
+    assert _est(2, [-1, -1], [5, -1], [0], [1], [1], V, tf, rf) == 2 * bitmap + 4 + 8
+    # the typed vertex (rank 1/600 > 1/V) is the plan's root: 600 rows, then
+    # 600 * (E / V) * (V / V) over the variable edge
+    got = _est(2, [-1, 0], [-1, -1], [0], [1], [-1], V, tf, rf)
+    assert got == 2 * bitmap + 4 * 600 + 8 * 600 * E // V
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_admission_estimate_monotone_in_edge_labels(seed):
+    """Edge labels do not change the plan (ranks use degrees and type
+    frequencies), so giving a variable edge the rarest relation never raises
+    the estimate, and the estimate never falls below the bitmaps."""
+    from tests.micro import random_query
+    rng = np.random.default_rng(seed)
+    V, tf, rf = 5000, [1000, 1500, 2500], [8000, 3000, 1000]
+    for _ in range(20):
+        q = random_query(rng, int(rng.integers(1, 9)), 3, 3, V)
+        base = _est(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel, V, tf, rf)
+        assert base >= q.n * 8 * ((V + 63) // 64)
+        for i in range(len(q.esrc)):
+            dup = any(q.esrc[j] == q.esrc[i] and q.edst[j] == q.edst[i] and q.elabel[j] == 2
+                      for j in range(len(q.esrc)))
+            if q.elabel[i] < 0 and not dup:
+                el = list(q.elabel)
+                el[i] = 2
+                assert _est(q.n, q.vlabel, q.vpin, q.esrc, q.edst, el, V, tf, rf) <= base
