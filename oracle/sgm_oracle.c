@@ -640,9 +640,11 @@ static int64_t st_freq(const oracle_graph *g, const st_query *q, int u) {
 
 /*
  * Query plan (Ch. 3 Sec. "Query Plan Generation", commonsense variant of
- * Sec. "GpSense"): the first query edge maximises f(a) + f(b) (lowest edge
- * index on ties); its endpoint of larger f (lower id on ties) is expanded
- * first; expanding a vertex adds its unreached neighbours to the spanning
+ * Sec. "GpSense"): a query with concept (pinned) nodes starts at the concept
+ * node of maximum degree (lowest id on ties), the commonsense rule; a query
+ * without any starts at the first query edge maximising f(a) + f(b) (lowest
+ * edge index on ties), at its endpoint of larger f (lower id on ties), the
+ * general rule; expanding a vertex adds its unreached neighbours to the spanning
  * tree (parent edge = lowest-index edge between them); the next vertex to
  * expand is the reached, unexpanded one with the most unreached neighbours
  * (then larger f, then lower id), until every vertex is reached.
@@ -670,18 +672,23 @@ int oracle_plan(const oracle_graph *g, int32_t n, int32_t m, const int32_t *vlab
         init_order[0] = 0;
         return OR_OK;
     }
-    int best = 0;
-    for (int i = 1; i < m; i++) {
-        int a = esrc[best], b = edst[best], c = esrc[i], d = edst[i];
-        __int128 lhs = ((__int128)fnum[a] * fden[b] + (__int128)fnum[b] * fden[a]) *
-                       ((__int128)fden[c] * fden[d]);
-        __int128 rhs = ((__int128)fnum[c] * fden[d] + (__int128)fnum[d] * fden[c]) *
-                       ((__int128)fden[a] * fden[b]);
-        if (rhs > lhs) best = i;
+    int root = -1;
+    for (int v = 0; v < n; v++)
+        if (vpin[v] >= 0 && (root < 0 || q.deg[v] > q.deg[root])) root = v;
+    if (root < 0) {
+        int best = 0;
+        for (int i = 1; i < m; i++) {
+            int a = esrc[best], b = edst[best], c = esrc[i], d = edst[i];
+            __int128 lhs = ((__int128)fnum[a] * fden[b] + (__int128)fnum[b] * fden[a]) *
+                           ((__int128)fden[c] * fden[d]);
+            __int128 rhs = ((__int128)fnum[c] * fden[d] + (__int128)fnum[d] * fden[c]) *
+                           ((__int128)fden[a] * fden[b]);
+            if (rhs > lhs) best = i;
+        }
+        int a = esrc[best], b = edst[best];
+        __int128 fa = (__int128)fnum[a] * fden[b], fb = (__int128)fnum[b] * fden[a];
+        root = fa > fb ? a : fb > fa ? b : (a < b ? a : b);
     }
-    int a = esrc[best], b = edst[best], root;
-    __int128 fa = (__int128)fnum[a] * fden[b], fb = (__int128)fnum[b] * fden[a];
-    root = fa > fb ? a : fb > fa ? b : (a < b ? a : b);
     uint32_t reached = 1u << root, expanded = 0;
     init_order[ni++] = root;
     int u = root;

@@ -3,9 +3,9 @@
 // Plan: thesis Ch. 3, Sec. "Query Plan Generation" (rank f(u) = deg(u) /
 // freq(u.label); first edge maximising f(u) + f(v); spanning tree T and
 // visit order O of expanded vertices) and the commonsense variant of Sec.
-// "GpSense" (a concept node has frequency 1, so pinned vertices of highest
-// degree come first; the next vertex is the one whose adjacency holds the
-// most vertices not yet reached; stop once the tree covers the query).
+// "GpSense" (a query with concept nodes starts at the concept node of
+// maximum degree; the next vertex is the one whose adjacency holds the most
+// vertices not yet reached; stop once the tree covers the query).
 #include "sgm_plan.h"
 
 #include <algorithm>
@@ -111,16 +111,23 @@ int make_plan(const QInfo &qi, int32_t V, const int64_t *type_freq, int32_t n_ty
         p->init[0] = 0;
         return SGM_OK;
     }
-    // first edge: maximum f(a) + f(b), lowest edge index on ties
-    int best = 0;
-    for (int i = 1; i < m; ++i)
-        if (sum_less(f[qi.esrc[best]], f[qi.edst[best]], f[qi.esrc[i]], f[qi.edst[i]])) best = i;
-    int a = qi.esrc[best], b = qi.edst[best];
-    // u = endpoint with f(u) >= f(v); lower vertex id if equal
-    int root;
-    if (frac_less(f[a], f[b])) root = b;
-    else if (frac_less(f[b], f[a])) root = a;
-    else root = std::min(a, b);
+    // commonsense rule: the concept (pinned) node of maximum degree, lowest
+    // id on ties
+    int root = -1;
+    for (int v = 0; v < n; ++v)
+        if (qi.pin[v] >= 0 && (root < 0 || qi.deg[v] > qi.deg[root])) root = v;
+    if (root < 0) {
+        // general rule: first edge of maximum f(a) + f(b), lowest edge index
+        // on ties; its endpoint with f(u) >= f(v), lower vertex id if equal
+        int best = 0;
+        for (int i = 1; i < m; ++i)
+            if (sum_less(f[qi.esrc[best]], f[qi.edst[best]], f[qi.esrc[i]], f[qi.edst[i]]))
+                best = i;
+        const int a = qi.esrc[best], b = qi.edst[best];
+        if (frac_less(f[a], f[b])) root = b;
+        else if (frac_less(f[b], f[a])) root = a;
+        else root = std::min(a, b);
+    }
 
     uint32_t in_tree = 0, expanded = 0;
     auto nbr_mask = [&](int u) { return qi.out_mask[u] | qi.in_mask[u]; };

@@ -80,6 +80,19 @@ def test_plan_prefers_pinned_vertex_of_max_degree():
     check_tree(p, 4, edges)
 
 
+def test_plan_starts_at_concept_node_of_max_degree():
+    # concept nodes 0 and 1 (degree 2 each) are adjacent, concept node 4 has
+    # degree 3: the edge rule would start at edge (0, 1) (f sum 4 > 3), the
+    # commonsense rule starts at the concept node of maximum degree, 4
+    edges = [(0, 1, -1), (0, 2, -1), (1, 3, -1), (4, 2, -1), (4, 3, -1), (4, 5, -1)]
+    p = plan(6, [-1] * 6, [10, 11, -1, -1, 12, -1], edges)
+    assert p["visit_order"][0] == 4
+    check_tree(p, 6, edges)
+    # ties: the lower index
+    p = plan(6, [-1] * 6, [10, 11, -1, -1, -1, -1], edges)
+    assert p["visit_order"][0] == 0
+
+
 def test_plan_rank_by_degree_over_frequency():
     # unpinned: f(u) = deg(u) / freq(label); rare label wins
     tf = np.full(64, 100)
@@ -224,3 +237,34 @@ def test_admission_estimate_monotone_in_edge_labels(seed):
                 el = list(q.elabel)
                 el[i] = 2
                 assert _est(q.n, q.vlabel, q.vpin, q.esrc, q.edst, el, V, tf, rf) <= base
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the public structs have the C layout of
+    include/sgm.h (size and every field offset, from a C compiler)."""
+    import subprocess
+    structs = {"sgm_options": P.sgm_options, "sgm_query": P.sgm_query, "sgm_stats": P.sgm_stats,
+               "sgm_result": P.sgm_result, "sgm_kstat": P.sgm_kstat, "sgm_tuning": P.sgm_tuning,
+               "sgm_serve_options": P.sgm_serve_options, "sgm_serve_stats": P.sgm_serve_stats}
+    inc = os.path.join(os.path.dirname(__file__), "..", "include")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sgm.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            lines.append(f'printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", inc, "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    seen = 0
+    for line in out:
+        if not line:
+            continue
+        name, field, val = line.split()
+        cls = structs[name]
+        want = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert int(val) == want, (name, field, int(val), want)
+        seen += 1
+    assert seen == sum(len(c._fields_) + 1 for c in structs.values())

@@ -42,6 +42,22 @@ def test_hand_path_explore_push():
     assert g.match_query(q).tolist() == [[0, 1, 3], [0, 2, 4]]
 
 
+def test_hand_plan_concept_node_first():
+    # concept nodes 0, 1 (degree 2, adjacent) and 4 (degree 3): the
+    # commonsense rule of Sec. "GpSense" starts at the concept node of
+    # maximum degree, 4 (the edge rule would take edge (0, 1): f sum 2 + 2);
+    # expanding 4 reaches 2, 3, 5; 2 and 3 each have one unreached neighbour
+    # and equal f (2/13): 2 (lower id) reaches 0; then 3 and 0 each have one
+    # (vertex 1), and the concept node 0 has the larger f (2/1): 0 reaches 1
+    g = og_of(MicroGraph(13, [0], [1], [0], [0] * 13))
+    q = MicroQuery(6, [-1] * 6, [10, 11, -1, -1, 12, -1], [0, 0, 1, 4, 4, 4],
+                   [1, 2, 3, 2, 3, 5], [-1] * 6)
+    p = g.plan(q)
+    assert p["visit_order"] == [4, 2, 0]
+    assert p["init_order"] == [4, 2, 3, 5, 0, 1]
+    assert p["parent"] == [2, 0, 4, 4, -1, 4]
+
+
 def test_hand_prune_by_relation():
     # 0->1 r0, 1->3 r1, 0->2 r0, 2->4 r0; query a -r0-> b -r1-> c
     g = og_of(MicroGraph(5, [0, 1, 0, 2], [1, 3, 2, 4], [0, 1, 0, 0], [0] * 5))
