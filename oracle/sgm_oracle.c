@@ -24,7 +24,11 @@
  * How: plain depth-first backtracking over the query vertices in a fixed
  * connected order, testing each condition above directly. It performs no
  * candidate filtering of any kind: every check is one clause of the
- * definition. OpenMP splits the work over the candidates of the first vertex.
+ * definition. A vertex's candidates are read from the adjacency row of an
+ * already-placed neighbour, indexed by relation and by the neighbour's type
+ * so that only entries that can satisfy clauses 2 and 4 for that edge are
+ * read. OpenMP splits the work over the candidates of the first vertex and
+ * pieces of the second vertex's rows.
  *
  * Parity pins (tests): brute-force enumeration of all V^n maps on micro
  * graphs, closed-form counts (complete digraphs, directed cycles, stars,
@@ -56,7 +60,14 @@ typedef struct oracle_graph {
     or_pair *out;       /* sorted by (dst, rel) within each source */
     int64_t *in_off;    /* [V+1] */
     or_pair *in;        /* (src, rel) sorted within each destination */
+    or_pair *out_r;     /* the rows of out, each sorted by (rel, type(dst), dst) */
+    or_pair *in_r;      /* the rows of in, each sorted by (rel, type(src), src) */
+    or_pair *out_t;     /* the rows of out, each sorted by (type(dst), dst, rel) */
+    or_pair *in_t;      /* the rows of in, each sorted by (type(src), src, rel) */
     int32_t *vtype;     /* [V] */
+    int32_t n_types, n_rels;
+    int64_t *type_count;  /* [n_types] vertices per type */
+    int64_t *rel_count;   /* [n_rels] distinct triples per relation */
 } oracle_graph;
 
 static int pair_cmp(const void *a, const void *b) {
@@ -103,12 +114,53 @@ static int64_t group_edges(int32_t V, int64_t E, const int32_t *key, const int32
     return w;
 }
 
+/* Sort keys of the indexed row copies (qsort_r with the vertex types). */
+static int pair_cmp_rel_type(const void *a, const void *b, void *t) {
+    const or_pair *x = (const or_pair *)a, *y = (const or_pair *)b;
+    const int32_t *vt = (const int32_t *)t;
+    if (x->rel != y->rel) return x->rel < y->rel ? -1 : 1;
+    if (vt[x->dst] != vt[y->dst]) return vt[x->dst] < vt[y->dst] ? -1 : 1;
+    if (x->dst != y->dst) return x->dst < y->dst ? -1 : 1;
+    return 0;
+}
+
+static int pair_cmp_type(const void *a, const void *b, void *t) {
+    const or_pair *x = (const or_pair *)a, *y = (const or_pair *)b;
+    const int32_t *vt = (const int32_t *)t;
+    if (vt[x->dst] != vt[y->dst]) return vt[x->dst] < vt[y->dst] ? -1 : 1;
+    if (x->dst != y->dst) return x->dst < y->dst ? -1 : 1;
+    if (x->rel != y->rel) return x->rel < y->rel ? -1 : 1;
+    return 0;
+}
+
+/* A copy of the rows of arr (extents off) with each row sorted by cmp: the
+ * entries of one relation (and type), or of one type, are then contiguous. */
+static or_pair *indexed_rows(int32_t V, const int64_t *off, const or_pair *arr,
+                             const int32_t *vtype,
+                             int (*cmp)(const void *, const void *, void *)) {
+    or_pair *r = (or_pair *)malloc(sizeof(or_pair) * (size_t)(off[V] > 0 ? off[V] : 1));
+    if (!r) return NULL;
+    memcpy(r, arr, sizeof(or_pair) * (size_t)off[V]);
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int32_t v = 0; v < V; v++)
+        if (off[v + 1] - off[v] > 1)
+            qsort_r(r + off[v], (size_t)(off[v + 1] - off[v]), sizeof(or_pair), cmp,
+                    (void *)vtype);
+    return r;
+}
+
 void oracle_graph_free(oracle_graph *g) {
     if (!g) return;
     free(g->out_off);
     free(g->out);
     free(g->in_off);
     free(g->in);
+    free(g->out_r);
+    free(g->in_r);
+    free(g->out_t);
+    free(g->in_t);
+    free(g->type_count);
+    free(g->rel_count);
     free(g->vtype);
     free(g);
 }
@@ -142,6 +194,23 @@ oracle_graph *oracle_graph_build(int32_t V, int64_t E, const int32_t *src, const
         return NULL;
     }
     g->E = e1;
+    g->out_r = indexed_rows(V, g->out_off, g->out, g->vtype, pair_cmp_rel_type);
+    g->in_r = indexed_rows(V, g->in_off, g->in, g->vtype, pair_cmp_rel_type);
+    g->out_t = indexed_rows(V, g->out_off, g->out, g->vtype, pair_cmp_type);
+    g->in_t = indexed_rows(V, g->in_off, g->in, g->vtype, pair_cmp_type);
+    int32_t mt = 0, mr = 0;
+    for (int32_t v = 0; v < V; v++) mt = vtype[v] > mt ? vtype[v] : mt;
+    for (int64_t i = 0; i < g->E; i++) mr = g->out[i].rel > mr ? g->out[i].rel : mr;
+    g->n_types = mt + 1;
+    g->n_rels = mr + 1;
+    g->type_count = (int64_t *)calloc((size_t)g->n_types, sizeof(int64_t));
+    g->rel_count = (int64_t *)calloc((size_t)g->n_rels, sizeof(int64_t));
+    if (!g->out_r || !g->in_r || !g->out_t || !g->in_t || !g->type_count || !g->rel_count) {
+        oracle_graph_free(g);
+        return NULL;
+    }
+    for (int32_t v = 0; v < V; v++) g->type_count[vtype[v]]++;
+    for (int64_t i = 0; i < g->E; i++) g->rel_count[g->out[i].rel]++;
     return g;
 }
 
@@ -284,8 +353,9 @@ static void dfs(or_ctx *c, int32_t *f, int depth) {
 }
 
 /* Candidates of vertex order[depth] from entries [lo, hi) of the data row
- * gen_range chose (a row is sorted by destination; repeated destinations,
- * i.e. other relations, are one candidate). */
+ * gen_range chose (a full row is sorted by destination, and a repeated
+ * destination, i.e. another relation, is one candidate; a relation's slice
+ * holds each destination once). */
 static void dfs_range(or_ctx *c, int32_t *f, int depth, int64_t lo, int64_t hi,
                       const or_pair *arr) {
     const or_query *q = c->q;
@@ -305,9 +375,34 @@ static void dfs_range(or_ctx *c, int32_t *f, int depth, int64_t lo, int64_t hi,
     }
 }
 
-/* The data row that generates the candidates of vertex u at this depth: the
- * row of the already-placed neighbour with the fewest entries (out-row of
- * f(a) for a query edge a -> u, in-row of f(b) for u -> b). 0 if u has no
+/* Narrow [lo, hi) of a row sorted with key(entry) ascending to the entries
+ * whose key equals k: key 0 = relation, 1 = type of the other endpoint. */
+static void key_slice(const oracle_graph *g, const or_pair *arr, int64_t *lo, int64_t *hi,
+                      int key, int32_t k) {
+#define OR_KEY(e) (key == 0 ? (e).rel : g->vtype[(e).dst])
+    int64_t a = *lo, b = *hi;
+    while (a < b) { /* first entry with key >= k */
+        int64_t mid = a + (b - a) / 2;
+        if (OR_KEY(arr[mid]) < k) a = mid + 1;
+        else b = mid;
+    }
+    int64_t c = a, d = *hi;
+    while (c < d) { /* first entry with key > k */
+        int64_t mid = c + (d - c) / 2;
+        if (OR_KEY(arr[mid]) <= k) c = mid + 1;
+        else d = mid;
+    }
+#undef OR_KEY
+    *lo = a;
+    *hi = c;
+}
+
+/* The data entries that generate the candidates of vertex u at this depth,
+ * from the already-placed neighbour whose entries are fewest: for a query
+ * edge a -> u the out-row of f(a), for u -> b the in-row of f(b); of that
+ * row only the entries of the edge's relation (a labelled edge) and of u's
+ * type (a typed u), read from a copy of the row sorted by those keys, since
+ * any other entry fails clause 2 or clause 4 for this edge. 0 if u has no
  * placed neighbour. */
 static int gen_range(const oracle_graph *g, const or_query *q, const int32_t *f, int depth,
                      int32_t u, int64_t *lo_out, int64_t *hi_out, const or_pair **arr_out) {
@@ -315,20 +410,22 @@ static int gen_range(const oracle_graph *g, const or_query *q, const int32_t *f,
     int64_t best_lo = 0, best_hi = 0;
     const or_pair *best_arr = NULL;
     for (int i = 0; i < q->m; i++) {
-        int32_t a = q->esrc[i], b = q->edst[i];
+        int32_t a = q->esrc[i], b = q->edst[i], rho = q->elabel[i], t = q->vlabel[u];
         int64_t lo, hi;
         const or_pair *arr;
         if (b == u && q->pos[a] < depth) { /* f(a) -> x : x among out-neighbours of f(a) */
             lo = g->out_off[f[a]];
             hi = g->out_off[f[a] + 1];
-            arr = g->out;
+            arr = rho >= 0 ? g->out_r : t >= 0 ? g->out_t : g->out;
         } else if (a == u && q->pos[b] < depth) { /* x -> f(b) : x among in-neighbours */
             lo = g->in_off[f[b]];
             hi = g->in_off[f[b] + 1];
-            arr = g->in;
+            arr = rho >= 0 ? g->in_r : t >= 0 ? g->in_t : g->in;
         } else {
             continue;
         }
+        if (rho >= 0) key_slice(g, arr, &lo, &hi, 0, rho);
+        if (t >= 0) key_slice(g, arr, &lo, &hi, 1, t);
         if (!best_len_set || hi - lo < best_hi - best_lo) {
             best_len_set = 1;
             best_lo = lo;
