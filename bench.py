@@ -99,6 +99,28 @@ def served_leg(P, kggen, g, queries, rates, arrivals):
     return out
 
 
+def phase_rates(stats, P, resident):
+    """Per-phase bytes and workgroup time of the persistent kernel over a
+    batch: the rate one workgroup sustains in each phase, and that rate
+    times the workgroups resident at once (the launch's slots) against the
+    HBM peak, i.e. the fraction the phase would reach if every slot were in
+    it at the same time."""
+    names = ("filter", "collect", "join", "finish")
+    keys = ("ns_filter", "ns_collect", "ns_join", "ns_finish")
+    narrow = [st for st in stats if st["path"] == P.SGM_PATH_NARROW]
+    out = {"queries": len(narrow), "resident_workgroups": resident}
+    tot_ns = sum(st[k] for st in narrow for k in keys)
+    for i, (nm, k) in enumerate(zip(names, keys)):
+        b = sum(st["phase_bytes"][i] for st in narrow)
+        ns = sum(st[k] for st in narrow)
+        per_wg = b / ns if ns else 0.0  # bytes per ns = GB/s
+        out[nm] = {"bytes": int(b), "workgroup_ms": round(ns / 1e6, 3),
+                   "share_of_device_time": round(ns / tot_ns, 4) if tot_ns else None,
+                   "per_workgroup_gbs": round(per_wg, 3),
+                   "frac_if_all_slots": round(per_wg * resident / HBM_PEAK_GBS, 5)}
+    return out
+
+
 def cpu_leg(kg, queries, seconds):
     """The oracle on a bounded sample of the same workload: the queries in
     order, cycling, until `seconds` of wall time have passed (queries that
@@ -267,6 +289,12 @@ def bench_large(args, P, kggen):
     lat_ms = np.sort(np.asarray(lat, np.float64)) / 1e6
     log(f"one at a time: {len(queries)} in {el_1:.3f}s")
 
+    # per-phase algorithmic bytes and device time of the persistent kernel
+    # (filter = root candidates, explore and refine; collect = candidate
+    # edges; join; finish = ordering and output), summed over the batch
+    _, bstats = g.match_batch(queries, count_only=True, with_stats=True)
+    phases = phase_rates(bstats, P, resident=min(tuned["slots"], len(queries)))
+
     gp.match_batch(queries)
     gp.reset_kernel_stats()
     for i in range(args.steps):
@@ -311,6 +339,7 @@ def bench_large(args, P, kggen):
         "served": served,
         "roofline": roofline(ks, "persist", "large:persist"),
         "roofline_root_sweep": roofline(ks, "check", "large:check"),
+        "persistent_kernel_phases": phases,
         "cpu_baseline": cpu,
     }
 

@@ -117,6 +117,9 @@ typedef struct {
                                       the multi-kernel path, device clock on the
                                       persistent kernel */
     int64_t device_bytes;          /* persistent kernel: algorithmic bytes moved */
+    int64_t phase_bytes[4];        /* persistent kernel: the same bytes by phase
+                                      (filter, collect, join, finish; the device
+                                      times are ns_filter .. ns_finish) */
     int32_t path;                  /* SGM_PATH_WIDE or SGM_PATH_NARROW: where it ran */
     int32_t fallback;              /* why a query outgrew a regular persistent-kernel
                                       slot: 1 candidate list capacity, 2 slot
@@ -202,6 +205,28 @@ int sgm_match_query(sgm_graph *g, const sgm_query *q, uint32_t flags, sgm_result
  */
 int sgm_match_batch(sgm_graph *g, const sgm_query *qs, int32_t n, uint32_t flags,
                     sgm_result **out);
+
+/*
+ * Projection (thesis Ch. 3, Sec. "Joining Phase", closing remarks on
+ * commonsense reasoning, and Sec. "GpSense": a commonsense query asks only
+ * for the matches of a subset of its nodes): the distinct tuples
+ * (f(u) for u in the projected set) over all matches f of q, as rows of
+ * popcount(project) columns (the projected vertices in index order), unique
+ * and ascending lexicographic; n_rows counts those distinct tuples (with
+ * SGM_COUNT_ONLY too). Equal tuples are collapsed on the device after the
+ * projected columns are ordered.
+ *   project: bit u set = query vertex u is returned; non-zero and within
+ *            the query's vertices (SGM_EINVAL otherwise); all vertices set
+ *            = sgm_match_query.
+ * Other arguments, errors and ownership as sgm_match_query /
+ * sgm_match_batch (project[i] for qs[i]); options.result_cap_rows bounds the
+ * distinct tuples on the persistent kernel and the full matches on the
+ * multi-kernel path.
+ */
+int sgm_match_query_proj(sgm_graph *g, const sgm_query *q, uint32_t project, uint32_t flags,
+                         sgm_result **out);
+int sgm_match_batch_proj(sgm_graph *g, const sgm_query *qs, const uint32_t *project, int32_t n,
+                         uint32_t flags, sgm_result **out);
 
 void sgm_free_result(sgm_result *r);
 void sgm_free_graph(sgm_graph *g);

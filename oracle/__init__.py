@@ -179,6 +179,19 @@ class Graph:
         return ec[:len(q.esrc)]
 
 
+def project_rows(rows: np.ndarray, cols) -> np.ndarray:
+    """Projection of a full match table (thesis Ch. 3, Sec. "GpSense": only
+    the matches of a subset of the query's nodes are wanted): the distinct
+    tuples (f(u) for u in cols, cols in ascending order) over the rows,
+    ascending lexicographic, as an [k, len(cols)] int32 array. Plain
+    definition: the set of projected tuples, sorted."""
+    cols = sorted(int(c) for c in cols)
+    if len(rows) == 0:
+        return np.empty((0, len(cols)), np.int32)
+    sub = np.ascontiguousarray(np.asarray(rows, np.int32)[:, cols])
+    return np.unique(sub, axis=0).astype(np.int32)
+
+
 def graph_from_kg(kg) -> Graph:
     s, d, r = kg.edge_list()
     return Graph(kg.V, s, d, r, kg.vtype)

@@ -61,6 +61,7 @@ class sgm_stats(ctypes.Structure):
                 ("ns_total", ctypes.c_int64), ("ns_filter", ctypes.c_int64),
                 ("ns_collect", ctypes.c_int64), ("ns_join", ctypes.c_int64),
                 ("ns_finish", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("phase_bytes", ctypes.c_int64 * 4),
                 ("path", ctypes.c_int32), ("fallback", ctypes.c_int32)]
 
 
@@ -104,6 +105,13 @@ EXPORTS = {
                                        ctypes.POINTER(ctypes.POINTER(sgm_result))]),
     "sgm_match_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query), ctypes.c_int32,
                                        ctypes.c_uint32, ctypes.POINTER(ctypes.POINTER(sgm_result))]),
+    "sgm_match_query_proj": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query),
+                                            ctypes.c_uint32, ctypes.c_uint32,
+                                            ctypes.POINTER(ctypes.POINTER(sgm_result))]),
+    "sgm_match_batch_proj": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query),
+                                            ctypes.POINTER(ctypes.c_uint32), ctypes.c_int32,
+                                            ctypes.c_uint32,
+                                            ctypes.POINTER(ctypes.POINTER(sgm_result))]),
     "sgm_free_result": (None, [ctypes.POINTER(sgm_result)]),
     "sgm_free_graph": (None, [ctypes.c_void_p]),
     "sgm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -223,6 +231,32 @@ def sgm_match_batch(g, qs, flags: int = SGM_SORTED):
     return rc, [outs[i] for i in range(n)]
 
 
+def sgm_match_query_proj(g, q: sgm_query, project: int, flags: int = SGM_SORTED):
+    out = ctypes.POINTER(sgm_result)()
+    rc = lib().sgm_match_query_proj(g, ctypes.byref(q), int(project), int(flags), ctypes.byref(out))
+    return rc, out
+
+
+def sgm_match_batch_proj(g, qs, projects, flags: int = SGM_SORTED):
+    n = len(qs)
+    arr = (sgm_query * max(n, 1))(*qs)
+    pm = (ctypes.c_uint32 * max(n, 1))(*[int(x) for x in projects])
+    outs = (ctypes.POINTER(sgm_result) * max(n, 1))()
+    rc = lib().sgm_match_batch_proj(g, arr, pm, n, int(flags), outs)
+    return rc, [outs[i] for i in range(n)]
+
+
+def project_mask(project) -> int:
+    """A projection as a bit mask: an int mask, or an iterable of query
+    vertex indices."""
+    if isinstance(project, (int, np.integer)):
+        return int(project)
+    m = 0
+    for u in project:
+        m |= 1 << int(u)
+    return m
+
+
 def sgm_free_result(r):
     lib().sgm_free_result(r)
 
@@ -307,7 +341,8 @@ def stats_dict(st: sgm_stats, n: int, m: int) -> dict:
                 peak_rows=st.peak_rows, peak_bytes=st.peak_bytes, n_chunks=st.n_chunks,
                 n_launches=st.n_launches, ns_total=st.ns_total, ns_filter=st.ns_filter,
                 ns_collect=st.ns_collect, ns_join=st.ns_join, ns_finish=st.ns_finish,
-                device_bytes=st.device_bytes, path=st.path, fallback=st.fallback)
+                device_bytes=st.device_bytes, phase_bytes=list(st.phase_bytes),
+                path=st.path, fallback=st.fallback)
 
 
 class Graph:
@@ -342,11 +377,18 @@ class Graph:
                              ctypes.byref(mi))
         return dict(n_vertices=nv.value, n_edges=ne.value, max_out=mo.value, max_in=mi.value)
 
-    def match(self, n, vlabel, vpin, esrc, edst, elabel, count_only=False, with_stats=False):
+    def match(self, n, vlabel, vpin, esrc, edst, elabel, count_only=False, with_stats=False,
+              project=None):
         """All matches as an [rows, n] int32 array (ascending lexicographic),
-        or the count when ``count_only``. Raises SGMError on failure."""
+        or the count when ``count_only``; with ``project`` (vertex indices or
+        a bit mask) the distinct projected tuples (sgm_match_query_proj).
+        Raises SGMError on failure."""
         q, keep = _make_query(n, vlabel, vpin, esrc, edst, elabel)
-        rc, r = sgm_match_query(self._h, q, SGM_COUNT_ONLY if count_only else SGM_SORTED)
+        fl = SGM_COUNT_ONLY if count_only else SGM_SORTED
+        if project is None:
+            rc, r = sgm_match_query(self._h, q, fl)
+        else:
+            rc, r = sgm_match_query_proj(self._h, q, project_mask(project), fl)
         if rc != SGM_OK:
             err = SGMError(rc, "sgm_match_query")
             if r:
@@ -360,20 +402,25 @@ class Graph:
             except Exception:
                 sgm_free_result(r)
                 raise
-        k, rows = _take_rows(r, n)
+        k, rows = _take_rows(r, int(r.contents.n_cols) if project is not None else n)
         out = k if count_only else rows
         return (out, st) if with_stats else out
 
     def match_query(self, q, **kw):
         return self.match(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel, **kw)
 
-    def match_batch(self, queries, count_only=False, with_stats=False):
+    def match_batch(self, queries, count_only=False, with_stats=False, projects=None):
         """Results (arrays, counts, or SGMError instances) for a list of
-        kggen-style queries, through sgm_match_batch; with_stats=True also
+        kggen-style queries, through sgm_match_batch (sgm_match_batch_proj
+        with ``projects``, one projection per query); with_stats=True also
         returns each member's statistics as a dict."""
         built = [_make_query(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel) for q in queries]
-        rc, outs = sgm_match_batch(self._h, [b[0] for b in built],
-                                   SGM_COUNT_ONLY if count_only else SGM_SORTED)
+        fl = SGM_COUNT_ONLY if count_only else SGM_SORTED
+        if projects is None:
+            rc, outs = sgm_match_batch(self._h, [b[0] for b in built], fl)
+        else:
+            rc, outs = sgm_match_batch_proj(self._h, [b[0] for b in built],
+                                            [project_mask(p) for p in projects], fl)
         if rc != SGM_OK:
             raise SGMError(rc, "sgm_match_batch")
         res, stats = [], []
@@ -385,7 +432,7 @@ class Graph:
                 res.append(SGMError(st, "batch member"))
                 sgm_free_result(r)
             else:
-                k, rows = _take_rows(r, q.n)
+                k, rows = _take_rows(r, int(r.contents.n_cols) if projects is not None else q.n)
                 res.append(k if count_only else rows)
         return (res, stats) if with_stats else res
 

@@ -468,10 +468,15 @@ struct Query {
     Plan pl;
     Scope sc;
     sgm_result *res;
+    // flags of the run: a projection's count needs its distinct rows, so a
+    // projected query materialises the join's final table even when only
+    // the count is asked for (want_rows then stays false)
     uint32_t flags;
+    bool want_rows;
     int next_slot = 0;
     Query(sgm_graph *g_, const QInfo &q_, sgm_result *r, uint32_t f)
-        : g(g_), qi(q_), sc(g_->pool), res(r), flags(f) {}
+        : g(g_), qi(q_), sc(g_->pool), res(r),
+          flags(q_.proj ? (f & ~SGM_COUNT_ONLY) : f), want_rows(!(f & SGM_COUNT_ONLY)) {}
 
     uint64_t *bits(int u) const { return g->d_bits + (int64_t)u * g->nwords; }
     uint64_t *scratch() const { return g->d_bits + (int64_t)SGM_MAX_QV * g->nwords; }
@@ -874,21 +879,37 @@ struct Query {
     }
 
     // Final ordering (rows ascending in query-vertex column order) and the
-    // copy to host.
-    void finish(const int32_t *table, int64_t R) {
+    // copy to host (when copy). With a projection (thesis Ch. 3, Sec.
+    // "GpSense") only the projected columns are ordered and kept, and equal
+    // projected rows, now adjacent, collapse into one. Returns the number
+    // of rows of the result.
+    int64_t finish(const int32_t *table, int64_t R, bool copy) {
         const int n = qi.n;
-        int32_t colpos[SGM_MAX_QV];
+        if (!table && R > 0) {
+            // the join materialises its final table whenever finish runs
+            g_last_error = "internal: final table not materialised";
+            throw DeviceError{SGM_EDEVICE};
+        }
+        // output columns: the projected query vertices (all of them without
+        // a projection) in index order, and where the table holds each
+        int32_t colpos[SGM_MAX_QV], colu[SGM_MAX_QV];
+        int no = 0;
         bool identity = true;
         for (int u = 0; u < n; ++u) {
-            colpos[u] = jpos[u];
             identity &= jpos[u] == u;
+            if (qi.proj && !((qi.proj >> u) & 1u)) continue;
+            colpos[no] = jpos[u];
+            colu[no] = u;
+            ++no;
         }
+        // a table in column order is already sorted on any prefix of columns
+        const bool lead = qi.proj == 0 || (qi.proj & (qi.proj + 1u)) == 0;
         int32_t *idx = nullptr;
-        if (!identity && R > 1) {
+        if (!(identity && lead) && R > 1) {
             if (R <= small_sort_limit()) {
                 idx = sc.get<int32_t>(R);
-                Prof p(g, SGM_K_SORT, 4.0 * R * n);
-                launch_sort_small(st(), table, n, colpos, (int32_t)R, idx);
+                Prof p(g, SGM_K_SORT, 4.0 * R * no);
+                launch_sort_small(st(), table, n, colpos, no, (int32_t)R, idx);
             } else {
                 int nbits = 1;
                 while ((1ll << nbits) < g->V) ++nbits;
@@ -905,21 +926,22 @@ struct Query {
                 // candidate ranks packed into one key of at most 64 bits:
                 // ceil(bits / 8) passes instead of a pass set per column
                 KeyCols kc{};
-                kc.n = n;
+                kc.n = no;
                 int tb = 0;
-                for (int u = 0; u < n; ++u) {
+                for (int c = 0; c < no; ++c) {
+                    const int u = colu[c];
                     int b = 0;
                     while ((1ll << b) < ccount[u]) ++b;
-                    kc.bits[u] = bits(u);
-                    kc.prefix[u] = prefix(u);
-                    kc.col[u] = colpos[u];
-                    kc.nbits[u] = b;
+                    kc.bits[c] = bits(u);
+                    kc.prefix[c] = prefix(u);
+                    kc.col[c] = colpos[c];
+                    kc.nbits[c] = b;
                     tb += b;
                 }
                 if (tb <= 64) {
                     uint64_t *keys = sc.get<uint64_t>(R);
                     {
-                        Prof p(g, SGM_K_SORT, 4.0 * R * n + 8.0 * R);
+                        Prof p(g, SGM_K_SORT, 4.0 * R * no + 8.0 * R);
                         launch_row_keys(st(), table, n, kc, R, keys);
                     }
                     for (int half = 0; half < 2; ++half) {
@@ -939,10 +961,10 @@ struct Query {
                         }
                     }
                 }
-                for (int u = n - 1; u >= 0 && tb > 64; --u) {
+                for (int c = no - 1; c >= 0 && tb > 64; --c) {
                     {
                         Prof p(g, SGM_K_SORT, 12.0 * R);
-                        launch_gather_key(st(), table, n, colpos[u], ia, R, ka);
+                        launch_gather_key(st(), table, n, colpos[c], ia, R, ka);
                     }
                     for (int sh = 0; sh < nbits; sh += 8) {
                         Prof p(g, SGM_K_SORT, 20.0 * R);
@@ -956,12 +978,26 @@ struct Query {
                 idx = ia;
             }
         }
-        int32_t *out = sc.get<int32_t>(R * n);
+        int32_t *out = sc.get<int32_t>(R * no);
         {
-            Prof p(g, SGM_K_OTHER, 8.0 * R * n);
-            launch_gather_rows(st(), table, n, idx, R, colpos, out);
+            Prof p(g, SGM_K_OTHER, 8.0 * R * no);
+            launch_gather_rows(st(), table, n, idx, R, colpos, no, out);
         }
-        const size_t bytes = sizeof(int32_t) * (size_t)R * n;
+        if (qi.proj && R > 1) {
+            int64_t *head = sc.get<int64_t>(R), *pos = sc.get<int64_t>(R + 1);
+            int64_t *tmp = sc.get<int64_t>(scan_tmp_words(R) + 1);
+            int32_t *uniq = sc.get<int32_t>(R * no);
+            {
+                Prof p(g, SGM_K_OTHER, 8.0 * R * no + 24.0 * R);
+                launch_unique_rows(st(), out, no, R, head, pos, tmp, uniq);
+            }
+            HIPX(hipMemcpyAsync(g->h_small, pos + R, sizeof(int64_t), hipMemcpyDeviceToHost, st()));
+            sync(g);
+            R = g->h_small[0];
+            out = uniq;
+        }
+        if (!copy) return R;
+        const size_t bytes = sizeof(int32_t) * (size_t)R * no;
         // readback through two pinned staging halves of kStageBytes: the
         // host copy of one chunk overlaps the transfer of the next
         const size_t half = std::min(bytes, kStageBytes);
@@ -992,6 +1028,7 @@ struct Query {
             const size_t off = i * half, len = std::min(half, bytes - off);
             parallel_copy({HostCopy{(char *)res->rows + off, stage[i & 1], len}});
         }
+        return R;
     }
 
     int run() {
@@ -1000,7 +1037,7 @@ struct Query {
         int rc = make_plan(qi, g->V, g->type_freq.data(), g->n_types, &pl);
         if (rc) return rc;
         for (int i = 0; i < SGM_MAX_QV; ++i) res->stats.visit_order[i] = pl.visit[i];
-        res->n_cols = n;
+        res->n_cols = qi.n_out;
         rc = filter();
         if (rc) return rc;
         HIPX(hipMemcpyAsync(g->h_cnt->cand_count, g->d_cnt->cand_count, sizeof(int32_t) * n,
@@ -1026,7 +1063,7 @@ struct Query {
                 res->n_rows = R;
                 return SGM_ETOOBIG;
             }
-            if (!(flags & SGM_COUNT_ONLY)) finish(list(0), R);
+            if (want_rows) finish(list(0), R, true);
             return done(R, t0);
         }
         rc = collect_edges();
@@ -1046,7 +1083,9 @@ struct Query {
             return rc;
         }
         if (rc) return rc;
-        if (!(flags & SGM_COUNT_ONLY) && R > 0) finish(table, R);
+        // a projection's row count needs its distinct rows, also when only
+        // the count is asked for (the join then materialised its table)
+        if (R > 0 && (want_rows || qi.proj)) R = finish(table, R, want_rows);
         res->stats.ns_finish = now_ns() - t3;
         return done(R, t0);
     }
@@ -1099,7 +1138,7 @@ struct Query {
     int done(int64_t R, int64_t t0) {
         res->n_rows = R;
         // rows is non-NULL for every successful SORTED result, also when empty
-        if (!(flags & SGM_COUNT_ONLY) && !res->rows) {
+        if (want_rows && !res->rows) {
             res->rows = (int32_t *)std::malloc(sizeof(int32_t));
             if (!res->rows) throw std::bad_alloc();
         }
@@ -1115,7 +1154,12 @@ struct Query {
 constexpr int kNarrowMaxSlots = 512;                 // 2 workgroups per CU
 constexpr int32_t kTypeTable = 1024;                 // vertex types covered by the sweep's table
 constexpr int64_t kNarrowSlabMin = 8ll << 20;        // per slot, small graphs
-constexpr int64_t kNarrowSlabMax = 32ll << 20;       // per slot, large graphs
+constexpr int64_t kNarrowSlabMax = 32ll << 20;       // per slot, large graphs (served form)
+// A graph's own batch context: 40 B per data vertex up to 160 MB per slot
+// (512 slots of a 4M-vertex graph hold about 87 GB of HBM), so that queries
+// with tables of ~1e6 rows finish in their slot and a batch is one launch.
+constexpr int64_t kBatchSlabPerVertex = 40;
+constexpr int64_t kBatchSlabMax = 160ll << 20;
 constexpr int32_t kNarrowListCap = 1 << 16;          // per query vertex
 constexpr int kNarrowQueryCap = 4096;                // queries per launch
 constexpr int64_t kNarrowOutCap = 256ll << 20;       // int32 elements (1 GB) per context
@@ -1128,8 +1172,13 @@ constexpr int64_t kBigSlab = 256ll << 20;            // per large slot
 
 // slot memory for edge tables, join tables and sort buffers: 8 bytes per
 // data vertex, within [8 MB, 32 MB]
-int64_t narrow_slab_bytes(const sgm_graph *g) {
-    return std::min<int64_t>(kNarrowSlabMax, std::max<int64_t>(kNarrowSlabMin, 8ll * g->V));
+// Slab of one regular slot: a server's contexts (several side by side, up
+// to max_batch slots each) keep theirs small; the graph's own batch context
+// takes room for large intermediate tables.
+int64_t narrow_slab_bytes(const sgm_graph *g, bool serve) {
+    if (serve) return std::min<int64_t>(kNarrowSlabMax, std::max<int64_t>(kNarrowSlabMin, 8ll * g->V));
+    return std::min<int64_t>(kBatchSlabMax,
+                             std::max<int64_t>(kNarrowSlabMin, kBatchSlabPerVertex * g->V));
 }
 
 template <class T>
@@ -1179,7 +1228,7 @@ void narrow_free(NarrowCtx &nw) {
 void narrow_reserve(sgm_graph *g, NarrowCtx &nw, int slots, int nq, int nroot) {
     if (nw.lcap == 0) {
         nw.lcap = std::min<int32_t>(g->V, nw.lcap_want ? nw.lcap_want : kNarrowListCap);
-        nw.slab_bytes = nw.slab_want ? nw.slab_want : narrow_slab_bytes(g);
+        nw.slab_bytes = nw.slab_want ? nw.slab_want : narrow_slab_bytes(g, nw.serve);
         // while filtering, a slot's slab holds two lists of up to lcap ints
         if (nw.slab_bytes < 8ll * nw.lcap) throw DeviceError{SGM_EUNSUPPORTED};
         HIPX(hipMalloc(&nw.d_ctr, sizeof(unsigned long long) * 3));
@@ -1260,6 +1309,7 @@ bool pack_query(sgm_graph *g, const QInfo &qi, const Plan &pl, NQuery *nq, int *
     nq->n_init = (int)pr.init.size();
     nq->n_ref = (int)pr.refine.size();
     nq->refine_rounds = g->opts.refine_rounds < 0 ? -1 : std::min(g->opts.refine_rounds, 32);
+    nq->proj = qi.proj;
     int k = 0;
     for (const auto *v : {&pr.init, &pr.refine})
         for (const PStep &s : *v) {
@@ -1564,7 +1614,7 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         }
         sgm_result *out = res[qi_idx];
         const QInfo &qi = qis[qi_idx];
-        out->n_cols = qi.n;
+        out->n_cols = qi.n_out;
         out->n_rows = r.n_rows;
         sgm_stats &stt = out->stats;
         for (int u = 0; u < qi.n; ++u) {
@@ -1584,6 +1634,7 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         stt.ns_join = (int64_t)(r.ticks[2] * g->ns_per_tick);
         stt.ns_finish = (int64_t)(r.ticks[3] * g->ns_per_tick);
         stt.device_bytes = r.bytes;
+        for (int i = 0; i < 4; ++i) stt.phase_bytes[i] = r.pbytes[i];
         stt.path = SGM_PATH_NARROW;
         if (g->opts.result_cap_rows > 0 && r.n_rows > g->opts.result_cap_rows) {
             out->status = SGM_ETOOBIG;
@@ -1591,7 +1642,7 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         }
         out->status = SGM_OK;
         if (!(flags & SGM_COUNT_ONLY)) {
-            const size_t bytes = sizeof(int32_t) * (size_t)r.n_rows * qi.n;
+            const size_t bytes = sizeof(int32_t) * (size_t)r.n_rows * qi.n_out;
             out->rows = alloc_rows(bytes);
             if (!out->rows) throw std::bad_alloc();
             if (bytes) copies.push_back({out->rows, nw.h_out + r.offset, bytes});
@@ -1657,7 +1708,7 @@ int wide_locked(sgm_graph *g, const QInfo &qi, uint32_t flags, sgm_result *res) 
 // Validate, run the persistent kernel on every valid query, rerun the ones
 // that outgrow a slot on the multi-kernel path. res[i] are zeroed results;
 // per-query outcomes go to res[i]->status. Returns a global error code.
-int run_queries(sgm_graph *g, const sgm_query *qs, int n, uint32_t flags,
+int run_queries(sgm_graph *g, const sgm_query *qs, const uint32_t *proj, int n, uint32_t flags,
                 std::vector<sgm_result *> &res) {
     std::vector<QInfo> qis((size_t)n);
     std::vector<int> valid, wide;
@@ -1666,7 +1717,8 @@ int run_queries(sgm_graph *g, const sgm_query *qs, int n, uint32_t flags,
         g->trace_n.assign((size_t)n, 0);
     }
     for (int i = 0; i < n; ++i) {
-        const int rc = check_query(&qs[i], g->V, &qis[i]);
+        int rc = check_query(&qs[i], g->V, &qis[i]);
+        if (rc == SGM_OK && proj) rc = set_projection(&qis[i], proj[i]);
         res[i]->status = rc;
         if (rc == SGM_OK) valid.push_back(i);
     }
@@ -1952,7 +2004,12 @@ int sgm_graph_info(const sgm_graph *g, int32_t *n_vertices, int64_t *n_edges,
     return SGM_OK;
 }
 
-int sgm_match_query(sgm_graph *g, const sgm_query *q, uint32_t flags, sgm_result **out) {
+}  // extern "C"
+
+namespace {
+
+int match_one(sgm_graph *g, const sgm_query *q, const uint32_t *proj, uint32_t flags,
+              sgm_result **out) {
     if (!out) return SGM_EINVAL;
     *out = nullptr;
     if (!g || !q || (flags & ~SGM_COUNT_ONLY)) return SGM_EINVAL;
@@ -1966,7 +2023,7 @@ int sgm_match_query(sgm_graph *g, const sgm_query *q, uint32_t flags, sgm_result
             return SGM_EDEVICE;
         }
         std::vector<sgm_result *> rv{res};
-        rc = run_queries(g, q, 1, flags, rv);
+        rc = run_queries(g, q, proj, 1, flags, rv);
         if (rc == SGM_OK) rc = res->status;
     }
     res->status = rc;
@@ -1983,8 +2040,8 @@ int sgm_match_query(sgm_graph *g, const sgm_query *q, uint32_t flags, sgm_result
     return rc;
 }
 
-int sgm_match_batch(sgm_graph *g, const sgm_query *qs, int32_t n, uint32_t flags,
-                    sgm_result **out) {
+int match_many(sgm_graph *g, const sgm_query *qs, const uint32_t *proj, int32_t n, uint32_t flags,
+               sgm_result **out) {
     if (!g || !out || n < 0 || (n > 0 && !qs) || (flags & ~SGM_COUNT_ONLY)) return SGM_EINVAL;
     std::vector<sgm_result *> rv((size_t)n, nullptr);
     for (int32_t i = 0; i < n; ++i) {
@@ -1999,7 +2056,7 @@ int sgm_match_batch(sgm_graph *g, const sgm_query *qs, int32_t n, uint32_t flags
     {
         std::lock_guard<std::mutex> lk(g->mu);
         if (hipSetDevice(g->device) != hipSuccess) rc = SGM_EDEVICE;
-        else rc = run_queries(g, qs, n, flags, rv);
+        else rc = run_queries(g, qs, proj, n, flags, rv);
     }
     if (rc != SGM_OK) {
         for (auto *r : rv) sgm_free_result(r);
@@ -2013,6 +2070,34 @@ int sgm_match_batch(sgm_graph *g, const sgm_query *qs, int32_t n, uint32_t flags
         out[i] = rv[i];
     }
     return SGM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sgm_match_query(sgm_graph *g, const sgm_query *q, uint32_t flags, sgm_result **out) {
+    return match_one(g, q, nullptr, flags, out);
+}
+
+int sgm_match_batch(sgm_graph *g, const sgm_query *qs, int32_t n, uint32_t flags,
+                    sgm_result **out) {
+    return match_many(g, qs, nullptr, n, flags, out);
+}
+
+int sgm_match_query_proj(sgm_graph *g, const sgm_query *q, uint32_t project, uint32_t flags,
+                         sgm_result **out) {
+    return match_one(g, q, &project, flags, out);
+}
+
+int sgm_match_batch_proj(sgm_graph *g, const sgm_query *qs, const uint32_t *project, int32_t n,
+                         uint32_t flags, sgm_result **out) {
+    if (n > 0 && !project) {
+        if (out)
+            for (int32_t i = 0; i < n; ++i) out[i] = nullptr;
+        return SGM_EINVAL;
+    }
+    return match_many(g, qs, project, n, flags, out);
 }
 
 int sgm_inspect_query(sgm_graph *g, const sgm_query *q, int64_t *counts, int32_t **ids,

@@ -144,16 +144,23 @@ void launch_keys_to_table(hipStream_t s, const int32_t *keys, const int32_t *key
 // final ordering
 void launch_iota(hipStream_t s, int32_t *idx, int64_t n);
 int64_t small_sort_limit();
+// order of the n rows of a k-wide table by columns colpos[0 .. ncols)
 void launch_sort_small(hipStream_t s, const int32_t *table, int32_t k, const int32_t *colpos,
-                       int32_t n, int32_t *idx);
+                       int32_t ncols, int32_t n, int32_t *idx);
 int64_t radix_tiles(int64_t n);
 void launch_gather_key(hipStream_t s, const int32_t *table, int32_t k, int32_t col,
                        const int32_t *idx, int64_t n, int32_t *key);
 void launch_radix_hist(hipStream_t s, const int32_t *key, int64_t n, int shift, int64_t *hist);
 void launch_radix_scatter(hipStream_t s, const int32_t *key_in, const int32_t *idx_in, int64_t n,
                           int shift, const int64_t *off, int32_t *key_out, int32_t *idx_out);
+// out[i] = columns colpos[0 .. ncols) of row idx[i] of a k-wide table
 void launch_gather_rows(hipStream_t s, const int32_t *table, int32_t k, const int32_t *idx,
-                        int64_t n, const int32_t *colpos, int32_t *out);
+                        int64_t n, const int32_t *colpos, int32_t ncols, int32_t *out);
+// Distinct rows of a sorted n x k table, in order, to out; pos[n] (device)
+// receives their number. head: n int64, pos: n + 1 int64, tmp:
+// scan_tmp_words(n) int64.
+void launch_unique_rows(hipStream_t s, const int32_t *rows, int32_t k, int64_t n, int64_t *head,
+                        int64_t *pos, int64_t *tmp, int32_t *out);
 
 // Ordering key of a row: the ranks of its values among the candidates of
 // their query vertices, concatenated in query-vertex order (nbits[u] bits

@@ -678,6 +678,36 @@ __global__ __launch_bounds__(kBlock) void k_gather_rows(const int32_t *table, in
     }
 }
 
+// Projection (thesis Ch. 3, Sec. "GpSense"): in a table of projected rows
+// sorted lexicographically, equal rows are adjacent; head[i] = 1 for the
+// first row of each run of equal rows.
+__global__ __launch_bounds__(kBlock) void k_row_heads(const int32_t *rows, int32_t k, int64_t n,
+                                                      int64_t *head) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t h = 1;
+        if (i > 0) {
+            h = 0;
+            for (int c = 0; c < k; ++c)
+                if (rows[i * k + c] != rows[(i - 1) * k + c]) h = 1;
+        }
+        head[i] = h;
+    }
+}
+
+// The head rows in order: row i goes to out[pos[i]] (pos = exclusive scan
+// of head).
+__global__ __launch_bounds__(kBlock) void k_compact_rows(const int32_t *rows, int32_t k, int64_t n,
+                                                         const int64_t *head, const int64_t *pos,
+                                                         int32_t *out) {
+    const int64_t total = n * k;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / k;
+        if (head[i]) out[pos[i] * k + (t - i * k)] = rows[t];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -775,10 +805,10 @@ void launch_iota(hipStream_t s, int32_t *idx, int64_t n) {
 }
 
 void launch_sort_small(hipStream_t s, const int32_t *table, int32_t k, const int32_t *colpos,
-                       int32_t n, int32_t *idx) {
+                       int32_t ncols, int32_t n, int32_t *idx) {
     ColPos cp{};
-    for (int c = 0; c < SGM_MAX_QV; ++c) cp.c[c] = c < k ? colpos[c] : 0;
-    hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(1024), 0, s, table, k, cp, k, n, idx);
+    for (int c = 0; c < SGM_MAX_QV; ++c) cp.c[c] = c < ncols ? colpos[c] : 0;
+    hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(1024), 0, s, table, k, cp, ncols, n, idx);
 }
 
 int64_t small_sort_limit() { return kSmallSort; }
@@ -815,11 +845,20 @@ void launch_radix_scatter(hipStream_t s, const int32_t *key_in, const int32_t *i
 }
 
 void launch_gather_rows(hipStream_t s, const int32_t *table, int32_t k, const int32_t *idx,
-                        int64_t n, const int32_t *colpos, int32_t *out) {
+                        int64_t n, const int32_t *colpos, int32_t ncols, int32_t *out) {
     ColPos cp{};
-    for (int c = 0; c < SGM_MAX_QV; ++c) cp.c[c] = c < k ? colpos[c] : 0;
-    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(n * k, kBlock, kGridCap)), dim3(kBlock), 0, s,
-                       table, k, idx, n, cp, k, out);
+    for (int c = 0; c < SGM_MAX_QV; ++c) cp.c[c] = c < ncols ? colpos[c] : 0;
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(n * ncols, kBlock, kGridCap)), dim3(kBlock), 0,
+                       s, table, k, idx, n, cp, ncols, out);
+}
+
+void launch_unique_rows(hipStream_t s, const int32_t *rows, int32_t k, int64_t n, int64_t *head,
+                        int64_t *pos, int64_t *tmp, int32_t *out) {
+    hipLaunchKernelGGL(k_row_heads, dim3(grid_for(n, kBlock, kGridCap)), dim3(kBlock), 0, s, rows,
+                       k, n, head);
+    launch_scan_i64(s, head, n, pos, tmp);
+    hipLaunchKernelGGL(k_compact_rows, dim3(grid_for(n * k, kBlock, kGridCap)), dim3(kBlock), 0, s,
+                       rows, k, n, head, pos, out);
 }
 
 }  // namespace sgm

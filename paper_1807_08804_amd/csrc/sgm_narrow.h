@@ -40,6 +40,7 @@ struct NQuery {
     int32_t root_slot;      // row of the root sweep output, -1 if the root is pinned
     int32_t n_init, n_ref;  // explore steps, then refine steps (one round)
     int32_t refine_rounds;  // -1: until nothing is removed
+    uint32_t proj;          // projected columns (bit u = query vertex u kept; 0: all)
     NStep steps[kNMaxSteps];
     NNbr nbr[kNMaxNbr];
 };
@@ -58,6 +59,7 @@ struct NResult {
     int32_t join_order[SGM_MAX_QV];
     int64_t bytes;         // algorithmic bytes the query's phases moved
     int64_t ticks[4];      // device wall-clock ticks: filter, edges, join, ordering
+    int64_t pbytes[4];     // algorithmic bytes of the same four phases
     int64_t need;          // kWhySlab at a join level: slab bytes its pairs could take
 };
 

@@ -77,6 +77,8 @@ struct Smem {
     int32_t reason;
     int32_t cand[SGM_MAX_QV];
     int32_t bitsn[SGM_MAX_QV];
+    int32_t ocol[SGM_MAX_QV];  // table position of each output column
+    int32_t nout;              // output columns (the projected ones)
     const int32_t *rkl[SGM_MAX_QV];  // list each key column ranks into (LDS copy if it fits)
     int64_t level_rows[SGM_MAX_QV];
     int64_t nrows;
@@ -84,6 +86,7 @@ struct Smem {
     int64_t need;
     unsigned long long bytes;  // algorithmic bytes moved (see add_bytes)
     int64_t t[5];              // wall clock at the phase boundaries
+    unsigned long long pb[5];  // bytes at the phase boundaries
 };
 
 // Dynamic LDS, 54 KB: with the static part a workgroup stays within 64 KB,
@@ -154,8 +157,14 @@ __device__ __forceinline__ void ev(Ctx &c, int code) {
     }
 }
 
+// Phase boundary i (0 start, 1 filtered, 2 edge tables built, 3 joined,
+// 4 ordered and written): its clock and the bytes counted so far. Callers
+// have passed a barrier since the phase's last byte count.
 __device__ __forceinline__ void mark(Ctx &c, int i) {
-    if (threadIdx.x == 0) c.s->t[i] = wall_clock64();
+    if (threadIdx.x == 0) {
+        c.s->t[i] = wall_clock64();
+        c.s->pb[i] = c.s->bytes;
+    }
 }
 
 // All threads call; returns the same pointer everywhere (nullptr + abort on
@@ -1733,7 +1742,10 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         s.qsrc[threadIdx.x] = threadIdx.x < Q.m ? (int8_t)Q.esrc[threadIdx.x] : 0;
         s.qdst[threadIdx.x] = threadIdx.x < Q.m ? (int8_t)Q.edst[threadIdx.x] : 0;
     }
-    if (threadIdx.x < 5) s.t[threadIdx.x] = 0;
+    if (threadIdx.x < 5) {
+        s.t[threadIdx.x] = 0;
+        s.pb[threadIdx.x] = 0ull;
+    }
     if (threadIdx.x == 0) {
         s.abort_ = 0;
         s.slab_used = 0;
@@ -2037,17 +2049,22 @@ __device__ __forceinline__ void run_query(Ctx &c) {
     }
     if (threadIdx.x == 0) s.nrows = rows;
     if (rows > 0) {
-        // ordering: key = concatenated candidate ranks in column order 0..n-1
+        // ordering: key = concatenated candidate ranks in column order 0..n-1;
+        // a projection (thesis Ch. 3, Sec. "GpSense") keys and keeps only
+        // its columns
         __syncthreads();
         if (threadIdx.x == 0) {
-            int tb = 0;
+            int tb = 0, no = 0;
             for (int u = 0; u < n; ++u) {
+                const bool kept = Q.proj == 0u || ((Q.proj >> u) & 1u);
                 int b = 0;
-                while ((1ll << b) < s.cnt[u]) ++b;
+                while (kept && (1ll << b) < s.cnt[u]) ++b;
                 s.bitsn[u] = b;
                 tb += b;
+                if (kept) s.ocol[no++] = s.jpos[u];
             }
             s.ctr = tb;
+            s.nout = no;
         }
         __syncthreads();
         if (s.ctr > 64 && rows > 1) {
@@ -2060,7 +2077,9 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         }
         const int tb = s.ctr;
         const int k = n;
-        const int32_t *idx;
+        const int no = s.nout;
+        int32_t *idx;
+        const uint64_t *skeys = nullptr;  // the sorted keys (rows > 1)
         if (rows > 1) stage_key_lists(c);
         if (rows == 1) {
             int32_t *ix = (int32_t *)c.dyn;
@@ -2084,8 +2103,11 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                         const int32_t lo = 2 * i - (i & (stride - 1));
                         const int32_t hi = lo + stride;
                         const bool up = (lo & size) == 0;
+                        // ties (a key of all ones against the padding)
+                        // by row index, so padding stays last
                         const uint64_t x = keys[lo], y = keys[hi];
-                        if ((x > y) == up) {
+                        const bool gt = x > y || (x == y && ix[lo] > ix[hi]);
+                        if (gt == up) {
                             keys[lo] = y;
                             keys[hi] = x;
                             const int32_t t = ix[lo];
@@ -2097,6 +2119,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                 }
             }
             idx = ix;
+            skeys = keys;
         } else {
             // LSD radix on (key, row) pairs in the slab, 8 bits per pass
             uint64_t *ka = (uint64_t *)slab_alloc(c, 8 * rows);
@@ -2127,10 +2150,30 @@ __device__ __forceinline__ void run_query(Ctx &c) {
             }
             if (threadIdx.x == 0) add_bytes(c, 24ull * rows * ((tb + 7) / 8));
             idx = ia;
+            skeys = ka;
+        }
+        if (Q.proj && rows > 1) {
+            // equal projected rows now have equal, adjacent keys: keep the
+            // first row of each run (in-place compaction of the order)
+            int64_t kept = 0;
+            for (int64_t base = 0; base < rows; base += NT) {
+                const int64_t i = base + threadIdx.x;
+                const bool head = i < rows && (i == 0 || skeys[i] != skeys[i - 1]);
+                const int32_t v = i < rows ? idx[i] : 0;
+                int64_t tot;
+                const int64_t ex = block_excl_scan((int64_t)(head ? 1 : 0), s.sh, &tot);
+                if (head) idx[kept + ex] = v;
+                kept += tot;
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) add_bytes(c, 16ull * rows);
+            rows = kept;
+            if (threadIdx.x == 0) s.nrows = rows;
+            __syncthreads();
         }
         ev(c, SGM_EV_SORT);
         if (threadIdx.x == 0) {
-            const unsigned long long need = (unsigned long long)rows * n;
+            const unsigned long long need = (unsigned long long)rows * no;
             const unsigned long long off = atomicAdd(c.out_used, need);
             s.offset = (off + need <= (unsigned long long)c.out_cap) ? (int64_t)off : -1;
         }
@@ -2141,14 +2184,15 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         } else {
             // one wave per 64 output rows: consecutive lanes write
             // consecutive ints of the rows, columns back in query-vertex
-            // order; e / n by a 16-bit reciprocal (exact for e < 64 n, n <= 16)
+            // order; e / no by a 16-bit reciprocal (exact for e < 64 no,
+            // no <= 16)
             const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-            const uint32_t inv = (65536u + (uint32_t)n - 1u) / (uint32_t)n;
+            const uint32_t inv = (65536u + (uint32_t)no - 1u) / (uint32_t)no;
             for (int64_t r0 = (int64_t)wid * 64; r0 < rows; r0 += NT) {
                 const int32_t my = r0 + lane < rows ? idx[r0 + lane] : 0;
                 const int nr = (int)min((int64_t)64, rows - r0);
-                int32_t *dst = c.out + off + r0 * n;
-                const int ne = nr * n;
+                int32_t *dst = c.out + off + r0 * no;
+                const int ne = nr * no;
                 for (int e0 = 0; e0 < ne; e0 += 256) {
                     // four gathers in flight per lane; every lane takes part
                     // in the shuffles
@@ -2158,14 +2202,14 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                         const int e = e0 + q * 64 + lane;
                         const int r = min(63, (int)(((uint32_t)e * inv) >> 16));
                         const int32_t src = __shfl(my, r, 64);
-                        v[q] = e < ne ? table[(int64_t)src * k + s.jpos[e - r * n]] : 0;
+                        v[q] = e < ne ? table[(int64_t)src * k + s.ocol[e - r * no]] : 0;
                     }
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
                         if (e0 + q * 64 + lane < ne) dst[e0 + q * 64 + lane] = v[q];
                 }
             }
-            if (threadIdx.x == 0) add_bytes(c, 20ull * rows * n);
+            if (threadIdx.x == 0) add_bytes(c, 20ull * rows * no);
         }
     }
     ev(c, SGM_EV_OUTPUT);
@@ -2358,7 +2402,7 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
                 for (int e = 0; e < SGM_MAX_QE; ++e) R.ec[e] = 0;
                 R.bytes = 0;
                 R.need = 0;
-                for (int i = 0; i < 4; ++i) R.ticks[i] = 0;
+                for (int i = 0; i < 4; ++i) R.ticks[i] = R.pbytes[i] = 0;
             }
             continue;
         }
@@ -2380,12 +2424,18 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
             for (int e = 0; e < SGM_MAX_QE; ++e) R.ec[e] = e < Q.m ? s.ectot[e] : 0;
             R.bytes = (int64_t)s.bytes;
             R.need = s.need;
-            // phases a query skipped carry the time of the previous mark
+            // phases a query skipped carry the time and bytes of the
+            // previous mark
             int64_t prev = s.t[0];
+            unsigned long long pbp = 0ull;
             for (int i = 1; i < 5; ++i) {
-                const int64_t ti = s.t[i] ? s.t[i] : prev;
+                const bool hit = s.t[i] != 0;
+                const int64_t ti = hit ? s.t[i] : prev;
+                const unsigned long long bi = hit ? s.pb[i] : pbp;
                 R.ticks[i - 1] = ti - prev;
+                R.pbytes[i - 1] = (int64_t)(bi - pbp);
                 prev = ti;
+                pbp = bi;
             }
         }
     }
@@ -2404,13 +2454,15 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
 // kernel_check, one sweep for all of them): bitmap row j holds the vertices
 // that satisfy root predicate j. Predicates come sorted: the n_any of them
 // without a type first, the typed ones by type. A block owns a tile of 64
-// bitmap words (4096 vertices, 16 per thread, kept in registers after one
+// bitmap words (4096 vertices, 8 per thread, kept in registers after one
 // coalesced read). Per chunk of predicates the tile's rows are built in LDS:
 // untyped predicates by ballot, typed ones by each vertex OR-ing its bit
 // into the rows of the predicates of its own type only (found by binary
 // search), so a vertex is tested against about n_pred / (number of types)
 // predicates instead of all of them. Rows then leave as 512-byte runs.
 constexpr int kSweepTile = 64;    // bitmap words per block
+constexpr int kSweepThreads = 512;                     // 8 waves per block
+constexpr int kSweepSlots = kSweepTile / (kSweepThreads / 64);  // words per wave
 constexpr int kSweepChunk = 64;   // predicates per LDS pass (32 KB of rows)
 // LDS row stride in words. Lanes of one wave OR into the same word of the
 // rows of different predicates; an unpadded stride of 512 bytes would put all
@@ -2419,7 +2471,7 @@ constexpr int kSweepStride = kSweepTile + 1;
 
 constexpr int kSweepTypes = 1024;  // type tables up to this size are staged in LDS
 
-__global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *preds, int32_t n_pred,
+__global__ __launch_bounds__(kSweepThreads) void k_root_sweep(DevGraph g, const VPred *preds, int32_t n_pred,
                                                     int32_t n_any, uint64_t *rootbits,
                                                     unsigned long long *ctr,
                                                     const int32_t *type_off, int32_t n_types) {
@@ -2432,18 +2484,18 @@ __global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *pre
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const bool table = n_types > 0 && n_types <= kSweepTypes;
     if (table)
-        for (int t = threadIdx.x; t <= n_types; t += 256) toff[t] = type_off[t];
+        for (int t = threadIdx.x; t <= n_types; t += kSweepThreads) toff[t] = type_off[t];
     const int32_t w0 = blockIdx.x * kSweepTile;
-    // vertex of slot i: word w0 + 16 * wid + i, bit lane
-    int2 vi[16];
+    // vertex of slot i: word w0 + kSweepSlots * wid + i, bit lane
+    int2 vi[kSweepSlots];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int64_t v = (int64_t)(w0 + 16 * wid + i) * 64 + lane;
+    for (int i = 0; i < kSweepSlots; ++i) {
+        const int64_t v = (int64_t)(w0 + kSweepSlots * wid + i) * 64 + lane;
         vi[i] = v < g.V ? g.vinfo[v] : make_int2(-1, -1);  // type -1: past the end
     }
     for (int32_t c0 = 0; c0 < n_pred; c0 += kSweepChunk) {
         const int cn = min(kSweepChunk, n_pred - c0);
-        for (int i = threadIdx.x; i < cn * kSweepStride; i += 256) rows[i] = 0ull;
+        for (int i = threadIdx.x; i < cn * kSweepStride; i += kSweepThreads) rows[i] = 0ull;
         if ((int)threadIdx.x < cn) {
             const VPred p = preds[c0 + threadIdx.x];
             pl[threadIdx.x] = p;
@@ -2451,26 +2503,27 @@ __global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *pre
         }
         __syncthreads();
         // untyped predicates: the same test for every lane; lane i keeps
-        // the ballot of slot i and lanes 0..15 store the wave's 16 words
+        // the ballot of slot i and the first kSweepSlots lanes store the
+        // wave's words
         for (int j = 0; j < min(n_any - c0, cn); ++j) {
             const int2 q = pq[j];
             uint64_t mine = 0;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < kSweepSlots; ++i) {
                 const bool ok = vi[i].x >= 0 && (vi[i].y & 255) >= q.x && (vi[i].y >> 8) >= q.y;
                 const uint64_t b = __ballot(ok);
                 mine = lane == i ? b : mine;
             }
-            if (lane < 16) rows[j * kSweepStride + 16 * wid + lane] = mine;
+            if (lane < kSweepSlots) rows[j * kSweepStride + kSweepSlots * wid + lane] = mine;
         }
         // typed predicates of this chunk: [t0, cn), sorted by type
         const int t0 = max(0, n_any - c0);
         if (table) {
-            // each vertex's range of predicates of its type, all 16 read
+            // each vertex's range of predicates of its type, all read
             // before any is used (independent LDS reads), packed lo | hi << 16
-            int32_t r[16];
+            int32_t r[kSweepSlots];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < kSweepSlots; ++i) {
                 const int32_t t = vi[i].x;
                 const bool ok = t >= 0 && t < n_types && t0 < cn;
                 const int32_t tc = ok ? t : 0;
@@ -2478,20 +2531,20 @@ __global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *pre
                 r[i] = ok && lo < hi ? (lo | (hi << 16)) : 0;
             }
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < kSweepSlots; ++i) {
                 const int od = vi[i].y & 255, id = vi[i].y >> 8;
                 const int hi = r[i] >> 16;
                 for (int j = r[i] & 0xffff; j < hi; ++j) {
                     const int2 q = pq[j];
                     if (od >= q.x && id >= q.y)
-                        atomicOr((unsigned long long *)&rows[j * kSweepStride + 16 * wid + i],
+                        atomicOr((unsigned long long *)&rows[j * kSweepStride + kSweepSlots * wid + i],
                                  1ull << lane);
                 }
             }
         } else {
             // more types than the table holds: binary search per vertex
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < kSweepSlots; ++i) {
                 const int32_t t = vi[i].x;
                 if (t < 0 || t0 >= cn) continue;
                 int lo = t0, hi = cn;
@@ -2503,12 +2556,12 @@ __global__ __launch_bounds__(256) void k_root_sweep(DevGraph g, const VPred *pre
                 const int od = vi[i].y & 255, id = vi[i].y >> 8;
                 for (int j = lo; j < cn && pl[j].label == t; ++j)
                     if (od >= pq[j].x && id >= pq[j].y)
-                        atomicOr((unsigned long long *)&rows[j * kSweepStride + 16 * wid + i],
+                        atomicOr((unsigned long long *)&rows[j * kSweepStride + kSweepSlots * wid + i],
                                  1ull << lane);
             }
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < cn * kSweepTile; k += 256) {
+        for (int k = threadIdx.x; k < cn * kSweepTile; k += kSweepThreads) {
             const int j = k / kSweepTile, w = k % kSweepTile;
             if (w0 + w < g.nwords) rootbits[(int64_t)(c0 + j) * g.nwords + w0 + w] = rows[j * kSweepStride + w];
         }
@@ -2532,7 +2585,7 @@ int sweep_grid(const SweepArgs &a) {
 }  // namespace
 
 void launch_root_sweep(hipStream_t s, const SweepArgs &a) {
-    hipLaunchKernelGGL(k_root_sweep, dim3(sweep_grid(a)), dim3(256), 0, s, a.g, a.preds, a.n_pred,
+    hipLaunchKernelGGL(k_root_sweep, dim3(sweep_grid(a)), dim3(kSweepThreads), 0, s, a.g, a.preds, a.n_pred,
                        a.n_any, a.rootbits, a.ctr, a.type_off, a.n_types);
 }
 
@@ -2550,7 +2603,7 @@ void narrow_node_params(SweepArgs *sa, NArgs *na, int narrow_grid, void **args,
     *sweep = hipKernelNodeParams{};
     sweep->func = reinterpret_cast<void *>(&k_root_sweep);
     sweep->gridDim = dim3(sweep_grid(*sa));
-    sweep->blockDim = dim3(256);
+    sweep->blockDim = dim3(kSweepThreads);
     sweep->sharedMemBytes = 0;
     sweep->kernelParams = args;
     sweep->extra = nullptr;

@@ -56,6 +56,16 @@ int check_query(const sgm_query *q, int32_t V, QInfo *qi) {
         frontier = next;
     }
     if (seen != ((n == 32) ? 0xffffffffu : ((1u << n) - 1u))) return SGM_EINVAL;
+    qi->proj = 0;
+    qi->n_out = n;
+    return SGM_OK;
+}
+
+int set_projection(QInfo *qi, uint32_t mask) {
+    const uint32_t all = (1u << qi->n) - 1u;
+    if (mask == 0 || (mask & ~all)) return SGM_EINVAL;
+    qi->proj = mask == all ? 0u : mask;
+    qi->n_out = __builtin_popcount(mask);
     return SGM_OK;
 }
 

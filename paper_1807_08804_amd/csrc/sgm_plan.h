@@ -19,7 +19,16 @@ struct QInfo {
     int32_t qout[SGM_MAX_QV];       // distinct out-neighbours
     int32_t qin[SGM_MAX_QV];        // distinct in-neighbours
     int32_t deg[SGM_MAX_QV];        // distinct neighbours, either direction
+    // projection (thesis Ch. 3, Sec. "GpSense": only the matches of a subset
+    // of the query's nodes are wanted): bit u set = column u is returned;
+    // 0 = every column (no projection). n_out = columns returned.
+    uint32_t proj;
+    int32_t n_out;
 };
+
+// Set a projection on a checked query: SGM_EINVAL for an empty mask or bits
+// beyond its vertices; a mask naming every vertex means no projection.
+int set_projection(QInfo *qi, uint32_t mask);
 
 // Spanning tree T and orders of the filtering phase.
 struct Plan {
@@ -44,9 +53,25 @@ struct PStep {
 struct PNbr {
     int v, dir, rel, mode;  // dir 0: out-edges of the candidate; mode 0: bitmap test
 };
+// A vector of at most N elements stored in place (planning allocates no
+// memory, so the entry point that allocates nothing can plan too).
+template <class T, int N>
+struct FixedVec {
+    T v[N];
+    int n = 0;
+    void clear() { n = 0; }
+    void push_back(const T &x) { v[n++] = x; }
+    int size() const { return n; }
+    bool empty() const { return n == 0; }
+    const T &operator[](int i) const { return v[i]; }
+    const T *begin() const { return v; }
+    const T *end() const { return v + n; }
+};
+// Explore steps hold each tree edge twice at most (2 (n - 1) entries),
+// refine steps each query edge twice at most (2 m).
 struct Program {
-    std::vector<PStep> init, refine;
-    std::vector<PNbr> nbr;
+    FixedVec<PStep, SGM_MAX_QV> init, refine;
+    FixedVec<PNbr, 2 * SGM_MAX_QV + 2 * SGM_MAX_QE> nbr;
 };
 void build_program(const QInfo &qi, const Plan &pl, int low_conn_degree, int refine_reversed,
                    Program *pr);

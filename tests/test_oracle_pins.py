@@ -352,3 +352,61 @@ def test_more_constraints_give_subsets(seed):
                         np.append(q.elabel, -1))
         pairs = {(s, d) for s, d, _ in E}
         assert rows_of(og.match_query(qe)) == [r for r in base if (r[a], r[b]) in pairs]
+
+
+# --------------------------------------------------------------------------
+# projection (the distinct projected tuples of all matches)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(12))
+def test_projection_bruteforce_micro(seed):
+    """The oracle's projection of its table equals the set of projected
+    tuples of the brute-force matches, sorted, for every non-empty subset of
+    a micro query's vertices."""
+    rng = np.random.default_rng(1000 + seed)
+    g = random_graph(rng, V=int(rng.integers(4, 9)), E=int(rng.integers(4, 20)), n_types=2,
+                     n_rels=2)
+    q = random_query(rng, int(rng.integers(2, 5)), 2, 2, g.V, p_pin=0.1)
+    og = og_of(g)
+    full = og.match_query(q)
+    bf = brute_force(g, q)
+    for mask in range(1, 1 << q.n):
+        cols = [u for u in range(q.n) if (mask >> u) & 1]
+        want = sorted({tuple(r[u] for u in cols) for r in bf})
+        got = oracle.project_rows(full, cols)
+        assert got.shape == (len(want), len(cols))
+        assert [tuple(r) for r in got.tolist()] == want
+
+
+def test_projection_closed_forms_medium(medium_kg, oracle_medium):
+    """On the medium graph (simple, no self-loops): projecting an unlabelled
+    edge a -> b onto a gives the vertices of out-degree >= 1, onto b those of
+    in-degree >= 1; a star with a type-5 centre and leaves of types 3 and 7,
+    onto its centre, gives the type-5 vertices with an out-neighbour of each
+    type; a 2-path a -> b -> c with typed ends onto (a, c) gives the ordered
+    pairs at distance two through some b with a != c (sparse A^2 off the
+    diagonal)."""
+    import scipy.sparse as sp
+    kg = medium_kg
+    outdeg = np.diff(kg.row_ptr)
+    indeg = np.bincount(kg.col, minlength=kg.V)
+    src = kg.src()
+    e = MicroQuery(2, [-1, -1], [-1, -1], [0], [1], [-1])
+    rows = oracle_medium.match_query(e)
+    assert np.array_equal(oracle.project_rows(rows, [0])[:, 0], np.nonzero(outdeg >= 1)[0])
+    assert np.array_equal(oracle.project_rows(rows, [1])[:, 0], np.nonzero(indeg >= 1)[0])
+    star = MicroQuery(3, [5, 3, 7], [-1, -1, -1], [0, 0], [1, 2], [-1, -1])
+    got = oracle.project_rows(oracle_medium.match_query(star), [0])
+    has3 = np.zeros(kg.V, bool)
+    has7 = np.zeros(kg.V, bool)
+    has3[src[kg.vtype[kg.col] == 3]] = True
+    has7[src[kg.vtype[kg.col] == 7]] = True
+    assert np.array_equal(got[:, 0], np.nonzero(has3 & has7 & (kg.vtype == 5))[0])
+    p2 = MicroQuery(3, [3, -1, 7], [-1, -1, -1], [0, 1], [1, 2], [-1, -1])
+    got = oracle.project_rows(oracle_medium.match_query(p2), [0, 2])
+    A = sp.csr_matrix((np.ones(kg.E), kg.col, kg.row_ptr), shape=(kg.V, kg.V))
+    A2 = (A @ A).tocoo()
+    keep = (A2.row != A2.col) & (kg.vtype[A2.row] == 3) & (kg.vtype[A2.col] == 7)
+    want = np.stack([A2.row[keep], A2.col[keep]], axis=1)
+    want = want[np.lexsort((want[:, 1], want[:, 0]))]
+    assert np.array_equal(got, want)
