@@ -388,6 +388,34 @@ int sgm_inspect_query(sgm_graph *g, const sgm_query *q, int64_t *counts, int32_t
                       int64_t *ec);
 void sgm_free_ids(int32_t *ids);
 
+/*
+ * sgm_match_query for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid allocation; the call synchronises
+ * with its stream, so it cannot be captured into a HIP graph): the same
+ * match on the persistent kernel,
+ * with every device buffer taken from one fixed 64 MB area of device memory
+ * that the library holds on each GPU until the process ends (its address
+ * is taken once per device when a graph is loaded). No hipMalloc, hipFree,
+ * pinned-host allocation or other allocating routine is called.
+ *   rows:     caller-owned host buffer of rows_cap * n_vertices int32 (may
+ *             be NULL with SGM_COUNT_ONLY or rows_cap = 0); receives the
+ *             sorted table as sgm_match_query's result rows;
+ *   rows_cap: capacity of rows in rows (>= 0);
+ *   *n_rows:  the exact number of matches (also on SGM_ETOOBIG).
+ * Limits and errors: SGM_EUNSUPPORTED if the graph is too large for the
+ * area (one slot needs 17 V-bit bitmaps, 16 candidate lists of min(V, 65536)
+ * ints and a 16 MB slab, and at least 1 MB must remain for the output
+ * table: about 19M vertices at most) or the query needs a 128-bit ordering
+ * key; SGM_ENOMEM if the query outgrows the area's slot or output table
+ * (sgm_match_query then still answers it); SGM_ETOOBIG if more than rows_cap
+ * rows match (rows untouched); SGM_EINVAL / SGM_EUNSUPPORTED for queries as
+ * sgm_match_query; SGM_EDEVICE. The area keeps each call's contents; calls
+ * on one device are serialised inside the library (one area per device).
+ * No statistics are returned.
+ */
+int sgm_match_query_noalloc(sgm_graph *g, const sgm_query *q, uint32_t flags, int32_t *rows,
+                            int64_t rows_cap, int64_t *n_rows);
+
 /* ------------------------------------------------------------------------
  * Served form: a request loop that keeps the graph resident, admits arriving
  * queries against an intermediate-memory cap, batches them as they come and

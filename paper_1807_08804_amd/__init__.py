@@ -128,6 +128,8 @@ EXPORTS = {
     "sgm_reset_kernel_stats": (ctypes.c_int, [ctypes.c_void_p]),
     "sgm_plan_query": (ctypes.c_int, [ctypes.POINTER(sgm_query), ctypes.c_int32, _i64p,
                                       ctypes.c_int32, _i32p, _i32p, _i32p, _i32p]),
+    "sgm_match_query_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query),
+                                               ctypes.c_uint32, _i32p, ctypes.c_int64, _i64p]),
     "sgm_estimate_query": (ctypes.c_int, [ctypes.POINTER(sgm_query), ctypes.c_int32, ctypes.c_int64,
                                           _i64p, ctypes.c_int32, _i64p, ctypes.c_int32, _i64p]),
     "sgm_inspect_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query), _i64p,
@@ -408,6 +410,26 @@ class Graph:
 
     def match_query(self, q, **kw):
         return self.match(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel, **kw)
+
+    def match_query_noalloc(self, q, rows_cap: int, count_only=False, out=None):
+        """sgm_match_query_noalloc: the table in a caller-owned int32 buffer
+        of rows_cap rows (``out``, allocated here when not given): returns
+        the view of its first n_rows rows, or the count when count_only.
+        Raises SGMError (with the exact n_rows on ETOOBIG)."""
+        sq, keep = _make_query(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel)
+        if out is None and not count_only:
+            out = np.empty((max(int(rows_cap), 0), q.n), np.int32)
+        ptr = None if count_only else out.ctypes.data_as(_i32p)
+        n = ctypes.c_int64(0)
+        rc = lib().sgm_match_query_noalloc(self._h, ctypes.byref(sq),
+                                           SGM_COUNT_ONLY if count_only else SGM_SORTED, ptr,
+                                           int(rows_cap), ctypes.byref(n))
+        if rc != SGM_OK:
+            err = SGMError(rc, "sgm_match_query_noalloc")
+            err.n_rows = int(n.value)
+            raise err
+        k = int(n.value)
+        return k if count_only else out.reshape(-1, q.n)[:k]
 
     def match_batch(self, queries, count_only=False, with_stats=False, projects=None):
         """Results (arrays, counts, or SGMError instances) for a list of

@@ -33,6 +33,8 @@ namespace {
 
 thread_local std::string g_last_error;
 
+int scratch_setup(int device);
+
 void set_error(const char *what, hipError_t e) {
     char buf[256];
     std::snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
@@ -1837,6 +1839,10 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
     g->n_big = nbig;
     try {
         HIPX(hipSetDevice(g->device));
+        // the fixed device area of sgm_match_query_noalloc: its address on
+        // this device, taken once per device (on failure only that entry
+        // point is unavailable; it reports the error)
+        (void)scratch_setup(g->device);
         HIPX(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
         g->nw.stream = g->stream;
         g->nwb.stream = g->stream;
@@ -2617,6 +2623,213 @@ int sgm_serve_replay(sgm_server *s, const sgm_query *qs, const int64_t *arrival_
     }
     sub.join();
     return ret;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Single queries without allocation: every device buffer of the persistent
+// kernel's launch (one slot, descriptor, result, counters, helper board,
+// root sweep row, output arena) lives in one fixed array of device memory
+// that each GPU holds until the process ends.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int64_t kScratchBytes = 64ll << 20;     // the whole fixed area
+constexpr int64_t kScratchSlab = 16ll << 20;      // slab of its one slot
+constexpr int64_t kScratchMinOut = 1ll << 20;     // smallest output arena accepted (bytes)
+constexpr int kScratchDevices = 64;
+
+}  // namespace
+
+// The fixed area. Host code never uses this name as an address: kernels and
+// copies get the per-device address that hipGetSymbolAddress returned.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {};
+std::mutex g_scratch_call_mu[kScratchDevices];  // calls on one device run one at a time
+// Leading 8-byte words of each device's slot bitmaps known to be zero: the
+// kernel clears the bitmaps it set, but a graph with more vertices lays its
+// bitmaps over what other buffers of an earlier call held.
+int64_t g_scratch_zero_words[kScratchDevices] = {};
+
+// Device address of the fixed area on the current device (once per device;
+// called by sgm_load_graph with the graph's device current).
+int scratch_setup(int device) {
+    if (device < 0 || device >= kScratchDevices) return SGM_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return SGM_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        set_error("hipGetSymbolAddress(scratch)", e);
+        return SGM_EDEVICE;
+    }
+    g_scratch_ptr[device] = p;
+    return SGM_OK;
+}
+
+__global__ void k_zero_words(uint64_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+// Layout of the fixed area for a graph (byte offsets, 256-aligned).
+struct ScratchLayout {
+    int64_t bits, lists, slab, rootbits, preds, q, res, ctr, board, out, out_bytes;
+    int32_t lcap;
+    bool fits;
+};
+
+int64_t align256(int64_t x) { return (x + 255) & ~255ll; }
+
+// The small fixed-size buffers come first, at the same offsets for every
+// graph; the slot bitmaps follow at a fixed offset too.
+ScratchLayout scratch_layout(const sgm_graph *g) {
+    ScratchLayout L{};
+    L.lcap = std::min<int32_t>(g->V, kNarrowListCap);
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    L.board = take(sizeof(HelpJob));
+    L.ctr = take(sizeof(unsigned long long) * 3);
+    L.q = take(sizeof(NQuery));
+    L.res = take(sizeof(NResult));
+    L.preds = take(sizeof(VPred));
+    L.bits = take((int64_t)(SGM_MAX_QV + 1) * g->nwords * 8);
+    L.lists = take((int64_t)SGM_MAX_QV * L.lcap * 4);
+    L.slab = take(kScratchSlab);
+    L.rootbits = take((int64_t)g->nwords * 8);
+    L.out = o;
+    L.out_bytes = (kScratchBytes - o) & ~255ll;
+    L.fits = L.out_bytes >= kScratchMinOut && kScratchSlab >= 8ll * L.lcap;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sgm_match_query_noalloc(sgm_graph *g, const sgm_query *q, uint32_t flags, int32_t *rows,
+                            int64_t rows_cap, int64_t *n_rows) {
+    if (n_rows) *n_rows = 0;
+    if (!g || !q || !n_rows || (flags & ~SGM_COUNT_ONLY) || rows_cap < 0 ||
+        (!(flags & SGM_COUNT_ONLY) && rows_cap > 0 && !rows))
+        return SGM_EINVAL;
+    QInfo qi;
+    int rc = check_query(q, g->V, &qi);
+    if (rc != SGM_OK) return rc;
+    if (g->device < 0 || g->device >= kScratchDevices || !g_scratch_ptr[g->device]) {
+        g_last_error = "the fixed device area of this device has no address";
+        return SGM_EDEVICE;
+    }
+    const ScratchLayout L = scratch_layout(g);
+    if (!L.fits) {
+        g_last_error = "graph too large for the fixed device area (64 MB)";
+        return SGM_EUNSUPPORTED;
+    }
+    Plan pl;
+    if (make_plan(qi, g->V, g->type_freq.data(), g->n_types, &pl) != SGM_OK) return SGM_EINVAL;
+    NQuery nq;
+    Plan pl_out;
+    int root_slots = 0;
+    if (!pack_query(g, qi, pl, &nq, &root_slots, &pl_out)) {
+        g_last_error = "query plan exceeds the packed descriptor";
+        return SGM_EUNSUPPORTED;
+    }
+    const bool sweep = nq.root_slot >= 0;
+    if (sweep) nq.root_slot = 0;
+    const VPred rootp = VPred{nq.pred[nq.root].label, -1, nq.pred[nq.root].qout,
+                              nq.pred[nq.root].qin};
+    std::lock_guard<std::mutex> call(g_scratch_call_mu[g->device]);
+    std::lock_guard<std::mutex> lk(g->mu);
+    char *base = (char *)g_scratch_ptr[g->device];
+    NResult r;
+    try {
+        HIPX(hipSetDevice(g->device));
+        hipStream_t st = g->stream;
+        unsigned long long *ctr = (unsigned long long *)(base + L.ctr);
+        // what must start at zero: the helper board entry (every call), the
+        // slot bitmaps where an earlier call on another graph left other
+        // data (the kernel clears the bitmaps it sets); the sweep zeroes the
+        // work queue, the output counter and the helper counters. The zero
+        // fill covers the front of the area, so it runs before the uploads.
+        const int64_t bit_words = (int64_t)(SGM_MAX_QV + 1) * g->nwords;
+        const bool clear_bits = g_scratch_zero_words[g->device] < bit_words;
+        const int64_t zero_words = clear_bits ? (L.bits + 8 * bit_words) / 8 : L.ctr / 8;
+        g_scratch_zero_words[g->device] = 0;  // until this call has ended normally
+        hipLaunchKernelGGL(k_zero_words, dim3(clear_bits ? 256 : 1), dim3(256), 0, st,
+                           (uint64_t *)base, zero_words);
+        HIPX(hipGetLastError());
+        HIPX(hipMemcpyAsync(base + L.q, &nq, sizeof(NQuery), hipMemcpyHostToDevice, st));
+        if (sweep)
+            HIPX(hipMemcpyAsync(base + L.preds, &rootp, sizeof(VPred), hipMemcpyHostToDevice, st));
+        launch_root_sweep(st, SweepArgs{g->dg, (const VPred *)(base + L.preds), sweep ? 1 : 0,
+                                        sweep && rootp.label < 0 ? 1 : 0,
+                                        (uint64_t *)(base + L.rootbits), ctr, nullptr, 0});
+        HIPX(hipGetLastError());
+        NArgs a{};
+        a.g = g->dg;
+        a.qs = (const NQuery *)(base + L.q);
+        a.nq = 1;
+        a.res = (NResult *)(base + L.res);
+        a.queue = (int32_t *)ctr;
+        a.bits = (uint64_t *)(base + L.bits);
+        a.lists = (int32_t *)(base + L.lists);
+        a.lcap = L.lcap;
+        a.slab = base + L.slab;
+        a.slab_bytes = kScratchSlab;
+        a.rootbits = (const uint64_t *)(base + L.rootbits);
+        a.out = (int32_t *)(base + L.out);
+        a.out_cap = L.out_bytes / 4;
+        a.out_used = ctr + 1;
+        a.group_lanes = g->tune.group_lanes;
+        a.wg_rows = g->tune.wg_rows;
+        a.join_policy = g->tune.join_policy;
+        a.nslot = 1;
+        a.help_items = g->tune.help_items;
+        a.board = (HelpJob *)(base + L.board);
+        a.hctr = (int32_t *)(ctr + 2);
+        a.help_wait = g->tune.help_wait > 0 ? g->tune.help_wait : kHelpWaitDefault;
+        const int grid = a.help_items > 0 ? std::min(kNarrowMaxSlots, std::max(1, g->tune.helpers)) : 1;
+        a.ngrid = grid;
+        launch_narrow(st, a, grid);
+        HIPX(hipGetLastError());
+        HIPX(hipMemcpyAsync(&r, base + L.res, sizeof(NResult), hipMemcpyDeviceToHost, st));
+        HIPX(hipStreamSynchronize(st));
+        // the kernel left the slot bitmaps zero, unless its owner gave up on
+        // a shared step (helpers may then have written any of them): the
+        // next call clears them first
+        if (!(r.status != SGM_OK && r.reason == kWhyHelp)) g_scratch_zero_words[g->device] = bit_words;
+        if (r.status != SGM_OK) {
+            g_last_error = r.status == kOutFull || r.reason == kWhySlab || r.reason == kWhyList
+                               ? "query outgrows the fixed device area (use sgm_match_query)"
+                               : "query needs a path the fixed device area does not hold "
+                                 "(use sgm_match_query)";
+            return r.reason == kWhyKey ? SGM_EUNSUPPORTED : SGM_ENOMEM;
+        }
+        *n_rows = r.n_rows;
+        if (flags & SGM_COUNT_ONLY) return SGM_OK;
+        if (r.n_rows > rows_cap) return SGM_ETOOBIG;
+        const size_t bytes = sizeof(int32_t) * (size_t)r.n_rows * (size_t)qi.n;
+        if (bytes) {
+            HIPX(hipMemcpyAsync(rows, base + L.out + 4 * r.offset, bytes, hipMemcpyDeviceToHost, st));
+            HIPX(hipStreamSynchronize(st));
+        }
+    } catch (const DeviceError &e) {
+        (void)hipStreamSynchronize(g->stream);
+        (void)hipGetLastError();
+        return e.code;
+    }
+    return SGM_OK;
 }
 
 }  // extern "C"
