@@ -2454,14 +2454,14 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
 // kernel_check, one sweep for all of them): bitmap row j holds the vertices
 // that satisfy root predicate j. Predicates come sorted: the n_any of them
 // without a type first, the typed ones by type. A block owns a tile of 64
-// bitmap words (4096 vertices, 8 per thread, kept in registers after one
+// bitmap words (4096 vertices, 16 per thread, kept in registers after one
 // coalesced read). Per chunk of predicates the tile's rows are built in LDS:
 // untyped predicates by ballot, typed ones by each vertex OR-ing its bit
 // into the rows of the predicates of its own type only (found by binary
 // search), so a vertex is tested against about n_pred / (number of types)
 // predicates instead of all of them. Rows then leave as 512-byte runs.
 constexpr int kSweepTile = 64;    // bitmap words per block
-constexpr int kSweepThreads = 512;                     // 8 waves per block
+constexpr int kSweepThreads = 256;                     // 4 waves per block
 constexpr int kSweepSlots = kSweepTile / (kSweepThreads / 64);  // words per wave
 constexpr int kSweepChunk = 64;   // predicates per LDS pass (32 KB of rows)
 // LDS row stride in words. Lanes of one wave OR into the same word of the
