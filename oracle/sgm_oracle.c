@@ -21,8 +21,9 @@
  * ascending lexicographic order. Several data relations between the same
  * pair still give one row, because a match is the vertex map.
  *
- * How: plain depth-first backtracking over the query vertices in a fixed
- * connected order, testing each condition above directly. It performs no
+ * How: plain depth-first backtracking over the query vertices, testing each
+ * condition above directly; the next vertex placed is a pinned one, else the
+ * one whose candidates (the entries of a placed neighbour's row) are fewest. It performs no
  * candidate filtering of any kind: every check is one clause of the
  * definition. A vertex's candidates are read from the adjacency row of an
  * already-placed neighbour, indexed by relation and by the neighbour's type
@@ -236,8 +237,6 @@ static int has_edge(const oracle_graph *g, int32_t x, int32_t y, int32_t rho) {
 typedef struct {
     int32_t n, m;
     const int32_t *vlabel, *vpin, *esrc, *edst, *elabel;
-    int32_t order[OR_MAXQ];
-    int32_t pos[OR_MAXQ];          /* pos[u] = depth of u in order */
 } or_query;
 
 typedef struct {
@@ -259,36 +258,122 @@ static int buf_push(or_buf *b, const int32_t *row, int32_t n) {
     return 0;
 }
 
+
 /* Clauses 1-4 of the definition for query vertex u mapped to data vertex x,
- * against every query vertex placed earlier in the order. */
-static int consistent(const oracle_graph *g, const or_query *q, const int32_t *f, int depth, int32_t u,
-                      int32_t x) {
+ * against every query vertex already placed (bit v of placed). */
+static int consistent(const oracle_graph *g, const or_query *q, const int32_t *f, uint32_t placed,
+                      int32_t u, int32_t x) {
     if (q->vlabel[u] >= 0 && g->vtype[x] != q->vlabel[u]) return 0;
     if (q->vpin[u] >= 0 && x != q->vpin[u]) return 0;
-    for (int d = 0; d < depth; d++)
-        if (f[q->order[d]] == x) return 0;
+    for (int v = 0; v < q->n; v++)
+        if (((placed >> v) & 1u) && f[v] == x) return 0;
     for (int i = 0; i < q->m; i++) {
         int32_t a = q->esrc[i], b = q->edst[i];
-        if (a == u && q->pos[b] < depth) {
+        if (a == u && ((placed >> b) & 1u)) {
             if (!has_edge(g, x, f[b], q->elabel[i])) return 0;
-        } else if (b == u && q->pos[a] < depth) {
+        } else if (b == u && ((placed >> a) & 1u)) {
             if (!has_edge(g, f[a], x, q->elabel[i])) return 0;
         }
     }
     return 1;
 }
 
-/* A unit of the parallel search: root candidate x, and either the whole
- * search below it (hi < 0) or the second vertex's candidates from entries
- * [lo, hi) of row array arr. */
-typedef struct {
-    int32_t x;
-    int64_t lo, hi;
-    const or_pair *arr;
-} or_item;
+/* Narrow [lo, hi) of a row sorted with key(entry) ascending to the entries
+ * whose key equals k: key 0 = relation, 1 = type of the other endpoint. */
+static void key_slice(const oracle_graph *g, const or_pair *arr, int64_t *lo, int64_t *hi,
+                      int key, int32_t k) {
+#define OR_KEY(e) (key == 0 ? (e).rel : g->vtype[(e).dst])
+    int64_t a = *lo, b = *hi;
+    while (a < b) { /* first entry with key >= k */
+        int64_t mid = a + (b - a) / 2;
+        if (OR_KEY(arr[mid]) < k) a = mid + 1;
+        else b = mid;
+    }
+    int64_t c = a, d = *hi;
+    while (c < d) { /* first entry with key > k */
+        int64_t mid = c + (d - c) / 2;
+        if (OR_KEY(arr[mid]) <= k) c = mid + 1;
+        else d = mid;
+    }
+#undef OR_KEY
+    *lo = a;
+    *hi = c;
+}
 
-/* Row entries per work item of a split root. */
-#define OR_PIECE 4096
+/* The data entries that generate the candidates of an unpinned vertex u,
+ * from the placed neighbour whose entries are fewest: for a query edge
+ * a -> u the out-row of f(a), for u -> b the in-row of f(b); of that row
+ * only the entries of the edge's relation (a labelled edge) and of u's type
+ * (a typed u), read from a copy of the row sorted by those keys, since any
+ * other entry fails clause 2 or clause 4 for this edge. 0 if u has no
+ * placed neighbour. */
+static int gen_range(const oracle_graph *g, const or_query *q, const int32_t *f, uint32_t placed,
+                     int32_t u, int64_t *lo_out, int64_t *hi_out, const or_pair **arr_out) {
+    int best_len_set = 0;
+    int64_t best_lo = 0, best_hi = 0;
+    const or_pair *best_arr = NULL;
+    for (int i = 0; i < q->m; i++) {
+        int32_t a = q->esrc[i], b = q->edst[i], rho = q->elabel[i], t = q->vlabel[u];
+        int64_t lo, hi;
+        const or_pair *arr;
+        if (b == u && ((placed >> a) & 1u)) { /* f(a) -> x : x among out-neighbours of f(a) */
+            lo = g->out_off[f[a]];
+            hi = g->out_off[f[a] + 1];
+            arr = rho >= 0 ? g->out_r : t >= 0 ? g->out_t : g->out;
+        } else if (a == u && ((placed >> b) & 1u)) { /* x -> f(b) : x among in-neighbours */
+            lo = g->in_off[f[b]];
+            hi = g->in_off[f[b] + 1];
+            arr = rho >= 0 ? g->in_r : t >= 0 ? g->in_t : g->in;
+        } else {
+            continue;
+        }
+        if (rho >= 0) key_slice(g, arr, &lo, &hi, 0, rho);
+        if (t >= 0) key_slice(g, arr, &lo, &hi, 1, t);
+        if (!best_len_set || hi - lo < best_hi - best_lo) {
+            best_len_set = 1;
+            best_lo = lo;
+            best_hi = hi;
+            best_arr = arr;
+        }
+    }
+    *lo_out = best_lo;
+    *hi_out = best_hi;
+    *arr_out = best_arr;
+    return best_len_set;
+}
+
+/* The next vertex to place (fail first): an unplaced pinned vertex (one
+ * candidate), else the unplaced vertex with a placed neighbour whose
+ * generating entries are fewest (lowest index on ties). Every order places
+ * each vertex once and checks every clause against all placed vertices, so
+ * the order decides only how fast the search runs. Returns the vertex; its
+ * entries in *lo..*hi of *arr (hi < 0 for a pinned vertex). */
+static int32_t pick_next(const oracle_graph *g, const or_query *q, const int32_t *f,
+                         uint32_t placed, int64_t *lo_out, int64_t *hi_out,
+                         const or_pair **arr_out) {
+    int32_t best = -1;
+    int64_t best_len = 0;
+    for (int32_t v = 0; v < q->n; v++) {
+        if ((placed >> v) & 1u) continue;
+        if (q->vpin[v] >= 0) {
+            *lo_out = 0;
+            *hi_out = -1;
+            *arr_out = NULL;
+            return v;
+        }
+        int64_t lo, hi;
+        const or_pair *arr;
+        if (!gen_range(g, q, f, placed, v, &lo, &hi, &arr)) continue;
+        if (best < 0 || hi - lo < best_len) {
+            best = v;
+            best_len = hi - lo;
+            *lo_out = lo;
+            *hi_out = hi;
+            *arr_out = arr;
+        }
+    }
+    return best;
+}
 
 typedef struct {
     const oracle_graph *g;
@@ -316,12 +401,12 @@ static int over_budget(or_ctx *c) {
     return 0;
 }
 
-static void dfs_range(or_ctx *c, int32_t *f, int depth, int64_t lo, int64_t hi,
-                      const or_pair *arr);
-static int gen_range(const oracle_graph *g, const or_query *q, const int32_t *f, int depth,
-                     int32_t u, int64_t *lo_out, int64_t *hi_out, const or_pair **arr_out);
+static void dfs_range(or_ctx *c, int32_t *f, uint32_t placed, int depth, int32_t u, int64_t lo,
+                      int64_t hi, const or_pair *arr);
 
-static void dfs(or_ctx *c, int32_t *f, int depth) {
+/* Extend the partial map f (vertices in placed, depth of them) by one more
+ * vertex; a full map is one row. */
+static void dfs(or_ctx *c, int32_t *f, uint32_t placed, int depth) {
     const or_query *q = c->q;
     const oracle_graph *g = c->g;
     if (__atomic_load_n(c->abort_flag, __ATOMIC_RELAXED)) return;
@@ -337,107 +422,55 @@ static void dfs(or_ctx *c, int32_t *f, int depth) {
         }
         return;
     }
-    int32_t u = q->order[depth];
-    if (q->vpin[u] >= 0) {
+    int64_t lo, hi;
+    const or_pair *arr;
+    int32_t u = pick_next(g, q, f, placed, &lo, &hi, &arr);
+    if (u < 0) return; /* unreachable for connected queries */
+    if (hi < 0) {
         int32_t x = q->vpin[u];
-        if (consistent(g, q, f, depth, u, x)) {
+        if (consistent(g, q, f, placed, u, x)) {
             f[u] = x;
-            dfs(c, f, depth + 1);
+            dfs(c, f, placed | (1u << u), depth + 1);
         }
         return;
     }
-    int64_t lo, hi;
-    const or_pair *arr;
-    if (!gen_range(g, q, f, depth, u, &lo, &hi, &arr)) return; /* unreachable past depth 0 */
-    dfs_range(c, f, depth, lo, hi, arr);
+    dfs_range(c, f, placed, depth, u, lo, hi, arr);
 }
 
-/* Candidates of vertex order[depth] from entries [lo, hi) of the data row
- * gen_range chose (a full row is sorted by destination, and a repeated
- * destination, i.e. another relation, is one candidate; a relation's slice
- * holds each destination once). */
-static void dfs_range(or_ctx *c, int32_t *f, int depth, int64_t lo, int64_t hi,
-                      const or_pair *arr) {
+/* Candidates of vertex u from entries [lo, hi) of the data row gen_range
+ * chose (a full row is sorted by destination, and a repeated destination,
+ * i.e. another relation, is one candidate; a relation's slice holds each
+ * destination once; pieces of a row never split a run of equal
+ * destinations). */
+static void dfs_range(or_ctx *c, int32_t *f, uint32_t placed, int depth, int32_t u, int64_t lo,
+                      int64_t hi, const or_pair *arr) {
     const or_query *q = c->q;
     const oracle_graph *g = c->g;
-    int32_t u = q->order[depth];
-    int32_t prev = -1; /* pieces of a row never split a run of equal destinations */
+    int32_t prev = -1;
     for (int64_t k = lo; k < hi; k++) {
         int32_t x = arr[k].dst;
         if (x == prev) continue; /* same neighbour, other relation */
         prev = x;
         if (over_budget(c)) return;
-        if (consistent(g, q, f, depth, u, x)) {
+        if (consistent(g, q, f, placed, u, x)) {
             f[u] = x;
-            dfs(c, f, depth + 1);
+            dfs(c, f, placed | (1u << u), depth + 1);
             if (__atomic_load_n(c->abort_flag, __ATOMIC_RELAXED)) return;
         }
     }
 }
 
-/* Narrow [lo, hi) of a row sorted with key(entry) ascending to the entries
- * whose key equals k: key 0 = relation, 1 = type of the other endpoint. */
-static void key_slice(const oracle_graph *g, const or_pair *arr, int64_t *lo, int64_t *hi,
-                      int key, int32_t k) {
-#define OR_KEY(e) (key == 0 ? (e).rel : g->vtype[(e).dst])
-    int64_t a = *lo, b = *hi;
-    while (a < b) { /* first entry with key >= k */
-        int64_t mid = a + (b - a) / 2;
-        if (OR_KEY(arr[mid]) < k) a = mid + 1;
-        else b = mid;
-    }
-    int64_t c = a, d = *hi;
-    while (c < d) { /* first entry with key > k */
-        int64_t mid = c + (d - c) / 2;
-        if (OR_KEY(arr[mid]) <= k) c = mid + 1;
-        else d = mid;
-    }
-#undef OR_KEY
-    *lo = a;
-    *hi = c;
-}
+/* A unit of the parallel search: root candidate x, and either the whole
+ * search below it (hi < 0) or the second vertex's candidates from entries
+ * [lo, hi) of row array arr. */
+typedef struct {
+    int32_t x, u2;
+    int64_t lo, hi;
+    const or_pair *arr;
+} or_item;
 
-/* The data entries that generate the candidates of vertex u at this depth,
- * from the already-placed neighbour whose entries are fewest: for a query
- * edge a -> u the out-row of f(a), for u -> b the in-row of f(b); of that
- * row only the entries of the edge's relation (a labelled edge) and of u's
- * type (a typed u), read from a copy of the row sorted by those keys, since
- * any other entry fails clause 2 or clause 4 for this edge. 0 if u has no
- * placed neighbour. */
-static int gen_range(const oracle_graph *g, const or_query *q, const int32_t *f, int depth,
-                     int32_t u, int64_t *lo_out, int64_t *hi_out, const or_pair **arr_out) {
-    int best_len_set = 0;
-    int64_t best_lo = 0, best_hi = 0;
-    const or_pair *best_arr = NULL;
-    for (int i = 0; i < q->m; i++) {
-        int32_t a = q->esrc[i], b = q->edst[i], rho = q->elabel[i], t = q->vlabel[u];
-        int64_t lo, hi;
-        const or_pair *arr;
-        if (b == u && q->pos[a] < depth) { /* f(a) -> x : x among out-neighbours of f(a) */
-            lo = g->out_off[f[a]];
-            hi = g->out_off[f[a] + 1];
-            arr = rho >= 0 ? g->out_r : t >= 0 ? g->out_t : g->out;
-        } else if (a == u && q->pos[b] < depth) { /* x -> f(b) : x among in-neighbours */
-            lo = g->in_off[f[b]];
-            hi = g->in_off[f[b] + 1];
-            arr = rho >= 0 ? g->in_r : t >= 0 ? g->in_t : g->in;
-        } else {
-            continue;
-        }
-        if (rho >= 0) key_slice(g, arr, &lo, &hi, 0, rho);
-        if (t >= 0) key_slice(g, arr, &lo, &hi, 1, t);
-        if (!best_len_set || hi - lo < best_hi - best_lo) {
-            best_len_set = 1;
-            best_lo = lo;
-            best_hi = hi;
-            best_arr = arr;
-        }
-    }
-    *lo_out = best_lo;
-    *hi_out = best_hi;
-    *arr_out = best_arr;
-    return best_len_set;
-}
+/* Row entries per work item of a split root. */
+#define OR_PIECE 4096
 
 static int row_cmp(const void *a, const void *b, void *arg) {
     const int32_t *x = (const int32_t *)a, *y = (const int32_t *)b;
@@ -535,26 +568,6 @@ int oracle_match_budget(const oracle_graph *g, int32_t n, int32_t m, const int32
             }
         }
     }
-    /* BFS order over the undirected query graph, neighbours by index */
-    int placed[OR_MAXQ] = {0};
-    int head = 0, tail = 0;
-    q.order[tail++] = root;
-    placed[root] = 1;
-    while (head < tail) {
-        int32_t u = q.order[head++];
-        for (int32_t v = 0; v < n; v++) {
-            if (placed[v]) continue;
-            int adj = 0;
-            for (int i = 0; i < m && !adj; i++)
-                adj = (esrc[i] == u && edst[i] == v) || (esrc[i] == v && edst[i] == u);
-            if (adj) {
-                placed[v] = 1;
-                q.order[tail++] = v;
-            }
-        }
-    }
-    for (int d = 0; d < n; d++) q.pos[q.order[d]] = d;
-
     /* first-level candidates */
     int32_t *roots = NULL;
     int64_t n_roots = 0;
@@ -571,24 +584,25 @@ int oracle_match_budget(const oracle_graph *g, int32_t n, int32_t m, const int32
     }
 
     /* Work items for the threads: a root candidate with the whole search
-     * below it, or, when the second vertex in the order is generated from a
-     * data row, a root candidate with a piece of that row (so that a hub
-     * root's search is spread over threads). Pieces never split a run of
-     * equal destinations. Every item is an independent part of the same
-     * depth-first search; rows are sorted at the end, so the split does not
-     * change the result. */
+     * below it, or, when the second vertex placed (chosen as in dfs) is
+     * generated from a data row, a root candidate with a piece of that row
+     * (so that a hub root's search is spread over threads). Pieces never
+     * split a run of equal destinations. Every item is an independent part
+     * of the same depth-first search; rows are sorted at the end, so the
+     * split does not change the result. */
     or_item *items = NULL;
     int64_t n_items = 0, cap_items = 0;
     {
         int32_t f0[OR_MAXQ];
+        const uint32_t p0 = 1u << root;
         for (int64_t i = 0; i < n_roots; i++) {
             int32_t x = roots[i];
-            if (!consistent(g, &q, f0, 0, root, x)) continue;
+            if (!consistent(g, &q, f0, 0u, root, x)) continue;
             f0[root] = x;
             int64_t lo = 0, hi = -1;
             const or_pair *arr = NULL;
-            int split = n > 1 && vpin[q.order[1]] < 0 &&
-                        gen_range(g, &q, f0, 1, q.order[1], &lo, &hi, &arr);
+            const int32_t u2 = n > 1 ? pick_next(g, &q, f0, p0, &lo, &hi, &arr) : -1;
+            int split = u2 >= 0 && hi >= 0;
             int64_t a = split ? lo : 0, end = split ? hi : 0;
             do {
                 int64_t b = split ? (end - a > OR_PIECE ? a + OR_PIECE : end) : 0;
@@ -604,6 +618,7 @@ int oracle_match_budget(const oracle_graph *g, int32_t n, int32_t m, const int32
                     items = t;
                 }
                 items[n_items].x = x;
+                items[n_items].u2 = u2;
                 items[n_items].lo = split ? a : 0;
                 items[n_items].hi = split ? b : -1;
                 items[n_items].arr = arr;
@@ -643,8 +658,8 @@ int oracle_match_budget(const oracle_graph *g, int32_t n, int32_t m, const int32
             if (__atomic_load_n(&abort_flag, __ATOMIC_RELAXED)) continue;
             if (over_budget(&c)) continue;
             f[root] = items[i].x;
-            if (items[i].hi < 0) dfs(&c, f, 1);
-            else dfs_range(&c, f, 1, items[i].lo, items[i].hi, items[i].arr);
+            if (items[i].hi < 0) dfs(&c, f, 1u << root, 1);
+            else dfs_range(&c, f, 1u << root, 1, items[i].u2, items[i].lo, items[i].hi, items[i].arr);
         }
     }
     free(items);

@@ -87,6 +87,8 @@ def main():
                     help="candidate tests per query (cyclic)")
     ap.add_argument("--row-cap", type=int, default=100_000_000,
                     help="largest table materialised and hashed")
+    ap.add_argument("--retry-unfinished", action="store_true",
+                    help="compute again the entries recorded as unfinished")
     args = ap.parse_args()
     doc = {}
     if os.path.exists(PATH):
@@ -113,7 +115,8 @@ def main():
         doc[name] = sec
         t0 = time.time()
         for i, q in enumerate(qs):
-            if str(i) in sec["entries"]:
+            e = sec["entries"].get(str(i))
+            if e is not None and not (args.retry_unfinished and "unfinished" in e):
                 continue
             e, el = one(og, q, budget, args.row_cap)
             e["oracle_s"] = round(el, 3)
