@@ -276,6 +276,9 @@ def bench_large(args, P, kggen):
     el_b = time.perf_counter() - t
     log(f"batched: {args.steps} x {len(queries)} in {el_b:.3f}s (default tuning {el_default:.3f}s)")
     gp.set_tuning(**tuned)
+    # one query at a time with the library's default tuning (its work
+    # sharing serves single queries; the batch's pick may switch it off)
+    g.set_tuning(**default_tuning)
     for q in queries[:32]:
         g.match_query(q)
     lat = []

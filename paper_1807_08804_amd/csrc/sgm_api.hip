@@ -226,6 +226,8 @@ struct sgm_graph {
     int32_t *d_out_off = nullptr, *d_in_off = nullptr;
     int2 *d_vinfo = nullptr;
     int2 *d_out_adj = nullptr, *d_in_adj = nullptr;
+    int2 *d_out_ta = nullptr, *d_out_tb = nullptr, *d_in_ta = nullptr, *d_in_tb = nullptr;
+    int32_t *d_hub_of = nullptr, *d_hub_toff = nullptr;
     uint64_t *d_bits = nullptr;   // [SGM_MAX_QV + 1][nwords] (last: push scratch)
     int32_t *d_lists = nullptr;   // [SGM_MAX_QV][V]
     int32_t *d_prefix = nullptr;  // [SGM_MAX_QV][nwords + 1]
@@ -387,7 +389,8 @@ void free_graph_mem(sgm_graph *g) {
     for (hipEvent_t e : g->ev_rows)
         if (e) (void)hipEventDestroy(e);
     void *dp[] = {g->d_out_off, g->d_in_off, g->d_vinfo, g->d_out_adj, g->d_in_adj, g->d_bits,
-                  g->d_lists,   g->d_prefix, g->d_big,   g->d_desc,    g->d_cnt,    g->d_slots};
+                  g->d_lists,   g->d_prefix, g->d_big,   g->d_desc,    g->d_cnt,    g->d_slots,
+                  g->d_out_ta,  g->d_out_tb, g->d_in_ta, g->d_in_tb,   g->d_hub_of, g->d_hub_toff};
     for (void *p : dp)
         if (p) (void)hipFree(p);
     void *hp[] = {g->h_desc, g->h_cnt, g->h_slots, g->h_small, g->h_rows};
@@ -396,6 +399,68 @@ void free_graph_mem(sgm_graph *g) {
     narrow_free(g->nw);
     narrow_free(g->nwb);
     if (g->stream) (void)hipStreamDestroy(g->stream);
+}
+
+// Hub-row index (DevGraph::out_ta ... hub_toff): copies of the adjacency
+// arrays whose hub rows are re-sorted by the other end's type first, and
+// per hub, direction, order and type the offset of the type's first entry.
+struct HubIndex {
+    std::vector<int2> out_ta, out_tb, in_ta, in_tb;
+    std::vector<int32_t> hub_of, toff;
+    int32_t types = 0;
+};
+
+void build_hub_index(int32_t V, const std::vector<int32_t> &off, const std::vector<int2> &adj,
+                     const std::vector<int32_t> &in_off, const std::vector<int2> &in_adj,
+                     const int32_t *type, int32_t n_types, HubIndex *h) {
+    h->types = n_types + 1;
+    h->hub_of.assign((size_t)V, -1);
+    std::vector<int32_t> hubs;
+    for (int32_t v = 0; v < V; ++v)
+        if (off[v + 1] - off[v] >= kHubRow || in_off[v + 1] - in_off[v] >= kHubRow) {
+            h->hub_of[v] = (int32_t)hubs.size();
+            hubs.push_back(v);
+        }
+    h->out_ta = adj;
+    h->out_tb = adj;
+    h->in_ta = in_adj;
+    h->in_tb = in_adj;
+    h->toff.assign(hubs.size() * 4 * (size_t)h->types, 0);
+    auto by_type_rel = [&](const int2 &a, const int2 &b) {
+        const int32_t ta = type[a.x], tb = type[b.x];
+        return ta != tb ? ta < tb : (a.y != b.y ? a.y < b.y : a.x < b.x);
+    };
+    auto by_type_end = [&](const int2 &a, const int2 &b) {
+        const int32_t ta = type[a.x], tb = type[b.x];
+        return ta != tb ? ta < tb : (a.x != b.x ? a.x < b.x : a.y < b.y);
+    };
+    auto work = [&](size_t lo, size_t hi) {
+        for (size_t k = lo; k < hi; ++k) {
+            const int32_t v = hubs[k];
+            for (int dir = 0; dir < 2; ++dir) {
+                const std::vector<int32_t> &o = dir ? in_off : off;
+                const int32_t b = o[v], e = o[v + 1];
+                for (int order = 0; order < 2; ++order) {
+                    std::vector<int2> &arr =
+                        dir ? (order ? h->in_tb : h->in_ta) : (order ? h->out_tb : h->out_ta);
+                    if (order) std::sort(arr.begin() + b, arr.begin() + e, by_type_end);
+                    else std::sort(arr.begin() + b, arr.begin() + e, by_type_rel);
+                    int32_t *t = &h->toff[((k * 2 + dir) * 2 + order) * (size_t)h->types];
+                    int32_t i = b;
+                    for (int32_t ty = 0; ty < h->types; ++ty) {
+                        while (i < e && type[arr[i].x] < ty) ++i;
+                        t[ty] = i - b;
+                    }
+                }
+            }
+        }
+    };
+    const size_t nt = std::max<size_t>(1, std::min<size_t>(8, hubs.size() / 16));
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < nt; ++t)
+        th.emplace_back(work, hubs.size() * t / nt, hubs.size() * (t + 1) / nt);
+    work(0, hubs.size() / nt);
+    for (auto &x : th) x.join();
 }
 
 // ---------------------------------------------------------------------------
@@ -462,6 +527,156 @@ int32_t *alloc_rows(size_t bytes) {
         return (int32_t *)p;
     }
     return (int32_t *)std::malloc(std::max<size_t>(bytes, 4));
+}
+
+// Host memory of the result tables of one persistent launch: a pinned block
+// into which the output arena (and the tables the host orders) are copied
+// straight from the device, with no second copy on the host; the results
+// point into it and hold a reference each. A block whose last result is
+// freed is kept for later launches (a few of them), so a steady stream of
+// batches reuses pinned, already-mapped memory.
+struct RowBlock {
+    char *ptr = nullptr;
+    size_t cap = 0;
+    std::atomic<int64_t> refs{0};
+};
+
+std::mutex g_blk_mu;
+std::vector<RowBlock *> g_blk_free;
+constexpr size_t kKeepBlocks = 3;
+constexpr size_t kBlockMin = (size_t)4 << 20;  // launches returning less copy as before
+
+RowBlock *block_get(size_t bytes) {
+    {
+        std::lock_guard<std::mutex> lk(g_blk_mu);
+        int best = -1;
+        for (size_t i = 0; i < g_blk_free.size(); ++i)
+            if (g_blk_free[i]->cap >= bytes &&
+                (best < 0 || g_blk_free[i]->cap < g_blk_free[(size_t)best]->cap))
+                best = (int)i;
+        if (best >= 0) {
+            RowBlock *b = g_blk_free[(size_t)best];
+            g_blk_free.erase(g_blk_free.begin() + best);
+            return b;
+        }
+    }
+    RowBlock *b = new RowBlock();
+    const size_t cap = std::max(bytes + (bytes >> 3), kBlockMin);
+    if (hipHostMalloc((void **)&b->ptr, cap, hipHostMallocDefault) != hipSuccess) {
+        delete b;
+        throw DeviceError{SGM_ENOMEM};
+    }
+    b->cap = cap;
+    return b;
+}
+
+void block_release(RowBlock *b) {
+    if (b->refs.fetch_sub(1) != 1) return;
+    RowBlock *drop = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_blk_mu);
+        g_blk_free.push_back(b);
+        if (g_blk_free.size() > kKeepBlocks) {
+            // drop the smallest kept block
+            size_t k = 0;
+            for (size_t i = 1; i < g_blk_free.size(); ++i)
+                if (g_blk_free[i]->cap < g_blk_free[k]->cap) k = i;
+            drop = g_blk_free[k];
+            g_blk_free.erase(g_blk_free.begin() + (long)k);
+        }
+    }
+    if (drop) {
+        (void)hipHostFree(drop->ptr);
+        delete drop;
+    }
+}
+
+// Every result the library hands out is the first member of a box that
+// knows whether its rows live in a block.
+struct ResultBox {
+    sgm_result r;
+    RowBlock *blk;
+};
+
+sgm_result *result_new() {
+    ResultBox *b = (ResultBox *)std::calloc(1, sizeof(ResultBox));
+    return b ? &b->r : nullptr;
+}
+
+RowBlock *&result_block(sgm_result *r) { return reinterpret_cast<ResultBox *>(r)->blk; }
+
+// Release a result's rows (its block reference, or its own buffer).
+void result_drop_rows(sgm_result *r) {
+    RowBlock *&b = result_block(r);
+    if (b) block_release(b);
+    else std::free(r->rows);
+    b = nullptr;
+    r->rows = nullptr;
+}
+
+// Copy a device table to host memory through two pinned staging halves of
+// kStageBytes on stream st (the host copy of one chunk overlaps the
+// transfer of the next). Caller holds g->mu.
+void readback_rows(sgm_graph *g, hipStream_t st, const int32_t *dev, size_t bytes, int32_t *host) {
+    if (bytes == 0) return;
+    const size_t half = std::min(bytes, kStageBytes);
+    if (g->h_rows_cap < 2 * half) {
+        if (g->h_rows) (void)hipHostFree(g->h_rows);
+        g->h_rows = nullptr;
+        g->h_rows_cap = 0;
+        const size_t cap = std::max<size_t>(2 * half, 1 << 20);
+        HIPX(hipHostMalloc(&g->h_rows, cap, hipHostMallocDefault));
+        g->h_rows_cap = cap;
+    }
+    for (hipEvent_t &e : g->ev_rows)
+        if (!e) HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    char *stage[2] = {(char *)g->h_rows, (char *)g->h_rows + half};
+    const size_t nch = (bytes + half - 1) / half;
+    auto issue = [&](size_t i) {
+        const size_t off = i * half, len = std::min(half, bytes - off);
+        HIPX(hipMemcpyAsync(stage[i & 1], (const char *)dev + off, len, hipMemcpyDeviceToHost, st));
+        HIPX(hipEventRecord(g->ev_rows[i & 1], st));
+    };
+    issue(0);
+    for (size_t i = 0; i < nch; ++i) {
+        if (i + 1 < nch) issue(i + 1);  // its half was copied out last round
+        HIPX(hipEventSynchronize(g->ev_rows[i & 1]));
+        const size_t off = i * half, len = std::min(half, bytes - off);
+        parallel_copy({HostCopy{(char *)host + off, stage[i & 1], len}});
+    }
+}
+
+// Order n rows by 64-bit keys of tb bits with whole-GPU LSD radix passes
+// (stable, 8-bit digits over the 32-bit halves); returns the order.
+int32_t *order_by_keys(sgm_graph *g, Scope &sc, const uint64_t *keys, int64_t n, int tb) {
+    int32_t *ia = sc.get<int32_t>(n), *ib = sc.get<int32_t>(n);
+    int32_t *ka = sc.get<int32_t>(n), *kb = sc.get<int32_t>(n);
+    const int64_t tiles = radix_tiles(n);
+    int64_t *hist = sc.get<int64_t>(256 * tiles);
+    int64_t *hoff = sc.get<int64_t>(256 * tiles + 1);
+    int64_t *tmp = sc.get<int64_t>(scan_tmp_words(256 * tiles) + 1);
+    hipStream_t st = g->stream;
+    {
+        Prof p(g, SGM_K_SORT, 4.0 * n);
+        launch_iota(st, ia, n);
+    }
+    for (int half = 0; half < 2; ++half) {
+        const int hb = half == 0 ? std::min(tb, 32) : tb - 32;
+        if (hb <= 0) break;
+        {
+            Prof p(g, SGM_K_SORT, 16.0 * n);
+            launch_key_half(st, keys, ia, n, half, ka);
+        }
+        for (int sh = 0; sh < hb; sh += 8) {
+            Prof p(g, SGM_K_SORT, 20.0 * n);
+            launch_radix_hist(st, ka, n, sh, hist);
+            launch_scan_i64(st, hist, 256 * tiles, hoff, tmp);
+            launch_radix_scatter(st, ka, ia, n, sh, hoff, kb, ib);
+            std::swap(ka, kb);
+            std::swap(ia, ib);
+        }
+    }
+    return ia;
 }
 
 struct Query {
@@ -1000,36 +1215,9 @@ struct Query {
         }
         if (!copy) return R;
         const size_t bytes = sizeof(int32_t) * (size_t)R * no;
-        // readback through two pinned staging halves of kStageBytes: the
-        // host copy of one chunk overlaps the transfer of the next
-        const size_t half = std::min(bytes, kStageBytes);
-        if (g->h_rows_cap < 2 * half) {
-            if (g->h_rows) (void)hipHostFree(g->h_rows);
-            g->h_rows = nullptr;
-            g->h_rows_cap = 0;
-            const size_t cap = std::max<size_t>(2 * half, 1 << 20);
-            HIPX(hipHostMalloc(&g->h_rows, cap, hipHostMallocDefault));
-            g->h_rows_cap = cap;
-        }
-        for (hipEvent_t &e : g->ev_rows)
-            if (!e) HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         res->rows = alloc_rows(bytes);
         if (!res->rows) throw DeviceError{SGM_ENOMEM};
-        char *stage[2] = {(char *)g->h_rows, (char *)g->h_rows + half};
-        const size_t nch = (bytes + half - 1) / half;
-        auto issue = [&](size_t i) {
-            const size_t off = i * half, len = std::min(half, bytes - off);
-            HIPX(hipMemcpyAsync(stage[i & 1], (const char *)out + off, len, hipMemcpyDeviceToHost,
-                                st()));
-            HIPX(hipEventRecord(g->ev_rows[i & 1], st()));
-        };
-        issue(0);
-        for (size_t i = 0; i < nch; ++i) {
-            if (i + 1 < nch) issue(i + 1);  // its half was copied out last round
-            HIPX(hipEventSynchronize(g->ev_rows[i & 1]));
-            const size_t off = i * half, len = std::min(half, bytes - off);
-            parallel_copy({HostCopy{(char *)res->rows + off, stage[i & 1], len}});
-        }
+        readback_rows(g, st(), out, bytes, res->rows);
         return R;
     }
 
@@ -1160,6 +1348,8 @@ constexpr int64_t kNarrowSlabMax = 32ll << 20;       // per slot, large graphs (
 // A graph's own batch context: 40 B per data vertex up to 160 MB per slot
 // (512 slots of a 4M-vertex graph hold about 87 GB of HBM), so that queries
 // with tables of ~1e6 rows finish in their slot and a batch is one launch.
+constexpr int32_t kHubTypesMax = 4096;    // more vertex types: no hub-row index
+constexpr int64_t kHostOrderRows = 65536;  // final tables from this size are ordered by the host
 constexpr int64_t kBatchSlabPerVertex = 40;
 constexpr int64_t kBatchSlabMax = 160ll << 20;
 constexpr int32_t kNarrowListCap = 1 << 16;          // per query vertex
@@ -1459,6 +1649,9 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     a.board = nw.d_board;
     a.hctr = (int32_t *)(nw.d_ctr + 2);
     a.help_wait = g->tune.help_wait > 0 ? g->tune.help_wait : kHelpWaitDefault;
+    // the graph's own contexts hand large final tables to the host for
+    // whole-GPU ordering (a server's completers do not hold the graph)
+    a.host_order_rows = nw.serve ? 0 : kHostOrderRows;
     const int grid =
         help ? std::min(kNarrowMaxSlots, std::max(slot_grid, g->tune.helpers)) : slot_grid;
     a.ngrid = grid;
@@ -1574,7 +1767,35 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         g->kstat[SGM_K_PERSIST].bytes_total += b;
     }
     const int64_t used = std::min<int64_t>((int64_t)nw.h_ctr[1], nw.out_cap);
-    if (!(flags & SGM_COUNT_ONLY) && used > kOutPrefix) {
+    const bool want = !(flags & SGM_COUNT_ONLY);
+    // bytes of rows this launch returns: the arena's used part, and room for
+    // the large tables the host orders
+    size_t host_bytes = 0;
+    for (int i = 0; i < np; ++i) {
+        const NResult &r = nw.h_res[i];
+        if (r.status == SGM_OK && r.host_order)
+            host_bytes += ((size_t)r.n_rows * qis[job.packed[i]].n_out * 4 + 255) & ~(size_t)255;
+    }
+    const size_t arena_bytes = ((size_t)used * 4 + 255) & ~(size_t)255;
+    RowBlock *blk = nullptr;
+    size_t blk_next = arena_bytes;  // next free byte of the block (host-ordered tables)
+    // this call's own reference to the block, dropped when it returns (or
+    // throws): a block that no result took goes back to the pool
+    struct Hold {
+        RowBlock *b = nullptr;
+        ~Hold() {
+            if (b) block_release(b);
+        }
+    } hold;
+    if (want && arena_bytes + host_bytes >= kBlockMin) {
+        blk = block_get(arena_bytes + host_bytes);
+        blk->refs.store(1);
+        hold.b = blk;
+        if (used > 0)
+            HIPX(hipMemcpyAsync(blk->ptr, nw.d_out, sizeof(int32_t) * used, hipMemcpyDeviceToHost,
+                                st));
+        HIPX(hipStreamSynchronize(st));
+    } else if (want && used > kOutPrefix) {
         // the launch read back the first kOutPrefix ints; the rest now
         int64_t from = kOutPrefix;
         if (nw.h_out_cap < used) {
@@ -1591,6 +1812,7 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
     }
     const int64_t t1 = now_ns();
     std::vector<HostCopy> copies;
+    std::vector<int> hostord;
     if (job.traced)
         for (int i = 0; i < np; ++i) {
             const size_t q = (size_t)job.packed[i];
@@ -1638,19 +1860,94 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         stt.device_bytes = r.bytes;
         for (int i = 0; i < 4; ++i) stt.phase_bytes[i] = r.pbytes[i];
         stt.path = SGM_PATH_NARROW;
+        if (r.host_order) {
+            hostord.push_back(i);
+            continue;
+        }
         if (g->opts.result_cap_rows > 0 && r.n_rows > g->opts.result_cap_rows) {
             out->status = SGM_ETOOBIG;
             continue;
         }
         out->status = SGM_OK;
-        if (!(flags & SGM_COUNT_ONLY)) {
+        if (want) {
             const size_t bytes = sizeof(int32_t) * (size_t)r.n_rows * qi.n_out;
-            out->rows = alloc_rows(bytes);
-            if (!out->rows) throw std::bad_alloc();
-            if (bytes) copies.push_back({out->rows, nw.h_out + r.offset, bytes});
+            if (blk) {
+                out->rows = (int32_t *)blk->ptr + r.offset;
+                result_block(out) = blk;
+                blk->refs.fetch_add(1);
+            } else {
+                out->rows = alloc_rows(bytes);
+                if (!out->rows) throw std::bad_alloc();
+                if (bytes) copies.push_back({out->rows, nw.h_out + r.offset, bytes});
+            }
         }
     }
     parallel_copy(copies);
+    // large final tables the kernel left unordered in its slots' slabs:
+    // order them (and collapse projections) with whole-GPU kernels on this
+    // context's stream (the graph's own; caller holds g->mu), then read them
+    // back
+    for (int i : hostord) {
+        const NResult &r = nw.h_res[i];
+        const int qi_idx = job.packed[i];
+        sgm_result *out = res[qi_idx];
+        const QInfo &qi = qis[qi_idx];
+        const int n = qi.n;
+        int32_t jpos[SGM_MAX_QV], colpos[SGM_MAX_QV];
+        for (int l = 0; l < n; ++l) jpos[r.join_order[l]] = l;
+        int no = 0;
+        for (int u = 0; u < n; ++u)
+            if (!qi.proj || ((qi.proj >> u) & 1u)) colpos[no++] = jpos[u];
+        int64_t R = r.n_rows;
+        const bool rows_wanted = !(flags & SGM_COUNT_ONLY);
+        if (rows_wanted || qi.proj) {
+            Scope sc(g->pool);
+            const int32_t *table = (const int32_t *)(uintptr_t)r.table_ptr;
+            const uint64_t *keys = (const uint64_t *)(uintptr_t)r.key_ptr;
+            const int32_t *idx = order_by_keys(g, sc, keys, R, r.key_bits);
+            int32_t *sorted = sc.get<int32_t>(R * no);
+            {
+                Prof p(g, SGM_K_OTHER, 8.0 * R * no);
+                launch_gather_rows(st, table, n, idx, R, colpos, no, sorted);
+            }
+            if (qi.proj && R > 1) {
+                int64_t *head = sc.get<int64_t>(R), *pos = sc.get<int64_t>(R + 1);
+                int64_t *tmp = sc.get<int64_t>(scan_tmp_words(R) + 1);
+                int32_t *uniq = sc.get<int32_t>(R * no);
+                {
+                    Prof p(g, SGM_K_OTHER, 8.0 * R * no + 24.0 * R);
+                    launch_unique_rows(st, sorted, no, R, head, pos, tmp, uniq);
+                }
+                HIPX(hipMemcpyAsync(g->h_small, pos + R, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                    st));
+                HIPX(hipStreamSynchronize(st));
+                R = g->h_small[0];
+                sorted = uniq;
+            }
+            out->n_rows = R;
+            if (rows_wanted && !(g->opts.result_cap_rows > 0 && R > g->opts.result_cap_rows)) {
+                const size_t bytes = sizeof(int32_t) * (size_t)R * no;
+                if (blk) {
+                    // straight into the pinned block (room was set aside)
+                    out->rows = (int32_t *)(blk->ptr + blk_next);
+                    blk_next += (bytes + 255) & ~(size_t)255;
+                    result_block(out) = blk;
+                    blk->refs.fetch_add(1);
+                    if (bytes)
+                        HIPX(hipMemcpyAsync(out->rows, sorted, bytes, hipMemcpyDeviceToHost, st));
+                    HIPX(hipStreamSynchronize(st));
+                } else {
+                    out->rows = alloc_rows(bytes);
+                    if (!out->rows) throw std::bad_alloc();
+                    readback_rows(g, st, sorted, bytes, out->rows);
+                }
+            }
+        }
+        out->n_rows = R;
+        out->status = g->opts.result_cap_rows > 0 && R > g->opts.result_cap_rows ? SGM_ETOOBIG
+                                                                                 : SGM_OK;
+    }
+    if (profiled) prof_flush(g);
 }
 
 // Run queries `which` (validated into qis) through the persistent kernel on
@@ -1861,6 +2158,17 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
             vi[v] = make_int2(type[v], std::min(off[v + 1] - off[v], 255) |
                                            std::min(in_off[v + 1] - in_off[v], 255) << 8);
         g->d_vinfo = dev_upload(vi);
+        if (g->n_types <= kHubTypesMax) {
+            HubIndex hx;
+            build_hub_index(n_vertices, off, adj, in_off, in_adj, type, g->n_types, &hx);
+            g->d_out_ta = dev_upload(hx.out_ta);
+            g->d_out_tb = dev_upload(hx.out_tb);
+            g->d_in_ta = dev_upload(hx.in_ta);
+            g->d_in_tb = dev_upload(hx.in_tb);
+            g->d_hub_of = dev_upload(hx.hub_of);
+            g->d_hub_toff = dev_upload(hx.toff);
+            g->dg.hub_types = hx.types;
+        }
         HIPX(hipMalloc(&g->d_bits, sizeof(uint64_t) * (size_t)(SGM_MAX_QV + 1) * g->nwords));
         HIPX(hipMalloc(&g->d_lists, sizeof(int32_t) * (size_t)SGM_MAX_QV * g->V));
         HIPX(hipMalloc(&g->d_prefix, sizeof(int32_t) * (size_t)SGM_MAX_QV * (g->nwords + 1)));
@@ -1879,6 +2187,12 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
         g->dg.out_adj = g->d_out_adj;
         g->dg.in_adj = g->d_in_adj;
         g->dg.vinfo = g->d_vinfo;
+        g->dg.out_ta = g->d_out_ta;
+        g->dg.out_tb = g->d_out_tb;
+        g->dg.in_ta = g->d_in_ta;
+        g->dg.in_tb = g->d_in_tb;
+        g->dg.hub_of = g->d_hub_of;
+        g->dg.hub_toff = g->d_hub_toff;
         HIPX(hipDeviceSynchronize());
     } catch (const DeviceError &e) {
         free_graph_mem(g);
@@ -2019,7 +2333,7 @@ int match_one(sgm_graph *g, const sgm_query *q, const uint32_t *proj, uint32_t f
     if (!out) return SGM_EINVAL;
     *out = nullptr;
     if (!g || !q || (flags & ~SGM_COUNT_ONLY)) return SGM_EINVAL;
-    sgm_result *res = (sgm_result *)std::calloc(1, sizeof(sgm_result));
+    sgm_result *res = result_new();
     if (!res) return SGM_ENOMEM;
     int rc;
     {
@@ -2034,15 +2348,11 @@ int match_one(sgm_graph *g, const sgm_query *q, const uint32_t *proj, uint32_t f
     }
     res->status = rc;
     if (rc == SGM_OK || rc == SGM_ETOOBIG) {
-        if (rc != SGM_OK) {
-            std::free(res->rows);
-            res->rows = nullptr;
-        }
+        if (rc != SGM_OK) result_drop_rows(res);
         *out = res;
         return rc;
     }
-    std::free(res->rows);
-    std::free(res);
+    sgm_free_result(res);
     return rc;
 }
 
@@ -2052,9 +2362,9 @@ int match_many(sgm_graph *g, const sgm_query *qs, const uint32_t *proj, int32_t 
     std::vector<sgm_result *> rv((size_t)n, nullptr);
     for (int32_t i = 0; i < n; ++i) {
         out[i] = nullptr;
-        rv[i] = (sgm_result *)std::calloc(1, sizeof(sgm_result));
+        rv[i] = result_new();
         if (!rv[i]) {
-            for (int32_t j = 0; j < i; ++j) std::free(rv[j]);
+            for (int32_t j = 0; j < i; ++j) sgm_free_result(rv[j]);
             return SGM_ENOMEM;
         }
     }
@@ -2069,10 +2379,7 @@ int match_many(sgm_graph *g, const sgm_query *qs, const uint32_t *proj, int32_t 
         return rc;
     }
     for (int32_t i = 0; i < n; ++i) {
-        if (rv[i]->status != SGM_OK) {
-            std::free(rv[i]->rows);
-            rv[i]->rows = nullptr;
-        }
+        if (rv[i]->status != SGM_OK) result_drop_rows(rv[i]);
         out[i] = rv[i];
     }
     return SGM_OK;
@@ -2141,8 +2448,8 @@ void sgm_free_ids(int32_t *ids) { std::free(ids); }
 
 void sgm_free_result(sgm_result *r) {
     if (!r) return;
-    std::free(r->rows);
-    std::free(r);
+    result_drop_rows(r);
+    std::free(reinterpret_cast<ResultBox *>(r));
 }
 
 int sgm_kernel_stats(sgm_graph *g, int32_t kernel, sgm_kstat *out) {
@@ -2313,10 +2620,7 @@ void serve_finish(sgm_server *S, uint64_t id, int64_t est, int64_t t_done) {
     t.t_done = t_done;
     t.done = true;
     sgm_result *r = t.res;
-    if (r->status != SGM_OK && r->status != SGM_ETOOBIG) {
-        std::free(r->rows);
-        r->rows = nullptr;
-    }
+    if (r->status != SGM_OK && r->status != SGM_ETOOBIG) result_drop_rows(r);
     r->stats.ns_total = t_done - t.t_submit;
     S->st.completed++;
     S->bytes_in_flight -= est;
@@ -2485,7 +2789,7 @@ int sgm_server_create(sgm_graph *g, const sgm_serve_options *opts, sgm_server **
 
 int sgm_submit(sgm_server *s, const sgm_query *q, uint32_t flags, uint64_t *ticket) {
     if (!s || !q || !ticket || (flags & ~SGM_COUNT_ONLY)) return SGM_EINVAL;
-    sgm_result *res = (sgm_result *)std::calloc(1, sizeof(sgm_result));
+    sgm_result *res = result_new();
     if (!res) return SGM_ENOMEM;
     sgm_server::Ticket t;
     t.status = check_query(q, s->g->V, &t.qi);
@@ -2502,7 +2806,7 @@ int sgm_submit(sgm_server *s, const sgm_query *q, uint32_t flags, uint64_t *tick
     t.t_submit = now_ns();
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) {
-        std::free(res);
+        sgm_free_result(res);
         return SGM_EINVAL;
     }
     const uint64_t id = s->next_id++;

@@ -31,7 +31,22 @@ struct DevGraph {
     // y = min(out-degree, 255) | min(in-degree, 255) << 8 (a query vertex has
     // at most 15 distinct neighbours per direction, so the clamp is exact)
     const int2 *vinfo;
+    // Hub rows (at least kHubRow entries) are also kept in two re-sorted
+    // copies of the adjacency arrays (same row extents; other rows keep the
+    // original order there): ta by (type of the other end, relation, other
+    // end) and tb by (type of the other end, other end, relation). For a
+    // vertex with a hub row, hub_of[v] = h >= 0 and
+    // hub_toff[((h * 2 + dir) * 2 + order) * hub_types + t] is the offset,
+    // from the row start, of the first entry whose other end has type >= t
+    // (t in [0, hub_types), order 0: ta, 1: tb). hub_types = 0: no index.
+    const int2 *out_ta, *out_tb, *in_ta, *in_tb;
+    const int32_t *hub_of;
+    const int32_t *hub_toff;
+    int32_t hub_types;
 };
+
+// rows this long get the per-type index above
+constexpr int32_t kHubRow = 16384;
 
 // Candidate predicate of one query vertex (thesis Def. 3.3 with pins and the
 // incoming-graph degree): type, pin, out-degree and in-degree bounds.

@@ -61,6 +61,12 @@ struct NResult {
     int64_t ticks[4];      // device wall-clock ticks: filter, edges, join, ordering
     int64_t pbytes[4];     // algorithmic bytes of the same four phases
     int64_t need;          // kWhySlab at a join level: slab bytes its pairs could take
+    // a large final table left unordered in the slot's slab for the host to
+    // order with whole-GPU kernels after the launch: device addresses of the
+    // table ([n_rows][n] in join-level column order, see join_order) and of
+    // its ordering keys (uint64 [n_rows], key_bits bits)
+    int32_t host_order, key_bits;
+    int64_t table_ptr, key_ptr;
 };
 
 constexpr int32_t kNeedWide = 1;  // a capacity of the per-query slot was exceeded
@@ -131,6 +137,10 @@ struct NArgs {
     HelpJob *board;           // [nslot]
     int32_t *hctr;            // [0] posted steps, [1] slot workgroups done
     int64_t help_wait;        // polls of a shared step's completion before its owner gives up
+    // final tables of at least this many rows are left in the slab for the
+    // host to order (0: never); the slab below such a table serves the
+    // slot's later queries of the launch
+    int64_t host_order_rows;
 };
 
 // Root sweep: rootbits[j][w] = vertices satisfying predicate j, for the

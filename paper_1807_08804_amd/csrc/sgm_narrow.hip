@@ -63,6 +63,12 @@ struct Smem {
     int32_t nmarks;
     int32_t ndef;  // candidates whose pushes go to row segments
     int32_t retired;  // this slot gave up on a shared step (see HelpJob::dirty)
+    int32_t unsorted; // ordering: some key is above the next one
+    int32_t hostord;  // the final table is left in the slab for the host to order
+    int32_t keybits;
+    int64_t pin_off;  // byte offset of that table in the slab
+    const int32_t *tableptr;
+    const uint64_t *keyptr;
     unsigned long long rowhit;  // item_wg: listed rows with a matching entry
     unsigned long long hseq;    // sequence number of the step this workgroup posted
     int32_t hq, hch;            // helper: board entry and chunk claimed (-1: none)
@@ -128,6 +134,7 @@ struct Ctx {
     int32_t q;          // index of the query in the batch
     int32_t nslot, ngrid;  // slot workgroups, all workgroups of the launch
     int64_t help_wait;  // polls of a shared step's completion before giving up
+    int64_t host_order_rows;  // final tables of this many rows go to the host (0: none)
     __device__ uint64_t *B(int u) const { return bits + (int64_t)u * g.nwords; }
     __device__ int32_t *L(int u) const { return lists + (int64_t)u * lcap; }
 };
@@ -165,6 +172,13 @@ __device__ __forceinline__ void mark(Ctx &c, int i) {
         c.s->t[i] = wall_clock64();
         c.s->pb[i] = c.s->bytes;
     }
+}
+
+// Lowest slab offset of a table left for the host: the slot's later
+// queries keep the filter's overflow list, marks, deferred list and row
+// segments ([0, 12 lcap) and beyond) plus 4 MB below it.
+__device__ __forceinline__ int64_t kPinFloor(const Ctx &c) {
+    return 16ll * c.lcap + (4ll << 20);
 }
 
 // All threads call; returns the same pointer everywhere (nullptr + abort on
@@ -390,6 +404,47 @@ __device__ __forceinline__ void row_of(const DevGraph &g, int32_t up, int dir, i
     *end = off[up + 1];
 }
 
+// Entries of candidate up's row that can pass test d: a hub row (at least
+// kHubRow entries) tested against a typed query vertex is read from its
+// copy sorted by the other end's type (then by relation for a labelled
+// test), restricted to that type (and relation); any other row in full.
+// Every entry left out fails the test (wrong type or relation), so the
+// outcome is the full row's; the slice keeps the other ends ascending.
+__device__ __forceinline__ const int2 *test_row(const Ctx &c, int32_t up, const NNbr &d,
+                                                int32_t *beg, int32_t *end) {
+    const DevGraph &g = c.g;
+    row_of(g, up, d.dir, beg, end);
+    const int2 *adj = d.dir ? g.in_adj : g.out_adj;
+    if (g.hub_types == 0 || *end - *beg < kHubRow) return adj;
+    const int32_t t = c.Q->pred[d.v].label;
+    if (t < 0 || t + 1 >= g.hub_types) return adj;
+    const int32_t h = g.hub_of[up];
+    const int order = d.rel >= 0 ? 0 : 1;
+    const int32_t *toff = g.hub_toff + ((int64_t)(h * 2 + d.dir) * 2 + order) * g.hub_types;
+    int32_t b = *beg + toff[t], e = *beg + toff[t + 1];
+    const int2 *arr = d.dir ? (order ? g.in_tb : g.in_ta) : (order ? g.out_tb : g.out_ta);
+    if (d.rel >= 0) {
+        // the type's entries are sorted by relation: its relation's range
+        int32_t lo = b, hi = e;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (arr[mid].y < d.rel) lo = mid + 1;
+            else hi = mid;
+        }
+        int32_t lo2 = lo, hi2 = e;
+        while (lo2 < hi2) {
+            const int32_t mid = (lo2 + hi2) >> 1;
+            if (arr[mid].y <= d.rel) lo2 = mid + 1;
+            else hi2 = mid;
+        }
+        b = lo;
+        e = lo2;
+    }
+    *beg = b;
+    *end = e;
+    return arr;
+}
+
 // Whole workgroup on one candidate (uniform call). Prune: the candidate
 // survives if every listed query edge has a matching neighbour; explore
 // then pushes every matching neighbour.
@@ -454,9 +509,8 @@ __device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb,
     uint64_t seen = 0;
     for (int j = 0; j < ncount && alive; ++j) {
         const NNbr d = nb[j];
-        const int2 *adj = d.dir ? g.in_adj : g.out_adj;
         int32_t beg, end;
-        row_of(g, up, d.dir, &beg, &end);
+        const int2 *adj = test_row(c, up, d, &beg, &end);
         bool found = false;
         for (int32_t base = beg; base < end; base += 4 * NT) {
             bool hit = false;
@@ -491,9 +545,8 @@ __device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb,
     if (st.push) {
         for (int j = 0; j < ncount; ++j) {
             const NNbr d = nb[j];
-            const int2 *adj = d.dir ? g.in_adj : g.out_adj;
             int32_t beg, end;
-            row_of(g, up, d.dir, &beg, &end);
+            const int2 *adj = test_row(c, up, d, &beg, &end);
             uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
             int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
             seen += end - beg;
@@ -529,9 +582,8 @@ __device__ __forceinline__ void item_wave(Ctx &c, const NStep &st, const NNbr *n
     uint64_t seen = 0;
     for (int j = 0; j < ncount && alive; ++j) {
         const NNbr d = nb[j];
-        const int2 *adj = d.dir ? g.in_adj : g.out_adj;
         int32_t beg, end;
-        row_of(g, up, d.dir, &beg, &end);
+        const int2 *adj = test_row(c, up, d, &beg, &end);
         bool found = false;
         for (int32_t base = beg; base < end; base += 256) {
             const int32_t i = base + lane;
@@ -568,9 +620,8 @@ __device__ __forceinline__ void item_wave(Ctx &c, const NStep &st, const NNbr *n
     if (st.push)
         for (int j = 0; j < ncount; ++j) {
             const NNbr d = nb[j];
-            const int2 *adj = d.dir ? g.in_adj : g.out_adj;
             int32_t beg, end;
-            row_of(g, up, d.dir, &beg, &end);
+            const int2 *adj = test_row(c, up, d, &beg, &end);
             uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
             int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
             seen += end - beg;
@@ -785,7 +836,8 @@ template <class K>
 __device__ __forceinline__ void push_segment(Ctx &c, const K &k, const NNbr *nb, int4 sg,
                                              uint64_t &fb) {
     const NNbr d = nb[sg.y];
-    const int2 *adj = d.dir ? c.g.in_adj : c.g.out_adj;
+    int32_t rb, re;  // the segment indexes the array test_row picks for its row
+    const int2 *adj = test_row(c, sg.x, d, &rb, &re);
     uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
     int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
     for (int32_t base = sg.z; base < sg.w; base += kSegEntries) {
@@ -814,7 +866,7 @@ __device__ __forceinline__ int32_t build_segments(Ctx &c, const NNbr *nb, int nc
         if (i < nd)
             for (int j = 0; j < ncount; ++j) {
                 int32_t b, e;
-                row_of(c.g, def[i], nb[j].dir, &b, &e);
+                test_row(c, def[i], nb[j], &b, &e);
                 cnt += (e - b + kSegEntries - 1) / kSegEntries;
             }
         int64_t tot;
@@ -823,7 +875,7 @@ __device__ __forceinline__ int32_t build_segments(Ctx &c, const NNbr *nb, int nc
             int64_t p = carry + ex;
             for (int j = 0; j < ncount; ++j) {
                 int32_t b, e;
-                row_of(c.g, def[i], nb[j].dir, &b, &e);
+                test_row(c, def[i], nb[j], &b, &e);
                 for (int32_t x = b; x < e; x += kSegEntries)
                     seg[p++] = make_int4(def[i], j, x, min(e, x + kSegEntries));
             }
@@ -972,7 +1024,7 @@ __device__ __forceinline__ void push_deferred(Ctx &c, const NStep &st, const NNb
         for (int32_t i = 0; i < nd; ++i)
             for (int j = 0; j < ncount; ++j) {
                 int32_t b, e;
-                row_of(c.g, def[i], nb[j].dir, &b, &e);
+                test_row(c, def[i], nb[j], &b, &e);
                 push_segment(c, LdsCtr{c.s}, nb, make_int4(def[i], j, b, e), fb);
             }
         __syncthreads();
@@ -1747,6 +1799,10 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         s.pb[threadIdx.x] = 0ull;
     }
     if (threadIdx.x == 0) {
+        s.hostord = 0;
+        s.keybits = 0;
+        s.tableptr = nullptr;
+        s.keyptr = nullptr;
         s.abort_ = 0;
         s.slab_used = 0;
         s.empty = 0;
@@ -2081,6 +2137,65 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         int32_t *idx;
         const uint64_t *skeys = nullptr;  // the sorted keys (rows > 1)
         if (rows > 1) stage_key_lists(c);
+        // A large final table in the slab, with room below it for the slot's
+        // later queries: its keys go beside it and the host orders it (and
+        // collapses a projection) with whole-GPU kernels after the launch;
+        // one workgroup would spend milliseconds on the passes and the
+        // gather.
+        int64_t toff = (int64_t)((const char *)table - c.slab);
+        if (c.host_order_rows > 0 && rows >= c.host_order_rows && toff >= 0 &&
+            toff < c.slab_bytes) {
+            uint64_t *ka = nullptr;
+            const int64_t tbytes = (rows * k * 4 + 255) & ~(int64_t)255;
+            const int64_t top = ((c.slab_bytes - 8 * rows) & ~(int64_t)255) - tbytes;
+            if (toff >= kPinFloor(c)) {
+                ka = (uint64_t *)slab_alloc(c, 8 * rows);
+            } else if (top >= kPinFloor(c) && top > toff) {
+                // too low in the slab to keep for the host: move it up to
+                // the top, keys above it; overlapping, so the chunks go from
+                // the end (every read of a chunk before its writes)
+                int32_t *dst = (int32_t *)(c.slab + top);
+                const int64_t nint = rows * k;
+                for (int64_t end = nint; end > 0; end -= 4 * NT) {
+                    const int64_t beg = end - 4 * NT > 0 ? end - 4 * NT : 0;
+                    int32_t v[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t i = beg + q * NT + threadIdx.x;
+                        v[q] = i < end ? table[i] : 0;
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t i = beg + q * NT + threadIdx.x;
+                        if (i < end) dst[i] = v[q];
+                    }
+                    __syncthreads();
+                }
+                if (threadIdx.x == 0) add_bytes(c, 8ull * nint);
+                table = dst;
+                toff = top;
+                ka = (uint64_t *)(c.slab + top + tbytes);
+            }
+            if (ka) {
+                for (int64_t r = threadIdx.x; r < rows; r += NT) ka[r] = row_key(c, table + r * k);
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    s.hostord = 1;
+                    s.keybits = tb;
+                    s.pin_off = toff;
+                    s.tableptr = table;
+                    s.keyptr = ka;
+                    add_bytes(c, (4ull * k + 8ull) * rows);
+                }
+                __syncthreads();
+                ev(c, SGM_EV_SORT);
+                ev(c, SGM_EV_OUTPUT);
+                clear_slot(c, false);
+                mark(c, 4);
+                return;
+            }
+        }
         if (rows == 1) {
             int32_t *ix = (int32_t *)c.dyn;
             if (threadIdx.x == 0) ix[0] = 0;
@@ -2134,12 +2249,21 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                 }
                 return;
             }
+            if (threadIdx.x == 0) s.unsorted = 0;
             for (int64_t r = threadIdx.x; r < rows; r += NT) {
                 ka[r] = row_key(c, table + r * k);
                 ia[r] = (int32_t)r;
             }
             __syncthreads();
-            for (int sh = 0; sh < tb; sh += 8) {
+            // a join that bound the key columns in key order has left the
+            // rows in order already: then no pass is needed
+            bool down = false;
+            for (int64_t r = threadIdx.x; r + 1 < rows; r += NT) down |= ka[r] > ka[r + 1];
+            if (down) s.unsorted = 1;
+            __syncthreads();
+            if (threadIdx.x == 0) add_bytes(c, 8ull * rows);
+            const bool passes = s.unsorted != 0;
+            for (int sh = 0; passes && sh < tb; sh += 8) {
                 wg_radix_pass(c, ka, ia, kb, ib, rows, sh);
                 uint64_t *tk = ka;
                 ka = kb;
@@ -2148,7 +2272,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                 ia = ib;
                 ib = ti;
             }
-            if (threadIdx.x == 0) add_bytes(c, 24ull * rows * ((tb + 7) / 8));
+            if (threadIdx.x == 0 && passes) add_bytes(c, 24ull * rows * ((tb + 7) / 8));
             idx = ia;
             skeys = ka;
         }
@@ -2218,20 +2342,22 @@ __device__ __forceinline__ void run_query(Ctx &c) {
 }
 
 // at least 4 waves per SIMD (registers <= 128): two workgroups per CU
+// slab_cap: the slot's slab below tables its earlier queries of the launch
+// left for the host to order (the whole slab otherwise)
 __device__ __forceinline__ Ctx slot_ctx(const NArgs &a, Smem &s, unsigned char *dyn, int slot,
-                                        int32_t q) {
+                                        int32_t q, int64_t slab_cap) {
     const int32_t nwords = a.g.nwords;
     uint64_t *bits = a.bits + (int64_t)slot * (SGM_MAX_QV + 1) * nwords;
     int32_t *lists = a.lists + (int64_t)slot * SGM_MAX_QV * a.lcap;
     char *slab = a.slab + (int64_t)slot * a.slab_bytes;
-    return Ctx{a.g,  a.lcap, a.slab_bytes, a.out, a.out_cap, a.out_used, a.rootbits, &a.qs[q], &s,
+    return Ctx{a.g,  a.lcap, slab_cap, a.out, a.out_cap, a.out_used, a.rootbits, &a.qs[q], &s,
                bits, bits + (int64_t)SGM_MAX_QV * nwords, lists, slab, dyn,
                a.trace ? a.trace + (int64_t)q * SGM_TRACE_CAP : nullptr, a.group_lanes,
                a.wg_rows, a.join_policy,
                // while filtering the slab holds the long-row overflow list in
                // [0, 4 lcap) bytes and the marks in [4 lcap, 8 lcap)
                (int32_t *)(slab + 4 * (int64_t)a.lcap), a.board ? a.board + slot : nullptr, a.hctr,
-               a.help_items, q, a.nslot, a.ngrid, a.help_wait};
+               a.help_items, q, a.nslot, a.ngrid, a.help_wait, a.host_order_rows};
 }
 
 // Chunks of the step posted on board entry e, starting with chunk ch, until
@@ -2253,7 +2379,7 @@ __device__ __forceinline__ void help_step(const NArgs &a, Smem &s, unsigned char
         s.nbl[threadIdx.x].rel = j->nbl[threadIdx.x].rel;
     }
     __syncthreads();
-    Ctx c = slot_ctx(a, s, dyn, e, j->q);
+    Ctx c = slot_ctx(a, s, dyn, e, j->q, a.slab_bytes);
     c.trace = nullptr;
     uint64_t fb = 0;
     int32_t n = 0;
@@ -2378,6 +2504,7 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
             atomicExch(&a.board[blockIdx.x].dirty, 0);
         }
     }
+    int64_t slab_cap = a.slab_bytes;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s.q = atomicAdd(a.queue, 1);
@@ -2403,13 +2530,15 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
                 R.bytes = 0;
                 R.need = 0;
                 for (int i = 0; i < 4; ++i) R.ticks[i] = R.pbytes[i] = 0;
+                R.host_order = 0;
             }
             continue;
         }
-        Ctx c = slot_ctx(a, s, dyn, blockIdx.x, q);
+        Ctx c = slot_ctx(a, s, dyn, blockIdx.x, q, slab_cap);
         if (threadIdx.x == 0) s.nev = 0;
         run_query(c);
         __syncthreads();
+        if (s.hostord) slab_cap = s.pin_off;  // keep that table until the launch ends
         if (threadIdx.x == 0) {
             R.status = s.status;
             R.reason = s.reason;
@@ -2424,6 +2553,10 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
             for (int e = 0; e < SGM_MAX_QE; ++e) R.ec[e] = e < Q.m ? s.ectot[e] : 0;
             R.bytes = (int64_t)s.bytes;
             R.need = s.need;
+            R.host_order = s.hostord;
+            R.key_bits = s.keybits;
+            R.table_ptr = (int64_t)(uintptr_t)s.tableptr;
+            R.key_ptr = (int64_t)(uintptr_t)s.keyptr;
             // phases a query skipped carry the time and bytes of the
             // previous mark
             int64_t prev = s.t[0];

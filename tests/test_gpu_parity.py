@@ -239,6 +239,39 @@ def test_medium_hub_star(medium_kg, g_medium, oracle_medium):
     same(g_medium.match_query(q), oracle_medium.match_query(q))
 
 
+@pytest.mark.parametrize("direction", ["out", "in"])
+def test_medium_hub_rows_by_type_and_relation(direction, medium_kg, oracle_medium):
+    """Hub rows (the medium graph's largest row, 64303 entries) read through
+    their per-type index: every mix of typed / untyped neighbour and labelled
+    / variable edge, pinned hub and unpinned hub-type centre, on every path,
+    in one batch and alone. The in-direction case runs on the reversed graph,
+    where that row is an in-row."""
+    kg = medium_kg.ensure_in()
+    og = oracle_medium
+    if direction == "in":
+        kg = kggen.KG(kg.V, kg.E, kg.in_ptr.astype(np.int32), kg.in_col, kg.in_rel, kg.vtype)
+        og = oracle.graph_from_kg(kg)
+    deg = np.diff(medium_kg.row_ptr)
+    hub = int(np.argmax(deg))
+    say(f"case: {direction} hub {hub} with {int(deg[hub])} entries")
+    qs = []
+    for t in (-1, 2, 9):
+        for r in (-1, 0, 2):
+            e1 = (0, 1, r) if direction == "out" else (1, 0, r)
+            e2 = (1, 2, -1) if direction == "out" else (2, 1, -1)
+            qs.append(any_query(3, [e1, e2], vlabel=[-1, t, 5], vpin=[hub, -1, -1]))
+            qs.append(any_query(2, [e1], vlabel=[int(kg.vtype[hub]), t], vpin=[-1, -1]))
+    want = [og.match_query(q) for q in qs]
+    assert max(len(w) for w in want) > 10000
+    for path in PATHS:
+        g = P.Graph.from_kg(kg, path=path)
+        for q, w in zip(qs, want):
+            same(g.match_query(q), w)
+        for r, w in zip(g.match_batch(qs), want):
+            same(r, w)
+        g.close()
+
+
 @pytest.mark.parametrize("opts", [dict(refine_rounds=0), dict(refine_rounds=-1),
                                   dict(refine_reversed=0), dict(low_conn_degree=0),
                                   dict(low_conn_degree=4, refine_rounds=3)])
