@@ -121,6 +121,57 @@ def phase_rates(stats, P, resident):
     return out
 
 
+# the thesis's four refinement variants (Ch. 3, Sec. "Effect of Optimization
+# Techniques"): (name, refine_rounds, refine_reversed)
+ABLATION_VARIANTS = [("converge", -1, 0), ("converge_reversed", -1, 1),
+                     ("one_round_reversed", 1, 1), ("none", 0, 1)]
+
+
+def ablation_leg(P, kg, queries):
+    """Each refinement variant with both graph representations and with the
+    outgoing graph alone, on the multi-kernel path (the one that runs both),
+    counting only. Intermediate bytes of a query: its candidate lists (4 B
+    per candidate), its candidate-edge tables (4 B per candidate edge) and
+    its largest join table; time is the host wall time per query."""
+    per = {}
+    for out_only in (0, 1):
+        for name, rounds, rev in ABLATION_VARIANTS:
+            key = f"{'out_only' if out_only else 'in_out'}/{name}"
+            g = P.Graph.from_kg(kg, path=P.SGM_PATH_WIDE, out_only=out_only,
+                                refine_rounds=rounds, refine_reversed=rev)
+            for q in queries[:4]:
+                g.match_query(q, count_only=True)
+            ms, inter, peak, cand, counts = [], [], [], [], []
+            for q in queries:
+                t = time.perf_counter()
+                n, st = g.match_query(q, count_only=True, with_stats=True)
+                ms.append((time.perf_counter() - t) * 1e3)
+                inter.append(4 * sum(st["cand"][:q.n]) + 4 * sum(st["ec"][:q.m]) + st["peak_bytes"])
+                peak.append(st["peak_rows"])
+                cand.append(sum(st["cand"][:q.n]))
+                counts.append(int(n))
+            g.close()
+            per[key] = dict(ms=ms, inter=inter, peak=peak, cand=cand, counts=counts)
+            log(f"ablation {key}: {np.mean(ms):.2f} ms/query, intermediate "
+                f"{np.mean(inter) / 2**20:.2f} MiB mean")
+    base = per["in_out/one_round_reversed"]
+    for k, v in per.items():
+        if v["counts"] != base["counts"]:
+            raise RuntimeError(f"ablation variant {k} changed a result count")
+    out = {}
+    for k, v in per.items():
+        ratio = np.asarray(v["inter"], np.float64) / np.maximum(np.asarray(base["inter"]), 1)
+        out[k] = {"ms_per_query": round(float(np.mean(v["ms"])), 3),
+                  "intermediate_mib_mean": round(float(np.mean(v["inter"])) / 2**20, 3),
+                  "intermediate_mib_max": round(float(np.max(v["inter"])) / 2**20, 3),
+                  "peak_rows_max": int(np.max(v["peak"])),
+                  "candidates_mean": round(float(np.mean(v["cand"])), 1),
+                  "intermediate_ratio_to_default_max": round(float(np.max(ratio)), 2),
+                  "intermediate_ratio_to_default_median": round(float(np.median(ratio)), 3)}
+    return {"queries": len(queries), "max_vertices": int(max(q.n for q in queries)),
+            "default": "in_out/one_round_reversed", "variants": out}
+
+
 def cpu_leg(kg, queries, seconds):
     """The oracle on a bounded sample of the same workload: the queries in
     order, cycling, until `seconds` of wall time have passed (queries that
@@ -310,6 +361,19 @@ def bench_large(args, P, kggen):
     if not args.no_serve:
         sq, _ = kggen.load_large_serve(args.serve_queries)
         served = served_leg(P, kggen, g, sq, [200.0, 1000.0, 5000.0], args.serve_arrivals)
+    ablation = None
+    if not args.no_ablation:
+        t = time.time()
+        # the 24 largest queries and the 24 with the largest join tables
+        # under the default settings (from the batch's own statistics)
+        big = sorted(range(len(queries)), key=lambda i: (-queries[i].n, i))[:24]
+        heavy = sorted((i for i in range(len(queries)) if i not in set(big)),
+                       key=lambda i: (-bstats[i]["peak_rows"], i))[:24]
+        lq = [queries[i] for i in big + heavy]
+        mkg = kggen.named_graph("medium")
+        mq, _ = kggen.medium_queries(mkg, 40)
+        ablation = {"large": ablation_leg(P, kg, lq), "medium": ablation_leg(P, mkg, mq)}
+        log(f"ablation legs in {time.time() - t:.1f}s")
     cpu = None if args.no_cpu else cpu_leg(kg, queries, args.cpu_seconds)
     nq = args.steps * len(queries)
     return {
@@ -343,6 +407,7 @@ def bench_large(args, P, kggen):
         "roofline": roofline(ks, "persist", "large:persist"),
         "roofline_root_sweep": roofline(ks, "check", "large:check"),
         "persistent_kernel_phases": phases,
+        "refinement_ablation": ablation,
         "cpu_baseline": cpu,
     }
 
@@ -431,6 +496,8 @@ def main():
                     help="arrival rates (qps) of the medium served-form measurement")
     ap.add_argument("--serve-arrivals", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form legs")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the refinement / two-graph ablation legs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (torch), the known-size "
                          "reference for HBM byte counters, and exit")

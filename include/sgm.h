@@ -67,7 +67,19 @@ typedef struct {
                                   root sweep, kernel, readback) is one HIP graph
                                   launch; 0: separate launches. Not used while
                                   profile != 0 (kernels are timed one by one) */
-    int32_t reserved[5];
+    int32_t out_only;          /* 1: keep only the outgoing graph (thesis Ch. 3,
+                                  Sec. "GpSense Framework": the incoming graph is
+                                  the second of the two representations). A query
+                                  vertex reached only over an edge into a filtered
+                                  vertex then starts from every vertex of its label
+                                  and is pruned over its own outgoing edges; edge
+                                  candidates keyed by a destination are built by
+                                  transposing the source-keyed ones. Results are
+                                  unchanged; it exists to measure what the
+                                  incoming graph saves. Runs on SGM_PATH_WIDE only
+                                  (AUTO means WIDE; NARROW, servers, autotuning
+                                  and sgm_match_query_noalloc: SGM_EINVAL) */
+    int32_t reserved[4];
 } sgm_options;
 
 /* Execution paths. NARROW: one persistent kernel in which each workgroup

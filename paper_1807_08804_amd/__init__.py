@@ -40,7 +40,8 @@ class sgm_options(ctypes.Structure):
                 ("refine_reversed", ctypes.c_int32), ("low_conn_degree", ctypes.c_int32),
                 ("result_cap_rows", ctypes.c_int64), ("join_budget_bytes", ctypes.c_int64),
                 ("profile", ctypes.c_int32), ("path", ctypes.c_int32),
-                ("graphs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("graphs", ctypes.c_int32), ("out_only", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class sgm_query(ctypes.Structure):

@@ -646,6 +646,31 @@ void readback_rows(sgm_graph *g, hipStream_t st, const int32_t *dev, size_t byte
     }
 }
 
+// Stable order of n non-negative int32 keys below 2^nbits (whole-GPU LSD
+// radix passes, 8-bit digits); key is overwritten. Returns the order.
+int32_t *order_by_i32(sgm_graph *g, Scope &sc, int32_t *key, int64_t n, int nbits) {
+    int32_t *ia = sc.get<int32_t>(n), *ib = sc.get<int32_t>(n);
+    int32_t *ka = key, *kb = sc.get<int32_t>(n);
+    const int64_t tiles = radix_tiles(n);
+    int64_t *hist = sc.get<int64_t>(256 * tiles);
+    int64_t *hoff = sc.get<int64_t>(256 * tiles + 1);
+    int64_t *tmp = sc.get<int64_t>(scan_tmp_words(256 * tiles) + 1);
+    hipStream_t st = g->stream;
+    {
+        Prof p(g, SGM_K_SORT, 4.0 * n);
+        launch_iota(st, ia, n);
+    }
+    for (int sh = 0; sh < nbits; sh += 8) {
+        Prof p(g, SGM_K_SORT, 20.0 * n);
+        launch_radix_hist(st, ka, n, sh, hist);
+        launch_scan_i64(st, hist, 256 * tiles, hoff, tmp);
+        launch_radix_scatter(st, ka, ia, n, sh, hoff, kb, ib);
+        std::swap(ka, kb);
+        std::swap(ia, ib);
+    }
+    return ia;
+}
+
 // Order n rows by 64-bit keys of tb bits with whole-GPU LSD radix passes
 // (stable, 8-bit digits over the 32-bit halves); returns the order.
 int32_t *order_by_keys(sgm_graph *g, Scope &sc, const uint64_t *keys, int64_t n, int tb) {
@@ -702,8 +727,9 @@ struct Query {
     int32_t *cand_count_dev(int u) const { return &g->d_cnt->cand_count[u]; }
     hipStream_t st() const { return g->stream; }
 
+    // with the outgoing graph only, in-degrees are unknown (not tested)
     VPred pred(int u) const {
-        return VPred{qi.label[u], qi.pin[u], qi.qout[u], qi.qin[u]};
+        return VPred{qi.label[u], qi.pin[u], qi.qout[u], g->opts.out_only ? 0 : qi.qin[u]};
     }
 
     void collect_one(int u) {
@@ -752,7 +778,10 @@ struct Query {
         HIPX(hipMemsetAsync(g->d_cnt, 0, sizeof(DevCounters), st()));
         // descriptors for every filter launch, uploaded once
         Program pr;
-        build_program(qi, pl, g->opts.low_conn_degree, g->opts.refine_reversed, &pr);
+        if (g->opts.out_only)
+            build_program_out_only(qi, pl, g->opts.low_conn_degree, g->opts.refine_reversed, &pr);
+        else
+            build_program(qi, pl, g->opts.low_conn_degree, g->opts.refine_reversed, &pr);
         std::vector<NbrDesc> &hd = desc_;
         hd.clear();
         for (const PNbr &p : pr.nbr) {
@@ -782,6 +811,17 @@ struct Query {
             launch_check_sweep(st(), g->dg, pred(root), bits(root));
         }
         for (const PStep &s : pr.init) {
+            if (s.sweep) {
+                // outgoing graph only: a vertex reached over an edge into
+                // its parent starts from its predicate alone
+                if (qi.pin[s.u] >= 0) {
+                    Prof p(g, SGM_K_CHECK, 8.0);
+                    launch_check_pin(st(), g->dg, pred(s.u), bits(s.u));
+                } else {
+                    Prof p(g, SGM_K_CHECK, 8.0 * g->V + g->nwords * 8.0);
+                    launch_check_sweep(st(), g->dg, pred(s.u), bits(s.u));
+                }
+            }
             collect_one(s.u);
             if (s.parent >= 0)
                 HIPX(hipMemsetAsync(scratch(), 0, sizeof(uint64_t) * g->nwords, st()));
@@ -802,9 +842,17 @@ struct Query {
             for (const PStep &s : pr.refine) {
                 collect_one(s.u);
                 const int64_t bound = qi.pin[s.u] >= 0 ? 1 : g->V;
-                int rc = filter_launch(s.u, g->d_desc + s.first, s.count, false, bound,
+                // a step with a parent (outgoing graph only) pushes into the
+                // scratch bitmap, then prunes the parent by it
+                if (s.parent >= 0)
+                    HIPX(hipMemsetAsync(scratch(), 0, sizeof(uint64_t) * g->nwords, st()));
+                int rc = filter_launch(s.u, g->d_desc + s.first, s.count, s.parent >= 0, bound,
                                        &g->d_cnt->removed[r], SGM_K_REFINE);
                 if (rc) return rc;
+                if (s.parent >= 0) {
+                    Prof p(g, SGM_K_OTHER, g->nwords * 24.0);
+                    launch_and(st(), bits(s.parent), scratch(), g->nwords, &g->d_cnt->removed[r]);
+                }
             }
             if (fixpoint) {
                 HIPX(hipMemcpyAsync(g->h_small, &g->d_cnt->removed[r], sizeof(unsigned long long),
@@ -914,12 +962,16 @@ struct Query {
             add_level(best);
         }
         for (int j = 0; j < qi.n; ++j) jpos[jorder[j]] = j;
-        // orientation: key = the endpoint bound first
+        // orientation: key = the endpoint bound first (with the outgoing
+        // graph only, a destination key is made by transposing below)
+        bool flip[SGM_MAX_QE] = {};
         for (int e = 0; e < m; ++e) {
             ECTab &t = ec[e];
             const int a = qi.esrc[e], b = qi.edst[e];
             const bool key_src = jpos[a] < jpos[b];
-            if (!key_src) {
+            if (!key_src && g->opts.out_only) {
+                flip[e] = true;
+            } else if (!key_src) {
                 sc.release(t.cnt);
                 sc.release(t.big);
                 t.key = b;
@@ -938,10 +990,51 @@ struct Query {
                 Prof p(g, SGM_K_OTHER, 8.0 * ccount[t.key]);
                 launch_scan_i32(st(), t.cnt, cand_count_dev(t.key), t.offs);
             }
-            Prof p(g, SGM_K_EC_WRITE, 0.0);
-            launch_ec_write(st(), g->dg, ec_desc(t, e), grid_small_for(ccount[t.key]), grid_big());
+            {
+                Prof p(g, SGM_K_EC_WRITE, 0.0);
+                launch_ec_write(st(), g->dg, ec_desc(t, e), grid_small_for(ccount[t.key]),
+                                grid_big());
+            }
+            if (flip[e]) transpose(t);
         }
         return SGM_OK;
+    }
+
+    // Re-key a source-keyed table by its destination without the incoming
+    // graph: (destination rank, source) per pair, a stable sort by the rank
+    // (sources stay ascending within a key), the counts scanned to offsets.
+    void transpose(ECTab &t) {
+        const int a = t.key, b = t.other;
+        const int64_t n = t.n;
+        int32_t *rk = sc.get<int32_t>(n), *src = sc.get<int32_t>(n);
+        int32_t *cnt = sc.get<int32_t>((int64_t)ccount[b] + 1);
+        HIPX(hipMemsetAsync(cnt, 0, sizeof(int32_t) * ((size_t)ccount[b] + 1), st()));
+        {
+            Prof p(g, SGM_K_EC_WRITE, 16.0 * n + 4.0 * ccount[a]);
+            launch_ec_pairs(st(), list(a), cand_count_dev(a), ccount[a], t.offs, t.vals,
+                            RankRef{bits(b), prefix(b)}, rk, src, cnt);
+        }
+        int nbits = 1;
+        while ((1ll << nbits) < ccount[b]) ++nbits;
+        const int32_t *idx = order_by_i32(g, sc, rk, n, nbits);
+        int32_t *vals = sc.get<int32_t>(n), *offs = sc.get<int32_t>((int64_t)ccount[b] + 1);
+        {
+            Prof p(g, SGM_K_EC_WRITE, 12.0 * n);
+            launch_gather_key(st(), src, 1, 0, idx, n, vals);
+        }
+        {
+            Prof p(g, SGM_K_OTHER, 8.0 * ccount[b]);
+            launch_scan_i32(st(), cnt, cand_count_dev(b), offs);
+        }
+        sc.release(t.cnt);
+        sc.release(t.offs);
+        sc.release(t.vals);
+        t.key = b;
+        t.other = a;
+        t.dir = 1;
+        t.cnt = cnt;
+        t.offs = offs;
+        t.vals = vals;
     }
 
     struct Level {
@@ -1503,15 +1596,16 @@ bool pack_query(sgm_graph *g, const QInfo &qi, const Plan &pl, NQuery *nq, int *
     nq->refine_rounds = g->opts.refine_rounds < 0 ? -1 : std::min(g->opts.refine_rounds, 32);
     nq->proj = qi.proj;
     int k = 0;
-    for (const auto *v : {&pr.init, &pr.refine})
-        for (const PStep &s : *v) {
-            NStep &t = nq->steps[k++];
-            t.u = (int8_t)s.u;
-            t.push = (int8_t)s.push;
-            t.parent = (int8_t)s.parent;
-            t.first = (int16_t)s.first;
-            t.count = (int16_t)s.count;
-        }
+    auto put = [&](const PStep &s) {
+        NStep &t = nq->steps[k++];
+        t.u = (int8_t)s.u;
+        t.push = (int8_t)s.push;
+        t.parent = (int8_t)s.parent;
+        t.first = (int16_t)s.first;
+        t.count = (int16_t)s.count;
+    };
+    for (const PStep &s : pr.init) put(s);
+    for (const PStep &s : pr.refine) put(s);
     for (size_t i = 0; i < pr.nbr.size(); ++i) {
         nq->nbr[i].v = (int8_t)pr.nbr[i].v;
         nq->nbr[i].dir = (int8_t)pr.nbr[i].dir;
@@ -2104,14 +2198,23 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
             g_last_error = "malformed CSR";
             return rc;
         }
-        build_in(n_vertices, off, adj, in_off, in_adj);
+        if (opts && opts->out_only) {
+            // outgoing graph only: every in-row empty
+            in_off.assign((size_t)n_vertices + 1, 0);
+            in_adj.assign(1, make_int2(0, 0));
+        } else {
+            build_in(n_vertices, off, adj, in_off, in_adj);
+        }
     } catch (const std::bad_alloc &) {
         return SGM_ENOMEM;
     }
+    if (opts && opts->out_only && (opts->out_only != 1 || opts->path == SGM_PATH_NARROW))
+        return SGM_EINVAL;
     sgm_graph *g = new (std::nothrow) sgm_graph();
     if (!g) return SGM_ENOMEM;
     if (opts) g->opts = *opts;
     else sgm_default_options(&g->opts);
+    if (g->opts.out_only) g->opts.path = SGM_PATH_WIDE;
     g->device = g->opts.device;
     g->V = n_vertices;
     g->E = (int64_t)adj.size();
@@ -2237,7 +2340,7 @@ int sgm_set_tuning(sgm_graph *g, const sgm_tuning *t) {
 }
 
 int sgm_autotune(sgm_graph *g, const sgm_query *qs, int32_t n, int32_t reps, sgm_tuning *best) {
-    if (!g || n <= 0 || !qs || reps < 1) return SGM_EINVAL;
+    if (!g || n <= 0 || !qs || reps < 1 || g->opts.out_only) return SGM_EINVAL;
     reps = std::min(reps, 16);
     std::lock_guard<std::mutex> lk(g->mu);
     std::vector<QInfo> qis((size_t)n);
@@ -2750,7 +2853,7 @@ void sgm_default_serve_options(sgm_serve_options *o) {
 int sgm_server_create(sgm_graph *g, const sgm_serve_options *opts, sgm_server **out) {
     if (!out) return SGM_EINVAL;
     *out = nullptr;
-    if (!g) return SGM_EINVAL;
+    if (!g || g->opts.out_only) return SGM_EINVAL;
     sgm_serve_options o;
     if (opts) o = *opts;
     else sgm_default_serve_options(&o);
@@ -3026,7 +3129,7 @@ int sgm_match_query_noalloc(sgm_graph *g, const sgm_query *q, uint32_t flags, in
                             int64_t rows_cap, int64_t *n_rows) {
     if (n_rows) *n_rows = 0;
     if (!g || !q || !n_rows || (flags & ~SGM_COUNT_ONLY) || rows_cap < 0 ||
-        (!(flags & SGM_COUNT_ONLY) && rows_cap > 0 && !rows))
+        (!(flags & SGM_COUNT_ONLY) && rows_cap > 0 && !rows) || g->opts.out_only)
         return SGM_EINVAL;
     QInfo qi;
     int rc = check_query(q, g->V, &qi);

@@ -140,7 +140,14 @@ void launch_collect_multi(hipStream_t s, const DevGraph &g, const uint64_t *bits
                           int32_t *count_base, int32_t *prefix_base, int64_t prefix_stride,
                           const int32_t *slots, int nslots);
 void launch_filter(hipStream_t s, const FilterArgs &a, int grid_small, int grid_big);
-void launch_and(hipStream_t s, uint64_t *dst, const uint64_t *src, int32_t nwords);
+// dst &= src over nwords; removed (optional, device) counts the bits cleared
+void launch_and(hipStream_t s, uint64_t *dst, const uint64_t *src, int32_t nwords,
+                unsigned long long *removed = nullptr);
+// transposition input of a source-keyed candidate-edge table: per pair, the
+// destination's rank and the source; cnt (zeroed) counts pairs per rank
+void launch_ec_pairs(hipStream_t s, const int32_t *keys, const int32_t *key_count, int64_t n_keys,
+                     const int32_t *offs, const int32_t *vals, RankRef rk, int32_t *rank,
+                     int32_t *src, int32_t *cnt);
 void launch_ec_count(hipStream_t s, const DevGraph &g, const ECDesc &d, int grid_small,
                      int grid_big);
 void launch_ec_write(hipStream_t s, const DevGraph &g, const ECDesc &d, int grid_small,

@@ -231,9 +231,16 @@ __global__ __launch_bounds__(kBlock) void k_filter_big(FilterArgs a) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_and(uint64_t *dst, const uint64_t *src, int32_t n) {
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        dst[i] &= src[i];
+// dst &= src; removed (optional) counts the bits cleared
+__global__ __launch_bounds__(kBlock) void k_and(uint64_t *dst, const uint64_t *src, int32_t n,
+                                                unsigned long long *removed) {
+    unsigned long long cut = 0;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint64_t d = dst[i];
+        cut += __popcll(d & ~src[i]);
+        dst[i] = d & src[i];
+    }
+    if (removed && cut) atomicAdd(removed, cut);
 }
 
 // ---------------------------------------------------------------------------
@@ -317,6 +324,28 @@ __global__ __launch_bounds__(kBlock) void k_ec_big(DevGraph g, ECDesc d) {
         if (!WRITE && threadIdx.x == 0) {
             d.cnt[it] = c;
             if (c) atomicAdd(d.total, (unsigned long long)c);
+        }
+    }
+}
+
+// Transposition of a source-keyed candidate-edge table (outgoing graph
+// only): pair i of key index it gets rank[i] = the rank of its value among
+// the destination's candidates and src[i] = keys[it]; cnt[rank] counts the
+// pairs of each destination candidate. One wave per key.
+__global__ __launch_bounds__(kBlock) void k_ec_pairs(const int32_t *keys, const int32_t *key_count,
+                                                     const int32_t *offs, const int32_t *vals,
+                                                     RankRef rk, int32_t *rank, int32_t *src,
+                                                     int32_t *cnt) {
+    const int lane = threadIdx.x & 63;
+    const int32_t n = *key_count;
+    const int32_t nw = (int32_t)((gridDim.x * blockDim.x) >> 6);
+    for (int32_t it = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); it < n; it += nw) {
+        const int32_t key = keys[it], end = offs[it + 1];
+        for (int32_t i = offs[it] + lane; i < end; i += 64) {
+            const int32_t r = rank_of(rk, vals[i]);
+            rank[i] = r;
+            src[i] = key;
+            atomicAdd(&cnt[r], 1);
         }
     }
 }
@@ -743,9 +772,10 @@ void launch_filter(hipStream_t s, const FilterArgs &a, int grid_small, int grid_
     hipLaunchKernelGGL(k_filter_big, dim3(grid_big), dim3(kBlock), 0, s, a);
 }
 
-void launch_and(hipStream_t s, uint64_t *dst, const uint64_t *src, int32_t nwords) {
+void launch_and(hipStream_t s, uint64_t *dst, const uint64_t *src, int32_t nwords,
+                unsigned long long *removed) {
     hipLaunchKernelGGL(k_and, dim3(grid_for(nwords, kBlock, kGridCap)), dim3(kBlock), 0, s, dst,
-                       src, nwords);
+                       src, nwords, removed);
 }
 
 void launch_ec_count(hipStream_t s, const DevGraph &g, const ECDesc &d, int grid_small,
@@ -814,6 +844,13 @@ void launch_sort_small(hipStream_t s, const int32_t *table, int32_t k, const int
 int64_t small_sort_limit() { return kSmallSort; }
 
 int64_t radix_tiles(int64_t n) { return (n + kRadixTile - 1) / kRadixTile; }
+
+void launch_ec_pairs(hipStream_t s, const int32_t *keys, const int32_t *key_count, int64_t n_keys,
+                     const int32_t *offs, const int32_t *vals, RankRef rk, int32_t *rank,
+                     int32_t *src, int32_t *cnt) {
+    hipLaunchKernelGGL(k_ec_pairs, dim3(grid_for(n_keys * 64, kBlock, kGridCap)), dim3(kBlock), 0,
+                       s, keys, key_count, offs, vals, rk, rank, src, cnt);
+}
 
 void launch_gather_key(hipStream_t s, const int32_t *table, int32_t k, int32_t col,
                        const int32_t *idx, int64_t n, int32_t *key) {

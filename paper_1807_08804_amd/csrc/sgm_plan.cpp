@@ -192,7 +192,7 @@ void build_program(const QInfo &qi, const Plan &pl, int low_conn_degree, int ref
     for (int oi = 0; oi < pl.n_visit; ++oi) {
         const int u = pl.visit[oi];
         initialized[u] = true;
-        PStep s{u, (int)pr->nbr.size(), 0, 1, -1};
+        PStep s{u, (int)pr->nbr.size(), 0, 1, -1, 0};
         auto add = [&](int v, int e) {
             PNbr d{};
             d.v = v;
@@ -213,7 +213,7 @@ void build_program(const QInfo &qi, const Plan &pl, int low_conn_degree, int ref
     for (int i = 0; i < pl.n_init; ++i) {
         const int u = pl.init[refine_reversed ? pl.n_init - 1 - i : i];
         if (qi.deg[u] <= low_conn_degree) continue;
-        PStep s{u, (int)pr->nbr.size(), 0, 0, -1};
+        PStep s{u, (int)pr->nbr.size(), 0, 0, -1, 0};
         for (int e = 0; e < qi.m; ++e) {
             PNbr d{};
             if (qi.esrc[e] == u) {
@@ -232,6 +232,65 @@ void build_program(const QInfo &qi, const Plan &pl, int low_conn_degree, int ref
         }
         s.count = (int)pr->nbr.size() - s.first;
         if (s.count) pr->refine.push_back(s);
+    }
+}
+
+void build_program_out_only(const QInfo &qi, const Plan &pl, int low_conn_degree,
+                            int refine_reversed, Program *pr) {
+    pr->init.clear();
+    pr->refine.clear();
+    pr->nbr.clear();
+    const int n = qi.n;
+    bool swept[SGM_MAX_QV] = {};
+    auto nbr = [&](int v, int32_t rel, int mode) {
+        PNbr d{};
+        d.v = v;
+        d.dir = 0;
+        d.rel = rel;
+        d.mode = mode;
+        pr->nbr.push_back(d);
+    };
+    for (int oi = 0; oi < pl.n_visit; ++oi) {
+        const int u = pl.visit[oi];
+        PStep s{u, (int)pr->nbr.size(), 0, 1, -1, 0};
+        // the tree edge u -> parent, unless u's sweep step has tested it
+        const int pe = pl.parent_edge[u];
+        if (pl.parent[u] >= 0 && qi.esrc[pe] == u && !swept[u]) {
+            nbr(pl.parent[u], qi.elabel[pe], 0);
+            s.parent = pl.parent[u];
+        }
+        for (int x = 0; x < n; ++x)
+            if (pl.parent[x] == u && qi.esrc[pl.parent_edge[x]] == u)
+                nbr(x, qi.elabel[pl.parent_edge[x]], 1);
+        s.count = (int)pr->nbr.size() - s.first;
+        if (s.count) pr->init.push_back(s);
+        // children with an edge into u: swept, then tested against u
+        for (int x = 0; x < n; ++x) {
+            if (pl.parent[x] != u || qi.esrc[pl.parent_edge[x]] != x) continue;
+            PStep t{x, (int)pr->nbr.size(), 1, 1, u, 1};
+            nbr(u, qi.elabel[pl.parent_edge[x]], 0);
+            pr->init.push_back(t);
+            swept[x] = true;
+        }
+    }
+    for (int i = 0; i < pl.n_init; ++i) {
+        const int u = pl.init[refine_reversed ? pl.n_init - 1 - i : i];
+        if (qi.deg[u] <= low_conn_degree) continue;
+        // out-edges of u: tested on u's candidates
+        PStep s{u, (int)pr->nbr.size(), 0, 0, -1, 0};
+        for (int e = 0; e < qi.m; ++e)
+            if (qi.esrc[e] == u && qi.deg[qi.edst[e]] > low_conn_degree)
+                nbr(qi.edst[e], qi.elabel[e], 0);
+        s.count = (int)pr->nbr.size() - s.first;
+        if (s.count) pr->refine.push_back(s);
+        // edges v -> u: a step on v pushing into u
+        for (int e = 0; e < qi.m; ++e) {
+            const int v = qi.esrc[e];
+            if (qi.edst[e] != u || qi.deg[v] <= low_conn_degree) continue;
+            PStep t{v, (int)pr->nbr.size(), 1, 1, u, 0};
+            nbr(u, qi.elabel[e], 0);
+            pr->refine.push_back(t);
+        }
     }
 }
 

@@ -49,6 +49,7 @@ struct Plan {
 // the low-connectivity threshold.
 struct PStep {
     int u, first, count, push, parent;
+    int sweep;  // 1: u starts from every vertex its predicate admits (out-only graph)
 };
 struct PNbr {
     int v, dir, rel, mode;  // dir 0: out-edges of the candidate; mode 0: bitmap test
@@ -68,13 +69,24 @@ struct FixedVec {
     const T *end() const { return v + n; }
 };
 // Explore steps hold each tree edge twice at most (2 (n - 1) entries),
-// refine steps each query edge twice at most (2 m).
+// refine steps each query edge twice at most (2 m); with the outgoing graph
+// only there are up to two explore steps per vertex and one refine step per
+// vertex and per edge.
 struct Program {
-    FixedVec<PStep, SGM_MAX_QV> init, refine;
+    FixedVec<PStep, 2 * SGM_MAX_QV> init;
+    FixedVec<PStep, SGM_MAX_QV + SGM_MAX_QE> refine;
     FixedVec<PNbr, 2 * SGM_MAX_QV + 2 * SGM_MAX_QE> nbr;
 };
 void build_program(const QInfo &qi, const Plan &pl, int low_conn_degree, int refine_reversed,
                    Program *pr);
+// The same phase with the outgoing graph only: every descriptor scans out-
+// edges (dir 0). A tree child reached over an edge into its parent starts
+// from a sweep of its predicate and is tested against the parent's bitmap,
+// pushing back into the parent; refinement over an edge v -> u runs as such
+// a step on v. Steps with parent >= 0 push into a scratch bitmap that is
+// then intersected into the parent.
+void build_program_out_only(const QInfo &qi, const Plan &pl, int low_conn_degree,
+                            int refine_reversed, Program *pr);
 
 // Estimated device bytes of a query's intermediate tables (the served
 // form's admission unit): candidate bitmaps of its vertices plus the largest

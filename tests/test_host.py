@@ -137,6 +137,19 @@ def test_load_graph_rejects_malformed_csr_before_touching_device():
         assert e.value.code == P.SGM_EINVAL
 
 
+def test_out_only_graph_options_checked_before_touching_device():
+    """The outgoing-graph-only option runs on the multi-kernel path alone:
+    asking for the persistent kernel with it, or a value other than 0/1, is
+    refused before any device call."""
+    for out_only, path in [(1, P.SGM_PATH_NARROW), (2, P.SGM_PATH_AUTO), (-1, P.SGM_PATH_WIDE)]:
+        o = P.sgm_options()
+        P.lib().sgm_default_options(ctypes.byref(o))
+        o.out_only, o.path = out_only, path
+        with pytest.raises(P.SGMError) as e:
+            P.sgm_load_graph(2, 2, [0, 1, 2], [1, 0], [0, 0], [0, 0], o)
+        assert e.value.code == P.SGM_EINVAL
+
+
 def test_strerror():
     assert P.sgm_strerror(P.SGM_ETOOBIG)
     assert P.sgm_strerror(12345) == "unknown error"
