@@ -1997,7 +1997,28 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         if (rows_wanted || qi.proj) {
             Scope sc(g->pool);
             const int32_t *table = (const int32_t *)(uintptr_t)r.table_ptr;
-            const uint64_t *keys = (const uint64_t *)(uintptr_t)r.key_ptr;
+            // keys from the key columns' lists the kernel left beside the
+            // table (the same columns and widths as its own ordering)
+            ListKeys lk{};
+            lk.list = (const int32_t *)(uintptr_t)r.list_ptr;
+            int64_t lo = 0;
+            for (int u = 0; u < n; ++u) {
+                const bool kept = !qi.proj || ((qi.proj >> u) & 1u);
+                int b = 0;
+                while (kept && (1ll << b) < r.cand[u]) ++b;
+                if (b == 0) continue;
+                lk.off[lk.n] = lo;
+                lk.cnt[lk.n] = (int32_t)r.cand[u];
+                lk.nbits[lk.n] = b;
+                lk.col[lk.n] = jpos[u];
+                ++lk.n;
+                lo += r.cand[u];
+            }
+            uint64_t *keys = sc.get<uint64_t>(R);
+            {
+                Prof p(g, SGM_K_SORT, (4.0 * lk.n + 8.0) * R);
+                launch_row_keys_lists(st, table, n, lk, R, keys);
+            }
             const int32_t *idx = order_by_keys(g, sc, keys, R, r.key_bits);
             int32_t *sorted = sc.get<int32_t>(R * no);
             {

@@ -197,6 +197,18 @@ struct KeyCols {
 };
 void launch_row_keys(hipStream_t s, const int32_t *table, int32_t k, const KeyCols &kc, int64_t n,
                      uint64_t *keys);
+// Key columns given by their sorted candidate lists (one device array, the
+// lists at off[c]): rank = position of the value in its list.
+struct ListKeys {
+    const int32_t *list;
+    int64_t off[SGM_MAX_QV];
+    int32_t cnt[SGM_MAX_QV];
+    int32_t nbits[SGM_MAX_QV];
+    int32_t col[SGM_MAX_QV];
+    int32_t n;
+};
+void launch_row_keys_lists(hipStream_t s, const int32_t *table, int32_t k, const ListKeys &lk,
+                           int64_t n, uint64_t *keys);
 // key[i] = 32-bit half (hi = 0: low, 1: high) of keys[idx[i]]
 void launch_key_half(hipStream_t s, const uint64_t *keys, const int32_t *idx, int64_t n, int hi,
                      int32_t *key);

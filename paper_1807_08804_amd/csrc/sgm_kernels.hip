@@ -858,6 +858,30 @@ void launch_gather_key(hipStream_t s, const int32_t *table, int32_t k, int32_t c
                        table, k, col, idx, n, key);
 }
 
+// Ordering keys from the key columns' sorted candidate lists: the rank of
+// each key column's value (binary search in its list), nbits[c] bits per
+// column, the first column highest. One thread per row.
+__global__ __launch_bounds__(kBlock) void k_row_keys_lists(const int32_t *table, int32_t k,
+                                                           ListKeys lk, int64_t n,
+                                                           uint64_t *keys) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t *row = table + r * k;
+        uint64_t key = 0;
+        for (int c = 0; c < lk.n; ++c) {
+            const int32_t rk = lower_bound_i32(lk.list + lk.off[c], 0, lk.cnt[c], row[lk.col[c]]);
+            key = (key << lk.nbits[c]) | (uint64_t)rk;
+        }
+        keys[r] = key;
+    }
+}
+
+void launch_row_keys_lists(hipStream_t s, const int32_t *table, int32_t k, const ListKeys &lk,
+                           int64_t n, uint64_t *keys) {
+    hipLaunchKernelGGL(k_row_keys_lists, dim3(grid_for(n, kBlock, kGridCap)), dim3(kBlock), 0, s,
+                       table, k, lk, n, keys);
+}
+
 void launch_row_keys(hipStream_t s, const int32_t *table, int32_t k, const KeyCols &kc, int64_t n,
                      uint64_t *keys) {
     hipLaunchKernelGGL(k_row_keys, dim3(grid_for(n, kBlock, kGridCap)), dim3(kBlock), 0, s, table,

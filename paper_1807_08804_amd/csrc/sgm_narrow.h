@@ -64,9 +64,11 @@ struct NResult {
     // a large final table left unordered in the slot's slab for the host to
     // order with whole-GPU kernels after the launch: device addresses of the
     // table ([n_rows][n] in join-level column order, see join_order) and of
-    // its ordering keys (uint64 [n_rows], key_bits bits)
+    // the sorted candidate lists of its key columns (those of more than one
+    // candidate that the result keeps, concatenated in query-vertex order;
+    // cand[u] entries each); the key has key_bits bits
     int32_t host_order, key_bits;
-    int64_t table_ptr, key_ptr;
+    int64_t table_ptr, list_ptr;
 };
 
 constexpr int32_t kNeedWide = 1;  // a capacity of the per-query slot was exceeded

@@ -68,7 +68,7 @@ struct Smem {
     int32_t keybits;
     int64_t pin_off;  // byte offset of that table in the slab
     const int32_t *tableptr;
-    const uint64_t *keyptr;
+    const int32_t *listptr;  // the key columns' sorted candidate lists beside it
     unsigned long long rowhit;  // item_wg: listed rows with a matching entry
     unsigned long long hseq;    // sequence number of the step this workgroup posted
     int32_t hq, hch;            // helper: board entry and chunk claimed (-1: none)
@@ -83,6 +83,7 @@ struct Smem {
     int32_t reason;
     int32_t cand[SGM_MAX_QV];
     int32_t bitsn[SGM_MAX_QV];
+    int32_t kdepth;  // steps of the key columns' binary searches
     int32_t ocol[SGM_MAX_QV];  // table position of each output column
     int32_t nout;              // output columns (the projected ones)
     const int32_t *rkl[SGM_MAX_QV];  // list each key column ranks into (LDS copy if it fits)
@@ -135,6 +136,7 @@ struct Ctx {
     int32_t nslot, ngrid;  // slot workgroups, all workgroups of the launch
     int64_t help_wait;  // polls of a shared step's completion before giving up
     int64_t host_order_rows;  // final tables of this many rows go to the host (0: none)
+    int64_t below_top;  // a last join level placed at the slab's top: the slab used below it
     __device__ uint64_t *B(int u) const { return bits + (int64_t)u * g.nwords; }
     __device__ int32_t *L(int u) const { return lists + (int64_t)u * lcap; }
 };
@@ -1645,14 +1647,47 @@ __device__ __forceinline__ bool ec_contains(const Ctx &c, int e, int32_t keyval,
 // ---------------------------------------------------------------------------
 
 // Sort key of a row: the ranks of its values within their (sorted) candidate
-// lists, concatenated in query-vertex order (s.bitsn bits each).
+// lists, concatenated in query-vertex order (s.bitsn bits each; a column of
+// a single candidate has rank 0 and no bits). The binary searches of up to
+// eight columns advance together, so their probes are independent loads;
+// s.kdepth steps bring every search to its end.
 __device__ __forceinline__ uint64_t row_key(const Ctx &c, const int32_t *row) {
+    const Smem &s = *c.s;
+    const int n = c.Q->n;
+    const int depth = s.kdepth;
     uint64_t key = 0;
-    for (int u = 0; u < c.Q->n; ++u) {
-        const int b = c.s->bitsn[u];
-        if (b == 0) continue;  // a single candidate: rank 0, no bits
-        const int32_t rk = lower_bound_i32(c.s->rkl[u], 0, c.s->cnt[u], row[c.s->jpos[u]]);
-        key = (key << b) | (uint64_t)rk;
+    for (int u0 = 0; u0 < n; u0 += 8) {
+        int32_t x[8], lo[8], len[8];
+        const int32_t *lst[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int u = u0 + j;
+            const bool on = u < n && s.bitsn[u] > 0;
+            lst[j] = on ? s.rkl[u] : nullptr;
+            x[j] = on ? row[s.jpos[u]] : 0;
+            lo[j] = 0;
+            len[j] = on ? s.cnt[u] : 0;
+        }
+        for (int it = 0; it < depth; ++it) {
+            int32_t v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = len[j] > 0 ? lst[j][lo[j] + (len[j] >> 1)] : 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int32_t h = len[j] >> 1;
+                if (len[j] > 0 && v[j] < x[j]) {
+                    lo[j] += h + 1;
+                    len[j] -= h + 1;
+                } else {
+                    len[j] = h;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int u = u0 + j;
+            if (u < n && s.bitsn[u] > 0) key = (key << s.bitsn[u]) | (uint64_t)lo[j];
+        }
     }
     return key;
 }
@@ -1802,7 +1837,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         s.hostord = 0;
         s.keybits = 0;
         s.tableptr = nullptr;
-        s.keyptr = nullptr;
+        s.listptr = nullptr;
         s.abort_ = 0;
         s.slab_used = 0;
         s.empty = 0;
@@ -1953,10 +1988,10 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                     const int cfirst = s.lv_first[lv];
                     // output capacity: what is left of the slab
                     __syncthreads();
-                    const int64_t left = c.slab_bytes - ((s.slab_used + 255) & ~(int64_t)255);
-                    const int64_t cap = left / (4 * (k + 1));
-                    int32_t *out = cap > 0 ? (int32_t *)slab_alloc(c, cap * 4 * (k + 1)) : nullptr;
-                    if (!out) {
+                    const int64_t used0 = (s.slab_used + 255) & ~(int64_t)255;
+                    const int64_t left = c.slab_bytes - used0;
+                    int64_t cap = left / (4 * (k + 1));
+                    if (cap <= 0) {
                         if (threadIdx.x == 0) s.abort_ = kWhySlab;
                         __syncthreads();
                         break;
@@ -1966,6 +2001,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                     // the level's pairs bound its rows: a level that could not
                     // fit even a much larger slot stops here rather than
                     // after filling this one
+                    int64_t pairs = -1;
                     if (rows > NT) {  // one chunk learns its pair count below
                         int64_t mp = 0;
                         for (int64_t r = threadIdx.x; r < rows; r += NT) {
@@ -1973,16 +2009,41 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                             const int32_t i = lower_bound_i32(pk, 0, npk, pv);
                             if (i < npk && pk[i] == pv) mp += ecnt[i];
                         }
-                        int64_t pairs;
                         block_excl_scan(mp, s.sh, &pairs);
                         if (pairs > kPairSlack * cap) {
                             if (threadIdx.x == 0) {
                                 s.abort_ = kWhySlab;
-                                s.need = (s.slab_used - cap * 4 * (k + 1)) + pairs * 4 * (k + 1);
+                                s.need = used0 + pairs * 4 * (k + 1);
                             }
                             __syncthreads();
                             break;
                         }
+                    }
+                    // A last level that may reach the size the host orders
+                    // goes to the top of the slab (its pairs bound its rows),
+                    // with room above for the key columns' candidate lists:
+                    // the slot's later queries keep the slab below it.
+                    int32_t *out = nullptr;
+                    if (lv == n - 2 && c.host_order_rows > 0 && pairs >= c.host_order_rows) {
+                        int64_t lint = 0;
+                        for (int u = 0; u < n; ++u) lint += s.cnt[u];
+                        const int64_t tneed = (pairs * 4 * (k + 1) + 255) & ~(int64_t)255;
+                        const int64_t lneed = (4 * lint + 256 * (n + 1)) & ~(int64_t)255;
+                        const int64_t at = (c.slab_bytes - tneed - lneed) & ~(int64_t)255;
+                        if (at >= kPinFloor(c) && at >= used0) {
+                            out = (int32_t *)(c.slab + at);
+                            cap = pairs;
+                            c.below_top = used0;
+                            __syncthreads();
+                            if (threadIdx.x == 0) s.slab_used = at + pairs * 4 * (k + 1);
+                            __syncthreads();
+                        }
+                    }
+                    if (!out) out = (int32_t *)slab_alloc(c, cap * 4 * (k + 1));
+                    if (!out) {
+                        if (threadIdx.x == 0) s.abort_ = kWhySlab;
+                        __syncthreads();
+                        break;
                     }
                     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
                     uint64_t jb = 0;  // algorithmic bytes of this thread's rows and pairs
@@ -2004,7 +2065,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                             // the single chunk's pairs: same early stop
                             if (threadIdx.x == 0) {
                                 s.abort_ = kWhySlab;
-                                s.need = (s.slab_used - cap * 4 * (k + 1)) + tot * 4 * (k + 1);
+                                s.need = used0 + tot * 4 * (k + 1);
                             }
                             __syncthreads();
                             break;
@@ -2110,7 +2171,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         // its columns
         __syncthreads();
         if (threadIdx.x == 0) {
-            int tb = 0, no = 0;
+            int tb = 0, no = 0, depth = 0;
             for (int u = 0; u < n; ++u) {
                 const bool kept = Q.proj == 0u || ((Q.proj >> u) & 1u);
                 int b = 0;
@@ -2118,9 +2179,12 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                 s.bitsn[u] = b;
                 tb += b;
                 if (kept) s.ocol[no++] = s.jpos[u];
+                // a lower bound over m entries ends after bit_length(m) halvings
+                if (b > 0) depth = max(depth, 32 - __clz(s.cnt[u]));
             }
             s.ctr = tb;
             s.nout = no;
+            s.kdepth = depth;
         }
         __syncthreads();
         if (s.ctr > 64 && rows > 1) {
@@ -2136,24 +2200,26 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         const int no = s.nout;
         int32_t *idx;
         const uint64_t *skeys = nullptr;  // the sorted keys (rows > 1)
-        if (rows > 1) stage_key_lists(c);
         // A large final table in the slab, with room below it for the slot's
-        // later queries: its keys go beside it and the host orders it (and
-        // collapses a projection) with whole-GPU kernels after the launch;
-        // one workgroup would spend milliseconds on the passes and the
-        // gather.
+        // later queries: the key columns' sorted candidate lists go beside
+        // it and the host orders it (and collapses a projection) with
+        // whole-GPU kernels after the launch; one workgroup would spend
+        // milliseconds on the keys, the passes and the gather.
         int64_t toff = (int64_t)((const char *)table - c.slab);
         if (c.host_order_rows > 0 && rows >= c.host_order_rows && toff >= 0 &&
             toff < c.slab_bytes) {
-            uint64_t *ka = nullptr;
+            int64_t lint = 0;
+            for (int u = 0; u < n; ++u)
+                if (s.bitsn[u] > 0) lint += s.cnt[u];
+            int32_t *lst = nullptr;
             const int64_t tbytes = (rows * k * 4 + 255) & ~(int64_t)255;
-            const int64_t top = ((c.slab_bytes - 8 * rows) & ~(int64_t)255) - tbytes;
+            const int64_t top = ((c.slab_bytes - 4 * lint) & ~(int64_t)255) - tbytes;
             if (toff >= kPinFloor(c)) {
-                ka = (uint64_t *)slab_alloc(c, 8 * rows);
+                lst = (int32_t *)slab_alloc(c, 4 * lint);
             } else if (top >= kPinFloor(c) && top > toff) {
                 // too low in the slab to keep for the host: move it up to
-                // the top, keys above it; overlapping, so the chunks go from
-                // the end (every read of a chunk before its writes)
+                // the top, lists above it; overlapping, so the chunks go
+                // from the end (every read of a chunk before its writes)
                 int32_t *dst = (int32_t *)(c.slab + top);
                 const int64_t nint = rows * k;
                 for (int64_t end = nint; end > 0; end -= 4 * NT) {
@@ -2175,18 +2241,24 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                 if (threadIdx.x == 0) add_bytes(c, 8ull * nint);
                 table = dst;
                 toff = top;
-                ka = (uint64_t *)(c.slab + top + tbytes);
+                lst = (int32_t *)(c.slab + top + tbytes);
             }
-            if (ka) {
-                for (int64_t r = threadIdx.x; r < rows; r += NT) ka[r] = row_key(c, table + r * k);
+            if (lst) {
+                int64_t o = 0;
+                for (int u = 0; u < n; ++u) {
+                    if (s.bitsn[u] == 0) continue;
+                    const int32_t *src = c.L(u);
+                    for (int32_t i = threadIdx.x; i < s.cnt[u]; i += NT) lst[o + i] = src[i];
+                    o += s.cnt[u];
+                }
                 __syncthreads();
                 if (threadIdx.x == 0) {
                     s.hostord = 1;
                     s.keybits = tb;
                     s.pin_off = toff;
                     s.tableptr = table;
-                    s.keyptr = ka;
-                    add_bytes(c, (4ull * k + 8ull) * rows);
+                    s.listptr = lst;
+                    add_bytes(c, 8ull * lint);
                 }
                 __syncthreads();
                 ev(c, SGM_EV_SORT);
@@ -2195,6 +2267,15 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                 mark(c, 4);
                 return;
             }
+        }
+        if (rows > 1) stage_key_lists(c);
+        if (c.below_top >= 0 && rows > kRowSortCap) {
+            // the last level sits at the slab's top but stayed on this
+            // workgroup: its sort buffers go into the slab below it
+            __syncthreads();
+            if (threadIdx.x == 0) s.slab_used = c.below_top;
+            __syncthreads();
+            c.slab_bytes = toff;
         }
         if (rows == 1) {
             int32_t *ix = (int32_t *)c.dyn;
@@ -2357,7 +2438,7 @@ __device__ __forceinline__ Ctx slot_ctx(const NArgs &a, Smem &s, unsigned char *
                // while filtering the slab holds the long-row overflow list in
                // [0, 4 lcap) bytes and the marks in [4 lcap, 8 lcap)
                (int32_t *)(slab + 4 * (int64_t)a.lcap), a.board ? a.board + slot : nullptr, a.hctr,
-               a.help_items, q, a.nslot, a.ngrid, a.help_wait, a.host_order_rows};
+               a.help_items, q, a.nslot, a.ngrid, a.help_wait, a.host_order_rows, -1};
 }
 
 // Chunks of the step posted on board entry e, starting with chunk ch, until
@@ -2556,7 +2637,7 @@ __global__ __launch_bounds__(NT, 4) void k_narrow(NArgs a) {
             R.host_order = s.hostord;
             R.key_bits = s.keybits;
             R.table_ptr = (int64_t)(uintptr_t)s.tableptr;
-            R.key_ptr = (int64_t)(uintptr_t)s.keyptr;
+            R.list_ptr = (int64_t)(uintptr_t)s.listptr;
             // phases a query skipped carry the time and bytes of the
             // previous mark
             int64_t prev = s.t[0];
