@@ -83,7 +83,7 @@ def main():
     ap.add_argument("which", nargs="*", default=["batch", "serve", "cyclic"])
     ap.add_argument("--budget", type=float, default=2e11,
                     help="candidate tests per query (batch and serve)")
-    ap.add_argument("--cyclic-budget", type=float, default=2e10,
+    ap.add_argument("--cyclic-budget", type=float, default=1e9,
                     help="candidate tests per query (cyclic)")
     ap.add_argument("--row-cap", type=int, default=100_000_000,
                     help="largest table materialised and hashed")
