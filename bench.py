@@ -121,6 +121,35 @@ def phase_rates(stats, P, resident):
     return out
 
 
+def cold_leg(P, g, queries):
+    """Single queries with cold caches: before each, 1 GiB of device memory
+    is written (torch fill), which evicts the graph's lines from the L2s and
+    the last-level cache; then the query runs alone. Per-phase device time
+    and algorithmic bytes come from the persistent kernel's own clocks."""
+    import torch
+    junk = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    lat, ph_ns, ph_b = [], np.zeros(4), np.zeros(4)
+    for i, q in enumerate(queries):
+        junk.fill_(i)
+        torch.cuda.synchronize()
+        t = time.perf_counter_ns()
+        _, st = g.match_query(q, with_stats=True)
+        lat.append((time.perf_counter_ns() - t) / 1e6)
+        ph_ns += [st["ns_filter"], st["ns_collect"], st["ns_join"], st["ns_finish"]]
+        ph_b += list(st["phase_bytes"])
+    del junk
+    torch.cuda.empty_cache()
+    lat = np.sort(np.asarray(lat))
+    names = ["filter", "collect", "join", "finish"]
+    return {"queries": len(queries),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "phases": {n: {"us_per_query": round(ph_ns[k] / len(queries) / 1e3, 2),
+                           "bytes_per_query": round(ph_b[k] / len(queries), 1),
+                           "gbs": round(ph_b[k] / max(ph_ns[k], 1), 3)}
+                       for k, n in enumerate(names)}}
+
+
 # the thesis's four refinement variants (Ch. 3, Sec. "Effect of Optimization
 # Techniques"): (name, refine_rounds, refine_reversed)
 ABLATION_VARIANTS = [("converge", -1, 0), ("converge_reversed", -1, 1),
@@ -342,6 +371,9 @@ def bench_large(args, P, kggen):
     el_1 = time.perf_counter() - t
     lat_ms = np.sort(np.asarray(lat, np.float64)) / 1e6
     log(f"one at a time: {len(queries)} in {el_1:.3f}s")
+    cold = None if args.no_cold else cold_leg(P, g, queries[:64])
+    if cold:
+        log(f"cold caches, one at a time: p50 {cold['p50_ms']} ms, p99 {cold['p99_ms']} ms")
 
     # per-phase algorithmic bytes and device time of the persistent kernel
     # (filter = root candidates, explore and refine; collect = candidate
@@ -398,7 +430,8 @@ def bench_large(args, P, kggen):
         "single_query": {"queries_per_s": round(len(queries) / el_1, 3),
                          "embeddings_per_s": round(rows_1 / el_1, 1),
                          "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
-                         "p99_ms": round(float(np.percentile(lat_ms, 99)), 3)},
+                         "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                         "cold_caches": cold},
         "batched_over_single": round((nq / el_b) / (len(queries) / el_1), 2),
         "tuning": tuned,
         "default_tuning": {"tuning": default_tuning,
@@ -496,6 +529,8 @@ def main():
                     help="arrival rates (qps) of the medium served-form measurement")
     ap.add_argument("--serve-arrivals", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form legs")
+    ap.add_argument("--no-cold", action="store_true",
+                    help="skip the cold-cache single-query leg (needs torch)")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the refinement / two-graph ablation legs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",

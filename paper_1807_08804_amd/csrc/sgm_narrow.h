@@ -92,11 +92,34 @@ constexpr int64_t kHelpWaitDefault = 1ll << 22;
 // allocated and every posted step is retired before its owner moves on.
 // claim packs (sequence:24 | chunks:20 | next chunk:20): one atomic add
 // claims a chunk and returns which step it belongs to and whether it exists.
+// One join level as every workgroup that works on it sees it: the parent
+// table, the extension edge's candidate-edge table (keyed by the parent
+// vertex's sorted candidates pk), the check edges' tables (each keyed by the
+// sorted candidates kl of the vertex at row column col) and the output.
+struct JChk {
+    const int32_t *kl, *offs, *cnt, *vals;
+    int32_t nkl, col;
+};
+struct JLevel {
+    const int32_t *table;
+    int64_t rows;
+    int32_t k, cp;  // columns of the parent table; column of the parent vertex
+    const int32_t *pk;
+    int32_t npk, nchk;
+    const int32_t *eoffs, *ecnt, *evals;
+    int32_t *out;
+    int64_t cap;   // output rows that fit
+    int32_t nsub;  // shared: chunks per block of NT parent rows
+    int32_t pad;
+    JChk chk[SGM_MAX_QE];
+};
+
 struct HelpJob {
     unsigned long long claim;
     unsigned long long bytes;  // algorithmic bytes of the helpers' chunks
     const int4 *seg;           // kind 1: the row segments, one per chunk
-    int32_t chunk, done, q, kind;  // kind 0: chunks of the candidate list; 1: row segments
+    int32_t chunk, done, q, kind;  // kind 0: chunks of the candidate list; 1: row segments;
+                                   // 2: parent rows of a join level
     int32_t n_items, G, ncount, revd;
     NStep st;
     int32_t nbig, removed, nmarks, abort_;
@@ -107,6 +130,10 @@ struct HelpJob {
     int32_t dirty;
     int32_t cnt[SGM_MAX_QV];
     NNbr nbl[SGM_MAX_QE];
+    // kind 2: chunks of a join level's parent rows; jrows counts the output
+    // rows placed so far
+    unsigned long long jrows;
+    JLevel jl;
 };
 
 struct NArgs {

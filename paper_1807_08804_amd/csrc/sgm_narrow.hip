@@ -54,6 +54,9 @@ struct Smem {
     int32_t big[kBigCap];
     int32_t pairoff[NT];
     int32_t rowlo[NT];
+    JLevel jl;                 // the join level being built
+    int32_t wnok[2][NW];       // shared join levels: rows per wave of a block of pairs
+    int64_t wbase[2];          // and the block's first output row
     int32_t abort_;
     int32_t q;
     int32_t nev;
@@ -96,12 +99,12 @@ struct Smem {
     unsigned long long pb[5];  // bytes at the phase boundaries
 };
 
-// Dynamic LDS, 54 KB: with the static part a workgroup stays within 64 KB,
+// Dynamic LDS, 51 KB: with the static part a workgroup stays within 64 KB,
 // and two workgroups per CU remain resident (registers allow no more). List
 // sorting uses [0, 32 KB); the final ordering keeps keys and indices
 // (bitonic) or digit counts (radix) in [0, 24 KB) and stages the candidate
-// lists its keys rank into at [24 KB, 54 KB).
-constexpr size_t kDynLds = 54 << 10;
+// lists its keys rank into at [24 KB, 51 KB).
+constexpr size_t kDynLds = 51 << 10;
 constexpr size_t kStageOff = 24 << 10;
 constexpr int32_t kStageInts = (int32_t)((kDynLds - kStageOff) / sizeof(int32_t));
 static_assert(sizeof(int32_t) * kListSortCap <= kDynLds, "list sort space");
@@ -110,7 +113,10 @@ static_assert(kDynLds + sizeof(Smem) <= (64 << 10), "LDS per workgroup");
 static_assert(8 * 256 * sizeof(int32_t) <= kStageOff, "radix counts");
 
 struct Ctx {
-    DevGraph g;
+    // the launch's graph, read in place from the kernel arguments (a copy in
+    // the context would live in scratch memory: its adjacency pointers are
+    // chosen by direction at run time)
+    const DevGraph &g;
     int32_t lcap;
     int64_t slab_bytes;
     int32_t *out;
@@ -1642,6 +1648,272 @@ __device__ __forceinline__ bool ec_contains(const Ctx &c, int e, int32_t keyval,
     return j < hi && c.s->ec_vals[e][j] == x;
 }
 
+// Shared join levels: a chunk is one block of NT parent rows, or 1/nsub of
+// its pairs (every nsub-th block of NT pairs) when the level's pairs are
+// few rows with long fan-outs; about kJoinChunkPairs pairs per chunk. A
+// level of at least kJoinSharePairs pairs is shared with the launch's idle
+// workgroups (those that become idle while it runs join in too).
+constexpr int64_t kJoinChunkPairs = 16384;
+constexpr int64_t kJoinSharePairs = 2 * kJoinChunkPairs;
+constexpr int kJoinMaxSub = 64;
+// blocks of pairs whose accepted rows take one output reservation (shared
+// levels): up to 4 NT pairs, staged per wave in LDS
+constexpr int kJoinGroup = 4;
+
+// Pair i of a block: its row rr within the block of parent rows (the last
+// whose pair offset is <= pi), its new value x, and whether the extended
+// row passes the injectivity test and every check edge of the level
+// (Sec. "Joining Phase").
+__device__ __forceinline__ bool join_pair(const Smem &s, const JLevel &L, int64_t r0, int64_t pi,
+                                          int32_t *rr_out, int32_t *x_out, uint64_t &jb) {
+    int32_t a0 = 0, a1 = NT;
+    while (a1 - a0 > 1) {
+        const int32_t mid = (a0 + a1) >> 1;
+        if (s.pairoff[mid] <= pi) a0 = mid;
+        else a1 = mid;
+    }
+    const int32_t x = L.evals[s.rowlo[a0] + (pi - s.pairoff[a0])];
+    const int k = L.k;
+    const int32_t *row = L.table + (r0 + a0) * k;
+    bool ok = true;
+    for (int cc = 0; cc < k; ++cc)
+        if (row[cc] == x) ok = false;
+    for (int ci = 0; ci < L.nchk && ok; ++ci) {
+        // the check edge's values for the row's key vertex hold x
+        const JChk &h = L.chk[ci];
+        const int32_t kval = row[h.col];
+        const int32_t i = lower_bound_i32(h.kl, 0, h.nkl, kval);
+        if (i >= h.nkl || h.kl[i] != kval) {
+            ok = false;
+        } else {
+            const int32_t vlo = h.offs[i], vhi = vlo + h.cnt[i];
+            const int32_t jx = lower_bound_i32(h.vals, vlo, vhi, x);
+            ok = jx < vhi && h.vals[jx] == x;
+        }
+    }
+    jb += 4ull + 4ull * k + 24ull * L.nchk + (ok ? 4ull * (k + 1) : 0ull);
+    *rr_out = a0;
+    *x_out = x;
+    return ok;
+}
+
+// Copy a wave's n staged output rows (parent row within the block, new
+// value) to out[base, base + n), consecutive lanes on consecutive ints.
+__device__ __forceinline__ void join_put(const JLevel &L, int64_t r0, const int32_t *wrr,
+                                         const int32_t *wx, int n, int64_t base, int lane) {
+    const int k = L.k, w = k + 1;
+    // e / w by a 16-bit reciprocal: exact for e < 4096, w <= 16
+    const uint32_t inv = (65536u + (uint32_t)w - 1u) / (uint32_t)w;
+    int32_t *dst = L.out + base * w;
+    for (int e = lane; e < n * w; e += 64) {
+        const int rw = (int)(((uint32_t)e * inv) >> 16);
+        const int cc = e - rw * w;
+        dst[e] = cc < k ? L.table[(r0 + wrr[rw]) * k + cc] : wx[rw];
+    }
+}
+
+// Rows [r0, r1) of join level L (at most NT of them): each row's fan-out
+// (the candidate-edge count of its parent vertex's value), then its pairs
+// in blocks of NT, the accepted rows appended to L.out.
+// Owner alone (SHARED false): every block of pairs, output places by one
+// LDS atomic per wave. SHARED: the blocks sub, sub + nsub, ... only, and
+// the accepted rows of up to kJoinGroup of them take their places with one
+// device-scope atomic on *gctr.
+template <bool SHARED>
+__device__ __forceinline__ void join_rows(Ctx &c, const JLevel &L, int64_t r0, int64_t r1,
+                                          int32_t sub, int32_t nsub, unsigned long long *gctr,
+                                          int32_t *gabort, uint64_t &jb) {
+    Smem &s = *c.s;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t r = r0 + threadIdx.x;
+    int32_t fan = 0, lo = 0;
+    if (r < r1) {
+        const int32_t pv = L.table[r * L.k + L.cp];
+        const int32_t i = lower_bound_i32(L.pk, 0, L.npk, pv);
+        if (i < L.npk && L.pk[i] == pv) {
+            lo = L.eoffs[i];
+            fan = L.ecnt[i];
+        }
+        jb += 16ull + 4ull * (32 - __clz(L.npk | 1));
+    }
+    int64_t tot;
+    const int64_t ex = block_excl_scan(fan, s.sh, &tot);
+    if (!SHARED && L.rows <= NT && tot > kPairSlack * L.cap) {
+        // the level's only block of rows: its pairs bound the level, so a
+        // level that could not fit even a much larger slot stops here
+        if (threadIdx.x == 0) {
+            s.abort_ = kWhySlab;
+            s.need = (int64_t)((const char *)L.out - c.slab) + tot * 4 * (L.k + 1);
+        }
+        __syncthreads();
+        return;
+    }
+    s.pairoff[threadIdx.x] = (int32_t)ex;
+    s.rowlo[threadIdx.x] = lo;
+    __syncthreads();
+    int32_t *wrr = (int32_t *)c.dyn + wid * 512;  // this wave's staged rows
+    int32_t *wx = wrr + 256;
+    if (!SHARED) {
+        for (int64_t pb = 0; pb < tot; pb += NT) {
+            const int64_t pi = pb + threadIdx.x;
+            int32_t rr = 0, x = 0;
+            const bool ok = pi < tot && join_pair(s, L, r0, pi, &rr, &x, jb);
+            const uint64_t bm = __ballot(ok);
+            const int nok = __popcll(bm);
+            int32_t base = 0;
+            const int leader = bm ? __builtin_ctzll(bm) : 0;
+            if (bm && lane == leader) base = atomicAdd(&s.ctr, nok);
+            base = __shfl(base, leader, 64);
+            if (ok) {
+                const int j = __popcll(bm & lanemask_lt(lane));
+                wrr[j] = rr;
+                wx[j] = x;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if ((int64_t)base + nok > L.cap) {
+                if (lane == 0) s.abort_ = kWhySlab;
+            } else {
+                join_put(L, r0, wrr, wx, nok, base, lane);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    } else {
+        const int64_t nblk = (tot + NT - 1) / NT;
+        int par = 0;
+        for (int64_t i0 = sub; i0 < nblk; i0 += (int64_t)nsub * kJoinGroup, par ^= 1) {
+            int wn = 0;
+            for (int t = 0; t < kJoinGroup; ++t) {
+                const int64_t bi = i0 + (int64_t)t * nsub;
+                if (bi >= nblk) break;
+                const int64_t pi = bi * NT + threadIdx.x;
+                int32_t rr = 0, x = 0;
+                const bool ok = pi < tot && join_pair(s, L, r0, pi, &rr, &x, jb);
+                const uint64_t bm = __ballot(ok);
+                if (ok) {
+                    const int j = wn + __popcll(bm & lanemask_lt(lane));
+                    wrr[j] = rr;
+                    wx[j] = x;
+                }
+                wn += __popcll(bm);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // one reservation for the group's accepted rows (two buffers: a
+            // wave may run one group ahead)
+            if (lane == 0) s.wnok[par][wid] = wn;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int32_t t = 0;
+                for (int w = 0; w < NW; ++w) t += s.wnok[par][w];
+                s.wbase[par] = t ? (int64_t)atomicAdd(gctr, (unsigned long long)t) : 0;
+            }
+            __syncthreads();
+            int64_t base = s.wbase[par];
+            for (int w = 0; w < wid; ++w) base += s.wnok[par][w];
+            if (base + wn > L.cap) {
+                if (lane == 0 && wn) atomicExch(gabort, kWhySlab);
+            } else {
+                join_put(L, r0, wrr, wx, wn, base, lane);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    __syncthreads();
+}
+
+// Chunk ch of a shared level: its block of parent rows and its share of
+// that block's pairs.
+__device__ __forceinline__ void join_chunk(Ctx &c, const JLevel &L, int32_t ch,
+                                           unsigned long long *gctr, int32_t *gabort,
+                                           uint64_t &jb) {
+    const int64_t b = ch / L.nsub;
+    const int64_t r0 = b * NT;
+    join_rows<true>(c, L, r0, min(L.rows, r0 + NT), ch % L.nsub, L.nsub, gctr, gabort, jb);
+}
+
+// A join level shared through this slot's board entry (kind 2): the level's
+// view goes to the entry, its parent rows are cut into nch chunks that the
+// owner and idle workgroups claim, output rows are placed through the
+// entry's counter; the owner waits for the chunks its helpers claimed (the
+// same protocol as a shared filter step) and takes the row count into
+// s.ctr.
+__device__ __forceinline__ void shared_join(Ctx &c, int32_t nch, uint64_t &jb) {
+    HelpJob *j = c.job;
+    Smem &s = *c.s;
+    {
+        const uint64_t *src = (const uint64_t *)&s.jl;
+        uint64_t *dst = (uint64_t *)&j->jl;
+        for (int i = threadIdx.x; i < (int)(sizeof(JLevel) / 8); i += NT) dst[i] = src[i];
+    }
+    if (threadIdx.x == 0) {
+        j->jrows = 0ull;
+        j->abort_ = 0;
+        j->bytes = 0ull;
+        j->done = 0;
+        j->kind = 2;
+        j->chunk = 0;
+        j->q = c.q;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t seq =
+            claim_seq(__hip_atomic_load(&j->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) + 1u;
+        // the level's view, tables and edge tables before the claim word
+        __threadfence();
+        atomicExch(&j->claim, claim_word(seq, nch));
+        atomicAdd(&c.hctr[0], 1);
+    }
+    __syncthreads();
+    int32_t own = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const unsigned long long w = take_chunk(j);
+            s.hch = claim_next(w) < claim_nch(w) ? claim_next(w) : -1;
+        }
+        __syncthreads();
+        const int32_t ch = s.hch;
+        __syncthreads();
+        if (ch < 0) break;
+        join_chunk(c, s.jl, ch, &j->jrows, &j->abort_, jb);
+        ++own;
+    }
+    ev(c, SGM_EV_SHARED);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t got = atomicAdd(&j->done, own) + own;
+        int64_t n = 0;
+        while (got < nch && n < c.help_wait) {
+            __builtin_amdgcn_s_sleep(1);
+            got = __hip_atomic_load(&j->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ++n;
+        }
+        if (got < nch) {
+            // give up as a filter step does: no further claims, and the
+            // slot stays out of use until the next launch clears it
+            const uint32_t seq = claim_seq(
+                __hip_atomic_load(&j->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            atomicExch(&j->claim, claim_word(seq, 0));
+            atomicExch(&j->dirty, 1);
+            s.retired = 1;
+        }
+        // the helpers' rows, written before their reports
+        __threadfence();
+        atomicSub(&c.hctr[0], 1);
+        const unsigned long long placed =
+            __hip_atomic_load(&j->jrows, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s.ctr = (int32_t)min((unsigned long long)s.jl.cap, placed);
+        const int32_t ab = __hip_atomic_load(&j->abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ab) s.abort_ = ab;
+        if (placed > (unsigned long long)s.jl.cap) s.abort_ = kWhySlab;
+        if (got < nch) s.abort_ = kWhyHelp;
+        add_bytes(c, __hip_atomic_load(&j->bytes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // final ordering helpers
 // ---------------------------------------------------------------------------
@@ -2002,7 +2274,11 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                     // fit even a much larger slot stops here rather than
                     // after filling this one
                     int64_t pairs = -1;
-                    if (rows > NT) {  // one chunk learns its pair count below
+                    const bool may_share = c.job && c.help_items > 0;
+                    // a block of rows whose pairs could reach a shared or a
+                    // host-ordered level (rows times the extension edge's
+                    // candidate edges bound them) counts them here too
+                    if (rows > NT || rows * s.ectot[ext] >= kJoinSharePairs) {
                         int64_t mp = 0;
                         for (int64_t r = threadIdx.x; r < rows; r += NT) {
                             const int32_t pv = table[r * k + cp];
@@ -2045,96 +2321,49 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                         __syncthreads();
                         break;
                     }
-                    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+                    // the level's view (parent column, edge tables of its
+                    // extension and check edges, output), the same for the
+                    // owner and for helpers
+                    __syncthreads();
+                    if (threadIdx.x == 0) {
+                        JLevel &L = s.jl;
+                        L.table = table;
+                        L.rows = rows;
+                        L.k = k;
+                        L.cp = cp;
+                        L.pk = pk;
+                        L.npk = npk;
+                        L.eoffs = eoffs;
+                        L.ecnt = ecnt;
+                        L.evals = evals;
+                        L.nchk = nchk;
+                        for (int ci = 0; ci < nchk; ++ci) {
+                            const int e = s.chk[cfirst + ci];
+                            const int kv = s.eckey[e];
+                            L.chk[ci] = JChk{c.L(kv), s.ec_offs[e], s.ec_cnt[e], s.ec_vals[e],
+                                             s.cnt[kv], s.jpos[kv]};
+                        }
+                        L.out = out;
+                        L.cap = cap;
+                    }
+                    // a level of many pairs is shared (whether or not
+                    // workgroups are idle yet: those that become idle join)
+                    const int64_t nrb = (rows + NT - 1) / NT;
+                    int64_t nsub = 1;
+                    if (may_share && pairs >= kJoinSharePairs)
+                        nsub = min((int64_t)kJoinMaxSub,
+                                   max((int64_t)1, (pairs + nrb * kJoinChunkPairs - 1) /
+                                                       (nrb * kJoinChunkPairs)));
+                    const bool share = may_share && pairs >= kJoinSharePairs && nrb * nsub <= kMaxChunks;
+                    if (threadIdx.x == 0) s.jl.nsub = (int32_t)nsub;
+                    __syncthreads();
                     uint64_t jb = 0;  // algorithmic bytes of this thread's rows and pairs
-                    for (int64_t rbase = 0; rbase < rows; rbase += NT) {
-                        const int64_t r = rbase + threadIdx.x;
-                        int32_t fan = 0, lo = 0;
-                        if (r < rows) {
-                            const int32_t pv = table[r * k + cp];
-                            const int32_t i = lower_bound_i32(pk, 0, npk, pv);
-                            if (i < npk && pk[i] == pv) {
-                                lo = eoffs[i];
-                                fan = ecnt[i];
-                            }
-                        }
-                        if (r < rows) jb += 16ull + 4ull * (32 - __clz(npk | 1));
-                        int64_t tot;
-                        const int64_t ex = block_excl_scan(fan, s.sh, &tot);
-                        if (rows <= NT && tot > kPairSlack * cap) {
-                            // the single chunk's pairs: same early stop
-                            if (threadIdx.x == 0) {
-                                s.abort_ = kWhySlab;
-                                s.need = used0 + tot * 4 * (k + 1);
-                            }
-                            __syncthreads();
-                            break;
-                        }
-                        s.pairoff[threadIdx.x] = (int32_t)ex;
-                        s.rowlo[threadIdx.x] = lo;
-                        __syncthreads();
-                        for (int64_t pb = 0; pb < tot; pb += NT) {
-                            const int64_t pi = pb + threadIdx.x;
-                            bool ok = false;
-                            int32_t x = 0;
-                            int32_t rr = 0;
-                            if (pi < tot) {
-                                // last chunk row whose pair offset <= pi
-                                int32_t a0 = 0, a1 = NT;
-                                while (a1 - a0 > 1) {
-                                    const int32_t mid = (a0 + a1) >> 1;
-                                    if (s.pairoff[mid] <= pi) a0 = mid;
-                                    else a1 = mid;
-                                }
-                                rr = a0;
-                                x = evals[s.rowlo[rr] + (pi - s.pairoff[rr])];
-                                const int32_t *row = table + (rbase + rr) * k;
-                                ok = true;
-                                for (int cc = 0; cc < k; ++cc)
-                                    if (row[cc] == x) ok = false;
-                                for (int ci = 0; ci < nchk && ok; ++ci) {
-                                    const int e = s.chk[cfirst + ci];
-                                    const int kv = s.eckey[e];
-                                    ok = ec_contains(c, e, row[s.jpos[kv]], x);
-                                }
-                            }
-                            if (pi < tot) jb += 4ull + 4ull * k + 24ull * nchk + (ok ? 4ull * (k + 1) : 0ull);
-                            const uint64_t bm = __ballot(ok);
-                            const int nok = __popcll(bm);
-                            int32_t base = 0;
-                            const int leader = bm ? __builtin_ctzll(bm) : 0;
-                            if (bm && lane == leader) base = atomicAdd(&s.ctr, nok);
-                            base = __shfl(base, leader, 64);
-                            // the wave's accepted rows are out[base, base + nok):
-                            // list (parent row, new value) per output row in
-                            // LDS, then copy the rows with consecutive lanes on
-                            // consecutive ints
-                            int32_t *wrr = (int32_t *)c.dyn + wid * 128;
-                            int32_t *wx = wrr + 64;
-                            if (ok) {
-                                const int j = __popcll(bm & lanemask_lt(lane));
-                                wrr[j] = rr;
-                                wx[j] = x;
-                            }
-                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                            __builtin_amdgcn_wave_barrier();
-                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                            if ((int64_t)base + nok > cap) {
-                                if (lane == 0) s.abort_ = kWhySlab;
-                            } else {
-                                const int w = k + 1;
-                                // e / w by a 16-bit reciprocal: exact for e < 64 w, w <= 16
-                                const uint32_t inv = (65536u + (uint32_t)w - 1u) / (uint32_t)w;
-                                int32_t *dst = out + (int64_t)base * w;
-                                for (int e = lane; e < nok * w; e += 64) {
-                                    const int r = (int)(((uint32_t)e * inv) >> 16);
-                                    const int cc = e - r * w;
-                                    dst[e] = cc < k ? table[(rbase + wrr[r]) * k + cc] : wx[r];
-                                }
-                            }
-                            __builtin_amdgcn_wave_barrier();
-                        }
-                        __syncthreads();
+                    if (share) {
+                        shared_join(c, (int32_t)(nrb * nsub), jb);
+                    } else {
+                        for (int64_t rbase = 0; rbase < rows && !aborted(c); rbase += NT)
+                            join_rows<false>(c, s.jl, rbase, min(rows, rbase + NT), 0, 1,
+                                             nullptr, nullptr, jb);
                     }
                     add_bytes(c, jb);
                     __syncthreads();
@@ -2459,17 +2688,25 @@ __device__ __forceinline__ void help_step(const NArgs &a, Smem &s, unsigned char
         s.nbl[threadIdx.x].mode = j->nbl[threadIdx.x].mode;
         s.nbl[threadIdx.x].rel = j->nbl[threadIdx.x].rel;
     }
+    if (kind == 2) {
+        const uint64_t *src = (const uint64_t *)&j->jl;
+        uint64_t *dst = (uint64_t *)&s.jl;
+        for (int i = threadIdx.x; i < (int)(sizeof(JLevel) / 8); i += NT) dst[i] = src[i];
+    }
     __syncthreads();
     Ctx c = slot_ctx(a, s, dyn, e, j->q, a.slab_bytes);
     c.trace = nullptr;
     uint64_t fb = 0;
     int32_t n = 0;
     while (ch >= 0) {
-        if (kind == 0)
+        if (kind == 0) {
             filter_items(c, BoardCtr{j}, st.push != 0, s.nbl, ncount, c.L(st.u), c.B(st.u), revd,
                          G, ch * K, min(n_items, ch * K + K), fb);
-        else
+        } else if (kind == 1) {
             push_segment(c, BoardCtr{j}, s.nbl, seg[ch], fb);
+        } else {
+            join_chunk(c, s.jl, ch, &j->jrows, &j->abort_, fb);
+        }
         ++n;
         __syncthreads();
         if (threadIdx.x == 0) {

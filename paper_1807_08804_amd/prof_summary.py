@@ -1,10 +1,13 @@
 """Summaries of rocprofv3 CSV output for the profiles/ folder.
 
-Two uses:
+Three uses:
 
 ``kernels``: per-kernel dispatch statistics of a ``--kernel-trace`` run, plus
 the dispatches of one kernel that a bench run times (the last N with at
 least a given grid), as a markdown table.
+
+``counters``: the mean per dispatch of every counter of one ``--pmc`` run
+(LDS bank conflicts and instructions, for instance) for selected dispatches.
 
 ``traffic``: HBM bytes per dispatch from a ``--pmc FETCH_SIZE`` run and a
 ``--pmc WRITE_SIZE`` run of the same command, each scaled by what the same
@@ -140,6 +143,36 @@ def cmd_traffic(a):
     print(json.dumps(rec["entries"][a.key]))
 
 
+def cmd_counters(a):
+    """Mean per dispatch of every counter of a --pmc run, for the selected
+    dispatches of each kernel spec; with SQ_LDS_BANK_CONFLICT and
+    SQ_INSTS_LDS both present, also the conflict cycles per LDS
+    instruction."""
+    rows = _csv(a.pmc, "counter_collection.csv")
+    out = [f"# rocprofv3 counters: {a.title}", "", f"Command: `{a.command}`", "",
+           "| kernel (selection) | counter | dispatches | mean per dispatch | min | max |",
+           "|---|---|---|---|---|---|"]
+    ratios = []
+    for spec in a.select:
+        name, min_grid, last = spec.split(":")
+        sel = [r for r in rows if name in r["Kernel_Name"] and _grid(r) >= int(min_grid)]
+        by = collections.OrderedDict()
+        for r in sel:
+            by.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        means = {}
+        for c, v in by.items():
+            v = v[-int(last):] if int(last) > 0 else v
+            means[c] = statistics.mean(v)
+            out.append(f"| `{name}` ({spec}) | {c} | {len(v)} | {means[c]:.4g} | {min(v):.4g} | "
+                       f"{max(v):.4g} |")
+        if "SQ_LDS_BANK_CONFLICT" in means and means.get("SQ_INSTS_LDS"):
+            ratios.append(f"`{name}`: {means['SQ_LDS_BANK_CONFLICT'] / means['SQ_INSTS_LDS']:.3f} "
+                          "bank-conflict cycles per LDS instruction")
+    if ratios:
+        out += [""] + ["* " + x for x in ratios]
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -153,8 +186,14 @@ def main():
         t.add_argument(o, required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--command", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("--pmc", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", required=True)
+    c.add_argument("--select", action="append", required=True,
+                   help="kernel:min_grid_threads:last_n")
     a = ap.parse_args()
-    cmd_kernels(a) if a.cmd == "kernels" else cmd_traffic(a)
+    {"kernels": cmd_kernels, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
 
 
 if __name__ == "__main__":
