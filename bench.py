@@ -123,22 +123,25 @@ def phase_rates(stats, P, resident):
 
 def cold_leg(P, g, queries):
     """Single queries with cold caches: before each, 1 GiB of device memory
-    is written (torch fill), which evicts the graph's lines from the L2s and
-    the last-level cache; then the query runs alone. Per-phase device time
-    and algorithmic bytes come from the persistent kernel's own clocks."""
-    import torch
-    junk = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    is written (hipMemset through the HIP runtime the library itself uses),
+    which evicts the graph's lines from the L2s and the last-level cache;
+    then the query runs alone. Per-phase device time and algorithmic bytes
+    come from the persistent kernel's own clocks."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    junk, size = ctypes.c_void_p(), ctypes.c_size_t(1 << 30)
+    if hip.hipMalloc(ctypes.byref(junk), size) != 0:
+        raise RuntimeError("hipMalloc of the 1 GiB eviction buffer failed")
     lat, ph_ns, ph_b = [], np.zeros(4), np.zeros(4)
     for i, q in enumerate(queries):
-        junk.fill_(i)
-        torch.cuda.synchronize()
+        if hip.hipMemset(junk, ctypes.c_int(i & 255), size) != 0 or hip.hipDeviceSynchronize() != 0:
+            raise RuntimeError("eviction write failed")
         t = time.perf_counter_ns()
         _, st = g.match_query(q, with_stats=True)
         lat.append((time.perf_counter_ns() - t) / 1e6)
         ph_ns += [st["ns_filter"], st["ns_collect"], st["ns_join"], st["ns_finish"]]
         ph_b += list(st["phase_bytes"])
-    del junk
-    torch.cuda.empty_cache()
+    hip.hipFree(junk)
     lat = np.sort(np.asarray(lat))
     names = ["filter", "collect", "join", "finish"]
     return {"queries": len(queries),
@@ -530,7 +533,7 @@ def main():
     ap.add_argument("--serve-arrivals", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true", help="skip the served-form legs")
     ap.add_argument("--no-cold", action="store_true",
-                    help="skip the cold-cache single-query leg (needs torch)")
+                    help="skip the cold-cache single-query leg")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the refinement / two-graph ablation legs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",

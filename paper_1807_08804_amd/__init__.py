@@ -220,6 +220,40 @@ def _make_query(n, vlabel, vpin, esrc, edst, elabel):
     return q, buf
 
 
+# numpy view of an array of sgm_query structs (two int32, five addresses)
+_QUERY_DTYPE = np.dtype({"names": ["n", "m", "p0", "p1", "p2", "p3", "p4"],
+                         "formats": [np.int32, np.int32] + [np.uint64] * 5,
+                         "offsets": [sgm_query.n_vertices.offset, sgm_query.n_edges.offset,
+                                     sgm_query.vertex_label.offset, sgm_query.vertex_pin.offset,
+                                     sgm_query.edge_src.offset, sgm_query.edge_dst.offset,
+                                     sgm_query.edge_label.offset],
+                         "itemsize": ctypes.sizeof(sgm_query)})
+
+
+def _pack_queries(queries):
+    """The C query structs of a list of queries in one array, and the one
+    int32 block their pointers refer to (keep both alive while in use):
+    the same layout _make_query gives each query, built with whole-array
+    operations."""
+    nq = len(queries)
+    arrs = [a for q in queries for a in (q.vlabel, q.vpin, q.esrc, q.edst, q.elabel)]
+    lens = np.fromiter((len(a) for a in arrs), np.int64, count=5 * nq).reshape(nq, 5)
+    if nq and ((lens[:, 1] != lens[:, 0]).any() or (lens[:, 3] != lens[:, 2]).any()
+               or (lens[:, 4] != lens[:, 2]).any()):
+        raise ValueError("vertex arrays and edge arrays must have matching lengths")
+    buf = np.concatenate(arrs).astype(np.int32, copy=False) if nq else np.zeros(1, np.int32)
+    starts = np.zeros((nq, 5), np.int64)
+    flat = np.cumsum(lens.reshape(-1))
+    starts.reshape(-1)[1:] = flat[:-1]
+    base = buf.__array_interface__["data"][0]
+    arr = np.zeros(max(nq, 1), _QUERY_DTYPE)
+    arr["n"][:nq] = np.fromiter((q.n for q in queries), np.int32, count=nq)
+    arr["m"][:nq] = lens[:, 2]
+    for f in range(5):
+        arr[f"p{f}"][:nq] = base + 4 * starts[:, f]
+    return arr, buf
+
+
 def sgm_match_query(g, q: sgm_query, flags: int = SGM_SORTED):
     out = ctypes.POINTER(sgm_result)()
     rc = lib().sgm_match_query(g, ctypes.byref(q), int(flags), ctypes.byref(out))
@@ -227,8 +261,12 @@ def sgm_match_query(g, q: sgm_query, flags: int = SGM_SORTED):
 
 
 def sgm_match_batch(g, qs, flags: int = SGM_SORTED):
+    """qs: a list of sgm_query, or a packed array from _pack_queries."""
     n = len(qs)
-    arr = (sgm_query * max(n, 1))(*qs)
+    if isinstance(qs, np.ndarray):
+        arr = qs.ctypes.data_as(ctypes.POINTER(sgm_query))
+    else:
+        arr = (sgm_query * max(n, 1))(*qs)
     outs = (ctypes.POINTER(sgm_result) * max(n, 1))()
     rc = lib().sgm_match_batch(g, arr, n, int(flags), outs)
     return rc, [outs[i] for i in range(n)]
@@ -242,7 +280,10 @@ def sgm_match_query_proj(g, q: sgm_query, project: int, flags: int = SGM_SORTED)
 
 def sgm_match_batch_proj(g, qs, projects, flags: int = SGM_SORTED):
     n = len(qs)
-    arr = (sgm_query * max(n, 1))(*qs)
+    if isinstance(qs, np.ndarray):
+        arr = qs.ctypes.data_as(ctypes.POINTER(sgm_query))
+    else:
+        arr = (sgm_query * max(n, 1))(*qs)
     pm = (ctypes.c_uint32 * max(n, 1))(*[int(x) for x in projects])
     outs = (ctypes.POINTER(sgm_result) * max(n, 1))()
     rc = lib().sgm_match_batch_proj(g, arr, pm, n, int(flags), outs)
@@ -332,9 +373,18 @@ def _take_rows(r, n):
         sgm_free_result(r)
         return k, out
     addr = ctypes.cast(res.rows, ctypes.c_void_p).value
-    buf = (ctypes.c_int32 * (k * n)).from_address(addr)
-    buf._owner = _ResultOwner(r)
-    return k, np.frombuffer(buf, np.int32).reshape(k, n)
+    return k, np.asarray(_RowsView(addr, k, n, _ResultOwner(r)))
+
+
+class _RowsView:
+    """The array interface of a result's row table: numpy arrays made from
+    it keep it (and so the library's result) alive."""
+    __slots__ = ("__array_interface__", "_owner")
+
+    def __init__(self, addr, k, n, owner):
+        self.__array_interface__ = {"data": (addr, False), "shape": (k, n), "typestr": "<i4",
+                                    "version": 3}
+        self._owner = owner
 
 
 def stats_dict(st: sgm_stats, n: int, m: int) -> dict:
@@ -437,25 +487,26 @@ class Graph:
         kggen-style queries, through sgm_match_batch (sgm_match_batch_proj
         with ``projects``, one projection per query); with_stats=True also
         returns each member's statistics as a dict."""
-        built = [_make_query(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel) for q in queries]
+        arr, keep = _pack_queries(queries)
         fl = SGM_COUNT_ONLY if count_only else SGM_SORTED
         if projects is None:
-            rc, outs = sgm_match_batch(self._h, [b[0] for b in built], fl)
+            rc, outs = sgm_match_batch(self._h, arr[:len(queries)], fl)
         else:
-            rc, outs = sgm_match_batch_proj(self._h, [b[0] for b in built],
+            rc, outs = sgm_match_batch_proj(self._h, arr[:len(queries)],
                                             [project_mask(p) for p in projects], fl)
         if rc != SGM_OK:
             raise SGMError(rc, "sgm_match_batch")
         res, stats = [], []
         for q, r in zip(queries, outs):
-            st = r.contents.status
+            rc_ = r.contents
+            st = rc_.status
             if with_stats:
-                stats.append(stats_dict(r.contents.stats, q.n, len(q.esrc)))
+                stats.append(stats_dict(rc_.stats, q.n, len(q.esrc)))
             if st != SGM_OK:
                 res.append(SGMError(st, "batch member"))
                 sgm_free_result(r)
             else:
-                k, rows = _take_rows(r, int(r.contents.n_cols) if projects is not None else q.n)
+                k, rows = _take_rows(r, int(rc_.n_cols) if projects is not None else q.n)
                 res.append(k if count_only else rows)
         return (res, stats) if with_stats else res
 

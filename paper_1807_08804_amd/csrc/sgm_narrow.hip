@@ -732,11 +732,16 @@ __device__ __forceinline__ void filter_items(Ctx &c, const K &k, bool push, cons
     // The overflow list sits at the start of the slot's slab, which no phase
     // uses while filtering (at most lcap entries, far below its size).
     int32_t *ov = (int32_t *)c.slab;
-    for (int32_t it = it0 + threadIdx.x / G; it < it1; it += NGr) {
-        const int32_t up = ul[it];
-        if (revd && !bit_test(ub, up)) continue;  // already dropped
+    // the next item's vertex is read while this one is tested, and its row
+    // offsets as soon as it has arrived (one dependent read less per item)
+    int32_t it = it0 + threadIdx.x / G;
+    int32_t upn = it < it1 ? ul[it] : 0;
+    for (; it < it1; it += NGr) {
+        const int32_t up = upn;
         const int32_t ob = g.out_off[up], oe = g.out_off[up + 1];
         const int32_t ib = g.in_off[up], ie = g.in_off[up + 1];
+        upn = it + NGr < it1 ? ul[it + NGr] : 0;
+        if (revd && !bit_test(ub, up)) continue;  // already dropped
         int32_t maxd = 0;
         for (int j = 0; j < ncount; ++j) maxd = max(maxd, nb[j].dir ? ie - ib : oe - ob);
         if (maxd > bigdeg) {
@@ -1131,8 +1136,11 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
         for (int32_t it = 0; it < n_items; ++it) item_wg(c, st, nb, ncount, ul[it], ub, fb, def);
         if (def) push_deferred(c, st, nb, ncount, def, fb);
     } else {
-        const int32_t helpers = n_items >= c.help_items ? helpers_now(c) : 0;
-        if (helpers > 0)
+        // a step of many candidates is shared whether or not workgroups are
+        // idle yet (in a batch they become idle while it runs)
+        const bool share = c.help_items > 0 && c.job && n_items >= c.help_items;
+        const int32_t helpers = share ? helpers_now(c) : 0;
+        if (share)
             shared_items(c, st, nb, ncount, ul, ub, revd, n_items, helpers, fb);
         else
             filter_items(c, LdsCtr{c.s}, st.push != 0, nb, ncount, ul, ub, revd,

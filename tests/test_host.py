@@ -150,6 +150,31 @@ def test_out_only_graph_options_checked_before_touching_device():
         assert e.value.code == P.SGM_EINVAL
 
 
+def test_batch_packing_points_at_each_querys_arrays():
+    """_pack_queries (one int32 block and one array of C query structs for a
+    whole batch) gives every struct the counts and the five arrays of its
+    query, read back through the struct's own addresses."""
+    from tests.micro import random_query
+    rng = np.random.default_rng(11)
+    qs = [random_query(rng, int(rng.integers(1, 17)), 4, 3, 1000, extra=4) for _ in range(50)]
+    arr, keep = P._pack_queries(qs)
+    structs = ctypes.cast(arr.ctypes.data, ctypes.POINTER(P.sgm_query))
+    for i, q in enumerate(qs):
+        sq = structs[i]
+        assert sq.n_vertices == q.n and sq.n_edges == len(q.esrc)
+        for name, want in (("vertex_label", q.vlabel), ("vertex_pin", q.vpin),
+                           ("edge_src", q.esrc), ("edge_dst", q.edst), ("edge_label", q.elabel)):
+            if len(want) == 0:
+                continue
+            got = np.ctypeslib.as_array(ctypes.cast(getattr(sq, name), ctypes.POINTER(ctypes.c_int32)),
+                                        (len(want),))
+            assert np.array_equal(got, want), (i, name)
+    with pytest.raises(ValueError):
+        bad = random_query(rng, 3, 4, 3, 1000)
+        bad.vpin = bad.vpin[:1]
+        P._pack_queries([bad])
+
+
 def test_strerror():
     assert P.sgm_strerror(P.SGM_ETOOBIG)
     assert P.sgm_strerror(12345) == "unknown error"
