@@ -184,6 +184,10 @@ struct NarrowCtx {
     int64_t *d_trace = nullptr, *h_trace = nullptr;  // [trace_cap][SGM_TRACE_CAP]
     int trace_cap = 0;
     hipEvent_t done = nullptr;
+    // result tables go to pinned host blocks on this second stream while
+    // the context's own stream orders the next large table
+    hipStream_t copy = nullptr;
+    std::vector<hipEvent_t> copy_ev;
     // one batch as a HIP graph: upload descriptors, upload root predicates,
     // root sweep, persistent kernel, read back results, read back counters.
     // Built on first use; every launch updates all node parameters.
@@ -1498,6 +1502,11 @@ void narrow_free(NarrowCtx &nw) {
     host_free(nw.h_trace);
     if (nw.done) (void)hipEventDestroy(nw.done);
     nw.done = nullptr;
+    if (nw.copy) {
+        (void)hipStreamSynchronize(nw.copy);
+        (void)hipStreamDestroy(nw.copy);
+    }
+    for (hipEvent_t e : nw.copy_ev) (void)hipEventDestroy(e);
     if (nw.gexec) (void)hipGraphExecDestroy(nw.gexec);
     if (nw.graph) (void)hipGraphDestroy(nw.graph);
     nw.gexec = nullptr;
@@ -1881,14 +1890,24 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
             if (b) block_release(b);
         }
     } hold;
+    // the copies into a pinned block run on the context's copy stream and
+    // are waited for before this call returns (also when it throws)
+    struct CopyWait {
+        hipStream_t s = nullptr;
+        ~CopyWait() {
+            if (s) (void)hipStreamSynchronize(s);
+        }
+    } copy_wait;
     if (want && arena_bytes + host_bytes >= kBlockMin) {
         blk = block_get(arena_bytes + host_bytes);
         blk->refs.store(1);
         hold.b = blk;
+        if (!nw.copy) HIPX(hipStreamCreateWithFlags(&nw.copy, hipStreamNonBlocking));
+        copy_wait.s = nw.copy;
+        // the kernel has finished (nw.done): the arena is final
         if (used > 0)
             HIPX(hipMemcpyAsync(blk->ptr, nw.d_out, sizeof(int32_t) * used, hipMemcpyDeviceToHost,
-                                st));
-        HIPX(hipStreamSynchronize(st));
+                                nw.copy));
     } else if (want && used > kOutPrefix) {
         // the launch read back the first kOutPrefix ints; the rest now
         int64_t from = kOutPrefix;
@@ -1981,6 +2000,10 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
     // order them (and collapse projections) with whole-GPU kernels on this
     // context's stream (the graph's own; caller holds g->mu), then read them
     // back
+    // one scope for all of them: each sorted table stays on the device until
+    // the copy stream has taken it
+    Scope sc(g->pool);
+    size_t nev = 0;
     for (int i : hostord) {
         const NResult &r = nw.h_res[i];
         const int qi_idx = job.packed[i];
@@ -1995,7 +2018,6 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         int64_t R = r.n_rows;
         const bool rows_wanted = !(flags & SGM_COUNT_ONLY);
         if (rows_wanted || qi.proj) {
-            Scope sc(g->pool);
             const int32_t *table = (const int32_t *)(uintptr_t)r.table_ptr;
             // keys from the key columns' lists the kernel left beside the
             // table (the same columns and widths as its own ordering)
@@ -2043,14 +2065,24 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
             if (rows_wanted && !(g->opts.result_cap_rows > 0 && R > g->opts.result_cap_rows)) {
                 const size_t bytes = sizeof(int32_t) * (size_t)R * no;
                 if (blk) {
-                    // straight into the pinned block (room was set aside)
+                    // straight into the pinned block (room was set aside), on
+                    // the copy stream once this stream has ordered the table
                     out->rows = (int32_t *)(blk->ptr + blk_next);
                     blk_next += (bytes + 255) & ~(size_t)255;
                     result_block(out) = blk;
                     blk->refs.fetch_add(1);
-                    if (bytes)
-                        HIPX(hipMemcpyAsync(out->rows, sorted, bytes, hipMemcpyDeviceToHost, st));
-                    HIPX(hipStreamSynchronize(st));
+                    if (bytes) {
+                        if (nev == nw.copy_ev.size()) {
+                            hipEvent_t e;
+                            HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                            nw.copy_ev.push_back(e);
+                        }
+                        HIPX(hipEventRecord(nw.copy_ev[nev], st));
+                        HIPX(hipStreamWaitEvent(nw.copy, nw.copy_ev[nev], 0));
+                        ++nev;
+                        HIPX(hipMemcpyAsync(out->rows, sorted, bytes, hipMemcpyDeviceToHost,
+                                            nw.copy));
+                    }
                 } else {
                     out->rows = alloc_rows(bytes);
                     if (!out->rows) throw std::bad_alloc();
@@ -2062,6 +2094,8 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
         out->status = g->opts.result_cap_rows > 0 && R > g->opts.result_cap_rows ? SGM_ETOOBIG
                                                                                  : SGM_OK;
     }
+    // every table in its block before the sorted copies go back to the pool
+    if (copy_wait.s) HIPX(hipStreamSynchronize(copy_wait.s));
     if (profiled) prof_flush(g);
 }
 
