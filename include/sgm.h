@@ -458,6 +458,15 @@ typedef struct {
 
 void sgm_default_serve_options(sgm_serve_options *o);
 
+/* Failure isolation test hook (not for production use): the member with
+ * index query_index (its position in the sgm_match_batch call, 0 for
+ * sgm_match_query) of the next persistent-kernel launch on g ends, on the
+ * device, as a fault confined to it would: its result carries SGM_EDEVICE,
+ * every other member of the launch completes normally. One-shot; -1
+ * cancels. Queries on the multi-kernel path are not affected. Errors:
+ * SGM_EINVAL for a NULL graph or an index below -1. */
+int sgm_inject_fault(sgm_graph *g, int64_t query_index);
+
 /* Start a server on g (g must outlive it). Errors: SGM_EINVAL, SGM_ENOMEM,
  * SGM_EDEVICE. The server owns its streams and its host threads: a
  * dispatcher (batching and admission), one completer per stream (each

@@ -131,6 +131,7 @@ EXPORTS = {
                                       ctypes.c_int32, _i32p, _i32p, _i32p, _i32p]),
     "sgm_match_query_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query),
                                                ctypes.c_uint32, _i32p, ctypes.c_int64, _i64p]),
+    "sgm_inject_fault": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
     "sgm_estimate_query": (ctypes.c_int, [ctypes.POINTER(sgm_query), ctypes.c_int32, ctypes.c_int64,
                                           _i64p, ctypes.c_int32, _i64p, ctypes.c_int32, _i64p]),
     "sgm_inspect_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query), _i64p,
@@ -585,6 +586,13 @@ class Graph:
             lib().sgm_kernel_stats(self._h, kid, ctypes.byref(s))
             out[name] = dict(launches=s.launches, ms=s.ms_total, bytes=s.bytes_total)
         return out
+
+    def inject_fault(self, query_index: int):
+        """sgm_inject_fault: member query_index of the next persistent-kernel
+        launch fails with SGM_EDEVICE (a failure-isolation test hook)."""
+        rc = lib().sgm_inject_fault(self._h, int(query_index))
+        if rc != SGM_OK:
+            raise SGMError(rc, "sgm_inject_fault")
 
     def reset_kernel_stats(self):
         lib().sgm_reset_kernel_stats(self._h)

@@ -209,6 +209,9 @@ struct NarrowCtx {
 }  // namespace
 
 struct sgm_graph {
+    // sgm_inject_fault: the query index of the next persistent-kernel launch
+    // that fails as if by a device fault (-1: none)
+    int64_t fault_query = -1;
     int device = 0;
     hipStream_t stream = nullptr;
     sgm_options opts;
@@ -1674,6 +1677,10 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
         NQuery *dst = &nw.h_q[job.packed.size()];
         int rs = nroot;
         if (pack_query(g, qis[which[i]], plans[i], dst, &rs, &pl)) {
+            if (g->fault_query >= 0 && which[i] == g->fault_query) {
+                dst->fault = 1;
+                g->fault_query = -1;
+            }
             nroot = rs;
             job.packed.push_back(which[i]);
             job.plans.push_back(pl);
@@ -1939,6 +1946,10 @@ void narrow_collect(sgm_graph *g, NarrowCtx &nw, NarrowJob &job, const std::vect
     for (int i = 0; i < np; ++i) {
         const NResult &r = nw.h_res[i];
         const int qi_idx = job.packed[i];
+        if (r.status == kFault) {
+            res[qi_idx]->status = SGM_EDEVICE;
+            continue;
+        }
         if (r.status != SGM_OK) {
             wide.push_back(qi_idx);
             // sgm_stats.fallback codes: the kernel's reasons 1, 2, 4; 8 for a
@@ -2365,6 +2376,13 @@ void sgm_free_graph(sgm_graph *g) {
     if (!g) return;
     free_graph_mem(g);
     delete g;
+}
+
+int sgm_inject_fault(sgm_graph *g, int64_t query_index) {
+    if (!g || query_index < -1) return SGM_EINVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->fault_query = query_index;
+    return SGM_OK;
 }
 
 void sgm_default_tuning(sgm_tuning *t) {

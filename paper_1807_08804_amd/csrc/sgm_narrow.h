@@ -41,6 +41,7 @@ struct NQuery {
     int32_t n_init, n_ref;  // explore steps, then refine steps (one round)
     int32_t refine_rounds;  // -1: until nothing is removed
     uint32_t proj;          // projected columns (bit u = query vertex u kept; 0: all)
+    int32_t fault;          // 1: fail as a device fault would (sgm_inject_fault)
     NStep steps[kNMaxSteps];
     NNbr nbr[kNMaxNbr];
 };
@@ -73,6 +74,7 @@ struct NResult {
 
 constexpr int32_t kNeedWide = 1;  // a capacity of the per-query slot was exceeded
 constexpr int32_t kOutFull = 2;   // the shared output arena was full
+constexpr int32_t kFault = 3;     // an injected device fault (no rerun: SGM_EDEVICE)
 // why a query left the persistent kernel
 constexpr int32_t kWhyList = 1;   // a candidate list outgrew its slot capacity
 constexpr int32_t kWhySlab = 2;   // edge tables / join tables / sort buffers outgrew the slab

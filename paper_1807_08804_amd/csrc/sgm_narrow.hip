@@ -2127,6 +2127,13 @@ __device__ __forceinline__ void run_query(Ctx &c) {
         s.offset = 0;
         s.need = 0;
         s.bytes = 0;
+        if (Q.fault) s.status = kFault;
+    }
+    if (Q.fault) {
+        // a failure injected from the host: this query alone ends with a
+        // device error, as a fault confined to it would
+        __syncthreads();
+        return;
     }
     __syncthreads();
     mark(c, 0);
