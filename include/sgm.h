@@ -271,6 +271,7 @@ const char *sgm_last_error(void);
 #define SGM_EV_SORT 9      /* final rows ordered */
 #define SGM_EV_OUTPUT 10   /* rows copied to the output arena */
 #define SGM_EV_SHARED 11   /* a shared join level: no chunk left for its owner to claim */
+#define SGM_EV_LONGROWS 12 /* a filter step's regular candidates done; its long rows follow */
 int sgm_trace_events(sgm_graph *g, int32_t i, int64_t *out, int32_t cap, double *ns_per_tick);
 
 /*

@@ -25,7 +25,8 @@ SGM_SORTED, SGM_COUNT_ONLY = 0, 1
 SGM_PATH_AUTO, SGM_PATH_WIDE, SGM_PATH_NARROW = 0, 1, 2
 SGM_TRACE_CAP = 256
 EVENT_NAMES = {1: "start", 2: "root", 3: "explore", 4: "refine", 5: "lists", 6: "edges",
-               7: "order", 8: "level", 9: "sort", 10: "output", 11: "shared"}
+               7: "order", 8: "level", 9: "sort", 10: "output", 11: "shared",
+               12: "longrows"}
 (SGM_K_CHECK, SGM_K_COLLECT, SGM_K_EXPLORE, SGM_K_REFINE, SGM_K_EC_COUNT, SGM_K_EC_WRITE,
  SGM_K_JOIN, SGM_K_SORT, SGM_K_OTHER, SGM_K_PERSIST, SGM_K_COUNT) = range(11)
 KERNEL_NAMES = ["check", "collect", "explore", "refine", "ec_count", "ec_write", "join",

@@ -120,6 +120,7 @@ struct HelpJob {
     unsigned long long claim;
     unsigned long long bytes;  // algorithmic bytes of the helpers' chunks
     const int4 *seg;           // kind 1: the row segments, one per chunk
+    const int32_t *ul;         // kind 0: the items (a candidate list, or long rows)
     int32_t chunk, done, q, kind;  // kind 0: chunks of the candidate list; 1: row segments;
                                    // 2: parent rows of a join level
     int32_t n_items, G, ncount, revd;

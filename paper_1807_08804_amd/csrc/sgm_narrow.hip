@@ -32,6 +32,10 @@ namespace {
 constexpr int NT = kNarrowThreads;
 constexpr int NW = NT / 64;
 constexpr int kBigCap = 256;         // LDS list of items for the whole workgroup
+// A shared step with at least kLongShare long rows (over 64 strides of its
+// lanes) shares them too, kLongChunk rows per chunk, one wave per row.
+constexpr int32_t kLongShare = 32;
+constexpr int32_t kLongChunk = 16;
 constexpr int32_t kRevMin = 256;      // candidates of u before a reverse check can pay
 constexpr int32_t kRevMaxCand = 4096; // neighbours with at most this many candidates
 constexpr int kListSortCap = 8192;    // int32 entries sorted in LDS
@@ -311,13 +315,28 @@ __device__ __forceinline__ void compact_list(Ctx &c, int u) {
     __syncthreads();
     const int32_t n = c.s->cnt[u];
     int64_t out = 0;
-    for (int32_t base = 0; base < n; base += NT) {
-        const int32_t i = base + threadIdx.x;
-        const int32_t x = i < n ? l[i] : 0;
-        const bool keep = i < n && bit_test(b, x);
+    // eight consecutive entries per thread, their reads and bit tests all in
+    // flight before the block scan; entries keep their order
+    constexpr int kI = 8;
+    for (int32_t base = 0; base < n; base += kI * NT) {
+        const int32_t i0 = base + threadIdx.x * kI;
+        int32_t x[kI];
+#pragma unroll
+        for (int k = 0; k < kI; ++k) x[k] = i0 + k < n ? l[i0 + k] : 0;
+        bool keep[kI];
+        int32_t cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kI; ++k) {
+            keep[k] = i0 + k < n && bit_test(b, x[k]);
+            cnt += keep[k] ? 1 : 0;
+        }
         int64_t tot;
-        const int64_t ex = block_excl_scan(keep ? 1 : 0, c.s->sh, &tot);
-        if (keep) l[out + ex] = x;
+        int64_t p = out + block_excl_scan(cnt, c.s->sh, &tot);
+        // the block scan's barriers ordered every read of this round before
+        // these writes, which stay at or below the entries just read
+#pragma unroll
+        for (int k = 0; k < kI; ++k)
+            if (keep[k]) l[p++] = x[k];
         out += tot;
     }
     __syncthreads();
@@ -334,20 +353,34 @@ __device__ __forceinline__ void list_from_bits(Ctx &c, int u, const uint64_t *sr
     uint64_t *b = c.B(u);
     int32_t *l = c.L(u);
     int64_t out = 0;
-    for (int32_t base = 0; base < nwords; base += NT) {
-        const int32_t w = base + threadIdx.x;
-        uint64_t word = w < nwords ? src[w] : 0ull;
-        if (copy_bits && w < nwords) b[w] = word;
+    // eight consecutive words per thread, all read before any is used (a
+    // dependent read per block scan would leave the workgroup waiting)
+    constexpr int kW = 8;
+    for (int32_t base = 0; base < nwords; base += kW * NT) {
+        const int32_t w0 = base + threadIdx.x * kW;
+        uint64_t wd[kW];
+#pragma unroll
+        for (int k = 0; k < kW; ++k) wd[k] = w0 + k < nwords ? src[w0 + k] : 0ull;
+        int32_t cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kW; ++k) {
+            if (copy_bits && w0 + k < nwords) b[w0 + k] = wd[k];
+            cnt += __popcll(wd[k]);
+        }
         int64_t tot;
-        const int64_t ex = block_excl_scan(__popcll(word), c.s->sh, &tot);
+        const int64_t ex = block_excl_scan(cnt, c.s->sh, &tot);
         if (out + tot > c.lcap) {
             if (threadIdx.x == 0) c.s->abort_ = kWhyList;
             break;  // uniform: tot and out are block-uniform
         }
         int64_t p = out + ex;
-        while (word) {
-            l[p++] = w * 64 + __builtin_ctzll(word);
-            word &= word - 1ull;
+#pragma unroll
+        for (int k = 0; k < kW; ++k) {
+            uint64_t word = wd[k];
+            while (word) {
+                l[p++] = (w0 + k) * 64 + __builtin_ctzll(word);
+                word &= word - 1ull;
+            }
         }
         out += tot;
     }
@@ -372,7 +405,7 @@ __device__ __forceinline__ void sort_list(Ctx &c, int u) {
     // barrier rounds of a bitonic network vs. an ordered rebuild from the
     // bitmap (two barriers per NT words)
     const int64_t cost_bitonic = (int64_t)lg * (lg + 1) / 2 * ((N / 2 + NT - 1) / NT);
-    const int64_t cost_bits = 2 * ((c.g.nwords + NT - 1) / NT);
+    const int64_t cost_bits = 2 * ((c.g.nwords + 8 * NT - 1) / (8 * NT));
     if (n > kListSortCap || cost_bits < cost_bitonic) {
         list_from_bits(c, u, c.B(u), false);
         return;
@@ -751,6 +784,34 @@ __device__ __forceinline__ void filter_items(Ctx &c, const K &k, bool push, cons
             if (gl == 0) ov[atomicAdd(k.nbig(), 1)] = up;
             continue;
         }
+        if (push && ncount == 1) {
+            // a single neighbour test: one scan pushes the hits it finds,
+            // and a candidate with none is dropped (it pushed nothing)
+            const NNbr d = nb[0];
+            const int2 *adj = d.dir ? g.in_adj : g.out_adj;
+            const int32_t beg = d.dir ? ib : ob, end = d.dir ? ie : oe;
+            uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
+            int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
+            bool any = false;
+            for (int32_t i = beg + gl; i < end; i += 4 * G) {
+                const int2 e0 = adj_at(adj, i, end), e1 = adj_at(adj, i + G, end);
+                const int2 e2 = adj_at(adj, i + 2 * G, end), e3 = adj_at(adj, i + 3 * G, end);
+                const bool h0 = (i < end) & nbr_hit(c, d, e0);
+                const bool h1 = (i + G < end) & nbr_hit(c, d, e1);
+                const bool h2 = (i + 2 * G < end) & nbr_hit(c, d, e2);
+                const bool h3 = (i + 3 * G < end) & nbr_hit(c, d, e3);
+                push4(c, k, tb, tl, d.v, h0, e0.x, h1, e1.x, h2, e2.x, h3, e3.x);
+                any |= h0 | h1 | h2 | h3;
+            }
+            if (!(__ballot(any) & gmask)) {
+                if (gl == 0) {
+                    atomicAnd((unsigned long long *)&ub[up >> 6], ~(1ull << (up & 63)));
+                    atomicAdd(k.removed(), 1);
+                }
+            }
+            if (gl == 0) fb += 20ull + 12ull * (uint64_t)(end - beg);
+            continue;
+        }
         bool alive = true;
         uint64_t seen = 0;
         for (int j = 0; j < ncount && alive; ++j) {
@@ -919,6 +980,7 @@ __device__ __forceinline__ void shared_job(Ctx &c, int kind, const NStep &st, co
         j->done = 0;
         j->kind = kind;
         j->seg = seg;
+        j->ul = ul;
         j->chunk = K;
         j->q = c.q;
         j->n_items = n_items;
@@ -1148,8 +1210,24 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
         const int lane = threadIdx.x & 63;
         int32_t *ov = (int32_t *)c.slab;
         __syncthreads();
+        if (share && c.s->nbig >= kLongShare && c.slab_bytes >= 16 * (int64_t)c.lcap) {
+            // many long rows: one wave per row, shared like the step itself
+            // (the rows move to a list of their own, since rows longer still
+            // come back to the overflow list)
+            ev(c, SGM_EV_LONGROWS);
+            const int32_t nl = c.s->nbig;
+            int32_t *rows = (int32_t *)(c.slab + 12 * (int64_t)c.lcap);
+            for (int32_t i = threadIdx.x; i < nl; i += NT) rows[i] = ov[i];
+            __syncthreads();
+            if (threadIdx.x == 0) c.s->nbig = 0;
+            const int32_t nch = (nl + kLongChunk - 1) / kLongChunk;
+            shared_job(c, 0, st, nb, ncount, rows, ub, revd, nl, kLongChunk, 64, nch, nullptr,
+                       fb);
+            __syncthreads();
+        }
         // one wave per long row; rows above wg_rows get the whole workgroup
         const int32_t nbig = c.s->nbig;
+        if (nbig > 0) ev(c, SGM_EV_LONGROWS);
         int32_t *def = nbig > 0 ? defer_list(c, st) : nullptr;
         for (int32_t b = threadIdx.x >> 6; b < nbig; b += NW) {
             const int32_t up = ov[b];
@@ -2697,6 +2775,7 @@ __device__ __forceinline__ void help_step(const NArgs &a, Smem &s, unsigned char
     const bool revd = j->revd != 0;
     const int kind = j->kind;
     const int4 *seg = j->seg;
+    const int32_t *hul = j->ul;
     if ((int)threadIdx.x < ncount) {
         s.nbl[threadIdx.x].v = j->nbl[threadIdx.x].v;
         s.nbl[threadIdx.x].dir = j->nbl[threadIdx.x].dir;
@@ -2715,8 +2794,8 @@ __device__ __forceinline__ void help_step(const NArgs &a, Smem &s, unsigned char
     int32_t n = 0;
     while (ch >= 0) {
         if (kind == 0) {
-            filter_items(c, BoardCtr{j}, st.push != 0, s.nbl, ncount, c.L(st.u), c.B(st.u), revd,
-                         G, ch * K, min(n_items, ch * K + K), fb);
+            filter_items(c, BoardCtr{j}, st.push != 0, s.nbl, ncount, hul, c.B(st.u), revd, G,
+                         ch * K, min(n_items, ch * K + K), fb);
         } else if (kind == 1) {
             push_segment(c, BoardCtr{j}, s.nbl, seg[ch], fb);
         } else {
