@@ -459,6 +459,12 @@ typedef struct {
 
 void sgm_default_serve_options(sgm_serve_options *o);
 
+/* The results of a batch at a glance, for bindings: for each of rs[0 .. n)
+ * four int64 values at out[4 i]: status, n_cols, n_rows and the address of
+ * rows (0 when NULL). A NULL entry reads as (SGM_EINVAL, 0, 0, 0). Takes no
+ * ownership; out holds 4 n values (caller-owned). */
+void sgm_results_summary(sgm_result *const *rs, int32_t n, int64_t *out);
+
 /* Failure isolation test hook (not for production use): the member with
  * index query_index (its position in the sgm_match_batch call, 0 for
  * sgm_match_query) of the next persistent-kernel launch on g ends, on the

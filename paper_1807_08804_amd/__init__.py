@@ -133,6 +133,8 @@ EXPORTS = {
     "sgm_match_query_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query),
                                                ctypes.c_uint32, _i32p, ctypes.c_int64, _i64p]),
     "sgm_inject_fault": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "sgm_results_summary": (None, [ctypes.POINTER(ctypes.POINTER(sgm_result)), ctypes.c_int32,
+                                   _i64p]),
     "sgm_estimate_query": (ctypes.c_int, [ctypes.POINTER(sgm_query), ctypes.c_int32, ctypes.c_int64,
                                           _i64p, ctypes.c_int32, _i64p, ctypes.c_int32, _i64p]),
     "sgm_inspect_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query), _i64p,
@@ -238,8 +240,11 @@ def _pack_queries(queries):
     the same layout _make_query gives each query, built with whole-array
     operations."""
     nq = len(queries)
-    arrs = [a for q in queries for a in (q.vlabel, q.vpin, q.esrc, q.edst, q.elabel)]
-    lens = np.fromiter((len(a) for a in arrs), np.int64, count=5 * nq).reshape(nq, 5)
+    arrs = []
+    ext = arrs.extend
+    for q in queries:
+        ext((q.vlabel, q.vpin, q.esrc, q.edst, q.elabel))
+    lens = np.fromiter(map(len, arrs), np.int64, count=5 * nq).reshape(nq, 5)
     if nq and ((lens[:, 1] != lens[:, 0]).any() or (lens[:, 3] != lens[:, 2]).any()
                or (lens[:, 4] != lens[:, 2]).any()):
         raise ValueError("vertex arrays and edge arrays must have matching lengths")
@@ -262,8 +267,9 @@ def sgm_match_query(g, q: sgm_query, flags: int = SGM_SORTED):
     return rc, out
 
 
-def sgm_match_batch(g, qs, flags: int = SGM_SORTED):
-    """qs: a list of sgm_query, or a packed array from _pack_queries."""
+def sgm_match_batch(g, qs, flags: int = SGM_SORTED, raw: bool = False):
+    """qs: a list of sgm_query, or a packed array from _pack_queries. The
+    results as a list of pointers, or (raw) the ctypes array itself."""
     n = len(qs)
     if isinstance(qs, np.ndarray):
         arr = qs.ctypes.data_as(ctypes.POINTER(sgm_query))
@@ -271,7 +277,7 @@ def sgm_match_batch(g, qs, flags: int = SGM_SORTED):
         arr = (sgm_query * max(n, 1))(*qs)
     outs = (ctypes.POINTER(sgm_result) * max(n, 1))()
     rc = lib().sgm_match_batch(g, arr, n, int(flags), outs)
-    return rc, [outs[i] for i in range(n)]
+    return rc, outs if raw else [outs[i] for i in range(n)]
 
 
 def sgm_match_query_proj(g, q: sgm_query, project: int, flags: int = SGM_SORTED):
@@ -280,7 +286,7 @@ def sgm_match_query_proj(g, q: sgm_query, project: int, flags: int = SGM_SORTED)
     return rc, out
 
 
-def sgm_match_batch_proj(g, qs, projects, flags: int = SGM_SORTED):
+def sgm_match_batch_proj(g, qs, projects, flags: int = SGM_SORTED, raw: bool = False):
     n = len(qs)
     if isinstance(qs, np.ndarray):
         arr = qs.ctypes.data_as(ctypes.POINTER(sgm_query))
@@ -289,7 +295,7 @@ def sgm_match_batch_proj(g, qs, projects, flags: int = SGM_SORTED):
     pm = (ctypes.c_uint32 * max(n, 1))(*[int(x) for x in projects])
     outs = (ctypes.POINTER(sgm_result) * max(n, 1))()
     rc = lib().sgm_match_batch_proj(g, arr, pm, n, int(flags), outs)
-    return rc, [outs[i] for i in range(n)]
+    return rc, outs if raw else [outs[i] for i in range(n)]
 
 
 def project_mask(project) -> int:
@@ -376,6 +382,25 @@ def _take_rows(r, n):
         return k, out
     addr = ctypes.cast(res.rows, ctypes.c_void_p).value
     return k, np.asarray(_RowsView(addr, k, n, _ResultOwner(r)))
+
+
+class _BatchOwner:
+    """Keeps the results of one sgm_match_batch call alive while numpy
+    arrays view any of their rows; frees them all after the last."""
+
+    __slots__ = ("outs", "n")
+
+    def __init__(self, outs, n):
+        self.outs, self.n = outs, n
+
+    def __del__(self):
+        outs, self.outs = self.outs, None
+        if outs is not None:
+            try:
+                for i in range(self.n):
+                    sgm_free_result(outs[i])
+            except Exception:
+                pass
 
 
 class _RowsView:
@@ -492,24 +517,30 @@ class Graph:
         arr, keep = _pack_queries(queries)
         fl = SGM_COUNT_ONLY if count_only else SGM_SORTED
         if projects is None:
-            rc, outs = sgm_match_batch(self._h, arr[:len(queries)], fl)
+            rc, outs = sgm_match_batch(self._h, arr[:len(queries)], fl, raw=True)
         else:
             rc, outs = sgm_match_batch_proj(self._h, arr[:len(queries)],
-                                            [project_mask(p) for p in projects], fl)
+                                            [project_mask(p) for p in projects], fl, raw=True)
         if rc != SGM_OK:
             raise SGMError(rc, "sgm_match_batch")
-        res, stats = [], []
-        for q, r in zip(queries, outs):
-            rc_ = r.contents
-            st = rc_.status
-            if with_stats:
-                stats.append(stats_dict(rc_.stats, q.n, len(q.esrc)))
+        n = len(queries)
+        # every member's (status, columns, rows, row address) in one call; the
+        # batch's results are freed together once no table of it is in use
+        info = np.zeros((max(n, 1), 4), np.int64)
+        lib().sgm_results_summary(outs, n, info.ctypes.data_as(_i64p))
+        owner = _BatchOwner(outs, n)
+        stats = [stats_dict(outs[i].contents.stats, q.n, len(q.esrc))
+                 for i, q in enumerate(queries)] if with_stats else []
+        res = []
+        for st, ncol, k, addr in info[:n].tolist():
             if st != SGM_OK:
                 res.append(SGMError(st, "batch member"))
-                sgm_free_result(r)
+            elif count_only:
+                res.append(k)
+            elif k == 0 or not addr:
+                res.append(np.empty((k, ncol), np.int32))
             else:
-                k, rows = _take_rows(r, int(rc_.n_cols) if projects is not None else q.n)
-                res.append(k if count_only else rows)
+                res.append(np.asarray(_RowsView(addr, k, ncol, owner)))
         return (res, stats) if with_stats else res
 
     def inspect_query(self, q):

@@ -2378,6 +2378,17 @@ void sgm_free_graph(sgm_graph *g) {
     delete g;
 }
 
+void sgm_results_summary(sgm_result *const *rs, int32_t n, int64_t *out) {
+    if (!rs || !out) return;
+    for (int32_t i = 0; i < n; ++i) {
+        const sgm_result *r = rs[i];
+        out[4 * (int64_t)i + 0] = r ? r->status : SGM_EINVAL;
+        out[4 * (int64_t)i + 1] = r ? r->n_cols : 0;
+        out[4 * (int64_t)i + 2] = r ? r->n_rows : 0;
+        out[4 * (int64_t)i + 3] = r ? (int64_t)(uintptr_t)r->rows : 0;
+    }
+}
+
 int sgm_inject_fault(sgm_graph *g, int64_t query_index) {
     if (!g || query_index < -1) return SGM_EINVAL;
     std::lock_guard<std::mutex> lk(g->mu);
