@@ -11,6 +11,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <functional>
 #include <deque>
 #include <thread>
 #include <cstdio>
@@ -519,6 +520,86 @@ void parallel_copy(const std::vector<HostCopy> &cs) {
     for (int t = 1; t < nt; ++t) th.emplace_back(work, per * t, std::min(total, per * (t + 1)));
     work(0, std::min(total, per));
     for (auto &x : th) x.join();
+}
+
+// Host worker threads for per-query planning and packing: started once,
+// kept for the life of the process (never destroyed, so no thread waits on
+// a pool that exit tears down), parked on a condition variable between
+// jobs. One job at a time; the caller works on it too.
+class HostPool {
+  public:
+    static HostPool &get() {
+        static HostPool *p = new HostPool();
+        return *p;
+    }
+    int workers() const { return (int)nworkers_; }
+    // run(c) for c in [0, nchunks), on the workers and the caller
+    void run(int nchunks, const std::function<void(int)> &fn) {
+        std::lock_guard<std::mutex> one(job_mu_);
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            fn_ = &fn;
+            nchunks_ = nchunks;
+            next_.store(0);
+            left_ = nchunks;
+            ++gen_;
+        }
+        cv_.notify_all();
+        work();
+        std::unique_lock<std::mutex> lk(mu_);
+        done_cv_.wait(lk, [&] { return left_ == 0; });
+        fn_ = nullptr;
+    }
+
+  private:
+    HostPool() {
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        nworkers_ = std::min(7u, hw > 1 ? hw - 1 : 0u);
+        for (unsigned t = 0; t < nworkers_; ++t) std::thread([this] { loop(); }).detach();
+    }
+    void work() {
+        for (;;) {
+            const int c = next_.fetch_add(1);
+            if (c >= nchunks_) return;
+            (*fn_)(c);
+            std::lock_guard<std::mutex> lk(mu_);
+            if (--left_ == 0) done_cv_.notify_all();
+        }
+    }
+    void loop() {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return gen_ != seen; });
+                seen = gen_;
+                if (!fn_) continue;
+            }
+            work();
+        }
+    }
+    unsigned nworkers_ = 0;
+    std::mutex job_mu_, mu_;
+    std::condition_variable cv_, done_cv_;
+    const std::function<void(int)> *fn_ = nullptr;
+    int nchunks_ = 0, left_ = 0;
+    std::atomic<int> next_{0};
+    uint64_t gen_ = 0;
+};
+
+// f(lo, hi) over [0, n) in chunks of at least min_each items, on the host
+// pool's workers and the caller (the caller alone for small n).
+template <class F>
+void parallel_for(int n, int min_each, F &&f) {
+    HostPool &pool = HostPool::get();
+    const int nt = std::min<int>(pool.workers() + 1, n / std::max(1, min_each));
+    if (nt <= 1) {
+        f(0, n);
+        return;
+    }
+    const int per = (n + nt - 1) / nt;
+    const std::function<void(int)> chunk = [&](int c) { f(c * per, std::min(n, (c + 1) * per)); };
+    pool.run(nt, chunk);
 }
 
 constexpr size_t kStageBytes = (size_t)256 << 20;  // multi-kernel readback chunk
@@ -1656,40 +1737,57 @@ bool narrow_launch(sgm_graph *g, NarrowCtx &nw, const std::vector<QInfo> &qis, c
     std::vector<int64_t> cost((size_t)count, -1);
     std::vector<int> order;
     order.reserve((size_t)count);
-    for (int i = 0; i < count; ++i) {
-        const QInfo &qi = qis[which[i]];
-        if (make_plan(qi, g->V, g->type_freq.data(), g->n_types, &plans[i]) != SGM_OK) {
-            wide.push_back(which[i]);
-            res[which[i]]->stats.fallback = 16;
-            continue;
+    parallel_for(count, 128, [&](int lo, int hi) {
+        for (int i = lo; i < hi; ++i) {
+            const QInfo &qi = qis[which[i]];
+            if (make_plan(qi, g->V, g->type_freq.data(), g->n_types, &plans[i]) != SGM_OK)
+                continue;  // cost stays -1
+            const int r = plans[i].visit[0];
+            const int32_t lab = qi.label[r];
+            const int64_t rootc = qi.pin[r] >= 0 ? 1
+                                  : (lab >= 0 && lab < g->n_types ? g->type_freq[lab] : g->V);
+            cost[i] = rootc * (SGM_MAX_QV + 1) + qi.n;
         }
-        const int r = plans[i].visit[0];
-        const int32_t lab = qi.label[r];
-        const int64_t rootc = qi.pin[r] >= 0 ? 1
-                              : (lab >= 0 && lab < g->n_types ? g->type_freq[lab] : g->V);
-        cost[i] = rootc * (SGM_MAX_QV + 1) + qi.n;
-        order.push_back(i);
-    }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    int nroot = 0;
-    for (int i : order) {
-        Plan pl;
-        NQuery *dst = &nw.h_q[job.packed.size()];
-        int rs = nroot;
-        if (pack_query(g, qis[which[i]], plans[i], dst, &rs, &pl)) {
-            if (g->fault_query >= 0 && which[i] == g->fault_query) {
-                dst->fault = 1;
-                g->fault_query = -1;
-            }
-            nroot = rs;
-            job.packed.push_back(which[i]);
-            job.plans.push_back(pl);
+    });
+    for (int i = 0; i < count; ++i) {
+        if (cost[i] >= 0) {
+            order.push_back(i);
         } else {
             wide.push_back(which[i]);
             res[which[i]]->stats.fallback = 16;
         }
     }
-    const int np = (int)job.packed.size();
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    // descriptors in queue order, packed in parallel (a root's sweep row is
+    // assigned below; here an unpinned root only gets a non-negative slot)
+    const int no = (int)order.size();
+    std::vector<Plan> pls((size_t)no);
+    std::vector<char> packed_ok((size_t)no, 0);
+    parallel_for(no, 128, [&](int lo, int hi) {
+        for (int k = lo; k < hi; ++k) {
+            const int i = order[k];
+            int rs = 0;
+            packed_ok[k] = pack_query(g, qis[which[i]], plans[i], &nw.h_q[k], &rs, &pls[k]);
+        }
+    });
+    int np = 0;
+    for (int k = 0; k < no; ++k) {
+        const int i = order[k];
+        if (!packed_ok[k]) {
+            wide.push_back(which[i]);
+            res[which[i]]->stats.fallback = 16;
+            continue;
+        }
+        if (np != k) std::memcpy(&nw.h_q[np], &nw.h_q[k], sizeof(NQuery));
+        if (g->fault_query >= 0 && which[i] == g->fault_query) {
+            nw.h_q[np].fault = 1;
+            g->fault_query = -1;
+        }
+        job.packed.push_back(which[i]);
+        job.plans.push_back(pls[k]);
+        ++np;
+    }
+    int nroot = 0;
     if (np == 0) return false;
     // one sweep row per distinct root predicate (type, degree bounds), rows
     // in (type, bounds) order with the untyped (-1) ones first, as the
@@ -2175,12 +2273,15 @@ int run_queries(sgm_graph *g, const sgm_query *qs, const uint32_t *proj, int n, 
         g->trace.assign((size_t)n * SGM_TRACE_CAP, 0);
         g->trace_n.assign((size_t)n, 0);
     }
-    for (int i = 0; i < n; ++i) {
-        int rc = check_query(&qs[i], g->V, &qis[i]);
-        if (rc == SGM_OK && proj) rc = set_projection(&qis[i], proj[i]);
-        res[i]->status = rc;
-        if (rc == SGM_OK) valid.push_back(i);
-    }
+    parallel_for(n, 128, [&](int lo, int hi) {
+        for (int i = lo; i < hi; ++i) {
+            int rc = check_query(&qs[i], g->V, &qis[i]);
+            if (rc == SGM_OK && proj) rc = set_projection(&qis[i], proj[i]);
+            res[i]->status = rc;
+        }
+    });
+    for (int i = 0; i < n; ++i)
+        if (res[i]->status == SGM_OK) valid.push_back(i);
     if (g->opts.path == SGM_PATH_WIDE) {
         wide = valid;
     } else {
