@@ -21,6 +21,10 @@ same queries as one batch and served at 1,000 / 5,000 / 20,000 qps).
 ``--workload large-cyclic``: 50 cyclic unpinned 8-16-vertex queries on the
 large graph (intermediate tables up to ~1e8 rows, chunked joins), one at a
 time: exact counts for all, sorted tables to host below a row cap.
+
+``--workload sweep``: query-size and average-degree sweeps on 1M-vertex
+graphs and graph-size scaling (0.1M-16M vertices) with the graph in device
+memory and in host memory; a record per point, batched and one at a time.
 """
 import argparse
 import json
@@ -515,12 +519,80 @@ def bench_large_cyclic(args, P, kggen):
     }
 
 
+def _point(P, g, qs, batches=3):
+    """One sweep point: the queries as one batch (warm once, then the mean
+    of ``batches`` calls) and one at a time, on graph g."""
+    g.match_batch(qs)
+    t = time.perf_counter()
+    for _ in range(batches):
+        res = g.match_batch(qs)
+    el_b = (time.perf_counter() - t) / batches
+    rows = [len(r) for r in res]
+    for q in qs[:4]:
+        g.match_query(q)
+    lat = []
+    for q in qs:
+        a = time.perf_counter_ns()
+        g.match_query(q)
+        lat.append(time.perf_counter_ns() - a)
+    lat_ms = np.asarray(lat, np.float64) / 1e6
+    return {"queries": len(qs), "batched_qps": round(len(qs) / el_b, 1),
+            "single_qps": round(len(qs) / (lat_ms.sum() / 1e3), 1),
+            "single_p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+            "single_p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+            "rows_mean": round(float(np.mean(rows)), 1), "rows_max": int(max(rows))}
+
+
+def bench_sweep(args, P, kggen):
+    """Query-size and average-degree sweeps (thesis Ch. 3, Sec. "Comparison
+    with state-of-the-art CPU algorithms": 6..14 query vertices at degree 16,
+    degree 8..24 at 10 query vertices, 1M-vertex graphs) and graph-size
+    scaling with the graph in device memory and in pinned host memory (Sec.
+    "Scalability Test": 6-vertex queries). Stored queries, 64 per point."""
+    pts = kggen.load_sweep()
+    out = {"metric": "size / degree / graph-size sweeps", "unit": "queries/s",
+           "n_gpus": 1, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "power-law KGs (64 types, 32 Zipf relations, out-degree "
+                                  "<= V/32): 1M vertices at average degree 8-24; 0.1M-16M "
+                                  "vertices at degree 5; one pinned vertex per query, other "
+                                  "labels 'any' with p 0.5 (vertices) / 0.25 (edges), H <= 1e6 "
+                                  "(kggen/fixtures/sweep.json)"},
+           "degree": {}, "size": {}, "scale": {}}
+    graphs = {}
+    # grouped by graph so that each graph is drawn once
+    for key, kind, param, n in sorted(kggen.sweep_points(), key=lambda p: (p[1], p[2])):
+        t = time.time()
+        gk = (kind, param)
+        if gk not in graphs:
+            graphs.clear()
+            graphs[gk] = kggen.sweep_point_graph(kind, param)
+        kg = graphs[gk]
+        qs = pts[key]
+        grp, val = key.split("/")
+        if kind == "scale":
+            rec = {"vertices": kg.V, "edges": kg.E}
+            for hg in (0, 1):
+                g = P.Graph.from_kg(kg, host_graph=hg)
+                rec["host_memory" if hg else "device_memory"] = _point(P, g, qs)
+                g.close()
+            rec["host_over_device_batched"] = round(rec["host_memory"]["batched_qps"] /
+                                                    rec["device_memory"]["batched_qps"], 3)
+        else:
+            g = P.Graph.from_kg(kg)
+            rec = dict(_point(P, g, qs), vertices=kg.V, edges=kg.E, query_vertices=n)
+            g.close()
+        out[grp][val] = rec
+        log(f"{key}: {json.dumps(rec)} ({time.time() - t:.1f}s)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["medium", "large", "large-cyclic"], default="large")
+    ap.add_argument("--workload", choices=["medium", "large", "large-cyclic", "sweep"],
+                    default="large")
     ap.add_argument("--row-cap", type=int, default=250_000_000,
                     help="large-cyclic: row cap for materialized tables")
     ap.add_argument("--queries", type=int, default=100)
@@ -556,7 +628,8 @@ def main():
         sys.exit(2)
     import kggen
     import paper_1807_08804_amd as P
-    run = {"medium": bench_medium, "large": bench_large, "large-cyclic": bench_large_cyclic}
+    run = {"medium": bench_medium, "large": bench_large, "large-cyclic": bench_large_cyclic,
+           "sweep": bench_sweep}
     out = run[args.workload](args, P, kggen)
     print(json.dumps(out), flush=True)
 

@@ -79,7 +79,18 @@ typedef struct {
                                   incoming graph saves. Runs on SGM_PATH_WIDE only
                                   (AUTO means WIDE; NARROW, servers, autotuning
                                   and sgm_match_query_noalloc: SGM_EINVAL) */
-    int32_t reserved[4];
+    int32_t host_graph;        /* 1: keep the graph's adjacency arrays (every
+                                  O(edges) array) in pinned host memory, mapped
+                                  into the device's address space; kernels read
+                                  them in place over the host link, and only the
+                                  O(vertices) arrays (row offsets, types, degrees)
+                                  and the per-query buffers use device memory.
+                                  For graphs larger than device memory (thesis
+                                  Ch. 3, Sec. "Scalability Test": the data graph
+                                  kept in main memory). Results are unchanged;
+                                  0 (default): everything in device memory. Other
+                                  values: SGM_EINVAL */
+    int32_t reserved[3];
 } sgm_options;
 
 /* Execution paths. NARROW: one persistent kernel in which each workgroup

@@ -142,15 +142,17 @@ class Query:
 # data graphs
 # --------------------------------------------------------------------------
 
-def _powerlaw_outdegrees(rng, V: int, E: int, alpha: float = DEG_EXPONENT) -> np.ndarray:
+def _powerlaw_outdegrees(rng, V: int, E: int, alpha: float = DEG_EXPONENT,
+                         dmax: int = 0) -> np.ndarray:
     d = np.arange(1, V, dtype=np.float64)
     cdf = np.cumsum(d ** -alpha)
     cdf /= cdf[-1]
     deg = np.searchsorted(cdf, rng.random(V), side="right").astype(np.int64) + 1
-    np.minimum(deg, V - 1, out=deg)
+    dmax = V - 1 if dmax <= 0 else min(dmax, V - 1)
+    np.minimum(deg, dmax, out=deg)
     # proportional correction to exactly E, then largest remainder +-1
     scaled = deg * (E / float(deg.sum()))
-    base = np.clip(np.floor(scaled).astype(np.int64), 1, V - 1)
+    base = np.clip(np.floor(scaled).astype(np.int64), 1, dmax)
     frac = scaled - np.floor(scaled)
     tie = rng.random(V)
     for _ in range(64):
@@ -158,7 +160,7 @@ def _powerlaw_outdegrees(rng, V: int, E: int, alpha: float = DEG_EXPONENT) -> np
         if diff == 0:
             break
         if diff > 0:
-            elig = np.nonzero(base < V - 1)[0]
+            elig = np.nonzero(base < dmax)[0]
             order = elig[np.lexsort((tie[elig], -frac[elig]))]
             take = order[:diff]
             base[take] += 1
@@ -208,10 +210,11 @@ def _distinct_destinations(rng, V: int, deg: np.ndarray) -> np.ndarray:
 
 
 def make_graph(V: int, E: int, seed: int, n_types: int = N_TYPES, n_rels: int = N_RELS,
-               alpha: float = DEG_EXPONENT, zipf_s: float = ZIPF_S) -> KG:
-    """Draw a seeded power-law knowledge graph (recipe in the module doc)."""
+               alpha: float = DEG_EXPONENT, zipf_s: float = ZIPF_S, dmax: int = 0) -> KG:
+    """Draw a seeded power-law knowledge graph (recipe in the module doc);
+    dmax > 0 caps the out-degree (default V - 1)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    deg = _powerlaw_outdegrees(rng, V, E, alpha)
+    deg = _powerlaw_outdegrees(rng, V, E, alpha, dmax)
     dst = _distinct_destinations(rng, V, deg)
     k = np.arange(1, n_rels + 1, dtype=np.float64)
     zcdf = np.cumsum(k ** -zipf_s)
@@ -620,6 +623,94 @@ def serve_queries(g: KG, count: int, seed: int = BASE_SEED + 4 + 100, hmax: floa
         else:
             rejected += 1
     return out, rejected
+
+
+# Size / degree sweeps and graph-size scaling (thesis Ch. 3, Sec.
+# "Comparison with state-of-the-art CPU algorithms": query graphs of 6..14
+# vertices, and average degrees 8..24 at 10 query vertices; Sec. "Scalability
+# Test": data graphs of growing vertex count, 6-vertex queries, kept in device
+# or in host memory). Same generator as the named graphs; only V and E vary.
+SWEEP_V = 1_000_000
+SWEEP_DEGREES = (8, 12, 16, 20, 24)
+SWEEP_SIZES = (6, 8, 10, 12, 14)
+SWEEP_SIZE_DEGREE = 16
+SCALE_VERTICES = (100_000, 1_000_000, 4_000_000, 16_000_000)
+SCALE_DEGREE = 5
+
+
+SWEEP_DMAX_DIV = 32  # out-degree cap V / 32: keeps the densest sweep graphs simple to draw
+
+
+def sweep_graph(avg_degree: int, V: int = SWEEP_V) -> KG:
+    """Power-law graph of V vertices and avg_degree * V edges."""
+    return make_graph(V, avg_degree * V, BASE_SEED + 10 + avg_degree, dmax=V // SWEEP_DMAX_DIV)
+
+
+def scale_graph(V: int) -> KG:
+    """Power-law graph of V vertices and SCALE_DEGREE * V edges."""
+    return make_graph(V, SCALE_DEGREE * V, BASE_SEED + 40 + V % 997, dmax=V // SWEEP_DMAX_DIV)
+
+
+def sweep_queries(g: KG, n: int, count: int, seed: int, hmax: float = 1e6,
+                  p_any_vertex: float = 0.5, p_any_edge: float = 0.25):
+    """``count`` queries of exactly ``n`` vertices: trees and trees with one
+    extra data edge (a cycle) alternately, one pinned vertex (a concept
+    node); every other vertex label is dropped to "any" with probability
+    p_any_vertex and every edge label with probability p_any_edge, so that
+    candidate sets and intermediate tables grow with the degree; accepted
+    when H(q) <= hmax."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out, rejected = [], 0
+    while len(out) < count:
+        try:
+            if len(out) % 2:
+                q = draw_cyclic_dense(g, rng, n, 1, n_pins=1)
+            else:
+                q = draw_query(g, rng, n, "tree", 1)
+        except RuntimeError:
+            rejected += 1
+            continue
+        anyv = (rng.random(q.n) < p_any_vertex) & (q.vpin < 0)
+        q.vlabel = np.where(anyv, -1, q.vlabel).astype(np.int32)
+        q.elabel = np.where(rng.random(q.m) < p_any_edge, -1, q.elabel).astype(np.int32)
+        if tree_hom_bound(g, q) <= hmax:
+            out.append(q)
+        else:
+            rejected += 1
+    return out, rejected
+
+
+SWEEP_COUNT = 64  # queries per sweep point
+SWEEP_RECIPE = ("sweep_queries(g, n, 64, seed=BASE_SEED+600+k) per sweep_points() entry k; "
+                "p_any_vertex=0.5, p_any_edge=0.25, H <= 1e6")
+
+
+def sweep_points():
+    """The sweep workloads as (key, graph kind, graph parameter, query size):
+    average degree 8..24 at 10 query vertices and 6..14 query vertices at
+    degree 16 (each on a SWEEP_V-vertex graph), and 6-vertex queries on the
+    SCALE_VERTICES graphs."""
+    pts = [(f"degree/{d}", "sweep", d, 10) for d in SWEEP_DEGREES]
+    pts += [(f"size/{n}", "sweep", SWEEP_SIZE_DEGREE, n) for n in SWEEP_SIZES]
+    pts += [(f"scale/{v}", "scale", v, 6) for v in SCALE_VERTICES]
+    return pts
+
+
+def sweep_point_graph(kind: str, param: int) -> KG:
+    return sweep_graph(param) if kind == "sweep" else scale_graph(param)
+
+
+def load_sweep():
+    """The stored sweep workloads (written by kggen/make_fixtures.py from
+    ``sweep_points`` and ``sweep_queries``): key -> list of queries."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fixtures", "sweep.json")
+    with open(path) as f:
+        doc = json.load(f)
+    if doc["recipe"] != SWEEP_RECIPE:
+        raise RuntimeError("sweep.json was drawn from another recipe; rerun make_fixtures")
+    return {k: [Query.from_dict(d) for d in v] for k, v in doc["points"].items()}
 
 
 def poisson_arrivals(count: int, qps: float, seed: int = BASE_SEED + 4 + 200) -> np.ndarray:

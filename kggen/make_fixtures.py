@@ -9,9 +9,12 @@ recipe.
 * large_batch.json: the 1,024-query mixed batch (3-16 vertices; paths,
   stars, trees, cyclic; 0-50% pinned; H <= 10^6), ``batch_queries``;
 * large_serve.json: 512 served-stream queries (3-12 vertices, tree plus 0-1
-  extra edge, 0-2 pins, H <= 10^6), ``serve_queries``.
+  extra edge, 0-2 pins, H <= 10^6), ``serve_queries``;
+* sweep.json: 64 queries per query-size / degree / graph-size point
+  (``sweep_points``, ``sweep_queries``), each point drawn on its own graph
+  in a worker process.
 
-    python -m kggen.make_fixtures [cyclic] [batch] [serve]
+    python -m kggen.make_fixtures [cyclic] [batch] [serve] [sweep]
 """
 import json
 import os
@@ -31,8 +34,36 @@ def _write(name, recipe, qs, rejected):
         json.dump(doc, f, separators=(",", ":"))
 
 
+def _sweep_point(arg):
+    k, (key, kind, param, n) = arg
+    g = kggen.sweep_point_graph(kind, param)
+    qs, rej = kggen.sweep_queries(g, n, kggen.SWEEP_COUNT, seed=kggen.BASE_SEED + 600 + k)
+    return key, [q.as_dict() for q in qs], rej
+
+
+def write_sweep(workers=6):
+    import multiprocessing as mp
+    pts = list(enumerate(kggen.sweep_points()))
+    # the largest graphs first so that they overlap the rest
+    pts.sort(key=lambda kp: -(kp[1][2] if kp[1][1] == "scale" else kp[1][2] * kggen.SWEEP_V // 5))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        got = pool.map(_sweep_point, pts, chunksize=1)
+    order = [key for key, *_ in kggen.sweep_points()]
+    by = {key: (qs, rej) for key, qs, rej in got}
+    doc = {"recipe": kggen.SWEEP_RECIPE, "rejected": {k: by[k][1] for k in order},
+           "points": {k: by[k][0] for k in order}}
+    with open(os.path.join(HERE, "fixtures", "sweep.json"), "w") as f:
+        json.dump(doc, f, separators=(",", ":"))
+
+
 def main(which):
     t = time.time()
+    if "sweep" in which:
+        write_sweep()
+        print(f"sweep: {len(kggen.sweep_points())} points at {time.time() - t:.0f}s")
+        which = [w for w in which if w != "sweep"]
+        if not which:
+            return
     kg = kggen.named_graph("large")
     kg.ensure_in()
     if "cyclic" in which:
@@ -50,4 +81,4 @@ def main(which):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["cyclic", "batch", "serve"])
+    main(sys.argv[1:] or ["cyclic", "batch", "serve", "sweep"])

@@ -42,7 +42,7 @@ class sgm_options(ctypes.Structure):
                 ("result_cap_rows", ctypes.c_int64), ("join_budget_bytes", ctypes.c_int64),
                 ("profile", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("graphs", ctypes.c_int32), ("out_only", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("host_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class sgm_query(ctypes.Structure):

@@ -236,6 +236,9 @@ struct sgm_graph {
     int2 *d_out_adj = nullptr, *d_in_adj = nullptr;
     int2 *d_out_ta = nullptr, *d_out_tb = nullptr, *d_in_ta = nullptr, *d_in_tb = nullptr;
     int32_t *d_hub_of = nullptr, *d_hub_toff = nullptr;
+    // with options.host_graph: the adjacency arrays above live in pinned host
+    // memory; (host address, device address) of each such allocation
+    std::vector<std::pair<void *, void *>> host_graph_bufs;
     uint64_t *d_bits = nullptr;   // [SGM_MAX_QV + 1][nwords] (last: push scratch)
     int32_t *d_lists = nullptr;   // [SGM_MAX_QV][V]
     int32_t *d_prefix = nullptr;  // [SGM_MAX_QV][nwords + 1]
@@ -384,6 +387,27 @@ T *dev_upload(const std::vector<T> &h) {
     return p;
 }
 
+// An O(E) graph array in pinned host memory that kernels read in place over
+// the host link (thesis Ch. 3, Sec. "Scalability Test": a data graph too
+// large for the device stays in main memory). Mapped into the device's
+// address space and cacheable on the device: the arrays are read-only after
+// this copy, which completes before any kernel runs.
+template <class T>
+T *host_upload(const std::vector<T> &h, std::vector<std::pair<void *, void *>> &bufs) {
+    void *p = nullptr;
+    HIPX(hipHostMalloc(&p, sizeof(T) * std::max<size_t>(h.size(), 1),
+                       hipHostMallocMapped | hipHostMallocNonCoherent));
+    void *d = nullptr;
+    const hipError_t e = hipHostGetDevicePointer(&d, p, 0);
+    if (e != hipSuccess) {
+        (void)hipHostFree(p);
+        HIPX(e);
+    }
+    bufs.emplace_back(p, d);
+    if (!h.empty()) std::memcpy(p, h.data(), sizeof(T) * h.size());
+    return (T *)d;
+}
+
 void narrow_free(NarrowCtx &nw);
 
 void free_graph_mem(sgm_graph *g) {
@@ -399,8 +423,12 @@ void free_graph_mem(sgm_graph *g) {
     void *dp[] = {g->d_out_off, g->d_in_off, g->d_vinfo, g->d_out_adj, g->d_in_adj, g->d_bits,
                   g->d_lists,   g->d_prefix, g->d_big,   g->d_desc,    g->d_cnt,    g->d_slots,
                   g->d_out_ta,  g->d_out_tb, g->d_in_ta, g->d_in_tb,   g->d_hub_of, g->d_hub_toff};
-    for (void *p : dp)
-        if (p) (void)hipFree(p);
+    for (void *p : dp) {
+        bool host = false;
+        for (const auto &b : g->host_graph_bufs) host |= b.second == p;
+        if (p && !host) (void)hipFree(p);
+    }
+    for (const auto &b : g->host_graph_bufs) (void)hipHostFree(b.first);
     void *hp[] = {g->h_desc, g->h_cnt, g->h_slots, g->h_small, g->h_rows};
     for (void *p : hp)
         if (p) (void)hipHostFree(p);
@@ -2377,6 +2405,7 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
     }
     if (opts && opts->out_only && (opts->out_only != 1 || opts->path == SGM_PATH_NARROW))
         return SGM_EINVAL;
+    if (opts && opts->host_graph != 0 && opts->host_graph != 1) return SGM_EINVAL;
     sgm_graph *g = new (std::nothrow) sgm_graph();
     if (!g) return SGM_ENOMEM;
     if (opts) g->opts = *opts;
@@ -2419,10 +2448,15 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device) == hipSuccess &&
             khz > 0)
             g->ns_per_tick = 1e6 / khz;
+        // the O(E) arrays: in HBM, or with options.host_graph in host memory
+        const bool hg = g->opts.host_graph != 0;
+        auto edges_upload = [&](const std::vector<int2> &h) {
+            return hg ? host_upload(h, g->host_graph_bufs) : dev_upload(h);
+        };
         g->d_out_off = dev_upload(off);
         g->d_in_off = dev_upload(in_off);
-        g->d_out_adj = dev_upload(adj);
-        g->d_in_adj = dev_upload(in_adj);
+        g->d_out_adj = edges_upload(adj);
+        g->d_in_adj = edges_upload(in_adj);
         std::vector<int2> vi((size_t)n_vertices);
         for (int32_t v = 0; v < n_vertices; ++v)
             vi[v] = make_int2(type[v], std::min(off[v + 1] - off[v], 255) |
@@ -2431,10 +2465,10 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
         if (g->n_types <= kHubTypesMax) {
             HubIndex hx;
             build_hub_index(n_vertices, off, adj, in_off, in_adj, type, g->n_types, &hx);
-            g->d_out_ta = dev_upload(hx.out_ta);
-            g->d_out_tb = dev_upload(hx.out_tb);
-            g->d_in_ta = dev_upload(hx.in_ta);
-            g->d_in_tb = dev_upload(hx.in_tb);
+            g->d_out_ta = edges_upload(hx.out_ta);
+            g->d_out_tb = edges_upload(hx.out_tb);
+            g->d_in_ta = edges_upload(hx.in_ta);
+            g->d_in_tb = edges_upload(hx.in_tb);
             g->d_hub_of = dev_upload(hx.hub_of);
             g->d_hub_toff = dev_upload(hx.toff);
             g->dg.hub_types = hx.types;

@@ -150,6 +150,18 @@ def test_out_only_graph_options_checked_before_touching_device():
         assert e.value.code == P.SGM_EINVAL
 
 
+def test_host_graph_option_checked_before_touching_device():
+    """The host-memory graph option takes 0 or 1; other values are refused
+    before any device call."""
+    for hg in (2, -1):
+        o = P.sgm_options()
+        P.lib().sgm_default_options(ctypes.byref(o))
+        o.host_graph = hg
+        with pytest.raises(P.SGMError) as e:
+            P.sgm_load_graph(2, 2, [0, 1, 2], [1, 0], [0, 0], [0, 0], o)
+        assert e.value.code == P.SGM_EINVAL
+
+
 def test_batch_packing_points_at_each_querys_arrays():
     """_pack_queries (one int32 block and one array of C query structs for a
     whole batch) gives every struct the counts and the five arrays of its
