@@ -116,13 +116,30 @@ struct JLevel {
     JChk chk[SGM_MAX_QE];
 };
 
+// One edge-candidate table build shared with helpers: the key vertex's
+// sorted candidates, the table's per-key space (degoff), counts and values,
+// the list of keys whose rows go to a later tier (ovl), the other
+// endpoint's candidate bitmap and sorted list, the edge's relation and the
+// direction of the rows scanned (0: out-rows of sources). tier 0: chunks of
+// key positions, G lanes per key; tier 1: chunks of items (positions of
+// long keys), one wave per key; tier 2: one item per chunk, the whole
+// workgroup per key.
+struct EcJob {
+    const int32_t *keys, *degoff;
+    int32_t *num, *vals, *ovl;
+    const uint64_t *ob;
+    const int32_t *ol, *items;
+    int32_t nk, rel, dir, no, tier, pad;
+};
+
 struct HelpJob {
     unsigned long long claim;
     unsigned long long bytes;  // algorithmic bytes of the helpers' chunks
     const int4 *seg;           // kind 1: the row segments, one per chunk
     const int32_t *ul;         // kind 0: the items (a candidate list, or long rows)
     int32_t chunk, done, q, kind;  // kind 0: chunks of the candidate list; 1: row segments;
-                                   // 2: parent rows of a join level
+                                   // 2: parent rows of a join level; 3: keys of an
+                                   // edge-candidate table
     int32_t n_items, G, ncount, revd;
     NStep st;
     int32_t nbig, removed, nmarks, abort_;
@@ -131,12 +148,16 @@ struct HelpJob {
     // workgroup takes no more queries in that launch and the next launch
     // clears the whole slot before using it
     int32_t dirty;
+    // kind 0: 1 when the chunks' items are long rows, which one wave takes
+    // up to wg_rows entries (longer ones go on to the workgroup tier)
+    int32_t nodefer;
     int32_t cnt[SGM_MAX_QV];
     NNbr nbl[SGM_MAX_QE];
     // kind 2: chunks of a join level's parent rows; jrows counts the output
-    // rows placed so far
+    // rows placed so far (kind 3: the table entries written so far)
     unsigned long long jrows;
     JLevel jl;
+    EcJob ecj;  // kind 3
 };
 
 struct NArgs {

@@ -756,12 +756,16 @@ template <class K>
 __device__ __forceinline__ void filter_items(Ctx &c, const K &k, bool push, const NNbr *nb,
                                              int ncount, const int32_t *ul, uint64_t *ub,
                                              bool revd, int G, int32_t it0, int32_t it1,
-                                             uint64_t &fb) {
+                                             uint64_t &fb, bool nodefer = false) {
     const DevGraph &g = c.g;
     const int NGr = NT / G;
     const int lane = threadIdx.x & 63, gl = lane & (G - 1), gb = lane & ~(G - 1);
     const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << gb;
-    const int32_t bigdeg = 64 * G;  // more than 64 strides: a wider tier
+    // more than 64 strides: a wider tier (a shared pass over long rows
+    // keeps the rows up to wg_rows, which the whole workgroup would take
+    // next; longer ones stay with the owner, whose pushes become shared
+    // row segments)
+    const int32_t bigdeg = nodefer ? max(64 * G, c.wg_rows) : 64 * G;
     // The overflow list sits at the start of the slot's slab, which no phase
     // uses while filtering (at most lcap entries, far below its size).
     int32_t *ov = (int32_t *)c.slab;
@@ -960,6 +964,9 @@ __device__ __forceinline__ int32_t build_segments(Ctx &c, const NNbr *nb, int nc
     return carry <= cap ? (int32_t)carry : -1;
 }
 
+__device__ __forceinline__ void ec_chunk(Ctx &c, const EcJob &E, HelpJob *j, int32_t i0, int32_t i1,
+                                         int G, uint64_t &fb);
+
 // A filter step shared with the launch's idle workgroups through this
 // slot's board entry: the counters move to the entry, the work is cut into
 // nch chunks that the owner and its helpers claim (kind 0: K candidates of
@@ -968,7 +975,8 @@ __device__ __forceinline__ int32_t build_segments(Ctx &c, const NNbr *nb, int nc
 __device__ __forceinline__ void shared_job(Ctx &c, int kind, const NStep &st, const NNbr *nb,
                                            int ncount, const int32_t *ul, uint64_t *ub, bool revd,
                                            int32_t n_items, int32_t K, int G, int32_t nch,
-                                           const int4 *seg, uint64_t &fb) {
+                                           const int4 *seg, uint64_t &fb,
+                                           const EcJob *ecj = nullptr, bool nodefer = false) {
     HelpJob *j = c.job;
     if (threadIdx.x == 0) {
         for (int v = 0; v < SGM_MAX_QV; ++v) j->cnt[v] = c.s->cnt[v];
@@ -979,6 +987,7 @@ __device__ __forceinline__ void shared_job(Ctx &c, int kind, const NStep &st, co
         j->bytes = 0ull;
         j->done = 0;
         j->kind = kind;
+        j->nodefer = nodefer;
         j->seg = seg;
         j->ul = ul;
         j->chunk = K;
@@ -993,6 +1002,10 @@ __device__ __forceinline__ void shared_job(Ctx &c, int kind, const NStep &st, co
             j->nbl[i].dir = nb[i].dir;
             j->nbl[i].mode = nb[i].mode;
             j->nbl[i].rel = nb[i].rel;
+        }
+        if (ecj) {
+            j->ecj = *ecj;
+            j->jrows = 0ull;
         }
         const uint32_t seq =
             claim_seq(__hip_atomic_load(&j->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) + 1u;
@@ -1014,7 +1027,9 @@ __device__ __forceinline__ void shared_job(Ctx &c, int kind, const NStep &st, co
         if (ch < 0) break;
         if (kind == 0)
             filter_items(c, BoardCtr{j}, st.push != 0, nb, ncount, ul, ub, revd, G, ch * K,
-                         min(n_items, ch * K + K), fb);
+                         min(n_items, ch * K + K), fb, nodefer);
+        else if (kind == 3)
+            ec_chunk(c, *ecj, j, ch * K, min(n_items, ch * K + K), G, fb);
         else
             push_segment(c, BoardCtr{j}, nb, seg[ch], fb);
         ++own;
@@ -1210,10 +1225,11 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
         const int lane = threadIdx.x & 63;
         int32_t *ov = (int32_t *)c.slab;
         __syncthreads();
-        if (share && c.s->nbig >= kLongShare && c.slab_bytes >= 16 * (int64_t)c.lcap) {
-            // many long rows: one wave per row, shared like the step itself
-            // (the rows move to a list of their own, since rows longer still
-            // come back to the overflow list)
+        if (c.help_items > 0 && c.job && c.s->nbig >= kLongShare &&
+            c.slab_bytes >= 16 * (int64_t)c.lcap) {
+            // many long rows: one wave per row up to wg_rows entries,
+            // shared like a step of many candidates (the rows move to a
+            // list of their own; longer ones come back to the overflow list)
             ev(c, SGM_EV_LONGROWS);
             const int32_t nl = c.s->nbig;
             int32_t *rows = (int32_t *)(c.slab + 12 * (int64_t)c.lcap);
@@ -1222,7 +1238,7 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
             if (threadIdx.x == 0) c.s->nbig = 0;
             const int32_t nch = (nl + kLongChunk - 1) / kLongChunk;
             shared_job(c, 0, st, nb, ncount, rows, ub, revd, nl, kLongChunk, 64, nch, nullptr,
-                       fb);
+                       fb, nullptr, true);
             __syncthreads();
         }
         // one wave per long row; rows above wg_rows get the whole workgroup
@@ -1418,8 +1434,141 @@ __device__ __forceinline__ int64_t ec_key_wave(int32_t rel, const uint64_t *ob, 
     return n;
 }
 
+// Keys [i0, i1) of a table build, G lanes per key; keys whose rows are
+// longer than 64 * G entries go to E.ovl (counted by *nbig) for the wave
+// tier. Returns the entries this thread's groups wrote (on their first lane).
+__device__ __forceinline__ int64_t ec_keys(const Ctx &c, const EcJob &Ej, int32_t i0, int32_t i1,
+                                           int G, int32_t *nbig, uint64_t &fb) {
+    const EcJob E = Ej;  // once, before the stores below
+    const int32_t *off = E.dir ? c.g.in_off : c.g.out_off;
+    const int2 *adj = E.dir ? c.g.in_adj : c.g.out_adj;
+    const int NGr = NT / G;
+    const int lane = threadIdx.x & 63, gl = lane & (G - 1), gb = lane & ~(G - 1);
+    const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << gb;
+    const int32_t bigdeg = 64 * G;
+    int64_t mytot = 0;
+    for (int32_t it = i0 + (int32_t)threadIdx.x / G; it < i1; it += NGr) {
+        const int32_t k = E.keys[it];
+        const int32_t beg = off[k], end = off[k + 1];
+        if (end - beg > bigdeg) {
+            if (gl == 0) E.ovl[atomicAdd(nbig, 1)] = it;
+            continue;
+        }
+        int32_t *dst = E.vals + E.degoff[it];
+        int32_t n = 0;
+        for (int32_t base = beg; base < end; base += G) {
+            const int32_t i = base + gl;
+            const bool hit = i < end && ec_hit(E.rel, E.ob, adj, beg, i, k);
+            const uint64_t bm = __ballot(hit) & gmask;
+            if (hit) dst[n + __popcll(bm & lanemask_lt(lane))] = adj[i].x;
+            n += __popcll(bm);
+        }
+        if (gl == 0) {
+            E.num[it] = n;
+            mytot += n;
+            fb += 16ull + 12ull * (end - beg) + 4ull * n;
+        }
+    }
+    return mytot;
+}
+
+// Long keys E.items[i0, i1), one wave each (scan or lookup, whichever
+// reads less); keys with rows above wg_rows go to E.ovl for the owner's
+// workgroup tier. Returns the entries written (on lane 0 of each wave).
+__device__ __forceinline__ int64_t ec_long_keys(const Ctx &c, const EcJob &Ej, int32_t i0,
+                                                int32_t i1, int32_t *ngiant, uint64_t &fb) {
+    const EcJob E = Ej;
+    const int32_t *off = E.dir ? c.g.in_off : c.g.out_off;
+    const int2 *adj = E.dir ? c.g.in_adj : c.g.out_adj;
+    const int lane = threadIdx.x & 63;
+    int64_t mytot = 0;
+    for (int32_t b = i0 + (int32_t)(threadIdx.x >> 6); b < i1; b += NW) {
+        const int32_t it = E.items[b];
+        const int32_t k = E.keys[it];
+        const int32_t beg = off[k], end = off[k + 1];
+        if (end - beg > c.wg_rows) {
+            if (lane == 0) E.ovl[atomicAdd(ngiant, 1)] = it;
+            continue;
+        }
+        const bool probe = probe_cheaper(E.no, end - beg);
+        int32_t *dst = E.vals + E.degoff[it];
+        const int64_t n = probe ? ec_probe_wave(E.rel, E.ol, E.no, adj, beg, end, k, dst)
+                                : ec_key_wave(E.rel, E.ob, adj, beg, end, k, dst);
+        if (lane == 0) {
+            E.num[it] = (int32_t)n;
+            mytot += n;
+            fb += 16ull + 4ull * n + (probe ? probe_bytes(E.no, end - beg) : 12ull * (end - beg));
+        }
+    }
+    return mytot;
+}
+
+// Keys with rows above wg_rows, E.items[i0, i1), the whole workgroup each.
+// Returns the entries written (on thread 0).
+__device__ __forceinline__ int64_t ec_giant_keys(Ctx &c, const EcJob &Ej, int32_t i0, int32_t i1,
+                                                 uint64_t &fb) {
+    const EcJob E = Ej;
+    const int32_t *off = E.dir ? c.g.in_off : c.g.out_off;
+    const int2 *adj = E.dir ? c.g.in_adj : c.g.out_adj;
+    int64_t mytot = 0;
+    for (int32_t b = i0; b < i1; ++b) {
+        const int32_t it = E.items[b];
+        const int32_t k = E.keys[it];
+        const int32_t beg = off[k], end = off[k + 1];
+        const bool probe = probe_cheaper(E.no, end - beg);
+        int32_t *dst = E.vals + E.degoff[it];
+        const int64_t n = probe ? ec_probe_wg(c, E.rel, E.ol, E.no, adj, beg, end, k, dst)
+                                : ec_key_wg(c, E.rel, E.ob, adj, beg, end, k, dst);
+        if (threadIdx.x == 0) {
+            E.num[it] = (int32_t)n;
+            mytot += n;
+            fb += 16ull + 4ull * n + (probe ? probe_bytes(E.no, end - beg) : 12ull * (end - beg));
+        }
+    }
+    return mytot;
+}
+
+// One chunk of a shared table build (owner or helper): the keys, and the
+// chunk's entry count added to the board.
+__device__ __forceinline__ void ec_chunk(Ctx &c, const EcJob &E, HelpJob *j, int32_t i0, int32_t i1,
+                                         int G, uint64_t &fb) {
+    int64_t t = E.tier == 2   ? ec_giant_keys(c, E, i0, i1, fb)
+                : E.tier == 1 ? ec_long_keys(c, E, i0, i1, &j->nbig, fb)
+                              : ec_keys(c, E, i0, i1, G, &j->nbig, fb);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((threadIdx.x & 63) == 0 && t) atomicAdd(&j->jrows, (unsigned long long)t);
+}
+
+// One shared pass of a table build (nch chunks of K items); adds the
+// entries written to mytot (thread 0). False when the owner gave up on its
+// helpers: the query is aborted (and rerun) and the build stops, since key
+// lists of unreported chunks may be incomplete.
+__device__ __forceinline__ bool ec_shared(Ctx &c, int e, const EcJob &E, int32_t n_items,
+                                          int32_t K, int G, const int32_t *ovl, uint64_t &fb,
+                                          int64_t &mytot) {
+    shared_job(c, 3, NStep{}, nullptr, 0, nullptr, nullptr, false, n_items, K, G,
+               (n_items + K - 1) / K, nullptr, fb, &E);
+    if (aborted(c)) {
+        if (threadIdx.x == 0) {
+            c.s->ectot[e] = 0;
+            c.s->slab_used = (int64_t)((const char *)ovl - c.slab);
+        }
+        __syncthreads();
+        return false;
+    }
+    if (threadIdx.x == 0)
+        mytot += (int64_t)__hip_atomic_load(&c.job->jrows, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    return true;
+}
+
 // Build the table of query edge e keyed by `key` (dir 0: keys are sources).
-// Sets s.ec_offs/ec_cnt/ec_vals[e], s.eckey[e] and s.ectot[e].
+// Sets s.ec_offs/ec_cnt/ec_vals[e], s.eckey[e] and s.ectot[e]. Tiers: G
+// lanes per key; one wave per key for rows above 64 G entries; the whole
+// workgroup per key above wg_rows. With a helper board, each tier with
+// enough keys is shared like a filter step (its chunks write disjoint keys
+// of the one-pass layout).
 __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int dir) {
     const DevGraph &g = c.g;
     const int32_t *keys = c.L(key);
@@ -1461,6 +1610,8 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
     __syncthreads();
     int64_t mytot = 0;
     uint64_t fb = 0;
+    const bool can_share = c.help_items > 0 && c.job;
+    const EcJob E{keys, degoff, num, vals, ovl, ob, ol, nullptr, nk, rel, dir, no, 0, 0};
     if (nk <= NW) {
         // a handful of keys: one wave each, rows above wg_rows get the
         // whole workgroup
@@ -1481,48 +1632,31 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
                 }
             }
         }
-        __syncthreads();
-        const int32_t ngiant = c.s->ngiant;
-        for (int32_t b = 0; b < ngiant; ++b) {
-            const int32_t it = c.s->big[b];
-            const int32_t k = keys[it];
-            const int32_t beg = off[k], end = off[k + 1];
-            const bool probe = probe_cheaper(no, end - beg);
-            const int64_t n = probe ? ec_probe_wg(c, rel, ol, no, adj, beg, end, k, vals + degoff[it])
-                                    : ec_key_wg(c, rel, ob, adj, beg, end, k, vals + degoff[it]);
-            if (threadIdx.x == 0) {
-                num[it] = (int32_t)n;
-                mytot += n;
-                fb += 16ull + 4ull * n + (probe ? probe_bytes(no, end - beg) : 12ull * (end - beg));
-            }
-        }
     } else {
-        const int G = lanes_for(nk, c.gmax);
-        const int NGr = NT / G;
-        const int lane = threadIdx.x & 63, gl = lane & (G - 1), gb = lane & ~(G - 1);
-        const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << gb;
-        const int32_t bigdeg = 64 * G;
-        for (int32_t it = threadIdx.x / G; it < nk; it += NGr) {
-            const int32_t k = keys[it];
-            const int32_t beg = off[k], end = off[k + 1];
-            if (end - beg > bigdeg) {
-                if (gl == 0) ovl[atomicAdd(&c.s->nbig, 1)] = it;
-                continue;
-            }
-            int32_t *dst = vals + degoff[it];
-            int32_t n = 0;
-            for (int32_t base = beg; base < end; base += G) {
-                const int32_t i = base + gl;
-                const bool hit = i < end && ec_hit(rel, ob, adj, beg, i, k);
-                const uint64_t bm = __ballot(hit) & gmask;
-                if (hit) dst[n + __popcll(bm & lanemask_lt(lane))] = adj[i].x;
-                n += __popcll(bm);
-            }
-            if (gl == 0) {
-                num[it] = n;
-                mytot += n;
-                fb += 16ull + 12ull * (end - beg) + 4ull * n;
-            }
+        const int lane = threadIdx.x & 63;
+        if (can_share && nk >= c.help_items) {
+            const int32_t helpers = helpers_now(c);
+            const int32_t K = min(512, max(64, max((nk + helpers) / (helpers + 1),
+                                                   (nk + kMaxChunks - 1) / kMaxChunks)));
+            if (!ec_shared(c, e, E, nk, K, lanes_for(K, c.gmax), ovl, fb, mytot)) return;
+        } else {
+            mytot += ec_keys(c, E, 0, nk, lanes_for(nk, c.gmax), &c.s->nbig, fb);
+        }
+        __syncthreads();
+        const int32_t nl = c.s->nbig;
+        if (can_share && nl >= kLongShare) {
+            // many long keys: one wave per key, shared the same way (the
+            // keys move to a list of their own; rows longer than wg_rows
+            // come back to ovl)
+            int32_t *items = (int32_t *)slab_alloc(c, 4ll * nl + 4);
+            if (!items) return;
+            for (int32_t i = threadIdx.x; i < nl; i += NT) items[i] = ovl[i];
+            __syncthreads();
+            if (threadIdx.x == 0) c.s->nbig = 0;
+            EcJob E1 = E;
+            E1.items = items;
+            E1.tier = 1;
+            if (!ec_shared(c, e, E1, nl, kLongChunk, 64, ovl, fb, mytot)) return;
         }
         __syncthreads();
         const int32_t nbig = c.s->nbig;
@@ -1548,21 +1682,24 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
                 fb += 16ull + 4ull * n + (probe ? probe_bytes(no, end - beg) : 12ull * (end - beg));
             }
         }
+    }
+    __syncthreads();
+    // keys with rows above wg_rows: one workgroup each, shared when several
+    const int32_t ngiant = min(c.s->ngiant, kBigCap);
+    if (can_share && ngiant >= 2) {
+        int32_t *items = (int32_t *)slab_alloc(c, 4ll * ngiant + 4);
+        if (!items) return;
+        for (int32_t i = threadIdx.x; i < ngiant; i += NT) items[i] = c.s->big[i];
         __syncthreads();
-        const int32_t ngiant = min(c.s->ngiant, kBigCap);
-        for (int32_t b = 0; b < ngiant; ++b) {
-            const int32_t it = c.s->big[b];
-            const int32_t k = keys[it];
-            const int32_t beg = off[k], end = off[k + 1];
-            const bool probe = probe_cheaper(no, end - beg);
-            const int64_t n = probe ? ec_probe_wg(c, rel, ol, no, adj, beg, end, k, vals + degoff[it])
-                                    : ec_key_wg(c, rel, ob, adj, beg, end, k, vals + degoff[it]);
-            if (threadIdx.x == 0) {
-                num[it] = (int32_t)n;
-                mytot += n;
-                fb += 16ull + 4ull * n + (probe ? probe_bytes(no, end - beg) : 12ull * (end - beg));
-            }
-        }
+        EcJob E2 = E;
+        E2.items = items;
+        E2.tier = 2;
+        if (!ec_shared(c, e, E2, ngiant, 1, NT, ovl, fb, mytot)) return;
+    } else if (ngiant > 0) {
+        int32_t *items = c.s->big;
+        EcJob E2 = E;
+        E2.items = items;
+        mytot += ec_giant_keys(c, E2, 0, ngiant, fb);
     }
     add_bytes_wave(c, fb);
     int64_t tot;
@@ -2776,6 +2913,7 @@ __device__ __forceinline__ void help_step(const NArgs &a, Smem &s, unsigned char
     const int kind = j->kind;
     const int4 *seg = j->seg;
     const int32_t *hul = j->ul;
+    const bool nodefer = j->nodefer != 0;
     if ((int)threadIdx.x < ncount) {
         s.nbl[threadIdx.x].v = j->nbl[threadIdx.x].v;
         s.nbl[threadIdx.x].dir = j->nbl[threadIdx.x].dir;
@@ -2795,9 +2933,11 @@ __device__ __forceinline__ void help_step(const NArgs &a, Smem &s, unsigned char
     while (ch >= 0) {
         if (kind == 0) {
             filter_items(c, BoardCtr{j}, st.push != 0, s.nbl, ncount, hul, c.B(st.u), revd, G,
-                         ch * K, min(n_items, ch * K + K), fb);
+                         ch * K, min(n_items, ch * K + K), fb, nodefer);
         } else if (kind == 1) {
             push_segment(c, BoardCtr{j}, s.nbl, seg[ch], fb);
+        } else if (kind == 3) {
+            ec_chunk(c, j->ecj, j, ch * K, min(n_items, ch * K + K), G, fb);
         } else {
             join_chunk(c, s.jl, ch, &j->jrows, &j->abort_, fb);
         }
