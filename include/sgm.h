@@ -517,6 +517,85 @@ void sgm_server_destroy(sgm_server *s);
 int sgm_serve_replay(sgm_server *s, const sgm_query *qs, const int64_t *arrival_ns, int32_t n,
                      uint32_t flags, int64_t *latency_ns, sgm_result **out);
 
+/* ---- Multi-level graph compression (thesis Ch. 3, Sec. "Multi-level Graph
+ * Compression", Def. 3.4-3.5, Thm. 3.1-3.2; Sec. "GpSense Framework") ----
+ *
+ * For graphs beyond device memory the thesis compresses the graph offline
+ * into a smaller weighted graph G_w whose vertices stand for groups of
+ * similar original vertices (mapping lists M(x)), matches queries on G_w
+ * and expands each weighted match through the mapping lists into the
+ * original graph's matches. */
+typedef struct {
+    int32_t max_levels;   /* levels of merging, 0..8 (default 3) */
+    float delta[8];       /* similarity threshold of each level, in (0, 1]:
+                             two vertices of one type merge when common
+                             edges make up at least this share of either's
+                             entries (default 0.8, then 0.7) */
+    double target_ratio;  /* > 0: stop once (|V_i| + |E_i|) / (|V| + |E|)
+                             is at most this (default 0: every level) */
+    int32_t max_partners; /* partners looked at per shared entry (default 64) */
+    int32_t reserved[3];
+} sgm_compress_options;
+
+/* A compressed graph (library-owned, host memory; sgm_free_compressed). */
+typedef struct {
+    int32_t n_vertices;       /* |V_w| */
+    int32_t n_original;       /* |V| of the input */
+    int64_t n_edges;          /* entries of the out-CSR below */
+    int32_t levels;           /* levels applied */
+    int32_t *row_ptr;         /* [n_vertices + 1] out-CSR of G_w */
+    int32_t *col, *rel;       /* [n_edges], rows ascending by (neighbour, relation);
+                                 an edge inside one group is a self-loop */
+    int32_t *weight;          /* [n_edges] w(x -> y, rel): at most this many
+                                 rel-edges from any vertex of M(x) into M(y) */
+    int32_t *type;            /* [n_vertices] the type of every member */
+    int32_t *out_bound;       /* [n_vertices] sum of x's out-entry weights:
+                                 bounds the out-degree of every member (Def. 3.5) */
+    int32_t *in_bound;        /* [n_vertices] the same for in-degrees */
+    int32_t *map_off;         /* [n_vertices + 1] mapping lists M(x) ... */
+    int32_t *map_ids;         /* [n_original] ... as ascending original ids */
+    int32_t *hyper_of;        /* [n_original] the weighted vertex of each vertex */
+    int64_t level_size[9];    /* |V_i| + |E_i| after level i (0: the input,
+                                 repeated triples removed) */
+} sgm_compressed;
+
+void sgm_default_compress_options(sgm_compress_options *o);
+
+/* Compress a graph given as sgm_load_graph takes it (host arrays, not
+ * kept). SGM_EINVAL for malformed input or options, SGM_ENOMEM. Host-only:
+ * no device is touched. */
+int sgm_compress(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr, const int32_t *col,
+                 const int32_t *rel, const int32_t *type, const sgm_compress_options *opts,
+                 sgm_compressed **out);
+void sgm_free_compressed(sgm_compressed *c);
+
+/* Make G_w resident for matching (like sgm_load_graph on c's CSR). A
+ * vertex's degree bounds are c's out/in bounds (Def. 3.5: a weighted vertex
+ * is a candidate when the query vertex's degree is at most its weight), and
+ * matches are homomorphisms: several query vertices may take one weighted
+ * vertex, and a query edge may take a self-loop, since the original match
+ * may use several members of one group. Runs on SGM_PATH_WIDE (NARROW,
+ * servers, autotuning and sgm_match_query_noalloc: SGM_EINVAL). c is not
+ * kept. */
+int sgm_load_compressed(const sgm_compressed *c, const sgm_options *opts, sgm_graph **out);
+
+/* Give the original graph g (resident, possibly with options.host_graph)
+ * the mapping lists of c, in device memory, for sgm_match_compressed.
+ * Replaces an earlier mapping. SGM_EINVAL when c was not made from a graph
+ * of g's vertex count. */
+int sgm_attach_mapping(sgm_graph *g, const sgm_compressed *c);
+
+/* Every match of q in the original graph g through the compressed graph gw
+ * (GpSense, Sec. "GpSense Framework"): q's pinned vertices take their
+ * weighted vertices, q is matched on gw, and each weighted match is
+ * expanded on the device: every choice of members of its groups that is
+ * injective, keeps the pins and holds every query edge in g is a match
+ * (Thm. 3.2: no match of g is lost). The result is that of
+ * sgm_match_query(g, q, flags): unique rows in ascending order. g needs
+ * sgm_attach_mapping of the compression gw was loaded from. */
+int sgm_match_compressed(sgm_graph *g, sgm_graph *gw, const sgm_query *q, uint32_t flags,
+                         sgm_result **out);
+
 #ifdef __cplusplus
 }
 #endif

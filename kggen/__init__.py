@@ -680,6 +680,50 @@ def sweep_queries(g: KG, n: int, count: int, seed: int, hmax: float = 1e6,
     return out, rejected
 
 
+# Graphs with similar vertices, for multi-level compression (thesis Ch. 3,
+# Sec. "Multi-level Graph Compression": a commonsense knowledge graph has
+# many concepts that share the same neighbours). Each round gives every
+# vertex, with probability p_twin, a twin of its type that keeps each of its
+# out-edges and each of its in-edges with probability p_keep; twins of twins
+# come from later rounds.
+def twin_graph(V: int, E: int, seed: int, rounds: int = 2, p_twin: float = 0.5,
+               p_keep: float = 0.9) -> KG:
+    base = make_graph(V, E, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    src = np.repeat(np.arange(base.V, dtype=np.int64), np.diff(base.row_ptr))
+    dst = base.col.astype(np.int64)
+    rel = base.rel.astype(np.int64)
+    vtype = base.vtype.astype(np.int32)
+    n = base.V
+    for _ in range(rounds):
+        tw = np.nonzero(rng.random(n) < p_twin)[0]
+        new_id = np.full(n, -1, np.int64)
+        new_id[tw] = n + np.arange(len(tw))
+        # out-edges of the twinned vertices, then their in-edges
+        mo = (new_id[src] >= 0) & (rng.random(len(src)) < p_keep)
+        mi = (new_id[dst] >= 0) & (rng.random(len(src)) < p_keep)
+        src, dst, rel = (np.concatenate((src, new_id[src[mo]], src[mi])),
+                         np.concatenate((dst, dst[mo], new_id[dst[mi]])),
+                         np.concatenate((rel, rel[mo], rel[mi])))
+        vtype = np.concatenate((vtype, vtype[tw]))
+        n += len(tw)
+    order = np.lexsort((rel, dst, src))
+    src, dst, rel = src[order], dst[order], rel[order]
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(src, minlength=n), out=row_ptr[1:])
+    return KG(V=n, E=len(dst), row_ptr=row_ptr.astype(np.int32), col=dst.astype(np.int32),
+              rel=rel.astype(np.int32), vtype=vtype)
+
+
+TWIN_GRAPHS = {"twin-small": (20_000, 80_000, 60), "twin-medium": (300_000, 1_600_000, 61),
+               "twin-large": (2_000_000, 10_000_000, 62)}
+
+
+def twin_named(name: str) -> KG:
+    V, E, off = TWIN_GRAPHS[name]
+    return twin_graph(V, E, BASE_SEED + off)
+
+
 SWEEP_COUNT = 64  # queries per sweep point
 SWEEP_RECIPE = ("sweep_queries(g, n, 64, seed=BASE_SEED+600+k) per sweep_points() entry k; "
                 "p_any_vertex=0.5, p_any_edge=0.25, H <= 1e6")

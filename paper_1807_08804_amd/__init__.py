@@ -94,6 +94,22 @@ TUNING_FIELDS = ("slots", "group_lanes", "wg_rows", "join_policy", "help_items",
                  "help_wait")
 
 
+class sgm_compress_options(ctypes.Structure):
+    _fields_ = [("max_levels", ctypes.c_int32), ("delta", ctypes.c_float * 8),
+                ("target_ratio", ctypes.c_double), ("max_partners", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+class sgm_compressed(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int32), ("n_original", ctypes.c_int32),
+                ("n_edges", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("rel", ctypes.c_void_p),
+                ("weight", ctypes.c_void_p), ("type", ctypes.c_void_p),
+                ("out_bound", ctypes.c_void_p), ("in_bound", ctypes.c_void_p),
+                ("map_off", ctypes.c_void_p), ("map_ids", ctypes.c_void_p),
+                ("hyper_of", ctypes.c_void_p), ("level_size", ctypes.c_int64 * 9)]
+
+
 class sgm_kstat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("bytes_total", ctypes.c_double)]
@@ -152,6 +168,18 @@ EXPORTS = {
     "sgm_serve_replay": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_query), _i64p,
                                         ctypes.c_int32, ctypes.c_uint32, _i64p,
                                         ctypes.POINTER(ctypes.POINTER(sgm_result))]),
+    "sgm_default_compress_options": (None, [ctypes.POINTER(sgm_compress_options)]),
+    "sgm_compress": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p,
+                                    ctypes.POINTER(sgm_compress_options),
+                                    ctypes.POINTER(ctypes.POINTER(sgm_compressed))]),
+    "sgm_free_compressed": (None, [ctypes.POINTER(sgm_compressed)]),
+    "sgm_load_compressed": (ctypes.c_int, [ctypes.POINTER(sgm_compressed),
+                                           ctypes.POINTER(sgm_options),
+                                           ctypes.POINTER(ctypes.c_void_p)]),
+    "sgm_attach_mapping": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sgm_compressed)]),
+    "sgm_match_compressed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(sgm_query), ctypes.c_uint32,
+                                            ctypes.POINTER(ctypes.POINTER(sgm_result))]),
 }
 
 _lib = None
@@ -628,6 +656,132 @@ class Graph:
 
     def reset_kernel_stats(self):
         lib().sgm_reset_kernel_stats(self._h)
+
+
+class Compressed:
+    """A multi-level compression of a graph (sgm_compress; thesis Ch. 3, Sec.
+    "Multi-level Graph Compression"): the weighted graph G_w and the mapping
+    lists, as numpy copies of the library's host arrays."""
+
+    def __init__(self, row_ptr, col, rel, vtype, max_levels=3, delta=None, target_ratio=0.0,
+                 max_partners=64):
+        o = sgm_compress_options()
+        lib().sgm_default_compress_options(ctypes.byref(o))
+        o.max_levels = int(max_levels)
+        if delta is not None:
+            ds = [float(delta)] * 8 if np.isscalar(delta) else list(delta)
+            for i, d in enumerate(ds[:8]):
+                o.delta[i] = d
+        o.target_ratio = float(target_ratio)
+        o.max_partners = int(max_partners)
+        row_ptr = np.asarray(row_ptr)
+        (rp, rpp), (c, cp), (r, rlp), (t, tp) = _arr(row_ptr), _arr(col), _arr(rel), _arr(vtype)
+        ptr = ctypes.POINTER(sgm_compressed)()
+        rc = lib().sgm_compress(int(len(row_ptr) - 1), int(row_ptr[-1]), rpp, cp, rlp, tp,
+                                ctypes.byref(o), ctypes.byref(ptr))
+        if rc != SGM_OK:
+            raise SGMError(rc, "sgm_compress")
+        self._p = ptr
+        cc = ptr.contents
+        self.n_vertices, self.n_original = int(cc.n_vertices), int(cc.n_original)
+        self.n_edges, self.levels = int(cc.n_edges), int(cc.levels)
+        self.level_size = [int(x) for x in cc.level_size[:self.levels + 1]]
+
+        def grab(addr, n):
+            out = np.empty(n, np.int32)
+            if n:
+                ctypes.memmove(out.ctypes.data, addr, 4 * n)
+            return out
+        nw, V, E = self.n_vertices, self.n_original, self.n_edges
+        self.row_ptr = grab(cc.row_ptr, nw + 1)
+        self.col, self.rel, self.weight = grab(cc.col, E), grab(cc.rel, E), grab(cc.weight, E)
+        self.type = grab(cc.type, nw)
+        self.out_bound, self.in_bound = grab(cc.out_bound, nw), grab(cc.in_bound, nw)
+        self.map_off, self.map_ids = grab(cc.map_off, nw + 1), grab(cc.map_ids, V)
+        self.hyper_of = grab(cc.hyper_of, V)
+
+    @classmethod
+    def from_kg(cls, kg, **kw):
+        return cls(kg.row_ptr, kg.col, kg.rel, kg.vtype, **kw)
+
+    def close(self):
+        if getattr(self, "_p", None):
+            lib().sgm_free_compressed(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class CompressedGraph:
+    """GpSense over a compressed graph (thesis Ch. 3, Sec. "GpSense
+    Framework"): the weighted graph resident for matching, and the original
+    graph (possibly kept in host memory) given the mapping lists; a query's
+    matches are found on the weighted graph and expanded on the device."""
+
+    def __init__(self, graph: Graph, comp: Compressed, **options):
+        if comp._p is None:
+            raise ValueError("compression already freed")
+        opts = sgm_default_options()
+        for k, v in options.items():
+            setattr(opts, k, v)
+        h = ctypes.c_void_p()
+        rc = lib().sgm_load_compressed(comp._p, ctypes.byref(opts), ctypes.byref(h))
+        if rc != SGM_OK:
+            raise SGMError(rc, "sgm_load_compressed")
+        rc = lib().sgm_attach_mapping(graph._h, comp._p)
+        if rc != SGM_OK:
+            sgm_free_graph(h)
+            raise SGMError(rc, "sgm_attach_mapping")
+        self._hw = h
+        self.graph = graph
+        self.hyper_of = comp.hyper_of
+
+    def close(self):
+        if getattr(self, "_hw", None):
+            sgm_free_graph(self._hw)
+            self._hw = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def match(self, n, vlabel, vpin, esrc, edst, elabel, count_only=False):
+        """Matches of the query in the original graph, as Graph.match."""
+        q, keep = _make_query(n, vlabel, vpin, esrc, edst, elabel)
+        out = ctypes.POINTER(sgm_result)()
+        fl = SGM_COUNT_ONLY if count_only else SGM_SORTED
+        rc = lib().sgm_match_compressed(self.graph._h, self._hw, ctypes.byref(q), fl,
+                                        ctypes.byref(out))
+        if rc != SGM_OK:
+            err = SGMError(rc, "sgm_match_compressed")
+            if out:
+                err.n_rows = int(out.contents.n_rows)
+                sgm_free_result(out)
+            raise err
+        k, rows = _take_rows(out, n)
+        return k if count_only else rows
+
+    def match_query(self, q, **kw):
+        return self.match(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel, **kw)
+
+    def match_weighted(self, q, count_only=False):
+        """Matches of the query on the weighted graph alone (homomorphisms,
+        pins moved to their weighted vertices)."""
+        vpin = np.where(q.vpin >= 0, self.hyper_of[np.maximum(q.vpin, 0)], -1).astype(np.int32)
+        qq, keep = _make_query(q.n, q.vlabel, vpin, q.esrc, q.edst, q.elabel)
+        rc, r = sgm_match_query(self._hw, qq, SGM_COUNT_ONLY if count_only else SGM_SORTED)
+        if rc != SGM_OK:
+            if r:
+                sgm_free_result(r)
+            raise SGMError(rc, "sgm_match_query")
+        k, rows = _take_rows(r, q.n)
+        return k if count_only else rows
 
 
 class Server:

@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgm.so")
 ARCH = os.environ.get("SGM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["sgm_kernels.hip", "sgm_narrow.hip", "sgm_api.hip", "sgm_plan.cpp"]
+SOURCES = ["sgm_kernels.hip", "sgm_narrow.hip", "sgm_api.hip", "sgm_plan.cpp", "sgm_compress.cpp"]
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

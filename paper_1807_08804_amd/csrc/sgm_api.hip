@@ -239,6 +239,12 @@ struct sgm_graph {
     // with options.host_graph: the adjacency arrays above live in pinned host
     // memory; (host address, device address) of each such allocation
     std::vector<std::pair<void *, void *>> host_graph_bufs;
+    // a compressed graph (sgm_load_compressed): matches are homomorphisms
+    bool homomorphic = false;
+    // sgm_attach_mapping: mapping lists of a compression of this graph
+    int32_t map_nw = 0;
+    int32_t *d_map_off = nullptr, *d_map_ids = nullptr;
+    std::vector<int32_t> hyper_of;
     uint64_t *d_bits = nullptr;   // [SGM_MAX_QV + 1][nwords] (last: push scratch)
     int32_t *d_lists = nullptr;   // [SGM_MAX_QV][V]
     int32_t *d_prefix = nullptr;  // [SGM_MAX_QV][nwords + 1]
@@ -420,9 +426,10 @@ void free_graph_mem(sgm_graph *g) {
     for (hipEvent_t e : g->ev_free) (void)hipEventDestroy(e);
     for (hipEvent_t e : g->ev_rows)
         if (e) (void)hipEventDestroy(e);
-    void *dp[] = {g->d_out_off, g->d_in_off, g->d_vinfo, g->d_out_adj, g->d_in_adj, g->d_bits,
-                  g->d_lists,   g->d_prefix, g->d_big,   g->d_desc,    g->d_cnt,    g->d_slots,
-                  g->d_out_ta,  g->d_out_tb, g->d_in_ta, g->d_in_tb,   g->d_hub_of, g->d_hub_toff};
+    void *dp[] = {g->d_out_off, g->d_in_off, g->d_vinfo,  g->d_out_adj, g->d_in_adj,
+                  g->d_bits,    g->d_lists,  g->d_prefix, g->d_big,     g->d_desc,
+                  g->d_cnt,     g->d_slots,  g->d_out_ta, g->d_out_tb,  g->d_in_ta,
+                  g->d_in_tb,   g->d_hub_of, g->d_hub_toff, g->d_map_off, g->d_map_ids};
     for (void *p : dp) {
         bool host = false;
         for (const auto &b : g->host_graph_bufs) host |= b.second == p;
@@ -998,6 +1005,7 @@ struct Query {
         d.cnt = t.cnt;
         d.offs = t.offs;
         d.vals = t.vals;
+        d.homomorphic = g->homomorphic ? 1 : 0;
         d.total = &g->d_cnt->ec_total[e];
         d.big_items = t.big;
         d.big_count = &g->d_cnt->big_count[t.slot];
@@ -1210,6 +1218,7 @@ struct Query {
         a.table = table;
         a.R = R;
         a.k = k;
+        a.homomorphic = g->homomorphic ? 1 : 0;
         a.ext = jedge(L.ext);
         a.n_chk = L.n_chk;
         for (int c = 0; c < L.n_chk; ++c) a.chk[c] = jedge(L.chk[c]);
@@ -2374,9 +2383,13 @@ const char *sgm_strerror(int code) {
 
 const char *sgm_last_error(void) { return g_last_error.c_str(); }
 
-int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
-                   const int32_t *col, const int32_t *rel, const int32_t *type,
-                   const sgm_options *opts, sgm_graph **out) {
+// sgm_load_graph, and sgm_load_compressed: a weighted graph's degree
+// bounds (out_bound, in_bound, or null for the rows' lengths) and
+// homomorphic matching
+static int load_graph_impl(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
+                           const int32_t *col, const int32_t *rel, const int32_t *type,
+                           const sgm_options *opts, const int32_t *out_bound,
+                           const int32_t *in_bound, bool homomorphic, sgm_graph **out) {
     if (!out) return SGM_EINVAL;
     *out = nullptr;
     if (n_vertices < 1 || n_edges < 0 || !row_ptr || !type || (n_edges > 0 && (!col || !rel)))
@@ -2411,6 +2424,8 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
     if (opts) g->opts = *opts;
     else sgm_default_options(&g->opts);
     if (g->opts.out_only) g->opts.path = SGM_PATH_WIDE;
+    g->homomorphic = homomorphic;
+    if (homomorphic) g->opts.path = SGM_PATH_WIDE;
     g->device = g->opts.device;
     g->V = n_vertices;
     g->E = (int64_t)adj.size();
@@ -2458,9 +2473,11 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
         g->d_out_adj = edges_upload(adj);
         g->d_in_adj = edges_upload(in_adj);
         std::vector<int2> vi((size_t)n_vertices);
-        for (int32_t v = 0; v < n_vertices; ++v)
-            vi[v] = make_int2(type[v], std::min(off[v + 1] - off[v], 255) |
-                                           std::min(in_off[v + 1] - in_off[v], 255) << 8);
+        for (int32_t v = 0; v < n_vertices; ++v) {
+            const int32_t od = out_bound ? out_bound[v] : off[v + 1] - off[v];
+            const int32_t id = in_bound ? in_bound[v] : in_off[v + 1] - in_off[v];
+            vi[v] = make_int2(type[v], std::min(od, 255) | std::min(id, 255) << 8);
+        }
         g->d_vinfo = dev_upload(vi);
         if (g->n_types <= kHubTypesMax) {
             HubIndex hx;
@@ -2505,6 +2522,210 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
     }
     *out = g;
     return SGM_OK;
+}
+
+int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
+                   const int32_t *col, const int32_t *rel, const int32_t *type,
+                   const sgm_options *opts, sgm_graph **out) {
+    return load_graph_impl(n_vertices, n_edges, row_ptr, col, rel, type, opts, nullptr, nullptr,
+                           false, out);
+}
+
+int sgm_load_compressed(const sgm_compressed *c, const sgm_options *opts, sgm_graph **out) {
+    if (!out) return SGM_EINVAL;
+    *out = nullptr;
+    if (!c || c->n_edges > INT32_MAX || (opts && (opts->path == SGM_PATH_NARROW || opts->out_only)))
+        return SGM_EINVAL;
+    for (int32_t v = 0; v < c->n_vertices; ++v)
+        if (c->out_bound[v] < 0 || c->in_bound[v] < 0) return SGM_EINVAL;
+    return load_graph_impl(c->n_vertices, (int32_t)c->n_edges, c->row_ptr, c->col, c->rel, c->type,
+                           opts, c->out_bound, c->in_bound, true, out);
+}
+
+int sgm_attach_mapping(sgm_graph *g, const sgm_compressed *c) {
+    if (!g || !c || c->n_original != g->V || c->n_vertices < 1 || !c->map_off || !c->map_ids ||
+        !c->hyper_of || c->map_off[0] != 0 || c->map_off[c->n_vertices] != g->V)
+        return SGM_EINVAL;
+    for (int32_t x = 0; x < c->n_vertices; ++x)
+        if (c->map_off[x + 1] < c->map_off[x]) return SGM_EINVAL;
+    for (int32_t v = 0; v < g->V; ++v)
+        if (c->map_ids[v] < 0 || c->map_ids[v] >= g->V || c->hyper_of[v] < 0 ||
+            c->hyper_of[v] >= c->n_vertices)
+            return SGM_EINVAL;
+    std::lock_guard<std::mutex> lk(g->mu);
+    try {
+        HIPX(hipSetDevice(g->device));
+        HIPX(hipStreamSynchronize(g->stream));
+        dev_free(g->d_map_off);
+        dev_free(g->d_map_ids);
+        g->map_nw = 0;
+        g->d_map_off = dev_upload(std::vector<int32_t>(c->map_off, c->map_off + c->n_vertices + 1));
+        g->d_map_ids = dev_upload(std::vector<int32_t>(c->map_ids, c->map_ids + g->V));
+        g->hyper_of.assign(c->hyper_of, c->hyper_of + g->V);
+        g->map_nw = c->n_vertices;
+    } catch (const DeviceError &e) {
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        return SGM_ENOMEM;
+    }
+    return SGM_OK;
+}
+
+int sgm_match_compressed(sgm_graph *g, sgm_graph *gw, const sgm_query *q, uint32_t flags,
+                         sgm_result **out) {
+    if (!out) return SGM_EINVAL;
+    *out = nullptr;
+    if (!g || !gw || !q || g == gw || (flags & ~SGM_COUNT_ONLY) || !gw->homomorphic ||
+        g->map_nw != gw->V || !g->d_map_off)
+        return SGM_EINVAL;
+    QInfo qi;
+    int rc = check_query(q, g->V, &qi);
+    if (rc) return rc;
+    // pinned query vertices take their weighted vertices
+    const int n = qi.n;
+    int32_t wpin[SGM_MAX_QV];
+    for (int u = 0; u < n; ++u) wpin[u] = qi.pin[u] >= 0 ? g->hyper_of[qi.pin[u]] : -1;
+    sgm_query qw = *q;
+    qw.vertex_pin = wpin;
+    sgm_result *rw = nullptr;
+    rc = sgm_match_query(gw, &qw, SGM_SORTED, &rw);
+    if (rc) return rc;
+    sgm_result *res = result_new();
+    if (!res) {
+        sgm_free_result(rw);
+        return SGM_ENOMEM;
+    }
+    res->n_cols = n;
+    res->stats = rw->stats;
+    const int64_t nw = rw->n_rows;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        try {
+            HIPX(hipSetDevice(g->device));
+            Scope sc(g->pool);
+            hipStream_t st = g->stream;
+            // assignment order: breadth first over the query's edges from a
+            // pinned vertex (else vertex 0), so that every vertex after the
+            // first meets a query edge to one chosen before it
+            ExpandArgs a{};
+            a.g = g->dg;
+            a.n = n;
+            a.nw = nw;
+            a.map_off = g->d_map_off;
+            a.map_ids = g->d_map_ids;
+            int depth[SGM_MAX_QV];
+            for (int u = 0; u < n; ++u) depth[u] = -1;
+            int nord = 0;
+            auto visit_from = [&](int s0) {
+                depth[s0] = nord;
+                a.order[nord++] = s0;
+                for (int i = depth[s0]; i < nord; ++i) {
+                    const int u = a.order[i];
+                    for (int e = 0; e < qi.m; ++e) {
+                        const int v = qi.esrc[e] == u ? qi.edst[e] : qi.edst[e] == u ? qi.esrc[e] : -1;
+                        if (v >= 0 && depth[v] < 0) {
+                            depth[v] = nord;
+                            a.order[nord++] = v;
+                        }
+                    }
+                }
+            };
+            int start = 0;
+            for (int u = n - 1; u >= 0; --u)
+                if (qi.pin[u] >= 0) start = u;
+            visit_from(start);
+            for (int u = 0; u < n; ++u)
+                if (depth[u] < 0) visit_from(u);
+            for (int u = 0; u < n; ++u) a.pin[u] = qi.pin[u];
+            // each query edge is checked once both ends are chosen
+            int ne = 0;
+            for (int d = 0; d < n; ++d) {
+                a.eb[d] = ne;
+                for (int e = 0; e < qi.m; ++e)
+                    if (std::max(depth[qi.esrc[e]], depth[qi.edst[e]]) == d) {
+                        a.es[ne] = qi.esrc[e];
+                        a.ed[ne] = qi.edst[e];
+                        a.el[ne] = qi.elabel[e];
+                        ++ne;
+                    }
+            }
+            a.eb[n] = ne;
+            int64_t total = 0;
+            int32_t *table = nullptr;
+            if (nw > 0) {
+                int32_t *wrows = sc.get<int32_t>(nw * n);
+                HIPX(hipMemcpyAsync(wrows, rw->rows, sizeof(int32_t) * (size_t)(nw * n),
+                                    hipMemcpyHostToDevice, st));
+                a.wrows = wrows;
+                a.cnt = sc.get<int64_t>(nw);
+                int64_t *offs = sc.get<int64_t>(nw + 1);
+                int64_t *tmp = sc.get<int64_t>(scan_tmp_words(nw) + 1);
+                launch_expand_count(st, a);
+                launch_scan_i64(st, a.cnt, nw, offs, tmp);
+                HIPX(hipMemcpyAsync(g->h_small, offs + nw, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+                HIPX(hipStreamSynchronize(st));
+                total = g->h_small[0];
+                a.offs = offs;
+                if (total > 0 && !(flags & SGM_COUNT_ONLY)) {
+                    table = sc.get<int32_t>(total * n);
+                    a.out = table;
+                    launch_expand_write(st, a);
+                }
+            }
+            res->n_rows = total;
+            if (g->opts.result_cap_rows > 0 && total > g->opts.result_cap_rows) {
+                rc = SGM_ETOOBIG;
+            } else if (!(flags & SGM_COUNT_ONLY)) {
+                // ascending lexicographic order: stable LSD passes over the
+                // columns, last column first
+                int32_t *rows = table;
+                if (total > 1) {
+                    int nbits = 1;
+                    while ((1ll << nbits) < g->V) ++nbits;
+                    int32_t *ia = sc.get<int32_t>(total), *ib = sc.get<int32_t>(total);
+                    int32_t *ka = sc.get<int32_t>(total), *kb = sc.get<int32_t>(total);
+                    const int64_t tiles = radix_tiles(total);
+                    int64_t *hist = sc.get<int64_t>(256 * tiles);
+                    int64_t *hoff = sc.get<int64_t>(256 * tiles + 1);
+                    int64_t *stmp = sc.get<int64_t>(scan_tmp_words(256 * tiles) + 1);
+                    launch_iota(st, ia, total);
+                    for (int c = n - 1; c >= 0; --c) {
+                        launch_gather_key(st, table, n, c, ia, total, ka);
+                        for (int sh = 0; sh < nbits; sh += 8) {
+                            launch_radix_hist(st, ka, total, sh, hist);
+                            launch_scan_i64(st, hist, 256 * tiles, hoff, stmp);
+                            launch_radix_scatter(st, ka, ia, total, sh, hoff, kb, ib);
+                            std::swap(ka, kb);
+                            std::swap(ia, ib);
+                        }
+                    }
+                    int32_t colpos[SGM_MAX_QV];
+                    for (int c = 0; c < n; ++c) colpos[c] = c;
+                    rows = sc.get<int32_t>(total * n);
+                    launch_gather_rows(st, table, n, ia, total, colpos, n, rows);
+                }
+                const size_t bytes = sizeof(int32_t) * (size_t)(total * n);
+                res->rows = alloc_rows(bytes);
+                if (!res->rows) throw DeviceError{SGM_ENOMEM};
+                if (total > 0) readback_rows(g, st, rows, bytes, res->rows);
+            }
+            HIPX(hipStreamSynchronize(st));
+        } catch (const DeviceError &e) {
+            rc = e.code;
+            (void)hipStreamSynchronize(g->stream);
+        } catch (const std::bad_alloc &) {
+            rc = SGM_ENOMEM;
+        }
+    }
+    sgm_free_result(rw);
+    res->status = rc;
+    if (rc == SGM_OK || rc == SGM_ETOOBIG) {
+        if (rc != SGM_OK) result_drop_rows(res);
+        *out = res;
+        return rc;
+    }
+    sgm_free_result(res);
+    return rc;
 }
 
 void sgm_free_graph(sgm_graph *g) {
@@ -2559,7 +2780,7 @@ int sgm_set_tuning(sgm_graph *g, const sgm_tuning *t) {
 }
 
 int sgm_autotune(sgm_graph *g, const sgm_query *qs, int32_t n, int32_t reps, sgm_tuning *best) {
-    if (!g || n <= 0 || !qs || reps < 1 || g->opts.out_only) return SGM_EINVAL;
+    if (!g || n <= 0 || !qs || reps < 1 || g->opts.out_only || g->homomorphic) return SGM_EINVAL;
     reps = std::min(reps, 16);
     std::lock_guard<std::mutex> lk(g->mu);
     std::vector<QInfo> qis((size_t)n);
@@ -3072,7 +3293,7 @@ void sgm_default_serve_options(sgm_serve_options *o) {
 int sgm_server_create(sgm_graph *g, const sgm_serve_options *opts, sgm_server **out) {
     if (!out) return SGM_EINVAL;
     *out = nullptr;
-    if (!g || g->opts.out_only) return SGM_EINVAL;
+    if (!g || g->opts.out_only || g->homomorphic) return SGM_EINVAL;
     sgm_serve_options o;
     if (opts) o = *opts;
     else sgm_default_serve_options(&o);
@@ -3348,7 +3569,7 @@ int sgm_match_query_noalloc(sgm_graph *g, const sgm_query *q, uint32_t flags, in
                             int64_t rows_cap, int64_t *n_rows) {
     if (n_rows) *n_rows = 0;
     if (!g || !q || !n_rows || (flags & ~SGM_COUNT_ONLY) || rows_cap < 0 ||
-        (!(flags & SGM_COUNT_ONLY) && rows_cap > 0 && !rows) || g->opts.out_only)
+        (!(flags & SGM_COUNT_ONLY) && rows_cap > 0 && !rows) || g->opts.out_only || g->homomorphic)
         return SGM_EINVAL;
     QInfo qi;
     int rc = check_query(q, g->V, &qi);

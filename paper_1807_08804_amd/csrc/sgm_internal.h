@@ -97,6 +97,7 @@ struct ECDesc {
     unsigned long long *total;  // total pairs (count pass)
     int32_t *big_items;       // overflow list (key indices)
     int32_t *big_count;
+    int32_t homomorphic;      // 1: a key may pair with itself (compressed graphs)
 };
 
 // Rank structure of one candidate bitmap: rank(x) = prefix[x>>6] +
@@ -128,6 +129,7 @@ struct JoinArgs {
     int32_t *out;             // [..][k+1] (write pass)
     int64_t *block_cnt;       // per-tile valid counts (count pass) / offsets (write pass)
     int64_t out_base;         // first output row (chunking)
+    int32_t homomorphic;      // 1: the new value may repeat one of the row (compressed graphs)
 };
 
 // ---- launchers (sgm_kernels.hip) ----
@@ -212,5 +214,29 @@ void launch_row_keys_lists(hipStream_t s, const int32_t *table, int32_t k, const
 // key[i] = 32-bit half (hi = 0: low, 1: high) of keys[idx[i]]
 void launch_key_half(hipStream_t s, const uint64_t *keys, const int32_t *idx, int64_t n, int hi,
                      int32_t *key);
+
+// Expansion of matches on a compressed graph (thesis Ch. 3, Sec. "GpSense
+// Framework"): each weighted match (a row of weighted vertices, one per
+// query vertex) stands for the choices of one member of each vertex's
+// mapping list; the choices that are injective, keep the pins and hold every
+// query edge in the original graph g are matches of g. Query vertices are
+// chosen in order[0 .. n); the query edges (es, ed, el) with index in
+// [eb[i], eb[i+1]) are checked when order[i] is chosen (both ends chosen).
+struct ExpandArgs {
+    DevGraph g;
+    const int32_t *wrows;  // [nw][n]
+    int64_t nw;
+    int32_t n;
+    const int32_t *map_off, *map_ids;
+    int32_t order[SGM_MAX_QV];
+    int32_t pin[SGM_MAX_QV];  // per query vertex: its original vertex, or -1
+    int32_t eb[SGM_MAX_QV + 1];
+    int32_t es[SGM_MAX_QE], ed[SGM_MAX_QE], el[SGM_MAX_QE];
+    int64_t *cnt;          // [nw] matches per weighted match (count pass)
+    const int64_t *offs;   // [nw + 1] their exclusive scan (write pass)
+    int32_t *out;          // [total][n] (write pass)
+};
+void launch_expand_count(hipStream_t s, const ExpandArgs &a);
+void launch_expand_write(hipStream_t s, const ExpandArgs &a);
 
 }  // namespace sgm

@@ -256,7 +256,7 @@ __device__ __forceinline__ bool ec_hit(const ECDesc &d, const int2 *adj, int32_t
     } else if (i > beg && adj[i - 1].x == e.x) {
         return false;  // same neighbour under another relation: one pair
     }
-    return e.x != key && bit_test(d.other_bits, e.x);
+    return (e.x != key || d.homomorphic) && bit_test(d.other_bits, e.x);
 }
 
 template <int G, bool WRITE>
@@ -468,8 +468,9 @@ __device__ __forceinline__ bool join_pair(const JoinArgs &a, int64_t t, int32_t 
     const int32_t pv = rp[a.ext.col];
     const int32_t pi = rank_of(a.ext.rank, pv);
     const int32_t x = a.ext.vals[a.ext.offs[pi] + j];
-    for (int c = 0; c < a.k; ++c)
-        if (rp[c] == x) return false;  // injectivity
+    if (!a.homomorphic)
+        for (int c = 0; c < a.k; ++c)
+            if (rp[c] == x) return false;  // injectivity
     for (int e = 0; e < a.n_chk; ++e) {
         const JoinEdge &ce = a.chk[e];
         const int32_t bi = rank_of(ce.rank, rp[ce.col]);
@@ -805,6 +806,82 @@ void launch_scan_i64(hipStream_t s, const int64_t *in, int64_t n, int64_t *out, 
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, tmp);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, tmp, nb);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, tmp, out);
+}
+
+// ---------------------------------------------------------------------------
+// expansion of weighted matches into the original graph's matches
+// ---------------------------------------------------------------------------
+
+// does g hold the edge s -> t with relation rel (-1: any)? (out-rows are
+// sorted by (neighbour, relation))
+__device__ __forceinline__ bool has_edge(const DevGraph &g, int32_t s, int32_t t, int32_t rel) {
+    int32_t lo = g.out_off[s], hi = g.out_off[s + 1];
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (g.out_adj[mid].x < t) lo = mid + 1;
+        else hi = mid;
+    }
+    for (int32_t i = lo; i < g.out_off[s + 1]; ++i) {
+        const int2 e = g.out_adj[i];
+        if (e.x != t) return false;
+        if (rel < 0 || e.y == rel) return true;
+    }
+    return false;
+}
+
+// One thread per weighted match: a depth-first walk over the members of the
+// mapping lists in the query's order; the count pass counts the matches,
+// the write pass writes them at the match's offset, in walk order.
+template <bool WRITE>
+__global__ __launch_bounds__(kBlock) void k_expand(ExpandArgs a) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < a.nw;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t *wr = a.wrows + r * a.n;
+        int32_t x[SGM_MAX_QV];    // chosen member per query vertex
+        int32_t pos[SGM_MAX_QV];  // next list position per depth
+        int64_t c = 0;
+        const int64_t o = WRITE ? a.offs[r] : 0;
+        int d = 0;
+        pos[0] = a.map_off[wr[a.order[0]]];
+        while (d >= 0) {
+            const int u = a.order[d];
+            const int32_t end = a.map_off[wr[u] + 1];
+            bool placed = false;
+            while (pos[d] < end && !placed) {
+                const int32_t m = a.map_ids[pos[d]++];
+                bool ok = a.pin[u] < 0 || m == a.pin[u];
+                for (int i = 0; i < d && ok; ++i) ok = x[a.order[i]] != m;
+                for (int e = a.eb[d]; e < a.eb[d + 1] && ok; ++e) {
+                    const int32_t s = a.es[e] == u ? m : x[a.es[e]];
+                    const int32_t t = a.ed[e] == u ? m : x[a.ed[e]];
+                    ok = has_edge(a.g, s, t, a.el[e]);
+                }
+                if (ok) {
+                    x[u] = m;
+                    placed = true;
+                }
+            }
+            if (!placed) {
+                --d;
+            } else if (d == a.n - 1) {
+                if (WRITE)
+                    for (int v = 0; v < a.n; ++v) a.out[(o + c) * a.n + v] = x[v];
+                ++c;
+            } else {
+                ++d;
+                pos[d] = a.map_off[wr[a.order[d]]];
+            }
+        }
+        if (!WRITE) a.cnt[r] = c;
+    }
+}
+
+void launch_expand_count(hipStream_t s, const ExpandArgs &a) {
+    hipLaunchKernelGGL(k_expand<false>, dim3(grid_for(a.nw, kBlock, kGridCap)), dim3(kBlock), 0, s, a);
+}
+
+void launch_expand_write(hipStream_t s, const ExpandArgs &a) {
+    hipLaunchKernelGGL(k_expand<true>, dim3(grid_for(a.nw, kBlock, kGridCap)), dim3(kBlock), 0, s, a);
 }
 
 void launch_join_fan(hipStream_t s, const JoinArgs &a, int64_t *fan) {
