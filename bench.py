@@ -25,6 +25,10 @@ time: exact counts for all, sorted tables to host below a row cap.
 ``--workload sweep``: query-size and average-degree sweeps on 1M-vertex
 graphs and graph-size scaling (0.1M-16M vertices) with the graph in device
 memory and in host memory; a record per point, batched and one at a time.
+
+``--workload compressed``: multi-level compression of graphs with similar
+vertices (size per level), and queries matched directly and through the
+weighted graph, the original graph in device or in host memory.
 """
 import argparse
 import json
@@ -586,12 +590,74 @@ def bench_sweep(args, P, kggen):
     return out
 
 
+def _one_at_a_time(f, qs):
+    for q in qs[:4]:
+        f(q)
+    lat = []
+    for q in qs:
+        a = time.perf_counter_ns()
+        f(q)
+        lat.append(time.perf_counter_ns() - a)
+    lat_ms = np.asarray(lat, np.float64) / 1e6
+    return {"queries_per_s": round(len(qs) / (lat_ms.sum() / 1e3), 1),
+            "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat_ms, 99)), 3)}
+
+
+def bench_compressed(args, P, kggen):
+    """Multi-level compression (thesis Ch. 3, Sec. "Multi-level Graph
+    Compression", Table 3.4) on graphs with similar vertices: the size of
+    each level, and the same queries matched directly and through the
+    weighted graph (expansion on the device), with the original graph in
+    device memory and in host memory (the thesis' setting: the original
+    graph in main memory, the compressed one on the GPU)."""
+    out = {"metric": "multi-level compression: size per level and queries/s one at a time",
+           "unit": "queries/s", "n_gpus": 1, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "twin graphs (kggen.twin_graph: power-law base, two rounds of "
+                                  "twins keeping 90 % of the edges), 64 queries of 2-8 vertices "
+                                  "(kggen.twin_queries), levels at delta 0.8 / 0.7 / 0.7"},
+           "graphs": {}}
+    for name in ("twin-medium", "twin-large"):
+        t = time.time()
+        kg = kggen.twin_named(name)
+        qs = kggen.twin_queries(kg, 64, kggen.BASE_SEED + 930)
+        log(f"{name}: {kg.V} vertices, {kg.E} edges, queries in {time.time() - t:.1f}s")
+        t = time.perf_counter()
+        comp = P.Compressed.from_kg(kg)
+        t_comp = time.perf_counter() - t
+        rec = {"vertices": kg.V, "edges": kg.E, "compress_s": round(t_comp, 2),
+               "levels": comp.levels,
+               "size_ratio_per_level": [round(x / comp.level_size[0], 4) for x in comp.level_size],
+               "weighted_vertices": comp.n_vertices, "weighted_edges": comp.n_edges,
+               "largest_mapping_list": int(np.diff(comp.map_off).max())}
+        g = P.Graph.from_kg(kg)
+        rows = [g.match_query(q, count_only=True) for q in qs]
+        rec["rows_mean"] = round(float(np.mean(rows)), 1)
+        rec["direct_device_graph"] = _one_at_a_time(lambda q: g.match_query(q), qs)
+        cg = P.CompressedGraph(g, comp)
+        wrows = [cg.match_weighted(q, count_only=True) for q in qs]
+        rec["weighted_rows_mean"] = round(float(np.mean(wrows)), 1)
+        rec["compressed_device_graph"] = _one_at_a_time(lambda q: cg.match_query(q), qs)
+        cg.close()
+        g.close()
+        gh = P.Graph.from_kg(kg, host_graph=1)
+        rec["direct_host_graph"] = _one_at_a_time(lambda q: gh.match_query(q), qs)
+        cgh = P.CompressedGraph(gh, comp)
+        rec["compressed_host_graph"] = _one_at_a_time(lambda q: cgh.match_query(q), qs)
+        cgh.close()
+        gh.close()
+        comp.close()
+        out["graphs"][name] = rec
+        log(f"{name}: {json.dumps(rec)}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["medium", "large", "large-cyclic", "sweep"],
+    ap.add_argument("--workload", choices=["medium", "large", "large-cyclic", "sweep", "compressed"],
                     default="large")
     ap.add_argument("--row-cap", type=int, default=250_000_000,
                     help="large-cyclic: row cap for materialized tables")
@@ -629,7 +695,7 @@ def main():
     import kggen
     import paper_1807_08804_amd as P
     run = {"medium": bench_medium, "large": bench_large, "large-cyclic": bench_large_cyclic,
-           "sweep": bench_sweep}
+           "sweep": bench_sweep, "compressed": bench_compressed}
     out = run[args.workload](args, P, kggen)
     print(json.dumps(out), flush=True)
 

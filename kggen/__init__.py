@@ -724,6 +724,31 @@ def twin_named(name: str) -> KG:
     return twin_graph(V, E, BASE_SEED + off)
 
 
+def twin_queries(kg: KG, count: int, seed: int, hmax: float = 2e5):
+    """Queries of 2..8 vertices on a twin graph: paths, trees and stars with
+    0..2 pins, and every fourth a cycle with one pin; every fifth has
+    vertex labels dropped to "any" with probability 0.4 and edge labels with
+    probability 0.3; accepted when H(q) <= hmax."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    while len(out) < count:
+        i = len(out)
+        n = int(rng.integers(2, 9))
+        try:
+            if i % 4 == 3:
+                q = draw_cyclic_dense(kg, rng, max(n, 4), 1, n_pins=1)
+            else:
+                q = draw_query(kg, rng, n, ("path", "tree", "star")[i % 3], int(rng.integers(0, 3)))
+        except RuntimeError:
+            continue
+        if i % 5 == 4:
+            q.vlabel = np.where(rng.random(q.n) < 0.4, -1, q.vlabel).astype(np.int32)
+            q.elabel = np.where(rng.random(q.m) < 0.3, -1, q.elabel).astype(np.int32)
+        if tree_hom_bound(kg, q) <= hmax:
+            out.append(q)
+    return out
+
+
 SWEEP_COUNT = 64  # queries per sweep point
 SWEEP_RECIPE = ("sweep_queries(g, n, 64, seed=BASE_SEED+600+k) per sweep_points() entry k; "
                 "p_any_vertex=0.5, p_any_edge=0.25, H <= 1e6")

@@ -26,32 +26,10 @@ def same(got, want, what):
     assert got.shape == want.shape and np.array_equal(got, want), what
 
 
-def twin_queries(kg, count, seed):
-    rng = np.random.Generator(np.random.PCG64(seed))
-    out = []
-    while len(out) < count:
-        i = len(out)
-        n = int(rng.integers(2, 9))
-        try:
-            if i % 4 == 3:
-                q = kggen.draw_cyclic_dense(kg, rng, max(n, 4), 1, n_pins=1)
-            else:
-                q = kggen.draw_query(kg, rng, n, ("path", "tree", "star")[i % 3],
-                                     int(rng.integers(0, 3)))
-        except RuntimeError:
-            continue
-        if i % 5 == 4:  # some labels dropped to "any"
-            q.vlabel = np.where(rng.random(q.n) < 0.4, -1, q.vlabel).astype(np.int32)
-            q.elabel = np.where(rng.random(q.m) < 0.3, -1, q.elabel).astype(np.int32)
-        if kggen.tree_hom_bound(kg, q) <= 2e5:
-            out.append(q)
-    return out
-
-
 @pytest.fixture(scope="module")
 def small_case():
     kg = kggen.twin_named("twin-small")
-    qs = twin_queries(kg, 40, kggen.BASE_SEED + 910)
+    qs = kggen.twin_queries(kg, 40, kggen.BASE_SEED + 910)
     og = oracle.graph_from_kg(kg)
     return kg, qs, [og.match_query(q) for q in qs]
 
@@ -115,7 +93,7 @@ def test_compressed_medium():
     three levels leave 29 %), 24 queries, original graph in host memory as
     in the thesis' setting, against the oracle."""
     kg = kggen.twin_named("twin-medium")
-    qs = twin_queries(kg, 24, kggen.BASE_SEED + 920)
+    qs = kggen.twin_queries(kg, 24, kggen.BASE_SEED + 920)
     og = oracle.graph_from_kg(kg)
     want = [og.match_query(q) for q in qs]
     comp = P.Compressed.from_kg(kg)
