@@ -103,6 +103,48 @@ int main(int argc, char **argv) {
 """
 
 
+COMPRESS_DRIVER = r"""
+#include <cstdio>
+#include <cstdlib>
+#include "sgm.h"
+static int32_t rd(FILE *f) { int32_t x; if (std::fscanf(f, "%d", &x) != 1) std::exit(3); return x; }
+int main(int argc, char **argv) {
+    FILE *f = std::fopen(argv[1], "r");
+    const int32_t V = rd(f), E = rd(f);
+    int32_t *rp = new int32_t[V + 1], *col = new int32_t[E + 1], *rel = new int32_t[E + 1];
+    int32_t *typ = new int32_t[V];
+    for (int32_t v = 0; v <= V; ++v) rp[v] = rd(f);
+    for (int32_t i = 0; i < E; ++i) { col[i] = rd(f); rel[i] = rd(f); }
+    for (int32_t v = 0; v < V; ++v) typ[v] = rd(f);
+    const int32_t nd = rd(f);
+    for (int k = 0; k < nd; ++k) {
+        sgm_compress_options o;
+        sgm_default_compress_options(&o);
+        o.max_levels = 4;
+        for (int i = 0; i < 8; ++i) o.delta[i] = rd(f) / 100.0f;
+        sgm_compressed *c = nullptr;
+        const int rc = sgm_compress(V, E, rp, col, rel, typ, &o, &c);
+        unsigned long long h = 1469598103934665603ull;
+        auto mix = [&](const int32_t *a, int64_t n) {
+            for (int64_t i = 0; i < n; ++i) h = (h ^ (uint32_t)a[i]) * 1099511628211ull;
+        };
+        if (rc == 0) {
+            mix(c->row_ptr, c->n_vertices + 1); mix(c->col, c->n_edges); mix(c->rel, c->n_edges);
+            mix(c->weight, c->n_edges); mix(c->out_bound, c->n_vertices); mix(c->in_bound, c->n_vertices);
+            mix(c->map_off, c->n_vertices + 1); mix(c->map_ids, V); mix(c->hyper_of, V);
+            std::printf("%d %d %lld %llu\n", rc, c->n_vertices, (long long)c->n_edges, h);
+        } else {
+            std::printf("%d\n", rc);
+        }
+        sgm_free_compressed(c);
+    }
+    delete[] rp; delete[] col; delete[] rel; delete[] typ;
+    std::fclose(f);
+    return 0;
+}
+"""
+
+
 def _compile(tool, args, tmp_path):
     exe = str(tmp_path / "drv")
     p = subprocess.run([tool, *SAN, *args, "-o", exe], capture_output=True, text=True)
@@ -178,3 +220,33 @@ def test_host_planning_under_sanitizers(tmp_path):
         visit = [int(x) for x in line.split("|")[0].split()[2:]]
         p = P.sgm_plan_query(q.n, q.vlabel, q.vpin, q.esrc, q.edst, q.elabel, V, tf)
         assert visit == p["visit_order"], (q, line)
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ is not installed")
+def test_compression_under_sanitizers(tmp_path):
+    """sgm_compress (host code) built with the sanitizers on micro graphs
+    with repeated triples and self-loops at several thresholds: no report,
+    and the same weighted graph and mapping as the library's build."""
+    rng = np.random.default_rng(406)
+    mg = random_graph(rng, 80, 400, n_types=2, n_rels=3)
+    rp, col, rel, typ = mg.csr()
+    deltas = [[100] * 8, [50] * 8, [20] * 8]
+    lines = [f"{len(rp) - 1} {len(col)}", " ".join(map(str, rp))]
+    lines += [f"{int(a)} {int(b)}" for a, b in zip(col, rel)]
+    lines += [" ".join(map(str, typ)), str(len(deltas))] + [" ".join(map(str, d)) for d in deltas]
+    inp = tmp_path / "in.txt"
+    inp.write_text("\n".join(lines) + "\n")
+    src = tmp_path / "drv.cpp"
+    src.write_text(COMPRESS_DRIVER)
+    csrc = os.path.join(ROOT, "paper_1807_08804_amd", "csrc")
+    exe = _compile("g++", ["-std=c++17", "-I", os.path.join(ROOT, "include"), str(src),
+                           os.path.join(csrc, "sgm_compress.cpp")], tmp_path)
+    out = _run(exe, inp)
+    for d, line in zip(deltas, out):
+        c = P.Compressed(rp, col, rel, typ, max_levels=4, delta=d[0] / 100.0)
+        h = 1469598103934665603
+        for a in (c.row_ptr, c.col, c.rel, c.weight, c.out_bound, c.in_bound, c.map_off,
+                  c.map_ids, c.hyper_of):
+            for x in a.astype(np.uint32).tolist():
+                h = ((h ^ x) * 1099511628211) & ((1 << 64) - 1)
+        assert line.split() == ["0", str(c.n_vertices), str(c.n_edges), str(h)], (d, line)
