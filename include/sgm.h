@@ -574,9 +574,9 @@ void sgm_free_compressed(sgm_compressed *c);
  * is a candidate when the query vertex's degree is at most its weight), and
  * matches are homomorphisms: several query vertices may take one weighted
  * vertex, and a query edge may take a self-loop, since the original match
- * may use several members of one group. Runs on SGM_PATH_WIDE (NARROW,
- * servers, autotuning and sgm_match_query_noalloc: SGM_EINVAL). c is not
- * kept. */
+ * may use several members of one group. Both execution paths serve it;
+ * servers, autotuning and sgm_match_query_noalloc refuse it (SGM_EINVAL),
+ * and so does options.out_only. c is not kept. */
 int sgm_load_compressed(const sgm_compressed *c, const sgm_options *opts, sgm_graph **out);
 
 /* Give the original graph g (resident, possibly with options.host_graph)

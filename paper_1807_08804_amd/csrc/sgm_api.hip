@@ -1725,6 +1725,7 @@ bool pack_query(sgm_graph *g, const QInfo &qi, const Plan &pl, NQuery *nq, int *
     nq->n_ref = (int)pr.refine.size();
     nq->refine_rounds = g->opts.refine_rounds < 0 ? -1 : std::min(g->opts.refine_rounds, 32);
     nq->proj = qi.proj;
+    nq->homo = g->homomorphic ? 1 : 0;
     int k = 0;
     auto put = [&](const PStep &s) {
         NStep &t = nq->steps[k++];
@@ -2425,7 +2426,6 @@ static int load_graph_impl(int32_t n_vertices, int32_t n_edges, const int32_t *r
     else sgm_default_options(&g->opts);
     if (g->opts.out_only) g->opts.path = SGM_PATH_WIDE;
     g->homomorphic = homomorphic;
-    if (homomorphic) g->opts.path = SGM_PATH_WIDE;
     g->device = g->opts.device;
     g->V = n_vertices;
     g->E = (int64_t)adj.size();
@@ -2534,8 +2534,7 @@ int sgm_load_graph(int32_t n_vertices, int32_t n_edges, const int32_t *row_ptr,
 int sgm_load_compressed(const sgm_compressed *c, const sgm_options *opts, sgm_graph **out) {
     if (!out) return SGM_EINVAL;
     *out = nullptr;
-    if (!c || c->n_edges > INT32_MAX || (opts && (opts->path == SGM_PATH_NARROW || opts->out_only)))
-        return SGM_EINVAL;
+    if (!c || c->n_edges > INT32_MAX || (opts && opts->out_only)) return SGM_EINVAL;
     for (int32_t v = 0; v < c->n_vertices; ++v)
         if (c->out_bound[v] < 0 || c->in_bound[v] < 0) return SGM_EINVAL;
     return load_graph_impl(c->n_vertices, (int32_t)c->n_edges, c->row_ptr, c->col, c->rel, c->type,

@@ -42,6 +42,7 @@ struct NQuery {
     int32_t refine_rounds;  // -1: until nothing is removed
     uint32_t proj;          // projected columns (bit u = query vertex u kept; 0: all)
     int32_t fault;          // 1: fail as a device fault would (sgm_inject_fault)
+    int32_t homo;           // 1: matches are homomorphisms (a compressed graph)
     NStep steps[kNMaxSteps];
     NNbr nbr[kNMaxNbr];
 };
@@ -112,7 +113,7 @@ struct JLevel {
     int32_t *out;
     int64_t cap;   // output rows that fit
     int32_t nsub;  // shared: chunks per block of NT parent rows
-    int32_t pad;
+    int32_t homo;  // 1: a value may repeat one of the row (a compressed graph)
     JChk chk[SGM_MAX_QE];
 };
 
@@ -129,7 +130,8 @@ struct EcJob {
     int32_t *num, *vals, *ovl;
     const uint64_t *ob;
     const int32_t *ol, *items;
-    int32_t nk, rel, dir, no, tier, pad;
+    int32_t nk, rel, dir, no, tier;
+    int32_t homo;  // 1: a key may pair with itself (a compressed graph)
 };
 
 struct HelpJob {

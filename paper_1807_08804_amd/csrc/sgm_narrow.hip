@@ -1458,7 +1458,7 @@ __device__ __forceinline__ int64_t ec_keys(const Ctx &c, const EcJob &Ej, int32_
         int32_t n = 0;
         for (int32_t base = beg; base < end; base += G) {
             const int32_t i = base + gl;
-            const bool hit = i < end && ec_hit(E.rel, E.ob, adj, beg, i, k);
+            const bool hit = i < end && ec_hit(E.rel, E.ob, adj, beg, i, E.homo ? -1 : k);
             const uint64_t bm = __ballot(hit) & gmask;
             if (hit) dst[n + __popcll(bm & lanemask_lt(lane))] = adj[i].x;
             n += __popcll(bm);
@@ -1492,8 +1492,9 @@ __device__ __forceinline__ int64_t ec_long_keys(const Ctx &c, const EcJob &Ej, i
         }
         const bool probe = probe_cheaper(E.no, end - beg);
         int32_t *dst = E.vals + E.degoff[it];
-        const int64_t n = probe ? ec_probe_wave(E.rel, E.ol, E.no, adj, beg, end, k, dst)
-                                : ec_key_wave(E.rel, E.ob, adj, beg, end, k, dst);
+        const int32_t ks = E.homo ? -1 : k;  // -1: the key may pair with itself
+        const int64_t n = probe ? ec_probe_wave(E.rel, E.ol, E.no, adj, beg, end, ks, dst)
+                                : ec_key_wave(E.rel, E.ob, adj, beg, end, ks, dst);
         if (lane == 0) {
             E.num[it] = (int32_t)n;
             mytot += n;
@@ -1517,8 +1518,9 @@ __device__ __forceinline__ int64_t ec_giant_keys(Ctx &c, const EcJob &Ej, int32_
         const int32_t beg = off[k], end = off[k + 1];
         const bool probe = probe_cheaper(E.no, end - beg);
         int32_t *dst = E.vals + E.degoff[it];
-        const int64_t n = probe ? ec_probe_wg(c, E.rel, E.ol, E.no, adj, beg, end, k, dst)
-                                : ec_key_wg(c, E.rel, E.ob, adj, beg, end, k, dst);
+        const int32_t ks = E.homo ? -1 : k;
+        const int64_t n = probe ? ec_probe_wg(c, E.rel, E.ol, E.no, adj, beg, end, ks, dst)
+                                : ec_key_wg(c, E.rel, E.ob, adj, beg, end, ks, dst);
         if (threadIdx.x == 0) {
             E.num[it] = (int32_t)n;
             mytot += n;
@@ -1611,7 +1613,8 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
     int64_t mytot = 0;
     uint64_t fb = 0;
     const bool can_share = c.help_items > 0 && c.job;
-    const EcJob E{keys, degoff, num, vals, ovl, ob, ol, nullptr, nk, rel, dir, no, 0, 0};
+    const int32_t homo = c.Q->homo;
+    const EcJob E{keys, degoff, num, vals, ovl, ob, ol, nullptr, nk, rel, dir, no, 0, homo};
     if (nk <= NW) {
         // a handful of keys: one wave each, rows above wg_rows get the
         // whole workgroup
@@ -1623,8 +1626,9 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
                 if (lane == 0) c.s->big[atomicAdd(&c.s->ngiant, 1)] = wave;  // at most NW
             } else {
                 const bool probe = probe_cheaper(no, end - beg);
-                const int64_t n = probe ? ec_probe_wave(rel, ol, no, adj, beg, end, k, vals + degoff[wave])
-                                        : ec_key_wave(rel, ob, adj, beg, end, k, vals + degoff[wave]);
+                const int32_t ks = homo ? -1 : k;
+                const int64_t n = probe ? ec_probe_wave(rel, ol, no, adj, beg, end, ks, vals + degoff[wave])
+                                        : ec_key_wave(rel, ob, adj, beg, end, ks, vals + degoff[wave]);
                 if (lane == 0) {
                     num[wave] = (int32_t)n;
                     mytot += n;
@@ -1674,8 +1678,9 @@ __device__ __forceinline__ void ec_build(Ctx &c, int e, int key, int other, int 
                 }
             }
             const bool probe = probe_cheaper(no, end - beg);
-            const int64_t n = probe ? ec_probe_wave(rel, ol, no, adj, beg, end, k, vals + degoff[it])
-                                    : ec_key_wave(rel, ob, adj, beg, end, k, vals + degoff[it]);
+            const int32_t ks = homo ? -1 : k;
+            const int64_t n = probe ? ec_probe_wave(rel, ol, no, adj, beg, end, ks, vals + degoff[it])
+                                    : ec_key_wave(rel, ob, adj, beg, end, ks, vals + degoff[it]);
             if (lane == 0) {
                 num[it] = (int32_t)n;
                 mytot += n;
@@ -1772,8 +1777,9 @@ __device__ __forceinline__ uint64_t ec_build_single(Ctx &c, uint64_t mask, int d
         const int32_t no = c.s->cnt[other];
         const int32_t rel = Q.elabel[ed];
         const bool probe = probe_cheaper(no, end - beg);
-        const int64_t n = probe ? ec_probe_wave(rel, c.L(other), no, adj, beg, end, k, vals)
-                                : ec_key_wave(rel, c.B(other), adj, beg, end, k, vals);
+        const int32_t ks = Q.homo ? -1 : k;
+        const int64_t n = probe ? ec_probe_wave(rel, c.L(other), no, adj, beg, end, ks, vals)
+                                : ec_key_wave(rel, c.B(other), adj, beg, end, ks, vals);
         if (lane == 0) {
             degoff[0] = 0;
             degoff[1] = end - beg;
@@ -1899,8 +1905,9 @@ __device__ __forceinline__ bool join_pair(const Smem &s, const JLevel &L, int64_
     const int k = L.k;
     const int32_t *row = L.table + (r0 + a0) * k;
     bool ok = true;
-    for (int cc = 0; cc < k; ++cc)
-        if (row[cc] == x) ok = false;
+    if (!L.homo)
+        for (int cc = 0; cc < k; ++cc)
+            if (row[cc] == x) ok = false;
     for (int ci = 0; ci < L.nchk && ok; ++ci) {
         // the check edge's values for the row's key vertex hold x
         const JChk &h = L.chk[ci];
@@ -2440,7 +2447,8 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                     int64_t r = 1;
                     for (int u = 0; u < n; ++u) {
                         const int32_t x = c.L(u)[0];
-                        for (int w = 0; w < u; ++w) r &= (int64_t)(one_row[w] != x);
+                        if (!Q.homo)
+                            for (int w = 0; w < u; ++w) r &= (int64_t)(one_row[w] != x);
                         one_row[u] = x;
                         s.jorder[u] = u;
                         s.jpos[u] = u;
@@ -2575,6 +2583,7 @@ __device__ __forceinline__ void run_query(Ctx &c) {
                         }
                         L.out = out;
                         L.cap = cap;
+                        L.homo = Q.homo;
                     }
                     // a level of many pairs is shared (whether or not
                     // workgroups are idle yet: those that become idle join)

@@ -34,15 +34,20 @@ def small_case():
     return kg, qs, [og.match_query(q) for q in qs]
 
 
+PATHS = [P.SGM_PATH_AUTO, P.SGM_PATH_WIDE, P.SGM_PATH_NARROW]
+
+
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("host_graph", [0, 1])
-def test_compressed_small(small_case, host_graph):
+def test_compressed_small(small_case, host_graph, path):
     """40 queries on the small graph with similar vertices (three levels of
-    compression), full tables and counts, against the oracle."""
+    compression), full tables and counts, against the oracle, with the
+    weighted graph matched on each execution path."""
     kg, qs, want = small_case
     comp = P.Compressed.from_kg(kg)
     g = P.Graph.from_kg(kg, host_graph=host_graph)
-    cg = P.CompressedGraph(g, comp)
-    say(f"case: compressed twin-small host_graph={host_graph} levels={comp.levels} "
+    cg = P.CompressedGraph(g, comp, path=path)
+    say(f"case: compressed twin-small host_graph={host_graph} path={path} levels={comp.levels} "
         f"|Vw|={comp.n_vertices}")
     for i, (q, w) in enumerate(zip(qs, want)):
         same(cg.match_query(q), w, i)
@@ -67,8 +72,9 @@ def test_weighted_matches_cover_the_original(small_case):
     g.close()
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("seed", range(8))
-def test_compressed_micro(seed):
+def test_compressed_micro(seed, path):
     """Micro graphs (repeated triples, self-loops, two types) compressed at
     a low threshold, queries with "any" labels and pins, against the oracle
     (weighted matches with self-loops and repeated weighted vertices)."""
@@ -79,11 +85,16 @@ def test_compressed_micro(seed):
     og = oracle.Graph(V, mg.src, mg.dst, mg.rel, mg.vtype)
     comp = P.Compressed(rp, col, rel, typ, max_levels=4, delta=0.3)
     g = P.Graph(rp, col, rel, typ)
-    cg = P.CompressedGraph(g, comp)
-    say(f"case: compressed micro seed={seed} V={V} |Vw|={comp.n_vertices}")
+    cg = P.CompressedGraph(g, comp, path=path)
+    say(f"case: compressed micro seed={seed} path={path} V={V} |Vw|={comp.n_vertices}")
     for _ in range(12):
         q = random_query(rng, int(rng.integers(1, 6)), 2, 2, V, p_pin=0.15, extra=3)
-        same(cg.match_query(q), og.match_query(q), q)
+        want = og.match_query(q)
+        try:
+            same(cg.match_query(q), want, q)
+        except P.SGMError as e:
+            # the persistent path alone refuses what fits no slot
+            assert path == P.SGM_PATH_NARROW and e.code == P.SGM_EUNSUPPORTED
     cg.close()
     g.close()
 
@@ -110,9 +121,9 @@ def test_compressed_entry_points_checked(small_case):
     kg, qs, _ = small_case
     comp = P.Compressed.from_kg(kg)
     g = P.Graph.from_kg(kg)
-    # a compressed graph serves the multi-kernel path only
+    # no outgoing-graph-only form of a compressed graph
     with pytest.raises(P.SGMError) as e:
-        P.CompressedGraph(g, comp, path=P.SGM_PATH_NARROW)
+        P.CompressedGraph(g, comp, out_only=1, path=P.SGM_PATH_WIDE)
     assert e.value.code == P.SGM_EINVAL
     # a mapping made from a graph of another size
     tiny = P.Compressed(np.array([0, 1, 1], np.int32), np.array([1], np.int32),
