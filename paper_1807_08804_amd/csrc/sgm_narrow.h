@@ -141,7 +141,8 @@ struct HelpJob {
     const int32_t *ul;         // kind 0: the items (a candidate list, or long rows)
     int32_t chunk, done, q, kind;  // kind 0: chunks of the candidate list; 1: row segments;
                                    // 2: parent rows of a join level; 3: keys of an
-                                   // edge-candidate table
+                                   // edge-candidate table; 4: rows above wg_rows of a
+                                   // prune-only step, one per chunk
     int32_t n_items, G, ncount, revd;
     NStep st;
     int32_t nbig, removed, nmarks, abort_;

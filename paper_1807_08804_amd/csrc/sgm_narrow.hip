@@ -491,8 +491,10 @@ __device__ __forceinline__ const int2 *test_row(const Ctx &c, int32_t up, const 
 // then pushes every matching neighbour.
 __device__ __forceinline__ int32_t max_row(const DevGraph &g, const NNbr *nb, int ncount, int32_t up);
 
-__device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb, int ncount, int32_t up,
-                        uint64_t *ub, uint64_t &fb, int32_t *defer = nullptr) {
+template <class K>
+__device__ __forceinline__ void item_wg_k(Ctx &c, const K &k, const NStep &st, const NNbr *nb,
+                                          int ncount, int32_t up, uint64_t *ub, uint64_t &fb,
+                                          int32_t *defer = nullptr) {
     const DevGraph &g = c.g;
     if (ncount <= 16 && max_row(g, nb, ncount, up) <= 4 * NT) {
         // Every listed row fits one pass: all rows are read and tested at
@@ -524,7 +526,7 @@ __device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb,
         if (!alive) {
             if (threadIdx.x == 0) {
                 atomicAnd((unsigned long long *)&ub[up >> 6], ~(1ull << (up & 63)));
-                atomicAdd(&c.s->removed, 1);
+                atomicAdd(k.removed(), 1);
                 fb += 20ull + 12ull * seen;
             }
             return;
@@ -540,8 +542,8 @@ __device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb,
                 uint64_t *tb = d.mode == 0 ? c.scratch : c.B(d.v);
                 int32_t *tl = d.mode == 0 ? nullptr : c.L(d.v);
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if ((hj >> k) & 1u) push_bit(c, tb, tl, d.v, adj[beg + threadIdx.x + k * NT].x);
+                for (int q = 0; q < 4; ++q)
+                    if ((hj >> q) & 1u) push_bit(c, k, tb, tl, d.v, adj[beg + threadIdx.x + q * NT].x);
             }
         if (threadIdx.x == 0) fb += 20ull + 12ull * seen;
         return;
@@ -556,8 +558,8 @@ __device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb,
         for (int32_t base = beg; base < end; base += 4 * NT) {
             bool hit = false;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int32_t i = base + k * NT + threadIdx.x;
+            for (int q = 0; q < 4; ++q) {
+                const int32_t i = base + q * NT + threadIdx.x;
                 if (i < end) hit |= nbr_hit(c, d, adj[i]);
             }
             seen += min(4 * NT, end - base);
@@ -571,7 +573,7 @@ __device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb,
     if (!alive) {
         if (threadIdx.x == 0) {
             atomicAnd((unsigned long long *)&ub[up >> 6], ~(1ull << (up & 63)));
-            atomicAdd(&c.s->removed, 1);
+            atomicAdd(k.removed(), 1);
             fb += 20ull + 12ull * seen;
         }
         return;
@@ -602,14 +604,19 @@ __device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb,
                 for (int q = 0; q < 8; ++q) e[q] = adj_at(adj, i + q * NT, end);
 #pragma unroll
                 for (int q = 0; q < 8; ++q) h[q] = (i + q * NT < end) && nbr_hit(c, d, e[q]);
-                push4<LdsCtr, false>(c, LdsCtr{c.s}, tb, tl, d.v, h[0], e[0].x, h[1], e[1].x,
+                push4<K, false>(c, k, tb, tl, d.v, h[0], e[0].x, h[1], e[1].x,
                                      h[2], e[2].x, h[3], e[3].x);
-                push4<LdsCtr, false>(c, LdsCtr{c.s}, tb, tl, d.v, h[4], e[4].x, h[5], e[5].x,
+                push4<K, false>(c, k, tb, tl, d.v, h[4], e[4].x, h[5], e[5].x,
                                      h[6], e[6].x, h[7], e[7].x);
             }
         }
     }
     if (threadIdx.x == 0) fb += 20ull + 12ull * seen;
+}
+
+__device__ __forceinline__ void item_wg(Ctx &c, const NStep &st, const NNbr *nb, int ncount, int32_t up,
+                                        uint64_t *ub, uint64_t &fb, int32_t *defer = nullptr) {
+    item_wg_k(c, LdsCtr{c.s}, st, nb, ncount, up, ub, fb, defer);
 }
 
 // One wave on one candidate (wave-uniform call, no workgroup barrier), four
@@ -1030,6 +1037,8 @@ __device__ __forceinline__ void shared_job(Ctx &c, int kind, const NStep &st, co
                          min(n_items, ch * K + K), fb, nodefer);
         else if (kind == 3)
             ec_chunk(c, *ecj, j, ch * K, min(n_items, ch * K + K), G, fb);
+        else if (kind == 4)
+            item_wg_k(c, BoardCtr{j}, st, nb, ncount, ul[ch], ub, fb);
         else
             push_segment(c, BoardCtr{j}, nb, seg[ch], fb);
         ++own;
@@ -1261,7 +1270,17 @@ __device__ __forceinline__ void filter_step(Ctx &c, const NStep &st) {
         }
         __syncthreads();
         const int32_t ngiant = min(c.s->ngiant, kBigCap);
-        for (int32_t b = 0; b < ngiant; ++b) item_wg(c, st, nb, ncount, c.s->big[b], ub, fb, def);
+        if (!st.push && ngiant >= 2 && c.help_items > 0 && c.job &&
+            c.slab_bytes >= 16 * (int64_t)c.lcap) {
+            // rows above wg_rows in a prune-only step: one workgroup each,
+            // shared (a pushing step's rows go out as shared row segments)
+            int32_t *rows = (int32_t *)(c.slab + 12 * (int64_t)c.lcap);
+            for (int32_t i = threadIdx.x; i < ngiant; i += NT) rows[i] = c.s->big[i];
+            __syncthreads();
+            shared_job(c, 4, st, nb, ncount, rows, ub, revd, ngiant, 1, NT, ngiant, nullptr, fb);
+        } else {
+            for (int32_t b = 0; b < ngiant; ++b) item_wg(c, st, nb, ncount, c.s->big[b], ub, fb, def);
+        }
         if (def) push_deferred(c, st, nb, ncount, def, fb);
     }
     add_bytes_wave(c, fb);
@@ -2947,6 +2966,8 @@ __device__ __forceinline__ void help_step(const NArgs &a, Smem &s, unsigned char
             push_segment(c, BoardCtr{j}, s.nbl, seg[ch], fb);
         } else if (kind == 3) {
             ec_chunk(c, j->ecj, j, ch * K, min(n_items, ch * K + K), G, fb);
+        } else if (kind == 4) {
+            item_wg_k(c, BoardCtr{j}, st, s.nbl, ncount, hul[ch], c.B(st.u), fb);
         } else {
             join_chunk(c, s.jl, ch, &j->jrows, &j->abort_, fb);
         }
