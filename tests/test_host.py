@@ -295,7 +295,9 @@ def test_binding_structs_match_the_header(tmp_path):
     import subprocess
     structs = {"sgm_options": P.sgm_options, "sgm_query": P.sgm_query, "sgm_stats": P.sgm_stats,
                "sgm_result": P.sgm_result, "sgm_kstat": P.sgm_kstat, "sgm_tuning": P.sgm_tuning,
-               "sgm_serve_options": P.sgm_serve_options, "sgm_serve_stats": P.sgm_serve_stats}
+               "sgm_serve_options": P.sgm_serve_options, "sgm_serve_stats": P.sgm_serve_stats,
+               "sgm_compress_options": P.sgm_compress_options,
+               "sgm_compressed": P.sgm_compressed}
     inc = os.path.join(os.path.dirname(__file__), "..", "include")
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sgm.h"', "int main(void) {"]
     for name, cls in structs.items():
