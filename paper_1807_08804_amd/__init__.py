@@ -559,14 +559,29 @@ class Graph:
         owner = _BatchOwner(outs, n)
         stats = [stats_dict(outs[i].contents.stats, q.n, len(q.esrc))
                  for i, q in enumerate(queries)] if with_stats else []
+        rows = info[:n].tolist()
+        # tables that sit close together (one launch's row block) are sliced
+        # from one view over their span instead of one view each
+        flat, lo = None, 0
+        if not count_only and n > 8:
+            spans = [(a, a + 4 * k * c) for st, c, k, a in rows if st == SGM_OK and k and a]
+            if spans:
+                lo = min(a for a, _ in spans)
+                hi = max(b for _, b in spans)
+                used = sum(b - a for a, b in spans)
+                if hi - lo <= 2 * used + (1 << 20):
+                    flat = np.asarray(_RowsView(lo, (hi - lo) // 4, 1, owner)).reshape(-1)
         res = []
-        for st, ncol, k, addr in info[:n].tolist():
+        for st, ncol, k, addr in rows:
             if st != SGM_OK:
                 res.append(SGMError(st, "batch member"))
             elif count_only:
                 res.append(k)
             elif k == 0 or not addr:
                 res.append(np.empty((k, ncol), np.int32))
+            elif flat is not None:
+                o = (addr - lo) >> 2
+                res.append(flat[o:o + k * ncol].reshape(k, ncol))
             else:
                 res.append(np.asarray(_RowsView(addr, k, ncol, owner)))
         return (res, stats) if with_stats else res
