@@ -196,3 +196,22 @@ def test_sweep_shared_steps_forced(sweep_fixture):
         for i in range(0, len(qs), 8):
             same(g.match_query(qs[i]), want[i], (key, i))
     g.close()
+
+
+def test_host_graph_served_and_allocation_free(medium_kg, oracle_medium):
+    """The served form and the allocation-free entry point on a graph kept
+    in host memory: a served stream and single queries into a caller's
+    buffer, against the oracle."""
+    qs, _ = kggen.medium_queries(medium_kg, 30)
+    want = [oracle_medium.match_query(q) for q in qs]
+    g = P.Graph.from_kg(medium_kg, host_graph=1)
+    say("case: host-graph served stream")
+    srv = P.Server(g)
+    lat, res = srv.replay(qs, kggen.poisson_arrivals(len(qs), 1000))
+    srv.close()
+    for i, (r, w) in enumerate(zip(res, want)):
+        same(r, w, i)
+    say("case: host-graph allocation-free entry point")
+    for i, (q, w) in enumerate(zip(qs[:10], want[:10])):
+        same(g.match_query_noalloc(q, max(len(w), 1)), w, i)
+    g.close()
