@@ -615,12 +615,15 @@ def bench_compressed(args, P, kggen):
            "unit": "queries/s", "n_gpus": 1, "dtype": "int32", "data": "synthetic",
            "config": {"workload": "twin graphs (kggen.twin_graph: power-law base, two rounds of "
                                   "twins keeping 90 % of the edges), 64 queries of 2-8 vertices "
-                                  "(kggen.twin_queries), levels at delta 0.8 / 0.7 / 0.7"},
+                                  "(kggen.twin_queries; kggen/fixtures/twin_large.json), levels at "
+                                  "delta 0.8 / 0.7 / 0.7"},
            "graphs": {}}
     for name in ("twin-medium", "twin-large"):
         t = time.time()
         kg = kggen.twin_named(name)
-        qs = kggen.twin_queries(kg, 64, kggen.BASE_SEED + 930)
+        # the large graph's queries are stored (drawing them takes ~30 s)
+        qs = (kggen.load_twin_large() if name == "twin-large"
+              else kggen.twin_queries(kg, 64, kggen.BASE_SEED + 930))
         log(f"{name}: {kg.V} vertices, {kg.E} edges, queries in {time.time() - t:.1f}s")
         t = time.perf_counter()
         comp = P.Compressed.from_kg(kg)

@@ -815,6 +815,15 @@ def load_large_cyclic():
     return _load_fixture("large_cyclic.json", LARGE_CYCLIC_RECIPE)[0]
 
 
+TWIN_LARGE_RECIPE = "twin_queries(twin_named('twin-large'), 64, seed=BASE_SEED+930)"
+
+
+def load_twin_large():
+    """The stored 64 queries of the large graph with similar vertices
+    (written by kggen/make_fixtures.py from ``twin_queries``)."""
+    return _load_fixture("twin_large.json", TWIN_LARGE_RECIPE)[0]
+
+
 def load_large_batch(count: int = 1024):
     """The stored 1,024-query mixed batch of the large graph (written by
     kggen/make_fixtures.py from ``batch_queries``; the first ``count``, which

@@ -12,9 +12,11 @@ recipe.
   extra edge, 0-2 pins, H <= 10^6), ``serve_queries``;
 * sweep.json: 64 queries per query-size / degree / graph-size point
   (``sweep_points``, ``sweep_queries``), each point drawn on its own graph
-  in a worker process.
+  in a worker process;
+* twin_large.json: 64 queries of the large graph with similar vertices
+  (``twin_queries`` on ``twin_named('twin-large')``).
 
-    python -m kggen.make_fixtures [cyclic] [batch] [serve] [sweep]
+    python -m kggen.make_fixtures [cyclic] [batch] [serve] [sweep] [twin]
 """
 import json
 import os
@@ -58,6 +60,13 @@ def write_sweep(workers=6):
 
 def main(which):
     t = time.time()
+    if "twin" in which:
+        qs = kggen.twin_queries(kggen.twin_named("twin-large"), 64, seed=kggen.BASE_SEED + 930)
+        _write("twin_large.json", kggen.TWIN_LARGE_RECIPE, qs, 0)
+        print(f"twin_large: {len(qs)} queries at {time.time() - t:.0f}s")
+        which = [w for w in which if w != "twin"]
+        if not which:
+            return
     if "sweep" in which:
         write_sweep()
         print(f"sweep: {len(kggen.sweep_points())} points at {time.time() - t:.0f}s")
@@ -81,4 +90,4 @@ def main(which):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["cyclic", "batch", "serve", "sweep"])
+    main(sys.argv[1:] or ["cyclic", "batch", "serve", "sweep", "twin"])

@@ -117,6 +117,26 @@ def test_compressed_medium():
     g.close()
 
 
+def test_compressed_large_bench_workload():
+    """The compressed-graph bench workload at its full size: the large
+    graph with similar vertices (4.5M vertices, 36.9M edges) compressed in
+    three levels, its 64 stored queries matched through the weighted graph
+    with the original graph in host memory, against the oracle."""
+    kg = kggen.twin_named("twin-large")
+    qs = kggen.load_twin_large()
+    og = oracle.graph_from_kg(kg)
+    want = [og.match_query(q) for q in qs]
+    comp = P.Compressed.from_kg(kg)
+    g = P.Graph.from_kg(kg, host_graph=1)
+    cg = P.CompressedGraph(g, comp)
+    say(f"case: compressed twin-large |Vw|={comp.n_vertices} levels={comp.levels}")
+    for i, (q, w) in enumerate(zip(qs, want)):
+        same(cg.match_query(q), w, i)
+    cg.close()
+    g.close()
+    comp.close()
+
+
 def test_compressed_entry_points_checked(small_case):
     kg, qs, _ = small_case
     comp = P.Compressed.from_kg(kg)
