@@ -13,7 +13,8 @@ Each query runs under a budget of candidate tests (``--budget``, per
 workload); a query whose table would exceed ``--row-cap`` rows is counted
 without materialising its rows (count only, no hash). Queries that hit the
 budget are recorded as unfinished: their GPU tables stay parity-unpinned
-against the oracle. The file is rewritten after every query, and a rerun
+against the oracle. ``--retry-unfinished --retry-budget B`` runs those
+entries again under a larger budget B, which the entry then records. The file is rewritten after every query, and a rerun
 keeps the entries already computed with the same budgets.
 
     python tests/golden/make_large_golden.py [batch] [serve] [cyclic]
@@ -89,6 +90,9 @@ def main():
                     help="largest table materialised and hashed")
     ap.add_argument("--retry-unfinished", action="store_true",
                     help="compute again the entries recorded as unfinished")
+    ap.add_argument("--retry-budget", type=float, default=0,
+                    help="candidate tests per query for the retried entries (default: the "
+                         "workload's budget); the entry records the budget it ran under")
     args = ap.parse_args()
     doc = {}
     if os.path.exists(PATH):
@@ -118,8 +122,12 @@ def main():
             e = sec["entries"].get(str(i))
             if e is not None and not (args.retry_unfinished and "unfinished" in e):
                 continue
-            e, el = one(og, q, budget, args.row_cap)
+            retry = e is not None and args.retry_budget > 0
+            eb = int(args.retry_budget) if retry else budget
+            e, el = one(og, q, eb, args.row_cap)
             e["oracle_s"] = round(el, 3)
+            if eb != budget:
+                e["budget"] = eb
             sec["entries"][str(i)] = e
             print(f"{name} {i}: {e}", flush=True)
             tmp = PATH + ".tmp"
