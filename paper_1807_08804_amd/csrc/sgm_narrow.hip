@@ -3185,6 +3185,8 @@ constexpr int kSweepChunk = 64;   // predicates per LDS pass (32 KB of rows)
 constexpr int kSweepStride = kSweepTile + 1;
 
 constexpr int kSweepTypes = 1024;  // type tables up to this size are staged in LDS
+constexpr int kSweepGroup = 4;     // slots whose typed predicates are walked together
+static_assert(kSweepSlots % kSweepGroup == 0, "slot groups must tile the slots");
 
 __global__ __launch_bounds__(kSweepThreads) void k_root_sweep(DevGraph g, const VPred *preds, int32_t n_pred,
                                                     int32_t n_any, uint64_t *rootbits,
@@ -3245,15 +3247,25 @@ __global__ __launch_bounds__(kSweepThreads) void k_root_sweep(DevGraph g, const 
                 const int32_t lo = max(t0, toff[tc] - c0), hi = min(cn, toff[tc + 1] - c0);
                 r[i] = ok && lo < hi ? (lo | (hi << 16)) : 0;
             }
+            // kSweepGroup slots walk their ranges side by side, so that
+            // their predicate reads and ORs are independent LDS operations
+            // in flight together instead of one dependent chain per slot;
+            // a slot whose range has ended reads a clamped, unused entry
 #pragma unroll
-            for (int i = 0; i < kSweepSlots; ++i) {
-                const int od = vi[i].y & 255, id = vi[i].y >> 8;
-                const int hi = r[i] >> 16;
-                for (int j = r[i] & 0xffff; j < hi; ++j) {
-                    const int2 q = pq[j];
-                    if (od >= q.x && id >= q.y)
-                        atomicOr((unsigned long long *)&rows[j * kSweepStride + kSweepSlots * wid + i],
-                                 1ull << lane);
+            for (int i0 = 0; i0 < kSweepSlots; i0 += kSweepGroup) {
+                int n = 0;
+#pragma unroll
+                for (int k = 0; k < kSweepGroup; ++k) n = max(n, (r[i0 + k] >> 16) - (r[i0 + k] & 0xffff));
+                for (int t = 0; t < n; ++t) {
+#pragma unroll
+                    for (int k = 0; k < kSweepGroup; ++k) {
+                        const int i = i0 + k;
+                        const int j = (r[i] & 0xffff) + t;
+                        const int2 q = pq[min(j, kSweepChunk - 1)];
+                        if (j < (r[i] >> 16) && (vi[i].y & 255) >= q.x && (vi[i].y >> 8) >= q.y)
+                            atomicOr((unsigned long long *)&rows[j * kSweepStride + kSweepSlots * wid + i],
+                                     1ull << lane);
+                    }
                 }
             }
         } else {
